@@ -1,0 +1,568 @@
+/*
+ * FP64 CPU oracle for the neural incident radiance cache (NIRC) and the two-level Monte Carlo
+ * estimator.  TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU-baseline
+ * leg call it; the HIP library never does.  It shares no code, header or table with the HIP path.
+ *
+ * Everything is plain loops in double precision (OpenMP only over independent points/queries),
+ * written so that each step can be checked against the paper by eye:
+ *
+ *   - cache-level estimator   F_c = (1/N_c) sum_k f_c(X_k)/p_c(X_k)          (eq. Fc; eq. L_c)
+ *   - residual estimator      F_r = (1/N_r) sum (f(Y) - f_c(Y))/p_r(Y)        (eq. Fr; eq. L_r)
+ *   - two-level estimator     F_tl = F_c + F_r                                 (eq. Fml; eq. L_mlmc)
+ *     With a white Lambertian BRDF (1/pi) and cosine-weighted sampling (p = cos/pi) the factor
+ *     f_r cos / p is exactly 1, so F_c is the mean of the N cache predictions and F_r is the
+ *     target radiance minus the cache prediction at one independent direction.
+ *   - the cache is an MLP (4 hidden ReLU layers, no biases, Sec. "Results": 4 hidden layers of
+ *     width 64, ReLU) on a sin/cos frequency encoding of (x, omega, n, roughness), with an
+ *     exponential output so that radiance predictions stay positive.
+ *   - training loss: relative L2 with a stop-gradient denominator (eq. 12), read on radiance
+ *     with p_r = 1; Adam (Sec. "Results": Adam, several steps per frame).
+ *   - ground truth: the cosine-weighted integral of the lobe field, reduced to a 1D integral
+ *     with a modified Bessel function and evaluated with Gauss-Legendre quadrature.
+ *
+ * Random numbers the method draws (sampling directions, training samples) come from
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC'11), implemented here from its published definition.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NIN 10
+#define NFREQ 8
+#define NFEAT 160
+#define NLOBES 4
+
+/* ------------------------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al. SC'11): 10 rounds of the multiply-xor S-box on a 4x32 counter;
+ * the two key words advance by the Weyl constants (golden ratio, sqrt(3)-1) between rounds.    */
+void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* A 24-bit uniform in [0,1) from one 32-bit word. */
+static double u24(uint32_t r) { return (double)(r >> 8) * (1.0 / 16777216.0); }
+
+/* Counter streams of the method's random numbers. */
+enum { STREAM_CACHE_DIR = 3, STREAM_RESIDUAL_DIR = 4, STREAM_TRAIN = 5 };
+
+/* The two uniforms of sampled direction k of point p in frame f (cache directions come in
+ * pairs from one Philox call; the residual direction uses its own stream). */
+static void direction_uniforms(uint64_t seed, uint32_t p, int k, int residual, uint32_t frame,
+                               double *u1, double *u2)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    if (residual) {
+        uint32_t ctr[4] = {p, 0u, frame, STREAM_RESIDUAL_DIR};
+        oracle_philox(ctr, key, out);
+        *u1 = u24(out[0]);
+        *u2 = u24(out[1]);
+    } else {
+        uint32_t ctr[4] = {p, (uint32_t)(k >> 1), frame, STREAM_CACHE_DIR};
+        oracle_philox(ctr, key, out);
+        if (k & 1) { *u1 = u24(out[2]); *u2 = u24(out[3]); }
+        else       { *u1 = u24(out[0]); *u2 = u24(out[1]); }
+    }
+}
+
+/* Cosine-weighted hemisphere sample about the normal n (pdf cos(theta)/pi).  Local direction
+ * (sqrt(u1) cos 2 pi u2, sqrt(u1) sin 2 pi u2, sqrt(1-u1)); world frame from the branchless
+ * orthonormal basis of Duff et al. ("Building an Orthonormal Basis, Revisited", JCGT 2017).  */
+static void cosine_direction(const double n[3], double u1, double u2, double w[3])
+{
+    double r = sqrt(u1);
+    double lx = r * cos(2.0 * M_PI * u2);
+    double ly = r * sin(2.0 * M_PI * u2);
+    double lz = sqrt(1.0 - u1);
+    double s = (n[2] >= 0.0) ? 1.0 : -1.0;
+    double a = -1.0 / (s + n[2]);
+    double b = n[0] * n[1] * a;
+    double t[3] = {1.0 + s * n[0] * n[0] * a, s * b, -s * n[0]};
+    double bb[3] = {b, s + n[1] * n[1] * a, -n[1]};
+    for (int d = 0; d < 3; ++d) w[d] = lx * t[d] + ly * bb[d] + lz * n[d];
+}
+
+void oracle_sample_dirs(int64_t P, const float *nx, const float *ny, const float *nz, int n_cache,
+                        uint64_t seed, uint64_t frame, double *dirs /* [P][n_cache+1][3] */)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < P; ++p) {
+        double n[3] = {nx[p], ny[p], nz[p]};
+        for (int k = 0; k <= n_cache; ++k) {
+            double u1, u2;
+            direction_uniforms(seed, (uint32_t)p, k, k == n_cache, (uint32_t)frame, &u1, &u2);
+            cosine_direction(n, u1, u2, dirs + ((size_t)p * (n_cache + 1) + k) * 3);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Frequency encoding: each of the 10 inputs v gives sin(2^k pi v), cos(2^k pi v), k = 0..7;
+ * feature index 16*i + 2*k + (0: sin, 1: cos); inputs in the order x, omega, n, roughness.
+ * sin/cos(pi t) use an exact reduction of t to [-1/4, 1/4] plus quadrant, so multiples of 1/2
+ * give exact values.                                                                          */
+static void sincospi(double t, double *s, double *c)
+{
+    double r = remainder(t, 2.0);          /* exact, in [-1, 1] */
+    double q = nearbyint(2.0 * r);         /* quadrant in {-2..2} */
+    double f = r - 0.5 * q;                /* exact, in [-1/4, 1/4] */
+    double sf = sin(M_PI * f), cf = cos(M_PI * f);
+    switch (((int)q) & 3) {
+    case 0: *s = sf;  *c = cf;  break;
+    case 1: *s = cf;  *c = -sf; break;
+    case 2: *s = -sf; *c = -cf; break;
+    default: *s = -cf; *c = sf; break;
+    }
+}
+
+static void encode_inputs(const double in[NIN], double feat[NFEAT])
+{
+    for (int i = 0; i < NIN; ++i)
+        for (int k = 0; k < NFREQ; ++k) {
+            double s, c;
+            sincospi(ldexp(in[i], k), &s, &c);
+            feat[16 * i + 2 * k + 0] = s;
+            feat[16 * i + 2 * k + 1] = c;
+        }
+}
+
+static void gather_inputs(const float *const pts[7], int64_t p, const double w[3], double in[NIN])
+{
+    in[0] = pts[0][p]; in[1] = pts[1][p]; in[2] = pts[2][p];
+    in[3] = w[0];      in[4] = w[1];      in[5] = w[2];
+    in[6] = pts[3][p]; in[7] = pts[4][p]; in[8] = pts[5][p];
+    in[9] = pts[6][p];
+}
+
+void oracle_encode(int64_t Q, const float *px, const float *py, const float *pz, const float *nx,
+                   const float *ny, const float *nz, const float *rough, const int32_t *point,
+                   const double *dirs /* [Q][3] */, double *feat /* [Q][160] */)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) {
+        double in[NIN];
+        gather_inputs(pts, point ? point[q] : q, dirs + 3 * q, in);
+        encode_inputs(in, feat + (size_t)q * NFEAT);
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* MLP: h1 = ReLU(W1 e), h_l = ReLU(W_l h_{l-1}) (l = 2..4), z = W5 h4, y = exp(z).
+ * Canonical parameter vector: W1 [W x 160], W2, W3, W4 [W x W], W5 [3 x W], row-major.       */
+typedef struct {
+    int width;
+    const double *W[5];
+    int rows[5], cols[5];
+} net_t;
+
+static int64_t n_params_of(int width) { return (int64_t)width * NFEAT + 3LL * width * width + 3LL * width; }
+
+int64_t oracle_n_params(int width) { return n_params_of(width); }
+
+static void net_setup(net_t *net, const double *w, int width)
+{
+    net->width = width;
+    int rows[5] = {width, width, width, width, 3};
+    int cols[5] = {NFEAT, width, width, width, width};
+    size_t off = 0;
+    for (int l = 0; l < 5; ++l) {
+        net->W[l] = w + off;
+        net->rows[l] = rows[l];
+        net->cols[l] = cols[l];
+        off += (size_t)rows[l] * cols[l];
+    }
+}
+
+/* Forward pass keeping pre-activations z_l (l = 0..3 hidden, 4 = output) and activations. */
+typedef struct {
+    double h[4][256];   /* hidden activations (width <= 256) */
+    double z[4][256];   /* hidden pre-activations */
+    double zo[3];       /* output pre-activation */
+    double y[3];        /* output */
+} acts_t;
+
+static void net_forward(const net_t *net, const double e[NFEAT], acts_t *a)
+{
+    const double *x = e;
+    for (int l = 0; l < 4; ++l) {
+        for (int r = 0; r < net->rows[l]; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < net->cols[l]; ++c) s += net->W[l][(size_t)r * net->cols[l] + c] * x[c];
+            a->z[l][r] = s;
+            a->h[l][r] = s > 0.0 ? s : 0.0;
+        }
+        x = a->h[l];
+    }
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < net->cols[4]; ++c) s += net->W[4][(size_t)r * net->cols[4] + c] * x[c];
+        a->zo[r] = s;
+        a->y[r] = exp(s);
+    }
+}
+
+/* Cache prediction for explicit queries (point index + direction). */
+void oracle_infer(int64_t Q, const float *px, const float *py, const float *pz, const float *nx,
+                  const float *ny, const float *nz, const float *rough, const int32_t *point,
+                  const double *dirs /* [Q][3] */, const double *w, int width, double *rgb /* [Q][3] */)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+    net_t net;
+    net_setup(&net, w, width);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) {
+        double in[NIN], e[NFEAT];
+        acts_t a;
+        gather_inputs(pts, point ? point[q] : q, dirs + 3 * q, in);
+        encode_inputs(in, e);
+        net_forward(&net, e, &a);
+        for (int c = 0; c < 3; ++c) rgb[3 * q + c] = a.y[c];
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Synthetic incident radiance: L_c(x, w) = sum_j a_jc(x) exp(kappa_j (mu_j . w - 1)),
+ * a_jc(x) = alpha_jc + sum_d beta_jcd x_d.  Lobe record (64 floats): axis[4][3], kappa[4],
+ * alpha[4][3], beta[4][3][3].                                                                 */
+typedef struct {
+    double axis[NLOBES][3], kappa[NLOBES], alpha[NLOBES][3], beta[NLOBES][3][3];
+} lobes_t;
+
+static void lobes_unpack(const float *rec, lobes_t *L)
+{
+    int o = 0;
+    for (int j = 0; j < NLOBES; ++j) for (int d = 0; d < 3; ++d) L->axis[j][d] = rec[o++];
+    for (int j = 0; j < NLOBES; ++j) L->kappa[j] = rec[o++];
+    for (int j = 0; j < NLOBES; ++j) for (int c = 0; c < 3; ++c) L->alpha[j][c] = rec[o++];
+    for (int j = 0; j < NLOBES; ++j)
+        for (int c = 0; c < 3; ++c) for (int d = 0; d < 3; ++d) L->beta[j][c][d] = rec[o++];
+}
+
+static void lobe_amplitude(const lobes_t *L, int j, const double x[3], double a[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        a[c] = L->alpha[j][c];
+        for (int d = 0; d < 3; ++d) a[c] += L->beta[j][c][d] * x[d];
+    }
+}
+
+static void field_eval(const lobes_t *L, const double x[3], const double w[3], double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    for (int j = 0; j < NLOBES; ++j) {
+        double a[3];
+        lobe_amplitude(L, j, x, a);
+        double mu_w = L->axis[j][0] * w[0] + L->axis[j][1] * w[1] + L->axis[j][2] * w[2];
+        double g = exp(L->kappa[j] * (mu_w - 1.0));
+        for (int c = 0; c < 3; ++c) out[c] += a[c] * g;
+    }
+}
+
+void oracle_field(int64_t Q, const float *lobes, const float *px, const float *py, const float *pz,
+                  const int32_t *point, const double *dirs, double *out)
+{
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) {
+        int64_t p = point ? point[q] : q;
+        double x[3] = {px[p], py[p], pz[p]};
+        field_eval(&L, x, dirs + 3 * q, out + 3 * q);
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Two-level estimator per point and channel (eq. L_c, L_r, L_mlmc with f_r cos/p = 1, L_e = 0):
+ *   F_c = (1/N) sum_k y(x, w_k),   F_r = L(x, w_r) - y(x, w_r),   F_tl = F_c + F_r.
+ * dirs == NULL: sample the directions here (Philox streams as above); otherwise use the given
+ * [P][N+1][3] directions (the last one of each point is the residual direction).
+ * plug_in != 0 replaces the network by the field itself (y := L), a special case where F_r = 0. */
+void oracle_estimate(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
+                     const float *ny, const float *nz, const float *rough, const float *lobes,
+                     const double *w, int width, int n_cache, uint64_t seed, uint64_t frame,
+                     const double *dirs, int plug_in, double *out_tl, double *out_c, double *out_r)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+    net_t net;
+    net_setup(&net, w, width);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < P; ++p) {
+        double x[3] = {px[p], py[p], pz[p]};
+        double n[3] = {nx[p], ny[p], nz[p]};
+        double fc[3] = {0, 0, 0}, fr[3];
+        for (int k = 0; k <= n_cache; ++k) {
+            double wdir[3];
+            if (dirs) {
+                const double *d = dirs + ((size_t)p * (n_cache + 1) + k) * 3;
+                wdir[0] = d[0]; wdir[1] = d[1]; wdir[2] = d[2];
+            } else {
+                double u1, u2;
+                direction_uniforms(seed, (uint32_t)p, k, k == n_cache, (uint32_t)frame, &u1, &u2);
+                cosine_direction(n, u1, u2, wdir);
+            }
+            double y[3];
+            if (plug_in) {
+                field_eval(&L, x, wdir, y);
+            } else {
+                double in[NIN], e[NFEAT];
+                acts_t a;
+                gather_inputs(pts, p, wdir, in);
+                encode_inputs(in, e);
+                net_forward(&net, e, &a);
+                y[0] = a.y[0]; y[1] = a.y[1]; y[2] = a.y[2];
+            }
+            if (k < n_cache) {
+                for (int c = 0; c < 3; ++c) fc[c] += y[c];
+            } else {
+                double Lr[3];
+                field_eval(&L, x, wdir, Lr);
+                for (int c = 0; c < 3; ++c) fr[c] = Lr[c] - y[c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            double Fc = n_cache > 0 ? fc[c] / n_cache : 0.0;
+            if (out_c) out_c[3 * p + c] = Fc;
+            if (out_r) out_r[3 * p + c] = fr[c];
+            if (out_tl) out_tl[3 * p + c] = Fc + fr[c];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Ground truth F(x, n) = (1/pi) int_{H+(n)} L(x, w) (n . w) dw = sum_j a_j(x) J(kappa_j, mu_j . n),
+ * with, after rotating n to +z and integrating the azimuth (which gives 2 pi I0),
+ *   J(kappa, t) = 2 e^{-kappa} int_0^1 u e^{kappa t u} I0(kappa sqrt(1-t^2) sqrt(1-u^2)) du.
+ * The integrand is entire in u, so Gauss-Legendre converges geometrically.                    */
+double oracle_bessel_i0(double z)
+{
+    /* power series sum_k (z^2/4)^k / (k!)^2, summed until the terms stop changing the sum */
+    double q = 0.25 * z * z, term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        double ns = sum + term;
+        if (ns == sum) break;
+        sum = ns;
+    }
+    return sum;
+}
+
+/* Gauss-Legendre nodes and weights on [0, 1] (Newton iteration on P_n). */
+void oracle_gauss_legendre(int n, double *x, double *wgt)
+{
+    for (int i = 0; i < n; ++i) {
+        double t = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            double dt = p1 / dp;
+            t -= dt;
+            if (fabs(dt) < 1e-16) break;
+        }
+        {   /* derivative at the converged node */
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1; p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+        }
+        x[i] = 0.5 * (1.0 - t);
+        wgt[i] = 1.0 / ((1.0 - t * t) * dp * dp);   /* 2/((1-t^2) P'^2) mapped to [0,1] */
+    }
+}
+
+static double J_on_nodes(double kappa, double t, int n, const double *xs, const double *ws)
+{
+    if (t > 1.0) t = 1.0;
+    if (t < -1.0) t = -1.0;
+    double s = sqrt(1.0 - t * t), acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double u = xs[i];
+        acc += ws[i] * u * exp(kappa * (t * u - 1.0)) * oracle_bessel_i0(kappa * s * sqrt(1.0 - u * u));
+    }
+    return 2.0 * acc;
+}
+
+double oracle_J(double kappa, double t, int n_nodes)
+{
+    double xs[1024], ws[1024];
+    if (n_nodes > 1024) n_nodes = 1024;
+    oracle_gauss_legendre(n_nodes, xs, ws);
+    return J_on_nodes(kappa, t, n_nodes, xs, ws);
+}
+
+void oracle_closed_form(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
+                        const float *ny, const float *nz, const float *lobes, int n_nodes, double *F)
+{
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+    double xs[1024], ws[1024];
+    if (n_nodes > 1024) n_nodes = 1024;
+    oracle_gauss_legendre(n_nodes, xs, ws);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t p = 0; p < P; ++p) {
+        double x[3] = {px[p], py[p], pz[p]};
+        double n[3] = {nx[p], ny[p], nz[p]};
+        double acc[3] = {0, 0, 0};
+        for (int j = 0; j < NLOBES; ++j) {
+            double a[3];
+            lobe_amplitude(&L, j, x, a);
+            double t = L.axis[j][0] * n[0] + L.axis[j][1] * n[1] + L.axis[j][2] * n[2];
+            double J = J_on_nodes(L.kappa[j], t, n_nodes, xs, ws);
+            for (int c = 0; c < 3; ++c) acc[c] += a[c] * J;
+        }
+        for (int c = 0; c < 3; ++c) F[3 * p + c] = acc[c];
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Training (Sec. "Radiance Cache Optimization", eq. 12 read on radiance with p_r = 1):
+ *   loss = (1/(3B)) sum_{b,c} (y - t)^2 / (sg(y)^2 + eps),
+ *   dloss/dy = (2/(3B)) (y - t) / (y^2 + eps)   (denominator held constant),
+ *   dloss/dz = dloss/dy * y                      (y = exp z),
+ * then plain backpropagation through the ReLU layers (ReLU'(0) = 0); only weight gradients.
+ * frozen == 0 differentiates through the denominator as well (a control, not the method).    */
+double oracle_loss_grad(int64_t B, const float *px, const float *py, const float *pz, const float *nx,
+                        const float *ny, const float *nz, const float *rough, const int32_t *point,
+                        const double *dirs, const double *target, const double *w, int width,
+                        double eps, int frozen, double *grad /* [n_params] or NULL */)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+    net_t net;
+    net_setup(&net, w, width);
+    int64_t np = n_params_of(width);
+    double loss = 0.0;
+    if (grad) memset(grad, 0, sizeof(double) * (size_t)np);
+    int W = width;
+    /* per-sample work is independent; accumulate per-thread and combine in a fixed order */
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    double *tg = grad ? (double *)calloc((size_t)nthreads * np, sizeof(double)) : NULL;
+    double *tl = (double *)calloc((size_t)nthreads, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *g = tg ? tg + (size_t)tid * np : NULL;
+#pragma omp for schedule(static)
+        for (int64_t b = 0; b < B; ++b) {
+            double in[NIN], e[NFEAT];
+            acts_t a;
+            gather_inputs(pts, point ? point[b] : b, dirs + 3 * b, in);
+            encode_inputs(in, e);
+            net_forward(&net, e, &a);
+            double dz[3];
+            for (int c = 0; c < 3; ++c) {
+                double y = a.y[c], t = target[3 * b + c];
+                double den = y * y + eps;
+                tl[tid] += (y - t) * (y - t) / den;
+                double dy = 2.0 * (y - t) / den;
+                if (!frozen) dy -= (y - t) * (y - t) * 2.0 * y / (den * den);
+                dz[c] = dy * y / (3.0 * (double)B);
+            }
+            if (!g) continue;
+            /* output layer */
+            double *gW5 = g + (size_t)W * NFEAT + 3LL * W * W;
+            for (int c = 0; c < 3; ++c)
+                for (int j = 0; j < W; ++j) gW5[(size_t)c * W + j] += dz[c] * a.h[3][j];
+            double delta[256], prev[256];
+            for (int j = 0; j < W; ++j) {
+                double s = 0.0;
+                for (int c = 0; c < 3; ++c) s += net.W[4][(size_t)c * W + j] * dz[c];
+                delta[j] = a.z[3][j] > 0.0 ? s : 0.0;
+            }
+            /* hidden layers 4..2 (weight index l = 3..1) */
+            for (int l = 3; l >= 1; --l) {
+                double *gW = g + (size_t)W * NFEAT + (size_t)(l - 1) * W * W;
+                for (int r = 0; r < W; ++r)
+                    for (int c = 0; c < W; ++c) gW[(size_t)r * W + c] += delta[r] * a.h[l - 1][c];
+                for (int c = 0; c < W; ++c) {
+                    double s = 0.0;
+                    for (int r = 0; r < W; ++r) s += net.W[l][(size_t)r * W + c] * delta[r];
+                    prev[c] = a.z[l - 1][c] > 0.0 ? s : 0.0;
+                }
+                memcpy(delta, prev, sizeof(double) * W);
+            }
+            /* first layer */
+            for (int r = 0; r < W; ++r)
+                for (int c = 0; c < NFEAT; ++c) g[(size_t)r * NFEAT + c] += delta[r] * e[c];
+        }
+    }
+    for (int t = 0; t < nthreads; ++t) loss += tl[t];
+    if (grad)
+        for (int t = 0; t < nthreads; ++t)
+            for (int64_t i = 0; i < np; ++i) grad[i] += tg[(size_t)t * np + i];
+    free(tg);
+    free(tl);
+    return loss / (3.0 * (double)B);
+}
+
+/* Adam (Kingma & Ba): m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
+ * w <- w - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), t = 1 for the first step.     */
+void oracle_adam(int64_t n, double *w, double *m, double *v, const double *g, int64_t t, double lr,
+                 double b1, double b2, double eps)
+{
+    double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* Training samples (the stand-in for the paper's separate training pass): sample b of training
+ * step s in frame f draws one Philox block from counter (b, s, f, STREAM_TRAIN): word 0 picks the
+ * point uniformly (floor(r0 * P / 2^32), integer arithmetic), words 1 and 2 give a fresh
+ * cosine-weighted direction about that point's normal; the target is the noise-free field.    */
+void oracle_train_batch(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
+                        const float *ny, const float *nz, const float *lobes, int64_t B, uint64_t seed,
+                        uint64_t frame, uint32_t step, int32_t *point, double *dirs, double *target)
+{
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < B; ++b) {
+        uint32_t ctr[4] = {(uint32_t)b, step, (uint32_t)frame, STREAM_TRAIN}, r[4];
+        oracle_philox(ctr, key, r);
+        int64_t p = (int64_t)(((uint64_t)r[0] * (uint64_t)P) >> 32);
+        point[b] = (int32_t)p;
+        double n[3] = {nx[p], ny[p], nz[p]};
+        cosine_direction(n, u24(r[1]), u24(r[2]), dirs + 3 * b);
+        double x[3] = {px[p], py[p], pz[p]};
+        field_eval(&L, x, dirs + 3 * b, target + 3 * b);
+    }
+}
