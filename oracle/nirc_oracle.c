@@ -66,18 +66,19 @@ static double u24(uint32_t r) { return (double)(r >> 8) * (1.0 / 16777216.0); }
 /* Counter streams of the method's random numbers. */
 enum { STREAM_CACHE_DIR = 3, STREAM_RESIDUAL_DIR = 4, STREAM_TRAIN = 5 };
 
-/* The two uniforms of sampled direction k of point p in frame f (cache directions come in
- * pairs from one Philox call; the residual direction uses its own stream). */
+/* The two uniforms of sampled direction k of point p in frame f.  One Philox block serves two
+ * directions: cache directions k and k+1 (k even) of a point share counter (p, k/2, f, 3); the
+ * residual directions of points p and p+1 (p even) share counter (p/2, 0, f, 4). */
 static void direction_uniforms(uint64_t seed, uint32_t p, int k, int residual, uint32_t frame,
                                double *u1, double *u2)
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t out[4];
     if (residual) {
-        uint32_t ctr[4] = {p, 0u, frame, STREAM_RESIDUAL_DIR};
+        uint32_t ctr[4] = {p >> 1, 0u, frame, STREAM_RESIDUAL_DIR};
         oracle_philox(ctr, key, out);
-        *u1 = u24(out[0]);
-        *u2 = u24(out[1]);
+        if (p & 1) { *u1 = u24(out[2]); *u2 = u24(out[3]); }
+        else       { *u1 = u24(out[0]); *u2 = u24(out[1]); }
     } else {
         uint32_t ctr[4] = {p, (uint32_t)(k >> 1), frame, STREAM_CACHE_DIR};
         oracle_philox(ctr, key, out);

@@ -127,7 +127,8 @@ def test_cosine_sampler_moments():
 def test_cosine_direction_from_philox_words():
     # direction k of point p: uniforms (r>>8)/2^24 from Philox(ctr=(p, k>>1, frame, 3)), words
     # (0,1) for even k and (2,3) for odd k; the local frame's z axis is the normal, so n.w is
-    # sqrt(1-u1) whatever basis is chosen.
+    # sqrt(1-u1) whatever basis is chosen.  Residual directions of points p, p+1 (p even) share
+    # counter (p/2, 0, frame, 4).
     pts = wl.make_points(21, 5)
     seed, frame = 0x1234_5678_9ABC, 3
     d = oracle.sample_dirs(pts, 4, seed, frame)
@@ -138,8 +139,8 @@ def test_cosine_direction_from_philox_words():
             r = oracle.philox([p, k >> 1, frame, 3], key)
             u1 = (int(r[2 * (k & 1)]) >> 8) / 2.0 ** 24
             assert abs(d[p, k] @ n / (n @ n) - math.sqrt(1 - u1)) < 1e-7
-        r = oracle.philox([p, 0, frame, 4], key)
-        u1 = (int(r[0]) >> 8) / 2.0 ** 24
+        r = oracle.philox([p >> 1, 0, frame, 4], key)
+        u1 = (int(r[2 * (p & 1)]) >> 8) / 2.0 ** 24
         assert abs(d[p, 4] @ n / (n @ n) - math.sqrt(1 - u1)) < 1e-7
 
 
