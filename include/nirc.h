@@ -1,0 +1,215 @@
+/*
+ * nirc.h - C ABI of the MI355X (gfx950) library for the neural incident radiance cache (NIRC)
+ * and the two-level Monte Carlo estimator built on it.
+ *
+ * The method (Sec. "Neural Incident Radiance Cache"):
+ *   - the cache n(x, w, phi; W) is a small MLP that predicts incident radiance at a shading point
+ *     x with features phi (normal, roughness) for an incident direction w (eq. 11);
+ *   - the two-level estimator of the reflected radiance is
+ *       L_o = L_c + L_r  (eq. L_mlmc, emission omitted),
+ *       L_c = (1/N) sum_k n(x, w_k) f_r cos / p       over N cache directions   (eq. L_c),
+ *       L_r = (L_i(x, w_r) - n(x, w_r)) f_r cos / p   over one independent direction (eq. L_r),
+ *     which is unbiased whatever the cache weights are (eq. Fc, Fr, Fml);
+ *   - the cache is trained online, several Adam steps per frame, with a relative L2 loss whose
+ *     denominator is excluded from differentiation (eq. 12).
+ * The library uses a white Lambertian BRDF (f_r = 1/pi) with cosine-weighted directions, so
+ * f_r cos / p = 1: L_c is the mean of the N cache predictions and L_r is target minus cache.
+ *
+ * Network: 10 inputs (x[3], w[3], n[3], roughness) -> sin/cos(2^k pi v), k = 0..7 -> 160
+ * features -> 4 hidden ReLU layers of `width` -> 3 outputs -> exp.  No biases.  Canonical
+ * parameter vector (FP32, row-major per layer, layers concatenated): W1 [width x 160],
+ * W2, W3, W4 [width x width], W5 [3 x width]; feature 16*i + 2*k + (0 sin | 1 cos) of input i
+ * in the order (x0, x1, x2, w0, w1, w2, n0, n1, n2, roughness).
+ *
+ * Conventions for every entry point:
+ *   - pointers are DEVICE pointers unless the comment says host; the caller owns all memory
+ *     (model state and workspace included) and the library never allocates device memory;
+ *   - every call only enqueues work on `stream` (a hipStream_t; NULL = the null stream) and
+ *     returns without synchronising;
+ *   - argument and shape errors are reported synchronously, before anything is enqueued, as a
+ *     negative nirc_status; a failed kernel launch returns NIRC_ERR_HIP;
+ *   - numeric faults in training (a non-finite loss or gradient) never trap: the Adam update is
+ *     skipped on the device and a flag is raised (nirc_read_flags);
+ *   - one model must not be used on two streams at once; distinct models may run concurrently.
+ */
+#ifndef NIRC_H
+#define NIRC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nirc_status;
+#define NIRC_OK 0
+#define NIRC_ERR_INVALID_ARG (-1)
+#define NIRC_ERR_UNSUPPORTED (-2)
+#define NIRC_ERR_WORKSPACE (-3)   /* state or workspace buffer too small */
+#define NIRC_ERR_HIP (-5)
+
+/* Arithmetic of the MLP layer products (FP32 accumulation in every case). */
+#define NIRC_FP32 0
+#define NIRC_BF16 1
+#define NIRC_FP16 2
+
+/* Device flags raised by training (sticky until nirc_clear_flags). */
+#define NIRC_FLAG_NONFINITE_GRAD 1u   /* a step saw a non-finite loss/gradient and was skipped */
+
+typedef struct nirc_model nirc_model;   /* opaque host handle */
+
+/* Host struct.  Adam hyper-parameters follow Kingma & Ba; the paper trains with Adam, several
+ * steps per frame (Sec. "Results").  loss_eps is the epsilon of the relative L2 loss (eq. 12).
+ * loss_scale multiplies the loss before the backward pass and divides the gradient after it. */
+typedef struct {
+    int32_t width;       /* hidden width: 64 (128 reserved) */
+    int32_t precision;   /* NIRC_FP32 | NIRC_BF16 | NIRC_FP16 */
+    float lr;            /* e.g. 1e-3 */
+    float beta1;         /* e.g. 0.9 */
+    float beta2;         /* e.g. 0.999 */
+    float adam_eps;      /* e.g. 1e-8 */
+    float loss_eps;      /* e.g. 1e-2 */
+    float loss_scale;    /* e.g. 1 (FP32/BF16); > 1 for FP16 */
+} nirc_config;
+
+/* Shading points, structure of arrays, FP32 device arrays of `count` entries each. */
+typedef struct {
+    const float *px, *py, *pz;   /* position */
+    const float *nx, *ny, *nz;   /* unit normal */
+    const float *rough;          /* roughness */
+    int64_t count;
+} nirc_points;
+
+/* Cache queries: a direction per query and the index of its shading point (point == NULL
+ * means query i uses point i).  FP32 / int32 device arrays of `count` entries.  Point indices
+ * outside [0, points.count) are clamped into range by the kernels. */
+typedef struct {
+    const float *wx, *wy, *wz;
+    const int32_t *point;
+    int64_t count;
+} nirc_queries;
+
+/* Synthetic incident radiance field standing in for path-traced radiance (host struct, passed
+ * by pointer and copied at the call): L_c(x, w) = sum_j a_jc(x) exp(kappa_j (mu_j . w - 1)),
+ * a_jc(x) = alpha_jc + sum_d beta_jcd x_d.  The record is 64 floats in this order. */
+typedef struct {
+    float axis[4][3];
+    float kappa[4];
+    float alpha[4][3];
+    float beta[4][3][3];
+} nirc_lobes;
+
+/* ------------------------------------------------------------------------------------------ */
+/* Sizes and model lifetime                                                                   */
+
+/* Number of parameters of the canonical vector: width*160 + 3*width^2 + 3*width; 0 if the
+ * width is unsupported. */
+int64_t nirc_n_params(int32_t width);
+
+/* Bytes of model state (FP32 master weights, Adam moments, step counter, flags and the packed
+ * copy the kernels read).  0 if the configuration is invalid. */
+size_t nirc_state_bytes(const nirc_config *cfg /* host */);
+
+/* Bytes of workspace needed by training calls on batches of up to max_batch queries
+ * (per-workgroup gradient partials, reduced gradient, loss).  Inference needs none. */
+size_t nirc_workspace_bytes(const nirc_config *cfg /* host */, int64_t max_batch);
+
+/* Create a model over caller-owned device buffers.  `state` must hold nirc_state_bytes and be
+ * 256-byte aligned; `workspace` may be NULL (no training) or hold nirc_workspace_bytes(cfg, B).
+ * `init_w` is the canonical FP32 parameter vector (device).  Adam moments and the step counter
+ * start at zero.  *out receives a host handle, freed by nirc_destroy (which frees no device
+ * memory). */
+nirc_status nirc_create(const nirc_config *cfg /* host */, void *state, size_t state_bytes,
+                        void *workspace, size_t workspace_bytes, const float *init_w,
+                        void *stream, nirc_model **out /* host */);
+nirc_status nirc_destroy(nirc_model *model);
+
+/* Replace the weights (canonical FP32, device) and reset Adam (moments and step). */
+nirc_status nirc_set_weights(nirc_model *model, const float *w, void *stream);
+/* Copy the FP32 master weights to `w` (canonical, device). */
+nirc_status nirc_get_weights(const nirc_model *model, float *w, void *stream);
+/* Copy the Adam state: m and v (canonical FP32, device, may be NULL) and the step counter
+ * (device int64, may be NULL). */
+nirc_status nirc_get_adam(const nirc_model *model, float *m, float *v, int64_t *step, void *stream);
+
+/* Sticky device flags (NIRC_FLAG_*).  Reads them synchronously on `stream` (host call that
+ * waits for the stream); returns 0xFFFFFFFF on error. */
+uint32_t nirc_read_flags(const nirc_model *model, void *stream);
+nirc_status nirc_clear_flags(nirc_model *model, void *stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Inference                                                                                   */
+
+/* The 160 input features of each query (Sec. "Neural Network Architecture": the network sees
+ * an encoding of the position, the direction and the surface features).  features is
+ * [queries.count][160] FP32 in canonical feature order. */
+nirc_status nirc_encode(nirc_points points, nirc_queries queries, float *features, void *stream);
+
+/* Cache predictions n(x, w) for explicit queries (eq. 11's network term): rgb is
+ * [queries.count][3] FP32.  Every query is evaluated independently (no sharing of the surface
+ * encoding between queries of one point). */
+nirc_status nirc_infer(const nirc_model *model, nirc_points points, nirc_queries queries,
+                       float *rgb, void *stream);
+
+/* The sampled directions the estimator uses (Sec. "Cache application": independent BSDF
+ * sampling for the cache and the residual).  dirs is [points.count][n_cache + 1][3] FP32; entry
+ * n_cache of each point is the residual direction.  Cosine-weighted about the normal, from
+ * Philox4x32-10 with key (seed lo, seed hi): cache direction k of point p uses counter
+ * (p, k >> 1, frame, 3), words (0,1) for even k and (2,3) for odd k; the residual direction of
+ * p uses counter (p >> 1, 0, frame, 4), words (0,1) for even p and (2,3) for odd p.  A word r
+ * gives u = (r >> 8) 2^-24. */
+nirc_status tlmc_sample_dirs(nirc_points points, int32_t n_cache, uint64_t seed, uint64_t frame,
+                             float *dirs, void *stream);
+
+/* The two-level estimator per shading point and channel (eq. L_mlmc, L_c, L_r):
+ *   out_c  = (1/N) sum_k n(x, w_k)         (cache level, N = n_cache >= 1)
+ *   out_r  = L(x, w_r) - n(x, w_r)          (residual; L from `field`)
+ *   out_tl = out_c + out_r
+ * Directions are generated in the kernel exactly as tlmc_sample_dirs returns them.  The
+ * surface part of the first layer is computed once per point and shared by its N + 1 queries
+ * (Sec. "Neural Network Architecture": amortised surface encoding).  out_c and out_r may be
+ * NULL.  All outputs are [points.count][3] FP32. */
+nirc_status tlmc_estimate(const nirc_model *model, nirc_points points,
+                          const nirc_lobes *field /* host */, int32_t n_cache, uint64_t seed,
+                          uint64_t frame, float *out_tl, float *out_c, float *out_r, void *stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Training                                                                                    */
+
+/* Training samples (stand-in for the paper's separate training pass, Sec. "Cache
+ * application"): sample b of step `step` in `frame` draws Philox counter (b, step, frame, 5):
+ * word 0 picks the point floor(r0 * count / 2^32), words 1 and 2 a cosine-weighted direction
+ * about its normal; the target is the field's radiance there.  Outputs: point [batch] int32,
+ * wx, wy, wz [batch] FP32 and target [batch][3] FP32. */
+nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field /* host */, int64_t batch,
+                             uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
+                             float *wx, float *wy, float *wz, float *target, void *stream);
+
+/* Gradient of the relative L2 loss (eq. 12, on radiance, stop-gradient denominator):
+ *   loss = (1/(3B)) sum_{b,c} (y - t)^2 / (sg(y)^2 + loss_eps)
+ * w.r.t. the weights, written to grad [n_params] (canonical FP32); loss (device float, may be
+ * NULL) receives the loss.  Needs the workspace.  Deterministic (fixed reduction order). */
+nirc_status nirc_loss_grad(nirc_model *model, nirc_points points, nirc_queries queries,
+                           const float *target, float *grad, float *loss, void *stream);
+
+/* Vector-Jacobian product for automatic differentiation: grad = d(sum_q,c d_rgb[q][c] *
+ * y[q][c]) / dW for the predictions y of nirc_infer.  Needs the workspace. */
+nirc_status nirc_backward(nirc_model *model, nirc_points points, nirc_queries queries,
+                          const float *d_rgb, float *grad, void *stream);
+
+/* One Adam step with the given gradient (canonical FP32); skipped, with
+ * NIRC_FLAG_NONFINITE_GRAD raised, if any gradient entry is not finite. */
+nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream);
+
+/* nirc_loss_grad followed by nirc_adam_step on the workspace gradient. */
+nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries queries,
+                            const float *target, float *loss, void *stream);
+
+const char *nirc_status_string(nirc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NIRC_H */

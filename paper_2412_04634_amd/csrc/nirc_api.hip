@@ -1,0 +1,318 @@
+// C ABI of the NIRC library: argument validation, state/workspace layout and kernel launches.
+#include <new>
+#include <string.h>
+
+#include "nirc_kernels.hpp"
+
+using namespace nirc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool width_ok(int32_t w) { return w == 64; }
+
+// State layout (each piece 256-byte aligned): master | m | v | packed | step | flags | bad.
+struct StateLayout {
+    size_t master, m, v, packed, step, flags, bad, total;
+    explicit StateLayout(int W) {
+        const size_t np = (size_t)n_params(W) * sizeof(float);
+        size_t o = 0;
+        master = o; o += align_up(np);
+        m = o; o += align_up(np);
+        v = o; o += align_up(np);
+        packed = o; o += align_up((size_t)F32Layout{W}.total() * sizeof(float));
+        step = o; o += align_up(sizeof(int64_t));
+        flags = o; o += align_up(sizeof(uint32_t));
+        bad = o; o += align_up(sizeof(uint32_t));
+        total = o;
+    }
+};
+
+// Workspace layout: partials [nblocks][np] | loss partials [nblocks] | grad [np] | loss.
+struct WorkLayout {
+    size_t partials, loss_partials, grad, loss, total;
+    WorkLayout(int W, int nblocks) {
+        const size_t np = (size_t)n_params(W);
+        size_t o = 0;
+        partials = o; o += align_up((size_t)nblocks * np * sizeof(float));
+        loss_partials = o; o += align_up((size_t)nblocks * sizeof(float));
+        grad = o; o += align_up(np * sizeof(float));
+        loss = o; o += align_up(sizeof(float));
+        total = o;
+    }
+};
+
+nirc_status check_points(const nirc_points &p) {
+    if (p.count < 0 || p.count > INT32_MAX) return NIRC_ERR_INVALID_ARG;
+    if (p.count > 0 && (!p.px || !p.py || !p.pz || !p.nx || !p.ny || !p.nz || !p.rough))
+        return NIRC_ERR_INVALID_ARG;
+    return NIRC_OK;
+}
+
+nirc_status check_queries(const nirc_queries &q, const nirc_points &p) {
+    if (q.count < 0) return NIRC_ERR_INVALID_ARG;
+    if (q.count > 0 && (!q.wx || !q.wy || !q.wz)) return NIRC_ERR_INVALID_ARG;
+    if (q.count > 0 && p.count == 0) return NIRC_ERR_INVALID_ARG;
+    if (!q.point && q.count > p.count) return NIRC_ERR_INVALID_ARG;
+    return NIRC_OK;
+}
+
+Points to_points(const nirc_points &p) { return Points{p.px, p.py, p.pz, p.nx, p.ny, p.nz, p.rough, p.count}; }
+Queries to_queries(const nirc_queries &q) { return Queries{q.wx, q.wy, q.wz, q.point, q.count}; }
+
+nirc_status hip_status(hipError_t e) { return e == hipSuccess ? NIRC_OK : NIRC_ERR_HIP; }
+
+}  // namespace
+
+struct nirc_model {
+    nirc_config cfg;
+    int W;
+    int64_t np;
+    float *master, *m, *v, *packed;
+    int64_t *step;
+    uint32_t *flags, *bad;
+    char *ws;
+    size_t ws_bytes;
+};
+
+extern "C" {
+
+const char *nirc_status_string(nirc_status s) {
+    switch (s) {
+    case NIRC_OK: return "ok";
+    case NIRC_ERR_INVALID_ARG: return "invalid argument";
+    case NIRC_ERR_UNSUPPORTED: return "unsupported configuration";
+    case NIRC_ERR_WORKSPACE: return "state or workspace buffer too small";
+    case NIRC_ERR_HIP: return "HIP error";
+    default: return "unknown status";
+    }
+}
+
+int64_t nirc_n_params(int32_t width) { return width_ok(width) ? n_params(width) : 0; }
+
+static nirc_status check_config(const nirc_config *cfg) {
+    if (!cfg) return NIRC_ERR_INVALID_ARG;
+    if (!width_ok(cfg->width)) return NIRC_ERR_UNSUPPORTED;
+    if (cfg->precision != NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
+    if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->adam_eps > 0.0f) ||
+        !(cfg->loss_eps > 0.0f) || !(cfg->loss_scale > 0.0f))
+        return NIRC_ERR_INVALID_ARG;
+    return NIRC_OK;
+}
+
+size_t nirc_state_bytes(const nirc_config *cfg) {
+    if (check_config(cfg) != NIRC_OK) return 0;
+    return StateLayout(cfg->width).total;
+}
+
+size_t nirc_workspace_bytes(const nirc_config *cfg, int64_t max_batch) {
+    if (check_config(cfg) != NIRC_OK || max_batch < 0) return 0;
+    return WorkLayout(cfg->width, train_blocks(max_batch)).total;
+}
+
+nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes, void *workspace,
+                        size_t workspace_bytes, const float *init_w, void *stream, nirc_model **out) {
+    nirc_status st = check_config(cfg);
+    if (st != NIRC_OK) return st;
+    if (!state || !init_w || !out || ((uintptr_t)state % kAlign) != 0) return NIRC_ERR_INVALID_ARG;
+    if (workspace && ((uintptr_t)workspace % kAlign) != 0) return NIRC_ERR_INVALID_ARG;
+    const StateLayout sl(cfg->width);
+    if (state_bytes < sl.total) return NIRC_ERR_WORKSPACE;
+    nirc_model *m = new (std::nothrow) nirc_model;
+    if (!m) return NIRC_ERR_INVALID_ARG;
+    char *base = (char *)state;
+    m->cfg = *cfg;
+    m->W = cfg->width;
+    m->np = n_params(m->W);
+    m->master = (float *)(base + sl.master);
+    m->m = (float *)(base + sl.m);
+    m->v = (float *)(base + sl.v);
+    m->packed = (float *)(base + sl.packed);
+    m->step = (int64_t *)(base + sl.step);
+    m->flags = (uint32_t *)(base + sl.flags);
+    m->bad = (uint32_t *)(base + sl.bad);
+    m->ws = (char *)workspace;
+    m->ws_bytes = workspace ? workspace_bytes : 0;
+    st = nirc_set_weights(m, init_w, stream);
+    if (st == NIRC_OK) {
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = launch_fill_u32(m->flags, 1, 0u, s);
+        if (e == hipSuccess) e = launch_fill_u32(m->bad, 1, 0u, s);
+        st = hip_status(e);
+    }
+    if (st != NIRC_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return NIRC_OK;
+}
+
+nirc_status nirc_destroy(nirc_model *model) {
+    delete model;
+    return NIRC_OK;
+}
+
+nirc_status nirc_set_weights(nirc_model *model, const float *w, void *stream) {
+    if (!model || !w) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_copy_f32(model->master, w, model->np, s);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->m, model->np, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->v, model->np, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->step, 2, 0u, s);
+    if (e == hipSuccess) e = launch_pack(model->packed, model->master, model->W, s);
+    return hip_status(e);
+}
+
+nirc_status nirc_get_weights(const nirc_model *model, float *w, void *stream) {
+    if (!model || !w) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_copy_f32(w, model->master, model->np, (hipStream_t)stream));
+}
+
+nirc_status nirc_get_adam(const nirc_model *model, float *m, float *v, int64_t *step, void *stream) {
+    if (!model) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (m) e = launch_copy_f32(m, model->m, model->np, s);
+    if (e == hipSuccess && v) e = launch_copy_f32(v, model->v, model->np, s);
+    if (e == hipSuccess && step) e = launch_copy_f32((float *)step, (const float *)model->step, 2, s);
+    return hip_status(e);
+}
+
+uint32_t nirc_read_flags(const nirc_model *model, void *stream) {
+    if (!model) return 0xFFFFFFFFu;
+    uint32_t f = 0;
+    if (hipMemcpyAsync(&f, model->flags, sizeof(f), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
+        return 0xFFFFFFFFu;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return 0xFFFFFFFFu;
+    return f;
+}
+
+nirc_status nirc_clear_flags(nirc_model *model, void *stream) {
+    if (!model) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_fill_u32(model->flags, 1, 0u, (hipStream_t)stream));
+}
+
+nirc_status nirc_encode(nirc_points points, nirc_queries queries, float *features, void *stream) {
+    nirc_status st = check_points(points);
+    if (st == NIRC_OK) st = check_queries(queries, points);
+    if (st != NIRC_OK) return st;
+    if (queries.count > 0 && !features) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_encode(to_points(points), to_queries(queries), features, (hipStream_t)stream));
+}
+
+nirc_status nirc_infer(const nirc_model *model, nirc_points points, nirc_queries queries, float *rgb,
+                       void *stream) {
+    if (!model) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points(points);
+    if (st == NIRC_OK) st = check_queries(queries, points);
+    if (st != NIRC_OK) return st;
+    if (queries.count > 0 && !rgb) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_infer(model->W, to_points(points), to_queries(queries), model->packed, rgb,
+                                   (hipStream_t)stream));
+}
+
+nirc_status tlmc_sample_dirs(nirc_points points, int32_t n_cache, uint64_t seed, uint64_t frame,
+                             float *dirs, void *stream) {
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK) return st;
+    if (n_cache < 1 || n_cache > 4096 || (points.count > 0 && !dirs)) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_sample_dirs(to_points(points), n_cache, seed, frame, dirs, (hipStream_t)stream));
+}
+
+nirc_status tlmc_estimate(const nirc_model *model, nirc_points points, const nirc_lobes *field,
+                          int32_t n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
+                          float *out_r, void *stream) {
+    if (!model || !field) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK) return st;
+    if (n_cache < 1 || n_cache > 4096 || (points.count > 0 && !out_tl)) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_tlmc(model->W, to_points(points), *field, model->packed, n_cache, seed, frame,
+                                  out_tl, out_c, out_r, (hipStream_t)stream));
+}
+
+nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field, int64_t batch, uint64_t seed,
+                             uint64_t frame, uint32_t step, int32_t *point, float *wx, float *wy, float *wz,
+                             float *target, void *stream) {
+    if (!field || batch < 0 || batch > INT32_MAX) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK) return st;
+    if (batch > 0 && (points.count == 0 || !point || !wx || !wy || !wz || !target)) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_train_batch(to_points(points), *field, batch, seed, frame, step, point, wx, wy, wz,
+                                         target, (hipStream_t)stream));
+}
+
+// Gradient partials + reduction into `grad`/`loss`; the step's `bad` flag is raised on a
+// non-finite value.
+static nirc_status grad_into(nirc_model *model, const nirc_points &points, const nirc_queries &queries,
+                             const float *target, const float *d_rgb, float *grad, float *loss,
+                             hipStream_t s) {
+    nirc_status st = check_points(points);
+    if (st == NIRC_OK) st = check_queries(queries, points);
+    if (st != NIRC_OK) return st;
+    if (queries.count < 1 || !grad) return NIRC_ERR_INVALID_ARG;
+    const int nb = train_blocks(queries.count);
+    const WorkLayout wl(model->W, nb);
+    if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
+    float *partials = (float *)(model->ws + wl.partials);
+    float *lpart = (float *)(model->ws + wl.loss_partials);
+    TrainArgs a{target, d_rgb, model->cfg.loss_eps, model->cfg.loss_scale};
+    hipError_t e = launch_grad_partials(model->W, to_points(points), to_queries(queries), model->packed, a,
+                                        partials, lpart, nb, s);
+    if (e != hipSuccess) return NIRC_ERR_HIP;
+    const float loss_norm = 1.0f / (3.0f * (float)queries.count);
+    e = launch_reduce_grad(model->W, partials, lpart, nb, 1.0f / model->cfg.loss_scale, loss_norm, grad, loss,
+                           model->bad, s);
+    return hip_status(e);
+}
+
+nirc_status nirc_loss_grad(nirc_model *model, nirc_points points, nirc_queries queries, const float *target,
+                           float *grad, float *loss, void *stream) {
+    if (!model || !target) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss, s);
+    if (st != NIRC_OK) return st;
+    // a standalone gradient does not start a step: clear the step's flag again
+    return hip_status(launch_fill_u32(model->bad, 1, 0u, s));
+}
+
+nirc_status nirc_backward(nirc_model *model, nirc_points points, nirc_queries queries, const float *d_rgb,
+                          float *grad, void *stream) {
+    if (!model || !d_rgb) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    nirc_status st = grad_into(model, points, queries, nullptr, d_rgb, grad, nullptr, s);
+    if (st != NIRC_OK) return st;
+    return hip_status(launch_fill_u32(model->bad, 1, 0u, s));
+}
+
+nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream) {
+    if (!model || !grad) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_check_finite(model->W, grad, model->bad, s);
+    if (e == hipSuccess)
+        e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags, model->bad,
+                        model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps, model->packed, s);
+    return hip_status(e);
+}
+
+nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries queries, const float *target,
+                            float *loss, void *stream) {
+    if (!model || !target) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = train_blocks(queries.count);
+    const WorkLayout wl(model->W, nb);
+    if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
+    float *grad = (float *)(model->ws + wl.grad);
+    float *wloss = (float *)(model->ws + wl.loss);
+    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss ? loss : wloss, s);
+    if (st != NIRC_OK) return st;
+    return hip_status(launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
+                                  model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2,
+                                  model->cfg.adam_eps, model->packed, s));
+}
+
+}  // extern "C"

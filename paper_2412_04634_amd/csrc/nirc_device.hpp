@@ -1,0 +1,238 @@
+// Device building blocks of the NIRC library for gfx950 (CDNA4): counter-based random numbers,
+// cosine-weighted sampling, the sin/cos input encoding, MFMA wrappers and the packed weight
+// layout that lets consecutive MLP layers chain through registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nirc.h"
+
+namespace nirc {
+
+constexpr int kInputs = 10;
+constexpr int kFreq = 8;
+constexpr int kFeat = 160;
+constexpr int kSurfInputs = 7;   // x0 x1 x2 n0 n1 n2 roughness
+constexpr int kDirInputs = 3;    // w0 w1 w2
+constexpr int kStreamCacheDir = 3, kStreamResidualDir = 4, kStreamTrain = 5;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Canonical input index (x, w, n, roughness order) of surface input s.
+__host__ __device__ constexpr int surf_input(int s) { return s < 3 ? s : s + 3; }
+
+struct Points {
+    const float *px, *py, *pz, *nx, *ny, *nz, *rough;
+    int64_t count;
+};
+
+struct Queries {
+    const float *wx, *wy, *wz;
+    const int32_t *point;
+    int64_t count;
+};
+
+// Point index of query i: explicit (clamped into [0, count) so that a bad index can never read
+// out of bounds) or i itself.
+__device__ inline int64_t query_point(const Queries &q, const Points &p, int64_t i) {
+    if (!q.point) return i;
+    const int64_t j = q.point[i];
+    return j < 0 ? 0 : (j >= p.count ? p.count - 1 : j);
+}
+
+// ------------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): multiply-xor rounds on a 4x32 counter, key bumped by
+// the Weyl constants between rounds.
+struct Rand4 {
+    uint32_t r[4];
+};
+
+__device__ inline Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                               uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return Rand4{{c0, c1, c2, c3}};
+}
+
+// 24-bit uniform in [0, 1), exact in FP32.
+__device__ inline float u24(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
+
+// Cosine-weighted direction about unit normal n from uniforms (u1, u2): local
+// (sqrt(u1) cos 2pi u2, sqrt(u1) sin 2pi u2, sqrt(1 - u1)) in the branchless orthonormal basis
+// of Duff et al. (JCGT 2017).  Contraction is off so that every kernel that inlines this
+// produces bit-identical directions.
+__device__ inline void cosine_dir(float nx, float ny, float nz, float u1, float u2, float &wx,
+                                  float &wy, float &wz) {
+#pragma clang fp contract(off)
+    const float r = sqrtf(u1);
+    float s2, c2;
+    sincospif(2.0f * u2, &s2, &c2);
+    const float lx = r * c2, ly = r * s2, lz = sqrtf(1.0f - u1);
+    const float s = nz >= 0.0f ? 1.0f : -1.0f;
+    const float a = -1.0f / (s + nz);
+    const float b = nx * ny * a;
+    const float tx = 1.0f + s * nx * nx * a, ty = s * b, tz = -s * nx;
+    const float bx = b, by = s + ny * ny * a, bz = -ny;
+    wx = lx * tx + ly * bx + lz * nx;
+    wy = lx * ty + ly * by + lz * ny;
+    wz = lx * tz + ly * bz + lz * nz;
+}
+
+// Philox counter of a sampled direction and which word pair it uses.  Cache direction k of
+// point p: (p, k >> 1, frame, 3), pair k & 1.  Residual direction of p: (p >> 1, 0, frame, 4),
+// pair p & 1.
+struct DirCounter {
+    uint32_t c0, c1;
+    uint32_t stream;
+    int half;
+};
+
+__device__ inline DirCounter dir_counter(uint32_t p, int k, bool residual) {
+    if (residual) return DirCounter{p >> 1, 0u, (uint32_t)kStreamResidualDir, (int)(p & 1u)};
+    return DirCounter{p, (uint32_t)k >> 1, (uint32_t)kStreamCacheDir, k & 1};
+}
+
+__device__ inline void dir_from_rand(const Rand4 &r, int half, float nx, float ny, float nz,
+                                     float &wx, float &wy, float &wz) {
+    const uint32_t a = half ? r.r[2] : r.r[0];
+    const uint32_t b = half ? r.r[3] : r.r[1];
+    cosine_dir(nx, ny, nz, u24(a), u24(b), wx, wy, wz);
+}
+
+// ------------------------------------------------------------------------------------------
+// Radiance field (stand-in for path-traced radiance): sum of four spherical-Gaussian lobes
+// with amplitudes linear in x.
+__device__ inline void field_eval(const nirc_lobes &L, float x0, float x1, float x2, float wx,
+                                  float wy, float wz, float out[3]) {
+    out[0] = out[1] = out[2] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float mw = L.axis[j][0] * wx + L.axis[j][1] * wy + L.axis[j][2] * wz;
+        const float g = expf(L.kappa[j] * (mw - 1.0f));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float a = L.alpha[j][c] + L.beta[j][c][0] * x0 + L.beta[j][c][1] * x1 +
+                            L.beta[j][c][2] * x2;
+            out[c] += a * g;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// MFMA wrappers (wave64).  16x16x4 FP32: lane l holds A[row l%16][k l/16], B[k l/16][col l%16];
+// the 16x16 result gives lane l rows 4(l/16)+i, i = 0..3, of column l%16.
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Exact-argument sin/cos(pi * 2^k * v): 2^k v is exact in FP32, sincospif reduces exactly.
+__device__ inline void enc_pair(float v, int k, float &s, float &c) {
+    sincospif(ldexpf(v, k), &s, &c);
+}
+
+// ------------------------------------------------------------------------------------------
+// Packed weights for the FP32 MFMA chain.
+//
+// Each layer product is computed as H^T = W X^T with the weights as the MFMA A operand and the
+// queries as the 16 columns of B.  The result leaves lane l with neurons 16m + 4(l/16) + i of
+// query l%16 (m = row tile, i = 0..3).  Reading K-block b = 4m + i of the next layer as "lane
+// group g holds neuron 16m + 4g + i" turns those registers into the next B operand with no data
+// movement, provided the next layer's weight columns are permuted to match; the packed copy
+// stores every layer's A fragments in that order:
+//   fragment (mt, kb), lane l: row 16 mt + l%16, K position 4 kb + l/16,
+//   stored at [mt][kb / 4][lane][kb % 4] so that one 16-byte LDS read fetches 4 K-blocks.
+// Input features are produced directly in B layout: lane group g computes frequencies 2g and
+// 2g+1 of every input, so its t-th feature (t = 4 i + 2 f + sc) is input i, frequency 2g + f,
+// sin (sc = 0) or cos (sc = 1), placed in K-block t at position g.
+//
+// Sections (W = hidden width):
+//   S   W1 surface columns    MT = W/16, KB = 28   (x0 x1 x2 n0 n1 n2 r)
+//   D   W1 direction columns  MT = W/16, KB = 12   (w0 w1 w2)
+//   H0..H2  W2, W3, W4        MT = W/16, KB = W/4
+//   O   W5 (3 rows padded)    MT = 1,    KB = W/4
+//   T0..T2  W2^T, W3^T, W4^T  MT = W/16, KB = W/4  (backward: delta_{l-1} = W_l^T delta_l)
+//   OT  W5^T                  MT = W/16, KB = 4    (K = output rows padded to 16)
+enum Section { SEC_S = 0, SEC_D, SEC_H0, SEC_H1, SEC_H2, SEC_O, SEC_T0, SEC_T1, SEC_T2, SEC_OT, SEC_N };
+
+struct F32Layout {
+    int W;
+    __host__ __device__ constexpr int mt(int s) const {
+        return (s == SEC_O) ? 1 : W / 16;
+    }
+    __host__ __device__ constexpr int kb(int s) const {
+        return s == SEC_S ? 28 : s == SEC_D ? 12 : s == SEC_OT ? 4 : W / 4;
+    }
+    __host__ __device__ constexpr int size(int s) const { return mt(s) * kb(s) * 64; }
+    __host__ __device__ constexpr int offset(int s) const {
+        int o = 0;
+        for (int i = 0; i < s; ++i) o += size(i);
+        return o;
+    }
+    __host__ __device__ constexpr int total() const { return offset(SEC_N); }
+};
+
+// Canonical offsets of the five weight matrices.
+__host__ __device__ constexpr int64_t w_offset(int W, int layer) {
+    return layer == 0 ? 0 : (int64_t)W * kFeat + (int64_t)(layer - 1) * W * W;
+}
+__host__ __device__ constexpr int64_t n_params(int W) {
+    return (int64_t)W * kFeat + 3LL * W * W + 3LL * W;
+}
+
+// Canonical feature index of lane group g's t-th feature of a surface (surface = true, t < 28)
+// or direction (t < 12) encoding.
+__host__ __device__ inline int feature_of(bool surface, int g, int t) {
+    const int i = t >> 2, f = (t >> 1) & 1, sc = t & 1;
+    const int input = surface ? surf_input(i) : 3 + i;
+    return 16 * input + 2 * (2 * g + f) + sc;
+}
+
+// Hidden-layer neuron held at K position (kb, g) of a chained B operand.
+__host__ __device__ inline int chained_neuron(int kb, int g) {
+    return 16 * (kb >> 2) + 4 * g + (kb & 3);
+}
+
+// Canonical parameter index of packed FP32 element e (or -1 for zero padding).
+__host__ __device__ inline int64_t f32_packed_source(int W, int e) {
+    const F32Layout L{W};
+    int s = 0;
+    while (s + 1 < SEC_N && e >= L.offset(s + 1)) ++s;
+    const int r = e - L.offset(s);
+    const int KB = L.kb(s);
+    const int kk = r & 3, lane = (r >> 2) & 63, rest = r >> 8;   // rest = mt * (KB/4) + kq
+    const int kq = rest % (KB / 4), m = rest / (KB / 4);
+    const int kb = 4 * kq + kk;
+    const int row = 16 * m + (lane & 15), g = lane >> 4;
+    switch (s) {
+    case SEC_S: return w_offset(W, 0) + (int64_t)row * kFeat + feature_of(true, g, kb);
+    case SEC_D: return w_offset(W, 0) + (int64_t)row * kFeat + feature_of(false, g, kb);
+    case SEC_H0: case SEC_H1: case SEC_H2:
+        return w_offset(W, 1 + (s - SEC_H0)) + (int64_t)row * W + chained_neuron(kb, g);
+    case SEC_O:
+        return row < 3 ? w_offset(W, 4) + (int64_t)row * W + chained_neuron(kb, g) : -1;
+    case SEC_T0: case SEC_T1: case SEC_T2:
+        // A = W_l^T: row = input neuron of W_l, K = output neuron of W_l (chained order)
+        return w_offset(W, 1 + (s - SEC_T0)) + (int64_t)chained_neuron(kb, g) * W + row;
+    case SEC_OT: {
+        const int o = 4 * g + kb;   // output row held at K position (kb, g)
+        return o < 3 ? w_offset(W, 4) + (int64_t)o * W + row : -1;
+    }
+    default: return -1;
+    }
+}
+
+}  // namespace nirc

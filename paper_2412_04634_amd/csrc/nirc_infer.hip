@@ -1,0 +1,411 @@
+// Inference-side kernels: weight packing, input encoding, direction sampling, training-sample
+// generation, per-query cache inference and the fused two-level estimator.
+#include "nirc_kernels.hpp"
+
+namespace nirc {
+
+// ------------------------------------------------------------------------------------------
+// Small utilities
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_copy_f32(float *dst, const float *src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// packed[e] = master[source(e)] (zero padding where the fragment has no weight).
+__global__ void k_pack_f32(float *packed, const float *master, int W, int total) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t s = f32_packed_source(W, e);
+    packed[e] = s >= 0 ? master[s] : 0.0f;
+}
+
+// ------------------------------------------------------------------------------------------
+// Encoding: one thread per (query, input); 16 features each, canonical order.
+__global__ void k_encode(Points pts, Queries q, float *feat) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= q.count * kInputs) return;
+    const int64_t qi = t / kInputs;
+    const int i = (int)(t - qi * kInputs);
+    const int64_t p = query_point(q, pts, qi);
+    float v;
+    switch (i) {
+    case 0: v = pts.px[p]; break;
+    case 1: v = pts.py[p]; break;
+    case 2: v = pts.pz[p]; break;
+    case 3: v = q.wx[qi]; break;
+    case 4: v = q.wy[qi]; break;
+    case 5: v = q.wz[qi]; break;
+    case 6: v = pts.nx[p]; break;
+    case 7: v = pts.ny[p]; break;
+    case 8: v = pts.nz[p]; break;
+    default: v = pts.rough[p]; break;
+    }
+    float *o = feat + qi * kFeat + 16 * i;
+#pragma unroll
+    for (int k = 0; k < kFreq; ++k) enc_pair(v, k, o[2 * k], o[2 * k + 1]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Sampled directions, one thread per (point, k): [P][N+1][3], entry N = residual.
+__global__ void k_sample_dirs(Points pts, int n_cache, uint32_t key0, uint32_t key1,
+                              uint32_t frame, float *dirs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = n_cache + 1;
+    if (t >= pts.count * per) return;
+    const int64_t p = t / per;
+    const int k = (int)(t - p * per);
+    const DirCounter c = dir_counter((uint32_t)p, k, k == n_cache);
+    const Rand4 r = philox(c.c0, c.c1, frame, c.stream, key0, key1);
+    float wx, wy, wz;
+    dir_from_rand(r, c.half, pts.nx[p], pts.ny[p], pts.nz[p], wx, wy, wz);
+    dirs[3 * t + 0] = wx;
+    dirs[3 * t + 1] = wy;
+    dirs[3 * t + 2] = wz;
+}
+
+// Training samples: one thread per sample.
+__global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint32_t key0,
+                              uint32_t key1, uint32_t frame, uint32_t step, int32_t *point,
+                              float *wx, float *wy, float *wz, float *target) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const Rand4 r = philox((uint32_t)b, step, frame, (uint32_t)kStreamTrain, key0, key1);
+    const int64_t p = (int64_t)(((uint64_t)r.r[0] * (uint64_t)pts.count) >> 32);
+    float x, y, z;
+    cosine_dir(pts.nx[p], pts.ny[p], pts.nz[p], u24(r.r[1]), u24(r.r[2]), x, y, z);
+    float L[3];
+    field_eval(lobes, pts.px[p], pts.py[p], pts.pz[p], x, y, z, L);
+    point[b] = (int32_t)p;
+    wx[b] = x;
+    wy[b] = y;
+    wz[b] = z;
+    target[3 * b + 0] = L[0];
+    target[3 * b + 1] = L[1];
+    target[3 * b + 2] = L[2];
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-query cache inference (every query encodes its own surface features): a wave takes 16
+// queries at a time; the first layer runs over all 160 features.
+template <int W, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
+                                                          const float *__restrict__ packed,
+                                                          float *__restrict__ rgb) {
+    constexpr F32Layout L{W};
+    constexpr int MT = W / 16;
+    constexpr int NW = InferLds<W>::kWeights;
+    __shared__ f32x4 smem4[NW / 4];
+    const float *smem = (const float *)smem4;
+    {
+        const f32x4 *src = (const f32x4 *)(packed + L.offset(SEC_D));
+        for (int i = threadIdx.x; i < NW / 4; i += WAVES * 64) smem4[i] = src[i];
+    }
+    __syncthreads();
+    const float *sD = smem;
+    const float *sH = smem + L.size(SEC_D);
+    const float *sO = sH + 3 * L.size(SEC_H0);
+    const float *gS = packed + L.offset(SEC_S);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t Q = q.count;
+    const int64_t n_tiles = (Q + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < n_tiles;
+         tile += (int64_t)gridDim.x * WAVES) {
+        const int64_t qi = min((tile << 4) + col, Q - 1);
+        const int64_t p = query_point(q, pts, qi);
+        const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+        const float ws[3] = {q.wx[qi], q.wy[qi], q.wz[qi]};
+        f32x4 h[1][MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) h[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer1_surface<W>(h[0], opaque(gS), xs, lane, g);
+        float dx[1] = {ws[0]}, dy[1] = {ws[1]}, dz[1] = {ws[2]};
+        layer1_direction<W, 1>(h, sD, dx, dy, dz, lane, g, 1);
+        relu_all<W, 1>(h, 1);
+        hidden_layers<W, 1>(h, sH, lane, 1);
+        f32x4 y[1];
+        output_layer<W, 1>(y, h, sO, lane, 1);
+        if (g == 0 && (tile << 4) + col < Q) {
+            float *o = rgb + 3 * ((tile << 4) + col);
+            o[0] = expf(y[0][0]);
+            o[1] = expf(y[0][1]);
+            o[2] = expf(y[0][2]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused two-level estimator.
+//
+// A wave owns 16 shading points at a time.  It encodes their surface inputs once and projects
+// them through the surface columns of the first layer (h_s = W1_s e_s, one MFMA pass for the
+// 16 points), keeping h_s in a per-wave LDS slab.  The point group's queries are laid out as
+// N cache tiles (query q = 16 t + column -> point q / N, direction q % N) followed by one
+// residual tile (column j -> point j).  Directions for 8 tiles (128 queries) are generated at a
+// time, one Philox block per lane giving two directions, and staged in the slab; the MLP then
+// runs 4 tiles at a time with h_s of each column's point as the first layer's accumulator
+// input, chains the hidden layers through registers and leaves RGB in lanes 0..15.  Cache
+// results are summed per point with a 16-lane prefix sum; the residual tile evaluates the
+// field and subtracts.  Only the final per-point values leave the chip.
+template <int W, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes lobes,
+                                                         const float *__restrict__ packed,
+                                                         int n_cache, uint32_t key0, uint32_t key1,
+                                                         uint32_t frame, float *__restrict__ out_tl,
+                                                         float *__restrict__ out_c,
+                                                         float *__restrict__ out_r) {
+    constexpr F32Layout L{W};
+    constexpr int MT = W / 16;
+    constexpr int NW = InferLds<W>::kWeights;
+    constexpr int SLAB = TlmcLds<W>::kSlab;
+    __shared__ f32x4 smem4[(NW + WAVES * SLAB) / 4];
+    __shared__ nirc_lobes s_lobes;
+    float *smem = (float *)smem4;
+    {
+        const f32x4 *src = (const f32x4 *)(packed + L.offset(SEC_D));
+        for (int i = threadIdx.x; i < NW / 4; i += WAVES * 64) smem4[i] = src[i];
+        if (threadIdx.x == 0) s_lobes = lobes;
+    }
+    __syncthreads();
+    const float *sD = smem;
+    const float *sH = smem + L.size(SEC_D);
+    const float *sO = sH + 3 * L.size(SEC_H0);
+    const float *gS = packed + L.offset(SEC_S);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    float *hs = smem + NW + wave * SLAB;   // [16 points][W]
+    float *db = hs + 16 * W;               // directions, SoA [3][128]
+    const int64_t P = pts.count;
+    const int64_t n_groups = (P + 15) >> 4;
+    const int n_tiles = n_cache + 1;
+    const float inv_n = 1.0f / (float)n_cache;
+
+    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups;
+         grp += (int64_t)gridDim.x * WAVES) {
+        const int64_t p0 = grp << 4;
+        const int64_t pc = min(p0 + col, P - 1);
+        const float xs[7] = {pts.px[pc], pts.py[pc], pts.pz[pc], pts.nx[pc], pts.ny[pc], pts.nz[pc], pts.rough[pc]};
+
+        // surface projection, once per point
+        {
+            f32x4 hsum[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            layer1_surface<W>(hsum, opaque(gS), xs, lane, g);
+            wave_sync();   // previous group's readers of the slab are done
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+        }
+
+        float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
+        for (int tb = 0; tb < n_tiles; tb += 8) {
+            // --- directions for tiles tb..tb+7: lane = pair of consecutive queries
+            {
+                const int T = tb + (lane >> 3);
+                const int c0 = (2 * lane) & 15;
+                float wa[3] = {0.f, 0.f, 0.f}, wb[3] = {0.f, 0.f, 0.f};
+                if (T <= n_cache) {
+                    const bool res = (T == n_cache);
+                    int ja, jb, ka = 0, kb = 0;
+                    if (res) {
+                        ja = c0;
+                        jb = c0 + 1;
+                    } else {
+                        const int qa = 16 * T + c0;
+                        ja = qa / n_cache;
+                        ka = qa - ja * n_cache;
+                        jb = (qa + 1) / n_cache;
+                        kb = qa + 1 - jb * n_cache;
+                    }
+                    const int64_t pa = p0 + ja, pb = p0 + jb;
+                    const DirCounter ca = dir_counter((uint32_t)pa, ka, res);
+                    const DirCounter cb = dir_counter((uint32_t)pb, kb, res);
+                    const Rand4 ra = philox(ca.c0, ca.c1, frame, ca.stream, key0, key1);
+                    Rand4 rb = ra;
+                    if (ca.c0 != cb.c0 || ca.c1 != cb.c1)   // only for odd N
+                        rb = philox(cb.c0, cb.c1, frame, cb.stream, key0, key1);
+                    const int64_t qa_ = min(pa, P - 1), qb_ = min(pb, P - 1);
+                    dir_from_rand(ra, ca.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], wa[0], wa[1], wa[2]);
+                    dir_from_rand(rb, cb.half, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], wb[0], wb[1], wb[2]);
+                }
+                wave_sync();   // the previous batch's readers are done
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    db[128 * d + 2 * lane] = wa[d];
+                    db[128 * d + 2 * lane + 1] = wb[d];
+                }
+                wave_sync();
+            }
+            // --- MLP over the staged tiles, 4 at a time
+#pragma unroll 1
+            for (int sb = 0; sb < 8; sb += 4) {
+                const int t0 = tb + sb;
+                if (t0 >= n_tiles) break;
+                const int nt = min(4, n_tiles - t0);
+                f32x4 h[4][MT];
+                float dx[4], dy[4], dz[4];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    const int T = t0 + tt;
+                    const int qi = 16 * (sb + tt) + col;
+                    dx[tt] = db[qi];
+                    dy[tt] = db[128 + qi];
+                    dz[tt] = db[256 + qi];
+                    const int j = (T < n_cache) ? (16 * T + col) / n_cache : col;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        h[tt][mt] = (tt < nt) ? *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g)
+                                              : f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+                layer1_direction<W, 4>(h, sD, dx, dy, dz, lane, g, nt);
+                relu_all<W, 4>(h, nt);
+                hidden_layers<W, 4>(h, sH, lane, nt);
+                f32x4 y[4];
+                output_layer<W, 4>(y, h, sO, lane, nt);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    if (tt >= nt) break;
+                    const int T = t0 + tt;
+                    const float y0 = expf(y[tt][0]), y1 = expf(y[tt][1]), y2 = expf(y[tt][2]);
+                    if (T < n_cache) {
+                        // 16-lane inclusive prefix sums of the cache predictions
+                        float s0 = y0, s1 = y1, s2 = y2;
+#pragma unroll
+                        for (int d = 1; d < 16; d <<= 1) {
+                            const float u0 = __shfl_up(s0, d, 16);
+                            const float u1 = __shfl_up(s1, d, 16);
+                            const float u2 = __shfl_up(s2, d, 16);
+                            if (col >= d) {
+                                s0 += u0;
+                                s1 += u1;
+                                s2 += u2;
+                            }
+                        }
+                        // point `col` owns queries [col N, col N + N) -> columns [lo, hi)
+                        const int a = col * n_cache - 16 * T;
+                        const int lo = max(a, 0), hi = min(a + n_cache, 16);
+                        const int shi = min(max(hi - 1, 0), 15), slo = min(max(lo - 1, 0), 15);
+                        const float h0 = __shfl(s0, shi, 16), l0 = __shfl(s0, slo, 16);
+                        const float h1 = __shfl(s1, shi, 16), l1 = __shfl(s1, slo, 16);
+                        const float h2 = __shfl(s2, shi, 16), l2 = __shfl(s2, slo, 16);
+                        if (lo < hi) {
+                            fc0 += lo > 0 ? h0 - l0 : h0;
+                            fc1 += lo > 0 ? h1 - l1 : h1;
+                            fc2 += lo > 0 ? h2 - l2 : h2;
+                        }
+                    } else {
+                        float Lr[3];
+                        field_eval(s_lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
+                        fr0 = Lr[0] - y0;
+                        fr1 = Lr[1] - y1;
+                        fr2 = Lr[2] - y2;
+                    }
+                }
+            }
+        }
+        if (g == 0 && p0 + col < P) {
+            const int64_t o = 3 * (p0 + col);
+            const float c0 = fc0 * inv_n, c1 = fc1 * inv_n, c2 = fc2 * inv_n;
+            out_tl[o + 0] = c0 + fr0;
+            out_tl[o + 1] = c1 + fr1;
+            out_tl[o + 2] = c2 + fr2;
+            if (out_c) {
+                out_c[o + 0] = c0;
+                out_c[o + 1] = c1;
+                out_c[o + 2] = c2;
+            }
+            if (out_r) {
+                out_r[o + 0] = fr0;
+                out_r[o + 1] = fr1;
+                out_r[o + 2] = fr2;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers
+
+hipError_t launch_pack(float *packed, const float *master, int W, hipStream_t s) {
+    const int total = F32Layout{W}.total();
+    hipLaunchKernelGGL(k_pack_f32, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const Points &pts, const Queries &q, float *feat, hipStream_t s) {
+    const int64_t n = q.count * kInputs;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_encode, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, q, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_dirs(const Points &pts, int n_cache, uint64_t seed, uint64_t frame,
+                              float *dirs, hipStream_t s) {
+    const int64_t n = pts.count * (n_cache + 1);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sample_dirs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, n_cache,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, dirs);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_t batch,
+                              uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
+                              float *wx, float *wy, float *wz, float *target, hipStream_t s) {
+    if (batch == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_train_batch, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, pts,
+                       lobes, batch, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, step,
+                       point, wx, wy, wz, target);
+    return hipGetLastError();
+}
+
+static unsigned grid_for(int64_t units_per_wave_total, int waves, int max_blocks) {
+    int64_t b = (units_per_wave_total + waves - 1) / waves;
+    if (b > max_blocks) b = max_blocks;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+hipError_t launch_infer(int W, const Points &pts, const Queries &q, const float *packed, float *rgb,
+                        hipStream_t s) {
+    if (q.count == 0) return hipSuccess;
+    constexpr int WAVES = 4;
+    const unsigned grid = grid_for((q.count + 15) / 16, WAVES, kMaxResidentBlocks);
+    if (W == 64)
+        hipLaunchKernelGGL((k_infer_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, packed, rgb);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_tlmc(int W, const Points &pts, const nirc_lobes &lobes, const float *packed,
+                       int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
+                       float *out_r, hipStream_t s) {
+    if (pts.count == 0) return hipSuccess;
+    constexpr int WAVES = 4;
+    const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, kMaxResidentBlocks);
+    if (W == 64)
+        hipLaunchKernelGGL((k_tlmc_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes,
+                           packed, n_cache, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame,
+                           out_tl, out_c, out_r);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace nirc

@@ -1,0 +1,189 @@
+// Shared device routines of the MLP layer chain (FP32 MFMA 16x16x4) and the launcher interface
+// used by the C ABI.
+#pragma once
+
+#include "nirc_device.hpp"
+
+namespace nirc {
+
+// Upper bound of resident workgroups used for grid-stride launches (256 CUs).
+constexpr int kMaxResidentBlocks = 256;
+
+template <int W>
+struct InferLds {
+    // first-layer direction columns, three hidden layers and the output layer, in packed order
+    static constexpr int kWeights = F32Layout{W}.offset(SEC_T0) - F32Layout{W}.offset(SEC_D);
+};
+
+template <int W>
+struct TlmcLds {
+    static constexpr int kSlab = 16 * W + 3 * 128;   // h_s of 16 points + 128 staged directions
+};
+
+// Orders this wave's LDS traffic around a point where lanes exchange data through LDS.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Returns p unchanged but opaque to the optimiser, so that weight loads inside a loop are not
+// hoisted out of it (hoisting every fragment load would need hundreds of registers).
+template <typename T>
+__device__ __forceinline__ const T *opaque(const T *p) {
+    uint64_t v = (uint64_t)p;
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return (const T *)(((uint64_t)hi << 32) | lo);
+}
+
+// h += W1_s e_s for one 16-column tile; the surface features are computed here in B layout.
+template <int W>
+__device__ __forceinline__ void layer1_surface(f32x4 (&h)[W / 16], const float *gS, const float xs[7],
+                                               int lane, int g) {
+    constexpr int MT = W / 16;
+#pragma unroll
+    for (int kq = 0; kq < 7; ++kq) {
+        float b[4];
+        enc_pair(xs[kq], 2 * g, b[0], b[1]);
+        enc_pair(xs[kq], 2 * g + 1, b[2], b[3]);
+        f32x4 a[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(gS + ((mt * 7 + kq) * 64 + lane) * 4);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) h[mt] = mfma4(a[mt][kk], b[kk], h[mt]);
+    }
+}
+
+// h[tt] += W1_w e_w(direction of tile tt) for up to T tiles (nt valid).
+template <int W, int T>
+__device__ __forceinline__ void layer1_direction(f32x4 (&h)[T][W / 16], const float *sD, const float *dx,
+                                                 const float *dy, const float *dz, int lane, int g,
+                                                 int nt) {
+    constexpr int MT = W / 16;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float b[T][4];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const float v = i == 0 ? dx[tt] : i == 1 ? dy[tt] : dz[tt];
+            enc_pair(v, 2 * g, b[tt][0], b[tt][1]);
+            enc_pair(v, 2 * g + 1, b[tt][2], b[tt][3]);
+        }
+        f32x4 a[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sD + ((mt * 3 + i) * 64 + lane) * 4);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt)
+                    if (tt < nt) h[tt][mt] = mfma4(a[mt][kk], b[tt][kk], h[tt][mt]);
+    }
+}
+
+template <int W, int T>
+__device__ __forceinline__ void relu_all(f32x4 (&h)[T][W / 16], int nt) {
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+        for (int mt = 0; mt < W / 16; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[tt][mt][i] = fmaxf(h[tt][mt][i], 0.0f);
+}
+
+// Hidden layers 2..4: K-quad kq of the packed fragments is exactly row tile kq of the previous
+// layer's result, so register (tt, kq, kk) feeds K-block 4 kq + kk.
+template <int W, int T>
+__device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float *sH, int lane, int nt) {
+    constexpr int MT = W / 16, KQ = W / 16;
+    constexpr int SEC = MT * (W / 4) * 64;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const float *sec = sH + l * SEC;
+        f32x4 o[T][MT];
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) o[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kq = 0; kq < KQ; ++kq) {
+            f32x4 a[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sec + ((mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int tt = 0; tt < T; ++tt)
+                        if (tt < nt) o[tt][mt] = mfma4(a[mt][kk], h[tt][kq][kk], o[tt][mt]);
+        }
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) h[tt][mt][i] = fmaxf(o[tt][mt][i], 0.0f);
+    }
+}
+
+// Output layer (rows 0..2 of a 16-row tile): lanes 0..15 receive z = W5 h4 of their column.
+template <int W, int T>
+__device__ __forceinline__ void output_layer(f32x4 (&y)[T], const f32x4 (&h)[T][W / 16], const float *sO,
+                                             int lane, int nt) {
+    constexpr int KQ = W / 16;
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) y[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kq = 0; kq < KQ; ++kq) {
+        const f32x4 a = *(const f32x4 *)(sO + (kq * 64 + lane) * 4);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+                if (tt < nt) y[tt] = mfma4(a[kk], h[tt][kq][kk], y[tt]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers (return the launch status).
+hipError_t launch_pack(float *packed, const float *master, int W, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
+hipError_t launch_encode(const Points &pts, const Queries &q, float *feat, hipStream_t s);
+hipError_t launch_sample_dirs(const Points &pts, int n_cache, uint64_t seed, uint64_t frame,
+                              float *dirs, hipStream_t s);
+hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_t batch,
+                              uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
+                              float *wx, float *wy, float *wz, float *target, hipStream_t s);
+hipError_t launch_infer(int W, const Points &pts, const Queries &q, const float *packed, float *rgb,
+                        hipStream_t s);
+hipError_t launch_tlmc(int W, const Points &pts, const nirc_lobes &lobes, const float *packed,
+                       int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
+                       float *out_r, hipStream_t s);
+
+// Training (gradient partials, reduction, Adam).
+struct TrainArgs {
+    const float *target;   // [B][3] for the loss, or NULL
+    const float *d_rgb;    // [B][3] upstream gradient for the VJP, or NULL
+    float loss_eps;
+    float loss_scale;
+};
+int train_blocks(int64_t batch);   // workgroups used by the gradient kernel for a batch
+hipError_t launch_grad_partials(int W, const Points &pts, const Queries &q, const float *packed,
+                                TrainArgs a, float *partials, float *loss_partials, int nblocks,
+                                hipStream_t s);
+hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_partials, int nblocks,
+                              float inv_scale, float loss_norm, float *grad, float *loss,
+                              uint32_t *bad, hipStream_t s);
+hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStream_t s);
+hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
+                       uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
+                       float *packed, hipStream_t s);
+
+}  // namespace nirc

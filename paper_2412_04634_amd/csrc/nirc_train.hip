@@ -1,0 +1,395 @@
+// Training kernels: fused forward + relative-L2 loss + backward to per-workgroup weight-gradient
+// partials, a fixed-order reduction, and Adam with a refresh of the packed weights.
+#include "nirc_kernels.hpp"
+
+namespace nirc {
+
+namespace {
+
+constexpr int kTrainWaves = 4;
+constexpr int kChunk = 16 * kTrainWaves;   // samples staged per round
+constexpr int kStride = kChunk + 4;        // LDS row stride (floats): conflict-free 16 B reads
+
+template <int W>
+struct GradLds {
+    static constexpr int kH = 4 * W * kStride;     // h1..h4   [layer][neuron][sample]
+    static constexpr int kD = 4 * W * kStride;     // delta1..delta4
+    static constexpr int kD5 = 4 * kStride;        // output-layer delta, rows 0..3
+    static constexpr int kX = kChunk * kInputs;    // raw inputs [sample][10]
+    static constexpr int kLoss = kTrainWaves;
+    static constexpr int kTotal = kH + kD + kD5 + kX + kLoss;
+};
+
+// Output-pre-activation gradient and loss term of one channel.
+__device__ inline float out_grad(float z, float t, float dr, bool use_loss, float eps, float k,
+                                 float &loss_term) {
+    const float y = expf(z);
+    if (use_loss) {
+        const float d = y - t, den = y * y + eps;
+        loss_term = d * d / den;
+        return k * d / den * y;   // k = 2 scale / (3B)
+    }
+    loss_term = 0.0f;
+    return k * dr * y;            // k = scale
+}
+
+}  // namespace
+
+// One workgroup of 4 waves processes rounds of 64 samples.  Phase 1: each wave runs one
+// 16-sample tile forward (the first layer reads all 160 features) and backward with the
+// transposed packed weights, keeping activations and deltas in registers, and stages them in
+// LDS as [neuron][sample].  Phase 2: each wave owns a fixed set of 16x16 weight-gradient tiles
+// (a quarter of every layer's column tiles) held in registers across rounds, and adds the
+// round's 64 samples with MFMAs whose K dimension is the sample index.  At the end every tile is
+// written once into this workgroup's partial gradient (canonical layout).
+template <int W>
+__global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queries q,
+                                                               const float *__restrict__ packed,
+                                                               TrainArgs args, float *__restrict__ partials,
+                                                               float *__restrict__ loss_partials) {
+    static_assert(W == 64, "gradient kernel is laid out for width 64");
+    constexpr F32Layout L{W};
+    constexpr int MT = W / 16, KQ = W / 16;
+    using S = GradLds<W>;
+    __shared__ f32x4 smem4[(S::kTotal + 3) / 4];
+    float *smem = (float *)smem4;
+    float *sH = smem;
+    float *sD = sH + S::kH;
+    float *sD5 = sD + S::kD;
+    float *sX = sD5 + S::kD5;
+    float *sLoss = sX + S::kX;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t B = q.count;
+    const bool use_loss = args.target != nullptr;
+    const float kscale = use_loss ? 2.0f * args.loss_scale / (3.0f * (float)B) : args.loss_scale;
+
+    // owned gradient tiles: first layer input columns {wave, wave+4, wave+8} (< 10), column tile
+    // `wave` of W2..W4 and of W5
+    f32x4 g1[3][MT], gh[3][MT], g5;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            g1[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            gh[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    g5 = f32x4{0.f, 0.f, 0.f, 0.f};
+    float loss_acc = 0.0f;
+
+    const int64_t n_chunks = (B + kChunk - 1) / kChunk;
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        // ---------------- phase 1: forward + backward of this wave's 16 samples
+        {
+            const float *pk = opaque(packed);
+            const int s = 16 * wave + col;   // sample slot in the chunk
+            const int64_t b = chunk * kChunk + s;
+            const bool valid = b < B;
+            const int64_t bi = valid ? b : B - 1;
+            const int64_t p = query_point(q, pts, bi);
+            const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+            const float ws[3] = {q.wx[bi], q.wy[bi], q.wz[bi]};
+            if (g == 0) {
+                float *x = sX + s * kInputs;
+                x[0] = xs[0]; x[1] = xs[1]; x[2] = xs[2];
+                x[3] = ws[0]; x[4] = ws[1]; x[5] = ws[2];
+                x[6] = xs[3]; x[7] = xs[4]; x[8] = xs[5]; x[9] = xs[6];
+            }
+            f32x4 h[4][MT];   // h1..h4
+            {
+                f32x4 a1[1][MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) a1[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                layer1_surface<W>(a1[0], pk + L.offset(SEC_S), xs, lane, g);
+                float dx[1] = {ws[0]}, dy[1] = {ws[1]}, dz[1] = {ws[2]};
+                layer1_direction<W, 1>(a1, pk + L.offset(SEC_D), dx, dy, dz, lane, g, 1);
+                relu_all<W, 1>(a1, 1);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[0][mt] = a1[0][mt];
+            }
+#pragma unroll
+            for (int l = 1; l < 4; ++l) {
+                const float *sec = pk + L.offset(SEC_H0 + (l - 1));
+                f32x4 o[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    f32x4 a[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sec + ((mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) o[mt] = mfma4(a[mt][kk], h[l - 1][kq][kk], o[mt]);
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) h[l][mt][i] = fmaxf(o[mt][i], 0.0f);
+            }
+            f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            {
+                const float *sec = pk + L.offset(SEC_O);
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    const f32x4 a = *(const f32x4 *)(sec + (kq * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) z5 = mfma4(a[kk], h[3][kq][kk], z5);
+                }
+            }
+            // output delta: rows 0..2 live in lanes 0..15; everything else is zero
+            f32x4 d5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (g == 0 && valid) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float t = use_loss ? args.target[3 * b + c] : 0.0f;
+                    const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
+                    float lt;
+                    d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    loss_acc += lt;
+                }
+            }
+            if (g == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sD5[c * kStride + s] = d5[c];
+            }
+            // stage activations
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        sH[(l * W + 16 * mt + 4 * g + i) * kStride + s] = h[l][mt][i];
+            // backward: delta4 = (W5^T d5) .* [h4 > 0], then through W4^T, W3^T, W2^T
+            f32x4 d[MT];
+            {
+                const float *sec = pk + L.offset(SEC_OT);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const f32x4 a = *(const f32x4 *)(sec + (mt * 64 + lane) * 4);
+                    f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) o = mfma4(a[kk], d5[kk], o);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) d[mt][i] = h[3][mt][i] > 0.0f ? o[i] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sD[(3 * W + 16 * mt + 4 * g + i) * kStride + s] = d[mt][i];
+#pragma unroll
+            for (int l = 3; l >= 1; --l) {   // delta_l = (W_{l+1}^T delta_{l+1}) .* [h_l > 0]
+                const float *sec = pk + L.offset(SEC_T0 + (l - 1));
+                f32x4 o[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    f32x4 a[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sec + ((mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) o[mt] = mfma4(a[mt][kk], d[kq][kk], o[mt]);
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        d[mt][i] = h[l - 1][mt][i] > 0.0f ? o[mt][i] : 0.0f;
+                        sD[((l - 1) * W + 16 * mt + 4 * g + i) * kStride + s] = d[mt][i];
+                    }
+            }
+        }
+        __syncthreads();
+        // ---------------- phase 2: owned gradient tiles += staged deltas x activations
+        // K position (step kk, lane group g) of sample group sq <-> sample 16 sq + 4 g + kk
+#pragma unroll 1
+        for (int sq = 0; sq < kChunk / 16; ++sq) {
+            const int s0 = 16 * sq + 4 * g;
+            // hidden layers W2..W4 (a = 0..2) and the output layer: column tile `wave`
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const f32x4 bv = *(const f32x4 *)(sH + (a * W + 16 * wave + col) * kStride + s0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const f32x4 av = *(const f32x4 *)(sD + ((a + 1) * W + 16 * mt + col) * kStride + s0);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) gh[a][mt] = mfma4(av[kk], bv[kk], gh[a][mt]);
+                }
+            }
+            {
+                const f32x4 bv = *(const f32x4 *)(sH + (3 * W + 16 * wave + col) * kStride + s0);
+                f32x4 av = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (col < 3) av = *(const f32x4 *)(sD5 + col * kStride + s0);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) g5 = mfma4(av[kk], bv[kk], g5);
+            }
+            // first layer: column tile = input index; features recomputed from staged inputs
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int input = wave + 4 * a;
+                if (input >= kInputs) break;
+                const int k = col >> 1, sc = col & 1;
+                float bv[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    float sn, cs;
+                    enc_pair(sX[(s0 + kk) * kInputs + input], k, sn, cs);
+                    bv[kk] = sc ? cs : sn;
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const f32x4 av = *(const f32x4 *)(sD + (16 * mt + col) * kStride + s0);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) g1[a][mt] = mfma4(av[kk], bv[kk], g1[a][mt]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---------------- write this workgroup's partial gradient (every entry exactly once)
+    float *out = partials + (int64_t)blockIdx.x * n_params(W);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int input = wave + 4 * a;
+        if (input >= kInputs) break;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[w_offset(W, 0) + (int64_t)(16 * mt + 4 * g + i) * kFeat + 16 * input + col] = g1[a][mt][i];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[w_offset(W, 1 + a) + (int64_t)(16 * mt + 4 * g + i) * W + 16 * wave + col] = gh[a][mt][i];
+    if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[w_offset(W, 4) + (int64_t)i * W + 16 * wave + col] = g5[i];
+    }
+    // loss partial: fixed-order wave sum, then waves in order
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) loss_acc += __shfl_xor(loss_acc, d, 64);
+    if (lane == 0) sLoss[wave] = loss_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kTrainWaves; ++w) t += sLoss[w];
+        loss_partials[blockIdx.x] = t;
+    }
+}
+
+// grad[i] = inv_scale * sum_blk partials[blk][i] (fixed order); raises `bad` on a non-finite
+// entry.  Thread 0 also reduces the loss partials.
+__global__ void k_reduce_grad(const float *__restrict__ partials, const float *__restrict__ loss_partials,
+                              int nblocks, int64_t np, float inv_scale, float loss_norm,
+                              float *__restrict__ grad, float *__restrict__ loss, uint32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) {
+        float s = 0.0f;
+        for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * np + i];
+        s *= inv_scale;
+        grad[i] = s;
+        if (bad && !isfinite(s)) atomicOr(bad, 1u);
+    }
+    if (i == 0) {
+        float t = 0.0f;
+        for (int b = 0; b < nblocks; ++b) t += loss_partials[b];
+        t *= loss_norm;
+        if (loss) loss[0] = t;
+        if (bad && !isfinite(t)) atomicOr(bad, 1u);
+    }
+}
+
+__global__ void k_check_finite(const float *__restrict__ grad, int64_t np, uint32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np && !isfinite(grad[i])) atomicOr(bad, 1u);
+}
+
+// Adam (Kingma & Ba) with bias correction, t = step + 1; skipped entirely when `bad` is set.
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ grad, const int64_t *step, const uint32_t *bad,
+                       int64_t np, float lr, float b1, float b2, float eps) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np || *bad) return;
+    const float t = (float)(*step + 1);
+    const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
+    const float gi = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Repack the kernels' weight copy; thread 0 then commits the step (or records the skip).
+__global__ void k_pack_commit(float *packed, const float *master, int W, int total, int64_t *step,
+                              uint32_t *flags, uint32_t *bad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < total) {
+        const int64_t s = f32_packed_source(W, e);
+        packed[e] = s >= 0 ? master[s] : 0.0f;
+    }
+    if (e == 0) {
+        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        else *step += 1;
+        *bad = 0u;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+
+int train_blocks(int64_t batch) {
+    int64_t chunks = (batch + kChunk - 1) / kChunk;
+    if (chunks > kMaxResidentBlocks) chunks = kMaxResidentBlocks;
+    return (int)(chunks < 1 ? 1 : chunks);
+}
+
+hipError_t launch_grad_partials(int W, const Points &pts, const Queries &q, const float *packed,
+                                TrainArgs a, float *partials, float *loss_partials, int nblocks,
+                                hipStream_t s) {
+    if (W != 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_grad_f32<64>), dim3(nblocks), dim3(kTrainWaves * 64), 0, s, pts, q, packed, a,
+                       partials, loss_partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_partials, int nblocks,
+                              float inv_scale, float loss_norm, float *grad, float *loss,
+                              uint32_t *bad, hipStream_t s) {
+    const int64_t np = n_params(W);
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, partials,
+                       loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStream_t s) {
+    const int64_t np = n_params(W);
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, grad, np, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
+                       uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
+                       float *packed, hipStream_t s) {
+    const int64_t np = n_params(W);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad,
+                       step, bad, np, lr, b1, b2, eps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int total = F32Layout{W}.total();
+    hipLaunchKernelGGL(k_pack_commit, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
+                       step, flags, bad);
+    return hipGetLastError();
+}
+
+}  // namespace nirc

@@ -1,0 +1,325 @@
+"""ctypes binding of libnirc (include/nirc.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch provides device memory and the current
+stream.  If the library is missing this module raises instead of computing anything itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+from . import workload
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnirc.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "nirc.h")
+
+NIRC_FP32, NIRC_BF16, NIRC_FP16 = 0, 1, 2
+NIRC_FLAG_NONFINITE_GRAD = 1
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_sz = ctypes.c_size_t
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("width", _i32), ("precision", _i32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float), ("loss_eps", ctypes.c_float),
+                ("loss_scale", ctypes.c_float)]
+
+
+class _Points(ctypes.Structure):
+    _fields_ = [("px", _vp), ("py", _vp), ("pz", _vp), ("nx", _vp), ("ny", _vp), ("nz", _vp),
+                ("rough", _vp), ("count", _i64)]
+
+
+class _Queries(ctypes.Structure):
+    _fields_ = [("wx", _vp), ("wy", _vp), ("wz", _vp), ("point", _vp), ("count", _i64)]
+
+
+class Lobes(ctypes.Structure):
+    _fields_ = [("rec", ctypes.c_float * 64)]   # axis[4][3], kappa[4], alpha[4][3], beta[4][3][3]
+
+
+class NircError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NircError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "nirc_n_params": (_i64, [_i32]),
+            "nirc_state_bytes": (_sz, [ctypes.POINTER(Config)]),
+            "nirc_workspace_bytes": (_sz, [ctypes.POINTER(Config), _i64]),
+            "nirc_create": (_i32, [ctypes.POINTER(Config), _vp, _sz, _vp, _sz, _vp, _vp, ctypes.POINTER(_vp)]),
+            "nirc_destroy": (_i32, [_vp]),
+            "nirc_set_weights": (_i32, [_vp, _vp, _vp]),
+            "nirc_get_weights": (_i32, [_vp, _vp, _vp]),
+            "nirc_get_adam": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+            "nirc_read_flags": (_u32, [_vp, _vp]),
+            "nirc_clear_flags": (_i32, [_vp, _vp]),
+            "nirc_encode": (_i32, [_Points, _Queries, _vp, _vp]),
+            "nirc_infer": (_i32, [_vp, _Points, _Queries, _vp, _vp]),
+            "tlmc_sample_dirs": (_i32, [_Points, _i32, _u64, _u64, _vp, _vp]),
+            "tlmc_estimate": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp, _vp]),
+            "tlmc_train_batch": (_i32, [_Points, ctypes.POINTER(Lobes), _i64, _u64, _u64, _u32, _vp, _vp, _vp,
+                                        _vp, _vp, _vp]),
+            "nirc_loss_grad": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp, _vp]),
+            "nirc_backward": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
+            "nirc_adam_step": (_i32, [_vp, _vp, _vp]),
+            "nirc_train_step": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
+            "nirc_status_string": (ctypes.c_char_p, [_i32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/nirc.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:nirc|tlmc)_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        msg = lib().nirc_status_string(status).decode()
+        raise NircError(f"{what} failed: {msg} ({status})")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(a, device):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+
+
+# ------------------------------------------------------------------------------------------
+
+class Points:
+    """Shading points on the GPU (structure of arrays, FP32)."""
+
+    def __init__(self, arrays, device="cuda"):
+        self.t = [a if isinstance(a, torch.Tensor) else _dev_f32(a, device) for a in arrays]
+        for a in self.t:
+            assert a.dtype == torch.float32 and a.is_contiguous() and a.numel() == self.t[0].numel()
+        self.count = int(self.t[0].numel())
+
+    @classmethod
+    def from_workload(cls, pts: workload.Points, device="cuda"):
+        return cls(pts.arrays(), device)
+
+    def c(self):
+        return _Points(*[a.data_ptr() for a in self.t], self.count)
+
+
+class Queries:
+    """Cache queries: direction (SoA FP32) and point index (int32) per query."""
+
+    def __init__(self, wx, wy, wz, point=None):
+        self.wx, self.wy, self.wz = wx, wy, wz
+        self.point = point
+        self.count = int(wx.numel())
+
+    @classmethod
+    def from_dirs(cls, dirs: torch.Tensor, point: torch.Tensor | None = None):
+        d = dirs.reshape(-1, 3)
+        return cls(d[:, 0].contiguous(), d[:, 1].contiguous(), d[:, 2].contiguous(),
+                   None if point is None else point.to(torch.int32).contiguous())
+
+    def c(self):
+        return _Queries(self.wx.data_ptr(), self.wy.data_ptr(), self.wz.data_ptr(),
+                        None if self.point is None else self.point.data_ptr(), self.count)
+
+
+def lobes_struct(packed64) -> Lobes:
+    a = np.ascontiguousarray(packed64, dtype=np.float32).ravel()
+    assert a.size == 64
+    L = Lobes()
+    ctypes.memmove(ctypes.addressof(L), a.ctypes.data, 64 * 4)
+    return L
+
+
+def make_config(width=64, precision=NIRC_FP32, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
+                loss_eps=1e-2, loss_scale=1.0) -> Config:
+    return Config(width, precision, lr, beta1, beta2, adam_eps, loss_eps, loss_scale)
+
+
+def nirc_n_params(width: int) -> int:
+    return int(lib().nirc_n_params(width))
+
+
+def nirc_state_bytes(cfg: Config) -> int:
+    return int(lib().nirc_state_bytes(ctypes.byref(cfg)))
+
+
+def nirc_workspace_bytes(cfg: Config, max_batch: int) -> int:
+    return int(lib().nirc_workspace_bytes(ctypes.byref(cfg), max_batch))
+
+
+class Model:
+    """A cache model over torch-allocated state and workspace."""
+
+    def __init__(self, init_w, cfg: Config | None = None, max_batch: int = 65536, device="cuda"):
+        self.cfg = cfg or make_config()
+        self.width = self.cfg.width
+        self.n_params = nirc_n_params(self.width)
+        sb = nirc_state_bytes(self.cfg)
+        if sb == 0:
+            raise NircError("unsupported configuration")
+        self.state = torch.empty(sb, dtype=torch.uint8, device=device)
+        wb = nirc_workspace_bytes(self.cfg, max_batch) if max_batch > 0 else 0
+        self.workspace = torch.empty(max(wb, 1), dtype=torch.uint8, device=device) if wb else None
+        w = init_w if isinstance(init_w, torch.Tensor) else _dev_f32(init_w, device)
+        assert w.numel() == self.n_params
+        self._w0 = w.contiguous()
+        h = _vp()
+        _check(lib().nirc_create(ctypes.byref(self.cfg), _ptr(self.state), sb, _ptr(self.workspace), wb,
+                                 _ptr(self._w0), _stream(), ctypes.byref(h)), "nirc_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.nirc_destroy(h)
+            self.handle = None
+
+    def set_weights(self, w: torch.Tensor):
+        self._w0 = w.contiguous()
+        _check(lib().nirc_set_weights(self.handle, _ptr(self._w0), _stream()), "nirc_set_weights")
+
+    def get_weights(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.state.device)
+        _check(lib().nirc_get_weights(self.handle, _ptr(out), _stream()), "nirc_get_weights")
+        return out
+
+    def get_adam(self):
+        m = torch.empty(self.n_params, dtype=torch.float32, device=self.state.device)
+        v = torch.empty_like(m)
+        step = torch.zeros(1, dtype=torch.int64, device=self.state.device)
+        _check(lib().nirc_get_adam(self.handle, _ptr(m), _ptr(v), _ptr(step), _stream()), "nirc_get_adam")
+        return m, v, step
+
+    def read_flags(self) -> int:
+        return int(lib().nirc_read_flags(self.handle, _stream()))
+
+    def clear_flags(self):
+        _check(lib().nirc_clear_flags(self.handle, _stream()), "nirc_clear_flags")
+
+
+# ------------------------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+
+def nirc_encode(points: Points, queries: Queries) -> torch.Tensor:
+    out = torch.empty((queries.count, 160), dtype=torch.float32, device=points.t[0].device)
+    _check(lib().nirc_encode(points.c(), queries.c(), _ptr(out), _stream()), "nirc_encode")
+    return out
+
+
+def nirc_infer(model: Model, points: Points, queries: Queries) -> torch.Tensor:
+    out = torch.empty((queries.count, 3), dtype=torch.float32, device=points.t[0].device)
+    _check(lib().nirc_infer(model.handle, points.c(), queries.c(), _ptr(out), _stream()), "nirc_infer")
+    return out
+
+
+def tlmc_sample_dirs(points: Points, n_cache: int, seed: int, frame: int) -> torch.Tensor:
+    out = torch.empty((points.count, n_cache + 1, 3), dtype=torch.float32, device=points.t[0].device)
+    _check(lib().tlmc_sample_dirs(points.c(), n_cache, seed, frame, _ptr(out), _stream()), "tlmc_sample_dirs")
+    return out
+
+
+def tlmc_estimate(model: Model, points: Points, lobes, n_cache: int, seed: int, frame: int,
+                  parts: bool = False, out=None):
+    """Two-level estimate per point; returns F_tl, or (F_tl, F_c, F_r) with parts=True."""
+    dev = points.t[0].device
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    tl = out if out is not None else torch.empty((points.count, 3), dtype=torch.float32, device=dev)
+    c = torch.empty_like(tl) if parts else None
+    r = torch.empty_like(tl) if parts else None
+    _check(lib().tlmc_estimate(model.handle, points.c(), ctypes.byref(L), n_cache, seed, frame, _ptr(tl),
+                               _ptr(c), _ptr(r), _stream()), "tlmc_estimate")
+    return (tl, c, r) if parts else tl
+
+
+def tlmc_train_batch(points: Points, lobes, batch: int, seed: int, frame: int, step: int):
+    """Training samples: (Queries with point indices, targets [B,3])."""
+    dev = points.t[0].device
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    idx = torch.empty(batch, dtype=torch.int32, device=dev)
+    wx = torch.empty(batch, dtype=torch.float32, device=dev)
+    wy = torch.empty_like(wx)
+    wz = torch.empty_like(wx)
+    tgt = torch.empty((batch, 3), dtype=torch.float32, device=dev)
+    _check(lib().tlmc_train_batch(points.c(), ctypes.byref(L), batch, seed, frame, step, _ptr(idx), _ptr(wx),
+                                  _ptr(wy), _ptr(wz), _ptr(tgt), _stream()), "tlmc_train_batch")
+    return Queries(wx, wy, wz, idx), tgt
+
+
+def nirc_loss_grad(model: Model, points: Points, queries: Queries, target: torch.Tensor):
+    grad = torch.empty(model.n_params, dtype=torch.float32, device=target.device)
+    loss = torch.empty(1, dtype=torch.float32, device=target.device)
+    _check(lib().nirc_loss_grad(model.handle, points.c(), queries.c(), _ptr(target), _ptr(grad), _ptr(loss),
+                                _stream()), "nirc_loss_grad")
+    return loss, grad
+
+
+def nirc_backward(model: Model, points: Points, queries: Queries, d_rgb: torch.Tensor) -> torch.Tensor:
+    grad = torch.empty(model.n_params, dtype=torch.float32, device=d_rgb.device)
+    d = d_rgb.contiguous()
+    _check(lib().nirc_backward(model.handle, points.c(), queries.c(), _ptr(d), _ptr(grad), _stream()),
+           "nirc_backward")
+    return grad
+
+
+def nirc_adam_step(model: Model, grad: torch.Tensor):
+    _check(lib().nirc_adam_step(model.handle, _ptr(grad.contiguous()), _stream()), "nirc_adam_step")
+
+
+def nirc_train_step(model: Model, points: Points, queries: Queries, target: torch.Tensor, loss=None):
+    _check(lib().nirc_train_step(model.handle, points.c(), queries.c(), _ptr(target), _ptr(loss), _stream()),
+           "nirc_train_step")
+    return loss
+
+
+class NircFunction(torch.autograd.Function):
+    """y = cache(w; points, queries) with the hand-written backward (weight gradients only).
+
+    forward loads w into `model` with nirc_set_weights (which also resets that model's Adam
+    state, so use a model dedicated to evaluation) and runs nirc_infer; backward runs
+    nirc_backward with the upstream gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, w, model, points, queries):
+        _check(lib().nirc_set_weights(model.handle, _ptr(w.contiguous()), _stream()), "nirc_set_weights")
+        ctx.model, ctx.points, ctx.queries = model, points, queries
+        return nirc_infer(model, points, queries)
+
+    @staticmethod
+    def backward(ctx, dy):
+        g = nirc_backward(ctx.model, ctx.points, ctx.queries, dy.contiguous())
+        return g, None, None, None

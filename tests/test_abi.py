@@ -1,0 +1,50 @@
+"""The C ABI library loads, exports every declared entry point, and validates arguments on the
+host (no GPU needed for any call made here)."""
+import ctypes
+
+import pytest
+
+from paper_2412_04634_amd import nirc
+
+
+def test_library_exports_every_declared_function():
+    names = nirc.header_functions()
+    assert len(names) >= 20
+    L = nirc.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert missing == []
+    for n in ("nirc_encode", "nirc_infer", "nirc_train_step", "tlmc_estimate"):
+        assert n in names
+
+
+def test_sizes_and_params():
+    assert nirc.nirc_n_params(64) == 64 * 160 + 3 * 64 * 64 + 3 * 64 == 22720
+    assert nirc.nirc_n_params(63) == 0
+    cfg = nirc.make_config()
+    sb = nirc.nirc_state_bytes(cfg)
+    assert sb >= 3 * 22720 * 4
+    assert nirc.nirc_workspace_bytes(cfg, 65536) > nirc.nirc_workspace_bytes(cfg, 64) > 0
+    bad = nirc.make_config(width=48)
+    assert nirc.nirc_state_bytes(bad) == 0
+    assert nirc.nirc_state_bytes(nirc.make_config(precision=7)) == 0
+
+
+def test_host_side_argument_errors():
+    L = nirc.lib()
+    cfg = nirc.make_config()
+    h = ctypes.c_void_p()
+    # NULL state / weights / output handle: rejected before any device work
+    assert L.nirc_create(ctypes.byref(cfg), None, 0, None, 0, None, None, ctypes.byref(h)) == -1
+    assert L.nirc_infer(None, nirc._Points(), nirc._Queries(), None, None) == -1
+    assert L.tlmc_estimate(None, nirc._Points(), None, 8, 0, 0, None, None, None, None) == -1
+    assert L.tlmc_sample_dirs(nirc._Points(), 0, 0, 0, None, None) == -1     # n_cache < 1
+    bad_pts = nirc._Points(0, 0, 0, 0, 0, 0, 0, 5)                          # NULL arrays, count 5
+    assert L.nirc_encode(bad_pts, nirc._Queries(), None, None) == -1
+    assert L.nirc_status_string(-3).decode() == "state or workspace buffer too small"
+
+
+def test_empty_inputs_are_no_ops():
+    L = nirc.lib()
+    # zero points / zero queries enqueue nothing and succeed
+    assert L.tlmc_sample_dirs(nirc._Points(), 4, 0, 0, None, None) == 0
+    assert L.nirc_encode(nirc._Points(), nirc._Queries(), None, None) == 0

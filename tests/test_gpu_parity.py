@@ -1,0 +1,335 @@
+"""Parity of the HIP path with the FP64 oracle on the same seeded inputs (needs the GPU).
+
+Tolerances (FP32 arithmetic on the GPU against FP64):
+  * Philox words and training point indices: bit-exact;
+  * directions: 2e-6 absolute (FP32 rounding of the sampling map);
+  * features: 1e-6 absolute;
+  * cache outputs, estimator outputs, loss: relative L2 <= 1e-5 when both sides use the same
+    directions (the GPU's FP32 directions passed to the oracle);
+  * estimator against the oracle's own FP64 directions: relative L2 <= 2e-3, because a
+    direction error of ~3e-7 is amplified by the highest encoding frequency (2^7 pi);
+  * gradients: relative L2 <= 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2412_04634_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+W = 64
+
+
+@pytest.fixture(scope="module")
+def nirc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_04634_amd import nirc as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+def scene(seed, P):
+    pts = wl.make_points(seed, P)
+    return pts, wl.make_lobes(seed).packed(), wl.make_weights(seed, W)
+
+
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("P,N", [(1, 1), (17, 3), (256, 8), (1000, 16)])
+def test_sample_dirs_match_oracle(nirc, P, N):
+    say(f"sample_dirs P={P} N={N}")
+    pts, _, _ = scene(3, P)
+    dp = nirc.Points.from_workload(pts)
+    seed, frame = 0xDEADBEEF12, 5
+    d = host(nirc.tlmc_sample_dirs(dp, N, seed, frame))
+    ref = oracle.sample_dirs(pts, N, seed, frame)
+    assert np.abs(d - ref).max() <= 2e-6
+
+
+def test_encode_matches_oracle(nirc):
+    say("encode")
+    pts, _, _ = scene(4, 300)
+    dp = nirc.Points.from_workload(pts)
+    dirs = nirc.tlmc_sample_dirs(dp, 2, 9, 0)
+    idx = torch.arange(300, device="cuda", dtype=torch.int32).repeat_interleave(3)
+    q = nirc.Queries.from_dirs(dirs, idx)
+    f = host(nirc.nirc_encode(dp, q))
+    ref = oracle.encode(pts, idx.cpu().numpy(), host(dirs).reshape(-1, 3))
+    assert np.abs(f - ref).max() <= 1e-6
+    # exact special values: v = 0, 1/2, 1
+    sp = wl.Points(*[np.array([0.0, 0.5, 1.0], np.float32) for _ in range(7)])
+    spd = nirc.Points.from_workload(sp)
+    dd = torch.tensor([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5], [1.0, 1.0, 1.0]], device="cuda")
+    fe = host(nirc.nirc_encode(spd, nirc.Queries.from_dirs(dd)))
+    fo = oracle.encode(sp, None, host(dd))
+    assert np.abs(fe - fo).max() <= 1e-7
+
+
+@pytest.mark.parametrize("Q", [0, 1, 15, 16, 1000, 4099])
+def test_infer_matches_oracle(nirc, Q):
+    say(f"infer Q={Q}")
+    P = 300
+    pts, _, w0 = scene(5, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=0)
+    g = torch.Generator().manual_seed(Q)
+    idx = torch.randint(0, P, (Q,), generator=g, dtype=torch.int32)
+    d = torch.randn(Q, 3, generator=g, dtype=torch.float64)
+    d = (d / d.norm(dim=1, keepdim=True).clamp_min(1e-9)).float()
+    q = nirc.Queries.from_dirs(d.cuda(), idx.cuda())
+    y = host(nirc.nirc_infer(model, dp, q))
+    if Q == 0:
+        assert y.shape == (0, 3)
+        return
+    ref = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0, W)
+    assert rel_l2(y, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("P,N", [(1, 1), (17, 3), (4096, 8), (1000, 16), (333, 24), (100, 64)])
+def test_estimate_matches_oracle_on_gpu_directions(nirc, P, N):
+    say(f"estimate P={P} N={N}")
+    pts, lobes, w0 = scene(6, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=0)
+    seed, frame = 77, 2
+    tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lobes, N, seed, frame, parts=True))
+    dirs = host(nirc.tlmc_sample_dirs(dp, N, seed, frame))
+    o_tl, o_c, o_r = oracle.estimate(pts, lobes, w0, W, N, seed, frame, dirs=dirs)
+    assert rel_l2(c, o_c) <= 1e-5
+    assert rel_l2(tl, o_tl) <= 1e-5
+    # F_r = L - y can cancel: bound its error relative to the cache prediction's scale
+    assert np.linalg.norm(r - o_r) <= 1e-5 * np.linalg.norm(o_c)
+    np.testing.assert_array_equal(tl, host(nirc.tlmc_estimate(model, dp, lobes, N, seed, frame)))
+
+
+def test_estimate_matches_oracle_own_directions(nirc):
+    say("estimate vs oracle-sampled directions")
+    P, N = 2048, 8
+    pts, lobes, w0 = scene(7, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=0)
+    tl = host(nirc.tlmc_estimate(model, dp, lobes, N, 5, 1))
+    o_tl, _, _ = oracle.estimate(pts, lobes, w0, W, N, 5, 1)
+    assert rel_l2(tl, o_tl) <= 2e-3
+
+
+def test_estimate_zero_output_layer_and_empty(nirc):
+    say("estimate special cases")
+    P, N = 100, 4
+    pts, lobes, w0 = scene(8, P)
+    w = w0.copy()
+    w[-3 * W:] = 0.0
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w, max_batch=0)
+    tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lobes, N, 3, 0, parts=True))
+    assert np.all(c == 1.0)
+    dirs = host(nirc.tlmc_sample_dirs(dp, N, 3, 0))[:, N, :]
+    L = oracle.field(lobes, pts, None, dirs)
+    assert rel_l2(tl, L) <= 1e-5
+    empty = nirc.Points([torch.zeros(0, device="cuda") for _ in range(7)])
+    out = nirc.tlmc_estimate(model, empty, lobes, N, 3, 0)
+    assert out.shape == (0, 3)
+
+
+def test_train_batch_matches_oracle(nirc):
+    say("train_batch")
+    P, B = 5000, 4099
+    pts, lobes, _ = scene(9, P)
+    dp = nirc.Points.from_workload(pts)
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 11, 4, 3)
+    idx, d, t = oracle.train_batch(pts, lobes, B, 11, 4, 3)
+    np.testing.assert_array_equal(q.point.cpu().numpy(), idx)
+    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+    assert np.abs(gd - d).max() <= 2e-6
+    # targets on the GPU's directions
+    t_same = oracle.field(lobes, pts, idx, gd)
+    assert rel_l2(host(tgt), t_same) <= 1e-5
+
+
+@pytest.mark.parametrize("B", [1, 65, 1000, 4096])
+def test_loss_grad_matches_oracle(nirc, B):
+    say(f"loss_grad B={B}")
+    P = 3000
+    pts, lobes, w0 = scene(10, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=4096)
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 12, 0, 0)
+    loss, grad = nirc.nirc_loss_grad(model, dp, q, tgt)
+    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    assert abs(float(loss.item()) - o_loss) <= 1e-5 * abs(o_loss)
+    assert rel_l2(host(grad), o_grad) <= 1e-5
+    # every layer separately
+    offs = [0, W * 160, W * 160 + W * W, W * 160 + 2 * W * W, W * 160 + 3 * W * W, o_grad.size]
+    for a, b in zip(offs[:-1], offs[1:]):
+        assert rel_l2(host(grad)[a:b], o_grad[a:b]) <= 1e-5
+
+
+def test_backward_is_the_loss_vjp(nirc):
+    # d_rgb = dloss/dy (frozen denominator) makes the VJP equal the loss gradient
+    say("backward")
+    P, B = 2000, 777
+    pts, lobes, w0 = scene(13, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 14, 0, 0)
+    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+    idx = q.point.cpu().numpy()
+    y = oracle.infer(pts, idx, gd, w0, W)
+    t = host(tgt)
+    dy = 2.0 * (y - t) / (y * y + 1e-2) / (3.0 * B)
+    g = host(nirc.nirc_backward(model, dp, q, torch.tensor(dy, dtype=torch.float32, device="cuda")))
+    _, o_grad = oracle.loss_grad(pts, idx, gd, t, w0, W)
+    assert rel_l2(g, o_grad) <= 1e-5
+
+
+def test_train_step_single_step_parity(nirc):
+    say("train_step")
+    P, B = 3000, 4096
+    pts, lobes, w0 = scene(15, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 16, 0, 0)
+    loss = torch.zeros(1, device="cuda")
+    nirc.nirc_train_step(model, dp, q, tgt, loss)
+    w1 = host(model.get_weights())
+    m, v, step = model.get_adam()
+    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    ow = w0.astype(np.float64).copy()
+    om = np.zeros_like(ow)
+    ov = np.zeros_like(ow)
+    oracle.adam(ow, om, ov, o_grad, 1, lr=1e-3)
+    assert int(step.item()) == 1
+    assert abs(float(loss.item()) - o_loss) <= 1e-5 * o_loss
+    assert rel_l2(host(m), om) <= 1e-5
+    # first Adam step moves every weight by ~lr * sign(g); compare the update itself
+    upd, oupd = w1 - w0, ow - w0
+    big = np.abs(o_grad) > 1e-6
+    assert np.abs(upd[big] - oupd[big]).max() <= 1e-6
+    assert np.abs(upd - oupd).max() <= 1e-3 + 1e-6
+
+
+def test_train_steps_follow_oracle(nirc):
+    # several frames of 4 steps on fresh batches; trajectories compared after every step
+    say("train_steps 3 frames")
+    P, B = 4096, 4096
+    pts, lobes, w0 = scene(17, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=B)
+    ow = w0.astype(np.float64).copy()
+    om = np.zeros_like(ow)
+    ov = np.zeros_like(ow)
+    t = 0
+    for f in range(3):
+        for s in range(4):
+            q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 18, f, s)
+            nirc.nirc_train_step(model, dp, q, tgt)
+            gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+            _, g = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), ow, W)
+            t += 1
+            oracle.adam(ow, om, ov, g, t, lr=1e-3)
+    w = host(model.get_weights())
+    # FP32 vs FP64 trajectories: each step moves weights by <= lr; agreement to a small
+    # fraction of the accumulated update
+    assert np.abs(w - ow).max() <= 0.05 * 12 * 1e-3
+    assert rel_l2(w - w0, ow - w0) <= 1e-2
+
+
+def test_nonfinite_gradient_skips_step(nirc):
+    say("nonfinite")
+    P, B = 500, 256
+    pts, lobes, w0 = scene(19, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 20, 0, 0)
+    tgt[5, 1] = float("nan")
+    nirc.nirc_train_step(model, dp, q, tgt)
+    assert model.read_flags() & nirc.NIRC_FLAG_NONFINITE_GRAD
+    np.testing.assert_array_equal(host(model.get_weights()), w0.astype(np.float64))
+    _, _, step = model.get_adam()
+    assert int(step.item()) == 0
+    model.clear_flags()
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 20, 0, 1)
+    nirc.nirc_train_step(model, dp, q, tgt)
+    assert model.read_flags() == 0
+    _, _, step = model.get_adam()
+    assert int(step.item()) == 1
+
+
+def test_determinism(nirc):
+    say("determinism")
+    P, B = 3000, 3000
+    pts, lobes, w0 = scene(21, P)
+    dp = nirc.Points.from_workload(pts)
+    m1 = nirc.Model(w0, max_batch=B)
+    m2 = nirc.Model(w0, max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 22, 0, 0)
+    for m in (m1, m2):
+        for _ in range(2):
+            nirc.nirc_train_step(m, dp, q, tgt)
+    np.testing.assert_array_equal(host(m1.get_weights()), host(m2.get_weights()))
+    a = host(nirc.tlmc_estimate(m1, dp, lobes, 16, 1, 1))
+    b = host(nirc.tlmc_estimate(m2, dp, lobes, 16, 1, 1))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_autograd_function(nirc):
+    say("autograd")
+    P, Q = 400, 333
+    pts, _, w0 = scene(23, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=Q)
+    g = torch.Generator().manual_seed(0)
+    idx = torch.randint(0, P, (Q,), generator=g, dtype=torch.int32)
+    d = torch.randn(Q, 3, generator=g)
+    d = d / d.norm(dim=1, keepdim=True)
+    q = nirc.Queries.from_dirs(d.cuda(), idx.cuda())
+    w = torch.tensor(w0, device="cuda", requires_grad=True)
+    y = nirc.NircFunction.apply(w, model, dp, q)
+    up = torch.randn(Q, 3, generator=g).cuda()
+    (y * up).sum().backward()
+    # finite-difference directional derivative along a random direction, FP64 oracle
+    v = np.random.default_rng(1).normal(size=w0.size) * 1e-3
+    h = 1.0
+    yp = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0 + h * v, W)
+    ym = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0 - h * v, W)
+    fd = ((yp - ym) / (2 * h) * up.cpu().double().numpy()).sum()
+    an = float((w.grad.double().cpu().numpy() * v).sum())
+    assert an == pytest.approx(fd, rel=1e-3)
+
+
+def test_full_1080p_sampled_points(nirc):
+    # the bench configuration: 1920x1080 points, N = 16, checked on sampled points
+    say("full-size 1080p N=16 sampled")
+    P, N = 1920 * 1080, 16
+    pts, lobes, w0 = scene(2, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=0)
+    tl = nirc.tlmc_estimate(model, dp, lobes, N, 2, 0)
+    dirs = nirc.tlmc_sample_dirs(dp, N, 2, 0)
+    rng = np.random.default_rng(0)
+    sel = np.unique(np.concatenate([rng.choice(P, 3000, replace=False), np.arange(P - 40, P), np.arange(40)]))
+    sub = pts.subset(sel)
+    o_tl, _, _ = oracle.estimate(sub, lobes, w0, W, N, 2, 0, dirs=host(dirs[torch.tensor(sel, device="cuda")]))
+    assert rel_l2(host(tl)[sel], o_tl) <= 1e-5
+    assert np.isfinite(host(tl)).all()
