@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of one frame of the NIRC two-level Monte Carlo hot path on one MI355X.
+
+A step is one frame of the dynamic 1080p scene (lobe axes rotate one degree per frame):
+  tlmc_estimate (N = 16 cache directions + 1 residual per point)      gather .. combine
+  tlmc_frame_stats (FP64 MRSE against the exact integral)             frame statistics
+  4 x (tlmc_train_batch + nirc_train_step), batch 65,536               training + Adam
+All inputs are resident in HBM before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NIRC queries/s + ms/frame at 1080p N=16; BF16 vs FP32 at equal MRSE"
+PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix peak, FLOP/s
+PEAK_HBM = 8.0e12              # bytes/s
+
+
+def algorithmic_flops_estimate(P: int, N: int, W: int) -> float:
+    """Per launch of the fused estimator: surface projection once per point plus, per query,
+    the direction columns of layer 1, three hidden layers and the output layer."""
+    surface = 2 * 112 * W
+    per_query = 2 * (48 * W + 3 * W * W + 3 * W)
+    return float(P) * (surface + (N + 1) * per_query)
+
+
+def algorithmic_flops_train(B: int, W: int) -> float:
+    """One training step: forward (160-wide input), weight gradients and deltas (no input grads)."""
+    fwd = 2 * (160 * W + 3 * W * W + 3 * W)
+    dw = fwd
+    delta = 2 * (3 * W * W + 3 * W)
+    return float(B) * (fwd + dw + delta)
+
+
+def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=15.0):
+    """The FP64 oracle on a bounded sample of the same frame: a seeded subset of points and a
+    proportional share of the training batch; reported as queries/s of the whole frame."""
+    import numpy as np
+    import oracle
+
+    P = pts.count
+    rng = np.random.default_rng(1234)
+
+    def run(n_pts):
+        sel = np.sort(rng.choice(P, n_pts, replace=False))
+        sub = pts.subset(sel)
+        b = max(1, int(round(B * n_pts / P)))
+        lob = lobes_for(0)
+        t0 = time.perf_counter()
+        oracle.estimate(sub, lob, w0, W, N, 2, 0)
+        w = w0.astype(np.float64).copy()
+        m = np.zeros_like(w)
+        v = np.zeros_like(w)
+        for s in range(steps_per_frame):
+            idx, d, t = oracle.train_batch(sub, lob, b, 2, 0, s)
+            _, g = oracle.loss_grad(sub, idx, d, t, w, W)
+            oracle.adam(w, m, v, g, s + 1)
+        return time.perf_counter() - t0, b
+
+    t_small, _ = run(512)
+    n = int(min(P, max(512, 512 * target_s / max(t_small, 1e-3))))
+    t, b = run(n)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n * (N + 1) / t, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} of {P} points (seeded subset) x {N}+1 queries + {steps_per_frame} training "
+                      f"steps of {b} samples (batch scaled by the same fraction); {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="1080p_n16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the hot path has no "
+                                   "multi-GPU mode (--gpus must be 1)"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2412_04634_amd import nirc, workload as wl
+
+    cfgw = wl.WORKLOADS[args.workload]
+    P, N, W, seed = cfgw["points"], cfgw["n_cache"], cfgw["width"], cfgw["seed"]
+    B, S = cfgw["train_batch"], cfgw["train_steps"]
+    dev = "cuda"
+    torch.cuda.set_device(0)
+
+    scene = wl.make_scene(seed, P)
+    w0 = wl.make_weights(seed, W)
+    base_lobes = scene.lobes
+    dp = nirc.Points.from_workload(scene.points)
+    model = nirc.Model(w0, max_batch=B)
+    lobes_frames = {}
+
+    def lobes_for(f):
+        if f not in lobes_frames:
+            lobes_frames[f] = base_lobes.rotated(f).packed()
+        return lobes_frames[f]
+
+    table = nirc.tlmc_reference_table(lobes_for(0))
+    fs = nirc.FrameStats()
+    out_tl = torch.empty((P, 3), dtype=torch.float32, device=dev)
+    out_c = torch.empty_like(out_tl)
+    out_r = torch.empty_like(out_tl)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    mrse_hist = []
+    stream = torch.cuda.current_stream()
+
+    def frame(f, ev=None):
+        lob = nirc.lobes_struct(lobes_for(f))
+        if ev is not None:
+            ev[0].record(stream)
+        nirc._check(nirc.lib().tlmc_estimate(model.handle, dp.c(), nirc.ctypes.byref(lob), N, seed, f,
+                                             nirc._ptr(out_tl), nirc._ptr(out_c), nirc._ptr(out_r), nirc._stream()),
+                    "tlmc_estimate")
+        if ev is not None:
+            ev[1].record(stream)
+        st = nirc.tlmc_frame_stats(dp, lob, table, out_tl, out_c, out_r, fs=fs)
+        if ev is not None:
+            ev[2].record(stream)
+        for s in range(S):
+            q, tgt = nirc.tlmc_train_batch(dp, lob, B, seed, f, s)
+            nirc.nirc_train_step(model, dp, q, tgt, loss)
+        if ev is not None:
+            ev[3].record(stream)
+        return st
+
+    for f in range(args.warmup):
+        frame(f)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        stats.append(frame(args.warmup + i, evs[i]).clone())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    t_est = [e[0].elapsed_time(e[1]) * 1e-3 for e in evs]
+    t_stats = [e[1].elapsed_time(e[2]) * 1e-3 for e in evs]
+    t_train = [e[2].elapsed_time(e[3]) * 1e-3 for e in evs]
+    mrse = [float(s[4].item()) for s in stats]
+    ms_frame = elapsed / args.steps * 1e3
+    queries = P * (N + 1)
+    value = queries * args.steps / elapsed
+    t_est_avg = sum(t_est) / len(t_est)
+    flops = algorithmic_flops_estimate(P, N, W)
+    achieved = flops / t_est_avg
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_frame,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dynamic lobe scene, {P} shading points (1920x1080), N={N} cache + 1 residual, "
+                               f"MLP 4x{W} ReLU, {S} Adam steps of {B} samples per frame",
+                   "points": P, "n_cache": N, "width": W, "train_batch": B, "train_steps_per_frame": S,
+                   "precision": "fp32"},
+        "roofline": {"bound": "mfma", "kernel": "k_tlmc_f32", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": t_est_avg * 1e3},
+        "estimate_queries_per_s": queries / t_est_avg,
+        "ms_estimate": t_est_avg * 1e3,
+        "ms_frame_stats": sum(t_stats) / len(t_stats) * 1e3,
+        "ms_train": sum(t_train) / len(t_train) * 1e3,
+        "train_samples_per_s": S * B / (sum(t_train) / len(t_train)),
+        "train_tflops": algorithmic_flops_train(B, W) * S / (sum(t_train) / len(t_train)) / 1e12,
+        "mrse_first_last": [mrse[0], mrse[-1]],
+        "final_loss": float(loss.item()),
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scene.points, lobes_for, w0, W, N, B, S)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

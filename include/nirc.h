@@ -206,6 +206,45 @@ nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream);
 nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries queries,
                             const float *target, float *loss, void *stream);
 
+/* ------------------------------------------------------------------------------------------ */
+/* Frame statistics (FP64 on the device)                                                       */
+
+/* Coefficients per lobe of the Chebyshev expansion used for the ground truth. */
+#define TLMC_CHEB_COEFFS 128
+/* Doubles written by tlmc_frame_stats. */
+#define TLMC_STATS 8
+
+/* Ground truth of the estimator for the lobe field with f_r = 1/pi (the quantity eq. L_mlmc
+ * estimates, emission omitted): F(x, n) = sum_j a_j(x) J(kappa_j, mu_j . n), where
+ * J(kappa, t) = (1/pi) int_{H+} exp(kappa (mu . w - 1)) cos(theta) dw reduces to a 1D integral
+ * with a modified Bessel function.  tlmc_reference_table builds, for each lobe, a Chebyshev
+ * expansion of J(kappa_j, .) on [-1, 1] by Gauss-Legendre quadrature: table is
+ * [4][TLMC_CHEB_COEFFS] FP64 (device) and depends only on the kappas, so a scene whose lobes
+ * rotate keeps its table. */
+nirc_status tlmc_reference_table(const nirc_lobes *field /* host */, double *table, void *stream);
+
+/* F per point: [points.count][3] FP64. */
+nirc_status tlmc_reference(nirc_points points, const nirc_lobes *field /* host */, const double *table,
+                           double *F, void *stream);
+
+/* Bytes of scratch tlmc_frame_stats needs. */
+size_t tlmc_frame_stats_scratch_bytes(void);
+
+/* Per-frame error statistics of an estimate against F, summed in FP64 in a fixed order:
+ *   stats[0] = sum (F_tl - F)^2 / (F^2 + eps)    stats[4] = stats[0] / stats[3]  (MRSE)
+ *   stats[1] = sum (F_c  - F)^2 / (F^2 + eps)    stats[5] = stats[1] / stats[3]
+ *   stats[2] = sum  F_r^2       / (F^2 + eps)    stats[6] = stats[2] / stats[3]
+ *   stats[3] = number of terms (3 * points.count)
+ * over points and channels (est_c / est_r may be NULL: their sums are 0).  The paper reports
+ * the mean relative squared error (MRSE) without defining it; this is the usual form with
+ * eps guarding dark pixels. */
+nirc_status tlmc_frame_stats(nirc_points points, const nirc_lobes *field /* host */, const double *table,
+                             const float *est_tl, const float *est_c, const float *est_r, double eps,
+                             void *scratch, double *stats /* [TLMC_STATS] */, void *stream);
+
+/* sum[i] += v[i], sumsq[i] += v[i]^2 in FP64 (per-point accumulation over seeds). */
+nirc_status tlmc_accumulate(const float *values, int64_t count, double *sum, double *sumsq, void *stream);
+
 const char *nirc_status_string(nirc_status s);
 
 #ifdef __cplusplus

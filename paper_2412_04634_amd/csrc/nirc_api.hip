@@ -315,4 +315,38 @@ nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries 
                                   model->cfg.adam_eps, model->packed, s));
 }
 
+nirc_status tlmc_reference_table(const nirc_lobes *field, double *table, void *stream) {
+    if (!field || !table) return NIRC_ERR_INVALID_ARG;
+    for (int j = 0; j < 4; ++j)
+        if (!(field->kappa[j] >= 0.0f) || field->kappa[j] > 1000.0f) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_reference_table(*field, table, (hipStream_t)stream));
+}
+
+nirc_status tlmc_reference(nirc_points points, const nirc_lobes *field, const double *table, double *F,
+                           void *stream) {
+    if (!field || !table) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK) return st;
+    if (points.count > 0 && !F) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_reference(to_points(points), *field, table, F, (hipStream_t)stream));
+}
+
+size_t tlmc_frame_stats_scratch_bytes(void) { return frame_stats_scratch_bytes(); }
+
+nirc_status tlmc_frame_stats(nirc_points points, const nirc_lobes *field, const double *table, const float *est_tl,
+                             const float *est_c, const float *est_r, double eps, void *scratch, double *stats,
+                             void *stream) {
+    if (!field || !table || !scratch || !stats || !(eps > 0.0)) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK) return st;
+    if (points.count > 0 && !est_tl) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_frame_stats(to_points(points), *field, table, est_tl, est_c, est_r, eps,
+                                         (double *)scratch, stats, (hipStream_t)stream));
+}
+
+nirc_status tlmc_accumulate(const float *values, int64_t count, double *sum, double *sumsq, void *stream) {
+    if (count < 0 || (count > 0 && (!values || !sum || !sumsq))) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_accumulate(values, count, sum, sumsq, (hipStream_t)stream));
+}
+
 }  // extern "C"

@@ -167,6 +167,16 @@ hipError_t launch_tlmc(int W, const Points &pts, const nirc_lobes &lobes, const 
                        int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
                        float *out_r, hipStream_t s);
 
+// Frame statistics (FP64).
+hipError_t launch_reference_table(const nirc_lobes &lobes, double *table, hipStream_t s);
+hipError_t launch_reference(const Points &pts, const nirc_lobes &lobes, const double *table, double *F,
+                            hipStream_t s);
+hipError_t launch_frame_stats(const Points &pts, const nirc_lobes &lobes, const double *table, const float *tl,
+                              const float *fc, const float *fr, double eps, double *scratch, double *stats,
+                              hipStream_t s);
+size_t frame_stats_scratch_bytes();
+hipError_t launch_accumulate(const float *v, int64_t n, double *sum, double *sumsq, hipStream_t s);
+
 // Training (gradient partials, reduction, Adam).
 struct TrainArgs {
     const float *target;   // [B][3] for the loss, or NULL

@@ -1,0 +1,238 @@
+// Frame statistics in FP64: the exact reflected radiance of the lobe field, the mean relative
+// squared error of an estimate against it, and per-point sums over seeds (unbiasedness).
+//
+// Ground truth with f_r = 1/pi and p = cos/pi: F(x, n) = sum_j a_j(x) J(kappa_j, mu_j . n) with
+//   J(kappa, t) = (1/pi) int_{H+(n)} exp(kappa (mu . w - 1)) (n . w) dw
+//               = 2 e^{-kappa} int_0^1 u e^{kappa t u} I0(kappa sqrt(1-t^2) sqrt(1-u^2)) du
+// (rotate n to +z and integrate the azimuth, which yields 2 pi I0).  J is entire in t, so a
+// Chebyshev expansion in t converges super-geometrically; each lobe's expansion is built once
+// per set of kappas (it does not depend on the lobe axis, so a rotating scene reuses it).
+#include "nirc_kernels.hpp"
+
+namespace nirc {
+
+namespace {
+
+constexpr int kGL = 128;   // Gauss-Legendre nodes for J
+// Chebyshev coefficients per lobe: TLMC_CHEB_COEFFS (nirc.h)
+
+__device__ double bessel_i0(double z) {
+    const double q = 0.25 * z * z;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 400; ++k) {
+        term *= q / ((double)k * (double)k);
+        const double ns = sum + term;
+        if (ns == sum) break;
+        sum = ns;
+    }
+    return sum;
+}
+
+// Node i of the kGL-point Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n.
+__device__ void gl_node(int i, double &x, double &w) {
+    const int n = kGL;
+    double t = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 60; ++it) {
+        double p0 = 1.0, p1 = t;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (t * p1 - p0) / (t * t - 1.0);
+        const double dt = p1 / dp;
+        t -= dt;
+        if (fabs(dt) < 1e-15) break;
+    }
+    double p0 = 1.0, p1 = t;
+    for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    dp = n * (t * p1 - p0) / (t * t - 1.0);
+    x = t;
+    w = 2.0 / ((1.0 - t * t) * dp * dp);
+}
+
+}  // namespace
+
+// One workgroup per lobe: GL nodes into LDS, J at the Chebyshev nodes, then the coefficients
+//   c_k = (2/M) sum_m J(t_m) cos(pi k (m + 1/2) / M),  t_m = cos(pi (m + 1/2) / M),
+// with c_0 halved so that J(t) = sum_k c_k T_k(t).
+__global__ __launch_bounds__(256) void k_reference_table(nirc_lobes lobes, double *table) {
+    constexpr int M = TLMC_CHEB_COEFFS;
+    __shared__ double sx[kGL], sw[kGL], sJ[M];
+    const int j = blockIdx.x;
+    const double kappa = lobes.kappa[j];
+    for (int i = threadIdx.x; i < kGL; i += blockDim.x) gl_node(i, sx[i], sw[i]);
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        const double t = cos(M_PI * (m + 0.5) / M);
+        const double s = sqrt(fmax(0.0, 1.0 - t * t));
+        double acc = 0.0;
+        for (int i = 0; i < kGL; ++i) {
+            const double u = 0.5 * (sx[i] + 1.0);   // map [-1,1] -> [0,1]
+            acc += 0.5 * sw[i] * u * exp(kappa * (t * u - 1.0)) * bessel_i0(kappa * s * sqrt(1.0 - u * u));
+        }
+        sJ[m] = 2.0 * acc;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        double c = 0.0;
+        for (int m = 0; m < M; ++m) c += sJ[m] * cos(M_PI * k * (m + 0.5) / M);
+        c *= 2.0 / M;
+        if (k == 0) c *= 0.5;
+        table[j * M + k] = c;
+    }
+}
+
+__device__ inline double cheb_eval(const double *c, double t) {
+    // Clenshaw recurrence for sum_k c_k T_k(t)
+    double b1 = 0.0, b2 = 0.0;
+    for (int k = TLMC_CHEB_COEFFS - 1; k >= 1; --k) {
+        const double b0 = 2.0 * t * b1 - b2 + c[k];
+        b2 = b1;
+        b1 = b0;
+    }
+    return t * b1 - b2 + c[0];
+}
+
+__device__ inline void reference_at(const nirc_lobes &L, const double *tab, const Points &pts, int64_t p,
+                                    double F[3]) {
+    const double x0 = pts.px[p], x1 = pts.py[p], x2 = pts.pz[p];
+    const double n0 = pts.nx[p], n1 = pts.ny[p], n2 = pts.nz[p];
+    F[0] = F[1] = F[2] = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        double t = (double)L.axis[j][0] * n0 + (double)L.axis[j][1] * n1 + (double)L.axis[j][2] * n2;
+        t = fmin(1.0, fmax(-1.0, t));
+        const double J = cheb_eval(tab + j * TLMC_CHEB_COEFFS, t);
+        for (int c = 0; c < 3; ++c) {
+            const double a = (double)L.alpha[j][c] + (double)L.beta[j][c][0] * x0 + (double)L.beta[j][c][1] * x1 +
+                             (double)L.beta[j][c][2] * x2;
+            F[c] += a * J;
+        }
+    }
+}
+
+__global__ void k_reference(Points pts, nirc_lobes lobes, const double *table, double *F) {
+    __shared__ double tab[4 * TLMC_CHEB_COEFFS];
+    for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x) tab[i] = table[i];
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pts.count) return;
+    double f[3];
+    reference_at(lobes, tab, pts, p, f);
+    F[3 * p + 0] = f[0];
+    F[3 * p + 1] = f[1];
+    F[3 * p + 2] = f[2];
+}
+
+constexpr int kStatBlocks = 256;
+constexpr int kStatThreads = 256;
+
+// Per-block FP64 partial sums over points and channels:
+//   0: (F_tl - F)^2 / (F^2 + eps)      1: (F_c - F)^2 / (F^2 + eps)   (when F_c is given)
+//   2: F_r^2 / (F^2 + eps)             (when F_r is given)            3: number of terms
+__global__ __launch_bounds__(kStatThreads) void k_frame_stats(Points pts, nirc_lobes lobes, const double *table,
+                                                              const float *tl, const float *fc, const float *fr,
+                                                              double eps, double *partials) {
+    __shared__ double tab[4 * TLMC_CHEB_COEFFS];
+    __shared__ double red[kStatThreads / 64][4];
+    for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x) tab[i] = table[i];
+    __syncthreads();
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pts.count;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        double F[3];
+        reference_at(lobes, tab, pts, p, F);
+        for (int c = 0; c < 3; ++c) {
+            const double den = F[c] * F[c] + eps;
+            const double e = (double)tl[3 * p + c] - F[c];
+            acc[0] += e * e / den;
+            if (fc) {
+                const double ec = (double)fc[3 * p + c] - F[c];
+                acc[1] += ec * ec / den;
+            }
+            if (fr) {
+                const double r = fr[3 * p + c];
+                acc[2] += r * r / den;
+            }
+            acc[3] += 1.0;
+        }
+    }
+    // fixed-order reduction: wave butterflies, then waves in order
+    for (int k = 0; k < 4; ++k) {
+        double v = acc[k];
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+        acc[k] = v;
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int k = 0; k < 4; ++k) red[wave][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int w = 0; w < kStatThreads / 64; ++w) s += red[w][threadIdx.x];
+        partials[blockIdx.x * 4 + threadIdx.x] = s;
+    }
+}
+
+// stats[k] = sum over blocks (fixed order); stats[4] = MRSE, stats[5] = cache-level MRSE,
+// stats[6] = relative residual second moment.
+__global__ void k_stats_final(const double *partials, double *stats) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < kStatBlocks; ++b)
+        for (int k = 0; k < 4; ++k) s[k] += partials[b * 4 + k];
+    for (int k = 0; k < 4; ++k) stats[k] = s[k];
+    const double n = s[3] > 0.0 ? s[3] : 1.0;
+    stats[4] = s[0] / n;
+    stats[5] = s[1] / n;
+    stats[6] = s[2] / n;
+    stats[7] = 0.0;
+}
+
+__global__ void k_accumulate(const float *v, int64_t n, double *sum, double *sumsq) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = v[i];
+    sum[i] += x;
+    sumsq[i] += x * x;
+}
+
+// ------------------------------------------------------------------------------------------
+
+hipError_t launch_reference_table(const nirc_lobes &lobes, double *table, hipStream_t s) {
+    hipLaunchKernelGGL(k_reference_table, dim3(4), dim3(256), 0, s, lobes, table);
+    return hipGetLastError();
+}
+
+hipError_t launch_reference(const Points &pts, const nirc_lobes &lobes, const double *table, double *F,
+                            hipStream_t s) {
+    if (pts.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reference, dim3((unsigned)((pts.count + 255) / 256)), dim3(256), 0, s, pts, lobes, table, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_stats(const Points &pts, const nirc_lobes &lobes, const double *table, const float *tl,
+                              const float *fc, const float *fr, double eps, double *scratch, double *stats,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_frame_stats, dim3(kStatBlocks), dim3(kStatThreads), 0, s, pts, lobes, table, tl, fc, fr,
+                       eps, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, s, scratch, stats);
+    return hipGetLastError();
+}
+
+size_t frame_stats_scratch_bytes() { return (size_t)kStatBlocks * 4 * sizeof(double); }
+
+hipError_t launch_accumulate(const float *v, int64_t n, double *sum, double *sumsq, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, sum, sumsq);
+    return hipGetLastError();
+}
+
+}  // namespace nirc

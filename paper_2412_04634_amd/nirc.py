@@ -83,6 +83,12 @@ def lib():
             "nirc_backward": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
             "nirc_adam_step": (_i32, [_vp, _vp, _vp]),
             "nirc_train_step": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
+            "tlmc_reference_table": (_i32, [ctypes.POINTER(Lobes), _vp, _vp]),
+            "tlmc_reference": (_i32, [_Points, ctypes.POINTER(Lobes), _vp, _vp, _vp]),
+            "tlmc_frame_stats_scratch_bytes": (_sz, []),
+            "tlmc_frame_stats": (_i32, [_Points, ctypes.POINTER(Lobes), _vp, _vp, _vp, _vp, ctypes.c_double, _vp,
+                                        _vp, _vp]),
+            "tlmc_accumulate": (_i32, [_vp, _i64, _vp, _vp, _vp]),
             "nirc_status_string": (ctypes.c_char_p, [_i32]),
         }
         for name, (res, args) in sig.items():
@@ -303,6 +309,47 @@ def nirc_train_step(model: Model, points: Points, queries: Queries, target: torc
     _check(lib().nirc_train_step(model.handle, points.c(), queries.c(), _ptr(target), _ptr(loss), _stream()),
            "nirc_train_step")
     return loss
+
+
+TLMC_CHEB_COEFFS = 128
+TLMC_STATS = 8
+
+
+def tlmc_reference_table(lobes, device="cuda") -> torch.Tensor:
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    t = torch.empty((4, TLMC_CHEB_COEFFS), dtype=torch.float64, device=device)
+    _check(lib().tlmc_reference_table(ctypes.byref(L), _ptr(t), _stream()), "tlmc_reference_table")
+    return t
+
+
+def tlmc_reference(points: Points, lobes, table: torch.Tensor) -> torch.Tensor:
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    F = torch.empty((points.count, 3), dtype=torch.float64, device=table.device)
+    _check(lib().tlmc_reference(points.c(), ctypes.byref(L), _ptr(table), _ptr(F), _stream()), "tlmc_reference")
+    return F
+
+
+class FrameStats:
+    """Reusable scratch + output for tlmc_frame_stats."""
+
+    def __init__(self, device="cuda"):
+        nb = int(lib().tlmc_frame_stats_scratch_bytes())
+        self.scratch = torch.empty(nb // 8, dtype=torch.float64, device=device)
+        self.stats = torch.zeros(TLMC_STATS, dtype=torch.float64, device=device)
+
+
+def tlmc_frame_stats(points: Points, lobes, table: torch.Tensor, est_tl, est_c=None, est_r=None,
+                     eps: float = 1e-2, fs: FrameStats | None = None) -> torch.Tensor:
+    """FP64 stats [8]: sums of relative squared errors, count, and MRSE (index 4)."""
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    fs = fs or FrameStats(table.device)
+    _check(lib().tlmc_frame_stats(points.c(), ctypes.byref(L), _ptr(table), _ptr(est_tl), _ptr(est_c), _ptr(est_r),
+                                  eps, _ptr(fs.scratch), _ptr(fs.stats), _stream()), "tlmc_frame_stats")
+    return fs.stats
+
+
+def tlmc_accumulate(values: torch.Tensor, s: torch.Tensor, s2: torch.Tensor):
+    _check(lib().tlmc_accumulate(_ptr(values), values.numel(), _ptr(s), _ptr(s2), _stream()), "tlmc_accumulate")
 
 
 class NircFunction(torch.autograd.Function):
