@@ -60,6 +60,7 @@ def lib():
         L.oracle_J.argtypes = [_dbl, _dbl, _int]
         L.oracle_J.restype = _dbl
         L.oracle_closed_form.argtypes = [_i64] + [_f32p] * 6 + [_f32p, _int, _f64p]
+        L.oracle_second_moment.argtypes = [_i64] + [_f32p] * 6 + [_f32p, _int, _f64p]
         L.oracle_loss_grad.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _f64p, _int,
                                        _dbl, _int, _Opt(_f64p)])
         L.oracle_loss_grad.restype = _dbl
@@ -162,6 +163,16 @@ def closed_form(points, lobes_packed, n_nodes: int = 256) -> np.ndarray:
     p = _pts(points)
     lib().oracle_closed_form(P, p[0], p[1], p[2], p[3], p[4], p[5],
                              np.ascontiguousarray(lobes_packed, np.float32), n_nodes, out)
+    return out
+
+
+def second_moment(points, lobes_packed, n_nodes: int = 256) -> np.ndarray:
+    """E[L^2] under cosine-weighted sampling per point and channel, [P, 3] FP64."""
+    P = points.count
+    out = np.zeros((P, 3), np.float64)
+    p = _pts(points)
+    lib().oracle_second_moment(P, p[0], p[1], p[2], p[3], p[4], p[5],
+                               np.ascontiguousarray(lobes_packed, np.float32), n_nodes, out)
     return out
 
 

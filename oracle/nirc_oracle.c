@@ -445,6 +445,40 @@ void oracle_closed_form(int64_t P, const float *px, const float *py, const float
     }
 }
 
+/* Second moment of the field under cosine sampling, per channel:
+ *   E[L^2] = (1/pi) int L(x, w)^2 (n . w) dw
+ *          = sum_j sum_k a_j a_k e^{K_jk - kappa_j - kappa_k} J(K_jk, nu_jk . n),
+ * because the product of two lobes is a lobe: kappa_j mu_j . w + kappa_k mu_k . w = K nu . w with
+ * K = |kappa_j mu_j + kappa_k mu_k| and nu its direction (J(0, t) = 1).                         */
+void oracle_second_moment(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
+                          const float *ny, const float *nz, const float *lobes, int n_nodes, double *M2)
+{
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+    double xs[1024], ws[1024];
+    if (n_nodes > 1024) n_nodes = 1024;
+    oracle_gauss_legendre(n_nodes, xs, ws);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < P; ++p) {
+        double x[3] = {px[p], py[p], pz[p]};
+        double n[3] = {nx[p], ny[p], nz[p]};
+        double acc[3] = {0, 0, 0};
+        for (int j = 0; j < NLOBES; ++j)
+            for (int k = 0; k < NLOBES; ++k) {
+                double aj[3], ak[3], v[3];
+                lobe_amplitude(&L, j, x, aj);
+                lobe_amplitude(&L, k, x, ak);
+                for (int d = 0; d < 3; ++d) v[d] = L.kappa[j] * L.axis[j][d] + L.kappa[k] * L.axis[k][d];
+                double K = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                double J = 1.0;
+                if (K > 1e-12) J = J_on_nodes(K, (v[0] * n[0] + v[1] * n[1] + v[2] * n[2]) / K, n_nodes, xs, ws);
+                double e = exp(K - L.kappa[j] - L.kappa[k]) * J;
+                for (int c = 0; c < 3; ++c) acc[c] += aj[c] * ak[c] * e;
+            }
+        for (int c = 0; c < 3; ++c) M2[3 * p + c] = acc[c];
+    }
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Training (Sec. "Radiance Cache Optimization", eq. 12 read on radiance with p_r = 1):
  *   loss = (1/(3B)) sum_{b,c} (y - t)^2 / (sg(y)^2 + eps),

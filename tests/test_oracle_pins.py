@@ -232,6 +232,40 @@ def test_J_two_dimensional_brute_force(kappa, t):
     assert oracle.J(kappa, t) == pytest.approx(val / math.pi, rel=1e-9)
 
 
+def test_second_moment_against_quadrature():
+    # E[L^2] by the lobe-product closed form vs a deterministic hemisphere quadrature of L^2
+    pts = wl.make_points(22, 6)
+    lobes = wl.make_lobes(22).packed()
+    M2 = oracle.second_moment(pts, lobes)
+    gx, gw = np.polynomial.legendre.leggauss(400)
+    u1 = 0.5 * (gx + 1)
+    wu = 0.5 * gw
+    m2 = 400
+    u2 = (np.arange(m2) + 0.5) / m2
+    U1, U2 = np.meshgrid(u1, u2, indexing="ij")
+    Wt = np.outer(wu, np.full(m2, 1.0 / m2)).ravel()
+    for p in range(6):
+        nrm = np.array([pts.nx[p], pts.ny[p], pts.nz[p]], np.float64)
+        nrm /= np.linalg.norm(nrm)
+        a = np.array([1.0, 0, 0]) if abs(nrm[0]) < 0.9 else np.array([0, 1.0, 0])
+        t1 = np.cross(nrm, a); t1 /= np.linalg.norm(t1)
+        t2 = np.cross(nrm, t1)
+        r = np.sqrt(U1.ravel())
+        loc = np.stack([r * np.cos(2 * np.pi * U2.ravel()), r * np.sin(2 * np.pi * U2.ravel()),
+                        np.sqrt(1 - U1.ravel())], axis=1)
+        dirs = loc[:, :1] * t1 + loc[:, 1:2] * t2 + loc[:, 2:3] * nrm
+        L = oracle.field(lobes, pts, np.full(dirs.shape[0], p, np.int32), dirs)
+        q = (Wt[:, None] * L * L).sum(0)
+        np.testing.assert_allclose(M2[p], q, rtol=2e-4)
+    # kappa -> 0 with a single lobe: E[L^2] = a^2 exactly (J(0, t) = 1)
+    iso = wl.make_lobes(22)
+    iso.kappa[:] = 0.0
+    iso.alpha[1:] = 0.0
+    iso.beta[:] = 0.0
+    M0 = oracle.second_moment(pts, iso.packed())
+    np.testing.assert_allclose(M0, np.tile(iso.alpha[0].astype(np.float64) ** 2, (6, 1)), rtol=1e-12)
+
+
 def test_closed_form_against_plug_in_monte_carlo():
     # With the field itself as the cache (y := L), F_c is a plain cosine-weighted MC estimate
     # of F; its mean over many directions must reach the closed form within sampling error.
