@@ -22,6 +22,7 @@ if ROOT not in sys.path:
 
 METRIC = "NIRC queries/s + ms/frame at 1080p N=16; BF16 vs FP32 at equal MRSE"
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix peak, FLOP/s
+PEAK_BF16_MFMA = 2.5e15        # MI355X dense BF16/FP16 matrix peak, FLOP/s
 PEAK_HBM = 8.0e12              # bytes/s
 
 
@@ -75,6 +76,38 @@ def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=15.0):
                       f"steps of {b} samples (batch scaled by the same fraction); {t:.1f} s"}
 
 
+def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, frame, reps):
+    """BF16 and FP16 estimates with the FP32 model's current weights, same seed and frame:
+    time per launch (HIP events on the launch stream) and MRSE against the exact integral."""
+    import torch
+    stream = torch.cuda.current_stream()
+    w = model32.get_weights()
+    lob = nirc.lobes_struct(lobes_for(frame))
+    out = {}
+    for name, prec in (("fp32", 0), ("bf16", 1), ("fp16", 2)):
+        m = model32 if prec == 0 else nirc.Model(w, cfg=nirc.make_config(precision=prec), max_batch=0)
+        tl = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+        nirc.tlmc_estimate(m, dp, lob, N, seed, frame, out=tl)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            nirc.tlmc_estimate(m, dp, lob, N, seed, frame, out=tl)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+        mrse = float(nirc.tlmc_frame_stats(dp, lob, table, tl, fs=fs)[4].item())
+        flops = algorithmic_flops_estimate(P, N, W)
+        peak = PEAK_FP32_MFMA if prec == 0 else PEAK_BF16_MFMA
+        out[name] = {"ms_estimate": t * 1e3, "queries_per_s": P * (N + 1) / t, "mrse": mrse,
+                     "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": peak / 1e12,
+                                  "unit": "TFLOP/s", "frac": flops / t / peak}}
+    for name in ("bf16", "fp16"):
+        out[name]["speedup_vs_fp32"] = out["fp32"]["ms_estimate"] / out[name]["ms_estimate"]
+        out[name]["mrse_rel_diff_vs_fp32"] = (out[name]["mrse"] - out["fp32"]["mrse"]) / out["fp32"]["mrse"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +115,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="1080p_n16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-compare", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the hot path has no "
@@ -192,6 +226,9 @@ def main():
         "mrse_first_last": [mrse[0], mrse[-1]],
         "final_loss": float(loss.item()),
     }
+    if not args.no_precision_compare:
+        result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
+                                                        args.warmup + args.steps, args.steps)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene.points, lobes_for, w0, W, N, B, S)
     print(json.dumps(result), flush=True)

@@ -2,7 +2,7 @@
 #include <new>
 #include <string.h>
 
-#include "nirc_kernels.hpp"
+#include "nirc_h16.hpp"
 
 using namespace nirc;
 
@@ -14,16 +14,19 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool width_ok(int32_t w) { return w == 64; }
 
-// State layout (each piece 256-byte aligned): master | m | v | packed | step | flags | bad.
+// State layout (each piece 256-byte aligned): master | m | v | packed FP32 | packed 16-bit (BF16
+// and FP16 models only) | step | flags | bad.
 struct StateLayout {
-    size_t master, m, v, packed, step, flags, bad, total;
-    explicit StateLayout(int W) {
+    size_t master, m, v, packed, packed16, step, flags, bad, total;
+    StateLayout(int W, int prec) {
         const size_t np = (size_t)n_params(W) * sizeof(float);
         size_t o = 0;
         master = o; o += align_up(np);
         m = o; o += align_up(np);
         v = o; o += align_up(np);
         packed = o; o += align_up((size_t)F32Layout{W}.total() * sizeof(float));
+        packed16 = o;
+        if (prec != NIRC_FP32) o += align_up((size_t)H16Layout{W}.total() * sizeof(uint16_t));
         step = o; o += align_up(sizeof(int64_t));
         flags = o; o += align_up(sizeof(uint32_t));
         bad = o; o += align_up(sizeof(uint32_t));
@@ -72,6 +75,7 @@ struct nirc_model {
     int W;
     int64_t np;
     float *master, *m, *v, *packed;
+    uint16_t *packed16;   // NULL for FP32 models
     int64_t *step;
     uint32_t *flags, *bad;
     char *ws;
@@ -96,7 +100,8 @@ int64_t nirc_n_params(int32_t width) { return width_ok(width) ? n_params(width) 
 static nirc_status check_config(const nirc_config *cfg) {
     if (!cfg) return NIRC_ERR_INVALID_ARG;
     if (!width_ok(cfg->width)) return NIRC_ERR_UNSUPPORTED;
-    if (cfg->precision != NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
+    if (cfg->precision != NIRC_FP32 && cfg->precision != NIRC_BF16 && cfg->precision != NIRC_FP16)
+        return NIRC_ERR_UNSUPPORTED;
     if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
         !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->adam_eps > 0.0f) ||
         !(cfg->loss_eps > 0.0f) || !(cfg->loss_scale > 0.0f))
@@ -106,7 +111,7 @@ static nirc_status check_config(const nirc_config *cfg) {
 
 size_t nirc_state_bytes(const nirc_config *cfg) {
     if (check_config(cfg) != NIRC_OK) return 0;
-    return StateLayout(cfg->width).total;
+    return StateLayout(cfg->width, cfg->precision).total;
 }
 
 size_t nirc_workspace_bytes(const nirc_config *cfg, int64_t max_batch) {
@@ -120,7 +125,7 @@ nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes,
     if (st != NIRC_OK) return st;
     if (!state || !init_w || !out || ((uintptr_t)state % kAlign) != 0) return NIRC_ERR_INVALID_ARG;
     if (workspace && ((uintptr_t)workspace % kAlign) != 0) return NIRC_ERR_INVALID_ARG;
-    const StateLayout sl(cfg->width);
+    const StateLayout sl(cfg->width, cfg->precision);
     if (state_bytes < sl.total) return NIRC_ERR_WORKSPACE;
     nirc_model *m = new (std::nothrow) nirc_model;
     if (!m) return NIRC_ERR_INVALID_ARG;
@@ -132,6 +137,7 @@ nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes,
     m->m = (float *)(base + sl.m);
     m->v = (float *)(base + sl.v);
     m->packed = (float *)(base + sl.packed);
+    m->packed16 = cfg->precision != NIRC_FP32 ? (uint16_t *)(base + sl.packed16) : nullptr;
     m->step = (int64_t *)(base + sl.step);
     m->flags = (uint32_t *)(base + sl.flags);
     m->bad = (uint32_t *)(base + sl.bad);
@@ -165,6 +171,8 @@ nirc_status nirc_set_weights(nirc_model *model, const float *w, void *stream) {
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->v, model->np, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->step, 2, 0u, s);
     if (e == hipSuccess) e = launch_pack(model->packed, model->master, model->W, s);
+    if (e == hipSuccess && model->packed16)
+        e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
     return hip_status(e);
 }
 
@@ -212,7 +220,8 @@ nirc_status nirc_infer(const nirc_model *model, nirc_points points, nirc_queries
     if (st == NIRC_OK) st = check_queries(queries, points);
     if (st != NIRC_OK) return st;
     if (queries.count > 0 && !rgb) return NIRC_ERR_INVALID_ARG;
-    return hip_status(launch_infer(model->W, to_points(points), to_queries(queries), model->packed, rgb,
+    const void *pk = model->packed16 ? (const void *)model->packed16 : (const void *)model->packed;
+    return hip_status(launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries), pk, rgb,
                                    (hipStream_t)stream));
 }
 
@@ -231,8 +240,9 @@ nirc_status tlmc_estimate(const nirc_model *model, nirc_points points, const nir
     nirc_status st = check_points(points);
     if (st != NIRC_OK) return st;
     if (n_cache < 1 || n_cache > 4096 || (points.count > 0 && !out_tl)) return NIRC_ERR_INVALID_ARG;
-    return hip_status(launch_tlmc(model->W, to_points(points), *field, model->packed, n_cache, seed, frame,
-                                  out_tl, out_c, out_r, (hipStream_t)stream));
+    const void *pk = model->packed16 ? (const void *)model->packed16 : (const void *)model->packed;
+    return hip_status(launch_tlmc(model->W, model->cfg.precision, to_points(points), *field, pk, n_cache, seed,
+                                  frame, out_tl, out_c, out_r, (hipStream_t)stream));
 }
 
 nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field, int64_t batch, uint64_t seed,
@@ -296,6 +306,8 @@ nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream) {
     if (e == hipSuccess)
         e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags, model->bad,
                         model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps, model->packed, s);
+    if (e == hipSuccess && model->packed16)
+        e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
     return hip_status(e);
 }
 
@@ -310,9 +322,12 @@ nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries 
     float *wloss = (float *)(model->ws + wl.loss);
     nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss ? loss : wloss, s);
     if (st != NIRC_OK) return st;
-    return hip_status(launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
-                                  model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2,
-                                  model->cfg.adam_eps, model->packed, s));
+    hipError_t e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
+                               model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps,
+                               model->packed, s);
+    if (e == hipSuccess && model->packed16)
+        e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
+    return hip_status(e);
 }
 
 nirc_status tlmc_reference_table(const nirc_lobes *field, double *table, void *stream) {

@@ -1,0 +1,212 @@
+// 16-bit (BF16 / FP16) MLP chain on v_mfma_f32_16x16x32_{bf16,f16}: FP32 accumulation, 16-bit
+// operands, weights packed so that consecutive layers chain through registers.
+#pragma once
+
+#include "nirc_kernels.hpp"
+
+namespace nirc {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 8 16-bit values (one operand)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// ------------------------------------------------------------------------------------------
+// Layout.  MFMA 16x16x32: lane l holds A[row l%16][k 8(l/16) + j] and B[k 8(l/16) + j][col l%16],
+// j = 0..7; the result gives lane l rows 4(l/16) + i of column l%16 (as for 16x16x4).  K-block b
+// of a chained layer is built from result row tiles 2b (positions j < 4) and 2b + 1 (j >= 4):
+//   K position 32 b + 8 g + j  <->  neuron 32 b + 16 (j / 4) + 4 g + j % 4.
+// Input features: lane group g holds the same 28 surface / 12 direction features as in the FP32
+// layout (frequencies 2g, 2g+1 of every input); feature t goes to K-block t / 8, position t % 8,
+// and positions past the last feature are zero.
+// Sections (MT row tiles x KB K-blocks x 64 lanes x 8 values, stored [mt][kb][lane][8]):
+//   S  W1 surface    MT = W/16, KB = 4     D  W1 direction  MT = W/16, KB = 2
+//   H0..H2 W2..W4    MT = W/16, KB = W/32  O  W5           MT = 1,    KB = W/32
+//   T0..T2 W2^T..W4^T MT = W/16, KB = W/32 OT W5^T          MT = W/16, KB = 1
+struct H16Layout {
+    int W;
+    __host__ __device__ constexpr int mt(int s) const { return s == SEC_O ? 1 : W / 16; }
+    __host__ __device__ constexpr int kb(int s) const {
+        return s == SEC_S ? 4 : s == SEC_D ? 2 : s == SEC_OT ? 1 : W / 32;
+    }
+    __host__ __device__ constexpr int size(int s) const { return mt(s) * kb(s) * 512; }
+    __host__ __device__ constexpr int offset(int s) const {
+        int o = 0;
+        for (int i = 0; i < s; ++i) o += size(i);
+        return o;
+    }
+    __host__ __device__ constexpr int total() const { return offset(SEC_N); }
+};
+
+__host__ __device__ inline int chained_neuron16(int kb, int g, int j) {
+    return 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3);
+}
+
+// Canonical parameter index of packed 16-bit element e (or -1 for zero padding).
+__host__ __device__ inline int64_t h16_packed_source(int W, int e) {
+    const H16Layout L{W};
+    int s = 0;
+    while (s + 1 < SEC_N && e >= L.offset(s + 1)) ++s;
+    const int r = e - L.offset(s);
+    const int KB = L.kb(s);
+    const int j = r & 7, lane = (r >> 3) & 63, rest = r >> 9;
+    const int kb = rest % KB, m = rest / KB;
+    const int row = 16 * m + (lane & 15), g = lane >> 4;
+    const int t = 8 * kb + j;
+    switch (s) {
+    case SEC_S: return t < 28 ? w_offset(W, 0) + (int64_t)row * kFeat + feature_of(true, g, t) : -1;
+    case SEC_D: return t < 12 ? w_offset(W, 0) + (int64_t)row * kFeat + feature_of(false, g, t) : -1;
+    case SEC_H0: case SEC_H1: case SEC_H2:
+        return w_offset(W, 1 + (s - SEC_H0)) + (int64_t)row * W + chained_neuron16(kb, g, j);
+    case SEC_O:
+        return row < 3 ? w_offset(W, 4) + (int64_t)row * W + chained_neuron16(kb, g, j) : -1;
+    case SEC_T0: case SEC_T1: case SEC_T2:
+        return w_offset(W, 1 + (s - SEC_T0)) + (int64_t)chained_neuron16(kb, g, j) * W + row;
+    case SEC_OT: {
+        const int o = 4 * g + j;   // output row at (g, j < 4); j >= 4 would be a second tile
+        return (j < 4 && o < 3) ? w_offset(W, 4) + (int64_t)o * W + row : -1;
+    }
+    default: return -1;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Precision traits: PREC = NIRC_BF16 or NIRC_FP16.
+
+template <int PREC>
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+    const f32x2 v = {a, b};
+    if constexpr (PREC == NIRC_BF16) return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+    else return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+}
+
+// ReLU on two packed 16-bit values: both formats keep the sign in the top bit, so a signed
+// 16-bit max with 0 clears negatives (and -0).
+__device__ __forceinline__ uint32_t relu2(uint32_t x) {
+    i16x2 v = __builtin_bit_cast(i16x2, x);
+    const i16x2 z = {0, 0};
+    v = v > z ? v : z;
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
+    if constexpr (PREC == NIRC_BF16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+}
+
+// sin/cos(pi 2^k v) for k = 2g and 2g + 1: the hardware sine/cosine (argument in revolutions) at
+// the lower frequency, then one angle doubling.  Accurate to ~1e-6, far below 16-bit rounding.
+__device__ __forceinline__ void enc_pair2_fast(float v, int g, float &s0, float &c0, float &s1, float &c1) {
+    const float rev = ldexpf(v, 2 * g - 1);   // 2^(2g) pi v in revolutions
+    s0 = __builtin_amdgcn_sinf(rev);
+    c0 = __builtin_amdgcn_cosf(rev);
+    s1 = 2.0f * s0 * c0;
+    c1 = (c0 - s0) * (c0 + s0);
+}
+
+// B operand (two K-blocks of the chain) from two result tiles, with ReLU.
+template <int PREC>
+__device__ __forceinline__ u32x4 chain_operand(const f32x4 &lo, const f32x4 &hi) {
+    return u32x4{relu2(pack2<PREC>(lo[0], lo[1])), relu2(pack2<PREC>(lo[2], lo[3])),
+                 relu2(pack2<PREC>(hi[0], hi[1])), relu2(pack2<PREC>(hi[2], hi[3]))};
+}
+
+// h += W1_s e_s for one tile of 16 columns (surface features in B layout, 4 K-blocks).
+template <int W, int PREC>
+__device__ __forceinline__ void layer1_surface16(f32x4 (&h)[W / 16], const uint16_t *gS, const float xs[7],
+                                                 int lane, int g) {
+    constexpr int MT = W / 16;
+    float f[32];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) enc_pair2_fast(xs[i], g, f[4 * i], f[4 * i + 1], f[4 * i + 2], f[4 * i + 3]);
+    f[28] = f[29] = f[30] = f[31] = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const u32x4 b = {pack2<PREC>(f[8 * kb], f[8 * kb + 1]), pack2<PREC>(f[8 * kb + 2], f[8 * kb + 3]),
+                         pack2<PREC>(f[8 * kb + 4], f[8 * kb + 5]), pack2<PREC>(f[8 * kb + 6], f[8 * kb + 7])};
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const u32x4 a = *(const u32x4 *)(gS + ((mt * 4 + kb) * 64 + lane) * 8);
+            h[mt] = mfma16<PREC>(a, b, h[mt]);
+        }
+    }
+}
+
+// Direction features of one tile as two B operands.
+template <int PREC>
+__device__ __forceinline__ void direction_operands(float dx, float dy, float dz, int g, u32x4 &b0, u32x4 &b1) {
+    float f[12];
+    enc_pair2_fast(dx, g, f[0], f[1], f[2], f[3]);
+    enc_pair2_fast(dy, g, f[4], f[5], f[6], f[7]);
+    enc_pair2_fast(dz, g, f[8], f[9], f[10], f[11]);
+    b0 = u32x4{pack2<PREC>(f[0], f[1]), pack2<PREC>(f[2], f[3]), pack2<PREC>(f[4], f[5]), pack2<PREC>(f[6], f[7])};
+    b1 = u32x4{pack2<PREC>(f[8], f[9]), pack2<PREC>(f[10], f[11]), 0u, 0u};
+}
+
+// Layer 1 (direction part, accumulating onto h) + ReLU, then layers 2..4, for T tiles; leaves
+// the hidden activations of layer 4 as chained B operands hb[tt][kb].
+template <int W, int PREC, int T>
+__device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
+                                      const uint16_t *sD, const uint16_t *sH, int lane, int nt) {
+    constexpr int MT = W / 16, KB = W / 32;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const u32x4 a = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+                if (tt < nt) h[tt][mt] = mfma16<PREC>(a, bd[tt][kb], h[tt][mt]);
+        }
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const uint16_t *sec = sH + l * (MT * KB * 512);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) h[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const u32x4 a = *(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8);
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt)
+                    if (tt < nt) h[tt][mt] = mfma16<PREC>(a, hb[tt][kb], h[tt][mt]);
+            }
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
+    }
+}
+
+// Output layer: lanes 0..15 receive z = W5 h4 of their column.
+template <int W, int PREC, int T>
+__device__ __forceinline__ void output16(f32x4 (&y)[T], const u32x4 (&hb)[T][W / 32], const uint16_t *sO, int lane,
+                                         int nt) {
+    constexpr int KB = W / 32;
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) y[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const u32x4 a = *(const u32x4 *)(sO + (kb * 64 + lane) * 8);
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+            if (tt < nt) y[tt] = mfma16<PREC>(a, hb[tt][kb], y[tt]);
+    }
+}
+
+}  // namespace nirc

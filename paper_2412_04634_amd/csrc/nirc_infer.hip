@@ -203,43 +203,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
 
         float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
         for (int tb = 0; tb < n_tiles; tb += 8) {
-            // --- directions for tiles tb..tb+7: lane = pair of consecutive queries
-            {
-                const int T = tb + (lane >> 3);
-                const int c0 = (2 * lane) & 15;
-                float wa[3] = {0.f, 0.f, 0.f}, wb[3] = {0.f, 0.f, 0.f};
-                if (T <= n_cache) {
-                    const bool res = (T == n_cache);
-                    int ja, jb, ka = 0, kb = 0;
-                    if (res) {
-                        ja = c0;
-                        jb = c0 + 1;
-                    } else {
-                        const int qa = 16 * T + c0;
-                        ja = qa / n_cache;
-                        ka = qa - ja * n_cache;
-                        jb = (qa + 1) / n_cache;
-                        kb = qa + 1 - jb * n_cache;
-                    }
-                    const int64_t pa = p0 + ja, pb = p0 + jb;
-                    const DirCounter ca = dir_counter((uint32_t)pa, ka, res);
-                    const DirCounter cb = dir_counter((uint32_t)pb, kb, res);
-                    const Rand4 ra = philox(ca.c0, ca.c1, frame, ca.stream, key0, key1);
-                    Rand4 rb = ra;
-                    if (ca.c0 != cb.c0 || ca.c1 != cb.c1)   // only for odd N
-                        rb = philox(cb.c0, cb.c1, frame, cb.stream, key0, key1);
-                    const int64_t qa_ = min(pa, P - 1), qb_ = min(pb, P - 1);
-                    dir_from_rand(ra, ca.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], wa[0], wa[1], wa[2]);
-                    dir_from_rand(rb, cb.half, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], wb[0], wb[1], wb[2]);
-                }
-                wave_sync();   // the previous batch's readers are done
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    db[128 * d + 2 * lane] = wa[d];
-                    db[128 * d + 2 * lane + 1] = wb[d];
-                }
-                wave_sync();
-            }
+            gen_dirs_batch(pts, p0, tb, n_cache, key0, key1, frame, lane, db);
             // --- MLP over the staged tiles, 4 at a time
 #pragma unroll 1
             for (int sb = 0; sb < 8; sb += 4) {
@@ -272,31 +236,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
                     const int T = t0 + tt;
                     const float y0 = expf(y[tt][0]), y1 = expf(y[tt][1]), y2 = expf(y[tt][2]);
                     if (T < n_cache) {
-                        // 16-lane inclusive prefix sums of the cache predictions
-                        float s0 = y0, s1 = y1, s2 = y2;
-#pragma unroll
-                        for (int d = 1; d < 16; d <<= 1) {
-                            const float u0 = __shfl_up(s0, d, 16);
-                            const float u1 = __shfl_up(s1, d, 16);
-                            const float u2 = __shfl_up(s2, d, 16);
-                            if (col >= d) {
-                                s0 += u0;
-                                s1 += u1;
-                                s2 += u2;
-                            }
-                        }
-                        // point `col` owns queries [col N, col N + N) -> columns [lo, hi)
-                        const int a = col * n_cache - 16 * T;
-                        const int lo = max(a, 0), hi = min(a + n_cache, 16);
-                        const int shi = min(max(hi - 1, 0), 15), slo = min(max(lo - 1, 0), 15);
-                        const float h0 = __shfl(s0, shi, 16), l0 = __shfl(s0, slo, 16);
-                        const float h1 = __shfl(s1, shi, 16), l1 = __shfl(s1, slo, 16);
-                        const float h2 = __shfl(s2, shi, 16), l2 = __shfl(s2, slo, 16);
-                        if (lo < hi) {
-                            fc0 += lo > 0 ? h0 - l0 : h0;
-                            fc1 += lo > 0 ? h1 - l1 : h1;
-                            fc2 += lo > 0 ? h2 - l2 : h2;
-                        }
+                        reduce_cache_tile(T, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
                     } else {
                         float Lr[3];
                         field_eval(s_lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
@@ -307,23 +247,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
                 }
             }
         }
-        if (g == 0 && p0 + col < P) {
-            const int64_t o = 3 * (p0 + col);
-            const float c0 = fc0 * inv_n, c1 = fc1 * inv_n, c2 = fc2 * inv_n;
-            out_tl[o + 0] = c0 + fr0;
-            out_tl[o + 1] = c1 + fr1;
-            out_tl[o + 2] = c2 + fr2;
-            if (out_c) {
-                out_c[o + 0] = c0;
-                out_c[o + 1] = c1;
-                out_c[o + 2] = c2;
-            }
-            if (out_r) {
-                out_r[o + 0] = fr0;
-                out_r[o + 1] = fr1;
-                out_r[o + 2] = fr2;
-            }
-        }
+        if (g == 0 && p0 + col < P) store_estimate(p0 + col, inv_n, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
     }
 }
 
@@ -374,34 +298,38 @@ hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_
     return hipGetLastError();
 }
 
-static unsigned grid_for(int64_t units_per_wave_total, int waves, int max_blocks) {
+unsigned grid_for(int64_t units_per_wave_total, int waves, int max_blocks) {
     int64_t b = (units_per_wave_total + waves - 1) / waves;
     if (b > max_blocks) b = max_blocks;
     if (b < 1) b = 1;
     return (unsigned)b;
 }
 
-hipError_t launch_infer(int W, const Points &pts, const Queries &q, const float *packed, float *rgb,
+hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
                         hipStream_t s) {
     if (q.count == 0) return hipSuccess;
+    if (prec != NIRC_FP32) return launch_infer_h16(W, prec, pts, q, packed, rgb, s);
     constexpr int WAVES = 4;
-    const unsigned grid = grid_for((q.count + 15) / 16, WAVES, kMaxResidentBlocks);
+    const unsigned grid = grid_for((q.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
     if (W == 64)
-        hipLaunchKernelGGL((k_infer_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, packed, rgb);
+        hipLaunchKernelGGL((k_infer_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, (const float *)packed,
+                           rgb);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_tlmc(int W, const Points &pts, const nirc_lobes &lobes, const float *packed,
+hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
                        int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
                        float *out_r, hipStream_t s) {
     if (pts.count == 0) return hipSuccess;
+    if (prec != NIRC_FP32)
+        return launch_tlmc_h16(W, prec, pts, lobes, packed, n_cache, seed, frame, out_tl, out_c, out_r, s);
     constexpr int WAVES = 4;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, kMaxResidentBlocks);
     if (W == 64)
         hipLaunchKernelGGL((k_tlmc_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes,
-                           packed, n_cache, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame,
+                           (const float *)packed, n_cache, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame,
                            out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;

@@ -1,0 +1,203 @@
+// BF16 / FP16 inference kernels: per-query inference and the fused two-level estimator with
+// 16-bit MFMA operands and FP32 accumulation (master weights stay FP32; a 16-bit packed copy is
+// refreshed after every Adam step).
+#include "nirc_h16.hpp"
+
+namespace nirc {
+
+// packed16[e] = 16-bit(master[source(e)]) (round to nearest even), zero padding elsewhere.
+template <int PREC>
+__global__ void k_pack16(uint16_t *packed, const float *master, int W, int total) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int64_t s = h16_packed_source(W, e);
+    const float v = s >= 0 ? master[s] : 0.0f;
+    packed[e] = (uint16_t)(pack2<PREC>(v, 0.0f) & 0xFFFFu);
+}
+
+template <int W>
+struct Infer16Lds {
+    static constexpr int kWeights = H16Layout{W}.offset(SEC_T0) - H16Layout{W}.offset(SEC_D);   // elements
+};
+
+// Per-query inference: 16 queries per wave per iteration, all 160 features per query.
+template <int W, int PREC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q, const uint16_t *__restrict__ packed,
+                                                          float *__restrict__ rgb) {
+    constexpr H16Layout L{W};
+    constexpr int MT = W / 16, KB = W / 32;
+    constexpr int NW = Infer16Lds<W>::kWeights;
+    __shared__ u32x4 smem4[NW / 8];
+    {
+        const u32x4 *src = (const u32x4 *)(packed + L.offset(SEC_D));
+        for (int i = threadIdx.x; i < NW / 8; i += WAVES * 64) smem4[i] = src[i];
+    }
+    __syncthreads();
+    const uint16_t *smem = (const uint16_t *)smem4;
+    const uint16_t *sD = smem;
+    const uint16_t *sH = smem + L.size(SEC_D);
+    const uint16_t *sO = sH + 3 * L.size(SEC_H0);
+    const uint16_t *gS = packed + L.offset(SEC_S);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t Q = q.count;
+    const int64_t n_tiles = (Q + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < n_tiles; tile += (int64_t)gridDim.x * WAVES) {
+        const int64_t qi = min((tile << 4) + col, Q - 1);
+        const int64_t p = query_point(q, pts, qi);
+        const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+        f32x4 h[1][MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) h[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer1_surface16<W, PREC>(h[0], opaque(gS), xs, lane, g);
+        u32x4 bd[1][2];
+        direction_operands<PREC>(q.wx[qi], q.wy[qi], q.wz[qi], g, bd[0][0], bd[0][1]);
+        u32x4 hb[1][KB];
+        mlp16<W, PREC, 1>(h, hb, bd, sD, sH, lane, 1);
+        f32x4 y[1];
+        output16<W, PREC, 1>(y, hb, sO, lane, 1);
+        if (g == 0 && (tile << 4) + col < Q) {
+            float *o = rgb + 3 * ((tile << 4) + col);
+            o[0] = __expf(y[0][0]);
+            o[1] = __expf(y[0][1]);
+            o[2] = __expf(y[0][2]);
+        }
+    }
+}
+
+// Fused two-level estimator, same organisation as the FP32 kernel (16 points per wave, surface
+// projection once per point into an LDS slab, 8 tiles of directions per Philox batch, 4 tiles
+// per MLP pass, in-wave per-point reduction), with 16-bit operands.
+template <int W, int PREC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes lobes, const uint16_t *__restrict__ packed,
+                                                         int n_cache, uint32_t key0, uint32_t key1, uint32_t frame,
+                                                         float *__restrict__ out_tl, float *__restrict__ out_c,
+                                                         float *__restrict__ out_r) {
+    constexpr H16Layout L{W};
+    constexpr int MT = W / 16, KB = W / 32;
+    constexpr int NW = Infer16Lds<W>::kWeights;   // 16-bit elements
+    constexpr int SLAB = TlmcLds<W>::kSlab;         // floats per wave
+    __shared__ u32x4 wsm[NW / 8];
+    __shared__ f32x4 slab4[WAVES * SLAB / 4];
+    __shared__ nirc_lobes s_lobes;
+    {
+        const u32x4 *src = (const u32x4 *)(packed + L.offset(SEC_D));
+        for (int i = threadIdx.x; i < NW / 8; i += WAVES * 64) wsm[i] = src[i];
+        if (threadIdx.x == 0) s_lobes = lobes;
+    }
+    __syncthreads();
+    const uint16_t *sD = (const uint16_t *)wsm;
+    const uint16_t *sH = sD + L.size(SEC_D);
+    const uint16_t *sO = sH + 3 * L.size(SEC_H0);
+    const uint16_t *gS = packed + L.offset(SEC_S);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    float *hs = (float *)slab4 + wave * SLAB;   // [16 points][W]
+    float *db = hs + 16 * W;                    // directions, SoA [3][128]
+    const int64_t P = pts.count;
+    const int64_t n_groups = (P + 15) >> 4;
+    const int n_tiles = n_cache + 1;
+    const float inv_n = 1.0f / (float)n_cache;
+
+    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES) {
+        const int64_t p0 = grp << 4;
+        const int64_t pc = min(p0 + col, P - 1);
+        const float xs[7] = {pts.px[pc], pts.py[pc], pts.pz[pc], pts.nx[pc], pts.ny[pc], pts.nz[pc], pts.rough[pc]};
+        {
+            f32x4 hsum[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
+            wave_sync();
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+        }
+        float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
+        for (int tb = 0; tb < n_tiles; tb += 8) {
+            gen_dirs_batch(pts, p0, tb, n_cache, key0, key1, frame, lane, db);
+#pragma unroll 1
+            for (int sb = 0; sb < 8; sb += 4) {
+                const int t0 = tb + sb;
+                if (t0 >= n_tiles) break;
+                const int nt = min(4, n_tiles - t0);
+                f32x4 h[4][MT];
+                u32x4 bd[4][2];
+                float dx[4], dy[4], dz[4];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    const int T = t0 + tt;
+                    const int qi = 16 * (sb + tt) + col;
+                    dx[tt] = db[qi];
+                    dy[tt] = db[128 + qi];
+                    dz[tt] = db[256 + qi];
+                    const int j = (T < n_cache) ? (16 * T + col) / n_cache : col;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        h[tt][mt] = (tt < nt) ? *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
+                    direction_operands<PREC>(dx[tt], dy[tt], dz[tt], g, bd[tt][0], bd[tt][1]);
+                }
+                u32x4 hb[4][KB];
+                mlp16<W, PREC, 4>(h, hb, bd, sD, sH, lane, nt);
+                f32x4 y[4];
+                output16<W, PREC, 4>(y, hb, sO, lane, nt);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    if (tt >= nt) break;
+                    const int T = t0 + tt;
+                    const float y0 = __expf(y[tt][0]), y1 = __expf(y[tt][1]), y2 = __expf(y[tt][2]);
+                    if (T < n_cache) {
+                        reduce_cache_tile(T, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
+                    } else {
+                        float Lr[3];
+                        field_eval(s_lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
+                        fr0 = Lr[0] - y0;
+                        fr1 = Lr[1] - y1;
+                        fr2 = Lr[2] - y2;
+                    }
+                }
+            }
+        }
+        if (g == 0 && p0 + col < P) store_estimate(p0 + col, inv_n, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+
+hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s) {
+    const int total = H16Layout{W}.total();
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL(k_pack16<NIRC_BF16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total);
+    else
+        hipLaunchKernelGGL(k_pack16<NIRC_FP16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
+                            hipStream_t s) {
+    constexpr int WAVES = 4;
+    const unsigned grid = grid_for((q.count + 15) / 16, WAVES, 4 * kMaxResidentBlocks);
+    const uint16_t *pk = (const uint16_t *)packed;
+    if (W != 64) return hipErrorInvalidValue;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_infer_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+    else
+        hipLaunchKernelGGL((k_infer_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+    return hipGetLastError();
+}
+
+hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
+                           int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c, float *out_r,
+                           hipStream_t s) {
+    constexpr int WAVES = 8;
+    const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
+    const uint16_t *pk = (const uint16_t *)packed;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), f = (uint32_t)frame;
+    if (W != 64) return hipErrorInvalidValue;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
+                           n_cache, k0, k1, f, out_tl, out_c, out_r);
+    else
+        hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
+                           n_cache, k0, k1, f, out_tl, out_c, out_r);
+    return hipGetLastError();
+}
+
+}  // namespace nirc

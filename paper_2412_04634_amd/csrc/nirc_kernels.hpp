@@ -151,8 +151,103 @@ __device__ __forceinline__ void output_layer(f32x4 (&y)[T], const f32x4 (&h)[T][
 }
 
 // ------------------------------------------------------------------------------------------
+// Pieces of the fused estimator shared by all precisions.
+
+// Directions of queries 2 lane and 2 lane + 1 of the 128-query batch starting at tile tb of the
+// point group at p0 (N cache tiles, then one residual tile); one Philox block serves both
+// (two blocks only for odd N).  Written to db as SoA [3][128].
+__device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, int tb, int n_cache, uint32_t key0,
+                                               uint32_t key1, uint32_t frame, int lane, float *db) {
+    const int64_t P = pts.count;
+    const int T = tb + (lane >> 3);
+    const int c0 = (2 * lane) & 15;
+    float wa[3] = {0.f, 0.f, 0.f}, wb[3] = {0.f, 0.f, 0.f};
+    if (T <= n_cache) {
+        const bool res = (T == n_cache);
+        int ja, jb, ka = 0, kb = 0;
+        if (res) {
+            ja = c0;
+            jb = c0 + 1;
+        } else {
+            const int qa = 16 * T + c0;
+            ja = qa / n_cache;
+            ka = qa - ja * n_cache;
+            jb = (qa + 1) / n_cache;
+            kb = qa + 1 - jb * n_cache;
+        }
+        const int64_t pa = p0 + ja, pb = p0 + jb;
+        const DirCounter ca = dir_counter((uint32_t)pa, ka, res);
+        const DirCounter cb = dir_counter((uint32_t)pb, kb, res);
+        const Rand4 ra = philox(ca.c0, ca.c1, frame, ca.stream, key0, key1);
+        Rand4 rb = ra;
+        if (ca.c0 != cb.c0 || ca.c1 != cb.c1)   // only for odd N
+            rb = philox(cb.c0, cb.c1, frame, cb.stream, key0, key1);
+        const int64_t qa_ = min(pa, P - 1), qb_ = min(pb, P - 1);
+        dir_from_rand(ra, ca.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], wa[0], wa[1], wa[2]);
+        dir_from_rand(rb, cb.half, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], wb[0], wb[1], wb[2]);
+    }
+    wave_sync();   // the previous batch's readers are done
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        db[128 * d + 2 * lane] = wa[d];
+        db[128 * d + 2 * lane + 1] = wb[d];
+    }
+    wave_sync();
+}
+
+// Cache tile T: lanes 0..15 hold y of queries 16 T + column; point `col` (lanes 0..15) adds the
+// sum of its queries in this tile, found from 16-lane inclusive prefix sums.
+__device__ __forceinline__ void reduce_cache_tile(int T, int n_cache, int col, float y0, float y1, float y2,
+                                                  float &fc0, float &fc1, float &fc2) {
+    float s0 = y0, s1 = y1, s2 = y2;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+        const float u0 = __shfl_up(s0, d, 16);
+        const float u1 = __shfl_up(s1, d, 16);
+        const float u2 = __shfl_up(s2, d, 16);
+        if (col >= d) {
+            s0 += u0;
+            s1 += u1;
+            s2 += u2;
+        }
+    }
+    // point `col` owns queries [col N, col N + N) -> columns [lo, hi)
+    const int a = col * n_cache - 16 * T;
+    const int lo = max(a, 0), hi = min(a + n_cache, 16);
+    const int shi = min(max(hi - 1, 0), 15), slo = min(max(lo - 1, 0), 15);
+    const float h0 = __shfl(s0, shi, 16), l0 = __shfl(s0, slo, 16);
+    const float h1 = __shfl(s1, shi, 16), l1 = __shfl(s1, slo, 16);
+    const float h2 = __shfl(s2, shi, 16), l2 = __shfl(s2, slo, 16);
+    if (lo < hi) {
+        fc0 += lo > 0 ? h0 - l0 : h0;
+        fc1 += lo > 0 ? h1 - l1 : h1;
+        fc2 += lo > 0 ? h2 - l2 : h2;
+    }
+}
+
+__device__ __forceinline__ void store_estimate(int64_t p, float inv_n, float fc0, float fc1, float fc2, float fr0,
+                                               float fr1, float fr2, float *out_tl, float *out_c, float *out_r) {
+    const int64_t o = 3 * p;
+    const float c0 = fc0 * inv_n, c1 = fc1 * inv_n, c2 = fc2 * inv_n;
+    out_tl[o + 0] = c0 + fr0;
+    out_tl[o + 1] = c1 + fr1;
+    out_tl[o + 2] = c2 + fr2;
+    if (out_c) {
+        out_c[o + 0] = c0;
+        out_c[o + 1] = c1;
+        out_c[o + 2] = c2;
+    }
+    if (out_r) {
+        out_r[o + 0] = fr0;
+        out_r[o + 1] = fr1;
+        out_r[o + 2] = fr2;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Launchers (return the launch status).
 hipError_t launch_pack(float *packed, const float *master, int W, hipStream_t s);
+hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_encode(const Points &pts, const Queries &q, float *feat, hipStream_t s);
@@ -161,9 +256,15 @@ hipError_t launch_sample_dirs(const Points &pts, int n_cache, uint64_t seed, uin
 hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_t batch,
                               uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
                               float *wx, float *wy, float *wz, float *target, hipStream_t s);
-hipError_t launch_infer(int W, const Points &pts, const Queries &q, const float *packed, float *rgb,
+unsigned grid_for(int64_t units, int waves, int max_blocks);
+hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
+                            hipStream_t s);
+hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
+                           int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c, float *out_r,
+                           hipStream_t s);
+hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
                         hipStream_t s);
-hipError_t launch_tlmc(int W, const Points &pts, const nirc_lobes &lobes, const float *packed,
+hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
                        int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
                        float *out_r, hipStream_t s);
 

@@ -1,0 +1,114 @@
+"""BF16 / FP16 MFMA paths against the FP64 oracle (needs the GPU).
+
+Tolerances: cache outputs and estimator outputs rel-L2 <= 1e-2 (16-bit operands, FP32
+accumulation); estimator MRSE within 2 % of the FP32 path on identical weights, seeds and
+directions.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2412_04634_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+W = 64
+PRECS = {"bf16": 1, "fp16": 2}
+
+
+@pytest.fixture(scope="module")
+def nirc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_04634_amd import nirc as m
+    m.lib()
+    return m
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("Q", [1, 1000, 4099])
+def test_infer_16bit(nirc, prec, Q):
+    print(f"infer {prec} Q={Q}", flush=True)
+    P = 500
+    pts = wl.make_points(31, P)
+    w0 = wl.make_weights(31, W)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, cfg=nirc.make_config(precision=PRECS[prec]), max_batch=0)
+    g = torch.Generator().manual_seed(Q)
+    idx = torch.randint(0, P, (Q,), generator=g, dtype=torch.int32)
+    d = torch.randn(Q, 3, generator=g)
+    d = d / d.norm(dim=1, keepdim=True)
+    y = host(nirc.nirc_infer(model, dp, nirc.Queries.from_dirs(d.cuda(), idx.cuda())))
+    ref = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0, W)
+    assert rel_l2(y, ref) <= 1e-2
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("P,N", [(17, 3), (4096, 8), (1000, 16), (100, 64)])
+def test_estimate_16bit(nirc, prec, P, N):
+    print(f"estimate {prec} P={P} N={N}", flush=True)
+    pts = wl.make_points(32, P)
+    lob = wl.make_lobes(32).packed()
+    w0 = wl.make_weights(32, W)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, cfg=nirc.make_config(precision=PRECS[prec]), max_batch=0)
+    tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lob, N, 9, 1, parts=True))
+    dirs = host(nirc.tlmc_sample_dirs(dp, N, 9, 1))
+    o_tl, o_c, o_r = oracle.estimate(pts, lob, w0, W, N, 9, 1, dirs=dirs)
+    assert rel_l2(c, o_c) <= 1e-2
+    assert rel_l2(tl, o_tl) <= 1e-2
+    assert np.linalg.norm(r - o_r) <= 1e-2 * np.linalg.norm(o_c)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_mrse_within_two_percent_of_fp32(nirc, prec):
+    print(f"mrse {prec}", flush=True)
+    P, N = 65536, 16
+    pts = wl.make_points(33, P)
+    lob = wl.make_lobes(33).packed()
+    w0 = wl.make_weights(33, W)
+    dp = nirc.Points.from_workload(pts)
+    table = nirc.tlmc_reference_table(lob)
+    out = {}
+    for name, pr in (("fp32", 0), (prec, PRECS[prec])):
+        model = nirc.Model(w0, cfg=nirc.make_config(precision=pr), max_batch=65536)
+        # train a few frames so that the cache is not random, identically for both precisions
+        for f in range(3):
+            for s in range(4):
+                q, tgt = nirc.tlmc_train_batch(dp, lob, 65536, 5, f, s)
+                nirc.nirc_train_step(model, dp, q, tgt)
+        tl = nirc.tlmc_estimate(model, dp, lob, N, 5, 3)
+        out[name] = float(nirc.tlmc_frame_stats(dp, lob, table, tl)[4].item())
+    print(out, flush=True)
+    assert abs(out[prec] - out["fp32"]) <= 0.02 * out["fp32"]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_train_step_refreshes_16bit_copy(nirc, prec):
+    # training keeps FP32 master weights; after a step the 16-bit copy the kernels read must
+    # follow the new master weights
+    print(f"train refresh {prec}", flush=True)
+    P, B = 3000, 4096
+    pts = wl.make_points(34, P)
+    lob = wl.make_lobes(34).packed()
+    w0 = wl.make_weights(34, W)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, cfg=nirc.make_config(precision=PRECS[prec]), max_batch=B)
+    for s in range(3):
+        q, tgt = nirc.tlmc_train_batch(dp, lob, B, 7, 0, s)
+        nirc.nirc_train_step(model, dp, q, tgt)
+    w = host(model.get_weights())
+    assert np.abs(w - w0).max() > 1e-3
+    d = nirc.tlmc_sample_dirs(dp, 4, 1, 0)
+    idx = torch.arange(P, device="cuda", dtype=torch.int32).repeat_interleave(5)
+    y = host(nirc.nirc_infer(model, dp, nirc.Queries.from_dirs(d, idx)))
+    ref = oracle.infer(pts, idx.cpu().numpy(), host(d).reshape(-1, 3), w, W)
+    assert rel_l2(y, ref) <= 1e-2
