@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--workload", default="1080p_n16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="first run a plain device copy of this size (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the hot path has no "
@@ -132,6 +134,15 @@ def main():
     B, S = cfgw["train_batch"], cfgw["train_steps"]
     dev = "cuda"
     torch.cuda.set_device(0)
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.rand(n, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     scene = wl.make_scene(seed, P)
     w0 = wl.make_weights(seed, W)
