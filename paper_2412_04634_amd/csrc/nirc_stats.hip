@@ -79,57 +79,93 @@ __global__ __launch_bounds__(256) void k_reference_table(nirc_lobes lobes, doubl
         sJ[m] = 2.0 * acc;
     }
     __syncthreads();
+    __shared__ double sc[M];
     for (int k = threadIdx.x; k < M; k += blockDim.x) {
         double c = 0.0;
         for (int m = 0; m < M; ++m) c += sJ[m] * cos(M_PI * k * (m + 0.5) / M);
         c *= 2.0 / M;
         if (k == 0) c *= 0.5;
-        table[j * M + k] = c;
+        sc[k] = c;
     }
+    __syncthreads();
+    // coefficients below 1e-17 of the series' absolute sum do not change an FP64 result: store
+    // them as exact zeros so that evaluation can stop at the last nonzero one
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < M; ++k) tot += fabs(sc[k]);
+        int last = M - 1;
+        while (last > 0 && fabs(sc[last]) <= 1e-17 * tot) --last;
+        for (int k = last + 1; k < M; ++k) sc[k] = 0.0;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < M; k += blockDim.x) table[j * M + k] = sc[k];
 }
 
-__device__ inline double cheb_eval(const double *c, double t) {
-    // Clenshaw recurrence for sum_k c_k T_k(t)
-    double b1 = 0.0, b2 = 0.0;
-    for (int k = TLMC_CHEB_COEFFS - 1; k >= 1; --k) {
-        const double b0 = 2.0 * t * b1 - b2 + c[k];
-        b2 = b1;
-        b1 = b0;
-    }
-    return t * b1 - b2 + c[0];
+// Number of leading coefficients that can be nonzero (the maximum over the four lobes).
+__device__ inline int cheb_terms(const double *tab) {
+    int n = 1;
+    for (int j = 0; j < 4; ++j)
+        for (int k = TLMC_CHEB_COEFFS - 1; k >= n; --k)
+            if (tab[j * TLMC_CHEB_COEFFS + k] != 0.0) {
+                n = k + 1;
+                break;
+            }
+    return n;
 }
 
-__device__ inline void reference_at(const nirc_lobes &L, const double *tab, const Points &pts, int64_t p,
+// J_j(t_j) for the four lobes: Clenshaw recurrences for sum_k c_jk T_k(t_j), run side by side.
+__device__ inline void cheb_eval4(const double *tab, int nk, const double t[4], double J[4]) {
+    double b1[4] = {0.0, 0.0, 0.0, 0.0}, b2[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = nk - 1; k >= 1; --k) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double b0 = 2.0 * t[j] * b1[j] - b2[j] + tab[j * TLMC_CHEB_COEFFS + k];
+            b2[j] = b1[j];
+            b1[j] = b0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) J[j] = t[j] * b1[j] - b2[j] + tab[j * TLMC_CHEB_COEFFS];
+}
+
+__device__ inline void reference_at(const nirc_lobes &L, const double *tab, int nk, const Points &pts, int64_t p,
                                     double F[3]) {
     const double x0 = pts.px[p], x1 = pts.py[p], x2 = pts.pz[p];
     const double n0 = pts.nx[p], n1 = pts.ny[p], n2 = pts.nz[p];
-    F[0] = F[1] = F[2] = 0.0;
+    double t[4], J[4];
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-        double t = (double)L.axis[j][0] * n0 + (double)L.axis[j][1] * n1 + (double)L.axis[j][2] * n2;
-        t = fmin(1.0, fmax(-1.0, t));
-        const double J = cheb_eval(tab + j * TLMC_CHEB_COEFFS, t);
+        const double d = (double)L.axis[j][0] * n0 + (double)L.axis[j][1] * n1 + (double)L.axis[j][2] * n2;
+        t[j] = fmin(1.0, fmax(-1.0, d));
+    }
+    cheb_eval4(tab, nk, t, J);
+    F[0] = F[1] = F[2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double a = (double)L.alpha[j][c] + (double)L.beta[j][c][0] * x0 + (double)L.beta[j][c][1] * x1 +
                              (double)L.beta[j][c][2] * x2;
-            F[c] += a * J;
+            F[c] += a * J[j];
         }
-    }
 }
 
 __global__ void k_reference(Points pts, nirc_lobes lobes, const double *table, double *F) {
     __shared__ double tab[4 * TLMC_CHEB_COEFFS];
     for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x) tab[i] = table[i];
     __syncthreads();
+    const int nk = cheb_terms(tab);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= pts.count) return;
     double f[3];
-    reference_at(lobes, tab, pts, p, f);
+    reference_at(lobes, tab, nk, pts, p, f);
     F[3 * p + 0] = f[0];
     F[3 * p + 1] = f[1];
     F[3 * p + 2] = f[2];
 }
 
-constexpr int kStatBlocks = 256;
+constexpr int kStatBlocks = 2048;   // multiple of 64
+static_assert(kStatBlocks % 64 == 0, "final reduction splits the blocks into 64 chunks");
 constexpr int kStatThreads = 256;
 
 // Per-block FP64 partial sums over points and channels:
@@ -142,11 +178,12 @@ __global__ __launch_bounds__(kStatThreads) void k_frame_stats(Points pts, nirc_l
     __shared__ double red[kStatThreads / 64][4];
     for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x) tab[i] = table[i];
     __syncthreads();
+    const int nk = cheb_terms(tab);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pts.count;
          p += (int64_t)gridDim.x * blockDim.x) {
         double F[3];
-        reference_at(lobes, tab, pts, p, F);
+        reference_at(lobes, tab, nk, pts, p, F);
         for (int c = 0; c < 3; ++c) {
             const double den = F[c] * F[c] + eps;
             const double e = (double)tl[3 * p + c] - F[c];
@@ -179,19 +216,30 @@ __global__ __launch_bounds__(kStatThreads) void k_frame_stats(Points pts, nirc_l
     }
 }
 
-// stats[k] = sum over blocks (fixed order); stats[4] = MRSE, stats[5] = cache-level MRSE,
-// stats[6] = relative residual second moment.
-__global__ void k_stats_final(const double *partials, double *stats) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = 0; b < kStatBlocks; ++b)
-        for (int k = 0; k < 4; ++k) s[k] += partials[b * 4 + k];
-    for (int k = 0; k < 4; ++k) stats[k] = s[k];
-    const double n = s[3] > 0.0 ? s[3] : 1.0;
-    stats[4] = s[0] / n;
-    stats[5] = s[1] / n;
-    stats[6] = s[2] / n;
-    stats[7] = 0.0;
+// stats[k] = sum over blocks (fixed order: 64 contiguous chunks, then the chunk sums in order);
+// stats[4] = MRSE, stats[5] = cache-level MRSE, stats[6] = relative residual second moment.
+__global__ __launch_bounds__(256) void k_stats_final(const double *partials, double *stats) {
+    constexpr int kChunks = 64, kPer = kStatBlocks / kChunks;
+    __shared__ double part[4][kChunks];
+    const int k = threadIdx.x / kChunks, c = threadIdx.x % kChunks;
+    double v = 0.0;
+    for (int b = c * kPer; b < (c + 1) * kPer; ++b) v += partials[b * 4 + k];
+    part[k][c] = v;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int i = 0; i < kChunks; ++i) t += part[threadIdx.x][i];
+        part[threadIdx.x][0] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double n = part[3][0] > 0.0 ? part[3][0] : 1.0;
+        for (int i = 0; i < 4; ++i) stats[i] = part[i][0];
+        stats[4] = part[0][0] / n;
+        stats[5] = part[1][0] / n;
+        stats[6] = part[2][0] / n;
+        stats[7] = 0.0;
+    }
 }
 
 __global__ void k_accumulate(const float *v, int64_t n, double *sum, double *sumsq) {
@@ -223,7 +271,7 @@ hipError_t launch_frame_stats(const Points &pts, const nirc_lobes &lobes, const 
                        eps, scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, s, scratch, stats);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, s, scratch, stats);
     return hipGetLastError();
 }
 

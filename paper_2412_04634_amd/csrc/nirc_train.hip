@@ -288,20 +288,31 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
     }
 }
 
-// grad[i] = inv_scale * sum_blk partials[blk][i] (fixed order); raises `bad` on a non-finite
-// entry.  Thread 0 also reduces the loss partials.
-__global__ void k_reduce_grad(const float *__restrict__ partials, const float *__restrict__ loss_partials,
-                              int nblocks, int64_t np, float inv_scale, float loss_norm,
-                              float *__restrict__ grad, float *__restrict__ loss, uint32_t *bad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < np) {
-        float s = 0.0f;
-        for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * np + i];
-        s *= inv_scale;
-        grad[i] = s;
-        if (bad && !isfinite(s)) atomicOr(bad, 1u);
+// grad[i] = inv_scale * sum_blk partials[blk][i] in a fixed order: a block handles 64 parameters
+// (one per lane); wave w sums the w-th quarter of the partials in order, then the four quarter
+// sums are added in order.  Raises `bad` on a non-finite entry.  Block 0 also reduces the loss.
+__global__ __launch_bounds__(256) void k_reduce_grad(const float *__restrict__ partials,
+                                                     const float *__restrict__ loss_partials, int nblocks,
+                                                     int64_t np, float inv_scale, float loss_norm,
+                                                     float *__restrict__ grad, float *__restrict__ loss,
+                                                     uint32_t *bad) {
+    __shared__ float q[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int per = (nblocks + 3) / 4;
+    const int b0 = wave * per, b1 = min(nblocks, b0 + per);
+    float s = 0.0f;
+    if (i < np)
+        for (int b = b0; b < b1; ++b) s += partials[(int64_t)b * np + i];
+    q[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && i < np) {
+        const float t = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
+        const float gi = t * inv_scale;
+        grad[i] = gi;
+        if (bad && !isfinite(gi)) atomicOr(bad, 1u);
     }
-    if (i == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         float t = 0.0f;
         for (int b = 0; b < nblocks; ++b) t += loss_partials[b];
         t *= loss_norm;
@@ -367,7 +378,7 @@ hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_pa
                               float inv_scale, float loss_norm, float *grad, float *loss,
                               uint32_t *bad, hipStream_t s) {
     const int64_t np = n_params(W);
-    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, partials,
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 63) / 64)), dim3(256), 0, s, partials,
                        loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad);
     return hipGetLastError();
 }
