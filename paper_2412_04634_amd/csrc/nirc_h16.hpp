@@ -155,7 +155,7 @@ __device__ __forceinline__ void direction_operands(float dx, float dy, float dz,
 // the hidden activations of layer 4 as chained B operands hb[tt][kb].
 template <int W, int PREC, int T>
 __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
-                                      const uint16_t *sD, const uint16_t *sH, int lane, int nt) {
+                                      const uint16_t *sD, const uint16_t *sH, int lane) {
     constexpr int MT = W / 16, KB = W / 32;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb)
@@ -163,8 +163,7 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
         for (int mt = 0; mt < MT; ++mt) {
             const u32x4 a = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
 #pragma unroll
-            for (int tt = 0; tt < T; ++tt)
-                if (tt < nt) h[tt][mt] = mfma16<PREC>(a, bd[tt][kb], h[tt][mt]);
+            for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a, bd[tt][kb], h[tt][mt]);
         }
 #pragma unroll
     for (int tt = 0; tt < T; ++tt)
@@ -172,6 +171,8 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
         for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
+        // keep each layer's fragment loads inside the layer (hoisting them all costs registers)
+        __builtin_amdgcn_sched_barrier(0);
         const uint16_t *sec = sH + l * (MT * KB * 512);
 #pragma unroll
         for (int tt = 0; tt < T; ++tt)
@@ -183,8 +184,7 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
             for (int mt = 0; mt < MT; ++mt) {
                 const u32x4 a = *(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8);
 #pragma unroll
-                for (int tt = 0; tt < T; ++tt)
-                    if (tt < nt) h[tt][mt] = mfma16<PREC>(a, hb[tt][kb], h[tt][mt]);
+                for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a, hb[tt][kb], h[tt][mt]);
             }
 #pragma unroll
         for (int tt = 0; tt < T; ++tt)
@@ -195,17 +195,16 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
 
 // Output layer: lanes 0..15 receive z = W5 h4 of their column.
 template <int W, int PREC, int T>
-__device__ __forceinline__ void output16(f32x4 (&y)[T], const u32x4 (&hb)[T][W / 32], const uint16_t *sO, int lane,
-                                         int nt) {
+__device__ __forceinline__ void output16(f32x4 (&y)[T], const u32x4 (&hb)[T][W / 32], const uint16_t *sO, int lane) {
     constexpr int KB = W / 32;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) y[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         const u32x4 a = *(const u32x4 *)(sO + (kb * 64 + lane) * 8);
 #pragma unroll
-        for (int tt = 0; tt < T; ++tt)
-            if (tt < nt) y[tt] = mfma16<PREC>(a, hb[tt][kb], y[tt]);
+        for (int tt = 0; tt < T; ++tt) y[tt] = mfma16<PREC>(a, hb[tt][kb], y[tt]);
     }
 }
 

@@ -125,16 +125,59 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
         for (int mt = 0; mt < MT; ++mt) h[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
         layer1_surface<W>(h[0], opaque(gS), xs, lane, g);
         float dx[1] = {ws[0]}, dy[1] = {ws[1]}, dz[1] = {ws[2]};
-        layer1_direction<W, 1>(h, sD, dx, dy, dz, lane, g, 1);
-        relu_all<W, 1>(h, 1);
-        hidden_layers<W, 1>(h, sH, lane, 1);
+        layer1_direction<W, 1>(h, sD, dx, dy, dz, lane, g);
+        relu_all<W, 1>(h);
+        hidden_layers<W, 1>(h, sH, lane);
         f32x4 y[1];
-        output_layer<W, 1>(y, h, sO, lane, 1);
+        output_layer<W, 1>(y, h, sO, lane);
         if (g == 0 && (tile << 4) + col < Q) {
             float *o = rgb + 3 * ((tile << 4) + col);
             o[0] = expf(y[0][0]);
             o[1] = expf(y[0][1]);
             o[2] = expf(y[0][2]);
+        }
+    }
+}
+
+// T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
+// current point group through the FP32 chain, then per-point accumulation.
+template <int W, int T>
+__device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, const float *db, const float *hs,
+                                               const float *sD, const float *sH, const float *sO,
+                                               const nirc_lobes &lobes, const float *xs, int lane, int g, int col,
+                                               float &fc0, float &fc1, float &fc2, float &fr0, float &fr1,
+                                               float &fr2) {
+    constexpr int MT = W / 16;
+    f32x4 h[T][MT];
+    float dx[T], dy[T], dz[T];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int Tt = T0 + tt;
+        const int qi = 16 * (s0 + tt) + col;
+        dx[tt] = db[qi];
+        dy[tt] = db[128 + qi];
+        dz[tt] = db[256 + qi];
+        const int j = (Tt < n_cache) ? (16 * Tt + col) / n_cache : col;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g);
+    }
+    layer1_direction<W, T>(h, sD, dx, dy, dz, lane, g);
+    relu_all<W, T>(h);
+    hidden_layers<W, T>(h, sH, lane);
+    f32x4 y[T];
+    output_layer<W, T>(y, h, sO, lane);
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int Tt = T0 + tt;
+        const float y0 = expf(y[tt][0]), y1 = expf(y[tt][1]), y2 = expf(y[tt][2]);
+        if (Tt < n_cache) {
+            reduce_cache_tile(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
+        } else {
+            float Lr[3];
+            field_eval(lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
+            fr0 = Lr[0] - y0;
+            fr1 = Lr[1] - y1;
+            fr2 = Lr[2] - y2;
         }
     }
 }
@@ -204,48 +247,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
         float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
         for (int tb = 0; tb < n_tiles; tb += 8) {
             gen_dirs_batch(pts, p0, tb, n_cache, key0, key1, frame, lane, db);
-            // --- MLP over the staged tiles, 4 at a time
+            const int tend = min(tb + 8, n_tiles);
+            int t = tb;
 #pragma unroll 1
-            for (int sb = 0; sb < 8; sb += 4) {
-                const int t0 = tb + sb;
-                if (t0 >= n_tiles) break;
-                const int nt = min(4, n_tiles - t0);
-                f32x4 h[4][MT];
-                float dx[4], dy[4], dz[4];
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                    const int T = t0 + tt;
-                    const int qi = 16 * (sb + tt) + col;
-                    dx[tt] = db[qi];
-                    dy[tt] = db[128 + qi];
-                    dz[tt] = db[256 + qi];
-                    const int j = (T < n_cache) ? (16 * T + col) / n_cache : col;
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        h[tt][mt] = (tt < nt) ? *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g)
-                                              : f32x4{0.f, 0.f, 0.f, 0.f};
-                }
-                layer1_direction<W, 4>(h, sD, dx, dy, dz, lane, g, nt);
-                relu_all<W, 4>(h, nt);
-                hidden_layers<W, 4>(h, sH, lane, nt);
-                f32x4 y[4];
-                output_layer<W, 4>(y, h, sO, lane, nt);
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                    if (tt >= nt) break;
-                    const int T = t0 + tt;
-                    const float y0 = expf(y[tt][0]), y1 = expf(y[tt][1]), y2 = expf(y[tt][2]);
-                    if (T < n_cache) {
-                        reduce_cache_tile(T, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
-                    } else {
-                        float Lr[3];
-                        field_eval(s_lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
-                        fr0 = Lr[0] - y0;
-                        fr1 = Lr[1] - y1;
-                        fr2 = Lr[2] - y2;
-                    }
-                }
-            }
+            for (; t + 4 <= tend; t += 4)
+                tlmc_tiles_f32<W, 4>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
+                                     fc2, fr0, fr1, fr2);
+#pragma unroll 1
+            for (; t < tend; ++t)
+                tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
+                                     fc2, fr0, fr1, fr2);
         }
         if (g == 0 && p0 + col < P) store_estimate(p0 + col, inv_n, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
     }
@@ -325,7 +336,7 @@ hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lob
     if (pts.count == 0) return hipSuccess;
     if (prec != NIRC_FP32)
         return launch_tlmc_h16(W, prec, pts, lobes, packed, n_cache, seed, frame, out_tl, out_c, out_r, s);
-    constexpr int WAVES = 4;
+    constexpr int WAVES = 8;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, kMaxResidentBlocks);
     if (W == 64)
         hipLaunchKernelGGL((k_tlmc_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes,

@@ -52,14 +52,58 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
         u32x4 bd[1][2];
         direction_operands<PREC>(q.wx[qi], q.wy[qi], q.wz[qi], g, bd[0][0], bd[0][1]);
         u32x4 hb[1][KB];
-        mlp16<W, PREC, 1>(h, hb, bd, sD, sH, lane, 1);
+        mlp16<W, PREC, 1>(h, hb, bd, sD, sH, lane);
         f32x4 y[1];
-        output16<W, PREC, 1>(y, hb, sO, lane, 1);
+        output16<W, PREC, 1>(y, hb, sO, lane);
         if (g == 0 && (tile << 4) + col < Q) {
             float *o = rgb + 3 * ((tile << 4) + col);
             o[0] = __expf(y[0][0]);
             o[1] = __expf(y[0][1]);
             o[2] = __expf(y[0][2]);
+        }
+    }
+}
+
+// T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
+// current point group through the 16-bit chain, then per-point accumulation.
+template <int W, int PREC, int T>
+__device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, const float *db, const float *hs,
+                                               const uint16_t *sD, const uint16_t *sH, const uint16_t *sO,
+                                               const nirc_lobes &lobes, const float *xs, int lane, int g, int col,
+                                               float &fc0, float &fc1, float &fc2, float &fr0, float &fr1,
+                                               float &fr2) {
+    constexpr int MT = W / 16, KB = W / 32;
+    f32x4 h[T][MT];
+    u32x4 bd[T][2];
+    float dx[T], dy[T], dz[T];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int Tt = T0 + tt;
+        const int qi = 16 * (s0 + tt) + col;
+        dx[tt] = db[qi];
+        dy[tt] = db[128 + qi];
+        dz[tt] = db[256 + qi];
+        const int j = (Tt < n_cache) ? (16 * Tt + col) / n_cache : col;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g);
+        direction_operands<PREC>(dx[tt], dy[tt], dz[tt], g, bd[tt][0], bd[tt][1]);
+    }
+    u32x4 hb[T][KB];
+    mlp16<W, PREC, T>(h, hb, bd, sD, sH, lane);
+    f32x4 y[T];
+    output16<W, PREC, T>(y, hb, sO, lane);
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) {
+        const int Tt = T0 + tt;
+        const float y0 = __expf(y[tt][0]), y1 = __expf(y[tt][1]), y2 = __expf(y[tt][2]);
+        if (Tt < n_cache) {
+            reduce_cache_tile(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
+        } else {
+            float Lr[3];
+            field_eval(lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
+            fr0 = Lr[0] - y0;
+            fr1 = Lr[1] - y1;
+            fr2 = Lr[2] - y2;
         }
     }
 }
@@ -113,47 +157,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
         float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
         for (int tb = 0; tb < n_tiles; tb += 8) {
             gen_dirs_batch(pts, p0, tb, n_cache, key0, key1, frame, lane, db);
+            const int tend = min(tb + 8, n_tiles);
+            int t = tb;
 #pragma unroll 1
-            for (int sb = 0; sb < 8; sb += 4) {
-                const int t0 = tb + sb;
-                if (t0 >= n_tiles) break;
-                const int nt = min(4, n_tiles - t0);
-                f32x4 h[4][MT];
-                u32x4 bd[4][2];
-                float dx[4], dy[4], dz[4];
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                    const int T = t0 + tt;
-                    const int qi = 16 * (sb + tt) + col;
-                    dx[tt] = db[qi];
-                    dy[tt] = db[128 + qi];
-                    dz[tt] = db[256 + qi];
-                    const int j = (T < n_cache) ? (16 * T + col) / n_cache : col;
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        h[tt][mt] = (tt < nt) ? *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g) : f32x4{0.f, 0.f, 0.f, 0.f};
-                    direction_operands<PREC>(dx[tt], dy[tt], dz[tt], g, bd[tt][0], bd[tt][1]);
-                }
-                u32x4 hb[4][KB];
-                mlp16<W, PREC, 4>(h, hb, bd, sD, sH, lane, nt);
-                f32x4 y[4];
-                output16<W, PREC, 4>(y, hb, sO, lane, nt);
-#pragma unroll
-                for (int tt = 0; tt < 4; ++tt) {
-                    if (tt >= nt) break;
-                    const int T = t0 + tt;
-                    const float y0 = __expf(y[tt][0]), y1 = __expf(y[tt][1]), y2 = __expf(y[tt][2]);
-                    if (T < n_cache) {
-                        reduce_cache_tile(T, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
-                    } else {
-                        float Lr[3];
-                        field_eval(s_lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
-                        fr0 = Lr[0] - y0;
-                        fr1 = Lr[1] - y1;
-                        fr2 = Lr[2] - y2;
-                    }
-                }
-            }
+            for (; t + 4 <= tend; t += 4)
+                tlmc_tiles_h16<W, PREC, 4>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0,
+                                           fc1, fc2, fr0, fr1, fr2);
+#pragma unroll 1
+            for (; t < tend; ++t)
+                tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0,
+                                           fc1, fc2, fr0, fr1, fr2);
         }
         if (g == 0 && p0 + col < P) store_estimate(p0 + col, inv_n, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
     }

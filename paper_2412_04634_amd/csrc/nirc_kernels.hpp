@@ -61,8 +61,7 @@ __device__ __forceinline__ void layer1_surface(f32x4 (&h)[W / 16], const float *
 // h[tt] += W1_w e_w(direction of tile tt) for up to T tiles (nt valid).
 template <int W, int T>
 __device__ __forceinline__ void layer1_direction(f32x4 (&h)[T][W / 16], const float *sD, const float *dx,
-                                                 const float *dy, const float *dz, int lane, int g,
-                                                 int nt) {
+                                                 const float *dy, const float *dz, int lane, int g) {
     constexpr int MT = W / 16;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -81,13 +80,12 @@ __device__ __forceinline__ void layer1_direction(f32x4 (&h)[T][W / 16], const fl
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int tt = 0; tt < T; ++tt)
-                    if (tt < nt) h[tt][mt] = mfma4(a[mt][kk], b[tt][kk], h[tt][mt]);
+                for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma4(a[mt][kk], b[tt][kk], h[tt][mt]);
     }
 }
 
 template <int W, int T>
-__device__ __forceinline__ void relu_all(f32x4 (&h)[T][W / 16], int nt) {
+__device__ __forceinline__ void relu_all(f32x4 (&h)[T][W / 16]) {
 #pragma unroll
     for (int tt = 0; tt < T; ++tt)
 #pragma unroll
@@ -99,11 +97,13 @@ __device__ __forceinline__ void relu_all(f32x4 (&h)[T][W / 16], int nt) {
 // Hidden layers 2..4: K-quad kq of the packed fragments is exactly row tile kq of the previous
 // layer's result, so register (tt, kq, kk) feeds K-block 4 kq + kk.
 template <int W, int T>
-__device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float *sH, int lane, int nt) {
+__device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float *sH, int lane) {
     constexpr int MT = W / 16, KQ = W / 16;
     constexpr int SEC = MT * (W / 4) * 64;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
+        // keep each layer's fragment loads inside the layer (hoisting them all costs registers)
+        __builtin_amdgcn_sched_barrier(0);
         const float *sec = sH + l * SEC;
         f32x4 o[T][MT];
 #pragma unroll
@@ -120,8 +120,7 @@ __device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int tt = 0; tt < T; ++tt)
-                        if (tt < nt) o[tt][mt] = mfma4(a[mt][kk], h[tt][kq][kk], o[tt][mt]);
+                    for (int tt = 0; tt < T; ++tt) o[tt][mt] = mfma4(a[mt][kk], h[tt][kq][kk], o[tt][mt]);
         }
 #pragma unroll
         for (int tt = 0; tt < T; ++tt)
@@ -135,8 +134,9 @@ __device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float
 // Output layer (rows 0..2 of a 16-row tile): lanes 0..15 receive z = W5 h4 of their column.
 template <int W, int T>
 __device__ __forceinline__ void output_layer(f32x4 (&y)[T], const f32x4 (&h)[T][W / 16], const float *sO,
-                                             int lane, int nt) {
+                                             int lane) {
     constexpr int KQ = W / 16;
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) y[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -145,8 +145,7 @@ __device__ __forceinline__ void output_layer(f32x4 (&y)[T], const f32x4 (&h)[T][
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-            for (int tt = 0; tt < T; ++tt)
-                if (tt < nt) y[tt] = mfma4(a[kk], h[tt][kq][kk], y[tt]);
+            for (int tt = 0; tt < T; ++tt) y[tt] = mfma4(a[kk], h[tt][kq][kk], y[tt]);
     }
 }
 
@@ -195,10 +194,58 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
     wave_sync();
 }
 
+// Sums over aligned groups of 2, 4, 8 or 16 lanes of a 16-lane row with DPP (result in every
+// lane of the group): quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
+__device__ __forceinline__ float dpp_add(float x, int ctrl_step) {
+    int v = __builtin_bit_cast(int, x), r;
+    switch (ctrl_step) {
+    case 0: r = __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); break;
+    case 1: r = __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); break;
+    case 2: r = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false); break;
+    default: r = __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false); break;
+    }
+    return x + __builtin_bit_cast(float, r);
+}
+
 // Cache tile T: lanes 0..15 hold y of queries 16 T + column; point `col` (lanes 0..15) adds the
-// sum of its queries in this tile, found from 16-lane inclusive prefix sums.
+// sum of its queries in this tile.  N a multiple of 16: the tile belongs to one point and a DPP
+// row sum suffices; N dividing 16: DPP segment sums and one cross-lane read; any other N:
+// 16-lane inclusive prefix sums.
 __device__ __forceinline__ void reduce_cache_tile(int T, int n_cache, int col, float y0, float y1, float y2,
                                                   float &fc0, float &fc1, float &fc2) {
+    if ((n_cache & 15) == 0) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            y0 = dpp_add(y0, st);
+            y1 = dpp_add(y1, st);
+            y2 = dpp_add(y2, st);
+        }
+        if (col == (16 * T) / n_cache) {
+            fc0 += y0;
+            fc1 += y1;
+            fc2 += y2;
+        }
+        return;
+    }
+    if (n_cache < 16 && (16 % n_cache) == 0) {
+        const int steps = n_cache == 8 ? 3 : n_cache == 4 ? 2 : n_cache == 2 ? 1 : 0;
+        for (int st = 0; st < steps; ++st) {
+            y0 = dpp_add(y0, st);
+            y1 = dpp_add(y1, st);
+            y2 = dpp_add(y2, st);
+        }
+        // point `col` is segment (col - 16T/N) of this tile if that lies in [0, 16/N)
+        const int seg = col - (16 * T) / n_cache;
+        const bool mine = seg >= 0 && seg < 16 / n_cache;
+        const int src = mine ? seg * n_cache : 0;
+        const float s0 = __shfl(y0, src, 16), s1 = __shfl(y1, src, 16), s2 = __shfl(y2, src, 16);
+        if (mine) {
+            fc0 += s0;
+            fc1 += s1;
+            fc2 += s2;
+        }
+        return;
+    }
     float s0 = y0, s1 = y1, s2 = y2;
 #pragma unroll
     for (int d = 1; d < 16; d <<= 1) {

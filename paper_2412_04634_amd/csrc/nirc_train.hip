@@ -102,8 +102,8 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
                 for (int mt = 0; mt < MT; ++mt) a1[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
                 layer1_surface<W>(a1[0], pk + L.offset(SEC_S), xs, lane, g);
                 float dx[1] = {ws[0]}, dy[1] = {ws[1]}, dz[1] = {ws[2]};
-                layer1_direction<W, 1>(a1, pk + L.offset(SEC_D), dx, dy, dz, lane, g, 1);
-                relu_all<W, 1>(a1, 1);
+                layer1_direction<W, 1>(a1, pk + L.offset(SEC_D), dx, dy, dz, lane, g);
+                relu_all<W, 1>(a1);
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) h[0][mt] = a1[0][mt];
             }
