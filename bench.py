@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--workload", default="1080p_n16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true")
+    ap.add_argument("--estimate-only", choices=["fp32", "bf16", "fp16"], default=None,
+                    help="time only tlmc_estimate at this precision (for profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="first run a plain device copy of this size (reference for HBM counters)")
     args = ap.parse_args()
@@ -155,6 +157,25 @@ def main():
         if f not in lobes_frames:
             lobes_frames[f] = base_lobes.rotated(f).packed()
         return lobes_frames[f]
+
+    if args.estimate_only:
+        prec = {"fp32": 0, "bf16": 1, "fp16": 2}[args.estimate_only]
+        m = nirc.Model(w0, cfg=nirc.make_config(precision=prec), max_batch=0)
+        lob = nirc.lobes_struct(lobes_for(0))
+        out = torch.empty((P, 3), dtype=torch.float32, device=dev)
+        for _ in range(args.warmup):
+            nirc.tlmc_estimate(m, dp, lob, N, seed, 0, out=out)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(torch.cuda.current_stream())
+        for _ in range(args.steps):
+            nirc.tlmc_estimate(m, dp, lob, N, seed, 0, out=out)
+        ev[1].record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) * 1e-3 / args.steps
+        print(json.dumps({"estimate_only": args.estimate_only, "ms_estimate": t * 1e3,
+                          "tflops": algorithmic_flops_estimate(P, N, W) / t / 1e12}), flush=True)
+        return
 
     table = nirc.tlmc_reference_table(lobes_for(0))
     fs = nirc.FrameStats()

@@ -41,6 +41,22 @@ __device__ inline int64_t query_point(const Queries &q, const Points &p, int64_t
     return j < 0 ? 0 : (j >= p.count ? p.count - 1 : j);
 }
 
+// Division of a query index q by the cache sample count N without a hardware divide:
+// q / N = umulhi(q, ceil(2^32 / N)) exactly for q < 2^17 and 2 <= N <= 4096 (the rounding error
+// q (M - 2^32/N) / 2^32 < 2^-15 stays below 1/N); N = 1 is the identity.
+struct DivN {
+    uint32_t n, magic;
+};
+
+__host__ inline DivN make_divn(int n) {
+    DivN d;
+    d.n = (uint32_t)n;
+    d.magic = n <= 1 ? 0u : (uint32_t)((0x100000000ull + (uint64_t)n - 1) / (uint64_t)n);
+    return d;
+}
+
+__device__ __forceinline__ uint32_t div_n(uint32_t q, DivN d) { return d.n == 1 ? q : __umulhi(q, d.magic); }
+
 // ------------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): multiply-xor rounds on a 4x32 counter, key bumped by
 // the Weyl constants between rounds.
@@ -167,12 +183,12 @@ __device__ inline void enc_pair(float v, int k, float &s, float &c) {
 //   O   W5 (3 rows padded)    MT = 1,    KB = W/4
 //   T0..T2  W2^T, W3^T, W4^T  MT = W/16, KB = W/4  (backward: delta_{l-1} = W_l^T delta_l)
 //   OT  W5^T                  MT = W/16, KB = 4    (K = output rows padded to 16)
-enum Section { SEC_S = 0, SEC_D, SEC_H0, SEC_H1, SEC_H2, SEC_O, SEC_T0, SEC_T1, SEC_T2, SEC_OT, SEC_N };
+enum Section { SEC_S = 0, SEC_D, SEC_H0, SEC_H1, SEC_H2, SEC_O, SEC_OS, SEC_T0, SEC_T1, SEC_T2, SEC_OT, SEC_N };
 
 struct F32Layout {
     int W;
     __host__ __device__ constexpr int mt(int s) const {
-        return (s == SEC_O) ? 1 : W / 16;
+        return s == SEC_OS ? 0 : (s == SEC_O) ? 1 : W / 16;   // OS: 16-bit layout only
     }
     __host__ __device__ constexpr int kb(int s) const {
         return s == SEC_S ? 28 : s == SEC_D ? 12 : s == SEC_OT ? 4 : W / 4;

@@ -25,10 +25,12 @@ typedef short i16x2 __attribute__((ext_vector_type(2)));
 // Sections (MT row tiles x KB K-blocks x 64 lanes x 8 values, stored [mt][kb][lane][8]):
 //   S  W1 surface    MT = W/16, KB = 4     D  W1 direction  MT = W/16, KB = 2
 //   H0..H2 W2..W4    MT = W/16, KB = W/32  O  W5           MT = 1,    KB = W/32
+//   OS W5^T as a B operand, 4 column-shifted copies (MT = 4 copies, KB = W/32): copy t holds
+//      W5 row c in column 3t + c, so that Y = H W5^T of 4 tiles accumulates into one result
 //   T0..T2 W2^T..W4^T MT = W/16, KB = W/32 OT W5^T          MT = W/16, KB = 1
 struct H16Layout {
     int W;
-    __host__ __device__ constexpr int mt(int s) const { return s == SEC_O ? 1 : W / 16; }
+    __host__ __device__ constexpr int mt(int s) const { return s == SEC_O ? 1 : s == SEC_OS ? 4 : W / 16; }
     __host__ __device__ constexpr int kb(int s) const {
         return s == SEC_S ? 4 : s == SEC_D ? 2 : s == SEC_OT ? 1 : W / 32;
     }
@@ -63,6 +65,11 @@ __host__ __device__ inline int64_t h16_packed_source(int W, int e) {
         return w_offset(W, 1 + (s - SEC_H0)) + (int64_t)row * W + chained_neuron16(kb, g, j);
     case SEC_O:
         return row < 3 ? w_offset(W, 4) + (int64_t)row * W + chained_neuron16(kb, g, j) : -1;
+    case SEC_OS: {
+        // B operand: lane l holds B[k = 8g + j][column l%16]; copy m puts W5 row c at column 3m + c
+        const int c = (lane & 15) - 3 * m;
+        return (c >= 0 && c < 3) ? w_offset(W, 4) + (int64_t)c * W + chained_neuron16(kb, g, j) : -1;
+    }
     case SEC_T0: case SEC_T1: case SEC_T2:
         return w_offset(W, 1 + (s - SEC_T0)) + (int64_t)chained_neuron16(kb, g, j) * W + row;
     case SEC_OT: {
@@ -191,6 +198,26 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
     }
+}
+
+// Output layer for T <= 4 tiles into ONE accumulator: the chained activations hb[tt] (B layout:
+// lane l holds neuron positions 8g + j of query l%16) are exactly an A operand of the transposed
+// product Y = H W5^T (A[query l%16][k 8g + j]), and shifted copy tt of W5^T sends tile tt to
+// columns 3tt..3tt+2.  Lane (g, col) ends with z of queries 4g + i (i = 0..3) of tile col / 3,
+// channel col % 3 (columns >= 3T are zero).
+template <int W, int PREC, int T>
+__device__ __forceinline__ f32x4 output16_packed(const u32x4 (&hb)[T][W / 32], const uint16_t *sOS, int lane) {
+    constexpr int KB = W / 32;
+    __builtin_amdgcn_sched_barrier(0);
+    f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt) {
+            const u32x4 b = *(const u32x4 *)(sOS + ((tt * KB + kb) * 64 + lane) * 8);
+            y = mfma16<PREC>(hb[tt][kb], b, y);
+        }
+    return y;
 }
 
 // Output layer: lanes 0..15 receive z = W5 h4 of their column.

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
 // T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
 // current point group through the FP32 chain, then per-point accumulation.
 template <int W, int T>
-__device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, const float *db, const float *hs,
+__device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN dn, const float *db, const float *hs,
                                                const float *sD, const float *sH, const float *sO,
                                                const nirc_lobes &lobes, const float *xs, int lane, int g, int col,
                                                float &fc0, float &fc1, float &fc2, float &fr0, float &fr1,
@@ -157,7 +157,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, cons
         dx[tt] = db[qi];
         dy[tt] = db[128 + qi];
         dz[tt] = db[256 + qi];
-        const int j = (Tt < n_cache) ? (16 * Tt + col) / n_cache : col;
+        const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g);
     }
@@ -198,7 +198,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, cons
 template <int W, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes lobes,
                                                          const float *__restrict__ packed,
-                                                         int n_cache, uint32_t key0, uint32_t key1,
+                                                         int n_cache, DivN dn, uint32_t key0, uint32_t key1,
                                                          uint32_t frame, float *__restrict__ out_tl,
                                                          float *__restrict__ out_c,
                                                          float *__restrict__ out_r) {
@@ -246,16 +246,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
 
         float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
         for (int tb = 0; tb < n_tiles; tb += 8) {
-            gen_dirs_batch(pts, p0, tb, n_cache, key0, key1, frame, lane, db);
+            gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, db);
             const int tend = min(tb + 8, n_tiles);
             int t = tb;
 #pragma unroll 1
             for (; t + 4 <= tend; t += 4)
-                tlmc_tiles_f32<W, 4>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
+                tlmc_tiles_f32<W, 4>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
                                      fc2, fr0, fr1, fr2);
 #pragma unroll 1
             for (; t < tend; ++t)
-                tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
+                tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
                                      fc2, fr0, fr1, fr2);
         }
         if (g == 0 && p0 + col < P) store_estimate(p0 + col, inv_n, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
@@ -340,7 +340,8 @@ hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lob
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, kMaxResidentBlocks);
     if (W == 64)
         hipLaunchKernelGGL((k_tlmc_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes,
-                           (const float *)packed, n_cache, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame,
+                           (const float *)packed, n_cache, make_divn(n_cache), (uint32_t)seed, (uint32_t)(seed >> 32),
+                           (uint32_t)frame,
                            out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;

@@ -64,47 +64,108 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
     }
 }
 
+// Per-wave scratch of the estimator's point group (LDS, floats).
+struct GroupSlab {
+    float *hs;     // [16 points][W] surface projection
+    float *db;     // [3][128] staged directions
+    float *psum;   // [16 points][4] cache-level sums
+    float *yres;   // [16 points][4] residual-direction predictions
+    float *qbuf;   // [16 queries][4] one tile's predictions (general N only)
+};
+
 // T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
-// current point group through the 16-bit chain, then per-point accumulation.
+// current point group through the 16-bit chain.  The output layer of all T tiles lands in one
+// accumulator (tile tt in columns 3tt..3tt+2), so the exponential and the per-point sums are
+// done once per pass: a lane holds 4 consecutive queries of one tile and channel.
 template <int W, int PREC, int T>
-__device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, const float *db, const float *hs,
-                                               const uint16_t *sD, const uint16_t *sH, const uint16_t *sO,
-                                               const nirc_lobes &lobes, const float *xs, int lane, int g, int col,
-                                               float &fc0, float &fc1, float &fc2, float &fr0, float &fr1,
-                                               float &fr2) {
+__device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN dn, const GroupSlab &gs,
+                                               const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
+                                               int lane, int g, int col, float &rdx, float &rdy, float &rdz) {
     constexpr int MT = W / 16, KB = W / 32;
     f32x4 h[T][MT];
     u32x4 bd[T][2];
-    float dx[T], dy[T], dz[T];
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int Tt = T0 + tt;
         const int qi = 16 * (s0 + tt) + col;
-        dx[tt] = db[qi];
-        dy[tt] = db[128 + qi];
-        dz[tt] = db[256 + qi];
-        const int j = (Tt < n_cache) ? (16 * Tt + col) / n_cache : col;
+        const float dx = gs.db[qi], dy = gs.db[128 + qi], dz = gs.db[256 + qi];
+        if (Tt == n_cache) {   // residual tile: keep this column's direction for the final combine
+            rdx = dx;
+            rdy = dy;
+            rdz = dz;
+        }
+        const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g);
-        direction_operands<PREC>(dx[tt], dy[tt], dz[tt], g, bd[tt][0], bd[tt][1]);
+        for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(gs.hs + j * W + 16 * mt + 4 * g);
+        direction_operands<PREC>(dx, dy, dz, g, bd[tt][0], bd[tt][1]);
     }
     u32x4 hb[T][KB];
     mlp16<W, PREC, T>(h, hb, bd, sD, sH, lane);
-    f32x4 y[T];
-    output16<W, PREC, T>(y, hb, sO, lane);
+    const f32x4 z = output16_packed<W, PREC, T>(hb, sOS, lane);
+
+    // lane (g, col): tile tt = col / 3, channel c = col % 3, queries 4g + i of that tile
+    const int tt = col / 3, c = col - 3 * (col / 3);
+    const bool valid = col < 3 * T;
+    const int Tt = T0 + tt;
+    const float e0 = __expf(z[0]), e1 = __expf(z[1]), e2 = __expf(z[2]), e3 = __expf(z[3]);
+    const int q0 = 4 * g;   // first query (row) of this lane within its tile
+    if ((n_cache & 15) == 0) {
+        float sum = (e0 + e1) + (e2 + e3);
+        sum += __shfl_xor(sum, 16);
+        sum += __shfl_xor(sum, 32);
+        // one point per tile; tiles of a pass may share a point, so add tile by tile
 #pragma unroll
-    for (int tt = 0; tt < T; ++tt) {
-        const int Tt = T0 + tt;
-        const float y0 = __expf(y[tt][0]), y1 = __expf(y[tt][1]), y2 = __expf(y[tt][2]);
-        if (Tt < n_cache) {
-            reduce_cache_tile(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
-        } else {
-            float Lr[3];
-            field_eval(lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
-            fr0 = Lr[0] - y0;
-            fr1 = Lr[1] - y1;
-            fr2 = Lr[2] - y2;
+        for (int u = 0; u < T; ++u) {
+            if (valid && tt == u && g == 0 && Tt < n_cache) gs.psum[div_n((uint32_t)(16 * Tt), dn) * 4 + c] += sum;
+            wave_sync();
         }
+    } else if (n_cache <= 8 && (16 % n_cache) == 0) {
+        // every point of a cache tile lies inside the tile: plain stores of complete sums
+        if (valid && Tt < n_cache) {
+            const int pbase = (int)div_n((uint32_t)(16 * Tt + q0), dn);   // point of this lane's first query
+            if (n_cache == 1) {
+                gs.psum[(pbase + 0) * 4 + c] = e0;
+                gs.psum[(pbase + 1) * 4 + c] = e1;
+                gs.psum[(pbase + 2) * 4 + c] = e2;
+                gs.psum[(pbase + 3) * 4 + c] = e3;
+            } else if (n_cache == 2) {
+                gs.psum[(pbase + 0) * 4 + c] = e0 + e1;
+                gs.psum[(pbase + 1) * 4 + c] = e2 + e3;
+            } else if (n_cache == 4) {
+                gs.psum[pbase * 4 + c] = (e0 + e1) + (e2 + e3);
+            }
+        }
+        if (n_cache == 8) {
+            float sum = (e0 + e1) + (e2 + e3);
+            sum += __shfl_xor(sum, 16);
+            if (valid && Tt < n_cache && (g & 1) == 0) gs.psum[((16 * Tt + q0) / 8) * 4 + c] = sum;
+        }
+    } else {
+        // any other N: tile by tile through a query buffer, one lane per channel summing in order
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            if (valid && tt == u) {
+                gs.qbuf[(q0 + 0) * 4 + c] = e0;
+                gs.qbuf[(q0 + 1) * 4 + c] = e1;
+                gs.qbuf[(q0 + 2) * 4 + c] = e2;
+                gs.qbuf[(q0 + 3) * 4 + c] = e3;
+            }
+            wave_sync();
+            if (lane < 3 && T0 + u < n_cache) {
+                for (int q = 0; q < 16; ++q) {
+                    const int pt = (int)div_n((uint32_t)(16 * (T0 + u) + q), dn);
+                    gs.psum[pt * 4 + lane] += gs.qbuf[q * 4 + lane];
+                }
+            }
+            wave_sync();
+        }
+    }
+    // residual tile: predictions at each point's residual direction (query j = point j)
+    if (valid && Tt == n_cache) {
+        gs.yres[(q0 + 0) * 4 + c] = e0;
+        gs.yres[(q0 + 1) * 4 + c] = e1;
+        gs.yres[(q0 + 2) * 4 + c] = e2;
+        gs.yres[(q0 + 3) * 4 + c] = e3;
     }
 }
 
@@ -113,7 +174,7 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, cons
 // per MLP pass, in-wave per-point reduction), with 16-bit operands.
 template <int W, int PREC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes lobes, const uint16_t *__restrict__ packed,
-                                                         int n_cache, uint32_t key0, uint32_t key1, uint32_t frame,
+                                                         int n_cache, DivN dn, uint32_t key0, uint32_t key1, uint32_t frame,
                                                          float *__restrict__ out_tl, float *__restrict__ out_c,
                                                          float *__restrict__ out_r) {
     constexpr H16Layout L{W};
@@ -134,8 +195,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
     const uint16_t *sO = sH + 3 * L.size(SEC_H0);
     const uint16_t *gS = packed + L.offset(SEC_S);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
-    float *hs = (float *)slab4 + wave * SLAB;   // [16 points][W]
-    float *db = hs + 16 * W;                    // directions, SoA [3][128]
+    GroupSlab gs;
+    gs.hs = (float *)slab4 + wave * SLAB;
+    gs.db = gs.hs + 16 * W;
+    gs.psum = gs.db + 3 * 128;
+    gs.yres = gs.psum + 64;
+    gs.qbuf = gs.yres + 64;
+    const uint16_t *sOS = sO + L.size(SEC_O);
     const int64_t P = pts.count;
     const int64_t n_groups = (P + 15) >> 4;
     const int n_tiles = n_cache + 1;
@@ -150,25 +216,32 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
             layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
-            wave_sync();
+            wave_sync();   // the previous group's readers of the slab are done
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+            for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(gs.hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+            gs.psum[lane] = 0.0f;
+            wave_sync();
         }
-        float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
+        float rdx = 0.f, rdy = 0.f, rdz = 0.f;
         for (int tb = 0; tb < n_tiles; tb += 8) {
-            gen_dirs_batch(pts, p0, tb, n_cache, key0, key1, frame, lane, db);
+            gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db);
             const int tend = min(tb + 8, n_tiles);
             int t = tb;
 #pragma unroll 1
             for (; t + 4 <= tend; t += 4)
-                tlmc_tiles_h16<W, PREC, 4>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0,
-                                           fc1, fc2, fr0, fr1, fr2);
+                tlmc_tiles_h16<W, PREC, 4>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
 #pragma unroll 1
             for (; t < tend; ++t)
-                tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0,
-                                           fc1, fc2, fr0, fr1, fr2);
+                tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
         }
-        if (g == 0 && p0 + col < P) store_estimate(p0 + col, inv_n, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
+        wave_sync();
+        if (g == 0 && p0 + col < P) {
+            float Lr[3];
+            field_eval(s_lobes, xs[0], xs[1], xs[2], rdx, rdy, rdz, Lr);
+            const float *ps = gs.psum + 4 * col, *yr = gs.yres + 4 * col;
+            store_estimate(p0 + col, inv_n, ps[0], ps[1], ps[2], Lr[0] - yr[0], Lr[1] - yr[1], Lr[2] - yr[2], out_tl,
+                           out_c, out_r);
+        }
     }
 }
 
@@ -206,10 +279,10 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
     if (W != 64) return hipErrorInvalidValue;
     if (prec == NIRC_BF16)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, k0, k1, f, out_tl, out_c, out_r);
+                           n_cache, make_divn(n_cache), k0, k1, f, out_tl, out_c, out_r);
     else
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, k0, k1, f, out_tl, out_c, out_r);
+                           n_cache, make_divn(n_cache), k0, k1, f, out_tl, out_c, out_r);
     return hipGetLastError();
 }
 

@@ -17,7 +17,9 @@ struct InferLds {
 
 template <int W>
 struct TlmcLds {
-    static constexpr int kSlab = 16 * W + 3 * 128;   // h_s of 16 points + 128 staged directions
+    // h_s of 16 points, 128 staged directions, per-point cache sums [16][4], residual
+    // predictions [16][4] and a per-tile query buffer [16][4]
+    static constexpr int kSlab = 16 * W + 3 * 128 + 3 * 64;
 };
 
 // Orders this wave's LDS traffic around a point where lanes exchange data through LDS.
@@ -155,8 +157,8 @@ __device__ __forceinline__ void output_layer(f32x4 (&y)[T], const f32x4 (&h)[T][
 // Directions of queries 2 lane and 2 lane + 1 of the 128-query batch starting at tile tb of the
 // point group at p0 (N cache tiles, then one residual tile); one Philox block serves both
 // (two blocks only for odd N).  Written to db as SoA [3][128].
-__device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, int tb, int n_cache, uint32_t key0,
-                                               uint32_t key1, uint32_t frame, int lane, float *db) {
+__device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, int tb, int n_cache, DivN dn,
+                                               uint32_t key0, uint32_t key1, uint32_t frame, int lane, float *db) {
     const int64_t P = pts.count;
     const int T = tb + (lane >> 3);
     const int c0 = (2 * lane) & 15;
@@ -169,9 +171,9 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
             jb = c0 + 1;
         } else {
             const int qa = 16 * T + c0;
-            ja = qa / n_cache;
+            ja = (int)div_n((uint32_t)qa, dn);
             ka = qa - ja * n_cache;
-            jb = (qa + 1) / n_cache;
+            jb = (int)div_n((uint32_t)(qa + 1), dn);
             kb = qa + 1 - jb * n_cache;
         }
         const int64_t pa = p0 + ja, pb = p0 + jb;
@@ -197,12 +199,13 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
 // Sums over aligned groups of 2, 4, 8 or 16 lanes of a 16-lane row with DPP (result in every
 // lane of the group): quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
 __device__ __forceinline__ float dpp_add(float x, int ctrl_step) {
-    int v = __builtin_bit_cast(int, x), r;
+    const int v = __builtin_bit_cast(int, x);
+    int r;
     switch (ctrl_step) {
-    case 0: r = __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false); break;
-    case 1: r = __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false); break;
-    case 2: r = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false); break;
-    default: r = __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false); break;
+    case 0: r = __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true); break;
+    case 1: r = __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true); break;
+    case 2: r = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true); break;
+    default: r = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true); break;
     }
     return x + __builtin_bit_cast(float, r);
 }
