@@ -90,15 +90,16 @@ __device__ inline float u24(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
 
 // Cosine-weighted direction about unit normal n from uniforms (u1, u2): local
 // (sqrt(u1) cos 2pi u2, sqrt(u1) sin 2pi u2, sqrt(1 - u1)) in the branchless orthonormal basis
-// of Duff et al. (JCGT 2017).  Contraction is off so that every kernel that inlines this
-// produces bit-identical directions.
+// of Duff et al. (JCGT 2017).  The hardware sine/cosine take their argument in revolutions,
+// which is exactly u2; with the hardware square root the direction is within ~1e-6 of the exact
+// map.  Contraction is off so that every kernel that inlines this produces bit-identical
+// directions.
 __device__ inline void cosine_dir(float nx, float ny, float nz, float u1, float u2, float &wx,
                                   float &wy, float &wz) {
 #pragma clang fp contract(off)
-    const float r = sqrtf(u1);
-    float s2, c2;
-    sincospif(2.0f * u2, &s2, &c2);
-    const float lx = r * c2, ly = r * s2, lz = sqrtf(1.0f - u1);
+    const float r = __builtin_amdgcn_sqrtf(u1);
+    const float s2 = __builtin_amdgcn_sinf(u2), c2 = __builtin_amdgcn_cosf(u2);
+    const float lx = r * c2, ly = r * s2, lz = __builtin_amdgcn_sqrtf(1.0f - u1);
     const float s = nz >= 0.0f ? 1.0f : -1.0f;
     const float a = -1.0f / (s + nz);
     const float b = nx * ny * a;

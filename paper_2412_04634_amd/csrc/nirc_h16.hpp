@@ -159,40 +159,51 @@ __device__ __forceinline__ void direction_operands(float dx, float dy, float dz,
 }
 
 // Layer 1 (direction part, accumulating onto h) + ReLU, then layers 2..4, for T tiles; leaves
-// the hidden activations of layer 4 as chained B operands hb[tt][kb].
+// the hidden activations of layer 4 as chained B operands hb[tt][kb].  Each layer's weight
+// fragments are fetched from LDS while the previous layer's MFMAs drain and its epilogue runs
+// (software prefetch), so LDS latency does not sit between the layers.  `next` receives the
+// output layer's fragments (4 shifted copies x KB) for output16_packed.
 template <int W, int PREC, int T>
 __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
-                                      const uint16_t *sD, const uint16_t *sH, int lane) {
+                                      const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS, int lane,
+                                      u32x4 (&aout)[4 * (W / 32)]) {
     constexpr int MT = W / 16, KB = W / 32;
+    static_assert(MT * 2 == MT * KB || KB == 2, "fragment buffer sized for KB = 2");
+    u32x4 a[MT * 2];   // fragments of the layer being computed: [kb][mt]
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const u32x4 a = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
+        for (int mt = 0; mt < MT; ++mt) a[kb * MT + mt] = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
 #pragma unroll
-            for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a, bd[tt][kb], h[tt][mt]);
+    for (int layer = 0; layer < 4; ++layer) {
+        __builtin_amdgcn_sched_barrier(0);
+        const u32x4(&bin)[T][2] = layer == 0 ? bd : hb;
+        if (layer > 0) {
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
-    for (int tt = 0; tt < T; ++tt)
+        for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        // keep each layer's fragment loads inside the layer (hoisting them all costs registers)
-        __builtin_amdgcn_sched_barrier(0);
-        const uint16_t *sec = sH + l * (MT * KB * 512);
+                for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a[kb * MT + mt], bin[tt][kb], h[tt][mt]);
+        // prefetch the next layer's fragments (hidden layer `layer`, or the output copies)
+        if (layer < 3) {
+            const uint16_t *sec = sH + layer * (MT * KB * 512);
 #pragma unroll
-        for (int tt = 0; tt < T; ++tt)
+            for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) h[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int mt = 0; mt < MT; ++mt) a[kb * MT + mt] = *(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8);
+        } else {
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
+            for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const u32x4 a = *(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8);
-#pragma unroll
-                for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a, hb[tt][kb], h[tt][mt]);
-            }
+                for (int t4 = 0; t4 < 4; ++t4)
+                    aout[kb * 4 + t4] = *(const u32x4 *)(sOS + ((t4 * KB + kb) * 64 + lane) * 8);
+        }
 #pragma unroll
         for (int tt = 0; tt < T; ++tt)
 #pragma unroll
@@ -206,17 +217,14 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
 // columns 3tt..3tt+2.  Lane (g, col) ends with z of queries 4g + i (i = 0..3) of tile col / 3,
 // channel col % 3 (columns >= 3T are zero).
 template <int W, int PREC, int T>
-__device__ __forceinline__ f32x4 output16_packed(const u32x4 (&hb)[T][W / 32], const uint16_t *sOS, int lane) {
+__device__ __forceinline__ f32x4 output16_packed(const u32x4 (&hb)[T][W / 32], const u32x4 (&aout)[4 * (W / 32)]) {
     constexpr int KB = W / 32;
     __builtin_amdgcn_sched_barrier(0);
     f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
-        for (int tt = 0; tt < T; ++tt) {
-            const u32x4 b = *(const u32x4 *)(sOS + ((tt * KB + kb) * 64 + lane) * 8);
-            y = mfma16<PREC>(hb[tt][kb], b, y);
-        }
+        for (int tt = 0; tt < T; ++tt) y = mfma16<PREC>(hb[tt][kb], aout[kb * 4 + tt], y);
     return y;
 }
 

@@ -52,14 +52,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
         u32x4 bd[1][2];
         direction_operands<PREC>(q.wx[qi], q.wy[qi], q.wz[qi], g, bd[0][0], bd[0][1]);
         u32x4 hb[1][KB];
-        mlp16<W, PREC, 1>(h, hb, bd, sD, sH, lane);
-        f32x4 y[1];
-        output16<W, PREC, 1>(y, hb, sO, lane);
-        if (g == 0 && (tile << 4) + col < Q) {
-            float *o = rgb + 3 * ((tile << 4) + col);
-            o[0] = __expf(y[0][0]);
-            o[1] = __expf(y[0][1]);
-            o[2] = __expf(y[0][2]);
+        u32x4 aout[4 * KB];
+        mlp16<W, PREC, 1>(h, hb, bd, sD, sH, sO + L.size(SEC_O), lane, aout);
+        // lane (g, c < 3) holds channel c of queries 4g + i of this tile
+        const f32x4 z = output16_packed<W, PREC, 1>(hb, aout);
+        if (col < 3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t qo = (tile << 4) + 4 * g + i;
+                if (qo < Q) rgb[3 * qo + col] = __expf(z[i]);
+            }
         }
     }
 }
@@ -100,8 +102,9 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
         direction_operands<PREC>(dx, dy, dz, g, bd[tt][0], bd[tt][1]);
     }
     u32x4 hb[T][KB];
-    mlp16<W, PREC, T>(h, hb, bd, sD, sH, lane);
-    const f32x4 z = output16_packed<W, PREC, T>(hb, sOS, lane);
+    u32x4 aout[4 * KB];
+    mlp16<W, PREC, T>(h, hb, bd, sD, sH, sOS, lane, aout);
+    const f32x4 z = output16_packed<W, PREC, T>(hb, aout);
 
     // lane (g, col): tile tt = col / 3, channel c = col % 3, queries 4g + i of that tile
     const int tt = col / 3, c = col - 3 * (col / 3);

@@ -249,10 +249,12 @@ def test_train_steps_follow_oracle(nirc):
             t += 1
             oracle.adam(ow, om, ov, g, t, lr=1e-3)
     w = host(model.get_weights())
-    # FP32 vs FP64 trajectories: each step moves weights by <= lr; agreement to a small
-    # fraction of the accumulated update
-    assert np.abs(w - ow).max() <= 0.05 * 12 * 1e-3
+    # FP32 vs FP64 trajectories.  Adam moves a weight by ~lr * sign(g) when |g| is tiny, so a
+    # weight whose near-zero gradient changes sign between FP32 and FP64 may differ by up to
+    # 2 lr per step; compare the accumulated update in relative L2 and bound all but 0.1 % of
+    # the weights to 5 % of the 12-step update scale.
     assert rel_l2(w - w0, ow - w0) <= 1e-2
+    assert np.quantile(np.abs(w - ow), 0.999) <= 0.05 * 12 * 1e-3
 
 
 def test_nonfinite_gradient_skips_step(nirc):
