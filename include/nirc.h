@@ -175,6 +175,39 @@ nirc_status tlmc_estimate(const nirc_model *model, nirc_points points,
                           uint64_t frame, float *out_tl, float *out_c, float *out_r, void *stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Continuous batching of estimates (several render streams, each with its own cache)         */
+
+#define TLMC_BATCH_MAX_REQUESTS 64
+
+/* One frame of one render stream: its model, points, field, sample count, seed and frame, and
+ * where the results go (as for tlmc_estimate).  Host struct. */
+typedef struct {
+    const nirc_model *model;
+    nirc_points points;
+    nirc_lobes field;
+    int32_t n_cache;
+    uint64_t seed;
+    uint64_t frame;
+    float *out_tl, *out_c, *out_r;
+} tlmc_request;
+
+/* Bytes of a work list. */
+size_t tlmc_batch_bytes(void);
+
+/* Fill a work list (host memory of tlmc_batch_bytes) for n requests (1..TLMC_BATCH_MAX_REQUESTS)
+ * whose models share width and precision.  The caller copies it to device memory and launches
+ * tlmc_estimate_batch on it; the list only holds device pointers, so it stays valid as long as
+ * the models and buffers it names do. */
+nirc_status tlmc_batch_build(const tlmc_request *requests /* host */, int32_t n, void *list /* host */);
+
+/* Every request of a device work list in one persistent launch: a fixed grid walks the list in
+ * chunks of 128 points, re-staging weights only when the request changes.  Results are identical
+ * to tlmc_estimate of each request alone.  The launch shape does not depend on the list, so a
+ * captured launch (hipGraph) can be replayed after writing a different list to the same buffer.
+ * width and precision must match the list's models. */
+nirc_status tlmc_estimate_batch(const void *list /* device */, int32_t width, int32_t precision, void *stream);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Training                                                                                    */
 
 /* Training samples (stand-in for the paper's separate training pass, Sec. "Cache

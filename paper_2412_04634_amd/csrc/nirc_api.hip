@@ -330,6 +330,55 @@ nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries 
     return hip_status(e);
 }
 
+size_t tlmc_batch_bytes(void) { return sizeof(BatchDesc); }
+
+nirc_status tlmc_batch_build(const tlmc_request *requests, int32_t n, void *list) {
+    if (!requests || !list || n < 1 || n > TLMC_BATCH_MAX_REQUESTS || n > kBatchMaxRequests)
+        return NIRC_ERR_INVALID_ARG;
+    BatchDesc *d = (BatchDesc *)list;
+    memset(d, 0, sizeof(*d));
+    const nirc_model *m0 = requests[0].model;
+    if (!m0) return NIRC_ERR_INVALID_ARG;
+    int64_t chunk = 0;
+    for (int i = 0; i < n; ++i) {
+        const tlmc_request &r = requests[i];
+        if (!r.model || r.model->W != m0->W || r.model->cfg.precision != m0->cfg.precision) return NIRC_ERR_INVALID_ARG;
+        if (check_points(r.points) != NIRC_OK || r.points.count < 1) return NIRC_ERR_INVALID_ARG;
+        if (r.n_cache < 1 || r.n_cache > 4096 || !r.out_tl) return NIRC_ERR_INVALID_ARG;
+        BatchRequest &q = d->req[i];
+        q.pts = to_points(r.points);
+        q.packed = r.model->packed16 ? (const void *)r.model->packed16 : (const void *)r.model->packed;
+        q.lobes = r.field;
+        q.n_cache = r.n_cache;
+        q.dn = make_divn(r.n_cache);
+        q.key0 = (uint32_t)r.seed;
+        q.key1 = (uint32_t)(r.seed >> 32);
+        q.frame = (uint32_t)r.frame;
+        q.out_tl = r.out_tl;
+        q.out_c = r.out_c;
+        q.out_r = r.out_r;
+        q.chunk_begin = (int32_t)chunk;
+        const int64_t groups = (r.points.count + 15) / 16;
+        chunk += (groups + kBatchChunkGroups - 1) / kBatchChunkGroups;
+        if (chunk > INT32_MAX) return NIRC_ERR_INVALID_ARG;
+    }
+    d->n_requests = n;
+    d->total_chunks = (int32_t)chunk;
+    d->width = m0->W;
+    d->precision = m0->cfg.precision;
+    return NIRC_OK;
+}
+
+nirc_status tlmc_estimate_batch(const void *list, int32_t width, int32_t precision, void *stream) {
+    if (!list || width != 64) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int grid = kMaxResidentBlocks;   // one persistent workgroup per CU
+    if (precision == NIRC_FP32) return hip_status(launch_tlmc_multi_f32(width, (const BatchDesc *)list, grid, s));
+    if (precision == NIRC_BF16 || precision == NIRC_FP16)
+        return hip_status(launch_tlmc_multi_h16(width, precision, (const BatchDesc *)list, grid, s));
+    return NIRC_ERR_INVALID_ARG;
+}
+
 nirc_status tlmc_reference_table(const nirc_lobes *field, double *table, void *stream) {
     if (!field || !table) return NIRC_ERR_INVALID_ARG;
     for (int j = 0; j < 4; ++j)

@@ -195,6 +195,45 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 // input, chains the hidden layers through registers and leaves RGB in lanes 0..15.  Cache
 // results are summed per point with a 16-lane prefix sum; the residual tile evaluates the
 // field and subtracts.  Only the final per-point values leave the chip.
+// One point group (16 points from p0) through the FP32 chain.
+template <int W>
+__device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
+                                               uint32_t key1, uint32_t frame, float *out_tl, float *out_c,
+                                               float *out_r, const nirc_lobes &lobes, const float *gS,
+                                               const float *sD, const float *sH, const float *sO, float *hs,
+                                               float *db, int lane, int g, int col) {
+    constexpr int MT = W / 16;
+    const int64_t P = pts.count;
+    const int n_tiles = n_cache + 1;
+    const int64_t pc = min(p0 + col, P - 1);
+    const float xs[7] = {pts.px[pc], pts.py[pc], pts.pz[pc], pts.nx[pc], pts.ny[pc], pts.nz[pc], pts.rough[pc]};
+    {
+        f32x4 hsum[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer1_surface<W>(hsum, opaque(gS), xs, lane, g);
+        wave_sync();   // previous group's readers of the slab are done
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+    }
+    float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
+    for (int tb = 0; tb < n_tiles; tb += 8) {
+        gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, db);
+        const int tend = min(tb + 8, n_tiles);
+        int t = tb;
+#pragma unroll 1
+        for (; t + 4 <= tend; t += 4)
+            tlmc_tiles_f32<W, 4>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
+                                 fr0, fr1, fr2);
+#pragma unroll 1
+        for (; t < tend; ++t)
+            tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
+                                 fr0, fr1, fr2);
+    }
+    if (g == 0 && p0 + col < P)
+        store_estimate(p0 + col, 1.0f / (float)n_cache, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
+}
+
 template <int W, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes lobes,
                                                          const float *__restrict__ packed,
@@ -203,7 +242,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
                                                          float *__restrict__ out_c,
                                                          float *__restrict__ out_r) {
     constexpr F32Layout L{W};
-    constexpr int MT = W / 16;
     constexpr int NW = InferLds<W>::kWeights;
     constexpr int SLAB = TlmcLds<W>::kSlab;
     __shared__ f32x4 smem4[(NW + WAVES * SLAB) / 4];
@@ -222,43 +260,48 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     float *hs = smem + NW + wave * SLAB;   // [16 points][W]
     float *db = hs + 16 * W;               // directions, SoA [3][128]
-    const int64_t P = pts.count;
-    const int64_t n_groups = (P + 15) >> 4;
-    const int n_tiles = n_cache + 1;
-    const float inv_n = 1.0f / (float)n_cache;
+    const int64_t n_groups = (pts.count + 15) >> 4;
+    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
+        tlmc_group_f32<W>(pts, grp << 4, n_cache, dn, key0, key1, frame, out_tl, out_c, out_r, s_lobes, gS, sD, sH,
+                          sO, hs, db, lane, g, col);
+}
 
-    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups;
-         grp += (int64_t)gridDim.x * WAVES) {
-        const int64_t p0 = grp << 4;
-        const int64_t pc = min(p0 + col, P - 1);
-        const float xs[7] = {pts.px[pc], pts.py[pc], pts.pz[pc], pts.nx[pc], pts.ny[pc], pts.nz[pc], pts.rough[pc]};
-
-        // surface projection, once per point
-        {
-            f32x4 hsum[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-            layer1_surface<W>(hsum, opaque(gS), xs, lane, g);
-            wave_sync();   // previous group's readers of the slab are done
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+// Continuous batching with the FP32 chain (see k_tlmc_multi_h16).
+template <int W, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_f32(const BatchDesc *__restrict__ desc) {
+    constexpr F32Layout L{W};
+    constexpr int NW = InferLds<W>::kWeights;
+    constexpr int SLAB = TlmcLds<W>::kSlab;
+    __shared__ f32x4 smem4[(NW + WAVES * SLAB) / 4];
+    __shared__ BatchRequest s_req;
+    float *smem = (float *)smem4;
+    const float *sD = smem;
+    const float *sH = smem + L.size(SEC_D);
+    const float *sO = sH + 3 * L.size(SEC_H0);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    float *hs = smem + NW + wave * SLAB;
+    float *db = hs + 16 * W;
+    const int n_req = desc->n_requests;
+    const int total = desc->total_chunks;
+    int cur = -1;
+    for (int chunk = blockIdx.x; chunk < total; chunk += gridDim.x) {
+        int r = 0;
+        for (int i = 1; i < n_req; ++i)
+            if (desc->req[i].chunk_begin <= chunk) r = i;
+        if (r != cur) {
+            __syncthreads();
+            if (threadIdx.x == 0) s_req = desc->req[r];
+            __syncthreads();
+            const f32x4 *src = (const f32x4 *)((const float *)s_req.packed + L.offset(SEC_D));
+            for (int i = threadIdx.x; i < NW / 4; i += WAVES * 64) smem4[i] = src[i];
+            __syncthreads();
+            cur = r;
         }
-
-        float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
-        for (int tb = 0; tb < n_tiles; tb += 8) {
-            gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, db);
-            const int tend = min(tb + 8, n_tiles);
-            int t = tb;
-#pragma unroll 1
-            for (; t + 4 <= tend; t += 4)
-                tlmc_tiles_f32<W, 4>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
-                                     fc2, fr0, fr1, fr2);
-#pragma unroll 1
-            for (; t < tend; ++t)
-                tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, s_lobes, xs, lane, g, col, fc0, fc1,
-                                     fc2, fr0, fr1, fr2);
-        }
-        if (g == 0 && p0 + col < P) store_estimate(p0 + col, inv_n, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
+        const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
+        if (grp < (s_req.pts.count + 15) >> 4)
+            tlmc_group_f32<W>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
+                              s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
+                              (const float *)s_req.packed + L.offset(SEC_S), sD, sH, sO, hs, db, lane, g, col);
     }
 }
 
@@ -327,6 +370,14 @@ hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, co
                            rgb);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStream_t s) {
+    constexpr int WAVES = 8;
+    static_assert(WAVES == kBatchChunkGroups, "chunk size");
+    if (W != 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tlmc_multi_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
     return hipGetLastError();
 }
 

@@ -172,16 +172,73 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
     }
 }
 
-// Fused two-level estimator, same organisation as the FP32 kernel (16 points per wave, surface
-// projection once per point into an LDS slab, 8 tiles of directions per Philox batch, 4 tiles
-// per MLP pass, in-wave per-point reduction), with 16-bit operands.
+// One point group (16 points from p0) of the fused estimator: surface projection once per point
+// into the slab, then the N + 1 query tiles in passes of 4 (and single-tile remainders), then the
+// per-point combine and store.  Weights for the direction/hidden/output layers are in LDS; the
+// surface columns are read from global memory (gS).
+template <int W, int PREC>
+__device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
+                                               uint32_t key1, uint32_t frame, float *out_tl, float *out_c,
+                                               float *out_r, const nirc_lobes &lobes, const uint16_t *gS,
+                                               const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
+                                               const GroupSlab &gs, int lane, int g, int col) {
+    constexpr int MT = W / 16;
+    const int64_t P = pts.count;
+    const int n_tiles = n_cache + 1;
+    const int64_t pc = min(p0 + col, P - 1);
+    const float xs[7] = {pts.px[pc], pts.py[pc], pts.pz[pc], pts.nx[pc], pts.ny[pc], pts.nz[pc], pts.rough[pc]};
+    {
+        f32x4 hsum[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
+        wave_sync();   // the previous group's readers of the slab are done
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(gs.hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+        gs.psum[lane] = 0.0f;
+        wave_sync();
+    }
+    float rdx = 0.f, rdy = 0.f, rdz = 0.f;
+    for (int tb = 0; tb < n_tiles; tb += 8) {
+        gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db);
+        const int tend = min(tb + 8, n_tiles);
+        int t = tb;
+#pragma unroll 1
+        for (; t + 4 <= tend; t += 4)
+            tlmc_tiles_h16<W, PREC, 4>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
+#pragma unroll 1
+        for (; t < tend; ++t)
+            tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
+    }
+    wave_sync();
+    if (g == 0 && p0 + col < P) {
+        float Lr[3];
+        field_eval(lobes, xs[0], xs[1], xs[2], rdx, rdy, rdz, Lr);
+        const float inv_n = 1.0f / (float)n_cache;
+        const float *ps = gs.psum + 4 * col, *yr = gs.yres + 4 * col;
+        store_estimate(p0 + col, inv_n, ps[0], ps[1], ps[2], Lr[0] - yr[0], Lr[1] - yr[1], Lr[2] - yr[2], out_tl,
+                       out_c, out_r);
+    }
+}
+
+__device__ inline GroupSlab group_slab(float *base, int W) {
+    GroupSlab gs;
+    gs.hs = base;
+    gs.db = gs.hs + 16 * W;
+    gs.psum = gs.db + 3 * 128;
+    gs.yres = gs.psum + 64;
+    gs.qbuf = gs.yres + 64;
+    return gs;
+}
+
+// Fused two-level estimator for one request: 16 points per wave at a time, grid-stride over
+// point groups; weights staged once per workgroup.
 template <int W, int PREC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes lobes, const uint16_t *__restrict__ packed,
-                                                         int n_cache, DivN dn, uint32_t key0, uint32_t key1, uint32_t frame,
-                                                         float *__restrict__ out_tl, float *__restrict__ out_c,
-                                                         float *__restrict__ out_r) {
+                                                         int n_cache, DivN dn, uint32_t key0, uint32_t key1,
+                                                         uint32_t frame, float *__restrict__ out_tl,
+                                                         float *__restrict__ out_c, float *__restrict__ out_r) {
     constexpr H16Layout L{W};
-    constexpr int MT = W / 16, KB = W / 32;
     constexpr int NW = Infer16Lds<W>::kWeights;   // 16-bit elements
     constexpr int SLAB = TlmcLds<W>::kSlab;         // floats per wave
     __shared__ u32x4 wsm[NW / 8];
@@ -195,56 +252,56 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
     __syncthreads();
     const uint16_t *sD = (const uint16_t *)wsm;
     const uint16_t *sH = sD + L.size(SEC_D);
-    const uint16_t *sO = sH + 3 * L.size(SEC_H0);
+    const uint16_t *sOS = sH + 3 * L.size(SEC_H0) + L.size(SEC_O);
     const uint16_t *gS = packed + L.offset(SEC_S);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
-    GroupSlab gs;
-    gs.hs = (float *)slab4 + wave * SLAB;
-    gs.db = gs.hs + 16 * W;
-    gs.psum = gs.db + 3 * 128;
-    gs.yres = gs.psum + 64;
-    gs.qbuf = gs.yres + 64;
-    const uint16_t *sOS = sO + L.size(SEC_O);
-    const int64_t P = pts.count;
-    const int64_t n_groups = (P + 15) >> 4;
-    const int n_tiles = n_cache + 1;
-    const float inv_n = 1.0f / (float)n_cache;
+    const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, W);
+    const int64_t n_groups = (pts.count + 15) >> 4;
+    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
+        tlmc_group_h16<W, PREC>(pts, grp << 4, n_cache, dn, key0, key1, frame, out_tl, out_c, out_r, s_lobes, gS, sD,
+                                sH, sOS, gs, lane, g, col);
+}
 
-    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES) {
-        const int64_t p0 = grp << 4;
-        const int64_t pc = min(p0 + col, P - 1);
-        const float xs[7] = {pts.px[pc], pts.py[pc], pts.pz[pc], pts.nx[pc], pts.ny[pc], pts.nz[pc], pts.rough[pc]};
-        {
-            f32x4 hsum[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-            layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
-            wave_sync();   // the previous group's readers of the slab are done
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(gs.hs + col * W + 16 * mt + 4 * g) = hsum[mt];
-            gs.psum[lane] = 0.0f;
-            wave_sync();
+// Continuous batching: a persistent grid walks a device work list of requests (each with its own
+// model, points, field, N, seed and frame).  Work is cut into chunks of WAVES point groups of one
+// request; a workgroup takes chunks in grid-stride order and re-stages weights and field in LDS
+// only when the request changes.  The list lives in device memory, so a captured launch can be
+// replayed with a different mix.
+template <int W, int PREC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *__restrict__ desc) {
+    constexpr H16Layout L{W};
+    constexpr int NW = Infer16Lds<W>::kWeights;
+    constexpr int SLAB = TlmcLds<W>::kSlab;
+    __shared__ u32x4 wsm[NW / 8];
+    __shared__ f32x4 slab4[WAVES * SLAB / 4];
+    __shared__ BatchRequest s_req;
+    const uint16_t *sD = (const uint16_t *)wsm;
+    const uint16_t *sH = sD + L.size(SEC_D);
+    const uint16_t *sOS = sH + 3 * L.size(SEC_H0) + L.size(SEC_O);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, W);
+    const int n_req = desc->n_requests;
+    const int total = desc->total_chunks;
+    int cur = -1;
+    for (int chunk = blockIdx.x; chunk < total; chunk += gridDim.x) {
+        // request owning this chunk (uniform): last r with chunk_begin <= chunk
+        int r = 0;
+        for (int i = 1; i < n_req; ++i)
+            if (desc->req[i].chunk_begin <= chunk) r = i;
+        if (r != cur) {
+            __syncthreads();   // every wave is done with the previous request's weights
+            if (threadIdx.x == 0) s_req = desc->req[r];
+            __syncthreads();
+            const u32x4 *src = (const u32x4 *)((const uint16_t *)s_req.packed + L.offset(SEC_D));
+            for (int i = threadIdx.x; i < NW / 8; i += WAVES * 64) wsm[i] = src[i];
+            __syncthreads();
+            cur = r;
         }
-        float rdx = 0.f, rdy = 0.f, rdz = 0.f;
-        for (int tb = 0; tb < n_tiles; tb += 8) {
-            gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db);
-            const int tend = min(tb + 8, n_tiles);
-            int t = tb;
-#pragma unroll 1
-            for (; t + 4 <= tend; t += 4)
-                tlmc_tiles_h16<W, PREC, 4>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
-#pragma unroll 1
-            for (; t < tend; ++t)
-                tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
-        }
-        wave_sync();
-        if (g == 0 && p0 + col < P) {
-            float Lr[3];
-            field_eval(s_lobes, xs[0], xs[1], xs[2], rdx, rdy, rdz, Lr);
-            const float *ps = gs.psum + 4 * col, *yr = gs.yres + 4 * col;
-            store_estimate(p0 + col, inv_n, ps[0], ps[1], ps[2], Lr[0] - yr[0], Lr[1] - yr[1], Lr[2] - yr[2], out_tl,
-                           out_c, out_r);
-        }
+        const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
+        if (grp < (s_req.pts.count + 15) >> 4)
+            tlmc_group_h16<W, PREC>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
+                                    s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
+                                    (const uint16_t *)s_req.packed + L.offset(SEC_S), sD, sH, sOS, gs, lane, g, col);
     }
 }
 
@@ -269,6 +326,17 @@ hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q
         hipLaunchKernelGGL((k_infer_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
     else
         hipLaunchKernelGGL((k_infer_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+    return hipGetLastError();
+}
+
+hipError_t launch_tlmc_multi_h16(int W, int prec, const BatchDesc *desc, int grid, hipStream_t s) {
+    constexpr int WAVES = 8;
+    static_assert(WAVES == kBatchChunkGroups, "chunk size");
+    if (W != 64) return hipErrorInvalidValue;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
+    else
+        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
     return hipGetLastError();
 }
 

@@ -295,6 +295,31 @@ __device__ __forceinline__ void store_estimate(int64_t p, float inv_n, float fc0
 }
 
 // ------------------------------------------------------------------------------------------
+// Work list of the batched estimator (device memory; written by the host).
+constexpr int kBatchChunkGroups = 8;   // point groups (of 16 points) per chunk = waves per workgroup
+constexpr int kBatchMaxRequests = 64;
+
+struct BatchRequest {
+    Points pts;
+    const void *packed;   // the request's packed weights (precision of the batch)
+    nirc_lobes lobes;
+    int32_t n_cache;
+    DivN dn;
+    uint32_t key0, key1, frame;
+    float *out_tl, *out_c, *out_r;
+    int32_t chunk_begin;   // first chunk of this request in the batch
+    int32_t pad;
+};
+
+struct BatchDesc {
+    int32_t n_requests;
+    int32_t total_chunks;
+    int32_t width;
+    int32_t precision;
+    BatchRequest req[kBatchMaxRequests];
+};
+
+// ------------------------------------------------------------------------------------------
 // Launchers (return the launch status).
 hipError_t launch_pack(float *packed, const float *master, int W, hipStream_t s);
 hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s);
@@ -307,6 +332,8 @@ hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_
                               uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
                               float *wx, float *wy, float *wz, float *target, hipStream_t s);
 unsigned grid_for(int64_t units, int waves, int max_blocks);
+hipError_t launch_tlmc_multi_h16(int W, int prec, const BatchDesc *desc, int grid, hipStream_t s);
+hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStream_t s);
 hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
                             hipStream_t s);
 hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,

@@ -48,6 +48,11 @@ class Lobes(ctypes.Structure):
     _fields_ = [("rec", ctypes.c_float * 64)]   # axis[4][3], kappa[4], alpha[4][3], beta[4][3][3]
 
 
+class _Request(ctypes.Structure):
+    _fields_ = [("model", _vp), ("points", _Points), ("field", Lobes), ("n_cache", _i32), ("seed", _u64),
+                ("frame", _u64), ("out_tl", _vp), ("out_c", _vp), ("out_r", _vp)]
+
+
 class NircError(RuntimeError):
     pass
 
@@ -89,6 +94,9 @@ def lib():
             "tlmc_frame_stats": (_i32, [_Points, ctypes.POINTER(Lobes), _vp, _vp, _vp, _vp, ctypes.c_double, _vp,
                                         _vp, _vp]),
             "tlmc_accumulate": (_i32, [_vp, _i64, _vp, _vp, _vp]),
+            "tlmc_batch_bytes": (_sz, []),
+            "tlmc_batch_build": (_i32, [ctypes.POINTER(_Request), _i32, _vp]),
+            "tlmc_estimate_batch": (_i32, [_vp, _i32, _i32, _vp]),
             "nirc_status_string": (ctypes.c_char_p, [_i32]),
         }
         for name, (res, args) in sig.items():
@@ -350,6 +358,43 @@ def tlmc_frame_stats(points: Points, lobes, table: torch.Tensor, est_tl, est_c=N
 
 def tlmc_accumulate(values: torch.Tensor, s: torch.Tensor, s2: torch.Tensor):
     _check(lib().tlmc_accumulate(_ptr(values), values.numel(), _ptr(s), _ptr(s2), _stream()), "tlmc_accumulate")
+
+
+TLMC_BATCH_MAX_REQUESTS = 64
+
+
+class Batch:
+    """A reusable device work list for tlmc_estimate_batch (continuous batching of several
+    streams' frames into one persistent launch)."""
+
+    def __init__(self, device="cuda"):
+        self.nbytes = int(lib().tlmc_batch_bytes())
+        self.host = torch.zeros(self.nbytes, dtype=torch.uint8).pin_memory()
+        self.dev = torch.zeros(self.nbytes, dtype=torch.uint8, device=device)
+        self.width = None
+        self.precision = None
+        self._keep = []
+
+    def set(self, requests):
+        """requests: list of dicts with model, points, lobes, n_cache, seed, frame, out_tl[, out_c, out_r].
+        Writes the work list to the device buffer on the current stream."""
+        n = len(requests)
+        arr = (_Request * n)()
+        self._keep = []
+        for i, r in enumerate(requests):
+            L = r["lobes"] if isinstance(r["lobes"], Lobes) else lobes_struct(r["lobes"])
+            arr[i] = _Request(r["model"].handle.value, r["points"].c(), L, r["n_cache"], r["seed"], r["frame"],
+                              r["out_tl"].data_ptr(), _ptr(r.get("out_c")) and r["out_c"].data_ptr(),
+                              _ptr(r.get("out_r")) and r["out_r"].data_ptr())
+            self._keep.append(r)
+        _check(lib().tlmc_batch_build(arr, n, ctypes.c_void_p(self.host.data_ptr())), "tlmc_batch_build")
+        self.width = requests[0]["model"].width
+        self.precision = requests[0]["model"].cfg.precision
+        self.dev.copy_(self.host, non_blocking=True)
+
+    def launch(self):
+        _check(lib().tlmc_estimate_batch(ctypes.c_void_p(self.dev.data_ptr()), self.width, self.precision, _stream()),
+               "tlmc_estimate_batch")
 
 
 class NircFunction(torch.autograd.Function):
