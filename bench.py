@@ -108,6 +108,43 @@ def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, fr
     return out
 
 
+def serving_run(seconds):
+    """16 render streams (resolutions 360p..4K, N in {4, 8, 32}, width-64 BF16 caches with their
+    own Adam state), Poisson arrivals at 240 frames/s, HBM-budget admission, continuous batching
+    into a graph-captured persistent launch, 4 training steps of 65,536 per frame."""
+    from paper_2412_04634_amd import serve
+    st, sch, ex = serve.serve_run(seed=5, n_streams=16, rate_hz=240.0, duration_s=seconds, precision=1)
+    # the same streams one frame each: one batched launch vs one launch per stream (GPU time)
+    import torch
+    nirc = ex.nirc
+    specs = serve.make_stream_specs(5, 16)
+    for s in specs:
+        ex.admit(s)
+    reqs = []
+    for s in specs:
+        x = ex.streams[s.sid]
+        reqs.append(dict(model=x["model"], points=x["points"], lobes=x["lobes"].packed(), n_cache=s.n_cache,
+                         seed=s.seed, frame=0, out_tl=x["out"]))
+    b = nirc.Batch()
+    b.set(reqs)
+    b.launch()
+    for r in reqs:
+        nirc.tlmc_estimate(r["model"], r["points"], r["lobes"], r["n_cache"], r["seed"], 0, out=r["out_tl"])
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record()
+    b.launch()
+    e[1].record()
+    for r in reqs:
+        nirc.tlmc_estimate(r["model"], r["points"], r["lobes"], r["n_cache"], r["seed"], 0, out=r["out_tl"])
+    e[2].record()
+    torch.cuda.synchronize()
+    q = sum(s.points * (s.n_cache + 1) for s in specs)
+    st["one_frame_per_stream"] = {"queries": q, "batched_ms": e[0].elapsed_time(e[1]),
+                                  "separate_launches_ms": e[1].elapsed_time(e[2])}
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +155,8 @@ def main():
     ap.add_argument("--no-precision-compare", action="store_true")
     ap.add_argument("--estimate-only", choices=["fp32", "bf16", "fp16"], default=None,
                     help="time only tlmc_estimate at this precision (for profiling runs)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="duration of the multi-stream serving run (0 to skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="first run a plain device copy of this size (reference for HBM counters)")
     args = ap.parse_args()
@@ -198,9 +237,7 @@ def main():
         st = nirc.tlmc_frame_stats(dp, lob, table, out_tl, out_c, out_r, fs=fs)
         if ev is not None:
             ev[2].record(stream)
-        for s in range(S):
-            q, tgt = nirc.tlmc_train_batch(dp, lob, B, seed, f, s)
-            nirc.nirc_train_step(model, dp, q, tgt, loss)
+        nirc.nirc_train_frame(model, dp, lob, B, S, seed, f, loss)
         if ev is not None:
             ev[3].record(stream)
         return st
@@ -261,6 +298,8 @@ def main():
     if not args.no_precision_compare:
         result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
                                                         args.warmup + args.steps, args.steps)
+    if args.serve_seconds > 0:
+        result["serving"] = serving_run(args.serve_seconds)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scene.points, lobes_for, w0, W, N, B, S)
     print(json.dumps(result), flush=True)

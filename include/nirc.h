@@ -112,7 +112,8 @@ int64_t nirc_n_params(int32_t width);
 size_t nirc_state_bytes(const nirc_config *cfg /* host */);
 
 /* Bytes of workspace needed by training calls on batches of up to max_batch queries
- * (per-workgroup gradient partials, reduced gradient, loss).  Inference needs none. */
+ * (per-workgroup gradient partials, reduced gradient, loss, and the sample buffers of
+ * nirc_train_frame).  Inference needs none. */
 size_t nirc_workspace_bytes(const nirc_config *cfg /* host */, int64_t max_batch);
 
 /* Create a model over caller-owned device buffers.  `state` must hold nirc_state_bytes and be
@@ -277,6 +278,15 @@ nirc_status tlmc_frame_stats(nirc_points points, const nirc_lobes *field /* host
 
 /* sum[i] += v[i], sumsq[i] += v[i]^2 in FP64 (per-point accumulation over seeds). */
 nirc_status tlmc_accumulate(const float *values, int64_t count, double *sum, double *sumsq, void *stream);
+
+/* One frame's online training (Sec. "Results": several Adam steps per frame on samples of a
+ * separate training pass): for step s = 0..steps-1, tlmc_train_batch(points, field, batch, seed,
+ * frame, s) into the workspace, then nirc_train_step on it.  The workspace must hold
+ * nirc_workspace_bytes(cfg, batch).  loss (device float, may be NULL) receives the last step's
+ * loss. */
+nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_lobes *field /* host */,
+                             int64_t batch, int32_t steps, uint64_t seed, uint64_t frame, float *loss,
+                             void *stream);
 
 const char *nirc_status_string(nirc_status s);
 

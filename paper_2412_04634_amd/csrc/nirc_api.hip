@@ -34,16 +34,18 @@ struct StateLayout {
     }
 };
 
-// Workspace layout: partials [nblocks][np] | loss partials [nblocks] | grad [np] | loss.
+// Workspace layout: partials [nblocks][np] | loss partials [nblocks] | grad [np] | loss |
+// training samples of nirc_train_frame (point [B], wx, wy, wz [B], target [B][3]).
 struct WorkLayout {
-    size_t partials, loss_partials, grad, loss, total;
-    WorkLayout(int W, int nblocks) {
+    size_t partials, loss_partials, grad, loss, samples, total;
+    WorkLayout(int W, int nblocks, int64_t batch = 0) {
         const size_t np = (size_t)n_params(W);
         size_t o = 0;
         partials = o; o += align_up((size_t)nblocks * np * sizeof(float));
         loss_partials = o; o += align_up((size_t)nblocks * sizeof(float));
         grad = o; o += align_up(np * sizeof(float));
         loss = o; o += align_up(sizeof(float));
+        samples = o; o += align_up((size_t)batch * 7 * sizeof(float));
         total = o;
     }
 };
@@ -116,7 +118,7 @@ size_t nirc_state_bytes(const nirc_config *cfg) {
 
 size_t nirc_workspace_bytes(const nirc_config *cfg, int64_t max_batch) {
     if (check_config(cfg) != NIRC_OK || max_batch < 0) return 0;
-    return WorkLayout(cfg->width, train_blocks(max_batch)).total;
+    return WorkLayout(cfg->width, train_blocks(max_batch), max_batch).total;
 }
 
 nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes, void *workspace,
@@ -328,6 +330,28 @@ nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries 
     if (e == hipSuccess && model->packed16)
         e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
     return hip_status(e);
+}
+
+nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_lobes *field, int64_t batch,
+                             int32_t steps, uint64_t seed, uint64_t frame, float *loss, void *stream) {
+    if (!model || !field || batch < 1 || batch > INT32_MAX || steps < 0) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK || points.count < 1) return NIRC_ERR_INVALID_ARG;
+    const WorkLayout wl(model->W, train_blocks(batch), batch);
+    if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    float *smp = (float *)(model->ws + wl.samples);
+    int32_t *pidx = (int32_t *)smp;
+    float *wx = smp + batch, *wy = wx + batch, *wz = wy + batch, *tgt = wz + batch;
+    for (int32_t k = 0; k < steps; ++k) {
+        hipError_t e = launch_train_batch(to_points(points), *field, batch, seed, frame, (uint32_t)k, pidx, wx, wy, wz,
+                                          tgt, s);
+        if (e != hipSuccess) return NIRC_ERR_HIP;
+        nirc_queries q{wx, wy, wz, pidx, batch};
+        st = nirc_train_step(model, points, q, tgt, k + 1 == steps ? loss : nullptr, s);
+        if (st != NIRC_OK) return st;
+    }
+    return NIRC_OK;
 }
 
 size_t tlmc_batch_bytes(void) { return sizeof(BatchDesc); }

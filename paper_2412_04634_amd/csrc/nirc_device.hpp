@@ -91,9 +91,9 @@ __device__ inline float u24(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
 // Cosine-weighted direction about unit normal n from uniforms (u1, u2): local
 // (sqrt(u1) cos 2pi u2, sqrt(u1) sin 2pi u2, sqrt(1 - u1)) in the branchless orthonormal basis
 // of Duff et al. (JCGT 2017).  The hardware sine/cosine take their argument in revolutions,
-// which is exactly u2; with the hardware square root the direction is within ~1e-6 of the exact
-// map.  Contraction is off so that every kernel that inlines this produces bit-identical
-// directions.
+// which is exactly u2; with the hardware square root and reciprocal the direction is within
+// ~1e-6 of the exact map.  Contraction is off so that every kernel that inlines this produces
+// bit-identical directions.
 __device__ inline void cosine_dir(float nx, float ny, float nz, float u1, float u2, float &wx,
                                   float &wy, float &wz) {
 #pragma clang fp contract(off)
@@ -101,7 +101,7 @@ __device__ inline void cosine_dir(float nx, float ny, float nz, float u1, float 
     const float s2 = __builtin_amdgcn_sinf(u2), c2 = __builtin_amdgcn_cosf(u2);
     const float lx = r * c2, ly = r * s2, lz = __builtin_amdgcn_sqrtf(1.0f - u1);
     const float s = nz >= 0.0f ? 1.0f : -1.0f;
-    const float a = -1.0f / (s + nz);
+    const float a = -__builtin_amdgcn_rcpf(s + nz);   // |s + nz| is in [1, 2]: no range issues
     const float b = nx * ny * a;
     const float tx = 1.0f + s * nx * nx * a, ty = s * b, tz = -s * nx;
     const float bx = b, by = s + ny * ny * a, bz = -ny;

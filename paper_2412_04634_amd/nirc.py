@@ -97,6 +97,7 @@ def lib():
             "tlmc_batch_bytes": (_sz, []),
             "tlmc_batch_build": (_i32, [ctypes.POINTER(_Request), _i32, _vp]),
             "tlmc_estimate_batch": (_i32, [_vp, _i32, _i32, _vp]),
+            "nirc_train_frame": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i64, _i32, _u64, _u64, _vp, _vp]),
             "nirc_status_string": (ctypes.c_char_p, [_i32]),
         }
         for name, (res, args) in sig.items():
@@ -198,7 +199,10 @@ def nirc_workspace_bytes(cfg: Config, max_batch: int) -> int:
 class Model:
     """A cache model over torch-allocated state and workspace."""
 
-    def __init__(self, init_w, cfg: Config | None = None, max_batch: int = 65536, device="cuda"):
+    def __init__(self, init_w, cfg: Config | None = None, max_batch: int = 65536, device="cuda",
+                 workspace: torch.Tensor | None = None):
+        """workspace: an existing training workspace to share (calls on the models that share it
+        must not overlap); otherwise one for batches of up to max_batch is allocated."""
         self.cfg = cfg or make_config()
         self.width = self.cfg.width
         self.n_params = nirc_n_params(self.width)
@@ -206,8 +210,11 @@ class Model:
         if sb == 0:
             raise NircError("unsupported configuration")
         self.state = torch.empty(sb, dtype=torch.uint8, device=device)
-        wb = nirc_workspace_bytes(self.cfg, max_batch) if max_batch > 0 else 0
-        self.workspace = torch.empty(max(wb, 1), dtype=torch.uint8, device=device) if wb else None
+        if workspace is not None:
+            self.workspace, wb = workspace, workspace.numel()
+        else:
+            wb = nirc_workspace_bytes(self.cfg, max_batch) if max_batch > 0 else 0
+            self.workspace = torch.empty(max(wb, 1), dtype=torch.uint8, device=device) if wb else None
         w = init_w if isinstance(init_w, torch.Tensor) else _dev_f32(init_w, device)
         assert w.numel() == self.n_params
         self._w0 = w.contiguous()
@@ -360,6 +367,14 @@ def tlmc_accumulate(values: torch.Tensor, s: torch.Tensor, s2: torch.Tensor):
     _check(lib().tlmc_accumulate(_ptr(values), values.numel(), _ptr(s), _ptr(s2), _stream()), "tlmc_accumulate")
 
 
+def nirc_train_frame(model: Model, points: Points, lobes, batch: int, steps: int, seed: int, frame: int,
+                     loss: torch.Tensor | None = None):
+    """steps x (training samples + train step) in one native call; samples live in the workspace."""
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    _check(lib().nirc_train_frame(model.handle, points.c(), ctypes.byref(L), batch, steps, seed, frame, _ptr(loss),
+                                  _stream()), "nirc_train_frame")
+
+
 TLMC_BATCH_MAX_REQUESTS = 64
 
 
@@ -374,11 +389,14 @@ class Batch:
         self.width = None
         self.precision = None
         self._keep = []
+        self._copied = None
 
     def set(self, requests):
         """requests: list of dicts with model, points, lobes, n_cache, seed, frame, out_tl[, out_c, out_r].
         Writes the work list to the device buffer on the current stream."""
         n = len(requests)
+        if self._copied is not None:
+            self._copied.synchronize()   # the previous list's host-to-device copy has run
         arr = (_Request * n)()
         self._keep = []
         for i, r in enumerate(requests):
@@ -391,6 +409,8 @@ class Batch:
         self.width = requests[0]["model"].width
         self.precision = requests[0]["model"].cfg.precision
         self.dev.copy_(self.host, non_blocking=True)
+        self._copied = torch.cuda.Event()
+        self._copied.record()
 
     def launch(self):
         _check(lib().tlmc_estimate_batch(ctypes.c_void_p(self.dev.data_ptr()), self.width, self.precision, _stream()),

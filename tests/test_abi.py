@@ -40,6 +40,8 @@ def test_host_side_argument_errors():
     assert L.tlmc_sample_dirs(nirc._Points(), 0, 0, 0, None, None) == -1     # n_cache < 1
     bad_pts = nirc._Points(0, 0, 0, 0, 0, 0, 0, 5)                          # NULL arrays, count 5
     assert L.nirc_encode(bad_pts, nirc._Queries(), None, None) == -1
+    lob = nirc.Lobes()
+    assert L.nirc_train_frame(None, nirc._Points(), ctypes.byref(lob), 16, 1, 0, 0, None, None) == -1
     assert L.nirc_status_string(-3).decode() == "state or workspace buffer too small"
 
 
