@@ -76,9 +76,10 @@ def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=15.0):
                       f"steps of {b} samples (batch scaled by the same fraction); {t:.1f} s"}
 
 
-def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, frame, reps):
+def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, frame, reps, B, S):
     """BF16 and FP16 estimates with the FP32 model's current weights, same seed and frame:
-    time per launch (HIP events on the launch stream) and MRSE against the exact integral."""
+    time per launch (HIP events on the launch stream) and MRSE against the exact integral; and
+    one frame of training (S steps of B samples) at each precision, on a copy of the model."""
     import torch
     stream = torch.cuda.current_stream()
     w = model32.get_weights()
@@ -99,13 +100,63 @@ def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, fr
         mrse = float(nirc.tlmc_frame_stats(dp, lob, table, tl, fs=fs)[4].item())
         flops = algorithmic_flops_estimate(P, N, W)
         peak = PEAK_FP32_MFMA if prec == 0 else PEAK_BF16_MFMA
+        mt = nirc.Model(w, cfg=nirc.make_config(precision=prec), max_batch=B)
+        nirc.nirc_train_frame(mt, dp, lob, B, S, seed, frame)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for r in range(reps):
+            nirc.nirc_train_frame(mt, dp, lob, B, S, seed, frame + 1 + r)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        tt = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
         out[name] = {"ms_estimate": t * 1e3, "queries_per_s": P * (N + 1) / t, "mrse": mrse,
                      "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": peak / 1e12,
-                                  "unit": "TFLOP/s", "frac": flops / t / peak}}
+                                  "unit": "TFLOP/s", "frac": flops / t / peak},
+                     "ms_train_frame": tt * 1e3, "train_samples_per_s": S * B / tt,
+                     "train_tflops": algorithmic_flops_train(B, W) * S / tt / 1e12}
     for name in ("bf16", "fp16"):
         out[name]["speedup_vs_fp32"] = out["fp32"]["ms_estimate"] / out[name]["ms_estimate"]
         out[name]["mrse_rel_diff_vs_fp32"] = (out[name]["mrse"] - out["fp32"]["mrse"]) / out["fp32"]["mrse"]
     return out
+
+
+def precision_form(nirc, w64, dp, lob_packed, table, fs, P, seed, frame, reps=3):
+    """The precision matrix: N in {4, 16, 64} x width {64, 128} x {FP32, BF16, FP16} estimates
+    of one 1080p frame on identical weights (width 64: the benchmark's trained FP32 cache;
+    width 128: Glorot initial weights, since training runs at width 64 only).  Per entry: time
+    per launch, queries/s, MFMA fraction, MRSE against the exact integral, and rel-L2 of F_tl
+    against the FP32 result on the same weights and directions."""
+    import torch
+    from paper_2412_04634_amd import workload as wl
+    stream = torch.cuda.current_stream()
+    lob = nirc.lobes_struct(lob_packed)
+    rows = []
+    for W in (64, 128):
+        w = w64 if W == 64 else torch.tensor(wl.make_weights(seed, W), device="cuda")
+        for N in (4, 16, 64):
+            ref = None
+            for name, prec in (("fp32", 0), ("bf16", 1), ("fp16", 2)):
+                m = nirc.Model(w, cfg=nirc.make_config(width=W, precision=prec), max_batch=0)
+                tl = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+                nirc.tlmc_estimate(m, dp, lob, N, seed, frame, out=tl)
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                torch.cuda.synchronize()
+                ev[0].record(stream)
+                for _ in range(reps):
+                    nirc.tlmc_estimate(m, dp, lob, N, seed, frame, out=tl)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
+                t = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+                mrse = float(nirc.tlmc_frame_stats(dp, lob, table, tl, fs=fs)[4].item())
+                if ref is None:
+                    ref = tl.clone()
+                flops = algorithmic_flops_estimate(P, N, W)
+                peak = PEAK_FP32_MFMA if prec == 0 else PEAK_BF16_MFMA
+                rows.append({"width": W, "n_cache": N, "precision": name, "ms_estimate": t * 1e3,
+                             "queries_per_s": P * (N + 1) / t, "mfma_frac": flops / t / peak, "mrse": mrse,
+                             "rel_l2_vs_fp32": float((tl - ref).norm() / ref.norm())})
+                del m
+    return rows
 
 
 def serving_run(seconds):
@@ -157,6 +208,8 @@ def main():
                     help="time only tlmc_estimate at this precision (for profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="duration of the multi-stream serving run (0 to skip)")
+    ap.add_argument("--precision-form", action="store_true",
+                    help="also run the N x width x precision matrix of estimates")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="first run a plain device copy of this size (reference for HBM counters)")
     args = ap.parse_args()
@@ -297,7 +350,10 @@ def main():
     }
     if not args.no_precision_compare:
         result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
-                                                        args.warmup + args.steps, args.steps)
+                                                        args.warmup + args.steps, args.steps, B, S)
+    if args.precision_form:
+        result["precision_form"] = precision_form(nirc, model.get_weights(), dp, lobes_for(args.warmup + args.steps),
+                                                  table, fs, P, seed, args.warmup + args.steps)
     if args.serve_seconds > 0:
         result["serving"] = serving_run(args.serve_seconds)
     if not args.no_cpu_baseline:

@@ -12,7 +12,7 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool width_ok(int32_t w) { return w == 64; }
+bool width_ok(int32_t w) { return w == 64 || w == 128; }
 
 // State layout (each piece 256-byte aligned): master | m | v | packed FP32 | packed 16-bit (BF16
 // and FP16 models only) | step | flags | bad.
@@ -267,18 +267,24 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
     if (st == NIRC_OK) st = check_queries(queries, points);
     if (st != NIRC_OK) return st;
     if (queries.count < 1 || !grad) return NIRC_ERR_INVALID_ARG;
-    const int nb = train_blocks(queries.count);
+    if (model->W != 64) return NIRC_ERR_UNSUPPORTED;   // the gradient kernels are laid out for width 64
+    const bool h16 = model->packed16 != nullptr;
+    const int nb = h16 ? train_blocks16(queries.count) : train_blocks(queries.count);
     const WorkLayout wl(model->W, nb);
     if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
     float *partials = (float *)(model->ws + wl.partials);
     float *lpart = (float *)(model->ws + wl.loss_partials);
-    TrainArgs a{target, d_rgb, model->cfg.loss_eps, model->cfg.loss_scale};
-    hipError_t e = launch_grad_partials(model->W, to_points(points), to_queries(queries), model->packed, a,
-                                        partials, lpart, nb, s);
+    // 16-bit models: the batch size is folded into the loss scale, so that per-sample deltas stay
+    // near unit magnitude in the 16-bit operands; the reduction divides it out again
+    const float scale = h16 ? model->cfg.loss_scale * (float)queries.count : model->cfg.loss_scale;
+    TrainArgs a{target, d_rgb, model->cfg.loss_eps, scale};
+    hipError_t e = h16 ? launch_grad_partials16(model->W, model->cfg.precision, to_points(points),
+                                                to_queries(queries), model->packed16, a, partials, lpart, nb, s)
+                       : launch_grad_partials(model->W, to_points(points), to_queries(queries), model->packed, a,
+                                              partials, lpart, nb, s);
     if (e != hipSuccess) return NIRC_ERR_HIP;
     const float loss_norm = 1.0f / (3.0f * (float)queries.count);
-    e = launch_reduce_grad(model->W, partials, lpart, nb, 1.0f / model->cfg.loss_scale, loss_norm, grad, loss,
-                           model->bad, s);
+    e = launch_reduce_grad(model->W, partials, lpart, nb, 1.0f / scale, loss_norm, grad, loss, model->bad, s);
     return hip_status(e);
 }
 
@@ -363,6 +369,7 @@ nirc_status tlmc_batch_build(const tlmc_request *requests, int32_t n, void *list
     memset(d, 0, sizeof(*d));
     const nirc_model *m0 = requests[0].model;
     if (!m0) return NIRC_ERR_INVALID_ARG;
+    if (m0->W != 64) return NIRC_ERR_UNSUPPORTED;
     int64_t chunk = 0;
     for (int i = 0; i < n; ++i) {
         const tlmc_request &r = requests[i];
@@ -394,7 +401,8 @@ nirc_status tlmc_batch_build(const tlmc_request *requests, int32_t n, void *list
 }
 
 nirc_status tlmc_estimate_batch(const void *list, int32_t width, int32_t precision, void *stream) {
-    if (!list || width != 64) return NIRC_ERR_INVALID_ARG;
+    if (!list) return NIRC_ERR_INVALID_ARG;
+    if (width != 64) return NIRC_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const int grid = kMaxResidentBlocks;   // one persistent workgroup per CU
     if (precision == NIRC_FP32) return hip_status(launch_tlmc_multi_f32(width, (const BatchDesc *)list, grid, s));

@@ -150,6 +150,16 @@ __device__ inline void field_eval(const nirc_lobes &L, float x0, float x1, float
     }
 }
 
+// Lobe j's contribution to the field (the terms of field_eval for one j).
+__device__ inline void field_lobe(const nirc_lobes &L, int j, float x0, float x1, float x2, float wx, float wy,
+                                  float wz, float out[3]) {
+    const float mw = L.axis[j][0] * wx + L.axis[j][1] * wy + L.axis[j][2] * wz;
+    const float gj = expf(L.kappa[j] * (mw - 1.0f));
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        out[c] = (L.alpha[j][c] + L.beta[j][c][0] * x0 + L.beta[j][c][1] * x1 + L.beta[j][c][2] * x2) * gj;
+}
+
 // ------------------------------------------------------------------------------------------
 // MFMA wrappers (wave64).  16x16x4 FP32: lane l holds A[row l%16][k l/16], B[k l/16][col l%16];
 // the 16x16 result gives lane l rows 4(l/16)+i, i = 0..3, of column l%16.

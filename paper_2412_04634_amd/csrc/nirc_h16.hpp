@@ -80,6 +80,16 @@ __host__ __device__ inline int64_t h16_packed_source(int W, int e) {
     }
 }
 
+// Scale applied to packed element e: the 16-bit input features carry 2 cos instead of cos
+// (angle doubling is then one multiply and one FMA per step), so the weights of the cosine
+// features (odd positions of the S and D sections) are stored halved.  Halving is exact in
+// both 16-bit formats (barring FP16 subnormals).
+__host__ __device__ inline float h16_packed_scale(int W, int e) {
+    const H16Layout L{W};
+    const bool feat = (e >= L.offset(SEC_S) && e < L.offset(SEC_D) + L.size(SEC_D));
+    return (feat && (e & 1)) ? 0.5f : 1.0f;
+}
+
 // ------------------------------------------------------------------------------------------
 // Precision traits: PREC = NIRC_BF16 or NIRC_FP16.
 
@@ -109,14 +119,49 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                       0, 0, 0);
 }
 
-// sin/cos(pi 2^k v) for k = 2g and 2g + 1: the hardware sine/cosine (argument in revolutions) at
-// the lower frequency, then one angle doubling.  Accurate to ~1e-6, far below 16-bit rounding.
-__device__ __forceinline__ void enc_pair2_fast(float v, int g, float &s0, float &c0, float &s1, float &c1) {
+// Features in the 16-bit chain are pairs (sin a, 2 cos a): with u = 2 cos a, doubling the angle
+// is sin 2a = u sin a and 2 cos 2a = u^2 - 2.
+// sin(pi 2^k v) and 2 cos(pi 2^k v) for k = 2g and 2g + 1: the hardware sine/cosine (argument in
+// revolutions) at the lower frequency, then one doubling.  Accurate to ~1e-6, far below 16-bit
+// rounding.
+__device__ __forceinline__ void enc_pair2_fast(float v, int g, float &s0, float &u0, float &s1, float &u1) {
     const float rev = ldexpf(v, 2 * g - 1);   // 2^(2g) pi v in revolutions
     s0 = __builtin_amdgcn_sinf(rev);
-    c0 = __builtin_amdgcn_cosf(rev);
-    s1 = 2.0f * s0 * c0;
-    c1 = (c0 - s0) * (c0 + s0);
+    u0 = 2.0f * __builtin_amdgcn_cosf(rev);
+    s1 = s0 * u0;
+    u1 = u0 * u0 - 2.0f;
+}
+
+// All eight frequencies of one coordinate as packed 16-bit (sin, 2 cos) pairs, by seven angle
+// doublings from k = 0 (each doubling at most doubles the FP32 error: ~1e-5 at k = 7).
+template <int PREC>
+__device__ __forceinline__ void chain8(float v, uint32_t (&p)[8]) {
+    float s = __builtin_amdgcn_sinf(0.5f * v);   // sin(pi v); argument in revolutions
+    float u = 2.0f * __builtin_amdgcn_cosf(0.5f * v);
+    p[0] = pack2<PREC>(s, u);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        const float s2 = s * u;
+        u = u * u - 2.0f;
+        s = s2;
+        p[k] = pack2<PREC>(s, u);
+    }
+}
+
+// Direction features of one query for all four lane groups, in the order of the D section's
+// B operands: fa[g] = x(2g), x(2g+1), y(2g), y(2g+1) and fb[g] = z(2g), z(2g+1) (each a packed
+// (sin, 2 cos) pair).  `stride` is the distance between consecutive lane groups' entries.
+template <int PREC>
+__device__ __forceinline__ void dir_features16(float dx, float dy, float dz, u32x4 *fa, uint2 *fb, int stride) {
+    uint32_t px[8], py[8], pz[8];
+    chain8<PREC>(dx, px);
+    chain8<PREC>(dy, py);
+    chain8<PREC>(dz, pz);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        fa[g * stride] = u32x4{px[2 * g], px[2 * g + 1], py[2 * g], py[2 * g + 1]};
+        fb[g * stride] = make_uint2(pz[2 * g], pz[2 * g + 1]);
+    }
 }
 
 // B operand (two K-blocks of the chain) from two result tiles, with ReLU.
@@ -209,6 +254,57 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
     }
+}
+
+// The same chain for widths above 64, whose weights stay in global memory: fragments are loaded
+// one K-block (MT fragments) at a time, and only the T shifted output copies the pass needs.
+template <int W, int PREC, int T>
+__device__ __forceinline__ void mlp16_wide(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
+                                           const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS, int lane,
+                                           u32x4 (&aout)[4 * (W / 32)]) {
+    constexpr int MT = W / 16, KB = W / 32;
+#pragma unroll
+    for (int layer = 0; layer < 4; ++layer) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (layer > 0) {
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (layer == 0) {
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                u32x4 a[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) a[mt] = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a[mt], bd[tt][kb], h[tt][mt]);
+            }
+        } else {
+            const uint16_t *sec = sH + (layer - 1) * (MT * KB * 512);
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                u32x4 a[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) a[mt] = *(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a[mt], hb[tt][kb], h[tt][mt]);
+            }
+        }
+#pragma unroll
+        for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
+    }
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+        for (int t4 = 0; t4 < T; ++t4) aout[kb * 4 + t4] = *(const u32x4 *)(sOS + ((t4 * KB + kb) * 64 + lane) * 8);
 }
 
 // Output layer for T <= 4 tiles into ONE accumulator: the chained activations hb[tt] (B layout:

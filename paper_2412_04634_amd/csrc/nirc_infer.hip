@@ -99,23 +99,23 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
                                                           float *__restrict__ rgb) {
     constexpr F32Layout L{W};
     constexpr int MT = W / 16;
-    constexpr int NW = InferLds<W>::kWeights;
+    constexpr bool kLds = lds_weights(W);
+    constexpr int NW = kLds ? InferLds<W>::kWeights : 4;
     __shared__ f32x4 smem4[NW / 4];
-    const float *smem = (const float *)smem4;
-    {
+    if constexpr (kLds) {
         const f32x4 *src = (const f32x4 *)(packed + L.offset(SEC_D));
         for (int i = threadIdx.x; i < NW / 4; i += WAVES * 64) smem4[i] = src[i];
+        __syncthreads();
     }
-    __syncthreads();
-    const float *sD = smem;
-    const float *sH = smem + L.size(SEC_D);
-    const float *sO = sH + 3 * L.size(SEC_H0);
     const float *gS = packed + L.offset(SEC_S);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const int64_t Q = q.count;
     const int64_t n_tiles = (Q + 15) >> 4;
     for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < n_tiles;
          tile += (int64_t)gridDim.x * WAVES) {
+        const float *sD = kLds ? (const float *)smem4 : opaque(packed) + L.offset(SEC_D);
+        const float *sH = sD + L.size(SEC_D);
+        const float *sO = sH + 3 * L.size(SEC_H0);
         const int64_t qi = min((tile << 4) + col, Q - 1);
         const int64_t p = query_point(q, pts, qi);
         const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
@@ -148,6 +148,11 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
                                                float &fc0, float &fc1, float &fc2, float &fr0, float &fr1,
                                                float &fr2) {
     constexpr int MT = W / 16;
+    if constexpr (!lds_weights(W)) {   // weights in global memory: keep their loads inside the pass
+        sD = opaque(sD);
+        sH = opaque(sH);
+        sO = opaque(sO);
+    }
     f32x4 h[T][MT];
     float dx[T], dy[T], dz[T];
 #pragma unroll
@@ -221,10 +226,11 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, db);
         const int tend = min(tb + 8, n_tiles);
         int t = tb;
+        constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
-        for (; t + 4 <= tend; t += 4)
-            tlmc_tiles_f32<W, 4>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
-                                 fr0, fr1, fr2);
+        for (; t + TP <= tend; t += TP)
+            tlmc_tiles_f32<W, TP>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
+                                  fr0, fr1, fr2);
 #pragma unroll 1
         for (; t < tend; ++t)
             tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
@@ -242,7 +248,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
                                                          float *__restrict__ out_c,
                                                          float *__restrict__ out_r) {
     constexpr F32Layout L{W};
-    constexpr int NW = InferLds<W>::kWeights;
+    constexpr bool kLds = lds_weights(W);
+    constexpr int NW = kLds ? InferLds<W>::kWeights : 0;
     constexpr int SLAB = TlmcLds<W>::kSlab;
     __shared__ f32x4 smem4[(NW + WAVES * SLAB) / 4];
     __shared__ nirc_lobes s_lobes;
@@ -253,8 +260,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
         if (threadIdx.x == 0) s_lobes = lobes;
     }
     __syncthreads();
-    const float *sD = smem;
-    const float *sH = smem + L.size(SEC_D);
+    const float *sD = kLds ? (const float *)smem : packed + L.offset(SEC_D);
+    const float *sH = sD + L.size(SEC_D);   // LDS for width 64, global memory above
     const float *sO = sH + 3 * L.size(SEC_H0);
     const float *gS = packed + L.offset(SEC_S);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
@@ -368,6 +375,9 @@ hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, co
     if (W == 64)
         hipLaunchKernelGGL((k_infer_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, (const float *)packed,
                            rgb);
+    else if (W == 128)
+        hipLaunchKernelGGL((k_infer_f32<128, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q,
+                           (const float *)packed, rgb);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -394,6 +404,10 @@ hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lob
                            (const float *)packed, n_cache, make_divn(n_cache), (uint32_t)seed, (uint32_t)(seed >> 32),
                            (uint32_t)frame,
                            out_tl, out_c, out_r);
+    else if (W == 128)   // one wave per SIMD: the width-128 FP32 pass needs more than 256 registers
+        hipLaunchKernelGGL((k_tlmc_f32<128, 4>), dim3(grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks)),
+                           dim3(4 * 64), 0, s, pts, lobes, (const float *)packed, n_cache, make_divn(n_cache),
+                           (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -11,7 +11,7 @@ __global__ void k_pack16(uint16_t *packed, const float *master, int W, int total
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     const int64_t s = h16_packed_source(W, e);
-    const float v = s >= 0 ? master[s] : 0.0f;
+    const float v = s >= 0 ? master[s] * h16_packed_scale(W, e) : 0.0f;
     packed[e] = (uint16_t)(pack2<PREC>(v, 0.0f) & 0xFFFFu);
 }
 
@@ -26,22 +26,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
                                                           float *__restrict__ rgb) {
     constexpr H16Layout L{W};
     constexpr int MT = W / 16, KB = W / 32;
-    constexpr int NW = Infer16Lds<W>::kWeights;
+    constexpr bool kLds = lds_weights(W);
+    constexpr int NW = kLds ? Infer16Lds<W>::kWeights : 8;
     __shared__ u32x4 smem4[NW / 8];
-    {
+    if constexpr (kLds) {
         const u32x4 *src = (const u32x4 *)(packed + L.offset(SEC_D));
         for (int i = threadIdx.x; i < NW / 8; i += WAVES * 64) smem4[i] = src[i];
+        __syncthreads();
     }
-    __syncthreads();
-    const uint16_t *smem = (const uint16_t *)smem4;
-    const uint16_t *sD = smem;
-    const uint16_t *sH = smem + L.size(SEC_D);
-    const uint16_t *sO = sH + 3 * L.size(SEC_H0);
     const uint16_t *gS = packed + L.offset(SEC_S);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const int64_t Q = q.count;
     const int64_t n_tiles = (Q + 15) >> 4;
     for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < n_tiles; tile += (int64_t)gridDim.x * WAVES) {
+        const uint16_t *sD = kLds ? (const uint16_t *)smem4 : opaque(packed) + L.offset(SEC_D);
+        const uint16_t *sH = sD + L.size(SEC_D);
+        const uint16_t *sO = sH + 3 * L.size(SEC_H0);
         const int64_t qi = min((tile << 4) + col, Q - 1);
         const int64_t p = query_point(q, pts, qi);
         const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
@@ -53,7 +53,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
         direction_operands<PREC>(q.wx[qi], q.wy[qi], q.wz[qi], g, bd[0][0], bd[0][1]);
         u32x4 hb[1][KB];
         u32x4 aout[4 * KB];
-        mlp16<W, PREC, 1>(h, hb, bd, sD, sH, sO + L.size(SEC_O), lane, aout);
+        if constexpr (kLds) mlp16<W, PREC, 1>(h, hb, bd, sD, sH, sO + L.size(SEC_O), lane, aout);
+        else mlp16_wide<W, PREC, 1>(h, hb, bd, sD, sH, sO + L.size(SEC_O), lane, aout);
         // lane (g, c < 3) holds channel c of queries 4g + i of this tile
         const f32x4 z = output16_packed<W, PREC, 1>(hb, aout);
         if (col < 3) {
@@ -66,13 +67,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
     }
 }
 
-// Per-wave scratch of the estimator's point group (LDS, floats).
+// Per-wave scratch of the estimator's point group (LDS).
 struct GroupSlab {
     float *hs;     // [16 points][W] surface projection
     float *db;     // [3][128] staged directions
     float *psum;   // [16 points][4] cache-level sums
     float *yres;   // [16 points][4] residual-direction predictions
     float *qbuf;   // [16 queries][4] one tile's predictions (general N only)
+    u32x4 *fa;     // [4 tiles][4 lane groups][16 queries] direction features, first K-block
+    uint2 *fb;     // [4 tiles][4 lane groups][16 queries] direction features, second K-block
+};
+
+template <int W>
+struct Tlmc16Lds {
+    static constexpr int kSlab = TlmcLds<W>::kSlab + 4 * 64 * 4 + 4 * 64 * 2;   // floats per wave
 };
 
 // T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
@@ -86,24 +94,43 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
     constexpr int MT = W / 16, KB = W / 32;
     f32x4 h[T][MT];
     u32x4 bd[T][2];
+    if constexpr (T == 4) {
+        // a full pass: lane 16 tt + c encodes query c of tile tt once (all frequencies, by angle
+        // doubling) into LDS, where every lane group picks up its part of the B operands
+        const int q = 16 * s0 + lane;
+        const int e0 = 64 * (lane >> 4) + (lane & 15);   // entry (tile lane / 16, group 0, query lane % 16)
+        wave_sync();   // the previous pass's readers of fa / fb are done
+        dir_features16<PREC>(gs.db[q], gs.db[128 + q], gs.db[256 + q], gs.fa + e0, gs.fb + e0, 16);
+        wave_sync();
+    }
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int Tt = T0 + tt;
         const int qi = 16 * (s0 + tt) + col;
-        const float dx = gs.db[qi], dy = gs.db[128 + qi], dz = gs.db[256 + qi];
         if (Tt == n_cache) {   // residual tile: keep this column's direction for the final combine
-            rdx = dx;
-            rdy = dy;
-            rdz = dz;
+            rdx = gs.db[qi];
+            rdy = gs.db[128 + qi];
+            rdz = gs.db[256 + qi];
         }
         const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(gs.hs + j * W + 16 * mt + 4 * g);
-        direction_operands<PREC>(dx, dy, dz, g, bd[tt][0], bd[tt][1]);
+        if constexpr (T == 4) {
+            const int e = (tt * 4 + g) * 16 + col;
+            const uint2 b = gs.fb[e];
+            bd[tt][0] = gs.fa[e];
+            bd[tt][1] = u32x4{b.x, b.y, 0u, 0u};
+        } else {
+            direction_operands<PREC>(gs.db[qi], gs.db[128 + qi], gs.db[256 + qi], g, bd[tt][0], bd[tt][1]);
+        }
     }
     u32x4 hb[T][KB];
     u32x4 aout[4 * KB];
-    mlp16<W, PREC, T>(h, hb, bd, sD, sH, sOS, lane, aout);
+    if constexpr (lds_weights(W)) {
+        mlp16<W, PREC, T>(h, hb, bd, sD, sH, sOS, lane, aout);
+    } else {   // weights in global memory: keep their loads inside the pass
+        mlp16_wide<W, PREC, T>(h, hb, bd, opaque(sD), opaque(sH), opaque(sOS), lane, aout);
+    }
     const f32x4 z = output16_packed<W, PREC, T>(hb, aout);
 
     // lane (g, col): tile tt = col / 3, channel c = col % 3, queries 4g + i of that tile
@@ -116,12 +143,23 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
         float sum = (e0 + e1) + (e2 + e3);
         sum += __shfl_xor(sum, 16);
         sum += __shfl_xor(sum, 32);
-        // one point per tile; tiles of a pass may share a point, so add tile by tile
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-            if (valid && tt == u && g == 0 && Tt < n_cache) gs.psum[div_n((uint32_t)(16 * Tt), dn) * 4 + c] += sum;
-            wave_sync();
+        // one point per tile, N / 16 consecutive tiles per point.  A pass of T = 2 or 4 tiles
+        // starts at a tile index divisible by T, so its tiles of one point are neighbours in the
+        // pass: fold them into the lane of the run's last tile (tile tt sits 3 columns after tile
+        // tt - 1), which then adds to the point's sum; every storing lane has its own point.
+        bool last = true;
+        if constexpr (T >= 2) {
+            const int tpp = n_cache >> 4;
+            if (tpp >= 2) {
+                sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0x113, 0xF,
+                                                                           0xF, true));   // row_shr:3
+                if (T == 4 && tpp >= 4)
+                    sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0x116,
+                                                                               0xF, 0xF, true));   // row_shr:6
+                last = ((tt + 1) & (min(tpp, T) - 1)) == 0;
+            }
         }
+        if (valid && last && g == 0 && Tt < n_cache) gs.psum[div_n((uint32_t)(16 * Tt), dn) * 4 + c] += sum;
     } else if (n_cache <= 8 && (16 % n_cache) == 0) {
         // every point of a cache tile lies inside the tile: plain stores of complete sums
         if (valid && Tt < n_cache) {
@@ -203,17 +241,25 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db);
         const int tend = min(tb + 8, n_tiles);
         int t = tb;
+        constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
-        for (; t + 4 <= tend; t += 4)
-            tlmc_tiles_h16<W, PREC, 4>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
+        for (; t + TP <= tend; t += TP)
+            tlmc_tiles_h16<W, PREC, TP>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
 #pragma unroll 1
         for (; t < tend; ++t)
             tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
     }
     wave_sync();
+    // residual sample of the field: lane group g evaluates lobe g at its column's point and
+    // residual direction, and the four lobes are summed across the lane groups
+    float Lr[3];
+    field_lobe(lobes, g, xs[0], xs[1], xs[2], rdx, rdy, rdz, Lr);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Lr[c] += __shfl_xor(Lr[c], 16);
+        Lr[c] += __shfl_xor(Lr[c], 32);
+    }
     if (g == 0 && p0 + col < P) {
-        float Lr[3];
-        field_eval(lobes, xs[0], xs[1], xs[2], rdx, rdy, rdz, Lr);
         const float inv_n = 1.0f / (float)n_cache;
         const float *ps = gs.psum + 4 * col, *yr = gs.yres + 4 * col;
         store_estimate(p0 + col, inv_n, ps[0], ps[1], ps[2], Lr[0] - yr[0], Lr[1] - yr[1], Lr[2] - yr[2], out_tl,
@@ -228,6 +274,8 @@ __device__ inline GroupSlab group_slab(float *base, int W) {
     gs.psum = gs.db + 3 * 128;
     gs.yres = gs.psum + 64;
     gs.qbuf = gs.yres + 64;
+    gs.fa = (u32x4 *)(gs.qbuf + 64);
+    gs.fb = (uint2 *)(gs.fa + 4 * 64);
     return gs;
 }
 
@@ -239,18 +287,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
                                                          uint32_t frame, float *__restrict__ out_tl,
                                                          float *__restrict__ out_c, float *__restrict__ out_r) {
     constexpr H16Layout L{W};
-    constexpr int NW = Infer16Lds<W>::kWeights;   // 16-bit elements
-    constexpr int SLAB = TlmcLds<W>::kSlab;         // floats per wave
+    constexpr bool kLds = lds_weights(W);
+    constexpr int NW = kLds ? Infer16Lds<W>::kWeights : 8;   // 16-bit elements
+    constexpr int SLAB = Tlmc16Lds<W>::kSlab;                   // floats per wave
     __shared__ u32x4 wsm[NW / 8];
     __shared__ f32x4 slab4[WAVES * SLAB / 4];
     __shared__ nirc_lobes s_lobes;
     {
         const u32x4 *src = (const u32x4 *)(packed + L.offset(SEC_D));
-        for (int i = threadIdx.x; i < NW / 8; i += WAVES * 64) wsm[i] = src[i];
+        if (kLds)
+            for (int i = threadIdx.x; i < NW / 8; i += WAVES * 64) wsm[i] = src[i];
         if (threadIdx.x == 0) s_lobes = lobes;
     }
     __syncthreads();
-    const uint16_t *sD = (const uint16_t *)wsm;
+    const uint16_t *sD = kLds ? (const uint16_t *)wsm : packed + L.offset(SEC_D);
     const uint16_t *sH = sD + L.size(SEC_D);
     const uint16_t *sOS = sH + 3 * L.size(SEC_H0) + L.size(SEC_O);
     const uint16_t *gS = packed + L.offset(SEC_S);
@@ -271,7 +321,7 @@ template <int W, int PREC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *__restrict__ desc) {
     constexpr H16Layout L{W};
     constexpr int NW = Infer16Lds<W>::kWeights;
-    constexpr int SLAB = TlmcLds<W>::kSlab;
+    constexpr int SLAB = Tlmc16Lds<W>::kSlab;
     __shared__ u32x4 wsm[NW / 8];
     __shared__ f32x4 slab4[WAVES * SLAB / 4];
     __shared__ BatchRequest s_req;
@@ -321,11 +371,16 @@ hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q
     constexpr int WAVES = 4;
     const unsigned grid = grid_for((q.count + 15) / 16, WAVES, 4 * kMaxResidentBlocks);
     const uint16_t *pk = (const uint16_t *)packed;
-    if (W != 64) return hipErrorInvalidValue;
-    if (prec == NIRC_BF16)
+    if (W == 64 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_infer_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
-    else
+    else if (W == 64)
         hipLaunchKernelGGL((k_infer_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+    else if (W == 128 && prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_infer_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+    else if (W == 128)
+        hipLaunchKernelGGL((k_infer_h16<128, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -347,13 +402,21 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
     const uint16_t *pk = (const uint16_t *)packed;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), f = (uint32_t)frame;
-    if (W != 64) return hipErrorInvalidValue;
-    if (prec == NIRC_BF16)
+    const DivN dn = make_divn(n_cache);
+    if (W == 64 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, make_divn(n_cache), k0, k1, f, out_tl, out_c, out_r);
-    else
+                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+    else if (W == 64)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, make_divn(n_cache), k0, k1, f, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+    else if (W == 128 && prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
+                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+    else if (W == 128)
+        hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
+                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -9,6 +9,11 @@ namespace nirc {
 // Upper bound of resident workgroups used for grid-stride launches (256 CUs).
 constexpr int kMaxResidentBlocks = 256;
 
+// Width-64 weights are staged in LDS once per workgroup; width 128 would not leave room for
+// the per-wave slabs (the FP32 hidden layers alone are 192 KB), so those kernels read their
+// weight fragments from global memory (L2-resident) inside each pass.
+__host__ __device__ constexpr bool lds_weights(int W) { return W <= 64; }
+
 template <int W>
 struct InferLds {
     // first-layer direction columns, three hidden layers and the output layer, in packed order
@@ -31,13 +36,16 @@ __device__ inline void wave_sync() {
 
 // Returns p unchanged but opaque to the optimiser, so that weight loads inside a loop are not
 // hoisted out of it (hoisting every fragment load would need hundreds of registers).
+// Only for pointers to global memory: the result is rebuilt in the global address space, so
+// loads through it stay global loads.
 template <typename T>
 __device__ __forceinline__ const T *opaque(const T *p) {
     uint64_t v = (uint64_t)p;
     uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     asm volatile("" : "+s"(lo), "+s"(hi));
-    return (const T *)(((uint64_t)hi << 32) | lo);
+    typedef const T __attribute__((address_space(1))) *global_ptr;
+    return (const T *)(global_ptr)(((uint64_t)hi << 32) | lo);
 }
 
 // h += W1_s e_s for one 16-column tile; the surface features are computed here in B layout.
@@ -362,7 +370,10 @@ struct TrainArgs {
     float loss_eps;
     float loss_scale;
 };
-int train_blocks(int64_t batch);   // workgroups used by the gradient kernel for a batch
+int train_blocks(int64_t batch);     // workgroups used by the FP32 gradient kernel for a batch
+int train_blocks16(int64_t batch);   // workgroups used by the 16-bit gradient kernel
+hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Queries &q, const void *packed,
+                                  TrainArgs a, float *partials, float *loss_partials, int nblocks, hipStream_t s);
 hipError_t launch_grad_partials(int W, const Points &pts, const Queries &q, const float *packed,
                                 TrainArgs a, float *partials, float *loss_partials, int nblocks,
                                 hipStream_t s);

@@ -1,0 +1,332 @@
+// 16-bit training: fused forward + relative-L2 loss + backward to per-workgroup weight-gradient
+// partials with BF16 / FP16 MFMA operands and FP32 accumulation.  Partials use the canonical
+// layout of the FP32 kernel, so the fixed-order reduction and Adam (on the FP32 master weights)
+// are shared.  The per-sample output gradient is not divided by the batch size inside the
+// kernel (the host folds 1/B into the loss scale), which keeps every 16-bit delta near unit
+// magnitude whatever the batch; the reduction divides the scale out again.
+#include "nirc_h16.hpp"
+
+namespace nirc {
+
+namespace {
+
+constexpr int kWaves16 = 4;
+constexpr int kChunk16 = 16 * kWaves16;   // samples per round (two 32-sample K-blocks)
+constexpr int kRow16 = kChunk16 + 8;      // LDS row stride in 16-bit elements (144 B)
+
+template <int W>
+struct Grad16Lds {
+    static constexpr int kH = 4 * W * kRow16;    // h1..h4 (after ReLU)  [layer][neuron][sample]
+    static constexpr int kD = 4 * W * kRow16;    // delta1..delta4       [layer][neuron][sample]
+    static constexpr int kD5 = 4 * kRow16;       // output-layer delta, rows 0..3
+    static constexpr int kE = kFeat * kRow16;    // input features      [canonical feature][sample]
+    static constexpr int kTotal = kH + kD + kD5 + kE;   // 16-bit elements
+};
+
+template <int PREC>
+__device__ __forceinline__ uint16_t to16(float x) {
+    return (uint16_t)(pack2<PREC>(x, 0.0f) & 0xFFFFu);
+}
+
+// Packs two result tiles into a chained B operand without ReLU (backward deltas).
+template <int PREC>
+__device__ __forceinline__ u32x4 chain_plain(const f32x4 &lo, const f32x4 &hi) {
+    return u32x4{pack2<PREC>(lo[0], lo[1]), pack2<PREC>(lo[2], lo[3]), pack2<PREC>(hi[0], hi[1]),
+                 pack2<PREC>(hi[2], hi[3])};
+}
+
+// 16-bit element e of an operand (8 values in 4 dwords).
+__device__ __forceinline__ uint16_t half_of(const u32x4 &v, int e) {
+    return (uint16_t)((v[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+}
+
+// Stores chained activations (B layout, lane (g, col): K position 8g + j of K-block kb is
+// neuron 32 kb + 16 (j / 4) + 4 g + j % 4) as rows [neuron][sample].
+template <int W>
+__device__ __forceinline__ void stage_chain(uint16_t *rows, const u32x4 (&v)[W / 32], int g, int s) {
+#pragma unroll
+    for (int kb = 0; kb < W / 32; ++kb)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rows[chained_neuron16(kb, g, j) * kRow16 + s] = half_of(v[kb], j);
+}
+
+__device__ inline float out_grad16(float z, float t, float dr, bool use_loss, float eps, float k, float &loss_term) {
+    const float y = expf(z);
+    if (use_loss) {
+        const float d = y - t, den = y * y + eps;
+        loss_term = d * d / den;
+        return k * d / den * y;
+    }
+    loss_term = 0.0f;
+    return k * dr * y;
+}
+
+}  // namespace
+
+// One workgroup of 4 waves processes rounds of 64 samples.  Phase 1: each wave takes 16 samples
+// through the 16-bit forward chain (packed weights read from global memory) and back through
+// the transposed sections, and stages the ReLU outputs, the deltas and the input features as
+// 16-bit rows [neuron][sample] in LDS (the ReLU masks come from the 16-bit activations).
+// Phase 2: each wave owns the same weight-gradient tiles as in the FP32 kernel and adds the
+// round with 16x16x32 MFMAs whose K dimension is the sample index.
+template <int W, int PREC>
+__global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries q, const uint16_t *__restrict__ packed,
+                                                            TrainArgs args, float *__restrict__ partials,
+                                                            float *__restrict__ loss_partials) {
+    static_assert(W == 64, "gradient kernel is laid out for width 64");
+    constexpr H16Layout L{W};
+    constexpr int MT = W / 16, KB = W / 32;
+    using S = Grad16Lds<W>;
+    __shared__ u32x4 smem4[(S::kTotal + 7) / 8];
+    __shared__ float sLoss[kWaves16];
+    uint16_t *smem = (uint16_t *)smem4;
+    uint16_t *sH = smem;
+    uint16_t *sD = sH + S::kH;
+    uint16_t *sD5 = sD + S::kD;
+    uint16_t *sE = sD5 + S::kD5;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t B = q.count;
+    const bool use_loss = args.target != nullptr;
+    // the host passes loss_scale * B for 16-bit models: k = 2 loss_scale / 3 per sample
+    const float kscale = use_loss ? 2.0f * args.loss_scale / (3.0f * (float)B) : args.loss_scale;
+
+    f32x4 g1[3][MT], gh[3][MT], g5;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            g1[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            gh[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    g5 = f32x4{0.f, 0.f, 0.f, 0.f};
+    float loss_acc = 0.0f;
+
+    const int64_t n_chunks = (B + kChunk16 - 1) / kChunk16;
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        // ---------------- phase 1: forward + backward of this wave's 16 samples
+        {
+            const uint16_t *pk = opaque(packed);
+            const int s = 16 * wave + col;   // sample slot in the round
+            const int64_t b = chunk * kChunk16 + s;
+            const bool valid = b < B;
+            const int64_t bi = valid ? b : B - 1;
+            const int64_t p = query_point(q, pts, bi);
+            const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+            const float ws[3] = {q.wx[bi], q.wy[bi], q.wz[bi]};
+
+            // input features of frequencies 2g, 2g + 1: (sin, 2 cos) pairs for the MFMAs, and
+            // (sin, cos) rows for the first layer's gradient
+            float f[44];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) enc_pair2_fast(xs[i], g, f[4 * i], f[4 * i + 1], f[4 * i + 2], f[4 * i + 3]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                enc_pair2_fast(ws[i], g, f[28 + 4 * i], f[29 + 4 * i], f[30 + 4 * i], f[31 + 4 * i]);
+#pragma unroll
+            for (int t = 0; t < 28; ++t)
+                sE[feature_of(true, g, t) * kRow16 + s] = to16<PREC>((t & 1) ? 0.5f * f[t] : f[t]);
+#pragma unroll
+            for (int t = 0; t < 12; ++t)
+                sE[feature_of(false, g, t) * kRow16 + s] = to16<PREC>((t & 1) ? 0.5f * f[28 + t] : f[28 + t]);
+
+            // forward
+            u32x4 hb[4][KB];   // h1..h4 after ReLU, as chained B operands
+            {
+                f32x4 h[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const uint16_t *gS = pk + L.offset(SEC_S);
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    const float *fk = f + 8 * kb;
+                    const u32x4 bop = kb < 3 ? u32x4{pack2<PREC>(fk[0], fk[1]), pack2<PREC>(fk[2], fk[3]),
+                                                     pack2<PREC>(fk[4], fk[5]), pack2<PREC>(fk[6], fk[7])}
+                                             : u32x4{pack2<PREC>(fk[0], fk[1]), pack2<PREC>(fk[2], fk[3]), 0u, 0u};
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        h[mt] = mfma16<PREC>(*(const u32x4 *)(gS + ((mt * 4 + kb) * 64 + lane) * 8), bop, h[mt]);
+                }
+                const float *fd = f + 28;
+                const u32x4 bd0 = {pack2<PREC>(fd[0], fd[1]), pack2<PREC>(fd[2], fd[3]), pack2<PREC>(fd[4], fd[5]),
+                                   pack2<PREC>(fd[6], fd[7])};
+                const u32x4 bd1 = {pack2<PREC>(fd[8], fd[9]), pack2<PREC>(fd[10], fd[11]), 0u, 0u};
+                const uint16_t *gD = pk + L.offset(SEC_D);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    h[mt] = mfma16<PREC>(*(const u32x4 *)(gD + ((mt * 2 + 0) * 64 + lane) * 8), bd0, h[mt]);
+                    h[mt] = mfma16<PREC>(*(const u32x4 *)(gD + ((mt * 2 + 1) * 64 + lane) * 8), bd1, h[mt]);
+                }
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) hb[0][kb] = chain_operand<PREC>(h[2 * kb], h[2 * kb + 1]);
+            }
+#pragma unroll
+            for (int l = 1; l < 4; ++l) {
+                const uint16_t *sec = pk + L.offset(SEC_H0 + (l - 1));
+                f32x4 h[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        h[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), hb[l - 1][kb],
+                                             h[mt]);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) hb[l][kb] = chain_operand<PREC>(h[2 * kb], h[2 * kb + 1]);
+            }
+            f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            {
+                const uint16_t *sec = pk + L.offset(SEC_O);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    z5 = mfma16<PREC>(*(const u32x4 *)(sec + (kb * 64 + lane) * 8), hb[3][kb], z5);
+            }
+#pragma unroll
+            for (int l = 0; l < 4; ++l) stage_chain<W>(sH + l * W * kRow16, hb[l], g, s);
+
+            // output delta (rows 0..2 in lanes 0..15)
+            float d5[3] = {0.f, 0.f, 0.f};
+            if (g == 0 && valid) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float t = use_loss ? args.target[3 * b + c] : 0.0f;
+                    const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
+                    float lt;
+                    d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    loss_acc += lt;
+                }
+            }
+            if (g == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sD5[c * kRow16 + s] = to16<PREC>(c < 3 ? d5[c] : 0.0f);
+            }
+
+            // backward: delta4 = (W5^T d5) .* [h4 > 0]; OT holds output o at K position 8g + j
+            // (j < 4, o = 4g + j), so only lane group 0 carries d5 in the B operand
+            f32x4 dl[MT];
+            {
+                const u32x4 bop = g == 0 ? u32x4{pack2<PREC>(d5[0], d5[1]), pack2<PREC>(d5[2], 0.0f), 0u, 0u}
+                                         : u32x4{0u, 0u, 0u, 0u};
+                const uint16_t *sec = pk + L.offset(SEC_OT);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    dl[mt] = mfma16<PREC>(*(const u32x4 *)(sec + (mt * 64 + lane) * 8), bop, f32x4{0.f, 0.f, 0.f, 0.f});
+            }
+#pragma unroll
+            for (int l = 3; l >= 0; --l) {
+                // mask with [h_{l+1} > 0]: result row i of tile mt is chained position
+                // (kb = mt / 2, j = 4 (mt % 2) + i) of hb[l]
+                u32x4 db[KB];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint16_t hv = half_of(hb[l][mt >> 1], 4 * (mt & 1) + i);
+                        if (hv == 0) dl[mt][i] = 0.0f;   // ReLU output is +0 exactly when inactive
+                    }
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) db[kb] = chain_plain<PREC>(dl[2 * kb], dl[2 * kb + 1]);
+                stage_chain<W>(sD + l * W * kRow16, db, g, s);
+                if (l == 0) break;
+                // delta_l = (W_{l+1}^T delta_{l+1}) .* [h_l > 0]
+                const uint16_t *sec = pk + L.offset(SEC_T0 + (l - 1));
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) dl[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        dl[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), db[kb], dl[mt]);
+            }
+        }
+        __syncthreads();
+        // ---------------- phase 2: owned gradient tiles += staged deltas x activations
+        // K position 8g + j of K-block kb <-> sample 32 kb + 8 g + j
+#pragma unroll
+        for (int kb = 0; kb < kChunk16 / 32; ++kb) {
+            const int s0 = 32 * kb + 8 * g;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const u32x4 bv = *(const u32x4 *)(sH + (a * W + 16 * wave + col) * kRow16 + s0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const u32x4 av = *(const u32x4 *)(sD + ((a + 1) * W + 16 * mt + col) * kRow16 + s0);
+                    gh[a][mt] = mfma16<PREC>(av, bv, gh[a][mt]);
+                }
+            }
+            {
+                const u32x4 bv = *(const u32x4 *)(sH + (3 * W + 16 * wave + col) * kRow16 + s0);
+                u32x4 av = u32x4{0u, 0u, 0u, 0u};
+                if (col < 3) av = *(const u32x4 *)(sD5 + col * kRow16 + s0);
+                g5 = mfma16<PREC>(av, bv, g5);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int input = wave + 4 * a;
+                if (input >= kInputs) break;
+                const u32x4 bv = *(const u32x4 *)(sE + (16 * input + col) * kRow16 + s0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const u32x4 av = *(const u32x4 *)(sD + (16 * mt + col) * kRow16 + s0);
+                    g1[a][mt] = mfma16<PREC>(av, bv, g1[a][mt]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---------------- write this workgroup's partial gradient (every entry exactly once)
+    float *out = partials + (int64_t)blockIdx.x * n_params(W);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int input = wave + 4 * a;
+        if (input >= kInputs) break;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[w_offset(W, 0) + (int64_t)(16 * mt + 4 * g + i) * kFeat + 16 * input + col] = g1[a][mt][i];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[w_offset(W, 1 + a) + (int64_t)(16 * mt + 4 * g + i) * W + 16 * wave + col] = gh[a][mt][i];
+    if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[w_offset(W, 4) + (int64_t)i * W + 16 * wave + col] = g5[i];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) loss_acc += __shfl_xor(loss_acc, d, 64);
+    if (lane == 0) sLoss[wave] = loss_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kWaves16; ++w) t += sLoss[w];
+        loss_partials[blockIdx.x] = t;
+    }
+}
+
+int train_blocks16(int64_t batch) {
+    int64_t chunks = (batch + kChunk16 - 1) / kChunk16;
+    if (chunks > kMaxResidentBlocks) chunks = kMaxResidentBlocks;
+    return (int)(chunks < 1 ? 1 : chunks);
+}
+
+hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Queries &q, const void *packed,
+                                  TrainArgs a, float *partials, float *loss_partials, int nblocks, hipStream_t s) {
+    if (W != 64) return hipErrorInvalidValue;
+    const uint16_t *pk = (const uint16_t *)packed;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_grad_h16<64, NIRC_BF16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, pk, a,
+                           partials, loss_partials);
+    else
+        hipLaunchKernelGGL((k_grad_h16<64, NIRC_FP16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, pk, a,
+                           partials, loss_partials);
+    return hipGetLastError();
+}
+
+}  // namespace nirc

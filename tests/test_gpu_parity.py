@@ -184,6 +184,24 @@ def test_loss_grad_matches_oracle(nirc, B):
         assert rel_l2(host(grad)[a:b], o_grad[a:b]) <= 1e-5
 
 
+@pytest.mark.parametrize("B", [1 << 18, 1 << 20])
+def test_loss_grad_large_batches(nirc, B):
+    # the training batches of the differentiation workload: activations are recomputed per
+    # round inside the gradient kernel (nothing per sample is kept in HBM), partial gradients
+    # of at most 256 workgroups are reduced in a fixed order
+    say(f"loss_grad large B={B}")
+    P = 200_000
+    pts, lobes, w0 = scene(31, P)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 32, 0, 0)
+    loss, grad = nirc.nirc_loss_grad(model, dp, q, tgt)
+    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    assert abs(float(loss.item()) - o_loss) <= 1e-5 * abs(o_loss)
+    assert rel_l2(host(grad), o_grad) <= 1e-5
+
+
 def test_backward_is_the_loss_vjp(nirc):
     # d_rgb = dloss/dy (frozen denominator) makes the VJP equal the loss gradient
     say("backward")

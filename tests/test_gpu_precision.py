@@ -14,6 +14,9 @@ from paper_2412_04634_amd import workload as wl
 pytestmark = pytest.mark.gpu
 W = 64
 PRECS = {"bf16": 1, "fp16": 2}
+# gradient tolerance: ten times the unit roundoff of the operand format (BF16 2^-9, FP16
+# 2^-12), for roundings that compound through four forward and four backward layers
+GRAD_TOL = {"bf16": 10 * 2.0 ** -9, "fp16": 10 * 2.0 ** -12}
 
 
 @pytest.fixture(scope="module")
@@ -66,6 +69,29 @@ def test_estimate_16bit(nirc, prec, P, N):
     assert rel_l2(c, o_c) <= 1e-2
     assert rel_l2(tl, o_tl) <= 1e-2
     assert np.linalg.norm(r - o_r) <= 1e-2 * np.linalg.norm(o_c)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("B", [1, 1000, 65536])
+def test_loss_grad_16bit(nirc, prec, B):
+    # 16-bit forward and backward operands (FP32 accumulation, FP32 output gradient) against the
+    # FP64 gradient on the same samples
+    print(f"loss_grad {prec} B={B}", flush=True)
+    P = 3000
+    pts = wl.make_points(35, P)
+    lob = wl.make_lobes(35).packed()
+    w0 = wl.make_weights(35, W)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, cfg=nirc.make_config(precision=PRECS[prec]), max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lob, B, 36, 0, 0)
+    loss, grad = nirc.nirc_loss_grad(model, dp, q, tgt)
+    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    e_loss = abs(float(loss.item()) - o_loss) / abs(o_loss)
+    e_grad = rel_l2(host(grad), o_grad)
+    print(f"  loss rel err {e_loss:.3e}  grad rel-L2 {e_grad:.3e}", flush=True)
+    assert e_loss <= GRAD_TOL[prec]
+    assert e_grad <= GRAD_TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
