@@ -123,16 +123,23 @@ def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, fr
 def precision_form(nirc, w64, dp, lob_packed, table, fs, P, seed, frame, reps=3):
     """The precision matrix: N in {4, 16, 64} x width {64, 128} x {FP32, BF16, FP16} estimates
     of one 1080p frame on identical weights (width 64: the benchmark's trained FP32 cache;
-    width 128: Glorot initial weights, since training runs at width 64 only).  Per entry: time
-    per launch, queries/s, MFMA fraction, MRSE against the exact integral, and rel-L2 of F_tl
-    against the FP32 result on the same weights and directions."""
+    width 128: an FP32 cache trained for 20 frames here).  Per entry: time per launch,
+    queries/s, MFMA fraction, MRSE against the exact integral, and rel-L2 of F_tl against the
+    FP32 result on the same weights and directions."""
     import torch
     from paper_2412_04634_amd import workload as wl
     stream = torch.cuda.current_stream()
     lob = nirc.lobes_struct(lob_packed)
     rows = []
     for W in (64, 128):
-        w = w64 if W == 64 else torch.tensor(wl.make_weights(seed, W), device="cuda")
+        if W == 64:
+            w = w64
+        else:
+            m128 = nirc.Model(wl.make_weights(seed, W), cfg=nirc.make_config(width=W), max_batch=65536)
+            for f in range(20):
+                nirc.nirc_train_frame(m128, dp, lob, 65536, 4, seed, f)
+            w = m128.get_weights()
+            del m128
         for N in (4, 16, 64):
             ref = None
             for name, prec in (("fp32", 0), ("bf16", 1), ("fp16", 2)):
@@ -169,8 +176,22 @@ def serving_run(seconds):
     import torch
     nirc = ex.nirc
     specs = serve.make_stream_specs(5, 16)
+    st["one_frame_per_stream"] = batched_vs_separate(nirc, ex, specs)
+    # small frames (16 streams of 640 x 360, N = 4), where one launch per stream leaves the GPU
+    # partly idle
+    small = [serve.StreamSpec(100 + i, 640, 360, 4, 5000 + i, 5500) for i in range(16)]
+    st["small_frames_16x360p_n4"] = batched_vs_separate(nirc, ex, small)
+    return st
+
+
+def batched_vs_separate(nirc, ex, specs, reps=5):
+    """One frame of each stream: one batched persistent launch against one tlmc_estimate launch
+    per stream (GPU time per round, average of `reps`)."""
+    import torch
+    ex.prepare(specs)
     for s in specs:
-        ex.admit(s)
+        if s.sid not in ex.streams:
+            ex.admit(s)
     reqs = []
     for s in specs:
         x = ex.streams[s.sid]
@@ -184,16 +205,17 @@ def serving_run(seconds):
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     e[0].record()
-    b.launch()
+    for _ in range(reps):
+        b.launch()
     e[1].record()
-    for r in reqs:
-        nirc.tlmc_estimate(r["model"], r["points"], r["lobes"], r["n_cache"], r["seed"], 0, out=r["out_tl"])
+    for _ in range(reps):
+        for r in reqs:
+            nirc.tlmc_estimate(r["model"], r["points"], r["lobes"], r["n_cache"], r["seed"], 0, out=r["out_tl"])
     e[2].record()
     torch.cuda.synchronize()
     q = sum(s.points * (s.n_cache + 1) for s in specs)
-    st["one_frame_per_stream"] = {"queries": q, "batched_ms": e[0].elapsed_time(e[1]),
-                                  "separate_launches_ms": e[1].elapsed_time(e[2])}
-    return st
+    return {"queries": q, "batched_ms": e[0].elapsed_time(e[1]) / reps,
+            "separate_launches_ms": e[1].elapsed_time(e[2]) / reps}
 
 
 def main():
@@ -312,6 +334,13 @@ def main():
     t_stats = [e[1].elapsed_time(e[2]) * 1e-3 for e in evs]
     t_train = [e[2].elapsed_time(e[3]) * 1e-3 for e in evs]
     mrse = [float(s[4].item()) for s in stats]
+    # relative residual variance V_rel(F_r) per frame (mean F_r^2 / (F^2 + eps): the residual's
+    # relative second moment, its variance once the cache integrates to F), smoothed over frames
+    # with an exponential moving average of weight 0.95
+    v_rel_ema = None
+    for st_f in stats:
+        v = float(st_f[6].item())
+        v_rel_ema = v if v_rel_ema is None else 0.95 * v_rel_ema + 0.05 * v
     ms_frame = elapsed / args.steps * 1e3
     queries = P * (N + 1)
     value = queries * args.steps / elapsed
@@ -346,6 +375,7 @@ def main():
         "train_samples_per_s": S * B / (sum(t_train) / len(t_train)),
         "train_tflops": algorithmic_flops_train(B, W) * S / (sum(t_train) / len(t_train)) / 1e12,
         "mrse_first_last": [mrse[0], mrse[-1]],
+        "v_rel_residual_ema": v_rel_ema,
         "final_loss": float(loss.item()),
     }
     if not args.no_precision_compare:

@@ -63,7 +63,7 @@ typedef struct nirc_model nirc_model;   /* opaque host handle */
  * steps per frame (Sec. "Results").  loss_eps is the epsilon of the relative L2 loss (eq. 12).
  * loss_scale multiplies the loss before the backward pass and divides the gradient after it. */
 typedef struct {
-    int32_t width;       /* hidden width: 64 or 128 (training and batching: 64 only) */
+    int32_t width;       /* hidden width: 64 or 128 (the batched estimator: 64 only) */
     int32_t precision;   /* NIRC_FP32 | NIRC_BF16 | NIRC_FP16 */
     float lr;            /* e.g. 1e-3 */
     float beta1;         /* e.g. 0.9 */
@@ -226,8 +226,8 @@ nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field /* host
  * NULL) receives the loss.  Needs the workspace.  Deterministic (fixed reduction order).
  * FP32 models run FP32 MFMA; BF16 / FP16 models run the forward and backward with 16-bit
  * operands and FP32 accumulation, with the output gradient scaled by loss_scale * B before the
- * backward and the gradient unscaled after the reduction.  Width 64 only
- * (NIRC_ERR_UNSUPPORTED otherwise), as for nirc_backward and the training calls below. */
+ * backward and the gradient unscaled after the reduction.  Width 128 sweeps the batch several
+ * times (each sweep owns a disjoint part of the gradient). */
 nirc_status nirc_loss_grad(nirc_model *model, nirc_points points, nirc_queries queries,
                            const float *target, float *grad, float *loss, void *stream);
 

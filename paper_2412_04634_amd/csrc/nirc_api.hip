@@ -267,7 +267,6 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
     if (st == NIRC_OK) st = check_queries(queries, points);
     if (st != NIRC_OK) return st;
     if (queries.count < 1 || !grad) return NIRC_ERR_INVALID_ARG;
-    if (model->W != 64) return NIRC_ERR_UNSUPPORTED;   // the gradient kernels are laid out for width 64
     const bool h16 = model->packed16 != nullptr;
     const int nb = h16 ? train_blocks16(queries.count) : train_blocks(queries.count);
     const WorkLayout wl(model->W, nb);
@@ -313,9 +312,8 @@ nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream) {
     hipError_t e = launch_check_finite(model->W, grad, model->bad, s);
     if (e == hipSuccess)
         e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags, model->bad,
-                        model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps, model->packed, s);
-    if (e == hipSuccess && model->packed16)
-        e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
+                        model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps, model->packed,
+                        model->packed16, model->cfg.precision, s);
     return hip_status(e);
 }
 
@@ -332,9 +330,7 @@ nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries 
     if (st != NIRC_OK) return st;
     hipError_t e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
                                model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps,
-                               model->packed, s);
-    if (e == hipSuccess && model->packed16)
-        e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
+                               model->packed, model->packed16, model->cfg.precision, s);
     return hip_status(e);
 }
 

@@ -172,6 +172,7 @@ __device__ inline void enc_pair(float v, int k, float &s, float &c) {
     sincospif(ldexpf(v, k), &s, &c);
 }
 
+
 // ------------------------------------------------------------------------------------------
 // Packed weights for the FP32 MFMA chain.
 //

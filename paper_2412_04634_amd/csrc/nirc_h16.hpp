@@ -208,21 +208,29 @@ __device__ __forceinline__ void direction_operands(float dx, float dy, float dz,
 // fragments are fetched from LDS while the previous layer's MFMAs drain and its epilogue runs
 // (software prefetch), so LDS latency does not sit between the layers.  `next` receives the
 // output layer's fragments (4 shifted copies x KB) for output16_packed.
-template <int W, int PREC, int T>
-__device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
-                                      const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS, int lane,
-                                      u32x4 (&aout)[4 * (W / 32)]) {
-    constexpr int MT = W / 16, KB = W / 32;
-    static_assert(MT * 2 == MT * KB || KB == 2, "fragment buffer sized for KB = 2");
-    u32x4 a[MT * 2];   // fragments of the layer being computed: [kb][mt]
+// The direction-layer fragments (`dfrag`, [kb][mt], from load_dir_fragments) stay in registers
+// across passes.
+template <int W>
+__device__ __forceinline__ void load_dir_fragments(u32x4 (&dfrag)[W / 8], const uint16_t *sD, int lane) {
+    constexpr int MT = W / 16;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) a[kb * MT + mt] = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
+        for (int mt = 0; mt < MT; ++mt) dfrag[kb * MT + mt] = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
+}
+
+template <int W, int PREC, int T>
+__device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
+                                      const u32x4 (&dfrag)[W / 8], const uint16_t *sH, const uint16_t *sOS, int lane,
+                                      u32x4 (&aout)[4 * (W / 32)]) {
+    constexpr int MT = W / 16, KB = W / 32;
+    static_assert(KB == 2, "fragment buffer sized for KB = 2");
+    u32x4 a[MT * 2];   // fragments of the hidden layer being computed: [kb][mt]
 #pragma unroll
     for (int layer = 0; layer < 4; ++layer) {
         __builtin_amdgcn_sched_barrier(0);
         const u32x4(&bin)[T][2] = layer == 0 ? bd : hb;
+        const u32x4(&af)[MT * 2] = layer == 0 ? dfrag : a;
         if (layer > 0) {
 #pragma unroll
             for (int tt = 0; tt < T; ++tt)
@@ -234,7 +242,7 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a[kb * MT + mt], bin[tt][kb], h[tt][mt]);
+                for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(af[kb * MT + mt], bin[tt][kb], h[tt][mt]);
         // prefetch the next layer's fragments (hidden layer `layer`, or the output copies)
         if (layer < 3) {
             const uint16_t *sec = sH + layer * (MT * KB * 512);

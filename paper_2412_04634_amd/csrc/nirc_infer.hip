@@ -160,8 +160,8 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
         const int Tt = T0 + tt;
         const int qi = 16 * (s0 + tt) + col;
         dx[tt] = db[qi];
-        dy[tt] = db[128 + qi];
-        dz[tt] = db[256 + qi];
+        dy[tt] = db[kDirSlots + qi];
+        dz[tt] = db[2 * kDirSlots + qi];
         const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g);
@@ -222,9 +222,10 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
     }
     float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
-    for (int tb = 0; tb < n_tiles; tb += 8) {
-        gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, db);
-        const int tend = min(tb + 8, n_tiles);
+    for (int tb = 0; tb < n_tiles;) {
+        const bool fold = n_tiles - tb == 9;   // last 8 cache tiles + the residual tile
+        gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, db, fold);
+        const int tend = fold ? n_tiles : min(tb + 8, n_tiles);
         int t = tb;
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
@@ -235,6 +236,7 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         for (; t < tend; ++t)
             tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
                                  fr0, fr1, fr2);
+        tb = tend;
     }
     if (g == 0 && p0 + col < P)
         store_estimate(p0 + col, 1.0f / (float)n_cache, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
     const float *gS = packed + L.offset(SEC_S);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     float *hs = smem + NW + wave * SLAB;   // [16 points][W]
-    float *db = hs + 16 * W;               // directions, SoA [3][128]
+    float *db = hs + 16 * W;               // directions, SoA [3][kDirSlots]
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
         tlmc_group_f32<W>(pts, grp << 4, n_cache, dn, key0, key1, frame, out_tl, out_c, out_r, s_lobes, gS, sD, sH,

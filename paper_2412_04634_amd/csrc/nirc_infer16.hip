@@ -6,13 +6,21 @@
 namespace nirc {
 
 // packed16[e] = 16-bit(master[source(e)]) (round to nearest even), zero padding elsewhere.
+// After an Adam step (step != NULL) thread 0 also commits the step or records its skip.
 template <int PREC>
-__global__ void k_pack16(uint16_t *packed, const float *master, int W, int total) {
+__global__ void k_pack16(uint16_t *packed, const float *master, int W, int total, int64_t *step, uint32_t *flags,
+                         uint32_t *bad) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    const int64_t s = h16_packed_source(W, e);
-    const float v = s >= 0 ? master[s] * h16_packed_scale(W, e) : 0.0f;
-    packed[e] = (uint16_t)(pack2<PREC>(v, 0.0f) & 0xFFFFu);
+    if (e < total) {
+        const int64_t s = h16_packed_source(W, e);
+        const float v = s >= 0 ? master[s] * h16_packed_scale(W, e) : 0.0f;
+        packed[e] = (uint16_t)(pack2<PREC>(v, 0.0f) & 0xFFFFu);
+    }
+    if (step && e == 0) {
+        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        else *step += 1;
+        *bad = 0u;
+    }
 }
 
 template <int W>
@@ -53,8 +61,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
         direction_operands<PREC>(q.wx[qi], q.wy[qi], q.wz[qi], g, bd[0][0], bd[0][1]);
         u32x4 hb[1][KB];
         u32x4 aout[4 * KB];
-        if constexpr (kLds) mlp16<W, PREC, 1>(h, hb, bd, sD, sH, sO + L.size(SEC_O), lane, aout);
-        else mlp16_wide<W, PREC, 1>(h, hb, bd, sD, sH, sO + L.size(SEC_O), lane, aout);
+        if constexpr (kLds) {
+            u32x4 dfrag[W / 8];
+            load_dir_fragments<W>(dfrag, sD, lane);
+            mlp16<W, PREC, 1>(h, hb, bd, dfrag, sH, sO + L.size(SEC_O), lane, aout);
+        } else {
+            mlp16_wide<W, PREC, 1>(h, hb, bd, sD, sH, sO + L.size(SEC_O), lane, aout);
+        }
         // lane (g, c < 3) holds channel c of queries 4g + i of this tile
         const f32x4 z = output16_packed<W, PREC, 1>(hb, aout);
         if (col < 3) {
@@ -70,7 +83,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
 // Per-wave scratch of the estimator's point group (LDS).
 struct GroupSlab {
     float *hs;     // [16 points][W] surface projection
-    float *db;     // [3][128] staged directions
+    float *db;     // [3][kDirSlots] staged directions
     float *psum;   // [16 points][4] cache-level sums
     float *yres;   // [16 points][4] residual-direction predictions
     float *qbuf;   // [16 queries][4] one tile's predictions (general N only)
@@ -90,7 +103,8 @@ struct Tlmc16Lds {
 template <int W, int PREC, int T>
 __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN dn, const GroupSlab &gs,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
-                                               int lane, int g, int col, float &rdx, float &rdy, float &rdz) {
+                                               const u32x4 (&dfrag)[W / 8], int lane, int g, int col, float &rdx,
+                                               float &rdy, float &rdz) {
     constexpr int MT = W / 16, KB = W / 32;
     f32x4 h[T][MT];
     u32x4 bd[T][2];
@@ -99,9 +113,9 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
         // doubling) into LDS, where every lane group picks up its part of the B operands
         const int q = 16 * s0 + lane;
         const int e0 = 64 * (lane >> 4) + (lane & 15);   // entry (tile lane / 16, group 0, query lane % 16)
-        wave_sync();   // the previous pass's readers of fa / fb are done
-        dir_features16<PREC>(gs.db[q], gs.db[128 + q], gs.db[256 + q], gs.fa + e0, gs.fb + e0, 16);
-        wave_sync();
+        wave_lds_order();   // after the previous pass's reads of fa / fb
+        dir_features16<PREC>(gs.db[q], gs.db[kDirSlots + q], gs.db[2 * kDirSlots + q], gs.fa + e0, gs.fb + e0, 16);
+        wave_lds_order();
     }
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
@@ -109,8 +123,8 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
         const int qi = 16 * (s0 + tt) + col;
         if (Tt == n_cache) {   // residual tile: keep this column's direction for the final combine
             rdx = gs.db[qi];
-            rdy = gs.db[128 + qi];
-            rdz = gs.db[256 + qi];
+            rdy = gs.db[kDirSlots + qi];
+            rdz = gs.db[2 * kDirSlots + qi];
         }
         const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
 #pragma unroll
@@ -121,13 +135,14 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
             bd[tt][0] = gs.fa[e];
             bd[tt][1] = u32x4{b.x, b.y, 0u, 0u};
         } else {
-            direction_operands<PREC>(gs.db[qi], gs.db[128 + qi], gs.db[256 + qi], g, bd[tt][0], bd[tt][1]);
+            direction_operands<PREC>(gs.db[qi], gs.db[kDirSlots + qi], gs.db[2 * kDirSlots + qi], g, bd[tt][0],
+                                     bd[tt][1]);
         }
     }
     u32x4 hb[T][KB];
     u32x4 aout[4 * KB];
     if constexpr (lds_weights(W)) {
-        mlp16<W, PREC, T>(h, hb, bd, sD, sH, sOS, lane, aout);
+        mlp16<W, PREC, T>(h, hb, bd, dfrag, sH, sOS, lane, aout);
     } else {   // weights in global memory: keep their loads inside the pass
         mlp16_wide<W, PREC, T>(h, hb, bd, opaque(sD), opaque(sH), opaque(sOS), lane, aout);
     }
@@ -237,17 +252,21 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         wave_sync();
     }
     float rdx = 0.f, rdy = 0.f, rdz = 0.f;
-    for (int tb = 0; tb < n_tiles; tb += 8) {
-        gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db);
-        const int tend = min(tb + 8, n_tiles);
+    u32x4 dfrag[W / 8];   // direction-layer fragments, resident across the group's passes
+    if constexpr (lds_weights(W)) load_dir_fragments<W>(dfrag, sD, lane);
+    for (int tb = 0; tb < n_tiles;) {
+        const bool fold = n_tiles - tb == 9;   // last 8 cache tiles + the residual tile
+        gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db, fold);
+        const int tend = fold ? n_tiles : min(tb + 8, n_tiles);
         int t = tb;
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_h16<W, PREC, TP>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
+            tlmc_tiles_h16<W, PREC, TP>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, lane, g, col, rdx, rdy, rdz);
+            tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz);
+        tb = tend;
     }
     wave_sync();
     // residual sample of the field: lane group g evaluates lobe g at its column's point and
@@ -271,7 +290,7 @@ __device__ inline GroupSlab group_slab(float *base, int W) {
     GroupSlab gs;
     gs.hs = base;
     gs.db = gs.hs + 16 * W;
-    gs.psum = gs.db + 3 * 128;
+    gs.psum = gs.db + 3 * kDirSlots;
     gs.yres = gs.psum + 64;
     gs.qbuf = gs.yres + 64;
     gs.fa = (u32x4 *)(gs.qbuf + 64);
@@ -357,12 +376,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *
 
 // ------------------------------------------------------------------------------------------
 
-hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s) {
+hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s, int64_t *step,
+                         uint32_t *flags, uint32_t *bad) {
     const int total = H16Layout{W}.total();
     if (prec == NIRC_BF16)
-        hipLaunchKernelGGL(k_pack16<NIRC_BF16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total);
+        hipLaunchKernelGGL(k_pack16<NIRC_BF16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
+                           step, flags, bad);
     else
-        hipLaunchKernelGGL(k_pack16<NIRC_FP16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total);
+        hipLaunchKernelGGL(k_pack16<NIRC_FP16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
+                           step, flags, bad);
     return hipGetLastError();
 }
 

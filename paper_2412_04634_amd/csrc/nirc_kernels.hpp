@@ -20,12 +20,24 @@ struct InferLds {
     static constexpr int kWeights = F32Layout{W}.offset(SEC_T0) - F32Layout{W}.offset(SEC_D);
 };
 
+// Staged directions per wave: 8 tiles of 16, plus one more tile when a point group's residual
+// tile is generated together with its last 8 cache tiles (N a multiple of 8).
+constexpr int kDirSlots = 144;
+
 template <int W>
 struct TlmcLds {
     // h_s of 16 points, 128 staged directions, per-point cache sums [16][4], residual
     // predictions [16][4] and a per-tile query buffer [16][4]
-    static constexpr int kSlab = 16 * W + 3 * 128 + 3 * 64;
+    static constexpr int kSlab = 16 * W + 3 * kDirSlots + 3 * 64;
 };
+
+// Orders this wave's LDS traffic for an exchange between its own lanes without waiting for
+// outstanding LDS loads: a wave's LDS instructions execute in issue order, so only the compiler
+// has to be kept from moving the accesses across this point.
+__device__ inline void wave_lds_order() {
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
 
 // Orders this wave's LDS traffic around a point where lanes exchange data through LDS.
 __device__ inline void wave_sync() {
@@ -164,9 +176,12 @@ __device__ __forceinline__ void output_layer(f32x4 (&y)[T], const f32x4 (&h)[T][
 
 // Directions of queries 2 lane and 2 lane + 1 of the 128-query batch starting at tile tb of the
 // point group at p0 (N cache tiles, then one residual tile); one Philox block serves both
-// (two blocks only for odd N).  Written to db as SoA [3][128].
+// (two blocks only for odd N).  With `fold` (the batch holds the group's last 8 cache tiles and
+// the residual tile follows), lanes 0..7 also generate the residual tile into slots 128..143,
+// which saves a batch that would hold one tile.  Written to db as SoA [3][kDirSlots].
 __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, int tb, int n_cache, DivN dn,
-                                               uint32_t key0, uint32_t key1, uint32_t frame, int lane, float *db) {
+                                               uint32_t key0, uint32_t key1, uint32_t frame, int lane, float *db,
+                                               bool fold) {
     const int64_t P = pts.count;
     const int T = tb + (lane >> 3);
     const int c0 = (2 * lane) & 15;
@@ -195,11 +210,27 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
         dir_from_rand(ra, ca.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], wa[0], wa[1], wa[2]);
         dir_from_rand(rb, cb.half, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], wb[0], wb[1], wb[2]);
     }
+    float ra_[3] = {0.f, 0.f, 0.f}, rb_[3] = {0.f, 0.f, 0.f};
+    if (fold && lane < 8) {   // residual directions of points 2 lane, 2 lane + 1 (one Philox block)
+        const int64_t pa = p0 + 2 * lane;
+        const DirCounter c = dir_counter((uint32_t)pa, 0, true);
+        const Rand4 r = philox(c.c0, c.c1, frame, c.stream, key0, key1);
+        const int64_t qa_ = min(pa, P - 1), qb_ = min(pa + 1, P - 1);
+        dir_from_rand(r, 0, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], ra_[0], ra_[1], ra_[2]);
+        dir_from_rand(r, 1, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], rb_[0], rb_[1], rb_[2]);
+    }
     wave_sync();   // the previous batch's readers are done
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        db[128 * d + 2 * lane] = wa[d];
-        db[128 * d + 2 * lane + 1] = wb[d];
+        db[kDirSlots * d + 2 * lane] = wa[d];
+        db[kDirSlots * d + 2 * lane + 1] = wb[d];
+    }
+    if (fold && lane < 8) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            db[kDirSlots * d + 128 + 2 * lane] = ra_[d];
+            db[kDirSlots * d + 128 + 2 * lane + 1] = rb_[d];
+        }
     }
     wave_sync();
 }
@@ -330,7 +361,9 @@ struct BatchDesc {
 // ------------------------------------------------------------------------------------------
 // Launchers (return the launch status).
 hipError_t launch_pack(float *packed, const float *master, int W, hipStream_t s);
-hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s);
+// Packs the 16-bit copy; with step/flags/bad (after Adam) it also commits the step.
+hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s,
+                         int64_t *step = nullptr, uint32_t *flags = nullptr, uint32_t *bad = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_encode(const Points &pts, const Queries &q, float *feat, hipStream_t s);
@@ -381,8 +414,10 @@ hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_pa
                               float inv_scale, float loss_norm, float *grad, float *loss,
                               uint32_t *bad, hipStream_t s);
 hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStream_t s);
+// Adam on the master weights, then the refresh of the copy the kernels read (the FP32 copy for
+// FP32 models, only the 16-bit copy for 16-bit models) and the step commit.
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
-                       float *packed, hipStream_t s);
+                       float *packed, uint16_t *packed16, int prec, hipStream_t s);
 
 }  // namespace nirc

@@ -288,6 +288,298 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Width 128 (FP32).  Neither the weight-gradient tiles (280 of 16 x 16) nor the staged rows of
+// all layers (278 KB) fit one pass, so the batch is swept three times; each sweep recomputes the
+// forward and backward of every sample, stages only the rows its tiles need and owns a disjoint
+// set of tiles (wave w: column tiles 2w, 2w + 1, or inputs w, w + 4, w + 8):
+//   sweep 0: W2, W3    (rows h1, h2, delta2, delta3)
+//   sweep 1: W4, W5    (rows h3, h4, delta4, output delta)
+//   sweep 2: W1 + loss (rows delta1; features recomputed from the staged raw inputs)
+template <int W>
+struct GradWideLds {
+    static constexpr int kRows = 4 * W + 4;                       // largest sweep
+    static constexpr int kTotal = kRows * kStride + kChunk * kInputs;
+};
+
+template <int W, int SWEEP>
+__global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32_wide(Points pts, Queries q,
+                                                                    const float *__restrict__ packed, TrainArgs args,
+                                                                    float *__restrict__ partials,
+                                                                    float *__restrict__ loss_partials) {
+    static_assert(W == 128, "wide gradient kernel");
+    constexpr F32Layout L{W};
+    constexpr int MT = W / 16, KQ = W / 16;
+    using S = GradWideLds<W>;
+    __shared__ f32x4 smem4[(S::kTotal + 3) / 4];
+    __shared__ float sLoss[kTrainWaves];
+    float *smem = (float *)smem4;
+    float *rows = smem;                          // staged rows [row][sample]
+    float *sX = smem + S::kRows * kStride;       // raw inputs [sample][10] (sweep 2)
+    // row bases: sweep 0: h1 0, h2 W, delta2 2W, delta3 3W; sweep 1: h3 0, h4 W, delta4 2W,
+    // d5 3W (4 rows); sweep 2: delta1 0
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t B = q.count;
+    const bool use_loss = args.target != nullptr;
+    const float kscale = use_loss ? 2.0f * args.loss_scale / (3.0f * (float)B) : args.loss_scale;
+
+    constexpr int NACC = SWEEP == 0 ? 2 * 2 * MT : SWEEP == 1 ? 2 * MT + 2 : 3 * MT;
+    f32x4 acc[NACC];
+#pragma unroll
+    for (int i = 0; i < NACC; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float loss_acc = 0.0f;
+
+    const int64_t n_chunks = (B + kChunk - 1) / kChunk;
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        {
+            const float *pk = opaque(packed);
+            const int s = 16 * wave + col;
+            const int64_t b = chunk * kChunk + s;
+            const bool valid = b < B;
+            const int64_t bi = valid ? b : B - 1;
+            const int64_t p = query_point(q, pts, bi);
+            const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+            const float ws[3] = {q.wx[bi], q.wy[bi], q.wz[bi]};
+            if (SWEEP == 2 && g == 0) {
+                float *x = sX + s * kInputs;
+                x[0] = xs[0]; x[1] = xs[1]; x[2] = xs[2];
+                x[3] = ws[0]; x[4] = ws[1]; x[5] = ws[2];
+                x[6] = xs[3]; x[7] = xs[4]; x[8] = xs[5]; x[9] = xs[6];
+            }
+            f32x4 h[4][MT];
+            {
+                f32x4 a1[1][MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) a1[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                layer1_surface<W>(a1[0], pk + L.offset(SEC_S), xs, lane, g);
+                float dx[1] = {ws[0]}, dy[1] = {ws[1]}, dz[1] = {ws[2]};
+                layer1_direction<W, 1>(a1, pk + L.offset(SEC_D), dx, dy, dz, lane, g);
+                relu_all<W, 1>(a1);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[0][mt] = a1[0][mt];
+            }
+#pragma unroll
+            for (int l = 1; l < 4; ++l) {
+                const float *sec = pk + L.offset(SEC_H0 + (l - 1));
+                f32x4 o[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    f32x4 a[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sec + ((mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) o[mt] = mfma4(a[mt][kk], h[l - 1][kq][kk], o[mt]);
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) h[l][mt][i] = fmaxf(o[mt][i], 0.0f);
+            }
+            f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            {
+                const float *sec = pk + L.offset(SEC_O);
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    const f32x4 a = *(const f32x4 *)(sec + (kq * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) z5 = mfma4(a[kk], h[3][kq][kk], z5);
+                }
+            }
+            f32x4 d5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (g == 0 && valid) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float t = use_loss ? args.target[3 * b + c] : 0.0f;
+                    const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
+                    float lt;
+                    d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    loss_acc += lt;
+                }
+            }
+            // stage the activations this sweep needs
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int base = SWEEP == 0 ? (l < 2 ? l * W : -1) : SWEEP == 1 ? (l >= 2 ? (l - 2) * W : -1) : -1;
+                if (base < 0) continue;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) rows[(base + 16 * mt + 4 * g + i) * kStride + s] = h[l][mt][i];
+            }
+            if (SWEEP == 1 && g == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) rows[(3 * W + c) * kStride + s] = d5[c];
+            }
+            // backward: delta4 = (W5^T d5) .* [h4 > 0], then through W4^T, W3^T, W2^T
+            f32x4 d[MT];
+            {
+                const float *sec = pk + L.offset(SEC_OT);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const f32x4 a = *(const f32x4 *)(sec + (mt * 64 + lane) * 4);
+                    f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) o = mfma4(a[kk], d5[kk], o);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) d[mt][i] = h[3][mt][i] > 0.0f ? o[i] : 0.0f;
+                }
+            }
+            if (SWEEP == 1) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) rows[(2 * W + 16 * mt + 4 * g + i) * kStride + s] = d[mt][i];
+            }
+#pragma unroll
+            for (int l = 3; l >= 1; --l) {   // delta_l = (W_{l+1}^T delta_{l+1}) .* [h_l > 0]
+                const float *sec = pk + L.offset(SEC_T0 + (l - 1));
+                f32x4 o[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    f32x4 a[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sec + ((mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) o[mt] = mfma4(a[mt][kk], d[kq][kk], o[mt]);
+                }
+                // delta_l rows: sweep 0 keeps delta2 (l = 2) at 2W and delta3 (l = 3) at 3W; sweep 2
+                // keeps delta1 (l = 1) at 0
+                const int base = SWEEP == 0 ? (l >= 2 ? l * W : -1) : SWEEP == 2 ? (l == 1 ? 0 : -1) : -1;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        d[mt][i] = h[l - 1][mt][i] > 0.0f ? o[mt][i] : 0.0f;
+                        if (base >= 0) rows[(base + 16 * mt + 4 * g + i) * kStride + s] = d[mt][i];
+                    }
+            }
+        }
+        __syncthreads();
+        // phase 2: K position (step kk, lane group g) of sample group sq <-> sample 16 sq + 4 g + kk
+#pragma unroll 1
+        for (int sq = 0; sq < kChunk / 16; ++sq) {
+            const int s0 = 16 * sq + 4 * g;
+            if constexpr (SWEEP == 0) {
+                // W2 = delta2 h1^T (rows 2W, 0), W3 = delta3 h2^T (rows 3W, W)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        const int ct = 2 * wave + cc;
+                        const f32x4 bv = *(const f32x4 *)(rows + (a * W + 16 * ct + col) * kStride + s0);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const f32x4 av = *(const f32x4 *)(rows + ((2 + a) * W + 16 * mt + col) * kStride + s0);
+                            f32x4 &c = acc[(a * 2 + cc) * MT + mt];
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk) c = mfma4(av[kk], bv[kk], c);
+                        }
+                    }
+            } else if constexpr (SWEEP == 1) {
+                // W4 = delta4 h3^T (rows 2W, 0), W5 = d5 h4^T (rows 3W, W)
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const int ct = 2 * wave + cc;
+                    const f32x4 bv = *(const f32x4 *)(rows + (16 * ct + col) * kStride + s0);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const f32x4 av = *(const f32x4 *)(rows + (2 * W + 16 * mt + col) * kStride + s0);
+                        f32x4 &c = acc[cc * MT + mt];
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) c = mfma4(av[kk], bv[kk], c);
+                    }
+                    const f32x4 b4 = *(const f32x4 *)(rows + (W + 16 * ct + col) * kStride + s0);
+                    f32x4 a5 = f32x4{0.f, 0.f, 0.f, 0.f};
+                    if (col < 3) a5 = *(const f32x4 *)(rows + (3 * W + col) * kStride + s0);
+                    f32x4 &c5 = acc[2 * MT + cc];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) c5 = mfma4(a5[kk], b4[kk], c5);
+                }
+            } else {
+                // W1 = delta1 e^T: column tile = input index, features recomputed from raw inputs
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int input = wave + 4 * a;
+                    if (input >= kInputs) break;
+                    const int k = col >> 1, sc = col & 1;
+                    float bv[4];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        float sn, cs;
+                        enc_pair(sX[(s0 + kk) * kInputs + input], k, sn, cs);
+                        bv[kk] = sc ? cs : sn;
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const f32x4 av = *(const f32x4 *)(rows + (16 * mt + col) * kStride + s0);
+                        f32x4 &c = acc[a * MT + mt];
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) c = mfma4(av[kk], bv[kk], c);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    float *out = partials + (int64_t)blockIdx.x * n_params(W);
+    if constexpr (SWEEP == 0) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        out[w_offset(W, 1 + a) + (int64_t)(16 * mt + 4 * g + i) * W + 16 * (2 * wave + cc) + col] =
+                            acc[(a * 2 + cc) * MT + mt][i];
+    } else if constexpr (SWEEP == 1) {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    out[w_offset(W, 3) + (int64_t)(16 * mt + 4 * g + i) * W + 16 * (2 * wave + cc) + col] =
+                        acc[cc * MT + mt][i];
+            if (g == 0) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    out[w_offset(W, 4) + (int64_t)i * W + 16 * (2 * wave + cc) + col] = acc[2 * MT + cc][i];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int input = wave + 4 * a;
+            if (input >= kInputs) break;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    out[w_offset(W, 0) + (int64_t)(16 * mt + 4 * g + i) * kFeat + 16 * input + col] = acc[a * MT + mt][i];
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) loss_acc += __shfl_xor(loss_acc, d, 64);
+        if (lane == 0) sLoss[wave] = loss_acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.0f;
+            for (int w = 0; w < kTrainWaves; ++w) t += sLoss[w];
+            loss_partials[blockIdx.x] = t;
+        }
+    }
+}
+
 // grad[i] = inv_scale * sum_blk partials[blk][i] in a fixed order: a block handles 64 parameters
 // (one per lane); wave w sums the w-th quarter of the partials in order, then the four quarter
 // sums are added in order.  Raises `bad` on a non-finite entry.  Block 0 also reduces the loss.
@@ -301,9 +593,16 @@ __global__ __launch_bounds__(256) void k_reduce_grad(const float *__restrict__ p
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     const int per = (nblocks + 3) / 4;
     const int b0 = wave * per, b1 = min(nblocks, b0 + per);
-    float s = 0.0f;
-    if (i < np)
-        for (int b = b0; b < b1; ++b) s += partials[(int64_t)b * np + i];
+    // eight independent running sums (loads in flight together), combined in a fixed order
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < np) {
+        int b = b0;
+        for (; b + 8 <= b1; b += 8)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += partials[(int64_t)(b + u) * np + i];
+        for (int u = 0; b < b1; ++b, ++u) acc[u] += partials[(int64_t)b * np + i];
+    }
+    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     q[wave][lane] = s;
     __syncthreads();
     if (wave == 0 && i < np) {
@@ -368,6 +667,13 @@ int train_blocks(int64_t batch) {
 hipError_t launch_grad_partials(int W, const Points &pts, const Queries &q, const float *packed,
                                 TrainArgs a, float *partials, float *loss_partials, int nblocks,
                                 hipStream_t s) {
+    if (W == 128) {
+        const dim3 grid(nblocks), block(kTrainWaves * 64);
+        hipLaunchKernelGGL((k_grad_f32_wide<128, 0>), grid, block, 0, s, pts, q, packed, a, partials, loss_partials);
+        hipLaunchKernelGGL((k_grad_f32_wide<128, 1>), grid, block, 0, s, pts, q, packed, a, partials, loss_partials);
+        hipLaunchKernelGGL((k_grad_f32_wide<128, 2>), grid, block, 0, s, pts, q, packed, a, partials, loss_partials);
+        return hipGetLastError();
+    }
     if (W != 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_grad_f32<64>), dim3(nblocks), dim3(kTrainWaves * 64), 0, s, pts, q, packed, a,
                        partials, loss_partials);
@@ -391,12 +697,13 @@ hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStrea
 
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
-                       float *packed, hipStream_t s) {
+                       float *packed, uint16_t *packed16, int prec, hipStream_t s) {
     const int64_t np = n_params(W);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad,
                        step, bad, np, lr, b1, b2, eps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (packed16) return launch_pack16(packed16, master, W, prec, s, step, flags, bad);
     const int total = F32Layout{W}.total();
     hipLaunchKernelGGL(k_pack_commit, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
                        step, flags, bad);

@@ -310,6 +310,274 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries 
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Width 128.  The weight gradient no longer fits in the registers of one workgroup pass (280
+// tiles of 16 x 16), so the batch is swept twice, each sweep owning a disjoint set of tiles and
+// recomputing the forward and backward of every sample:
+//   sweep 0: W2, W3, W4 (wave w owns column tiles 2w, 2w + 1 of each, 48 tiles);
+//   sweep 1: W1 (inputs w, w + 4, w + 8) and W5 (column tiles 2w, 2w + 1), and the loss.
+// Each sweep stages in LDS only the rows its tiles need.  Weights are read from global memory.
+template <int W>
+struct Grad16WideLds {
+    static constexpr int kRows0 = 6 * W;                  // sweep 0: h1..h3, delta2..delta4
+    static constexpr int kRows1 = 2 * W + kFeat + 4;      // sweep 1: h4, delta1, features, d5
+    static constexpr int kTotal = (kRows0 > kRows1 ? kRows0 : kRows1) * kRow16;   // 16-bit elements
+};
+
+template <int W, int PREC, int SWEEP>
+__global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16_wide(Points pts, Queries q,
+                                                                 const uint16_t *__restrict__ packed, TrainArgs args,
+                                                                 float *__restrict__ partials,
+                                                                 float *__restrict__ loss_partials) {
+    static_assert(W == 128, "wide gradient kernel");
+    constexpr H16Layout L{W};
+    constexpr int MT = W / 16, KB = W / 32;
+    using S = Grad16WideLds<W>;
+    __shared__ u32x4 smem4[(S::kTotal + 7) / 8];
+    __shared__ float sLoss[kWaves16];
+    uint16_t *smem = (uint16_t *)smem4;
+    // sweep 0 rows: h1..h3 at 0..3W, delta2..delta4 at 3W..6W
+    // sweep 1 rows: h4 at 0, delta1 at W, features at 2W, d5 at 2W + 160
+    uint16_t *rH = smem;
+    uint16_t *rD = smem + (SWEEP == 0 ? 3 : 1) * W * kRow16;
+    uint16_t *rE = smem + 2 * W * kRow16;
+    uint16_t *rD5 = rE + kFeat * kRow16;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t B = q.count;
+    const bool use_loss = args.target != nullptr;
+    const float kscale = use_loss ? 2.0f * args.loss_scale / (3.0f * (float)B) : args.loss_scale;
+
+    constexpr int NACC = SWEEP == 0 ? 3 * 2 * MT : 3 * MT + 2;
+    f32x4 acc[NACC];
+#pragma unroll
+    for (int i = 0; i < NACC; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float loss_acc = 0.0f;
+
+    const int64_t n_chunks = (B + kChunk16 - 1) / kChunk16;
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        {
+            const uint16_t *pk = opaque(packed);
+            const int s = 16 * wave + col;
+            const int64_t b = chunk * kChunk16 + s;
+            const bool valid = b < B;
+            const int64_t bi = valid ? b : B - 1;
+            const int64_t p = query_point(q, pts, bi);
+            const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+            const float ws[3] = {q.wx[bi], q.wy[bi], q.wz[bi]};
+            float f[44];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) enc_pair2_fast(xs[i], g, f[4 * i], f[4 * i + 1], f[4 * i + 2], f[4 * i + 3]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                enc_pair2_fast(ws[i], g, f[28 + 4 * i], f[29 + 4 * i], f[30 + 4 * i], f[31 + 4 * i]);
+            if constexpr (SWEEP == 1) {
+#pragma unroll
+                for (int t = 0; t < 28; ++t)
+                    rE[feature_of(true, g, t) * kRow16 + s] = to16<PREC>((t & 1) ? 0.5f * f[t] : f[t]);
+#pragma unroll
+                for (int t = 0; t < 12; ++t)
+                    rE[feature_of(false, g, t) * kRow16 + s] = to16<PREC>((t & 1) ? 0.5f * f[28 + t] : f[28 + t]);
+            }
+
+            u32x4 hb[4][KB];
+            {
+                f32x4 h[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const uint16_t *gS = pk + L.offset(SEC_S);
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb) {
+                    const float *fk = f + 8 * kb;
+                    const u32x4 bop = kb < 3 ? u32x4{pack2<PREC>(fk[0], fk[1]), pack2<PREC>(fk[2], fk[3]),
+                                                     pack2<PREC>(fk[4], fk[5]), pack2<PREC>(fk[6], fk[7])}
+                                             : u32x4{pack2<PREC>(fk[0], fk[1]), pack2<PREC>(fk[2], fk[3]), 0u, 0u};
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        h[mt] = mfma16<PREC>(*(const u32x4 *)(gS + ((mt * 4 + kb) * 64 + lane) * 8), bop, h[mt]);
+                }
+                const float *fd = f + 28;
+                const u32x4 bd0 = {pack2<PREC>(fd[0], fd[1]), pack2<PREC>(fd[2], fd[3]), pack2<PREC>(fd[4], fd[5]),
+                                   pack2<PREC>(fd[6], fd[7])};
+                const u32x4 bd1 = {pack2<PREC>(fd[8], fd[9]), pack2<PREC>(fd[10], fd[11]), 0u, 0u};
+                const uint16_t *gD = pk + L.offset(SEC_D);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    h[mt] = mfma16<PREC>(*(const u32x4 *)(gD + ((mt * 2 + 0) * 64 + lane) * 8), bd0, h[mt]);
+                    h[mt] = mfma16<PREC>(*(const u32x4 *)(gD + ((mt * 2 + 1) * 64 + lane) * 8), bd1, h[mt]);
+                }
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) hb[0][kb] = chain_operand<PREC>(h[2 * kb], h[2 * kb + 1]);
+            }
+#pragma unroll
+            for (int l = 1; l < 4; ++l) {
+                const uint16_t *sec = pk + L.offset(SEC_H0 + (l - 1));
+                f32x4 h[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        h[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), hb[l - 1][kb],
+                                             h[mt]);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) hb[l][kb] = chain_operand<PREC>(h[2 * kb], h[2 * kb + 1]);
+            }
+            f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            {
+                const uint16_t *sec = pk + L.offset(SEC_O);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    z5 = mfma16<PREC>(*(const u32x4 *)(sec + (kb * 64 + lane) * 8), hb[3][kb], z5);
+            }
+            if constexpr (SWEEP == 0) {
+#pragma unroll
+                for (int l = 0; l < 3; ++l) stage_chain<W>(rH + l * W * kRow16, hb[l], g, s);
+            } else {
+                stage_chain<W>(rH, hb[3], g, s);
+            }
+
+            float d5[3] = {0.f, 0.f, 0.f};
+            if (g == 0 && valid) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float t = use_loss ? args.target[3 * b + c] : 0.0f;
+                    const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
+                    float lt;
+                    d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    loss_acc += lt;
+                }
+            }
+            if constexpr (SWEEP == 1) {
+                if (g == 0) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) rD5[c * kRow16 + s] = to16<PREC>(c < 3 ? d5[c] : 0.0f);
+                }
+            }
+
+            f32x4 dl[MT];
+            {
+                const u32x4 bop = g == 0 ? u32x4{pack2<PREC>(d5[0], d5[1]), pack2<PREC>(d5[2], 0.0f), 0u, 0u}
+                                         : u32x4{0u, 0u, 0u, 0u};
+                const uint16_t *sec = pk + L.offset(SEC_OT);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    dl[mt] = mfma16<PREC>(*(const u32x4 *)(sec + (mt * 64 + lane) * 8), bop, f32x4{0.f, 0.f, 0.f, 0.f});
+            }
+#pragma unroll
+            for (int l = 3; l >= 0; --l) {
+                u32x4 db[KB];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint16_t hv = half_of(hb[l][mt >> 1], 4 * (mt & 1) + i);
+                        if (hv == 0) dl[mt][i] = 0.0f;
+                    }
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) db[kb] = chain_plain<PREC>(dl[2 * kb], dl[2 * kb + 1]);
+                // delta_{l+1}: sweep 0 keeps delta2..delta4 (l = 1..3), sweep 1 keeps delta1 (l = 0)
+                if constexpr (SWEEP == 0) {
+                    if (l >= 1) stage_chain<W>(rD + (l - 1) * W * kRow16, db, g, s);
+                } else {
+                    if (l == 0) stage_chain<W>(rD, db, g, s);
+                }
+                if (l == 0) break;
+                const uint16_t *sec = pk + L.offset(SEC_T0 + (l - 1));
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) dl[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        dl[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), db[kb], dl[mt]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < kChunk16 / 32; ++kb) {
+            const int s0 = 32 * kb + 8 * g;
+            if constexpr (SWEEP == 0) {
+                // W_{a+2} = delta_{a+2} h_{a+1}^T: A rows of delta (rD slot a), B rows of h (rH slot a)
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        const int ct = 2 * wave + cc;
+                        const u32x4 bv = *(const u32x4 *)(rH + (a * W + 16 * ct + col) * kRow16 + s0);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const u32x4 av = *(const u32x4 *)(rD + (a * W + 16 * mt + col) * kRow16 + s0);
+                            acc[(a * 2 + cc) * MT + mt] = mfma16<PREC>(av, bv, acc[(a * 2 + cc) * MT + mt]);
+                        }
+                    }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int input = wave + 4 * a;
+                    if (input >= kInputs) break;
+                    const u32x4 bv = *(const u32x4 *)(rE + (16 * input + col) * kRow16 + s0);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const u32x4 av = *(const u32x4 *)(rD + (16 * mt + col) * kRow16 + s0);
+                        acc[a * MT + mt] = mfma16<PREC>(av, bv, acc[a * MT + mt]);
+                    }
+                }
+                u32x4 av5 = u32x4{0u, 0u, 0u, 0u};
+                if (col < 3) av5 = *(const u32x4 *)(rD5 + col * kRow16 + s0);
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const u32x4 bv = *(const u32x4 *)(rH + (16 * (2 * wave + cc) + col) * kRow16 + s0);
+                    acc[3 * MT + cc] = mfma16<PREC>(av5, bv, acc[3 * MT + cc]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    float *out = partials + (int64_t)blockIdx.x * n_params(W);
+    if constexpr (SWEEP == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        out[w_offset(W, 1 + a) + (int64_t)(16 * mt + 4 * g + i) * W + 16 * (2 * wave + cc) + col] =
+                            acc[(a * 2 + cc) * MT + mt][i];
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int input = wave + 4 * a;
+            if (input >= kInputs) break;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    out[w_offset(W, 0) + (int64_t)(16 * mt + 4 * g + i) * kFeat + 16 * input + col] = acc[a * MT + mt][i];
+        }
+        if (g == 0) {
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    out[w_offset(W, 4) + (int64_t)i * W + 16 * (2 * wave + cc) + col] = acc[3 * MT + cc][i];
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) loss_acc += __shfl_xor(loss_acc, d, 64);
+        if (lane == 0) sLoss[wave] = loss_acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.0f;
+            for (int w = 0; w < kWaves16; ++w) t += sLoss[w];
+            loss_partials[blockIdx.x] = t;
+        }
+    }
+}
+
 int train_blocks16(int64_t batch) {
     int64_t chunks = (batch + kChunk16 - 1) / kChunk16;
     if (chunks > kMaxResidentBlocks) chunks = kMaxResidentBlocks;
@@ -318,8 +586,23 @@ int train_blocks16(int64_t batch) {
 
 hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Queries &q, const void *packed,
                                   TrainArgs a, float *partials, float *loss_partials, int nblocks, hipStream_t s) {
-    if (W != 64) return hipErrorInvalidValue;
     const uint16_t *pk = (const uint16_t *)packed;
+    if (W == 128) {
+        const dim3 grid(nblocks), block(kWaves16 * 64);
+        if (prec == NIRC_BF16) {
+            hipLaunchKernelGGL((k_grad_h16_wide<128, NIRC_BF16, 0>), grid, block, 0, s, pts, q, pk, a, partials,
+                               loss_partials);
+            hipLaunchKernelGGL((k_grad_h16_wide<128, NIRC_BF16, 1>), grid, block, 0, s, pts, q, pk, a, partials,
+                               loss_partials);
+        } else {
+            hipLaunchKernelGGL((k_grad_h16_wide<128, NIRC_FP16, 0>), grid, block, 0, s, pts, q, pk, a, partials,
+                               loss_partials);
+            hipLaunchKernelGGL((k_grad_h16_wide<128, NIRC_FP16, 1>), grid, block, 0, s, pts, q, pk, a, partials,
+                               loss_partials);
+        }
+        return hipGetLastError();
+    }
+    if (W != 64) return hipErrorInvalidValue;
     if (prec == NIRC_BF16)
         hipLaunchKernelGGL((k_grad_h16<64, NIRC_BF16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, pk, a,
                            partials, loss_partials);

@@ -1,7 +1,7 @@
 """Width-128 caches (the precision form's second width) against the FP64 oracle (needs the GPU).
 
 Same tolerances as at width 64: FP32 rel-L2 <= 1e-5 on the same directions, 16-bit operands
-rel-L2 <= 1e-2.  Training at width 128 is reported as unsupported.
+rel-L2 <= 1e-2, 16-bit gradients ten unit roundoffs.  The batched estimator is width 64 only.
 """
 import numpy as np
 import pytest
@@ -72,12 +72,107 @@ def test_estimate_width128(nirc, prec, P, N):
     assert np.linalg.norm(r - o_r) <= TOL[prec] * np.linalg.norm(o_c)
 
 
-def test_training_width128_unsupported(nirc):
-    P, B = 500, 256
-    pts = wl.make_points(43, P)
-    lob = wl.make_lobes(43).packed()
+# gradients at width 128 (three FP32 / two 16-bit sweeps over the batch): FP32 rel-L2 1e-5 as at
+# width 64; 16-bit ten unit roundoffs.  16-bit gradients are checked on batches of >= 1000: the
+# gradient of a single sample is dominated by any ReLU mask that 16-bit rounding flips (for this
+# seed's single sample a flip in the first hidden layer gives 15 % in W1 and W2; the CPU model of
+# 16-bit rounding in test_precision_model.py gives the same), while over a batch the flipped
+# masks are a small fraction.
+GRAD_TOL = {"fp32": 1e-5, "bf16": 10 * 2.0 ** -9, "fp16": 10 * 2.0 ** -12}
+GRAD_CASES = [("fp32", 1), ("fp32", 1000), ("fp32", 16384), ("bf16", 1000), ("bf16", 16384), ("fp16", 1000),
+              ("fp16", 16384)]
+
+
+@pytest.mark.parametrize("prec,B", GRAD_CASES)
+def test_loss_grad_width128(nirc, prec, B):
+    print(f"loss_grad W=128 {prec} B={B}", flush=True)
+    P = 3000
+    pts = wl.make_points(44, P)
+    lob = wl.make_lobes(44).packed()
+    w0 = wl.make_weights(44, W)
     dp = nirc.Points.from_workload(pts)
-    model = nirc.Model(wl.make_weights(43, W), cfg=nirc.make_config(width=W), max_batch=B)
-    q, tgt = nirc.tlmc_train_batch(dp, lob, B, 1, 0, 0)
+    model = nirc.Model(w0, cfg=nirc.make_config(width=W, precision=PRECS[prec]), max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lob, B, 45, 0, 0)
+    loss, grad = nirc.nirc_loss_grad(model, dp, q, tgt)
+    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
+    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    e_loss = abs(float(loss.item()) - o_loss) / abs(o_loss)
+    e_grad = rel_l2(host(grad), o_grad)
+    print(f"  loss rel err {e_loss:.3e}  grad rel-L2 {e_grad:.3e}", flush=True)
+    assert e_loss <= GRAD_TOL[prec]
+    assert e_grad <= GRAD_TOL[prec]
+    # every layer separately (each sweep owns different layers, so a wrong sweep shows up as an
+    # O(1) error in its layers).  FP32: twice the total bound.  16-bit: 0.1 — the first layer's
+    # gradient sums many cancelling per-sample terms, which magnifies its relative rounding error
+    # (the CPU model of 16-bit rounding gives 3.7e-2 BF16 and 1.4e-2 FP16 there at B = 1000).
+    layer_tol = 2 * GRAD_TOL[prec] if prec == "fp32" else 0.1
+    offs = [0, W * 160, W * 160 + W * W, W * 160 + 2 * W * W, W * 160 + 3 * W * W, o_grad.size]
+    g = host(grad)
+    for a, b in zip(offs[:-1], offs[1:]):
+        assert rel_l2(g[a:b], o_grad[a:b]) <= layer_tol
+
+
+def test_batched_estimate_width128_unsupported(nirc):
+    pts = wl.make_points(48, 100)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(wl.make_weights(48, W), cfg=nirc.make_config(width=W), max_batch=0)
+    out = torch.empty((100, 3), device="cuda")
+    b = nirc.Batch()
     with pytest.raises(nirc.NircError, match="unsupported"):
-        nirc.nirc_train_step(model, dp, q, tgt)
+        b.set([dict(model=model, points=dp, lobes=wl.make_lobes(48).packed(), n_cache=4, seed=1, frame=0,
+                    out_tl=out)])
+
+
+@pytest.fixture(scope="module")
+def oracle_trajectory():
+    """Six frames of four Adam steps at width 128 in FP64 (the oracle's own training samples,
+    which the GPU's tlmc_train_batch reproduces): loss after each frame and final weights.  The
+    loss rises over these first frames (Adam moves every weight by ~lr per step, and 128-wide sums
+    make those moves coherent), so the check is the trajectory itself, not a falling loss."""
+    P, B = 4096, 4096
+    pts = wl.make_points(46, P)
+    lob = wl.make_lobes(46).packed()
+    w = wl.make_weights(46, W).astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    losses, t = [], 0
+    for f in range(6):
+        for s in range(4):
+            idx, d, tg = oracle.train_batch(pts, lob, B, 47, f, s)
+            loss, g = oracle.loss_grad(pts, idx, d, tg, w, W)
+            t += 1
+            oracle.adam(w, m, v, g, t, lr=1e-3)
+        losses.append(loss)
+    return np.array(losses), w
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_train_frames_width128(nirc, prec, oracle_trajectory):
+    # six frames of training at width 128 follow the FP64 trajectory (FP32: loss to 1e-3 and
+    # weights to rel-L2 1e-2 as in the width-64 trajectory test; 16-bit: loss within 10 %), and the
+    # estimate on the trained weights matches the oracle
+    print(f"train W=128 {prec}", flush=True)
+    o_losses, o_w = oracle_trajectory
+    P, B = 4096, 4096
+    pts = wl.make_points(46, P)
+    lob = wl.make_lobes(46).packed()
+    w0 = wl.make_weights(46, W)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, cfg=nirc.make_config(width=W, precision=PRECS[prec]), max_batch=B)
+    loss = torch.zeros(1, device="cuda")
+    losses = []
+    for f in range(6):
+        nirc.nirc_train_frame(model, dp, lob, B, 4, 47, f, loss)
+        losses.append(float(loss.item()))
+    assert model.read_flags() == 0
+    print("  losses", np.round(losses, 4), "oracle", np.round(o_losses, 4), flush=True)
+    w = host(model.get_weights())
+    if prec == "fp32":
+        assert np.max(np.abs(np.array(losses) - o_losses) / o_losses) <= 1e-3
+        assert rel_l2(w - w0, o_w - w0) <= 1e-2
+    else:
+        assert np.max(np.abs(np.array(losses) - o_losses) / o_losses) <= 0.1
+    tl = host(nirc.tlmc_estimate(model, dp, lob, 8, 3, 6))
+    dirs = host(nirc.tlmc_sample_dirs(dp, 8, 3, 6))
+    o_tl, _, _ = oracle.estimate(pts, lob, w, W, 8, 3, 6, dirs=dirs)
+    assert rel_l2(tl, o_tl) <= TOL[prec]
