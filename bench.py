@@ -24,6 +24,10 @@ METRIC = "NIRC queries/s + ms/frame at 1080p N=16; BF16 vs FP32 at equal MRSE"
 PEAK_FP32_MFMA = 157.3e12      # MI355X dense FP32 matrix peak, FLOP/s
 PEAK_BF16_MFMA = 2.5e15        # MI355X dense BF16/FP16 matrix peak, FLOP/s
 PEAK_HBM = 8.0e12              # bytes/s
+# HBM bytes per launch of k_tlmc_f32 in the frame configuration (1080p, N = 16, F_tl + F_c + F_r
+# written), from FETCH_SIZE x 2.0 + WRITE_SIZE (factors from a plain 512 MiB copy); recorded in
+# profiles/k_tlmc_hbm_counters_1080p_n16.md and to be measured again whenever the kernel changes.
+TRAFFIC_K_TLMC_F32 = 134449365
 
 
 def algorithmic_flops_estimate(P: int, N: int, W: int) -> float:
@@ -164,6 +168,39 @@ def precision_form(nirc, w64, dp, lob_packed, table, fs, P, seed, frame, reps=3)
                              "rel_l2_vs_fp32": float((tl - ref).norm() / ref.norm())})
                 del m
     return rows
+
+
+def precision_trained(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S):
+    """Each precision trains its own cache from the same initial weights over the same rotating
+    frames (estimate with W(f), then S Adam steps of B samples): MRSE of the last frame's estimate
+    against the exact integral, and the average estimate / training time per frame."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, prec in (("fp32", 0), ("bf16", 1), ("fp16", 2)):
+        m = nirc.Model(w0, cfg=nirc.make_config(precision=prec), max_batch=B)
+        tl = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(frames)]
+        mrse = None
+        for f in range(frames):
+            lob = nirc.lobes_struct(lobes_for(f))
+            ev[f][0].record(stream)
+            nirc.tlmc_estimate(m, dp, lob, N, seed, f, out=tl)
+            ev[f][1].record(stream)
+            if f == frames - 1:
+                mrse = float(nirc.tlmc_frame_stats(dp, lob, table, tl, fs=fs)[4].item())
+            nirc.nirc_train_frame(m, dp, lob, B, S, seed, f)
+            ev[f][2].record(stream)
+        torch.cuda.synchronize()
+        t_est = sum(e[0].elapsed_time(e[1]) for e in ev[1:]) / (frames - 1)
+        t_all = sum(e[0].elapsed_time(e[2]) for e in ev[1:]) / (frames - 1)
+        out[name] = {"mrse_last_frame": mrse, "ms_estimate": t_est, "ms_estimate_plus_train": t_all}
+        del m
+    for name in ("bf16", "fp16"):
+        out[name]["mrse_rel_diff_vs_fp32"] = (out[name]["mrse_last_frame"] - out["fp32"]["mrse_last_frame"]) / \
+            out["fp32"]["mrse_last_frame"]
+    out["frames"] = frames
+    return out
 
 
 def serving_run(seconds):
@@ -367,7 +404,9 @@ def main():
                    "precision": "fp32"},
         "roofline": {"bound": "mfma", "kernel": "k_tlmc_f32", "achieved": achieved / 1e12,
                      "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
-                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": t_est_avg * 1e3},
+                     "traffic": TRAFFIC_K_TLMC_F32 if cfgw is wl.WORKLOADS["1080p_n16"] else None,
+                     "traffic_unit": "bytes per launch", "flops_per_launch": flops,
+                     "avg_launch_ms": t_est_avg * 1e3},
         "estimate_queries_per_s": queries / t_est_avg,
         "ms_estimate": t_est_avg * 1e3,
         "ms_frame_stats": sum(t_stats) / len(t_stats) * 1e3,
@@ -381,6 +420,7 @@ def main():
     if not args.no_precision_compare:
         result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
                                                         args.warmup + args.steps, args.steps, B, S)
+        result["precision_trained"] = precision_trained(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 20, B, S)
     if args.precision_form:
         result["precision_form"] = precision_form(nirc, model.get_weights(), dp, lobes_for(args.warmup + args.steps),
                                                   table, fs, P, seed, args.warmup + args.steps)

@@ -172,6 +172,23 @@ __device__ inline void enc_pair(float v, int k, float &s, float &c) {
     sincospif(ldexpf(v, k), &s, &c);
 }
 
+// ReLU on the FP32 bits: a signed integer max with 0 maps every negative value (sign bit set)
+// to +0 and leaves the rest unchanged, in one instruction (a float max must first quiet
+// signalling NaNs, which doubles its cost).
+__device__ __forceinline__ float relu_f32(float x) {
+    const int v = __builtin_bit_cast(int, x);
+    return __builtin_bit_cast(float, v > 0 ? v : 0);
+}
+
+// Frequencies k and k + 1: the exact pair at k, then one angle doubling (sin 2a = 2 sin a cos a,
+// cos 2a = (cos a - sin a)(cos a + sin a)), within ~2 ulp of the exact pair at k + 1.
+// Contraction is off so that every kernel that inlines this computes the same bits.
+__device__ inline void enc_pair2(float v, int k, float &s0, float &c0, float &s1, float &c1) {
+#pragma clang fp contract(off)
+    enc_pair(v, k, s0, c0);
+    s1 = 2.0f * (s0 * c0);
+    c1 = (c0 - s0) * (c0 + s0);
+}
 
 // ------------------------------------------------------------------------------------------
 // Packed weights for the FP32 MFMA chain.

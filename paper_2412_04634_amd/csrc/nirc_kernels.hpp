@@ -68,8 +68,7 @@ __device__ __forceinline__ void layer1_surface(f32x4 (&h)[W / 16], const float *
 #pragma unroll
     for (int kq = 0; kq < 7; ++kq) {
         float b[4];
-        enc_pair(xs[kq], 2 * g, b[0], b[1]);
-        enc_pair(xs[kq], 2 * g + 1, b[2], b[3]);
+        enc_pair2(xs[kq], 2 * g, b[0], b[1], b[2], b[3]);
         f32x4 a[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(gS + ((mt * 7 + kq) * 64 + lane) * 4);
@@ -91,8 +90,7 @@ __device__ __forceinline__ void layer1_direction(f32x4 (&h)[T][W / 16], const fl
 #pragma unroll
         for (int tt = 0; tt < T; ++tt) {
             const float v = i == 0 ? dx[tt] : i == 1 ? dy[tt] : dz[tt];
-            enc_pair(v, 2 * g, b[tt][0], b[tt][1]);
-            enc_pair(v, 2 * g + 1, b[tt][2], b[tt][3]);
+            enc_pair2(v, 2 * g, b[tt][0], b[tt][1], b[tt][2], b[tt][3]);
         }
         f32x4 a[MT];
 #pragma unroll
@@ -113,7 +111,7 @@ __device__ __forceinline__ void relu_all(f32x4 (&h)[T][W / 16]) {
 #pragma unroll
         for (int mt = 0; mt < W / 16; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) h[tt][mt][i] = fmaxf(h[tt][mt][i], 0.0f);
+            for (int i = 0; i < 4; ++i) h[tt][mt][i] = relu_f32(h[tt][mt][i]);
 }
 
 // Hidden layers 2..4: K-quad kq of the packed fragments is exactly row tile kq of the previous
@@ -149,7 +147,7 @@ __device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) h[tt][mt][i] = fmaxf(o[tt][mt][i], 0.0f);
+                for (int i = 0; i < 4; ++i) h[tt][mt][i] = relu_f32(o[tt][mt][i]);
     }
 }
 
@@ -210,9 +208,13 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
         dir_from_rand(ra, ca.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], wa[0], wa[1], wa[2]);
         dir_from_rand(rb, cb.half, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], wb[0], wb[1], wb[2]);
     }
+    // residual directions of points 2 rl, 2 rl + 1 (one Philox block): every lane computes the
+    // pair of rl = lane % 8 and all lanes store, so lanes with the same rl write the same values
+    // (no divergent branch: the SIMD pays for the block either way)
     float ra_[3] = {0.f, 0.f, 0.f}, rb_[3] = {0.f, 0.f, 0.f};
-    if (fold && lane < 8) {   // residual directions of points 2 lane, 2 lane + 1 (one Philox block)
-        const int64_t pa = p0 + 2 * lane;
+    const int rl = lane & 7;
+    if (fold) {
+        const int64_t pa = p0 + 2 * rl;
         const DirCounter c = dir_counter((uint32_t)pa, 0, true);
         const Rand4 r = philox(c.c0, c.c1, frame, c.stream, key0, key1);
         const int64_t qa_ = min(pa, P - 1), qb_ = min(pa + 1, P - 1);
@@ -225,11 +227,11 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
         db[kDirSlots * d + 2 * lane] = wa[d];
         db[kDirSlots * d + 2 * lane + 1] = wb[d];
     }
-    if (fold && lane < 8) {
+    if (fold) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            db[kDirSlots * d + 128 + 2 * lane] = ra_[d];
-            db[kDirSlots * d + 128 + 2 * lane + 1] = rb_[d];
+            db[kDirSlots * d + 128 + 2 * rl] = ra_[d];
+            db[kDirSlots * d + 128 + 2 * rl + 1] = rb_[d];
         }
     }
     wave_sync();

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) h[l][mt][i] = fmaxf(o[mt][i], 0.0f);
+                    for (int i = 0; i < 4; ++i) h[l][mt][i] = relu_f32(o[mt][i]);
             }
             f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
             {
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32_wide(Points pts, 
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) h[l][mt][i] = fmaxf(o[mt][i], 0.0f);
+                    for (int i = 0; i < 4; ++i) h[l][mt][i] = relu_f32(o[mt][i]);
             }
             f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
             {
