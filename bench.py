@@ -203,6 +203,39 @@ def precision_trained(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
     return out
 
 
+def train_convergence(nirc, dp, lobes_for, W, seed, frames=300, batches=(1 << 16, 1 << 18, 1 << 20),
+                      precision=0):
+    """The differentiation workload: online training only, 4 Adam steps per frame on the rotating
+    1080p field for each batch size; every 30 frames the cache's relative L2 error against the
+    field on a fixed-size probe of fresh samples of that frame (65,536 queries), and the training
+    throughput."""
+    import torch
+    from paper_2412_04634_amd import workload as wl
+    stream = torch.cuda.current_stream()
+    out = {}
+    for B in batches:
+        m = nirc.Model(wl.make_weights(seed, W), cfg=nirc.make_config(width=W, precision=precision), max_batch=B)
+        curve = []
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        t_train = 0.0
+        for f in range(frames):
+            lob = nirc.lobes_struct(lobes_for(f))
+            if f % 30 == 0 or f == frames - 1:
+                q, tgt = nirc.tlmc_train_batch(dp, lob, 65536, seed + 7919, f, 0)
+                y = nirc.nirc_infer(m, dp, q)
+                curve.append([f, float((y - tgt).norm() / tgt.norm())])
+            ev[0].record(stream)
+            nirc.nirc_train_frame(m, dp, lob, B, 4, seed, f)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            t_train += ev[0].elapsed_time(ev[1]) * 1e-3
+        out[str(B)] = {"cache_rel_l2": curve, "ms_train_frame": t_train / frames * 1e3,
+                       "train_samples_per_s": 4 * B * frames / t_train,
+                       "train_tflops": algorithmic_flops_train(B, W) * 4 * frames / t_train / 1e12}
+        del m
+    return out
+
+
 def serving_run(seconds):
     """16 render streams (resolutions 360p..4K, N in {4, 8, 32}, width-64 BF16 caches with their
     own Adam state), Poisson arrivals at 240 frames/s, HBM-budget admission, continuous batching
@@ -269,6 +302,8 @@ def main():
                     help="duration of the multi-stream serving run (0 to skip)")
     ap.add_argument("--precision-form", action="store_true",
                     help="also run the N x width x precision matrix of estimates")
+    ap.add_argument("--train-convergence", action="store_true",
+                    help="also run 300 frames of training only at batches 2^16, 2^18, 2^20")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="first run a plain device copy of this size (reference for HBM counters)")
     args = ap.parse_args()
@@ -424,6 +459,9 @@ def main():
     if args.precision_form:
         result["precision_form"] = precision_form(nirc, model.get_weights(), dp, lobes_for(args.warmup + args.steps),
                                                   table, fs, P, seed, args.warmup + args.steps)
+    if args.train_convergence:
+        result["train_convergence"] = {p: train_convergence(nirc, dp, lobes_for, W, seed, precision=i)
+                                       for p, i in (("fp32", 0), ("bf16", 1))}
     if args.serve_seconds > 0:
         result["serving"] = serving_run(args.serve_seconds)
     if not args.no_cpu_baseline:

@@ -581,19 +581,21 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32_wide(Points pts, 
 }
 
 // grad[i] = inv_scale * sum_blk partials[blk][i] in a fixed order: a block handles 64 parameters
-// (one per lane); wave w sums the w-th quarter of the partials in order, then the four quarter
-// sums are added in order.  Raises `bad` on a non-finite entry.  Block 0 also reduces the loss.
-__global__ __launch_bounds__(256) void k_reduce_grad(const float *__restrict__ partials,
-                                                     const float *__restrict__ loss_partials, int nblocks,
-                                                     int64_t np, float inv_scale, float loss_norm,
-                                                     float *__restrict__ grad, float *__restrict__ loss,
-                                                     uint32_t *bad) {
-    __shared__ float q[4][64];
+// (one per lane) with 16 waves; wave w sums the w-th sixteenth of the partials with eight running
+// sums, then the sixteen wave sums are added in a fixed tree.  Raises `bad` on a non-finite
+// entry.  Block 0 also reduces the loss.
+constexpr int kReduceWaves = 16;
+
+__global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *__restrict__ partials,
+                                                                   const float *__restrict__ loss_partials,
+                                                                   int nblocks, int64_t np, float inv_scale,
+                                                                   float loss_norm, float *__restrict__ grad,
+                                                                   float *__restrict__ loss, uint32_t *bad) {
+    __shared__ float q[kReduceWaves][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
-    const int per = (nblocks + 3) / 4;
-    const int b0 = wave * per, b1 = min(nblocks, b0 + per);
-    // eight independent running sums (loads in flight together), combined in a fixed order
+    const int per = (nblocks + kReduceWaves - 1) / kReduceWaves;
+    const int b0 = min(nblocks, wave * per), b1 = min(nblocks, b0 + per);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (i < np) {
         int b = b0;
@@ -602,12 +604,14 @@ __global__ __launch_bounds__(256) void k_reduce_grad(const float *__restrict__ p
             for (int u = 0; u < 8; ++u) acc[u] += partials[(int64_t)(b + u) * np + i];
         for (int u = 0; b < b1; ++b, ++u) acc[u] += partials[(int64_t)b * np + i];
     }
-    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    q[wave][lane] = s;
+    q[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
     if (wave == 0 && i < np) {
-        const float t = ((q[0][lane] + q[1][lane]) + q[2][lane]) + q[3][lane];
-        const float gi = t * inv_scale;
+        float t[kReduceWaves / 2];
+#pragma unroll
+        for (int k = 0; k < kReduceWaves / 2; ++k) t[k] = q[2 * k][lane] + q[2 * k + 1][lane];
+        const float sum = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+        const float gi = sum * inv_scale;
         grad[i] = gi;
         if (bad && !isfinite(gi)) atomicOr(bad, 1u);
     }
@@ -684,7 +688,7 @@ hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_pa
                               float inv_scale, float loss_norm, float *grad, float *loss,
                               uint32_t *bad, hipStream_t s) {
     const int64_t np = n_params(W);
-    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 63) / 64)), dim3(256), 0, s, partials,
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 63) / 64)), dim3(kReduceWaves * 64), 0, s, partials,
                        loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad);
     return hipGetLastError();
 }
