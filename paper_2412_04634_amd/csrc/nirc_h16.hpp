@@ -332,19 +332,4 @@ __device__ __forceinline__ f32x4 output16_packed(const u32x4 (&hb)[T][W / 32], c
     return y;
 }
 
-// Output layer: lanes 0..15 receive z = W5 h4 of their column.
-template <int W, int PREC, int T>
-__device__ __forceinline__ void output16(f32x4 (&y)[T], const u32x4 (&hb)[T][W / 32], const uint16_t *sO, int lane) {
-    constexpr int KB = W / 32;
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int tt = 0; tt < T; ++tt) y[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-        const u32x4 a = *(const u32x4 *)(sO + (kb * 64 + lane) * 8);
-#pragma unroll
-        for (int tt = 0; tt < T; ++tt) y[tt] = mfma16<PREC>(a, hb[tt][kb], y[tt]);
-    }
-}
-
 }  // namespace nirc

@@ -229,7 +229,7 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
 // into the slab, then the N + 1 query tiles in passes of 4 (and single-tile remainders), then the
 // per-point combine and store.  Weights for the direction/hidden/output layers are in LDS; the
 // surface columns are read from global memory (gS).
-template <int W, int PREC>
+template <int W, int PREC, int TP = 4>
 __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
                                                uint32_t key1, uint32_t frame, float *out_tl, float *out_c,
                                                float *out_r, const nirc_lobes &lobes, const uint16_t *gS,
@@ -259,7 +259,6 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db, fold);
         const int tend = fold ? n_tiles : min(tb + 8, n_tiles);
         int t = tb;
-        constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
             tlmc_tiles_h16<W, PREC, TP>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz);
@@ -327,8 +326,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
     const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, W);
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_h16<W, PREC>(pts, grp << 4, n_cache, dn, key0, key1, frame, out_tl, out_c, out_r, s_lobes, gS, sD,
-                                sH, sOS, gs, lane, g, col);
+        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2>(pts, grp << 4, n_cache, dn, key0, key1, frame, out_tl,
+                                                                 out_c, out_r, s_lobes, gS, sD, sH, sOS, gs, lane, g,
+                                                                 col);
 }
 
 // Continuous batching: a persistent grid walks a device work list of requests (each with its own
@@ -431,7 +431,17 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
     else if (W == 64)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
                            n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
-    else if (W == 128 && prec == NIRC_BF16)
+    // width 128: from 16 cache queries per point on, one wave per SIMD with 4-tile passes (half the weight
+    // traffic from L2 per tile); below that, two waves per SIMD with 2-tile passes hide the per-point work better
+    else if (W == 128 && n_cache >= 16) {
+        const unsigned g4 = grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks);
+        if (prec == NIRC_BF16)
+            hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
+                               dn, k0, k1, f, out_tl, out_c, out_r);
+        else
+            hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
+                               dn, k0, k1, f, out_tl, out_c, out_r);
+    } else if (W == 128 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
                            n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
     else if (W == 128)
