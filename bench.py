@@ -46,9 +46,10 @@ def algorithmic_flops_train(B: int, W: int) -> float:
     return float(B) * (fwd + dw + delta)
 
 
-def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=15.0):
+def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=12.0, target_1core_s=6.0):
     """The FP64 oracle on a bounded sample of the same frame: a seeded subset of points and a
-    proportional share of the training batch; reported as queries/s of the whole frame."""
+    proportional share of the training batch; reported as queries/s of the whole frame, on all
+    the oracle's threads and on one."""
     import numpy as np
     import oracle
 
@@ -71,13 +72,22 @@ def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=15.0):
             oracle.adam(w, m, v, g, s + 1)
         return time.perf_counter() - t0, b
 
+    threads = oracle.threads()
     t_small, _ = run(512)
     n = int(min(P, max(512, 512 * target_s / max(t_small, 1e-3))))
     t, b = run(n)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(1)
+    try:
+        t1_small, _ = run(64)
+        n1 = int(min(P, max(64, 64 * target_1core_s / max(t1_small, 1e-3))))
+        t1, b1 = run(n1)
+    finally:
+        oracle.set_threads(threads)
     return {"value": n * (N + 1) / t, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} of {P} points (seeded subset) x {N}+1 queries + {steps_per_frame} training "
-                      f"steps of {b} samples (batch scaled by the same fraction); {t:.1f} s"}
+                      f"steps of {b} samples (batch scaled by the same fraction); {t:.1f} s",
+            "one_core": {"value": n1 * (N + 1) / t1, "unit": "queries/s", "cores": 1,
+                         "sample": f"{n1} points, training batch {b1}; {t1:.1f} s"}}
 
 
 def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, frame, reps, B, S):
@@ -291,8 +301,8 @@ def batched_vs_separate(nirc, ex, specs, reps=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="1080p_n16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true")
@@ -405,6 +415,7 @@ def main():
     t_est = [e[0].elapsed_time(e[1]) * 1e-3 for e in evs]
     t_stats = [e[1].elapsed_time(e[2]) * 1e-3 for e in evs]
     t_train = [e[2].elapsed_time(e[3]) * 1e-3 for e in evs]
+    t_frame = np.sort([e[0].elapsed_time(e[3]) for e in evs])
     mrse = [float(s[4].item()) for s in stats]
     # relative residual variance V_rel(F_r) per frame (mean F_r^2 / (F^2 + eps): the residual's
     # relative second moment, its variance once the cache integrates to F), smoothed over frames
@@ -446,6 +457,8 @@ def main():
         "ms_estimate": t_est_avg * 1e3,
         "ms_frame_stats": sum(t_stats) / len(t_stats) * 1e3,
         "ms_train": sum(t_train) / len(t_train) * 1e3,
+        "ms_frame_gpu_p50": float(np.percentile(t_frame, 50)),
+        "ms_frame_gpu_p99": float(np.percentile(t_frame, 99)),
         "train_samples_per_s": S * B / (sum(t_train) / len(t_train)),
         "train_tflops": algorithmic_flops_train(B, W) * S / (sum(t_train) / len(t_train)) / 1e12,
         "mrse_first_last": [mrse[0], mrse[-1]],
@@ -455,7 +468,7 @@ def main():
     if not args.no_precision_compare:
         result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
                                                         args.warmup + args.steps, args.steps, B, S)
-        result["precision_trained"] = precision_trained(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 20, B, S)
+        result["precision_trained"] = precision_trained(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
     if args.precision_form:
         result["precision_form"] = precision_form(nirc, model.get_weights(), dp, lobes_for(args.warmup + args.steps),
                                                   table, fs, P, seed, args.warmup + args.steps)

@@ -20,6 +20,7 @@ _lib = None
 _f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
 _i64 = ctypes.c_int64
 _u64 = ctypes.c_uint64
@@ -48,7 +49,7 @@ def lib():
         L = ctypes.CDLL(path)
         L.oracle_philox.argtypes = [_u32p, _u32p, _u32p]
         L.oracle_philox.restype = None
-        L.oracle_sample_dirs.argtypes = [_i64, _f32p, _f32p, _f32p, _int, _u64, _u64, _f64p]
+        L.oracle_sample_dirs.argtypes = [_i64, _f32p, _f32p, _f32p, _Opt(_i64p), _int, _u64, _u64, _f64p]
         L.oracle_encode.argtypes = [_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p]
         L.oracle_infer.argtypes = [_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _int, _f64p]
         L.oracle_field.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _Opt(_i32p), _f64p, _f64p]
@@ -69,6 +70,10 @@ def lib():
                                          _i32p, _f64p, _f64p])
         L.oracle_n_params.argtypes = [_int]
         L.oracle_n_params.restype = _i64
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = _int
+        L.oracle_set_threads.argtypes = [_int]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -81,6 +86,16 @@ def _w64(w):
     return np.ascontiguousarray(w, dtype=np.float64)
 
 
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count of the oracle's parallel loops (timing only)."""
+    lib().oracle_set_threads(int(n))
+
+
 def n_params(width: int) -> int:
     return int(lib().oracle_n_params(width))
 
@@ -91,11 +106,14 @@ def philox(ctr, key):
     return out
 
 
-def sample_dirs(points, n_cache: int, seed: int, frame: int) -> np.ndarray:
-    """[P, n_cache+1, 3] FP64 directions; the last one of each point is the residual direction."""
+def sample_dirs(points, n_cache: int, seed: int, frame: int, ids=None) -> np.ndarray:
+    """[P, n_cache+1, 3] FP64 directions; the last one of each point is the residual direction.
+    ids: for a subset of a frame's points, the frame index of each (its Philox counter)."""
     P = points.count
     out = np.zeros((P, n_cache + 1, 3), np.float64)
-    lib().oracle_sample_dirs(P, points.nx, points.ny, points.nz, n_cache, seed, frame, out)
+    i64 = None if ids is None else np.ascontiguousarray(ids, np.int64)
+    assert i64 is None or i64.shape == (P,)
+    lib().oracle_sample_dirs(P, points.nx, points.ny, points.nz, i64, n_cache, seed, frame, out)
     return out
 
 

@@ -104,15 +104,18 @@ static void cosine_direction(const double n[3], double u1, double u2, double w[3
     for (int d = 0; d < 3; ++d) w[d] = lx * t[d] + ly * bb[d] + lz * n[d];
 }
 
-void oracle_sample_dirs(int64_t P, const float *nx, const float *ny, const float *nz, int n_cache,
-                        uint64_t seed, uint64_t frame, double *dirs /* [P][n_cache+1][3] */)
+/* ids == NULL: point p of the array is point p of the frame; otherwise the arrays hold a subset
+ * of a frame's points and ids[p] is the frame index of entry p (its Philox counter). */
+void oracle_sample_dirs(int64_t P, const float *nx, const float *ny, const float *nz, const int64_t *ids,
+                        int n_cache, uint64_t seed, uint64_t frame, double *dirs /* [P][n_cache+1][3] */)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < P; ++p) {
         double n[3] = {nx[p], ny[p], nz[p]};
+        const uint32_t id = (uint32_t)(ids ? ids[p] : p);
         for (int k = 0; k <= n_cache; ++k) {
             double u1, u2;
-            direction_uniforms(seed, (uint32_t)p, k, k == n_cache, (uint32_t)frame, &u1, &u2);
+            direction_uniforms(seed, id, k, k == n_cache, (uint32_t)frame, &u1, &u2);
             cosine_direction(n, u1, u2, dirs + ((size_t)p * (n_cache + 1) + k) * 3);
         }
     }
@@ -181,6 +184,25 @@ typedef struct {
 static int64_t n_params_of(int width) { return (int64_t)width * NFEAT + 3LL * width * width + 3LL * width; }
 
 int64_t oracle_n_params(int width) { return n_params_of(width); }
+
+/* Thread control for timing the oracle on one core and on all of them. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 static void net_setup(net_t *net, const double *w, int width)
 {

@@ -88,17 +88,47 @@ __device__ inline Rand4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c
 // 24-bit uniform in [0, 1), exact in FP32.
 __device__ inline float u24(uint32_t r) { return (float)(r >> 8) * 0x1p-24f; }
 
+// sin and cos of 2 pi u for u in [0, 1) with at most 24 fractional bits (a 24-bit uniform).
+// Octant reduction is exact: q = 8u, j = floor(q) and f = q - j carry no rounding, and the
+// octant symmetries map the angle to x = g pi/4 with g = f (even j) or 1 - f (odd j), also
+// exact.  On [0, pi/4] the Taylor series of sin to x^9 and of cos to x^10 truncate below
+// 2e-9, so the pair is within a few ulp; the octant then swaps the two and sets their signs
+// (swap for j = 1, 2, 5, 6; sin < 0 for j >= 4; cos < 0 for j = 2..5).
+__host__ __device__ inline void sincos_turns(float u, float &s, float &c) {
+#pragma clang fp contract(off)
+    const float q = u * 8.0f;
+    const float jf = floorf(q);
+    const int j = (int)jf;
+    const float f = q - jf;
+    const float g = (j & 1) ? 1.0f - f : f;
+    const float x = g * 0.785398163397448309616f;
+    const float x2 = x * x;
+    float sp = fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    sp = fmaf(x2, sp, 1.0f / 120.0f);
+    sp = fmaf(x2, sp, -1.0f / 6.0f);
+    const float sn = fmaf(x * x2, sp, x);
+    float cp = fmaf(x2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    cp = fmaf(x2, cp, -1.0f / 720.0f);
+    cp = fmaf(x2, cp, 1.0f / 24.0f);
+    cp = fmaf(x2, cp, -0.5f);
+    const float cs = fmaf(x2, cp, 1.0f);
+    const bool swap = ((j + 1) >> 1) & 1;
+    const float a = swap ? cs : sn, b = swap ? sn : cs;
+    s = (j >= 4) ? -a : a;
+    c = (((j + 2) >> 2) & 1) ? -b : b;
+}
+
 // Cosine-weighted direction about unit normal n from uniforms (u1, u2): local
 // (sqrt(u1) cos 2pi u2, sqrt(u1) sin 2pi u2, sqrt(1 - u1)) in the branchless orthonormal basis
-// of Duff et al. (JCGT 2017).  The hardware sine/cosine take their argument in revolutions,
-// which is exactly u2; with the hardware square root and reciprocal the direction is within
-// ~1e-6 of the exact map.  Contraction is off so that every kernel that inlines this produces
-// bit-identical directions.
+// of Duff et al. (JCGT 2017).  sin/cos from sincos_turns, square roots and the reciprocal from
+// the hardware instructions (1 ulp): the direction is within a few 1e-7 of the exact map.
+// Contraction is off so that every kernel that inlines this produces bit-identical directions.
 __device__ inline void cosine_dir(float nx, float ny, float nz, float u1, float u2, float &wx,
                                   float &wy, float &wz) {
 #pragma clang fp contract(off)
     const float r = __builtin_amdgcn_sqrtf(u1);
-    const float s2 = __builtin_amdgcn_sinf(u2), c2 = __builtin_amdgcn_cosf(u2);
+    float s2, c2;
+    sincos_turns(u2, s2, c2);
     const float lx = r * c2, ly = r * s2, lz = __builtin_amdgcn_sqrtf(1.0f - u1);
     const float s = nz >= 0.0f ? 1.0f : -1.0f;
     const float a = -__builtin_amdgcn_rcpf(s + nz);   // |s + nz| is in [1, 2]: no range issues

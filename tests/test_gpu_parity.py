@@ -1,13 +1,19 @@
 """Parity of the HIP path with the FP64 oracle on the same seeded inputs (needs the GPU).
 
+Every input of the oracle is its own: the seeded scene, the oracle's own sampled directions and
+training samples (passed to the GPU as FP32 query buffers where a call takes queries).
+
 Tolerances (FP32 arithmetic on the GPU against FP64):
   * Philox words and training point indices: bit-exact;
-  * directions: 2e-6 absolute (FP32 rounding of the sampling map);
+  * directions: DIR_TOL absolute (FP32 rounding of the sampling map, a few ulp);
   * features: 1e-6 absolute;
-  * cache outputs, estimator outputs, loss: relative L2 <= 1e-5 when both sides use the same
-    directions (the GPU's FP32 directions passed to the oracle);
-  * estimator against the oracle's own FP64 directions: relative L2 <= 2e-3, because a
-    direction error of ~3e-7 is amplified by the highest encoding frequency (2^7 pi);
+  * cache outputs and loss on the same queries: relative L2 <= 1e-5;
+  * the fused estimator (directions sampled inside the kernel, against the oracle's FP64
+    directions): F_c relative L2 <= 1e-5, and F_tl, F_r within EST_TOL = 1e-5 of the norm of
+    F_c.  A direction error delta moves the highest-frequency features by 2^7 pi delta and a
+    lobe of sharpness kappa <= 50 by kappa delta; the oracle alone, fed directions perturbed by
+    2e-7, moves F_r by 3.4e-6 of |F_c|, so directions within DIR_TOL = 3e-7 keep F_r and F_tl
+    inside 1e-5 of |F_c| together with the FP32 rounding of the network;
   * gradients: relative L2 <= 1e-5.
 """
 import math
@@ -18,10 +24,13 @@ import torch
 
 import oracle
 from paper_2412_04634_amd import workload as wl
+from tests.common import Samples, host, oracle_dirs32, rel_l2
 
 pytestmark = pytest.mark.gpu
 
 W = 64
+DIR_TOL = 3e-7
+EST_TOL = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -35,16 +44,6 @@ def nirc():
 
 def say(*a):
     print(*a, flush=True)
-
-
-def rel_l2(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
-def host(t):
-    return t.detach().cpu().double().numpy()
 
 
 def scene(seed, P):
@@ -62,25 +61,27 @@ def test_sample_dirs_match_oracle(nirc, P, N):
     seed, frame = 0xDEADBEEF12, 5
     d = host(nirc.tlmc_sample_dirs(dp, N, seed, frame))
     ref = oracle.sample_dirs(pts, N, seed, frame)
-    assert np.abs(d - ref).max() <= 2e-6
+    err = np.abs(d - ref).max()
+    say(f"  max direction error {err:.2e}")
+    assert err <= DIR_TOL
 
 
 def test_encode_matches_oracle(nirc):
     say("encode")
     pts, _, _ = scene(4, 300)
     dp = nirc.Points.from_workload(pts)
-    dirs = nirc.tlmc_sample_dirs(dp, 2, 9, 0)
+    dirs = oracle_dirs32(pts, 2, 9, 0)
     idx = torch.arange(300, device="cuda", dtype=torch.int32).repeat_interleave(3)
-    q = nirc.Queries.from_dirs(dirs, idx)
+    q = nirc.Queries.from_dirs(torch.from_numpy(dirs).cuda(), idx)
     f = host(nirc.nirc_encode(dp, q))
-    ref = oracle.encode(pts, idx.cpu().numpy(), host(dirs).reshape(-1, 3))
+    ref = oracle.encode(pts, idx.cpu().numpy(), dirs.astype(np.float64))
     assert np.abs(f - ref).max() <= 1e-6
     # exact special values: v = 0, 1/2, 1
     sp = wl.Points(*[np.array([0.0, 0.5, 1.0], np.float32) for _ in range(7)])
     spd = nirc.Points.from_workload(sp)
-    dd = torch.tensor([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5], [1.0, 1.0, 1.0]], device="cuda")
-    fe = host(nirc.nirc_encode(spd, nirc.Queries.from_dirs(dd)))
-    fo = oracle.encode(sp, None, host(dd))
+    dd = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.5], [1.0, 1.0, 1.0]], np.float32)
+    fe = host(nirc.nirc_encode(spd, nirc.Queries.from_dirs(torch.from_numpy(dd).cuda())))
+    fo = oracle.encode(sp, None, dd.astype(np.float64))
     assert np.abs(fe - fo).max() <= 1e-7
 
 
@@ -104,32 +105,28 @@ def test_infer_matches_oracle(nirc, Q):
     assert rel_l2(y, ref) <= 1e-5
 
 
-@pytest.mark.parametrize("P,N", [(1, 1), (17, 3), (4096, 8), (1000, 16), (333, 24), (100, 64)])
-def test_estimate_matches_oracle_on_gpu_directions(nirc, P, N):
+def check_estimate(tl, c, r, o_tl, o_c, o_r):
+    e_c = rel_l2(c, o_c)
+    e_tl = np.linalg.norm(tl - o_tl) / np.linalg.norm(o_c)
+    e_r = np.linalg.norm(r - o_r) / np.linalg.norm(o_c)
+    say(f"  F_c rel-L2 {e_c:.2e}; F_tl, F_r error / |F_c| {e_tl:.2e}, {e_r:.2e}")
+    assert e_c <= 1e-5
+    assert e_tl <= EST_TOL
+    # F_r = L - y can cancel: its error is bounded relative to the cache prediction's scale
+    assert e_r <= EST_TOL
+
+
+@pytest.mark.parametrize("P,N", [(1, 1), (17, 3), (2048, 8), (4096, 8), (1000, 16), (333, 24), (100, 64)])
+def test_estimate_matches_oracle(nirc, P, N):
     say(f"estimate P={P} N={N}")
     pts, lobes, w0 = scene(6, P)
     dp = nirc.Points.from_workload(pts)
     model = nirc.Model(w0, max_batch=0)
     seed, frame = 77, 2
     tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lobes, N, seed, frame, parts=True))
-    dirs = host(nirc.tlmc_sample_dirs(dp, N, seed, frame))
-    o_tl, o_c, o_r = oracle.estimate(pts, lobes, w0, W, N, seed, frame, dirs=dirs)
-    assert rel_l2(c, o_c) <= 1e-5
-    assert rel_l2(tl, o_tl) <= 1e-5
-    # F_r = L - y can cancel: bound its error relative to the cache prediction's scale
-    assert np.linalg.norm(r - o_r) <= 1e-5 * np.linalg.norm(o_c)
+    o_tl, o_c, o_r = oracle.estimate(pts, lobes, w0, W, N, seed, frame)
+    check_estimate(tl, c, r, o_tl, o_c, o_r)
     np.testing.assert_array_equal(tl, host(nirc.tlmc_estimate(model, dp, lobes, N, seed, frame)))
-
-
-def test_estimate_matches_oracle_own_directions(nirc):
-    say("estimate vs oracle-sampled directions")
-    P, N = 2048, 8
-    pts, lobes, w0 = scene(7, P)
-    dp = nirc.Points.from_workload(pts)
-    model = nirc.Model(w0, max_batch=0)
-    tl = host(nirc.tlmc_estimate(model, dp, lobes, N, 5, 1))
-    o_tl, _, _ = oracle.estimate(pts, lobes, w0, W, N, 5, 1)
-    assert rel_l2(tl, o_tl) <= 2e-3
 
 
 def test_estimate_zero_output_layer_and_empty(nirc):
@@ -142,9 +139,9 @@ def test_estimate_zero_output_layer_and_empty(nirc):
     model = nirc.Model(w, max_batch=0)
     tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lobes, N, 3, 0, parts=True))
     assert np.all(c == 1.0)
-    dirs = host(nirc.tlmc_sample_dirs(dp, N, 3, 0))[:, N, :]
-    L = oracle.field(lobes, pts, None, dirs)
-    assert rel_l2(tl, L) <= 1e-5
+    # y = 1 everywhere, so F_tl = L(x, w_r): the field at the oracle's residual directions
+    L = oracle.field(lobes, pts, None, oracle.sample_dirs(pts, N, 3, 0)[:, N, :])
+    assert np.linalg.norm(tl - L) <= EST_TOL * np.linalg.norm(c)
     empty = nirc.Points([torch.zeros(0, device="cuda") for _ in range(7)])
     out = nirc.tlmc_estimate(model, empty, lobes, N, 3, 0)
     assert out.shape == (0, 3)
@@ -159,10 +156,11 @@ def test_train_batch_matches_oracle(nirc):
     idx, d, t = oracle.train_batch(pts, lobes, B, 11, 4, 3)
     np.testing.assert_array_equal(q.point.cpu().numpy(), idx)
     gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
-    assert np.abs(gd - d).max() <= 2e-6
-    # targets on the GPU's directions
-    t_same = oracle.field(lobes, pts, idx, gd)
-    assert rel_l2(host(tgt), t_same) <= 1e-5
+    assert np.abs(gd - d).max() <= DIR_TOL
+    # targets: the field at directions within DIR_TOL, lobes of sharpness <= 50
+    e_t = rel_l2(host(tgt), t)
+    say(f"  target rel-L2 {e_t:.2e}")
+    assert e_t <= EST_TOL
 
 
 @pytest.mark.parametrize("B", [1, 65, 1000, 4096])
@@ -172,10 +170,9 @@ def test_loss_grad_matches_oracle(nirc, B):
     pts, lobes, w0 = scene(10, P)
     dp = nirc.Points.from_workload(pts)
     model = nirc.Model(w0, max_batch=4096)
-    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 12, 0, 0)
-    loss, grad = nirc.nirc_loss_grad(model, dp, q, tgt)
-    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
-    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    sm = Samples(pts, lobes, B, 12, 0, 0)
+    loss, grad = nirc.nirc_loss_grad(model, dp, sm.queries(nirc), sm.target())
+    o_loss, o_grad = sm.loss_grad(pts, w0, W)
     assert abs(float(loss.item()) - o_loss) <= 1e-5 * abs(o_loss)
     assert rel_l2(host(grad), o_grad) <= 1e-5
     # every layer separately
@@ -194,10 +191,9 @@ def test_loss_grad_large_batches(nirc, B):
     pts, lobes, w0 = scene(31, P)
     dp = nirc.Points.from_workload(pts)
     model = nirc.Model(w0, max_batch=B)
-    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 32, 0, 0)
-    loss, grad = nirc.nirc_loss_grad(model, dp, q, tgt)
-    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
-    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    sm = Samples(pts, lobes, B, 32, 0, 0)
+    loss, grad = nirc.nirc_loss_grad(model, dp, sm.queries(nirc), sm.target())
+    o_loss, o_grad = sm.loss_grad(pts, w0, W)
     assert abs(float(loss.item()) - o_loss) <= 1e-5 * abs(o_loss)
     assert rel_l2(host(grad), o_grad) <= 1e-5
 
@@ -209,14 +205,12 @@ def test_backward_is_the_loss_vjp(nirc):
     pts, lobes, w0 = scene(13, P)
     dp = nirc.Points.from_workload(pts)
     model = nirc.Model(w0, max_batch=B)
-    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 14, 0, 0)
-    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
-    idx = q.point.cpu().numpy()
-    y = oracle.infer(pts, idx, gd, w0, W)
-    t = host(tgt)
-    dy = 2.0 * (y - t) / (y * y + 1e-2) / (3.0 * B)
-    g = host(nirc.nirc_backward(model, dp, q, torch.tensor(dy, dtype=torch.float32, device="cuda")))
-    _, o_grad = oracle.loss_grad(pts, idx, gd, t, w0, W)
+    sm = Samples(pts, lobes, B, 14, 0, 0)
+    y = oracle.infer(pts, sm.idx, sm.d, w0, W)
+    dy = (2.0 * (y - sm.t) / (y * y + 1e-2) / (3.0 * B)).astype(np.float32)
+    g = host(nirc.nirc_backward(model, dp, sm.queries(nirc), torch.from_numpy(dy).cuda()))
+    # the oracle's VJP with the same FP32 output gradient equals its loss gradient to 1e-7
+    _, o_grad = sm.loss_grad(pts, w0, W)
     assert rel_l2(g, o_grad) <= 1e-5
 
 
@@ -226,13 +220,12 @@ def test_train_step_single_step_parity(nirc):
     pts, lobes, w0 = scene(15, P)
     dp = nirc.Points.from_workload(pts)
     model = nirc.Model(w0, max_batch=B)
-    q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 16, 0, 0)
+    sm = Samples(pts, lobes, B, 16, 0, 0)
     loss = torch.zeros(1, device="cuda")
-    nirc.nirc_train_step(model, dp, q, tgt, loss)
+    nirc.nirc_train_step(model, dp, sm.queries(nirc), sm.target(), loss)
     w1 = host(model.get_weights())
     m, v, step = model.get_adam()
-    gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
-    o_loss, o_grad = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), w0, W)
+    o_loss, o_grad = sm.loss_grad(pts, w0, W)
     ow = w0.astype(np.float64).copy()
     om = np.zeros_like(ow)
     ov = np.zeros_like(ow)
@@ -260,10 +253,9 @@ def test_train_steps_follow_oracle(nirc):
     t = 0
     for f in range(3):
         for s in range(4):
-            q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 18, f, s)
-            nirc.nirc_train_step(model, dp, q, tgt)
-            gd = np.stack([host(q.wx), host(q.wy), host(q.wz)], 1)
-            _, g = oracle.loss_grad(pts, q.point.cpu().numpy(), gd, host(tgt), ow, W)
+            sm = Samples(pts, lobes, B, 18, f, s)
+            nirc.nirc_train_step(model, dp, sm.queries(nirc), sm.target())
+            _, g = sm.loss_grad(pts, ow, W)
             t += 1
             oracle.adam(ow, om, ov, g, t, lr=1e-3)
     w = host(model.get_weights())
@@ -374,11 +366,12 @@ def test_full_1080p_sampled_points(nirc):
     pts, lobes, w0 = scene(2, P)
     dp = nirc.Points.from_workload(pts)
     model = nirc.Model(w0, max_batch=0)
-    tl = nirc.tlmc_estimate(model, dp, lobes, N, 2, 0)
-    dirs = nirc.tlmc_sample_dirs(dp, N, 2, 0)
+    tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lobes, N, 2, 0, parts=True))
     rng = np.random.default_rng(0)
     sel = np.unique(np.concatenate([rng.choice(P, 3000, replace=False), np.arange(P - 40, P), np.arange(40)]))
     sub = pts.subset(sel)
-    o_tl, _, _ = oracle.estimate(sub, lobes, w0, W, N, 2, 0, dirs=host(dirs[torch.tensor(sel, device="cuda")]))
-    assert rel_l2(host(tl)[sel], o_tl) <= 1e-5
-    assert np.isfinite(host(tl)).all()
+    # the oracle samples the directions of the selected points by their frame indices
+    dirs = oracle.sample_dirs(sub, N, 2, 0, ids=sel)
+    o_tl, o_c, o_r = oracle.estimate(sub, lobes, w0, W, N, 2, 0, dirs=dirs)
+    check_estimate(tl[sel], c[sel], r[sel], o_tl, o_c, o_r)
+    assert np.isfinite(tl).all()

@@ -65,15 +65,16 @@ def test_frame_stats_mrse(nirc):
     lob = wl.make_lobes(5).packed()
     w0 = wl.make_weights(5, W)
     dp = nirc.Points.from_workload(pts)
-    model = nirc.Model(w0, max_batch=0)
-    tl, c, r = nirc.tlmc_estimate(model, dp, lob, N, 1, 0, parts=True)
+    # estimates from the oracle, in FP32 as the statistics take them
+    o_tl, o_c, o_r = (a.astype(np.float32) for a in oracle.estimate(pts, lob, w0, W, N, 1, 0))
+    tl, c, r = (torch.from_numpy(a).cuda() for a in (o_tl, o_c, o_r))
     table = nirc.tlmc_reference_table(lob)
     st = host(nirc.tlmc_frame_stats(dp, lob, table, tl, c, r))
     F = oracle.closed_form(pts, lob)
     assert st[3] == 3 * P
-    assert st[4] == pytest.approx(oracle.mrse(host(tl), F), rel=1e-9)
-    assert st[5] == pytest.approx(oracle.mrse(host(c), F), rel=1e-9)
-    assert st[6] == pytest.approx(float(np.mean(host(r) ** 2 / (F * F + 1e-2))), rel=1e-9)
+    assert st[4] == pytest.approx(oracle.mrse(o_tl.astype(np.float64), F), rel=1e-9)
+    assert st[5] == pytest.approx(oracle.mrse(o_c.astype(np.float64), F), rel=1e-9)
+    assert st[6] == pytest.approx(float(np.mean(o_r.astype(np.float64) ** 2 / (F * F + 1e-2))), rel=1e-9)
     st2 = host(nirc.tlmc_frame_stats(dp, lob, table, tl))
     assert st2[1] == 0.0 and st2[2] == 0.0 and st2[4] == st[4]
 
