@@ -386,7 +386,7 @@ def main():
         lob = nirc.lobes_struct(lobes_for(f))
         if ev is not None:
             ev[0].record(stream)
-        nirc._check(nirc.lib().tlmc_estimate(model.handle, dp.c(), nirc.ctypes.byref(lob), N, seed, f,
+        nirc._check(nirc.lib().tlmc_estimate(model.handle, dp.c(), nirc.ctypes.byref(lob), N, seed, f, None,
                                              nirc._ptr(out_tl), nirc._ptr(out_c), nirc._ptr(out_r), nirc._stream()),
                     "tlmc_estimate")
         if ev is not None:

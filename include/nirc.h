@@ -134,6 +134,15 @@ nirc_status nirc_get_weights(const nirc_model *model, float *w, void *stream);
  * (device int64, may be NULL). */
 nirc_status nirc_get_adam(const nirc_model *model, float *m, float *v, int64_t *step, void *stream);
 
+/* The whole training state (FP32 weights, Adam moments and step, packed copies, flags) as one
+ * device blob of nirc_state_bytes(cfg) bytes, for checkpoint and resume.  nirc_set_state takes
+ * a blob written by nirc_get_state of a model of the same width (blob_bytes must equal this
+ * model's state size) and re-derives the packed copies from its FP32 weights, so a resumed
+ * model continues exactly as the saved one would have.  Both only enqueue device copies on
+ * `stream`; the blob belongs to the caller. */
+nirc_status nirc_get_state(const nirc_model *model, void *blob, size_t blob_bytes, void *stream);
+nirc_status nirc_set_state(nirc_model *model, const void *blob, size_t blob_bytes, void *stream);
+
 /* Sticky device flags (NIRC_FLAG_*).  Reads them synchronously on `stream` (host call that
  * waits for the stream); returns 0xFFFFFFFF on error. */
 uint32_t nirc_read_flags(const nirc_model *model, void *stream);
@@ -165,23 +174,28 @@ nirc_status tlmc_sample_dirs(nirc_points points, int32_t n_cache, uint64_t seed,
 
 /* The two-level estimator per shading point and channel (eq. L_mlmc, L_c, L_r):
  *   out_c  = (1/N) sum_k n(x, w_k)         (cache level, N = n_cache >= 1)
- *   out_r  = L(x, w_r) - n(x, w_r)          (residual; L from `field`)
+ *   out_r  = L(x, w_r) - n(x, w_r)          (residual)
  *   out_tl = out_c + out_r
  * Directions are generated in the kernel exactly as tlmc_sample_dirs returns them.  The
  * surface part of the first layer is computed once per point and shared by its N + 1 queries
- * (Sec. "Neural Network Architecture": amortised surface encoding).  out_c and out_r may be
- * NULL.  All outputs are [points.count][3] FP32. */
+ * (Sec. "Neural Network Architecture": amortised surface encoding).
+ * L(x, w_r) is the residual sample's radiance (Sec. "Cache application": one path-traced
+ * sample per shading point): residual_radiance ([points.count][3] FP32) when given — a
+ * renderer traces the residual directions tlmc_sample_dirs returns (entry n_cache of each
+ * point) and passes what it found — otherwise the synthetic lobe field `field` evaluated in the
+ * kernel (then `field` may be NULL).  out_c and out_r may be NULL.  All outputs are [points.count][3] FP32. */
 nirc_status tlmc_estimate(const nirc_model *model, nirc_points points,
                           const nirc_lobes *field /* host */, int32_t n_cache, uint64_t seed,
-                          uint64_t frame, float *out_tl, float *out_c, float *out_r, void *stream);
+                          uint64_t frame, const float *residual_radiance /* nullable */,
+                          float *out_tl, float *out_c, float *out_r, void *stream);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Continuous batching of estimates (several render streams, each with its own cache)         */
 
 #define TLMC_BATCH_MAX_REQUESTS 64
 
-/* One frame of one render stream: its model, points, field, sample count, seed and frame, and
- * where the results go (as for tlmc_estimate).  Host struct. */
+/* One frame of one render stream: its model, points, field or residual radiance, sample count,
+ * seed and frame, and where the results go (as for tlmc_estimate).  Host struct. */
 typedef struct {
     const nirc_model *model;
     nirc_points points;
@@ -189,6 +203,7 @@ typedef struct {
     int32_t n_cache;
     uint64_t seed;
     uint64_t frame;
+    const float *residual_radiance;   /* NULL: the field */
     float *out_tl, *out_c, *out_r;
 } tlmc_request;
 

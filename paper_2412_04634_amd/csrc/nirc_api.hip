@@ -183,6 +183,27 @@ nirc_status nirc_get_weights(const nirc_model *model, float *w, void *stream) {
     return hip_status(launch_copy_f32(w, model->master, model->np, (hipStream_t)stream));
 }
 
+// The state is one region from the FP32 weights on (StateLayout); a blob is its image.
+nirc_status nirc_get_state(const nirc_model *model, void *blob, size_t blob_bytes, void *stream) {
+    if (!model || !blob || ((uintptr_t)blob % 4) != 0) return NIRC_ERR_INVALID_ARG;
+    const size_t bytes = StateLayout(model->W, model->cfg.precision).total;
+    if (blob_bytes != bytes) return NIRC_ERR_INVALID_ARG;
+    return hip_status(launch_copy_f32((float *)blob, model->master, (int64_t)(bytes / 4), (hipStream_t)stream));
+}
+
+nirc_status nirc_set_state(nirc_model *model, const void *blob, size_t blob_bytes, void *stream) {
+    if (!model || !blob || ((uintptr_t)blob % 4) != 0) return NIRC_ERR_INVALID_ARG;
+    const size_t bytes = StateLayout(model->W, model->cfg.precision).total;
+    if (blob_bytes != bytes) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_copy_f32(model->master, (const float *)blob, (int64_t)(bytes / 4), s);
+    // the packed copies follow the restored FP32 weights whatever precision wrote the blob
+    if (e == hipSuccess) e = launch_pack(model->packed, model->master, model->W, s);
+    if (e == hipSuccess && model->packed16)
+        e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
+    return hip_status(e);
+}
+
 nirc_status nirc_get_adam(const nirc_model *model, float *m, float *v, int64_t *step, void *stream) {
     if (!model) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
@@ -236,15 +257,18 @@ nirc_status tlmc_sample_dirs(nirc_points points, int32_t n_cache, uint64_t seed,
 }
 
 nirc_status tlmc_estimate(const nirc_model *model, nirc_points points, const nirc_lobes *field,
-                          int32_t n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
-                          float *out_r, void *stream) {
-    if (!model || !field) return NIRC_ERR_INVALID_ARG;
+                          int32_t n_cache, uint64_t seed, uint64_t frame, const float *residual_radiance,
+                          float *out_tl, float *out_c, float *out_r, void *stream) {
+    if (!model || (!field && !residual_radiance)) return NIRC_ERR_INVALID_ARG;
     nirc_status st = check_points(points);
     if (st != NIRC_OK) return st;
     if (n_cache < 1 || n_cache > 4096 || (points.count > 0 && !out_tl)) return NIRC_ERR_INVALID_ARG;
     const void *pk = model->packed16 ? (const void *)model->packed16 : (const void *)model->packed;
-    return hip_status(launch_tlmc(model->W, model->cfg.precision, to_points(points), *field, pk, n_cache, seed,
-                                  frame, out_tl, out_c, out_r, (hipStream_t)stream));
+    nirc_lobes none;
+    memset(&none, 0, sizeof(none));
+    return hip_status(launch_tlmc(model->W, model->cfg.precision, to_points(points), field ? *field : none, pk,
+                                  n_cache, seed, frame, residual_radiance, out_tl, out_c, out_r,
+                                  (hipStream_t)stream));
 }
 
 nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field, int64_t batch, uint64_t seed,
@@ -381,6 +405,7 @@ nirc_status tlmc_batch_build(const tlmc_request *requests, int32_t n, void *list
         q.key0 = (uint32_t)r.seed;
         q.key1 = (uint32_t)(r.seed >> 32);
         q.frame = (uint32_t)r.frame;
+        q.rrad = r.residual_radiance;
         q.out_tl = r.out_tl;
         q.out_c = r.out_c;
         q.out_r = r.out_r;

@@ -144,9 +144,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
 template <int W, int T>
 __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN dn, const float *db, const float *hs,
                                                const float *sD, const float *sH, const float *sO,
-                                               const nirc_lobes &lobes, const float *xs, int lane, int g, int col,
-                                               float &fc0, float &fc1, float &fc2, float &fr0, float &fr1,
-                                               float &fr2) {
+                                               const nirc_lobes &lobes, const float *rrad, int64_t pc,
+                                               const float *xs, int lane, int g, int col, float &fc0, float &fc1,
+                                               float &fc2, float &fr0, float &fr1, float &fr2) {
     constexpr int MT = W / 16;
     if constexpr (!lds_weights(W)) {   // weights in global memory: keep their loads inside the pass
         sD = opaque(sD);
@@ -179,7 +179,13 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
             reduce_cache_tile(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
         } else {
             float Lr[3];
-            field_eval(lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
+            if (rrad) {   // uniform: the caller's residual radiance
+                Lr[0] = rrad[3 * pc];
+                Lr[1] = rrad[3 * pc + 1];
+                Lr[2] = rrad[3 * pc + 2];
+            } else {
+                field_eval(lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
+            }
             fr0 = Lr[0] - y0;
             fr1 = Lr[1] - y1;
             fr2 = Lr[2] - y2;
@@ -203,10 +209,10 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 // One point group (16 points from p0) through the FP32 chain.
 template <int W>
 __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
-                                               uint32_t key1, uint32_t frame, float *out_tl, float *out_c,
-                                               float *out_r, const nirc_lobes &lobes, const float *gS,
-                                               const float *sD, const float *sH, const float *sO, float *hs,
-                                               float *db, int lane, int g, int col) {
+                                               uint32_t key1, uint32_t frame, const float *rrad, float *out_tl,
+                                               float *out_c, float *out_r, const nirc_lobes &lobes,
+                                               const float *gS, const float *sD, const float *sH, const float *sO,
+                                               float *hs, float *db, int lane, int g, int col) {
     constexpr int MT = W / 16;
     const int64_t P = pts.count;
     const int n_tiles = n_cache + 1;
@@ -230,12 +236,12 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_f32<W, TP>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
-                                  fr0, fr1, fr2);
+            tlmc_tiles_f32<W, TP>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, xs, lane, g, col, fc0,
+                                  fc1, fc2, fr0, fr1, fr2);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, xs, lane, g, col, fc0, fc1, fc2,
-                                 fr0, fr1, fr2);
+            tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, xs, lane, g, col, fc0,
+                                 fc1, fc2, fr0, fr1, fr2);
         tb = tend;
     }
     if (g == 0 && p0 + col < P)
@@ -246,8 +252,8 @@ template <int W, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes lobes,
                                                          const float *__restrict__ packed,
                                                          int n_cache, DivN dn, uint32_t key0, uint32_t key1,
-                                                         uint32_t frame, float *__restrict__ out_tl,
-                                                         float *__restrict__ out_c,
+                                                         uint32_t frame, const float *__restrict__ rrad,
+                                                         float *__restrict__ out_tl, float *__restrict__ out_c,
                                                          float *__restrict__ out_r) {
     constexpr F32Layout L{W};
     constexpr bool kLds = lds_weights(W);
@@ -271,8 +277,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
     float *db = hs + 16 * W;               // directions, SoA [3][kDirSlots]
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_f32<W>(pts, grp << 4, n_cache, dn, key0, key1, frame, out_tl, out_c, out_r, s_lobes, gS, sD, sH,
-                          sO, hs, db, lane, g, col);
+        tlmc_group_f32<W>(pts, grp << 4, n_cache, dn, key0, key1, frame, rrad, out_tl, out_c, out_r, s_lobes, gS, sD,
+                          sH, sO, hs, db, lane, g, col);
 }
 
 // Continuous batching with the FP32 chain (see k_tlmc_multi_h16).
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_f32(const BatchDesc *
         const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
         if (grp < (s_req.pts.count + 15) >> 4)
             tlmc_group_f32<W>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
-                              s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
+                              uniform_ptr(s_req.rrad), s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
                               (const float *)s_req.packed + L.offset(SEC_S), sD, sH, sO, hs, db, lane, g, col);
     }
 }
@@ -394,22 +400,21 @@ hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStre
 }
 
 hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                       int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
+                       int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
                        float *out_r, hipStream_t s) {
     if (pts.count == 0) return hipSuccess;
     if (prec != NIRC_FP32)
-        return launch_tlmc_h16(W, prec, pts, lobes, packed, n_cache, seed, frame, out_tl, out_c, out_r, s);
+        return launch_tlmc_h16(W, prec, pts, lobes, packed, n_cache, seed, frame, rrad, out_tl, out_c, out_r, s);
     constexpr int WAVES = 8;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, kMaxResidentBlocks);
     if (W == 64)
         hipLaunchKernelGGL((k_tlmc_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes,
                            (const float *)packed, n_cache, make_divn(n_cache), (uint32_t)seed, (uint32_t)(seed >> 32),
-                           (uint32_t)frame,
-                           out_tl, out_c, out_r);
+                           (uint32_t)frame, rrad, out_tl, out_c, out_r);
     else if (W == 128)   // one wave per SIMD: the width-128 FP32 pass needs more than 256 registers
         hipLaunchKernelGGL((k_tlmc_f32<128, 4>), dim3(grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks)),
                            dim3(4 * 64), 0, s, pts, lobes, (const float *)packed, n_cache, make_divn(n_cache),
-                           (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, out_tl, out_c, out_r);
+                           (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, rrad, out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

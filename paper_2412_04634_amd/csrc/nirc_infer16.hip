@@ -231,8 +231,8 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
 // surface columns are read from global memory (gS).
 template <int W, int PREC, int TP = 4>
 __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
-                                               uint32_t key1, uint32_t frame, float *out_tl, float *out_c,
-                                               float *out_r, const nirc_lobes &lobes, const uint16_t *gS,
+                                               uint32_t key1, uint32_t frame, const float *rrad, float *out_tl,
+                                               float *out_c, float *out_r, const nirc_lobes &lobes, const uint16_t *gS,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
                                                const GroupSlab &gs, int lane, int g, int col) {
     constexpr int MT = W / 16;
@@ -268,14 +268,21 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         tb = tend;
     }
     wave_sync();
-    // residual sample of the field: lane group g evaluates lobe g at its column's point and
-    // residual direction, and the four lobes are summed across the lane groups
+    // residual sample: the caller's radiance (uniform branch), or the field: lane group g
+    // evaluates lobe g at its column's point and residual direction, and the four lobes are
+    // summed across the lane groups
     float Lr[3];
-    field_lobe(lobes, g, xs[0], xs[1], xs[2], rdx, rdy, rdz, Lr);
+    if (rrad) {
+        Lr[0] = rrad[3 * pc];
+        Lr[1] = rrad[3 * pc + 1];
+        Lr[2] = rrad[3 * pc + 2];
+    } else {
+        field_lobe(lobes, g, xs[0], xs[1], xs[2], rdx, rdy, rdz, Lr);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        Lr[c] += __shfl_xor(Lr[c], 16);
-        Lr[c] += __shfl_xor(Lr[c], 32);
+        for (int c = 0; c < 3; ++c) {
+            Lr[c] += __shfl_xor(Lr[c], 16);
+            Lr[c] += __shfl_xor(Lr[c], 32);
+        }
     }
     if (g == 0 && p0 + col < P) {
         const float inv_n = 1.0f / (float)n_cache;
@@ -302,8 +309,9 @@ __device__ inline GroupSlab group_slab(float *base, int W) {
 template <int W, int PREC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes lobes, const uint16_t *__restrict__ packed,
                                                          int n_cache, DivN dn, uint32_t key0, uint32_t key1,
-                                                         uint32_t frame, float *__restrict__ out_tl,
-                                                         float *__restrict__ out_c, float *__restrict__ out_r) {
+                                                         uint32_t frame, const float *__restrict__ rrad,
+                                                         float *__restrict__ out_tl, float *__restrict__ out_c,
+                                                         float *__restrict__ out_r) {
     constexpr H16Layout L{W};
     constexpr bool kLds = lds_weights(W);
     constexpr int NW = kLds ? Infer16Lds<W>::kWeights : 8;   // 16-bit elements
@@ -326,9 +334,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
     const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, W);
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2>(pts, grp << 4, n_cache, dn, key0, key1, frame, out_tl,
-                                                                 out_c, out_r, s_lobes, gS, sD, sH, sOS, gs, lane, g,
-                                                                 col);
+        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2>(pts, grp << 4, n_cache, dn, key0, key1, frame, rrad,
+                                                                 out_tl, out_c, out_r, s_lobes, gS, sD, sH, sOS, gs,
+                                                                 lane, g, col);
 }
 
 // Continuous batching: a persistent grid walks a device work list of requests (each with its own
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *
         const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
         if (grp < (s_req.pts.count + 15) >> 4)
             tlmc_group_h16<W, PREC>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
-                                    s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
+                                    uniform_ptr(s_req.rrad), s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
                                     (const uint16_t *)s_req.packed + L.offset(SEC_S), sD, sH, sOS, gs, lane, g, col);
     }
 }
@@ -418,8 +426,8 @@ hipError_t launch_tlmc_multi_h16(int W, int prec, const BatchDesc *desc, int gri
 }
 
 hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                           int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c, float *out_r,
-                           hipStream_t s) {
+                           int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
+                           float *out_r, hipStream_t s) {
     constexpr int WAVES = 8;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
     const uint16_t *pk = (const uint16_t *)packed;
@@ -427,26 +435,26 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
     const DivN dn = make_divn(n_cache);
     if (W == 64 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
     else if (W == 64)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
     // width 128: from 16 cache queries per point on, one wave per SIMD with 4-tile passes (half the weight
     // traffic from L2 per tile); below that, two waves per SIMD with 2-tile passes hide the per-point work better
     else if (W == 128 && n_cache >= 16) {
         const unsigned g4 = grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks);
         if (prec == NIRC_BF16)
             hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
-                               dn, k0, k1, f, out_tl, out_c, out_r);
+                               dn, k0, k1, f, rrad, out_tl, out_c, out_r);
         else
             hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
-                               dn, k0, k1, f, out_tl, out_c, out_r);
+                               dn, k0, k1, f, rrad, out_tl, out_c, out_r);
     } else if (W == 128 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
     else if (W == 128)
         hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -60,6 +60,15 @@ __device__ __forceinline__ const T *opaque(const T *p) {
     return (const T *)(global_ptr)(((uint64_t)hi << 32) | lo);
 }
 
+// A pointer that holds the same value in every lane, moved to scalar registers so that a branch
+// on it is taken by the whole wave (no divergent join).
+__device__ __forceinline__ const float *uniform_ptr(const float *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const float *)(((uint64_t)hi << 32) | lo);
+}
+
 // h += W1_s e_s for one 16-column tile; the surface features are computed here in B layout.
 template <int W>
 __device__ __forceinline__ void layer1_surface(f32x4 (&h)[W / 16], const float *gS, const float xs[7],
@@ -347,6 +356,7 @@ struct BatchRequest {
     int32_t n_cache;
     DivN dn;
     uint32_t key0, key1, frame;
+    const float *rrad;     // residual radiance [P][3], or NULL for the field
     float *out_tl, *out_c, *out_r;
     int32_t chunk_begin;   // first chunk of this request in the batch
     int32_t pad;
@@ -380,12 +390,13 @@ hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStre
 hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
                             hipStream_t s);
 hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                           int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c, float *out_r,
-                           hipStream_t s);
+                           int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
+                           float *out_r, hipStream_t s);
 hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
                         hipStream_t s);
+// rrad: residual radiance [P][3] (a renderer's sample), or NULL to evaluate the lobe field
 hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                       int n_cache, uint64_t seed, uint64_t frame, float *out_tl, float *out_c,
+                       int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
                        float *out_r, hipStream_t s);
 
 // Frame statistics (FP64).

@@ -50,7 +50,7 @@ class Lobes(ctypes.Structure):
 
 class _Request(ctypes.Structure):
     _fields_ = [("model", _vp), ("points", _Points), ("field", Lobes), ("n_cache", _i32), ("seed", _u64),
-                ("frame", _u64), ("out_tl", _vp), ("out_c", _vp), ("out_r", _vp)]
+                ("frame", _u64), ("residual_radiance", _vp), ("out_tl", _vp), ("out_c", _vp), ("out_r", _vp)]
 
 
 class NircError(RuntimeError):
@@ -76,12 +76,15 @@ def lib():
             "nirc_set_weights": (_i32, [_vp, _vp, _vp]),
             "nirc_get_weights": (_i32, [_vp, _vp, _vp]),
             "nirc_get_adam": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+            "nirc_get_state": (_i32, [_vp, _vp, _sz, _vp]),
+            "nirc_set_state": (_i32, [_vp, _vp, _sz, _vp]),
             "nirc_read_flags": (_u32, [_vp, _vp]),
             "nirc_clear_flags": (_i32, [_vp, _vp]),
             "nirc_encode": (_i32, [_Points, _Queries, _vp, _vp]),
             "nirc_infer": (_i32, [_vp, _Points, _Queries, _vp, _vp]),
             "tlmc_sample_dirs": (_i32, [_Points, _i32, _u64, _u64, _vp, _vp]),
-            "tlmc_estimate": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp, _vp]),
+            "tlmc_estimate": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp, _vp,
+                                     _vp]),
             "tlmc_train_batch": (_i32, [_Points, ctypes.POINTER(Lobes), _i64, _u64, _u64, _u32, _vp, _vp, _vp,
                                         _vp, _vp, _vp]),
             "nirc_loss_grad": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp, _vp]),
@@ -245,6 +248,18 @@ class Model:
         _check(lib().nirc_get_adam(self.handle, _ptr(m), _ptr(v), _ptr(step), _stream()), "nirc_get_adam")
         return m, v, step
 
+    def get_state(self) -> torch.Tensor:
+        """The whole training state as a device byte tensor (checkpoint)."""
+        out = torch.empty(self.state.numel(), dtype=torch.uint8, device=self.state.device)
+        _check(lib().nirc_get_state(self.handle, _ptr(out), out.numel(), _stream()), "nirc_get_state")
+        return out
+
+    def set_state(self, blob: torch.Tensor):
+        """Restore a state written by get_state of a model of the same width (resume)."""
+        b = blob.to(self.state.device).contiguous()
+        _check(lib().nirc_set_state(self.handle, _ptr(b), b.numel(), _stream()), "nirc_set_state")
+        torch.cuda.current_stream().synchronize()   # b may be a temporary
+
     def read_flags(self) -> int:
         return int(lib().nirc_read_flags(self.handle, _stream()))
 
@@ -274,15 +289,19 @@ def tlmc_sample_dirs(points: Points, n_cache: int, seed: int, frame: int) -> tor
 
 
 def tlmc_estimate(model: Model, points: Points, lobes, n_cache: int, seed: int, frame: int,
-                  parts: bool = False, out=None):
-    """Two-level estimate per point; returns F_tl, or (F_tl, F_c, F_r) with parts=True."""
+                  parts: bool = False, out=None, residual=None):
+    """Two-level estimate per point; returns F_tl, or (F_tl, F_c, F_r) with parts=True.
+    residual: the residual sample's radiance [P, 3] (FP32, on the device) at the directions
+    tlmc_sample_dirs returns; None evaluates the lobe field `lobes` (which may then be None)."""
     dev = points.t[0].device
-    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    L = None if lobes is None else (lobes if isinstance(lobes, Lobes) else lobes_struct(lobes))
     tl = out if out is not None else torch.empty((points.count, 3), dtype=torch.float32, device=dev)
     c = torch.empty_like(tl) if parts else None
     r = torch.empty_like(tl) if parts else None
-    _check(lib().tlmc_estimate(model.handle, points.c(), ctypes.byref(L), n_cache, seed, frame, _ptr(tl),
-                               _ptr(c), _ptr(r), _stream()), "tlmc_estimate")
+    if residual is not None:
+        assert residual.dtype == torch.float32 and residual.is_contiguous() and residual.numel() == 3 * points.count
+    _check(lib().tlmc_estimate(model.handle, points.c(), None if L is None else ctypes.byref(L), n_cache, seed,
+                               frame, _ptr(residual), _ptr(tl), _ptr(c), _ptr(r), _stream()), "tlmc_estimate")
     return (tl, c, r) if parts else tl
 
 
@@ -392,7 +411,8 @@ class Batch:
         self._copied = None
 
     def set(self, requests):
-        """requests: list of dicts with model, points, lobes, n_cache, seed, frame, out_tl[, out_c, out_r].
+        """requests: list of dicts with model, points, lobes, n_cache, seed, frame, out_tl[, out_c, out_r,
+        residual].
         Writes the work list to the device buffer on the current stream."""
         n = len(requests)
         if self._copied is not None:
@@ -400,8 +420,13 @@ class Batch:
         arr = (_Request * n)()
         self._keep = []
         for i, r in enumerate(requests):
-            L = r["lobes"] if isinstance(r["lobes"], Lobes) else lobes_struct(r["lobes"])
+            lb = r.get("lobes")
+            L = lb if isinstance(lb, Lobes) else (Lobes() if lb is None else lobes_struct(lb))
+            rr = r.get("residual")
+            if lb is None and rr is None:
+                raise NircError("a request needs lobes or residual radiance")
             arr[i] = _Request(r["model"].handle.value, r["points"].c(), L, r["n_cache"], r["seed"], r["frame"],
+                              None if rr is None else rr.data_ptr(),
                               r["out_tl"].data_ptr(), _ptr(r.get("out_c")) and r["out_c"].data_ptr(),
                               _ptr(r.get("out_r")) and r["out_r"].data_ptr())
             self._keep.append(r)

@@ -36,7 +36,9 @@ def test_host_side_argument_errors():
     # NULL state / weights / output handle: rejected before any device work
     assert L.nirc_create(ctypes.byref(cfg), None, 0, None, 0, None, None, ctypes.byref(h)) == -1
     assert L.nirc_infer(None, nirc._Points(), nirc._Queries(), None, None) == -1
-    assert L.tlmc_estimate(None, nirc._Points(), None, 8, 0, 0, None, None, None, None) == -1
+    assert L.tlmc_estimate(None, nirc._Points(), None, 8, 0, 0, None, None, None, None, None) == -1
+    assert L.nirc_get_state(None, None, 0, None) == -1
+    assert L.nirc_set_state(None, None, 0, None) == -1
     assert L.tlmc_sample_dirs(nirc._Points(), 0, 0, 0, None, None) == -1     # n_cache < 1
     bad_pts = nirc._Points(0, 0, 0, 0, 0, 0, 0, 5)                          # NULL arrays, count 5
     assert L.nirc_encode(bad_pts, nirc._Queries(), None, None) == -1
