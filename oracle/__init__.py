@@ -63,7 +63,7 @@ def lib():
         L.oracle_closed_form.argtypes = [_i64] + [_f32p] * 6 + [_f32p, _int, _f64p]
         L.oracle_second_moment.argtypes = [_i64] + [_f32p] * 6 + [_f32p, _int, _f64p]
         L.oracle_loss_grad.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _f64p, _int,
-                                       _dbl, _int, _Opt(_f64p)])
+                                       _dbl, _int, _int, _Opt(_f64p)])
         L.oracle_loss_grad.restype = _dbl
         L.oracle_adam.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, _i64, _dbl, _dbl, _dbl, _dbl]
         L.oracle_train_batch.argtypes = ([_i64] + [_f32p] * 6 + [_f32p, _i64, _u64, _u64, ctypes.c_uint32,
@@ -194,15 +194,19 @@ def second_moment(points, lobes_packed, n_nodes: int = 256) -> np.ndarray:
     return out
 
 
+LOSS_REL_L2, LOSS_L2, LOSS_VAR = 0, 1, 2
+
+
 def loss_grad(points, point_idx, dirs, target, w, width: int, eps: float = 1e-2, frozen: bool = True,
-              want_grad: bool = True):
-    """Relative-L2 loss (stop-gradient denominator) and its weight gradient (FP64)."""
+              want_grad: bool = True, kind: int = LOSS_REL_L2):
+    """Training loss (kind: relative L2, plain L2 or the residual-variance loss) and its weight
+    gradient (FP64)."""
     dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
     B = dirs.shape[0]
     g = np.zeros(n_params(width), np.float64) if want_grad else None
     idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
     loss = lib().oracle_loss_grad(B, *_pts(points), idx, dirs, np.ascontiguousarray(target, np.float64).reshape(-1),
-                                  _w64(w), width, eps, int(frozen), g)
+                                  _w64(w), width, eps, int(frozen), int(kind), g)
     return float(loss), g
 
 

@@ -502,16 +502,22 @@ void oracle_second_moment(int64_t P, const float *px, const float *py, const flo
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Training (Sec. "Radiance Cache Optimization", eq. 12 read on radiance with p_r = 1):
- *   loss = (1/(3B)) sum_{b,c} (y - t)^2 / (sg(y)^2 + eps),
- *   dloss/dy = (2/(3B)) (y - t) / (y^2 + eps)   (denominator held constant),
- *   dloss/dz = dloss/dy * y                      (y = exp z),
- * then plain backpropagation through the ReLU layers (ReLU'(0) = 0); only weight gradients.
- * frozen == 0 differentiates through the denominator as well (a control, not the method).    */
+/* Training (Sec. "Radiance Cache Optimization", read on radiance with p_r = 1).  Three losses of
+ * that section, per sample b and channel c with d = y - t:
+ *   kind 0, relative L2 (eq. 12, the method's):  d^2 / (sg(y)^2 + eps);
+ *   kind 1, squared difference (the plain L2 loss before the relative weighting):  d^2;
+ *   kind 2, variance of the residual estimator (eq. for L_V):  (t - y - F_r)^2, with F_r the
+ *           residual's expectation estimated per channel by the batch mean of t - y.
+ * loss = (1/(3B)) sum_{b,c} of the term.  Gradients: dloss/dy = (2/(3B)) d / den for kinds 0
+ * and 1 (den = y^2 + eps or 1, the denominator held constant), (2/(3B)) (y - t + F_r) for
+ * kind 2 (F_r's own derivative adds nothing: the centred terms sum to zero over the batch);
+ * dloss/dz = dloss/dy * y (y = exp z), then plain backpropagation through the ReLU layers
+ * (ReLU'(0) = 0); only weight gradients.  frozen == 0 differentiates through the relative
+ * loss's denominator as well (a control, not the method).                                    */
 double oracle_loss_grad(int64_t B, const float *px, const float *py, const float *pz, const float *nx,
                         const float *ny, const float *nz, const float *rough, const int32_t *point,
                         const double *dirs, const double *target, const double *w, int width,
-                        double eps, int frozen, double *grad /* [n_params] or NULL */)
+                        double eps, int frozen, int kind, double *grad /* [n_params] or NULL */)
 {
     const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
     net_t net;
@@ -525,6 +531,31 @@ double oracle_loss_grad(int64_t B, const float *px, const float *py, const float
 #ifdef _OPENMP
     nthreads = omp_get_max_threads();
 #endif
+    /* kind 2: the batch estimate of F_r = E[t - y] per channel, from a forward pass first */
+    double fr[3] = {0.0, 0.0, 0.0};
+    if (kind == 2) {
+        double *part = (double *)calloc((size_t)nthreads * 3, sizeof(double));
+#pragma omp parallel
+        {
+            int tid = 0;
+#ifdef _OPENMP
+            tid = omp_get_thread_num();
+#endif
+#pragma omp for schedule(static)
+            for (int64_t b = 0; b < B; ++b) {
+                double in[NIN], e[NFEAT];
+                acts_t a;
+                gather_inputs(pts, point ? point[b] : b, dirs + 3 * b, in);
+                encode_inputs(in, e);
+                net_forward(&net, e, &a);
+                for (int c = 0; c < 3; ++c) part[3 * tid + c] += target[3 * b + c] - a.y[c];
+            }
+        }
+        for (int t = 0; t < nthreads; ++t)
+            for (int c = 0; c < 3; ++c) fr[c] += part[3 * t + c];
+        for (int c = 0; c < 3; ++c) fr[c] /= (double)B;
+        free(part);
+    }
     double *tg = grad ? (double *)calloc((size_t)nthreads * np, sizeof(double)) : NULL;
     double *tl = (double *)calloc((size_t)nthreads, sizeof(double));
 #pragma omp parallel
@@ -544,10 +575,11 @@ double oracle_loss_grad(int64_t B, const float *px, const float *py, const float
             double dz[3];
             for (int c = 0; c < 3; ++c) {
                 double y = a.y[c], t = target[3 * b + c];
-                double den = y * y + eps;
-                tl[tid] += (y - t) * (y - t) / den;
-                double dy = 2.0 * (y - t) / den;
-                if (!frozen) dy -= (y - t) * (y - t) * 2.0 * y / (den * den);
+                double d = (kind == 2) ? (y - t) + fr[c] : y - t;
+                double den = (kind == 0) ? y * y + eps : 1.0;
+                tl[tid] += d * d / den;
+                double dy = 2.0 * d / den;
+                if (!frozen && kind == 0) dy -= d * d * 2.0 * y / (den * den);
                 dz[c] = dy * y / (3.0 * (double)B);
             }
             if (!g) continue;

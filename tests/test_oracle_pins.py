@@ -451,6 +451,72 @@ def test_gradient_stop_gradient_is_honoured():
 
 
 # ------------------------------------------------------------------------------------------
+# Loss variants of Sec. "Radiance Cache Optimization": plain L2 and the residual-variance loss
+
+@pytest.mark.parametrize("kind", [oracle.LOSS_L2, oracle.LOSS_VAR])
+def test_loss_variants_value_and_finite_differences(kind):
+    # the loss value against a numpy forward pass, and the gradient against central finite
+    # differences of the loss itself (for the variance loss the batch estimate of F_r moves with
+    # the weights too: its derivative must add nothing)
+    width, B = 64, 6
+    pts = wl.make_points(19, 32)
+    lobes = wl.make_lobes(19).packed()
+    w = wl.make_weights(19, width).astype(np.float64)
+    idx, dirs, target = oracle.train_batch(pts, lobes, B, 7, 0, 0)
+    loss, g = oracle.loss_grad(pts, idx, dirs, target, w, width, kind=kind)
+    feat = npref.encode(npref.inputs_of(pts, idx, dirs))
+    y0, pre0 = npref.forward(feat, w, width)
+    d = y0 - target
+    if kind == oracle.LOSS_VAR:
+        d = d + (target - y0).mean(axis=0)
+    assert loss == pytest.approx((d ** 2).sum() / (3 * B), rel=1e-12)
+    rng = np.random.default_rng(1)
+    n = w.shape[0]
+    check = np.concatenate([rng.choice(n, 200, replace=False), np.arange(n - 3 * width, n - 3 * width + 20)])
+    h = 1e-4
+    used = 0
+    for i in check:
+        wp = w.copy(); wp[i] += h
+        wm = w.copy(); wm[i] -= h
+        _, prep = npref.forward(feat, wp, width)
+        _, prem = npref.forward(feat, wm, width)
+        if any(np.any((a > 0) != (b > 0)) or np.any((a > 0) != (c > 0)) for a, b, c in zip(pre0, prep, prem)):
+            continue
+        lp, _ = oracle.loss_grad(pts, idx, dirs, target, wp, width, kind=kind, want_grad=False)
+        lm, _ = oracle.loss_grad(pts, idx, dirs, target, wm, width, kind=kind, want_grad=False)
+        fd = (lp - lm) / (2 * h)
+        scale = max(abs(fd), 1e-6 * np.abs(g).max())
+        assert abs(fd - g[i]) <= 1e-6 * scale + 1e-11, (i, fd, g[i])
+        used += 1
+    assert used > 180
+
+
+def test_loss_variant_special_cases():
+    width, B = 64, 40
+    pts = wl.make_points(20, 64)
+    lobes = wl.make_lobes(20).packed()
+    w = wl.make_weights(20, width).astype(np.float64)
+    idx, dirs, target = oracle.train_batch(pts, lobes, B, 8, 0, 0)
+    y = oracle.infer(pts, idx, dirs, w, width)
+    shift = np.array([0.3, -0.2, 1.1])
+    # the variance loss only sees the targets up to a constant per channel
+    la, ga = oracle.loss_grad(pts, idx, dirs, target, w, width, kind=oracle.LOSS_VAR)
+    lb, gb = oracle.loss_grad(pts, idx, dirs, target + shift, w, width, kind=oracle.LOSS_VAR)
+    assert lb == pytest.approx(la, rel=1e-10)
+    assert np.linalg.norm(gb - ga) <= 1e-9 * np.linalg.norm(ga)
+    # targets equal to the cache's own predictions (plus a constant for the variance loss): zero
+    for kind, t in ((oracle.LOSS_L2, y), (oracle.LOSS_VAR, y + shift), (oracle.LOSS_REL_L2, y)):
+        l0, g0 = oracle.loss_grad(pts, idx, dirs, t, w, width, kind=kind)
+        assert abs(l0) <= 1e-24 and np.abs(g0).max() <= 1e-12
+    # the relative loss with a huge epsilon is the plain L2 loss divided by epsilon
+    big = 1e12
+    lr, gr = oracle.loss_grad(pts, idx, dirs, target, w, width, eps=big, kind=oracle.LOSS_REL_L2)
+    l2, g2 = oracle.loss_grad(pts, idx, dirs, target, w, width, kind=oracle.LOSS_L2)
+    assert lr * big == pytest.approx(l2, rel=1e-9)
+    assert np.linalg.norm(gr * big - g2) <= 1e-9 * np.linalg.norm(g2)
+
+
+# ------------------------------------------------------------------------------------------
 # Adam closed forms
 
 def test_adam_first_step_closed_form():
