@@ -246,6 +246,41 @@ def train_convergence(nirc, dp, lobes_for, W, seed, frames=300, batches=(1 << 16
     return out
 
 
+def loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S):
+    """The three training losses of the optimisation section (relative L2, plain L2, residual
+    variance), each training its own FP32 cache from the same weights over the same rotating
+    frames: MRSE of the two-level estimate and of the cache level alone on the last frame, the
+    cache's relative L2 error on a probe of fresh samples, and the training time per frame."""
+    import torch
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, kind in (("rel_l2", 0), ("l2", 1), ("variance", 2)):
+        m = nirc.Model(w0, cfg=nirc.make_config(loss=kind), max_batch=B)
+        tl = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+        c = torch.empty_like(tl)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        t_train = 0.0
+        for f in range(frames):
+            lob = nirc.lobes_struct(lobes_for(f))
+            ev[0].record(stream)
+            nirc.nirc_train_frame(m, dp, lob, B, S, seed, f)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            t_train += ev[0].elapsed_time(ev[1])
+        lob = nirc.lobes_struct(lobes_for(frames))
+        nirc._check(nirc.lib().tlmc_estimate(m.handle, dp.c(), nirc.ctypes.byref(lob), N, seed, frames, None,
+                                             nirc._ptr(tl), nirc._ptr(c), None, nirc._stream()), "tlmc_estimate")
+        st = nirc.tlmc_frame_stats(dp, lob, table, tl, c, fs=fs)
+        q, tgt = nirc.tlmc_train_batch(dp, lob, 65536, seed + 7919, frames, 0)
+        y = nirc.nirc_infer(m, dp, q)
+        out[name] = {"mrse": float(st[4].item()), "mrse_cache_only": float(st[5].item()),
+                     "cache_rel_l2": float((y - tgt).norm() / tgt.norm()), "ms_train_frame": t_train / frames,
+                     "flags": m.read_flags()}
+        del m
+    out["frames"] = frames
+    return out
+
+
 def serving_run(seconds):
     """16 render streams (resolutions 360p..4K, N in {4, 8, 32}, width-64 BF16 caches with their
     own Adam state), Poisson arrivals at 240 frames/s, HBM-budget admission, continuous batching
@@ -312,6 +347,8 @@ def main():
                     help="duration of the multi-stream serving run (0 to skip)")
     ap.add_argument("--precision-form", action="store_true",
                     help="also run the N x width x precision matrix of estimates")
+    ap.add_argument("--loss-variants", action="store_true",
+                    help="train a cache with each loss of the optimisation section (100 frames) and compare")
     ap.add_argument("--train-convergence", action="store_true",
                     help="also run 300 frames of training only at batches 2^16, 2^18, 2^20")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -472,6 +509,8 @@ def main():
     if args.precision_form:
         result["precision_form"] = precision_form(nirc, model.get_weights(), dp, lobes_for(args.warmup + args.steps),
                                                   table, fs, P, seed, args.warmup + args.steps)
+    if args.loss_variants:
+        result["loss_variants"] = loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
     if args.train_convergence:
         result["train_convergence"] = {p: train_convergence(nirc, dp, lobes_for, W, seed, precision=i)
                                        for p, i in (("fp32", 0), ("bf16", 1))}

@@ -54,6 +54,16 @@ typedef int32_t nirc_status;
 #define NIRC_BF16 1
 #define NIRC_FP16 2
 
+/* Training loss (Sec. "Radiance Cache Optimization"), per sample and channel with d = y - t:
+ *   NIRC_LOSS_REL_L2  d^2 / (sg(y)^2 + loss_eps)         eq. 12, the method's loss (default);
+ *   NIRC_LOSS_L2      d^2                                 the plain squared difference;
+ *   NIRC_LOSS_VAR     (t - y - F_r)^2                     the residual-variance loss, with F_r the
+ *                     batch mean of t - y per channel (computed by a forward pass first).
+ * The loss is the mean over samples and channels; the training direction pdf is taken as 1. */
+#define NIRC_LOSS_REL_L2 0
+#define NIRC_LOSS_L2 1
+#define NIRC_LOSS_VAR 2
+
 /* Device flags raised by training (sticky until nirc_clear_flags). */
 #define NIRC_FLAG_NONFINITE_GRAD 1u   /* a step saw a non-finite loss/gradient and was skipped */
 
@@ -71,6 +81,7 @@ typedef struct {
     float adam_eps;      /* e.g. 1e-8 */
     float loss_eps;      /* e.g. 1e-2 */
     float loss_scale;    /* e.g. 1 (FP32/BF16); > 1 for FP16 */
+    int32_t loss;        /* NIRC_LOSS_REL_L2 | NIRC_LOSS_L2 | NIRC_LOSS_VAR */
 } nirc_config;
 
 /* Shading points, structure of arrays, FP32 device arrays of `count` entries each. */

@@ -35,20 +35,27 @@ struct StateLayout {
 };
 
 // Workspace layout: partials [nblocks][np] | loss partials [nblocks] | grad [np] | loss |
-// training samples of nirc_train_frame (point [B], wx, wy, wz [B], target [B][3]).
+// residual-variance loss pre-pass (predictions [B][3], kFrBlocks x 3 FP64 partials, F_r [3]; only
+// for NIRC_LOSS_VAR) | training samples of nirc_train_frame (point [B], wx, wy, wz [B],
+// target [B][3]).
 struct WorkLayout {
-    size_t partials, loss_partials, grad, loss, samples, total;
-    WorkLayout(int W, int nblocks, int64_t batch = 0) {
+    size_t partials, loss_partials, grad, loss, pred, fr_part, fr, samples, total;
+    WorkLayout(int W, int nblocks, int64_t var_batch = 0, int64_t sample_batch = 0) {
         const size_t np = (size_t)n_params(W);
         size_t o = 0;
         partials = o; o += align_up((size_t)nblocks * np * sizeof(float));
         loss_partials = o; o += align_up((size_t)nblocks * sizeof(float));
         grad = o; o += align_up(np * sizeof(float));
         loss = o; o += align_up(sizeof(float));
-        samples = o; o += align_up((size_t)batch * 7 * sizeof(float));
+        pred = o; o += var_batch ? align_up((size_t)var_batch * 3 * sizeof(float)) : 0;
+        fr_part = o; o += var_batch ? align_up((size_t)kFrBlocks * 3 * sizeof(double)) : 0;
+        fr = o; o += var_batch ? align_up(4 * sizeof(float)) : 0;
+        samples = o; o += align_up((size_t)sample_batch * 7 * sizeof(float));
         total = o;
     }
 };
+
+int64_t var_rows(const nirc_config &cfg, int64_t batch) { return cfg.loss == NIRC_LOSS_VAR ? batch : 0; }
 
 nirc_status check_points(const nirc_points &p) {
     if (p.count < 0 || p.count > INT32_MAX) return NIRC_ERR_INVALID_ARG;
@@ -102,6 +109,8 @@ int64_t nirc_n_params(int32_t width) { return width_ok(width) ? n_params(width) 
 static nirc_status check_config(const nirc_config *cfg) {
     if (!cfg) return NIRC_ERR_INVALID_ARG;
     if (!width_ok(cfg->width)) return NIRC_ERR_UNSUPPORTED;
+    if (cfg->loss != NIRC_LOSS_REL_L2 && cfg->loss != NIRC_LOSS_L2 && cfg->loss != NIRC_LOSS_VAR)
+        return NIRC_ERR_INVALID_ARG;
     if (cfg->precision != NIRC_FP32 && cfg->precision != NIRC_BF16 && cfg->precision != NIRC_FP16)
         return NIRC_ERR_UNSUPPORTED;
     if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
@@ -118,7 +127,7 @@ size_t nirc_state_bytes(const nirc_config *cfg) {
 
 size_t nirc_workspace_bytes(const nirc_config *cfg, int64_t max_batch) {
     if (check_config(cfg) != NIRC_OK || max_batch < 0) return 0;
-    return WorkLayout(cfg->width, train_blocks(max_batch), max_batch).total;
+    return WorkLayout(cfg->width, train_blocks(max_batch), var_rows(*cfg, max_batch), max_batch).total;
 }
 
 nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes, void *workspace,
@@ -293,14 +302,25 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
     if (queries.count < 1 || !grad) return NIRC_ERR_INVALID_ARG;
     const bool h16 = model->packed16 != nullptr;
     const int nb = h16 ? train_blocks16(queries.count) : train_blocks(queries.count);
-    const WorkLayout wl(model->W, nb);
+    const bool var = target && model->cfg.loss == NIRC_LOSS_VAR;
+    const WorkLayout wl(model->W, nb, var ? queries.count : 0);
     if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
     float *partials = (float *)(model->ws + wl.partials);
     float *lpart = (float *)(model->ws + wl.loss_partials);
     // 16-bit models: the batch size is folded into the loss scale, so that per-sample deltas stay
     // near unit magnitude in the 16-bit operands; the reduction divides it out again
     const float scale = h16 ? model->cfg.loss_scale * (float)queries.count : model->cfg.loss_scale;
-    TrainArgs a{target, d_rgb, model->cfg.loss_eps, scale};
+    TrainArgs a{target, d_rgb, model->cfg.loss_eps, scale, model->cfg.loss, nullptr};
+    if (var) {   // the residual-variance loss needs F_r = mean(t - y) of this batch first
+        float *pred = (float *)(model->ws + wl.pred);
+        float *fr = (float *)(model->ws + wl.fr);
+        const void *pk = h16 ? (const void *)model->packed16 : (const void *)model->packed;
+        hipError_t e = launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries), pk, pred, s);
+        if (e == hipSuccess)
+            e = launch_residual_mean(pred, target, queries.count, (double *)(model->ws + wl.fr_part), fr, s);
+        if (e != hipSuccess) return NIRC_ERR_HIP;
+        a.fr = fr;
+    }
     hipError_t e = h16 ? launch_grad_partials16(model->W, model->cfg.precision, to_points(points),
                                                 to_queries(queries), model->packed16, a, partials, lpart, nb, s)
                        : launch_grad_partials(model->W, to_points(points), to_queries(queries), model->packed, a,
@@ -363,7 +383,7 @@ nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_l
     if (!model || !field || batch < 1 || batch > INT32_MAX || steps < 0) return NIRC_ERR_INVALID_ARG;
     nirc_status st = check_points(points);
     if (st != NIRC_OK || points.count < 1) return NIRC_ERR_INVALID_ARG;
-    const WorkLayout wl(model->W, train_blocks(batch), batch);
+    const WorkLayout wl(model->W, train_blocks(batch), var_rows(model->cfg, batch), batch);
     if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     float *smp = (float *)(model->ws + wl.samples);

@@ -21,11 +21,13 @@ struct GradLds {
 };
 
 // Output-pre-activation gradient and loss term of one channel.
-__device__ inline float out_grad(float z, float t, float dr, bool use_loss, float eps, float k,
-                                 float &loss_term) {
+// rel: the relative loss (denominator y^2 + eps held constant), else den = 1; fr: the F_r shift of
+// the residual-variance loss (0 otherwise)
+__device__ inline float out_grad(float z, float t, float dr, bool use_loss, float eps, float k, bool rel,
+                                 float fr, float &loss_term) {
     const float y = expf(z);
     if (use_loss) {
-        const float d = y - t, den = y * y + eps;
+        const float d = (y - t) + fr, den = rel ? y * y + eps : 1.0f;
         loss_term = d * d / den;
         return k * d / den * y;   // k = 2 scale / (3B)
     }
@@ -146,7 +148,8 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
                     const float t = use_loss ? args.target[3 * b + c] : 0.0f;
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
-                    d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
+                                     args.fr ? args.fr[c] : 0.0f, lt);
                     loss_acc += lt;
                 }
             }
@@ -396,7 +399,8 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32_wide(Points pts, 
                     const float t = use_loss ? args.target[3 * b + c] : 0.0f;
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
-                    d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
+                                     args.fr ? args.fr[c] : 0.0f, lt);
                     loss_acc += lt;
                 }
             }
@@ -661,6 +665,49 @@ __global__ void k_pack_commit(float *packed, const float *master, int W, int tot
 }
 
 // ------------------------------------------------------------------------------------------
+
+// Batch estimate of the residual's expectation per channel for the residual-variance loss:
+// block b sums t - y over its contiguous share of the batch (lanes stride through it, then a
+// fixed tree), and one block adds the kFrBlocks partials in order.  FP64 sums: deterministic
+// and insensitive to the batch size.
+__global__ __launch_bounds__(256) void k_residual_partials(const float *__restrict__ y, const float *__restrict__ t,
+                                                           int64_t B, double *__restrict__ part) {
+    __shared__ double sh[3][256];
+    const int64_t per = (B + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(B, b0 + per);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
+        a0 += (double)t[3 * b] - (double)y[3 * b];
+        a1 += (double)t[3 * b + 1] - (double)y[3 * b + 1];
+        a2 += (double)t[3 * b + 2] - (double)y[3 * b + 2];
+    }
+    sh[0][threadIdx.x] = a0;
+    sh[1][threadIdx.x] = a1;
+    sh[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_residual_final(const double *__restrict__ part, int nblk, int64_t B,
+                                                       float *__restrict__ fr) {
+    if (threadIdx.x < 3) {
+        double a = 0.0;
+        for (int i = 0; i < nblk; ++i) a += part[3 * i + threadIdx.x];
+        fr[threadIdx.x] = (float)(a / (double)B);
+    }
+}
+
+hipError_t launch_residual_mean(const float *y, const float *t, int64_t B, double *part, float *fr, hipStream_t s) {
+    if (B < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_residual_partials, dim3(kFrBlocks), dim3(256), 0, s, y, t, B, part);
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(64), 0, s, part, kFrBlocks, B, fr);
+    return hipGetLastError();
+}
 
 int train_blocks(int64_t batch) {
     int64_t chunks = (batch + kChunk - 1) / kChunk;

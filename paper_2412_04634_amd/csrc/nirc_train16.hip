@@ -50,10 +50,11 @@ __device__ __forceinline__ void stage_chain(uint16_t *rows, const u32x4 (&v)[W /
         for (int j = 0; j < 8; ++j) rows[chained_neuron16(kb, g, j) * kRow16 + s] = half_of(v[kb], j);
 }
 
-__device__ inline float out_grad16(float z, float t, float dr, bool use_loss, float eps, float k, float &loss_term) {
+__device__ inline float out_grad16(float z, float t, float dr, bool use_loss, float eps, float k, bool rel, float fr,
+                                   float &loss_term) {
     const float y = expf(z);
     if (use_loss) {
-        const float d = y - t, den = y * y + eps;
+        const float d = (y - t) + fr, den = rel ? y * y + eps : 1.0f;
         loss_term = d * d / den;
         return k * d / den * y;
     }
@@ -193,7 +194,8 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries 
                     const float t = use_loss ? args.target[3 * b + c] : 0.0f;
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
-                    d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
+                                       args.fr ? args.fr[c] : 0.0f, lt);
                     loss_acc += lt;
                 }
             }
@@ -445,7 +447,8 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16_wide(Points pts, Que
                     const float t = use_loss ? args.target[3 * b + c] : 0.0f;
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
-                    d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, lt);
+                    d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
+                                       args.fr ? args.fr[c] : 0.0f, lt);
                     loss_acc += lt;
                 }
             }

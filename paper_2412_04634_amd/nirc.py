@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "nirc.h")
 
 NIRC_FP32, NIRC_BF16, NIRC_FP16 = 0, 1, 2
 NIRC_FLAG_NONFINITE_GRAD = 1
+NIRC_LOSS_REL_L2, NIRC_LOSS_L2, NIRC_LOSS_VAR = 0, 1, 2
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -32,7 +33,7 @@ _sz = ctypes.c_size_t
 class Config(ctypes.Structure):
     _fields_ = [("width", _i32), ("precision", _i32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float), ("loss_eps", ctypes.c_float),
-                ("loss_scale", ctypes.c_float)]
+                ("loss_scale", ctypes.c_float), ("loss", _i32)]
 
 
 class _Points(ctypes.Structure):
@@ -183,8 +184,9 @@ def lobes_struct(packed64) -> Lobes:
 
 
 def make_config(width=64, precision=NIRC_FP32, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
-                loss_eps=1e-2, loss_scale=1.0) -> Config:
-    return Config(width, precision, lr, beta1, beta2, adam_eps, loss_eps, loss_scale)
+                loss_eps=1e-2, loss_scale=1.0, loss=0) -> Config:
+    """loss: NIRC_LOSS_REL_L2 (eq. 12, default), NIRC_LOSS_L2 or NIRC_LOSS_VAR."""
+    return Config(width, precision, lr, beta1, beta2, adam_eps, loss_eps, loss_scale, loss)
 
 
 def nirc_n_params(width: int) -> int:

@@ -45,6 +45,22 @@ class Samples:
     def loss_grad(self, points, w, width):
         return oracle.loss_grad(points, self.idx, self.d, self.t, w, width)
 
+    def drop_relu_ties(self, points, w, width, band=1e-5):
+        """Drop the samples whose hidden pre-activations come within `band` of zero (FP64, numpy
+        matrix chain).  There the ReLU mask is decided by rounding: an FP32 forward pass may take
+        the other side, and the one sample's flipped unit moves a gradient over a few thousand
+        samples by ~1e-4.  FP32 pre-activations err by ~1e-6 at most, so 1e-5 leaves a margin.
+        Returns the number of samples dropped."""
+        from tests import npref
+        _, pre = npref.forward(npref.encode(npref.inputs_of(points, self.idx, self.d)), w, width)
+        keep = np.ones(self.idx.shape[0], bool)
+        for z in pre:
+            keep &= (np.abs(z) >= band).all(axis=1)
+        self.idx = np.ascontiguousarray(self.idx[keep])
+        self.d32 = np.ascontiguousarray(self.d32[keep])
+        self.t32 = np.ascontiguousarray(self.t32[keep])
+        return int((~keep).sum())
+
 
 def oracle_dirs32(points, n_cache, seed, frame):
     """The oracle's sampled directions of a frame rounded to FP32, [P * (n_cache + 1), 3]."""

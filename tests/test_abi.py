@@ -27,6 +27,9 @@ def test_sizes_and_params():
     bad = nirc.make_config(width=48)
     assert nirc.nirc_state_bytes(bad) == 0
     assert nirc.nirc_state_bytes(nirc.make_config(precision=7)) == 0
+    assert nirc.nirc_state_bytes(nirc.make_config(loss=3)) == 0
+    var = nirc.make_config(loss=nirc.NIRC_LOSS_VAR)
+    assert nirc.nirc_workspace_bytes(var, 65536) > nirc.nirc_workspace_bytes(cfg, 65536)
 
 
 def test_host_side_argument_errors():
