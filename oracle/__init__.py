@@ -55,6 +55,8 @@ def lib():
         L.oracle_field.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _Opt(_i32p), _f64p, _f64p]
         L.oracle_estimate.argtypes = ([_i64] + [_f32p] * 7 + [_f32p, _f64p, _int, _int, _u64, _u64,
                                       _Opt(_f64p), _int, _Opt(_f64p), _Opt(_f64p), _Opt(_f64p)])
+        L.oracle_estimate_biased.argtypes = ([_i64] + [_f32p] * 7 + [_f32p, _f64p, _int, _int, _u64, _u64,
+                                             _Opt(_f64p), _f64p, _Opt(_i32p)])
         L.oracle_bessel_i0.argtypes = [_dbl]
         L.oracle_bessel_i0.restype = _dbl
         L.oracle_gauss_legendre.argtypes = [_int, _f64p, _f64p]
@@ -157,6 +159,18 @@ def estimate(points, lobes_packed, w, width: int, n_cache: int, seed: int, frame
     lib().oracle_estimate(P, *_pts(points), np.ascontiguousarray(lobes_packed, np.float32), wd, width,
                           n_cache, seed, frame, d, int(plug_in), tl, c, r)
     return tl, c, r
+
+
+def estimate_biased(points, lobes_packed, w, width: int, n_cache: int, seed: int, frame: int, rrad=None):
+    """Biased estimate with the balanced termination heuristic at the shading point: (out [P,3],
+    continued [P] int32)."""
+    P = points.count
+    out = np.zeros((P, 3), np.float64)
+    cont = np.zeros(P, np.int32)
+    rr = None if rrad is None else np.ascontiguousarray(rrad, np.float64).reshape(P, 3)
+    lib().oracle_estimate_biased(P, *_pts(points), np.ascontiguousarray(lobes_packed, np.float32), _w64(w), width,
+                                 n_cache, seed, frame, rr, out, cont)
+    return out, cont
 
 
 def bessel_i0(z: float) -> float:

@@ -64,7 +64,7 @@ void oracle_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]
 static double u24(uint32_t r) { return (double)(r >> 8) * (1.0 / 16777216.0); }
 
 /* Counter streams of the method's random numbers. */
-enum { STREAM_CACHE_DIR = 3, STREAM_RESIDUAL_DIR = 4, STREAM_TRAIN = 5 };
+enum { STREAM_CACHE_DIR = 3, STREAM_RESIDUAL_DIR = 4, STREAM_TRAIN = 5, STREAM_TERMINATE = 6 };
 
 /* The two uniforms of sampled direction k of point p in frame f.  One Philox block serves two
  * directions: cache directions k and k+1 (k even) of a point share counter (p, k/2, f, 3); the
@@ -373,6 +373,53 @@ void oracle_estimate(int64_t P, const float *px, const float *py, const float *p
             if (out_tl) out_tl[3 * p + c] = Fc + fr[c];
         }
     }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Biased estimator with the Balanced Termination Heuristic at the shading point (Sec. "Path
+ * Termination Heuristics", first vertex): the path's scattering direction w_s is drawn from the
+ * BRDF (cosine-weighted, pdf p = cos/pi; it is the residual direction of the two-level
+ * estimator, same Philox stream), the continuation probability is P_s = p / (p + N/pi) =
+ * cos / (cos + N), and a uniform xi from counter (p >> 2, 0, frame, STREAM_TERMINATE), word
+ * p & 3, decides: xi > P_s stops the path and shades with the N cache samples (F_c); otherwise
+ * the path continues and its radiance L(x, w_s) is the estimate (f_r cos / p = 1).
+ * The decision is taken without a square root: with cos = sqrt(1 - u1) of the sampler,
+ * xi > cos / (cos + N)  <=>  (xi N)^2 > (1 - u1) (1 - xi)^2, in FP64 products only.
+ * rrad (nullable): the radiance found along w_s (the field otherwise).  cont[p] = 1 where the
+ * path continues. */
+void oracle_estimate_biased(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
+                            const float *ny, const float *nz, const float *rough, const float *lobes,
+                            const double *w, int width, int n_cache, uint64_t seed, uint64_t frame,
+                            const double *rrad, double *out, int32_t *cont)
+{
+    double *fc = (double *)malloc(sizeof(double) * 3 * (size_t)(P > 0 ? P : 1));
+    oracle_estimate(P, px, py, pz, nx, ny, nz, rough, lobes, w, width, n_cache, seed, frame, NULL, 0, NULL, fc,
+                    NULL);
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < P; ++p) {
+        double u1, u2, ws[3];
+        const double n[3] = {nx[p], ny[p], nz[p]};
+        direction_uniforms(seed, (uint32_t)p, n_cache, 1, (uint32_t)frame, &u1, &u2);
+        cosine_direction(n, u1, u2, ws);
+        uint32_t ctr[4] = {(uint32_t)p >> 2, 0u, (uint32_t)frame, STREAM_TERMINATE}, r[4];
+        oracle_philox(ctr, key, r);
+        const double xi = u24(r[p & 3]);
+        const double a = xi * (double)n_cache, b = 1.0 - xi;
+        const int stop = a * a > (1.0 - u1) * (b * b);
+        if (cont) cont[p] = !stop;
+        if (stop) {
+            for (int c = 0; c < 3; ++c) out[3 * p + c] = fc[3 * p + c];
+        } else if (rrad) {
+            for (int c = 0; c < 3; ++c) out[3 * p + c] = rrad[3 * p + c];
+        } else {
+            const double x[3] = {px[p], py[p], pz[p]};
+            field_eval(&L, x, ws, out + 3 * p);
+        }
+    }
+    free(fc);
 }
 
 /* ------------------------------------------------------------------------------------------ */

@@ -451,6 +451,53 @@ def test_gradient_stop_gradient_is_honoured():
 
 
 # ------------------------------------------------------------------------------------------
+# Biased estimator with the balanced termination heuristic (Sec. "Path Termination Heuristics")
+
+@pytest.mark.parametrize("N", [1, 4, 16])
+def test_bth_continuation_fraction_closed_form(N):
+    # cos(theta) of a cosine-weighted direction has density 2c on [0, 1], so the expected
+    # continuation probability is int_0^1 c / (c + N) 2c dc = 2 (1/2 - N + N^2 ln((N + 1) / N))
+    P = 200_000
+    pts = wl.make_points(21, P)
+    lobes = wl.make_lobes(21).packed()
+    w = wl.make_weights(21, 64)
+    _, cont = oracle.estimate_biased(pts, lobes, w, 64, N, 3, 0)
+    expect = 2.0 * (0.5 - N + N * N * math.log((N + 1.0) / N))
+    sd = math.sqrt(expect * (1 - expect) / P)
+    assert abs(cont.mean() - expect) < 5 * sd, (cont.mean(), expect)
+
+
+def test_bth_decision_and_outputs():
+    # the squared-form decision equals the paper's xi > P_s with P_s = p / (p + N / pi),
+    # p = cos / pi, where xi is not within rounding of P_s; stopped points carry F_c, continued
+    # points the field (or the given radiance) along the scattering direction
+    P, N, seed, frame = 20_000, 4, 9, 2
+    pts = wl.make_points(22, P)
+    lobes = wl.make_lobes(22).packed()
+    w = wl.make_weights(22, 64)
+    out, cont = oracle.estimate_biased(pts, lobes, w, 64, N, seed, frame)
+    _, fc, _ = oracle.estimate(pts, lobes, w, 64, N, seed, frame)
+    dirs = oracle.sample_dirs(pts, N, seed, frame)[:, N, :]
+    n = np.stack([pts.nx, pts.ny, pts.nz], 1).astype(np.float64)
+    cos = (n * dirs).sum(1)
+    p_s = (cos / np.pi) / (cos / np.pi + N / np.pi)
+    xi = np.array([(int(oracle.philox([p >> 2, 0, frame, 6], [seed & 0xFFFFFFFF, seed >> 32])[p & 3]) >> 8)
+                   * 2.0 ** -24 for p in range(P)])
+    clear = np.abs(xi - p_s) > 1e-9
+    assert clear.sum() > P - 5
+    np.testing.assert_array_equal(cont[clear] == 0, (xi > p_s)[clear])
+    stop = cont == 0
+    np.testing.assert_array_equal(out[stop], fc[stop])
+    np.testing.assert_array_equal(out[~stop], oracle.field(lobes, pts, None, dirs)[~stop])
+    assert 0 < (~stop).sum() < P
+    R = np.random.default_rng(0).uniform(0, 1, (P, 3))
+    out2, cont2 = oracle.estimate_biased(pts, lobes, w, 64, N, seed, frame, rrad=R)
+    np.testing.assert_array_equal(cont2, cont)
+    np.testing.assert_array_equal(out2[~stop], R[~stop])
+    np.testing.assert_array_equal(out2[stop], fc[stop])
+
+
+# ------------------------------------------------------------------------------------------
 # Loss variants of Sec. "Radiance Cache Optimization": plain L2 and the residual-variance loss
 
 @pytest.mark.parametrize("kind", [oracle.LOSS_L2, oracle.LOSS_VAR])
