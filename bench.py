@@ -246,6 +246,34 @@ def train_convergence(nirc, dp, lobes_for, W, seed, frames=300, batches=(1 << 16
     return out
 
 
+def biased_compare(nirc, model32, dp, lobes_for, table, fs, P, N, seed, frame, reps):
+    """The biased estimator with the balanced termination heuristic beside the unbiased two-level
+    estimator, on the FP32 model's current weights at FP32 and BF16: time per call (fused
+    estimator + decision kernel), fraction of continued paths, MRSE of both against the exact
+    integral."""
+    import torch
+    stream = torch.cuda.current_stream()
+    w = model32.get_weights()
+    lob = nirc.lobes_struct(lobes_for(frame))
+    out = {}
+    for name, prec in (("fp32", 0), ("bf16", 1)):
+        m = model32 if prec == 0 else nirc.Model(w, cfg=nirc.make_config(precision=prec), max_batch=0)
+        b, c, cont = nirc.tlmc_estimate_biased(m, dp, lob, N, seed, frame)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            nirc.tlmc_estimate_biased(m, dp, lob, N, seed, frame, out=b)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        tl = nirc.tlmc_estimate(m, dp, lob, N, seed, frame)
+        mrse_b = float(nirc.tlmc_frame_stats(dp, lob, table, b, fs=fs)[4].item())
+        mrse_u = float(nirc.tlmc_frame_stats(dp, lob, table, tl, fs=fs)[4].item())
+        out[name] = {"ms_biased": ev[0].elapsed_time(ev[1]) / reps, "continued_fraction": float(cont.float().mean()),
+                     "mrse_biased": mrse_b, "mrse_unbiased": mrse_u}
+    return out
+
+
 def loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S):
     """The three training losses of the optimisation section (relative L2, plain L2, residual
     variance), each training its own FP32 cache from the same weights over the same rotating
@@ -505,6 +533,8 @@ def main():
     if not args.no_precision_compare:
         result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
                                                         args.warmup + args.steps, args.steps, B, S)
+        result["biased_bth"] = biased_compare(nirc, model, dp, lobes_for, table, fs, P, N, seed,
+                                              args.warmup + args.steps, min(args.steps, 20))
         result["precision_trained"] = precision_trained(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
     if args.precision_form:
         result["precision_form"] = precision_form(nirc, model.get_weights(), dp, lobes_for(args.warmup + args.steps),

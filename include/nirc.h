@@ -200,6 +200,23 @@ nirc_status tlmc_estimate(const nirc_model *model, nirc_points points,
                           uint64_t frame, const float *residual_radiance /* nullable */,
                           float *out_tl, float *out_c, float *out_r, void *stream);
 
+/* The biased estimator with the Balanced Termination Heuristic at the shading point (Sec. "Path
+ * Termination Heuristics", first path vertex).  The path's scattering direction w_s is drawn from
+ * the BRDF (cosine-weighted, pdf p = cos/pi) — it is the residual direction of tlmc_estimate,
+ * entry n_cache of tlmc_sample_dirs — and continues with probability
+ *   P_s = p / (p + N/pi) = cos / (cos + N):
+ * a uniform xi (Philox counter (p >> 2, 0, frame, 6), word p & 3) stops the path if xi > P_s,
+ * and the point is then shaded by the N cache samples alone, out = F_c; otherwise the path goes
+ * on and its radiance L(x, w_s) is the estimate (residual_radiance when given — the renderer
+ * traces the continued paths — else the field).  The decision is taken in FP64 from the exact
+ * 24-bit uniforms ((xi N)^2 > (1 - u1)(1 - xi)^2 with cos = sqrt(1 - u1)).
+ * out_b [points.count][3]; out_c [points.count][3] (required: F_c); out_continue
+ * [points.count] int32, 1 where the path continues (nullable). */
+nirc_status tlmc_estimate_biased(const nirc_model *model, nirc_points points,
+                                 const nirc_lobes *field /* host */, int32_t n_cache, uint64_t seed,
+                                 uint64_t frame, const float *residual_radiance /* nullable */,
+                                 float *out_b, float *out_c, int32_t *out_continue, void *stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Continuous batching of estimates (several render streams, each with its own cache)         */
 

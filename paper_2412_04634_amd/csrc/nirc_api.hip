@@ -280,6 +280,20 @@ nirc_status tlmc_estimate(const nirc_model *model, nirc_points points, const nir
                                   (hipStream_t)stream));
 }
 
+nirc_status tlmc_estimate_biased(const nirc_model *model, nirc_points points, const nirc_lobes *field,
+                                 int32_t n_cache, uint64_t seed, uint64_t frame, const float *residual_radiance,
+                                 float *out_b, float *out_c, int32_t *out_continue, void *stream) {
+    if (points.count > 0 && (!out_b || !out_c)) return NIRC_ERR_INVALID_ARG;
+    // F_c (and F_tl, overwritten below) by the fused estimator, then the per-point decision
+    nirc_status st = tlmc_estimate(model, points, field, n_cache, seed, frame, residual_radiance, out_b, out_c,
+                                   nullptr, stream);
+    if (st != NIRC_OK || points.count == 0) return st;
+    nirc_lobes none;
+    memset(&none, 0, sizeof(none));
+    return hip_status(launch_bth(to_points(points), field ? *field : none, n_cache, seed, frame, residual_radiance,
+                                 out_c, out_b, out_continue, (hipStream_t)stream));
+}
+
 nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field, int64_t batch, uint64_t seed,
                              uint64_t frame, uint32_t step, int32_t *point, float *wx, float *wy, float *wz,
                              float *target, void *stream) {

@@ -15,7 +15,7 @@ constexpr int kFreq = 8;
 constexpr int kFeat = 160;
 constexpr int kSurfInputs = 7;   // x0 x1 x2 n0 n1 n2 roughness
 constexpr int kDirInputs = 3;    // w0 w1 w2
-constexpr int kStreamCacheDir = 3, kStreamResidualDir = 4, kStreamTrain = 5;
+constexpr int kStreamCacheDir = 3, kStreamResidualDir = 4, kStreamTrain = 5, kStreamTerminate = 6;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 

@@ -69,6 +69,49 @@ __global__ void k_sample_dirs(Points pts, int n_cache, uint32_t key0, uint32_t k
     dirs[3 * t + 2] = wz;
 }
 
+// Biased estimate with the balanced termination heuristic at the shading point, one thread per
+// point, after the fused estimator has written F_c: the path's scattering direction is the
+// residual direction (same Philox stream, same FP32 map, so the same direction as the fused
+// kernel's), P_s = cos / (cos + N) for the cosine pdf, and xi (counter (p >> 2, 0, frame, 6),
+// word p & 3) stops the path when xi > P_s, i.e. when (xi N)^2 > (1 - u1) (1 - xi)^2 with
+// cos = sqrt(1 - u1): FP64 products of exact 24-bit uniforms, so the decision does not depend
+// on the FP32 rounding of the direction.  Stopped: F_c; continued: the radiance along the
+// direction (rrad, or the field).
+__global__ void k_bth(Points pts, nirc_lobes lobes, int n_cache, uint32_t key0, uint32_t key1, uint32_t frame,
+                      const float *__restrict__ rrad, const float *__restrict__ fc, float *__restrict__ out,
+                      int32_t *__restrict__ cont) {
+#pragma clang fp contract(off)
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pts.count) return;
+    const DirCounter dc = dir_counter((uint32_t)p, n_cache, true);
+    const Rand4 r = philox(dc.c0, dc.c1, frame, dc.stream, key0, key1);
+    const float u1 = u24(dc.half ? r.r[2] : r.r[0]);
+    const Rand4 rt = philox((uint32_t)p >> 2, 0u, frame, (uint32_t)kStreamTerminate, key0, key1);
+    const int q = (int)(p & 3);
+    const uint32_t word = q == 0 ? rt.r[0] : q == 1 ? rt.r[1] : q == 2 ? rt.r[2] : rt.r[3];
+    const double xi = (double)u24(word);
+    const double a = xi * (double)n_cache, b = 1.0 - xi;
+    const bool stop = a * a > (1.0 - (double)u1) * (b * b);
+    if (cont) cont[p] = stop ? 0 : 1;
+    float v[3];
+    if (stop) {
+        v[0] = fc[3 * p];
+        v[1] = fc[3 * p + 1];
+        v[2] = fc[3 * p + 2];
+    } else if (rrad) {
+        v[0] = rrad[3 * p];
+        v[1] = rrad[3 * p + 1];
+        v[2] = rrad[3 * p + 2];
+    } else {
+        float wx, wy, wz;
+        dir_from_rand(r, dc.half, pts.nx[p], pts.ny[p], pts.nz[p], wx, wy, wz);
+        field_eval(lobes, pts.px[p], pts.py[p], pts.pz[p], wx, wy, wz, v);
+    }
+    out[3 * p] = v[0];
+    out[3 * p + 1] = v[1];
+    out[3 * p + 2] = v[2];
+}
+
 // Training samples: one thread per sample.
 __global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint32_t key0,
                               uint32_t key1, uint32_t frame, uint32_t step, int32_t *point,
@@ -354,6 +397,14 @@ hipError_t launch_sample_dirs(const Points &pts, int n_cache, uint64_t seed, uin
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sample_dirs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts, n_cache,
                        (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, dirs);
+    return hipGetLastError();
+}
+
+hipError_t launch_bth(const Points &pts, const nirc_lobes &lobes, int n_cache, uint64_t seed, uint64_t frame,
+                      const float *rrad, const float *fc, float *out, int32_t *cont, hipStream_t s) {
+    if (pts.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bth, dim3((unsigned)((pts.count + 255) / 256)), dim3(256), 0, s, pts, lobes, n_cache,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, rrad, fc, out, cont);
     return hipGetLastError();
 }
 

@@ -394,6 +394,10 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
                            float *out_r, hipStream_t s);
 hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
                         hipStream_t s);
+// Biased estimate (balanced termination heuristic) from F_c written by launch_tlmc: out [P][3],
+// cont [P] (1 = the path continues) or NULL.
+hipError_t launch_bth(const Points &pts, const nirc_lobes &lobes, int n_cache, uint64_t seed, uint64_t frame,
+                      const float *rrad, const float *fc, float *out, int32_t *cont, hipStream_t s);
 // rrad: residual radiance [P][3] (a renderer's sample), or NULL to evaluate the lobe field
 hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
                        int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,

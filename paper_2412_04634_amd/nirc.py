@@ -86,6 +86,8 @@ def lib():
             "tlmc_sample_dirs": (_i32, [_Points, _i32, _u64, _u64, _vp, _vp]),
             "tlmc_estimate": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp, _vp,
                                      _vp]),
+            "tlmc_estimate_biased": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp,
+                                            _vp, _vp]),
             "tlmc_train_batch": (_i32, [_Points, ctypes.POINTER(Lobes), _i64, _u64, _u64, _u32, _vp, _vp, _vp,
                                         _vp, _vp, _vp]),
             "nirc_loss_grad": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp, _vp]),
@@ -305,6 +307,23 @@ def tlmc_estimate(model: Model, points: Points, lobes, n_cache: int, seed: int, 
     _check(lib().tlmc_estimate(model.handle, points.c(), None if L is None else ctypes.byref(L), n_cache, seed,
                                frame, _ptr(residual), _ptr(tl), _ptr(c), _ptr(r), _stream()), "tlmc_estimate")
     return (tl, c, r) if parts else tl
+
+
+def tlmc_estimate_biased(model: Model, points: Points, lobes, n_cache: int, seed: int, frame: int,
+                         residual=None, out=None):
+    """Biased estimate with the balanced termination heuristic: (out [P,3], F_c [P,3],
+    continued [P] int32)."""
+    dev = points.t[0].device
+    L = None if lobes is None else (lobes if isinstance(lobes, Lobes) else lobes_struct(lobes))
+    b = out if out is not None else torch.empty((points.count, 3), dtype=torch.float32, device=dev)
+    c = torch.empty_like(b)
+    cont = torch.empty(points.count, dtype=torch.int32, device=dev)
+    if residual is not None:
+        assert residual.dtype == torch.float32 and residual.is_contiguous() and residual.numel() == 3 * points.count
+    _check(lib().tlmc_estimate_biased(model.handle, points.c(), None if L is None else ctypes.byref(L), n_cache, seed,
+                                      frame, _ptr(residual), _ptr(b), _ptr(c), _ptr(cont), _stream()),
+           "tlmc_estimate_biased")
+    return b, c, cont
 
 
 def tlmc_train_batch(points: Points, lobes, batch: int, seed: int, frame: int, step: int):
