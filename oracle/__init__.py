@@ -51,11 +51,13 @@ def lib():
         L.oracle_philox.restype = None
         L.oracle_sample_dirs.argtypes = [_i64, _f32p, _f32p, _f32p, _Opt(_i64p), _int, _u64, _u64, _f64p]
         L.oracle_encode.argtypes = [_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p]
-        L.oracle_infer.argtypes = [_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _int, _f64p]
+        L.oracle_infer.argtypes = [_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _int, _int, _f64p]
+        L.oracle_visibility.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _Opt(_i32p), _f64p, _f64p]
+        L.oracle_quadrature.argtypes = [_i64] + [_f32p] * 6 + [_f32p, _int, _int, _f64p]
         L.oracle_field.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p, _Opt(_i32p), _f64p, _f64p]
-        L.oracle_estimate.argtypes = ([_i64] + [_f32p] * 7 + [_f32p, _f64p, _int, _int, _u64, _u64,
+        L.oracle_estimate.argtypes = ([_i64] + [_f32p] * 7 + [_f32p, _f64p, _int, _int, _int, _u64, _u64,
                                       _Opt(_f64p), _int, _Opt(_f64p), _Opt(_f64p), _Opt(_f64p)])
-        L.oracle_estimate_biased.argtypes = ([_i64] + [_f32p] * 7 + [_f32p, _f64p, _int, _int, _u64, _u64,
+        L.oracle_estimate_biased.argtypes = ([_i64] + [_f32p] * 7 + [_f32p, _f64p, _int, _int, _int, _u64, _u64,
                                              _Opt(_f64p), _f64p, _Opt(_i32p)])
         L.oracle_bessel_i0.argtypes = [_dbl]
         L.oracle_bessel_i0.restype = _dbl
@@ -64,11 +66,11 @@ def lib():
         L.oracle_J.restype = _dbl
         L.oracle_closed_form.argtypes = [_i64] + [_f32p] * 6 + [_f32p, _int, _f64p]
         L.oracle_second_moment.argtypes = [_i64] + [_f32p] * 6 + [_f32p, _int, _f64p]
-        L.oracle_loss_grad.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _f64p, _int,
+        L.oracle_loss_grad.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _f64p, _int, _int,
                                        _dbl, _int, _int, _Opt(_f64p)])
         L.oracle_loss_grad.restype = _dbl
         L.oracle_adam.argtypes = [_i64, _f64p, _f64p, _f64p, _f64p, _i64, _dbl, _dbl, _dbl, _dbl]
-        L.oracle_train_batch.argtypes = ([_i64] + [_f32p] * 6 + [_f32p, _i64, _u64, _u64, ctypes.c_uint32,
+        L.oracle_train_batch.argtypes = ([_i64] + [_f32p] * 6 + [_f32p, _i64, _u64, _u64, ctypes.c_uint32, _int,
                                          _i32p, _f64p, _f64p])
         L.oracle_n_params.argtypes = [_int]
         L.oracle_n_params.restype = _i64
@@ -128,12 +130,37 @@ def encode(points, point_idx, dirs) -> np.ndarray:
     return out
 
 
-def infer(points, point_idx, dirs, w, width: int) -> np.ndarray:
+OUTPUT_RADIANCE, OUTPUT_VISIBILITY = 0, 1
+
+
+def infer(points, point_idx, dirs, w, width: int, output: int = OUTPUT_RADIANCE) -> np.ndarray:
+    """Cache predictions for explicit queries (the visibility for output 1)."""
     dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
     Q = dirs.shape[0]
     out = np.zeros((Q, 3), np.float64)
     idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
-    lib().oracle_infer(Q, *_pts(points), idx, dirs, _w64(w), width, out)
+    lib().oracle_infer(Q, *_pts(points), idx, dirs, _w64(w), width, int(output), out)
+    return out
+
+
+def visibility(lobes_packed, points, point_idx, dirs) -> np.ndarray:
+    """The synthetic visibility V(x, w) of the visibility-cache workload, [Q] FP64."""
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    Q = dirs.shape[0]
+    out = np.zeros(Q, np.float64)
+    idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
+    p = _pts(points)
+    lib().oracle_visibility(Q, np.ascontiguousarray(lobes_packed, np.float32), p[0], p[1], p[2], idx, dirs, out)
+    return out
+
+
+def quadrature(points, lobes_packed, output: int = OUTPUT_RADIANCE, n_nodes: int = 256) -> np.ndarray:
+    """F = (1/pi) int V L cos over the hemisphere by tensor Gauss-Legendre quadrature, [P, 3]."""
+    P = points.count
+    out = np.zeros((P, 3), np.float64)
+    p = _pts(points)
+    lib().oracle_quadrature(P, p[0], p[1], p[2], p[3], p[4], p[5], np.ascontiguousarray(lobes_packed, np.float32),
+                            int(output), n_nodes, out)
     return out
 
 
@@ -148,7 +175,7 @@ def field(lobes_packed, points, point_idx, dirs) -> np.ndarray:
 
 
 def estimate(points, lobes_packed, w, width: int, n_cache: int, seed: int, frame: int,
-             dirs=None, plug_in: bool = False):
+             dirs=None, plug_in: bool = False, output: int = OUTPUT_RADIANCE):
     """Two-level estimator per point: returns (F_tl, F_c, F_r), each [P, 3] FP64."""
     P = points.count
     tl = np.zeros((P, 3), np.float64)
@@ -156,12 +183,13 @@ def estimate(points, lobes_packed, w, width: int, n_cache: int, seed: int, frame
     r = np.zeros((P, 3), np.float64)
     d = None if dirs is None else np.ascontiguousarray(dirs, np.float64).reshape(P * (n_cache + 1) * 3)
     wd = _w64(w) if w is not None else np.zeros(n_params(width), np.float64)
-    lib().oracle_estimate(P, *_pts(points), np.ascontiguousarray(lobes_packed, np.float32), wd, width,
+    lib().oracle_estimate(P, *_pts(points), np.ascontiguousarray(lobes_packed, np.float32), wd, width, int(output),
                           n_cache, seed, frame, d, int(plug_in), tl, c, r)
     return tl, c, r
 
 
-def estimate_biased(points, lobes_packed, w, width: int, n_cache: int, seed: int, frame: int, rrad=None):
+def estimate_biased(points, lobes_packed, w, width: int, n_cache: int, seed: int, frame: int, rrad=None,
+                    output: int = OUTPUT_RADIANCE):
     """Biased estimate with the balanced termination heuristic at the shading point: (out [P,3],
     continued [P] int32)."""
     P = points.count
@@ -169,7 +197,7 @@ def estimate_biased(points, lobes_packed, w, width: int, n_cache: int, seed: int
     cont = np.zeros(P, np.int32)
     rr = None if rrad is None else np.ascontiguousarray(rrad, np.float64).reshape(P, 3)
     lib().oracle_estimate_biased(P, *_pts(points), np.ascontiguousarray(lobes_packed, np.float32), _w64(w), width,
-                                 n_cache, seed, frame, rr, out, cont)
+                                 int(output), n_cache, seed, frame, rr, out, cont)
     return out, cont
 
 
@@ -212,7 +240,7 @@ LOSS_REL_L2, LOSS_L2, LOSS_VAR = 0, 1, 2
 
 
 def loss_grad(points, point_idx, dirs, target, w, width: int, eps: float = 1e-2, frozen: bool = True,
-              want_grad: bool = True, kind: int = LOSS_REL_L2):
+              want_grad: bool = True, kind: int = LOSS_REL_L2, output: int = 0):
     """Training loss (kind: relative L2, plain L2 or the residual-variance loss) and its weight
     gradient (FP64)."""
     dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
@@ -220,7 +248,7 @@ def loss_grad(points, point_idx, dirs, target, w, width: int, eps: float = 1e-2,
     g = np.zeros(n_params(width), np.float64) if want_grad else None
     idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
     loss = lib().oracle_loss_grad(B, *_pts(points), idx, dirs, np.ascontiguousarray(target, np.float64).reshape(-1),
-                                  _w64(w), width, eps, int(frozen), int(kind), g)
+                                  _w64(w), width, int(output), eps, int(frozen), int(kind), g)
     return float(loss), g
 
 
@@ -229,14 +257,15 @@ def adam(w, m, v, g, t: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.99
     lib().oracle_adam(w.shape[0], w, m, v, np.ascontiguousarray(g, np.float64), t, lr, b1, b2, eps)
 
 
-def train_batch(points, lobes_packed, B: int, seed: int, frame: int, step: int):
+def train_batch(points, lobes_packed, B: int, seed: int, frame: int, step: int, output: int = 0):
     """Training samples of one step: (point index [B] int32, directions [B,3], targets [B,3])."""
     idx = np.zeros(B, np.int32)
     d = np.zeros((B, 3), np.float64)
     t = np.zeros((B, 3), np.float64)
     p = _pts(points)
     lib().oracle_train_batch(points.count, p[0], p[1], p[2], p[3], p[4], p[5],
-                             np.ascontiguousarray(lobes_packed, np.float32), B, seed, frame, step, idx, d, t)
+                             np.ascontiguousarray(lobes_packed, np.float32), B, seed, frame, step, int(output), idx, d,
+                             t)
     return idx, d, t
 
 

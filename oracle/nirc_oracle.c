@@ -173,10 +173,13 @@ void oracle_encode(int64_t Q, const float *px, const float *py, const float *pz,
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* MLP: h1 = ReLU(W1 e), h_l = ReLU(W_l h_{l-1}) (l = 2..4), z = W5 h4, y = exp(z).
+/* MLP: h1 = ReLU(W1 e), h_l = ReLU(W_l h_{l-1}) (l = 2..4), z = W5 h4, y = exp(z) for the
+ * radiance cache (output 0) or y = 1 / (1 + exp(-z)) for the visibility cache (output 1, Sec.
+ * "Neural Visibility Cache": visibility lies in [0, 1], hence a sigmoid on the outputs).
  * Canonical parameter vector: W1 [W x 160], W2, W3, W4 [W x W], W5 [3 x W], row-major.       */
 typedef struct {
     int width;
+    int vis;   /* 1: sigmoid outputs (visibility cache) */
     const double *W[5];
     int rows[5], cols[5];
 } net_t;
@@ -207,6 +210,7 @@ void oracle_set_threads(int n)
 static void net_setup(net_t *net, const double *w, int width)
 {
     net->width = width;
+    net->vis = 0;
     int rows[5] = {width, width, width, width, 3};
     int cols[5] = {NFEAT, width, width, width, width};
     size_t off = 0;
@@ -242,18 +246,20 @@ static void net_forward(const net_t *net, const double e[NFEAT], acts_t *a)
         double s = 0.0;
         for (int c = 0; c < net->cols[4]; ++c) s += net->W[4][(size_t)r * net->cols[4] + c] * x[c];
         a->zo[r] = s;
-        a->y[r] = exp(s);
+        a->y[r] = net->vis ? 1.0 / (1.0 + exp(-s)) : exp(s);
     }
 }
 
-/* Cache prediction for explicit queries (point index + direction). */
+/* Cache prediction for explicit queries (point index + direction); output 1: the visibility. */
 void oracle_infer(int64_t Q, const float *px, const float *py, const float *pz, const float *nx,
                   const float *ny, const float *nz, const float *rough, const int32_t *point,
-                  const double *dirs /* [Q][3] */, const double *w, int width, double *rgb /* [Q][3] */)
+                  const double *dirs /* [Q][3] */, const double *w, int width, int output,
+                  double *rgb /* [Q][3] */)
 {
     const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
     net_t net;
     net_setup(&net, w, width);
+    net.vis = output == 1;
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < Q; ++q) {
         double in[NIN], e[NFEAT];
@@ -303,6 +309,30 @@ static void field_eval(const lobes_t *L, const double x[3], const double w[3], d
     }
 }
 
+/* Synthetic visibility for the visibility cache (environment lighting, Sec. "Neural Visibility
+ * Cache"): a soft occluder over the first lobe's direction mu_0 that blocks 90 % of it,
+ *   V(x, w) = 1 - 0.9 / (1 + exp(-16 (mu_0 . w - c(x)))),   c(x) = 0.6 + 0.3 (x_0 - 0.5),
+ * so the occluded cap grows and shrinks across the scene; V is in [0.1, 1] and smooth.       */
+static double visibility(const lobes_t *L, const double x[3], const double w[3])
+{
+    const double m = L->axis[0][0] * w[0] + L->axis[0][1] * w[1] + L->axis[0][2] * w[2];
+    const double c = 0.6 + 0.3 * (x[0] - 0.5);
+    return 1.0 - 0.9 / (1.0 + exp(-16.0 * (m - c)));
+}
+
+void oracle_visibility(int64_t Q, const float *lobes, const float *px, const float *py, const float *pz,
+                       const int32_t *point, const double *dirs, double *out)
+{
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) {
+        int64_t p = point ? point[q] : q;
+        double x[3] = {px[p], py[p], pz[p]};
+        out[q] = visibility(&L, x, dirs + 3 * q);
+    }
+}
+
 void oracle_field(int64_t Q, const float *lobes, const float *px, const float *py, const float *pz,
                   const int32_t *point, const double *dirs, double *out)
 {
@@ -324,7 +354,7 @@ void oracle_field(int64_t Q, const float *lobes, const float *px, const float *p
  * plug_in != 0 replaces the network by the field itself (y := L), a special case where F_r = 0. */
 void oracle_estimate(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
                      const float *ny, const float *nz, const float *rough, const float *lobes,
-                     const double *w, int width, int n_cache, uint64_t seed, uint64_t frame,
+                     const double *w, int width, int output, int n_cache, uint64_t seed, uint64_t frame,
                      const double *dirs, int plug_in, double *out_tl, double *out_c, double *out_r)
 {
     const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
@@ -332,6 +362,10 @@ void oracle_estimate(int64_t P, const float *px, const float *py, const float *p
     lobes_unpack(lobes, &L);
     net_t net;
     net_setup(&net, w, width);
+    /* output 1, the visibility cache: incident radiance is the predicted visibility times the
+     * known radiance, n_V(x, w) L(x, w); the residual sample is V(x, w_r) L(x, w_r) minus it */
+    const int vis = output == 1;
+    net.vis = vis;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t p = 0; p < P; ++p) {
         double x[3] = {px[p], py[p], pz[p]};
@@ -347,23 +381,23 @@ void oracle_estimate(int64_t P, const float *px, const float *py, const float *p
                 direction_uniforms(seed, (uint32_t)p, k, k == n_cache, (uint32_t)frame, &u1, &u2);
                 cosine_direction(n, u1, u2, wdir);
             }
-            double y[3];
+            double y[3], Lw[3];
+            field_eval(&L, x, wdir, Lw);
+            const double V = vis ? visibility(&L, x, wdir) : 1.0;
             if (plug_in) {
-                field_eval(&L, x, wdir, y);
+                for (int c = 0; c < 3; ++c) y[c] = V * Lw[c];
             } else {
                 double in[NIN], e[NFEAT];
                 acts_t a;
                 gather_inputs(pts, p, wdir, in);
                 encode_inputs(in, e);
                 net_forward(&net, e, &a);
-                y[0] = a.y[0]; y[1] = a.y[1]; y[2] = a.y[2];
+                for (int c = 0; c < 3; ++c) y[c] = vis ? a.y[c] * Lw[c] : a.y[c];
             }
             if (k < n_cache) {
                 for (int c = 0; c < 3; ++c) fc[c] += y[c];
             } else {
-                double Lr[3];
-                field_eval(&L, x, wdir, Lr);
-                for (int c = 0; c < 3; ++c) fr[c] = Lr[c] - y[c];
+                for (int c = 0; c < 3; ++c) fr[c] = V * Lw[c] - y[c];
             }
         }
         for (int c = 0; c < 3; ++c) {
@@ -389,12 +423,12 @@ void oracle_estimate(int64_t P, const float *px, const float *py, const float *p
  * path continues. */
 void oracle_estimate_biased(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
                             const float *ny, const float *nz, const float *rough, const float *lobes,
-                            const double *w, int width, int n_cache, uint64_t seed, uint64_t frame,
+                            const double *w, int width, int output, int n_cache, uint64_t seed, uint64_t frame,
                             const double *rrad, double *out, int32_t *cont)
 {
     double *fc = (double *)malloc(sizeof(double) * 3 * (size_t)(P > 0 ? P : 1));
-    oracle_estimate(P, px, py, pz, nx, ny, nz, rough, lobes, w, width, n_cache, seed, frame, NULL, 0, NULL, fc,
-                    NULL);
+    oracle_estimate(P, px, py, pz, nx, ny, nz, rough, lobes, w, width, output, n_cache, seed, frame, NULL, 0, NULL,
+                    fc, NULL);
     lobes_t L;
     lobes_unpack(lobes, &L);
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -417,6 +451,10 @@ void oracle_estimate_biased(int64_t P, const float *px, const float *py, const f
         } else {
             const double x[3] = {px[p], py[p], pz[p]};
             field_eval(&L, x, ws, out + 3 * p);
+            if (output == 1) {   /* the continued path meets the occluder */
+                const double V = visibility(&L, x, ws);
+                for (int c = 0; c < 3; ++c) out[3 * p + c] *= V;
+            }
         }
     }
     free(fc);
@@ -564,11 +602,12 @@ void oracle_second_moment(int64_t P, const float *px, const float *py, const flo
 double oracle_loss_grad(int64_t B, const float *px, const float *py, const float *pz, const float *nx,
                         const float *ny, const float *nz, const float *rough, const int32_t *point,
                         const double *dirs, const double *target, const double *w, int width,
-                        double eps, int frozen, int kind, double *grad /* [n_params] or NULL */)
+                        int output, double eps, int frozen, int kind, double *grad /* [n_params] or NULL */)
 {
     const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
     net_t net;
     net_setup(&net, w, width);
+    net.vis = output == 1;   /* sigmoid outputs: dy/dz = y (1 - y) */
     int64_t np = n_params_of(width);
     double loss = 0.0;
     if (grad) memset(grad, 0, sizeof(double) * (size_t)np);
@@ -627,7 +666,7 @@ double oracle_loss_grad(int64_t B, const float *px, const float *py, const float
                 tl[tid] += d * d / den;
                 double dy = 2.0 * d / den;
                 if (!frozen && kind == 0) dy -= d * d * 2.0 * y / (den * den);
-                dz[c] = dy * y / (3.0 * (double)B);
+                dz[c] = dy * (net.vis ? y * (1.0 - y) : y) / (3.0 * (double)B);
             }
             if (!g) continue;
             /* output layer */
@@ -685,7 +724,7 @@ void oracle_adam(int64_t n, double *w, double *m, double *v, const double *g, in
  * cosine-weighted direction about that point's normal; the target is the noise-free field.    */
 void oracle_train_batch(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
                         const float *ny, const float *nz, const float *lobes, int64_t B, uint64_t seed,
-                        uint64_t frame, uint32_t step, int32_t *point, double *dirs, double *target)
+                        uint64_t frame, uint32_t step, int output, int32_t *point, double *dirs, double *target)
 {
     lobes_t L;
     lobes_unpack(lobes, &L);
@@ -699,6 +738,41 @@ void oracle_train_batch(int64_t P, const float *px, const float *py, const float
         double n[3] = {nx[p], ny[p], nz[p]};
         cosine_direction(n, u24(r[1]), u24(r[2]), dirs + 3 * b);
         double x[3] = {px[p], py[p], pz[p]};
-        field_eval(&L, x, dirs + 3 * b, target + 3 * b);
+        if (output == 1) {   /* the visibility cache learns V (the same target in every channel) */
+            const double V = visibility(&L, x, dirs + 3 * b);
+            for (int c = 0; c < 3; ++c) target[3 * b + c] = V;
+        } else {
+            field_eval(&L, x, dirs + 3 * b, target + 3 * b);
+        }
     }
+}
+
+/* Reference integral F(x) = (1/pi) int V(x, w) L(x, w) (n . w) dw (V = 1 for output 0) by tensor
+ * Gauss-Legendre quadrature over the uniforms (u1, u2) of the cosine-weighted map, whose pdf
+ * cancels the cosine: F = int_[0,1]^2 V L (w(u1, u2)) du1 du2.  Test reference only. */
+void oracle_quadrature(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
+                       const float *ny, const float *nz, const float *lobes, int output, int n_nodes, double *F)
+{
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+    double *xs = (double *)malloc(sizeof(double) * (size_t)n_nodes), *ws = (double *)malloc(sizeof(double) * (size_t)n_nodes);
+    oracle_gauss_legendre(n_nodes, xs, ws);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < P; ++p) {
+        const double x[3] = {px[p], py[p], pz[p]};
+        const double n[3] = {nx[p], ny[p], nz[p]};
+        double acc[3] = {0, 0, 0};
+        for (int i = 0; i < n_nodes; ++i)
+            for (int k = 0; k < n_nodes; ++k) {
+                const double u1 = xs[i], u2 = xs[k], wt = ws[i] * ws[k];   /* nodes on [0, 1] */
+                double wd[3], Lw[3];
+                cosine_direction(n, u1, u2, wd);
+                field_eval(&L, x, wd, Lw);
+                const double V = output == 1 ? visibility(&L, x, wd) : 1.0;
+                for (int c = 0; c < 3; ++c) acc[c] += wt * V * Lw[c];
+            }
+        for (int c = 0; c < 3; ++c) F[3 * p + c] = acc[c];
+    }
+    free(xs);
+    free(ws);
 }

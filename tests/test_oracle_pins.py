@@ -451,6 +451,117 @@ def test_gradient_stop_gradient_is_honoured():
 
 
 # ------------------------------------------------------------------------------------------
+# Visibility cache (Sec. "Neural Visibility Cache"): sigmoid outputs times the known radiance
+
+def test_quadrature_reference_matches_closed_form():
+    # the tensor Gauss-Legendre reference used for the occluded workload, on the unoccluded
+    # field, against the closed form (independent: Bessel-function integral).  They agree to
+    # 1.6e-7, not further: the closed form takes the FP32 lobe axes as exact unit vectors, the
+    # field evaluation uses mu . w as stored (|mu| = 1 +- 6e-8, times kappa <= 50)
+    pts = wl.make_points(23, 6)
+    lobes = wl.make_lobes(23).packed()
+    q = oracle.quadrature(pts, lobes, oracle.OUTPUT_RADIANCE, 384)
+    F = oracle.closed_form(pts, lobes)
+    assert np.abs(q - F).max() <= 4e-7 * np.abs(F).max()
+
+
+def test_visibility_special_values():
+    lob = wl.make_lobes(24)
+    packed = lob.packed()
+    mu = np.asarray(lob.axis[0], np.float64)
+    perp = np.cross(mu, [1.0, 0.0, 0.0] if abs(mu[0]) < 0.9 else [0.0, 1.0, 0.0])
+    perp /= np.linalg.norm(perp)
+    pts = wl.Points(*[np.full(2, 0.5, np.float32) for _ in range(7)])
+    v = oracle.visibility(packed, pts, None, np.stack([mu, perp]))
+    sig = lambda t: 1.0 / (1.0 + math.exp(-t))
+    # (the FP32 axis is a unit vector to 1e-7, so mu . mu = 1 to that accuracy)
+    assert v[0] == pytest.approx(1.0 - 0.9 * sig(16.0 * (1.0 - 0.6)), rel=1e-7)
+    assert v[1] == pytest.approx(1.0 - 0.9 * sig(16.0 * (0.0 - 0.6)), rel=1e-7)
+    # training targets of the visibility cache are V in every channel
+    P = 50
+    pts = wl.make_points(24, P)
+    idx, d, t = oracle.train_batch(pts, packed, 200, 3, 0, 0, output=oracle.OUTPUT_VISIBILITY)
+    vv = oracle.visibility(packed, pts, idx, d)
+    np.testing.assert_array_equal(t, np.repeat(vv[:, None], 3, 1))
+    assert (vv >= 0.1).all() and (vv <= 1.0).all()
+
+
+def test_visibility_cache_special_cases():
+    P, N, W = 40, 8, 64
+    pts = wl.make_points(25, P)
+    lobes = wl.make_lobes(25).packed()
+    w = wl.make_weights(25, W).copy()
+    dirs = oracle.sample_dirs(pts, N, 4, 1)
+    idx = np.repeat(np.arange(P), N + 1)
+    L = oracle.field(lobes, pts, idx, dirs.reshape(-1, 3)).reshape(P, N + 1, 3)
+    V = oracle.visibility(lobes, pts, idx, dirs.reshape(-1, 3)).reshape(P, N + 1)
+    # zero output layer: sigmoid(0) = 1/2, so F_c is half the mean radiance of the cache directions
+    w0 = w.copy()
+    w0[-3 * W:] = 0.0
+    _, c, r = oracle.estimate(pts, lobes, w0, W, N, 4, 1, output=oracle.OUTPUT_VISIBILITY)
+    np.testing.assert_allclose(c, 0.5 * L[:, :N].mean(1), rtol=1e-13)
+    np.testing.assert_allclose(r, (V[:, N, None] - 0.5) * L[:, N], rtol=1e-12, atol=1e-15)
+    # the exact integrand in place of the network: no residual, F_c the mean of V L
+    tl, c, r = oracle.estimate(pts, lobes, None, W, N, 4, 1, plug_in=True, output=oracle.OUTPUT_VISIBILITY)
+    assert np.abs(r).max() == 0.0
+    np.testing.assert_allclose(c, (V[:, :N, None] * L[:, :N]).mean(1), rtol=1e-13)
+    # the network's visibility prediction is a sigmoid of the radiance cache's log-output
+    y_rad = oracle.infer(pts, idx, dirs.reshape(-1, 3), w, W)
+    y_vis = oracle.infer(pts, idx, dirs.reshape(-1, 3), w, W, output=oracle.OUTPUT_VISIBILITY)
+    np.testing.assert_allclose(y_vis, y_rad / (1.0 + y_rad), rtol=1e-13)
+
+
+def test_visibility_cache_estimator_unbiased():
+    # mean over seeds of the two-level estimate with the visibility cache (random weights)
+    # against the quadrature of V L: aggregate z over points and channels
+    P, N, S, W = 24, 4, 600, 64
+    pts = wl.make_points(26, P)
+    lobes = wl.make_lobes(26).packed()
+    w = wl.make_weights(26, W)
+    F = oracle.quadrature(pts, lobes, oracle.OUTPUT_VISIBILITY, 256)
+    est = np.stack([oracle.estimate(pts, lobes, w, W, N, 1000 + s, 0, output=oracle.OUTPUT_VISIBILITY)[0]
+                    for s in range(S)])
+    mean, var = est.mean(0), est.var(0, ddof=1)
+    Z = (mean - F).sum() / math.sqrt((var / S).sum())
+    assert abs(Z) < 4.5, Z
+
+
+def test_visibility_cache_gradient_finite_differences():
+    width, B = 64, 6
+    pts = wl.make_points(27, 32)
+    lobes = wl.make_lobes(27).packed()
+    w = wl.make_weights(27, width).astype(np.float64)
+    idx, dirs, target = oracle.train_batch(pts, lobes, B, 9, 0, 0, output=oracle.OUTPUT_VISIBILITY)
+    vis = oracle.OUTPUT_VISIBILITY
+    loss, g = oracle.loss_grad(pts, idx, dirs, target, w, width, output=vis)
+    feat = npref.encode(npref.inputs_of(pts, idx, dirs))
+    y0, pre0 = npref.forward(feat, w, width)
+    s0 = y0 / (1.0 + y0)              # sigmoid(z) = e^z / (1 + e^z)
+    den = s0 ** 2 + 1e-2
+    assert loss == pytest.approx(((s0 - target) ** 2 / den).sum() / (3 * B), rel=1e-12)
+    rng = np.random.default_rng(2)
+    n = w.shape[0]
+    check = np.concatenate([rng.choice(n, 150, replace=False), np.arange(n - 3 * width, n - 3 * width + 20)])
+    h = 1e-4
+    used = 0
+    for i in check:
+        wp = w.copy(); wp[i] += h
+        wm = w.copy(); wm[i] -= h
+        yp, prep = npref.forward(feat, wp, width)
+        ym, prem = npref.forward(feat, wm, width)
+        if any(np.any((a > 0) != (b > 0)) or np.any((a > 0) != (c > 0)) for a, b, c in zip(pre0, prep, prem)):
+            continue
+        sp, sm_ = yp / (1 + yp), ym / (1 + ym)
+        lp = ((sp - target) ** 2 / den).sum() / (3 * B)   # denominator held at w (stop-gradient)
+        lm = ((sm_ - target) ** 2 / den).sum() / (3 * B)
+        fd = (lp - lm) / (2 * h)
+        scale = max(abs(fd), 1e-6 * np.abs(g).max())
+        assert abs(fd - g[i]) <= 1e-6 * scale + 1e-11, (i, fd, g[i])
+        used += 1
+    assert used > 140
+
+
+# ------------------------------------------------------------------------------------------
 # Biased estimator with the balanced termination heuristic (Sec. "Path Termination Heuristics")
 
 @pytest.mark.parametrize("N", [1, 4, 16])
