@@ -130,7 +130,7 @@ def encode(points, point_idx, dirs) -> np.ndarray:
     return out
 
 
-OUTPUT_RADIANCE, OUTPUT_VISIBILITY = 0, 1
+OUTPUT_RADIANCE, OUTPUT_VISIBILITY, OUTPUT_RADIANCE_OCCLUDED = 0, 1, 2
 
 
 def infer(points, point_idx, dirs, w, width: int, output: int = OUTPUT_RADIANCE) -> np.ndarray:

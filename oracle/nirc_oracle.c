@@ -363,8 +363,9 @@ void oracle_estimate(int64_t P, const float *px, const float *py, const float *p
     net_t net;
     net_setup(&net, w, width);
     /* output 1, the visibility cache: incident radiance is the predicted visibility times the
-     * known radiance, n_V(x, w) L(x, w); the residual sample is V(x, w_r) L(x, w_r) minus it */
-    const int vis = output == 1;
+     * known radiance, n_V(x, w) L(x, w); the residual sample is V(x, w_r) L(x, w_r) minus it.
+     * output 2, a radiance cache on the same occluded scene: the residual sample is V L. */
+    const int vis = output == 1, occ = output != 0;
     net.vis = vis;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t p = 0; p < P; ++p) {
@@ -383,7 +384,7 @@ void oracle_estimate(int64_t P, const float *px, const float *py, const float *p
             }
             double y[3], Lw[3];
             field_eval(&L, x, wdir, Lw);
-            const double V = vis ? visibility(&L, x, wdir) : 1.0;
+            const double V = occ ? visibility(&L, x, wdir) : 1.0;
             if (plug_in) {
                 for (int c = 0; c < 3; ++c) y[c] = V * Lw[c];
             } else {
@@ -451,7 +452,7 @@ void oracle_estimate_biased(int64_t P, const float *px, const float *py, const f
         } else {
             const double x[3] = {px[p], py[p], pz[p]};
             field_eval(&L, x, ws, out + 3 * p);
-            if (output == 1) {   /* the continued path meets the occluder */
+            if (output != 0) {   /* the continued path meets the occluder */
                 const double V = visibility(&L, x, ws);
                 for (int c = 0; c < 3; ++c) out[3 * p + c] *= V;
             }
@@ -738,18 +739,19 @@ void oracle_train_batch(int64_t P, const float *px, const float *py, const float
         double n[3] = {nx[p], ny[p], nz[p]};
         cosine_direction(n, u24(r[1]), u24(r[2]), dirs + 3 * b);
         double x[3] = {px[p], py[p], pz[p]};
-        if (output == 1) {   /* the visibility cache learns V (the same target in every channel) */
+        field_eval(&L, x, dirs + 3 * b, target + 3 * b);
+        if (output != 0) {   /* the occluded scene: the visibility cache learns V (in every
+                                channel), the radiance cache V L */
             const double V = visibility(&L, x, dirs + 3 * b);
-            for (int c = 0; c < 3; ++c) target[3 * b + c] = V;
-        } else {
-            field_eval(&L, x, dirs + 3 * b, target + 3 * b);
+            for (int c = 0; c < 3; ++c) target[3 * b + c] = output == 1 ? V : V * target[3 * b + c];
         }
     }
 }
 
-/* Reference integral F(x) = (1/pi) int V(x, w) L(x, w) (n . w) dw (V = 1 for output 0) by tensor
- * Gauss-Legendre quadrature over the uniforms (u1, u2) of the cosine-weighted map, whose pdf
- * cancels the cosine: F = int_[0,1]^2 V L (w(u1, u2)) du1 du2.  Test reference only. */
+/* Reference integral F(x) = (1/pi) int V(x, w) L(x, w) (n . w) dw (V = 1 for output 0, the
+ * unoccluded scene) by tensor Gauss-Legendre quadrature over the uniforms (u1, u2) of the
+ * cosine-weighted map, whose pdf cancels the cosine: F = int_[0,1]^2 V L (w(u1, u2)) du1 du2.
+ * Test reference only. */
 void oracle_quadrature(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
                        const float *ny, const float *nz, const float *lobes, int output, int n_nodes, double *F)
 {
@@ -768,7 +770,7 @@ void oracle_quadrature(int64_t P, const float *px, const float *py, const float 
                 double wd[3], Lw[3];
                 cosine_direction(n, u1, u2, wd);
                 field_eval(&L, x, wd, Lw);
-                const double V = output == 1 ? visibility(&L, x, wd) : 1.0;
+                const double V = output != 0 ? visibility(&L, x, wd) : 1.0;
                 for (int c = 0; c < 3; ++c) acc[c] += wt * V * Lw[c];
             }
         for (int c = 0; c < 3; ++c) F[3 * p + c] = acc[c];

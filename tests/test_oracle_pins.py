@@ -484,6 +484,9 @@ def test_visibility_special_values():
     vv = oracle.visibility(packed, pts, idx, d)
     np.testing.assert_array_equal(t, np.repeat(vv[:, None], 3, 1))
     assert (vv >= 0.1).all() and (vv <= 1.0).all()
+    # a radiance cache on the occluded scene learns V L
+    _, _, t2 = oracle.train_batch(pts, packed, 200, 3, 0, 0, output=oracle.OUTPUT_RADIANCE_OCCLUDED)
+    np.testing.assert_array_equal(t2, vv[:, None] * oracle.field(packed, pts, idx, d))
 
 
 def test_visibility_cache_special_cases():
@@ -505,6 +508,11 @@ def test_visibility_cache_special_cases():
     tl, c, r = oracle.estimate(pts, lobes, None, W, N, 4, 1, plug_in=True, output=oracle.OUTPUT_VISIBILITY)
     assert np.abs(r).max() == 0.0
     np.testing.assert_allclose(c, (V[:, :N, None] * L[:, :N]).mean(1), rtol=1e-13)
+    # a radiance cache on the occluded scene: exp outputs, residual sample V L, F_c unchanged
+    tl2, c2, r2 = oracle.estimate(pts, lobes, w, W, N, 4, 1, output=oracle.OUTPUT_RADIANCE_OCCLUDED)
+    _, c0, r0 = oracle.estimate(pts, lobes, w, W, N, 4, 1)
+    np.testing.assert_array_equal(c2, c0)
+    np.testing.assert_allclose(r2 - r0, (V[:, N, None] - 1.0) * L[:, N], rtol=1e-12, atol=1e-15)
     # the network's visibility prediction is a sigmoid of the radiance cache's log-output
     y_rad = oracle.infer(pts, idx, dirs.reshape(-1, 3), w, W)
     y_vis = oracle.infer(pts, idx, dirs.reshape(-1, 3), w, W, output=oracle.OUTPUT_VISIBILITY)
