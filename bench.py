@@ -274,6 +274,47 @@ def biased_compare(nirc, model32, dp, lobes_for, table, fs, P, N, seed, frame, r
     return out
 
 
+def visibility_compare(nirc, w0, dp, lobes_for, P, N, seed, frames, B, S):
+    """The occluded (environment-lit) scene: a visibility cache (sigmoid outputs times the known
+    radiance) against a radiance cache learning V L, each trained from the same weights over the
+    same rotating frames.  On the last frame: MRSE of the two-level estimate and of the cache
+    level alone against the 64-node quadrature of V L, the residual's relative second moment, and
+    the GPU time per estimate and per training frame.  (The MRSE of this comparison is computed
+    with torch in FP64 from the estimate and the reference, as the frame statistics' closed form
+    covers the unoccluded scene only.)"""
+    import torch
+    stream = torch.cuda.current_stream()
+    lob = nirc.lobes_struct(lobes_for(frames))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    F = nirc.tlmc_reference_occluded(dp, lob, 64)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    out = {"ms_reference_quadrature": ev[0].elapsed_time(ev[1])}
+    den = F * F + 1e-2
+    for name, mode in (("visibility_cache", 1), ("radiance_cache", 2)):
+        m = nirc.Model(w0, cfg=nirc.make_config(output=mode), max_batch=B)
+        t_train = 0.0
+        for f in range(frames):
+            ev[0].record(stream)
+            nirc.nirc_train_frame(m, dp, nirc.lobes_struct(lobes_for(f)), B, S, seed, f)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            t_train += ev[0].elapsed_time(ev[1])
+        tl, c, r = nirc.tlmc_estimate(m, dp, lob, N, seed, frames, parts=True)
+        ev[0].record(stream)
+        nirc.tlmc_estimate(m, dp, lob, N, seed, frames, out=tl)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        out[name] = {"mrse": float(((tl.double() - F) ** 2 / den).mean()),
+                     "mrse_cache_only": float(((c.double() - F) ** 2 / den).mean()),
+                     "residual_rel_second_moment": float((r.double() ** 2 / den).mean()),
+                     "ms_estimate": ev[0].elapsed_time(ev[1]), "ms_train_frame": t_train / frames}
+        del m
+    out["frames"] = frames
+    return out
+
+
 def loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S):
     """The three training losses of the optimisation section (relative L2, plain L2, residual
     variance), each training its own FP32 cache from the same weights over the same rotating
@@ -375,6 +416,8 @@ def main():
                     help="duration of the multi-stream serving run (0 to skip)")
     ap.add_argument("--precision-form", action="store_true",
                     help="also run the N x width x precision matrix of estimates")
+    ap.add_argument("--visibility", action="store_true",
+                    help="visibility cache against a radiance cache on the occluded scene (100 frames each)")
     ap.add_argument("--loss-variants", action="store_true",
                     help="train a cache with each loss of the optimisation section (100 frames) and compare")
     ap.add_argument("--train-convergence", action="store_true",
@@ -539,6 +582,8 @@ def main():
     if args.precision_form:
         result["precision_form"] = precision_form(nirc, model.get_weights(), dp, lobes_for(args.warmup + args.steps),
                                                   table, fs, P, seed, args.warmup + args.steps)
+    if args.visibility:
+        result["visibility"] = visibility_compare(nirc, w0, dp, lobes_for, P, N, seed, 100, B, S)
     if args.loss_variants:
         result["loss_variants"] = loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
     if args.train_convergence:

@@ -64,6 +64,22 @@ typedef int32_t nirc_status;
 #define NIRC_LOSS_L2 1
 #define NIRC_LOSS_VAR 2
 
+/* What the cache learns and which scene it sees (Sec. "Neural Visibility Cache").
+ *   NIRC_OUTPUT_RADIANCE           exp outputs predict incident radiance; the scene is the
+ *                                  field alone (the default).
+ *   NIRC_OUTPUT_VISIBILITY         the visibility cache: sigmoid outputs predict the visibility V
+ *                                  in [0, 1]; incident radiance is V times the known radiance
+ *                                  L (the field, standing in for an environment map), so the
+ *                                  estimator's cache level uses n_V(x, w) L(x, w), training
+ *                                  targets are V, and the residual sample is V L.
+ *   NIRC_OUTPUT_RADIANCE_OCCLUDED  a radiance cache (exp outputs) on the same occluded scene:
+ *                                  targets and residual samples are V L (the comparison case).
+ * The synthetic occluder: V(x, w) = 1 - 0.9 / (1 + exp(-16 (mu_0 . w - c(x)))), c(x) = 0.6 +
+ * 0.3 (x_0 - 0.5), with mu_0 the field's first lobe axis (a soft cap blocking 90 % of it). */
+#define NIRC_OUTPUT_RADIANCE 0
+#define NIRC_OUTPUT_VISIBILITY 1
+#define NIRC_OUTPUT_RADIANCE_OCCLUDED 2
+
 /* Device flags raised by training (sticky until nirc_clear_flags). */
 #define NIRC_FLAG_NONFINITE_GRAD 1u   /* a step saw a non-finite loss/gradient and was skipped */
 
@@ -82,6 +98,7 @@ typedef struct {
     float loss_eps;      /* e.g. 1e-2 */
     float loss_scale;    /* e.g. 1 (FP32/BF16); > 1 for FP16 */
     int32_t loss;        /* NIRC_LOSS_REL_L2 | NIRC_LOSS_L2 | NIRC_LOSS_VAR */
+    int32_t output;      /* NIRC_OUTPUT_RADIANCE | NIRC_OUTPUT_VISIBILITY | NIRC_OUTPUT_RADIANCE_OCCLUDED */
 } nirc_config;
 
 /* Shading points, structure of arrays, FP32 device arrays of `count` entries each. */
@@ -251,16 +268,24 @@ nirc_status tlmc_batch_build(const tlmc_request *requests /* host */, int32_t n,
  * width and precision must match the list's models. */
 nirc_status tlmc_estimate_batch(const void *list /* device */, int32_t width, int32_t precision, void *stream);
 
+/* Reference integral of the occluded scene, F(x) = (1/pi) int V(x, w) L(x, w) (n . w) dw, by
+ * tensor Gauss-Legendre quadrature with n_nodes (8..128) nodes per axis over the two uniforms of
+ * the cosine-weighted map (whose pdf cancels the cosine); FP32 integrand, FP64 sums.  F is
+ * [points.count][3] FP64.  A measurement reference (the occluded integral has no closed form). */
+nirc_status tlmc_reference_occluded(nirc_points points, const nirc_lobes *field /* host */, int32_t n_nodes,
+                                    double *F, void *stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Training                                                                                    */
 
 /* Training samples (stand-in for the paper's separate training pass, Sec. "Cache
  * application"): sample b of step `step` in `frame` draws Philox counter (b, step, frame, 5):
  * word 0 picks the point floor(r0 * count / 2^32), words 1 and 2 a cosine-weighted direction
- * about its normal; the target is the field's radiance there.  Outputs: point [batch] int32,
- * wx, wy, wz [batch] FP32 and target [batch][3] FP32. */
+ * about its normal; the target is what a cache of kind `output` learns there (NIRC_OUTPUT_*):
+ * the field's radiance L, the visibility V (in every channel) or V L.  Outputs: point [batch]
+ * int32, wx, wy, wz [batch] FP32 and target [batch][3] FP32. */
 nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field /* host */, int64_t batch,
-                             uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
+                             uint64_t seed, uint64_t frame, uint32_t step, int32_t output, int32_t *point,
                              float *wx, float *wy, float *wz, float *target, void *stream);
 
 /* Gradient of the relative L2 loss (eq. 12, on radiance, stop-gradient denominator):

@@ -1,4 +1,5 @@
 // C ABI of the NIRC library: argument validation, state/workspace layout and kernel launches.
+#include <cmath>
 #include <new>
 #include <string.h>
 
@@ -110,6 +111,9 @@ static nirc_status check_config(const nirc_config *cfg) {
     if (!cfg) return NIRC_ERR_INVALID_ARG;
     if (!width_ok(cfg->width)) return NIRC_ERR_UNSUPPORTED;
     if (cfg->loss != NIRC_LOSS_REL_L2 && cfg->loss != NIRC_LOSS_L2 && cfg->loss != NIRC_LOSS_VAR)
+        return NIRC_ERR_INVALID_ARG;
+    if (cfg->output != NIRC_OUTPUT_RADIANCE && cfg->output != NIRC_OUTPUT_VISIBILITY &&
+        cfg->output != NIRC_OUTPUT_RADIANCE_OCCLUDED)
         return NIRC_ERR_INVALID_ARG;
     if (cfg->precision != NIRC_FP32 && cfg->precision != NIRC_BF16 && cfg->precision != NIRC_FP16)
         return NIRC_ERR_UNSUPPORTED;
@@ -254,6 +258,7 @@ nirc_status nirc_infer(const nirc_model *model, nirc_points points, nirc_queries
     if (queries.count > 0 && !rgb) return NIRC_ERR_INVALID_ARG;
     const void *pk = model->packed16 ? (const void *)model->packed16 : (const void *)model->packed;
     return hip_status(launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries), pk, rgb,
+                                   model->cfg.output == NIRC_OUTPUT_VISIBILITY,
                                    (hipStream_t)stream));
 }
 
@@ -276,7 +281,7 @@ nirc_status tlmc_estimate(const nirc_model *model, nirc_points points, const nir
     nirc_lobes none;
     memset(&none, 0, sizeof(none));
     return hip_status(launch_tlmc(model->W, model->cfg.precision, to_points(points), field ? *field : none, pk,
-                                  n_cache, seed, frame, residual_radiance, out_tl, out_c, out_r,
+                                  n_cache, seed, frame, model->cfg.output, residual_radiance, out_tl, out_c, out_r,
                                   (hipStream_t)stream));
 }
 
@@ -290,19 +295,56 @@ nirc_status tlmc_estimate_biased(const nirc_model *model, nirc_points points, co
     if (st != NIRC_OK || points.count == 0) return st;
     nirc_lobes none;
     memset(&none, 0, sizeof(none));
-    return hip_status(launch_bth(to_points(points), field ? *field : none, n_cache, seed, frame, residual_radiance,
-                                 out_c, out_b, out_continue, (hipStream_t)stream));
+    return hip_status(launch_bth(to_points(points), field ? *field : none, n_cache, seed, frame, model->cfg.output,
+                                 residual_radiance, out_c, out_b, out_continue, (hipStream_t)stream));
+}
+
+static bool output_ok(int32_t o) {
+    return o == NIRC_OUTPUT_RADIANCE || o == NIRC_OUTPUT_VISIBILITY || o == NIRC_OUTPUT_RADIANCE_OCCLUDED;
 }
 
 nirc_status tlmc_train_batch(nirc_points points, const nirc_lobes *field, int64_t batch, uint64_t seed,
-                             uint64_t frame, uint32_t step, int32_t *point, float *wx, float *wy, float *wz,
-                             float *target, void *stream) {
-    if (!field || batch < 0 || batch > INT32_MAX) return NIRC_ERR_INVALID_ARG;
+                             uint64_t frame, uint32_t step, int32_t output, int32_t *point, float *wx, float *wy,
+                             float *wz, float *target, void *stream) {
+    if (!field || batch < 0 || batch > INT32_MAX || !output_ok(output)) return NIRC_ERR_INVALID_ARG;
     nirc_status st = check_points(points);
     if (st != NIRC_OK) return st;
     if (batch > 0 && (points.count == 0 || !point || !wx || !wy || !wz || !target)) return NIRC_ERR_INVALID_ARG;
-    return hip_status(launch_train_batch(to_points(points), *field, batch, seed, frame, step, point, wx, wy, wz,
-                                         target, (hipStream_t)stream));
+    return hip_status(launch_train_batch(to_points(points), *field, batch, seed, frame, step, output, point, wx, wy,
+                                         wz, target, (hipStream_t)stream));
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton's method on the Legendre recurrence).
+static void gauss_legendre01(int n, QuadNodes &q) {
+    q.n = n;
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                const double pk = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-15) break;
+        }
+        q.x[i] = 0.5 * (1.0 - t);
+        q.w[i] = 1.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+nirc_status tlmc_reference_occluded(nirc_points points, const nirc_lobes *field, int32_t n_nodes, double *F,
+                                    void *stream) {
+    if (!field || n_nodes < 8 || n_nodes > kMaxQuadNodes) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK) return st;
+    if (points.count > 0 && !F) return NIRC_ERR_INVALID_ARG;
+    QuadNodes q;
+    gauss_legendre01(n_nodes, q);
+    return hip_status(launch_reference_occluded(to_points(points), *field, q, F, (hipStream_t)stream));
 }
 
 // Gradient partials + reduction into `grad`/`loss`; the step's `bad` flag is raised on a
@@ -324,12 +366,14 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
     // 16-bit models: the batch size is folded into the loss scale, so that per-sample deltas stay
     // near unit magnitude in the 16-bit operands; the reduction divides it out again
     const float scale = h16 ? model->cfg.loss_scale * (float)queries.count : model->cfg.loss_scale;
-    TrainArgs a{target, d_rgb, model->cfg.loss_eps, scale, model->cfg.loss, nullptr};
+    TrainArgs a{target, d_rgb, model->cfg.loss_eps, scale, model->cfg.loss, nullptr,
+                model->cfg.output == NIRC_OUTPUT_VISIBILITY};
     if (var) {   // the residual-variance loss needs F_r = mean(t - y) of this batch first
         float *pred = (float *)(model->ws + wl.pred);
         float *fr = (float *)(model->ws + wl.fr);
         const void *pk = h16 ? (const void *)model->packed16 : (const void *)model->packed;
-        hipError_t e = launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries), pk, pred, s);
+        hipError_t e = launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries), pk, pred,
+                                    model->cfg.output == NIRC_OUTPUT_VISIBILITY, s);
         if (e == hipSuccess)
             e = launch_residual_mean(pred, target, queries.count, (double *)(model->ws + wl.fr_part), fr, s);
         if (e != hipSuccess) return NIRC_ERR_HIP;
@@ -404,7 +448,8 @@ nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_l
     int32_t *pidx = (int32_t *)smp;
     float *wx = smp + batch, *wy = wx + batch, *wz = wy + batch, *tgt = wz + batch;
     for (int32_t k = 0; k < steps; ++k) {
-        hipError_t e = launch_train_batch(to_points(points), *field, batch, seed, frame, (uint32_t)k, pidx, wx, wy, wz,
+        hipError_t e = launch_train_batch(to_points(points), *field, batch, seed, frame, (uint32_t)k, model->cfg.output,
+                                          pidx, wx, wy, wz,
                                           tgt, s);
         if (e != hipSuccess) return NIRC_ERR_HIP;
         nirc_queries q{wx, wy, wz, pidx, batch};
@@ -440,6 +485,7 @@ nirc_status tlmc_batch_build(const tlmc_request *requests, int32_t n, void *list
         q.key1 = (uint32_t)(r.seed >> 32);
         q.frame = (uint32_t)r.frame;
         q.rrad = r.residual_radiance;
+        q.mode = r.model->cfg.output;
         q.out_tl = r.out_tl;
         q.out_c = r.out_c;
         q.out_r = r.out_r;

@@ -190,6 +190,30 @@ __device__ inline void field_lobe(const nirc_lobes &L, int j, float x0, float x1
         out[c] = (L.alpha[j][c] + L.beta[j][c][0] * x0 + L.beta[j][c][1] * x1 + L.beta[j][c][2] * x2) * gj;
 }
 
+// Channel c of the field.
+__device__ inline float field_channel(const nirc_lobes &L, int c, float x0, float x1, float x2, float wx, float wy,
+                                      float wz) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float mw = L.axis[j][0] * wx + L.axis[j][1] * wy + L.axis[j][2] * wz;
+        acc += (L.alpha[j][c] + L.beta[j][c][0] * x0 + L.beta[j][c][1] * x1 + L.beta[j][c][2] * x2) *
+               expf(L.kappa[j] * (mw - 1.0f));
+    }
+    return acc;
+}
+
+// Synthetic visibility of the occluded (environment-lit) scene: a soft cap over the first lobe's
+// axis mu_0 that blocks 90 % of it, V = 1 - 0.9 / (1 + exp(-16 (mu_0 . w - c(x)))) with
+// c(x) = 0.6 + 0.3 (x_0 - 0.5).
+__device__ inline float visibility(const nirc_lobes &L, float x0, float wx, float wy, float wz) {
+    const float m = L.axis[0][0] * wx + L.axis[0][1] * wy + L.axis[0][2] * wz;
+    const float c = 0.6f + 0.3f * (x0 - 0.5f);
+    return 1.0f - 0.9f / (1.0f + expf(-16.0f * (m - c)));
+}
+
+__device__ inline float logistic(float z) { return 1.0f / (1.0f + expf(-z)); }
+
 // ------------------------------------------------------------------------------------------
 // MFMA wrappers (wave64).  16x16x4 FP32: lane l holds A[row l%16][k l/16], B[k l/16][col l%16];
 // the 16x16 result gives lane l rows 4(l/16)+i, i = 0..3, of column l%16.

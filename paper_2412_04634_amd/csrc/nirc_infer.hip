@@ -78,8 +78,8 @@ __global__ void k_sample_dirs(Points pts, int n_cache, uint32_t key0, uint32_t k
 // on the FP32 rounding of the direction.  Stopped: F_c; continued: the radiance along the
 // direction (rrad, or the field).
 __global__ void k_bth(Points pts, nirc_lobes lobes, int n_cache, uint32_t key0, uint32_t key1, uint32_t frame,
-                      const float *__restrict__ rrad, const float *__restrict__ fc, float *__restrict__ out,
-                      int32_t *__restrict__ cont) {
+                      int mode, const float *__restrict__ rrad, const float *__restrict__ fc,
+                      float *__restrict__ out, int32_t *__restrict__ cont) {
 #pragma clang fp contract(off)
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= pts.count) return;
@@ -106,15 +106,62 @@ __global__ void k_bth(Points pts, nirc_lobes lobes, int n_cache, uint32_t key0, 
         float wx, wy, wz;
         dir_from_rand(r, dc.half, pts.nx[p], pts.ny[p], pts.nz[p], wx, wy, wz);
         field_eval(lobes, pts.px[p], pts.py[p], pts.pz[p], wx, wy, wz, v);
+        if (mode != NIRC_OUTPUT_RADIANCE) {   // the continued path meets the occluder
+            const float V = visibility(lobes, pts.px[p], wx, wy, wz);
+            v[0] *= V;
+            v[1] *= V;
+            v[2] *= V;
+        }
     }
     out[3 * p] = v[0];
     out[3 * p + 1] = v[1];
     out[3 * p + 2] = v[2];
 }
 
+// Reference integral of the occluded scene, one workgroup per point: the n x n tensor
+// Gauss-Legendre nodes over the cosine map's uniforms (u1, u2), FP32 integrand V L, FP64 sums in a
+// fixed order (strided per thread, then a tree).
+__global__ __launch_bounds__(256) void k_reference_occluded(Points pts, nirc_lobes lobes, QuadNodes nodes,
+                                                            double *__restrict__ F) {
+    __shared__ double sh[3][256];
+    const int64_t p = blockIdx.x;
+    const float x0 = pts.px[p], x1 = pts.py[p], x2 = pts.pz[p];
+    const float nx = pts.nx[p], ny = pts.ny[p], nz = pts.nz[p];
+    const int n = nodes.n, nn = n * n;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int t = threadIdx.x; t < nn; t += 256) {
+        const int i = t / n, k = t - i * n;
+        float wx, wy, wz, L[3];
+        cosine_dir(nx, ny, nz, (float)nodes.x[i], (float)nodes.x[k], wx, wy, wz);
+        field_eval(lobes, x0, x1, x2, wx, wy, wz, L);
+        const double wt = nodes.w[i] * nodes.w[k] * (double)visibility(lobes, x0, wx, wy, wz);
+        a0 += wt * (double)L[0];
+        a1 += wt * (double)L[1];
+        a2 += wt * (double)L[2];
+    }
+    sh[0][threadIdx.x] = a0;
+    sh[1][threadIdx.x] = a1;
+    sh[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 3; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) F[3 * p + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_reference_occluded(const Points &pts, const nirc_lobes &lobes, const QuadNodes &nodes, double *F,
+                                     hipStream_t s) {
+    if (pts.count == 0) return hipSuccess;
+    if (nodes.n < 1 || nodes.n > kMaxQuadNodes || pts.count > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reference_occluded, dim3((unsigned)pts.count), dim3(256), 0, s, pts, lobes, nodes, F);
+    return hipGetLastError();
+}
+
 // Training samples: one thread per sample.
 __global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint32_t key0,
-                              uint32_t key1, uint32_t frame, uint32_t step, int32_t *point,
+                              uint32_t key1, uint32_t frame, uint32_t step, int mode, int32_t *point,
                               float *wx, float *wy, float *wz, float *target) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
@@ -124,6 +171,12 @@ __global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint3
     cosine_dir(pts.nx[p], pts.ny[p], pts.nz[p], u24(r.r[1]), u24(r.r[2]), x, y, z);
     float L[3];
     field_eval(lobes, pts.px[p], pts.py[p], pts.pz[p], x, y, z, L);
+    if (mode != NIRC_OUTPUT_RADIANCE) {   // occluded scene: the visibility cache learns V, the other V L
+        const float V = visibility(lobes, pts.px[p], x, y, z);
+        L[0] = mode == NIRC_OUTPUT_VISIBILITY ? V : V * L[0];
+        L[1] = mode == NIRC_OUTPUT_VISIBILITY ? V : V * L[1];
+        L[2] = mode == NIRC_OUTPUT_VISIBILITY ? V : V * L[2];
+    }
     point[b] = (int32_t)p;
     wx[b] = x;
     wy[b] = y;
@@ -139,7 +192,7 @@ __global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint3
 template <int W, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
                                                           const float *__restrict__ packed,
-                                                          float *__restrict__ rgb) {
+                                                          float *__restrict__ rgb, int sig) {
     constexpr F32Layout L{W};
     constexpr int MT = W / 16;
     constexpr bool kLds = lds_weights(W);
@@ -175,9 +228,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
         output_layer<W, 1>(y, h, sO, lane);
         if (g == 0 && (tile << 4) + col < Q) {
             float *o = rgb + 3 * ((tile << 4) + col);
-            o[0] = expf(y[0][0]);
-            o[1] = expf(y[0][1]);
-            o[2] = expf(y[0][2]);
+            o[0] = sig ? logistic(y[0][0]) : expf(y[0][0]);   // visibility cache: sigmoid outputs
+            o[1] = sig ? logistic(y[0][1]) : expf(y[0][1]);
+            o[2] = sig ? logistic(y[0][2]) : expf(y[0][2]);
         }
     }
 }
@@ -188,8 +241,9 @@ template <int W, int T>
 __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN dn, const float *db, const float *hs,
                                                const float *sD, const float *sH, const float *sO,
                                                const nirc_lobes &lobes, const float *rrad, int64_t pc,
-                                               const float *xs, int lane, int g, int col, float &fc0, float &fc1,
-                                               float &fc2, float &fr0, float &fr1, float &fr2) {
+                                               const Points &pts, int64_t p0, int mode, const float *xs, int lane,
+                                               int g, int col, float &fc0, float &fc1, float &fc2, float &fr0,
+                                               float &fr1, float &fr2) {
     constexpr int MT = W / 16;
     if constexpr (!lds_weights(W)) {   // weights in global memory: keep their loads inside the pass
         sD = opaque(sD);
@@ -198,6 +252,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
     }
     f32x4 h[T][MT];
     float dx[T], dy[T], dz[T];
+    int jq[T];   // the point (within the group) of this lane's query in each tile
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int Tt = T0 + tt;
@@ -206,6 +261,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
         dy[tt] = db[kDirSlots + qi];
         dz[tt] = db[2 * kDirSlots + qi];
         const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
+        jq[tt] = j;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g);
     }
@@ -217,7 +273,19 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 #pragma unroll
     for (int tt = 0; tt < T; ++tt) {
         const int Tt = T0 + tt;
-        const float y0 = expf(y[tt][0]), y1 = expf(y[tt][1]), y2 = expf(y[tt][2]);
+        float y0, y1, y2;
+        if (mode == NIRC_OUTPUT_VISIBILITY) {   // uniform: predicted visibility times the known radiance
+            const int64_t pj = min(p0 + jq[tt], pts.count - 1);
+            float Lq[3];
+            field_eval(lobes, pts.px[pj], pts.py[pj], pts.pz[pj], dx[tt], dy[tt], dz[tt], Lq);
+            y0 = logistic(y[tt][0]) * Lq[0];
+            y1 = logistic(y[tt][1]) * Lq[1];
+            y2 = logistic(y[tt][2]) * Lq[2];
+        } else {
+            y0 = expf(y[tt][0]);
+            y1 = expf(y[tt][1]);
+            y2 = expf(y[tt][2]);
+        }
         if (Tt < n_cache) {
             reduce_cache_tile(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
         } else {
@@ -228,6 +296,12 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
                 Lr[2] = rrad[3 * pc + 2];
             } else {
                 field_eval(lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
+                if (mode != NIRC_OUTPUT_RADIANCE) {   // the occluded scene's residual sample V L
+                    const float V = visibility(lobes, xs[0], dx[tt], dy[tt], dz[tt]);
+                    Lr[0] *= V;
+                    Lr[1] *= V;
+                    Lr[2] *= V;
+                }
             }
             fr0 = Lr[0] - y0;
             fr1 = Lr[1] - y1;
@@ -252,7 +326,8 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 // One point group (16 points from p0) through the FP32 chain.
 template <int W>
 __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
-                                               uint32_t key1, uint32_t frame, const float *rrad, float *out_tl,
+                                               uint32_t key1, uint32_t frame, int mode, const float *rrad,
+                                               float *out_tl,
                                                float *out_c, float *out_r, const nirc_lobes &lobes,
                                                const float *gS, const float *sD, const float *sH, const float *sO,
                                                float *hs, float *db, int lane, int g, int col) {
@@ -279,12 +354,12 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_f32<W, TP>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, xs, lane, g, col, fc0,
-                                  fc1, fc2, fr0, fr1, fr2);
+            tlmc_tiles_f32<W, TP>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
+                                  g, col, fc0, fc1, fc2, fr0, fr1, fr2);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, xs, lane, g, col, fc0,
-                                 fc1, fc2, fr0, fr1, fr2);
+            tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
+                                 g, col, fc0, fc1, fc2, fr0, fr1, fr2);
         tb = tend;
     }
     if (g == 0 && p0 + col < P)
@@ -295,7 +370,7 @@ template <int W, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes lobes,
                                                          const float *__restrict__ packed,
                                                          int n_cache, DivN dn, uint32_t key0, uint32_t key1,
-                                                         uint32_t frame, const float *__restrict__ rrad,
+                                                         uint32_t frame, int mode, const float *__restrict__ rrad,
                                                          float *__restrict__ out_tl, float *__restrict__ out_c,
                                                          float *__restrict__ out_r) {
     constexpr F32Layout L{W};
@@ -320,8 +395,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
     float *db = hs + 16 * W;               // directions, SoA [3][kDirSlots]
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_f32<W>(pts, grp << 4, n_cache, dn, key0, key1, frame, rrad, out_tl, out_c, out_r, s_lobes, gS, sD,
-                          sH, sO, hs, db, lane, g, col);
+        tlmc_group_f32<W>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode, rrad, out_tl, out_c, out_r, s_lobes, gS,
+                          sD, sH, sO, hs, db, lane, g, col);
 }
 
 // Continuous batching with the FP32 chain (see k_tlmc_multi_h16).
@@ -358,7 +433,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_f32(const BatchDesc *
         const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
         if (grp < (s_req.pts.count + 15) >> 4)
             tlmc_group_f32<W>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
-                              uniform_ptr(s_req.rrad), s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
+                              __builtin_amdgcn_readfirstlane(s_req.mode), uniform_ptr(s_req.rrad), s_req.out_tl,
+                              s_req.out_c, s_req.out_r, s_req.lobes,
                               (const float *)s_req.packed + L.offset(SEC_S), sD, sH, sO, hs, db, lane, g, col);
     }
 }
@@ -401,19 +477,19 @@ hipError_t launch_sample_dirs(const Points &pts, int n_cache, uint64_t seed, uin
 }
 
 hipError_t launch_bth(const Points &pts, const nirc_lobes &lobes, int n_cache, uint64_t seed, uint64_t frame,
-                      const float *rrad, const float *fc, float *out, int32_t *cont, hipStream_t s) {
+                      int mode, const float *rrad, const float *fc, float *out, int32_t *cont, hipStream_t s) {
     if (pts.count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bth, dim3((unsigned)((pts.count + 255) / 256)), dim3(256), 0, s, pts, lobes, n_cache,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, rrad, fc, out, cont);
+                       (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, mode, rrad, fc, out, cont);
     return hipGetLastError();
 }
 
 hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_t batch,
-                              uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
+                              uint64_t seed, uint64_t frame, uint32_t step, int mode, int32_t *point,
                               float *wx, float *wy, float *wz, float *target, hipStream_t s) {
     if (batch == 0) return hipSuccess;
     hipLaunchKernelGGL(k_train_batch, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, pts,
-                       lobes, batch, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, step,
+                       lobes, batch, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, step, mode,
                        point, wx, wy, wz, target);
     return hipGetLastError();
 }
@@ -426,17 +502,17 @@ unsigned grid_for(int64_t units_per_wave_total, int waves, int max_blocks) {
 }
 
 hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
-                        hipStream_t s) {
+                        int sig, hipStream_t s) {
     if (q.count == 0) return hipSuccess;
-    if (prec != NIRC_FP32) return launch_infer_h16(W, prec, pts, q, packed, rgb, s);
+    if (prec != NIRC_FP32) return launch_infer_h16(W, prec, pts, q, packed, rgb, sig, s);
     constexpr int WAVES = 4;
     const unsigned grid = grid_for((q.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
     if (W == 64)
         hipLaunchKernelGGL((k_infer_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, (const float *)packed,
-                           rgb);
+                           rgb, sig);
     else if (W == 128)
         hipLaunchKernelGGL((k_infer_f32<128, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q,
-                           (const float *)packed, rgb);
+                           (const float *)packed, rgb, sig);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -451,21 +527,23 @@ hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStre
 }
 
 hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                       int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
-                       float *out_r, hipStream_t s) {
+                       int n_cache, uint64_t seed, uint64_t frame, int mode, const float *rrad, float *out_tl,
+                       float *out_c, float *out_r, hipStream_t s) {
     if (pts.count == 0) return hipSuccess;
     if (prec != NIRC_FP32)
-        return launch_tlmc_h16(W, prec, pts, lobes, packed, n_cache, seed, frame, rrad, out_tl, out_c, out_r, s);
+        return launch_tlmc_h16(W, prec, pts, lobes, packed, n_cache, seed, frame, mode, rrad, out_tl, out_c, out_r,
+                               s);
     constexpr int WAVES = 8;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, kMaxResidentBlocks);
     if (W == 64)
         hipLaunchKernelGGL((k_tlmc_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes,
                            (const float *)packed, n_cache, make_divn(n_cache), (uint32_t)seed, (uint32_t)(seed >> 32),
-                           (uint32_t)frame, rrad, out_tl, out_c, out_r);
+                           (uint32_t)frame, mode, rrad, out_tl, out_c, out_r);
     else if (W == 128)   // one wave per SIMD: the width-128 FP32 pass needs more than 256 registers
         hipLaunchKernelGGL((k_tlmc_f32<128, 4>), dim3(grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks)),
                            dim3(4 * 64), 0, s, pts, lobes, (const float *)packed, n_cache, make_divn(n_cache),
-                           (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, rrad, out_tl, out_c, out_r);
+                           (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, mode, rrad, out_tl, out_c,
+                           out_r);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

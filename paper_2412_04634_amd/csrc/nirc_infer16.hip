@@ -31,7 +31,7 @@ struct Infer16Lds {
 // Per-query inference: 16 queries per wave per iteration, all 160 features per query.
 template <int W, int PREC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q, const uint16_t *__restrict__ packed,
-                                                          float *__restrict__ rgb) {
+                                                          float *__restrict__ rgb, int sig) {
     constexpr H16Layout L{W};
     constexpr int MT = W / 16, KB = W / 32;
     constexpr bool kLds = lds_weights(W);
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_h16(Points pts, Queries q,
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int64_t qo = (tile << 4) + 4 * g + i;
-                if (qo < Q) rgb[3 * qo + col] = __expf(z[i]);
+                if (qo < Q) rgb[3 * qo + col] = sig ? 1.0f / (1.0f + __expf(-z[i])) : __expf(z[i]);
             }
         }
     }
@@ -104,7 +104,8 @@ template <int W, int PREC, int T>
 __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN dn, const GroupSlab &gs,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
                                                const u32x4 (&dfrag)[W / 8], int lane, int g, int col, float &rdx,
-                                               float &rdy, float &rdz) {
+                                               float &rdy, float &rdz, const Points &pts, int64_t p0, int mode,
+                                               const nirc_lobes &lobes) {
     constexpr int MT = W / 16, KB = W / 32;
     f32x4 h[T][MT];
     u32x4 bd[T][2];
@@ -152,8 +153,33 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
     const int tt = col / 3, c = col - 3 * (col / 3);
     const bool valid = col < 3 * T;
     const int Tt = T0 + tt;
-    const float e0 = __expf(z[0]), e1 = __expf(z[1]), e2 = __expf(z[2]), e3 = __expf(z[3]);
     const int q0 = 4 * g;   // first query (row) of this lane within its tile
+    float e0, e1, e2, e3;
+    if (mode == NIRC_OUTPUT_VISIBILITY) {
+        // uniform: predicted visibility times channel c of the known radiance, for this lane's
+        // four queries (their staged directions and their points' positions)
+        const int ts = min(tt, T - 1);   // lanes past the pass's tiles compute an unused value
+        const int Ts = T0 + ts;
+        float ev[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int qi = 16 * (s0 + ts) + q0 + i;
+            const int j = (Ts < n_cache) ? (int)div_n((uint32_t)(16 * Ts + q0 + i), dn) : q0 + i;
+            const int64_t pj = min(p0 + j, pts.count - 1);
+            const float Lc = field_channel(lobes, c, pts.px[pj], pts.py[pj], pts.pz[pj], gs.db[qi],
+                                           gs.db[kDirSlots + qi], gs.db[2 * kDirSlots + qi]);
+            ev[i] = Lc / (1.0f + __expf(-z[i]));
+        }
+        e0 = ev[0];
+        e1 = ev[1];
+        e2 = ev[2];
+        e3 = ev[3];
+    } else {
+        e0 = __expf(z[0]);
+        e1 = __expf(z[1]);
+        e2 = __expf(z[2]);
+        e3 = __expf(z[3]);
+    }
     if ((n_cache & 15) == 0) {
         float sum = (e0 + e1) + (e2 + e3);
         sum += __shfl_xor(sum, 16);
@@ -231,7 +257,8 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
 // surface columns are read from global memory (gS).
 template <int W, int PREC, int TP = 4>
 __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
-                                               uint32_t key1, uint32_t frame, const float *rrad, float *out_tl,
+                                               uint32_t key1, uint32_t frame, int mode, const float *rrad,
+                                               float *out_tl,
                                                float *out_c, float *out_r, const nirc_lobes &lobes, const uint16_t *gS,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
                                                const GroupSlab &gs, int lane, int g, int col) {
@@ -261,10 +288,12 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         int t = tb;
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_h16<W, PREC, TP>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz);
+            tlmc_tiles_h16<W, PREC, TP>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
+                                        p0, mode, lobes);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz);
+            tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
+                                       p0, mode, lobes);
         tb = tend;
     }
     wave_sync();
@@ -282,6 +311,12 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         for (int c = 0; c < 3; ++c) {
             Lr[c] += __shfl_xor(Lr[c], 16);
             Lr[c] += __shfl_xor(Lr[c], 32);
+        }
+        if (mode != NIRC_OUTPUT_RADIANCE) {   // the occluded scene's residual sample V L
+            const float V = visibility(lobes, xs[0], rdx, rdy, rdz);
+            Lr[0] *= V;
+            Lr[1] *= V;
+            Lr[2] *= V;
         }
     }
     if (g == 0 && p0 + col < P) {
@@ -309,7 +344,7 @@ __device__ inline GroupSlab group_slab(float *base, int W) {
 template <int W, int PREC, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes lobes, const uint16_t *__restrict__ packed,
                                                          int n_cache, DivN dn, uint32_t key0, uint32_t key1,
-                                                         uint32_t frame, const float *__restrict__ rrad,
+                                                         uint32_t frame, int mode, const float *__restrict__ rrad,
                                                          float *__restrict__ out_tl, float *__restrict__ out_c,
                                                          float *__restrict__ out_r) {
     constexpr H16Layout L{W};
@@ -334,7 +369,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
     const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, W);
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2>(pts, grp << 4, n_cache, dn, key0, key1, frame, rrad,
+        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode,
+                                                                 rrad,
                                                                  out_tl, out_c, out_r, s_lobes, gS, sD, sH, sOS, gs,
                                                                  lane, g, col);
 }
@@ -377,7 +413,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *
         const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
         if (grp < (s_req.pts.count + 15) >> 4)
             tlmc_group_h16<W, PREC>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
-                                    uniform_ptr(s_req.rrad), s_req.out_tl, s_req.out_c, s_req.out_r, s_req.lobes,
+                                    __builtin_amdgcn_readfirstlane(s_req.mode), uniform_ptr(s_req.rrad), s_req.out_tl,
+                                    s_req.out_c, s_req.out_r, s_req.lobes,
                                     (const uint16_t *)s_req.packed + L.offset(SEC_S), sD, sH, sOS, gs, lane, g, col);
     }
 }
@@ -397,18 +434,18 @@ hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec,
 }
 
 hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
-                            hipStream_t s) {
+                            int sig, hipStream_t s) {
     constexpr int WAVES = 4;
     const unsigned grid = grid_for((q.count + 15) / 16, WAVES, 4 * kMaxResidentBlocks);
     const uint16_t *pk = (const uint16_t *)packed;
     if (W == 64 && prec == NIRC_BF16)
-        hipLaunchKernelGGL((k_infer_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+        hipLaunchKernelGGL((k_infer_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb, sig);
     else if (W == 64)
-        hipLaunchKernelGGL((k_infer_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+        hipLaunchKernelGGL((k_infer_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb, sig);
     else if (W == 128 && prec == NIRC_BF16)
-        hipLaunchKernelGGL((k_infer_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+        hipLaunchKernelGGL((k_infer_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb, sig);
     else if (W == 128)
-        hipLaunchKernelGGL((k_infer_h16<128, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb);
+        hipLaunchKernelGGL((k_infer_h16<128, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, q, pk, rgb, sig);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -426,8 +463,8 @@ hipError_t launch_tlmc_multi_h16(int W, int prec, const BatchDesc *desc, int gri
 }
 
 hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                           int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
-                           float *out_r, hipStream_t s) {
+                           int n_cache, uint64_t seed, uint64_t frame, int mode, const float *rrad, float *out_tl,
+                           float *out_c, float *out_r, hipStream_t s) {
     constexpr int WAVES = 8;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
     const uint16_t *pk = (const uint16_t *)packed;
@@ -435,26 +472,26 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
     const DivN dn = make_divn(n_cache);
     if (W == 64 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     else if (W == 64)
         hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     // width 128: from 16 cache queries per point on, one wave per SIMD with 4-tile passes (half the weight
     // traffic from L2 per tile); below that, two waves per SIMD with 2-tile passes hide the per-point work better
     else if (W == 128 && n_cache >= 16) {
         const unsigned g4 = grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks);
         if (prec == NIRC_BF16)
             hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
-                               dn, k0, k1, f, rrad, out_tl, out_c, out_r);
+                               dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
         else
             hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
-                               dn, k0, k1, f, rrad, out_tl, out_c, out_r);
+                               dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     } else if (W == 128 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     else if (W == 128)
         hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
+                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -357,6 +357,7 @@ struct BatchRequest {
     DivN dn;
     uint32_t key0, key1, frame;
     const float *rrad;     // residual radiance [P][3], or NULL for the field
+    int32_t mode;          // NIRC_OUTPUT_* of the model
     float *out_tl, *out_c, *out_r;
     int32_t chunk_begin;   // first chunk of this request in the batch
     int32_t pad;
@@ -382,26 +383,38 @@ hipError_t launch_encode(const Points &pts, const Queries &q, float *feat, hipSt
 hipError_t launch_sample_dirs(const Points &pts, int n_cache, uint64_t seed, uint64_t frame,
                               float *dirs, hipStream_t s);
 hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_t batch,
-                              uint64_t seed, uint64_t frame, uint32_t step, int32_t *point,
+                              uint64_t seed, uint64_t frame, uint32_t step, int mode, int32_t *point,
                               float *wx, float *wy, float *wz, float *target, hipStream_t s);
+// Reference integral of V L over the hemisphere (tensor Gauss-Legendre on the cosine map's
+// uniforms; nodes and weights on [0, 1] from the host), FP64 [P][3].
+constexpr int kMaxQuadNodes = 128;
+struct QuadNodes {
+    double x[kMaxQuadNodes], w[kMaxQuadNodes];
+    int n;
+};
+hipError_t launch_reference_occluded(const Points &pts, const nirc_lobes &lobes, const QuadNodes &nodes, double *F,
+                                     hipStream_t s);
 unsigned grid_for(int64_t units, int waves, int max_blocks);
 hipError_t launch_tlmc_multi_h16(int W, int prec, const BatchDesc *desc, int grid, hipStream_t s);
 hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStream_t s);
 hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
-                            hipStream_t s);
+                            int sig, hipStream_t s);
 hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                           int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
-                           float *out_r, hipStream_t s);
+                           int n_cache, uint64_t seed, uint64_t frame, int mode, const float *rrad, float *out_tl,
+                           float *out_c, float *out_r, hipStream_t s);
+// sig: sigmoid outputs (the visibility cache) instead of exp
 hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
-                        hipStream_t s);
+                        int sig, hipStream_t s);
 // Biased estimate (balanced termination heuristic) from F_c written by launch_tlmc: out [P][3],
 // cont [P] (1 = the path continues) or NULL.
 hipError_t launch_bth(const Points &pts, const nirc_lobes &lobes, int n_cache, uint64_t seed, uint64_t frame,
-                      const float *rrad, const float *fc, float *out, int32_t *cont, hipStream_t s);
+                      int mode, const float *rrad, const float *fc, float *out, int32_t *cont, hipStream_t s);
 // rrad: residual radiance [P][3] (a renderer's sample), or NULL to evaluate the lobe field
+// mode: NIRC_OUTPUT_* (the visibility cache multiplies its predictions by the field; the occluded
+// modes take V L as the residual sample)
 hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
-                       int n_cache, uint64_t seed, uint64_t frame, const float *rrad, float *out_tl, float *out_c,
-                       float *out_r, hipStream_t s);
+                       int n_cache, uint64_t seed, uint64_t frame, int mode, const float *rrad, float *out_tl,
+                       float *out_c, float *out_r, hipStream_t s);
 
 // Frame statistics (FP64).
 hipError_t launch_reference_table(const nirc_lobes &lobes, double *table, hipStream_t s);
@@ -421,6 +434,7 @@ struct TrainArgs {
     float loss_scale;
     int32_t loss_kind;     // NIRC_LOSS_*
     const float *fr;       // NIRC_LOSS_VAR: batch estimate of F_r per channel [3], else NULL
+    int32_t sig;           // sigmoid outputs (the visibility cache) instead of exp
 };
 // NIRC_LOSS_VAR: fr[c] = mean over the batch of t - y (y: the model's predictions [B][3]),
 // summed in a fixed order; part holds kFrBlocks x 3 doubles.

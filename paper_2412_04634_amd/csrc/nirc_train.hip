@@ -23,16 +23,18 @@ struct GradLds {
 // Output-pre-activation gradient and loss term of one channel.
 // rel: the relative loss (denominator y^2 + eps held constant), else den = 1; fr: the F_r shift of
 // the residual-variance loss (0 otherwise)
+// sig: sigmoid outputs (dy/dz = y (1 - y)) instead of exp (dy/dz = y)
 __device__ inline float out_grad(float z, float t, float dr, bool use_loss, float eps, float k, bool rel,
-                                 float fr, float &loss_term) {
-    const float y = expf(z);
+                                 float fr, bool sig, float &loss_term) {
+    const float y = sig ? logistic(z) : expf(z);
+    const float dydz = sig ? y * (1.0f - y) : y;
     if (use_loss) {
         const float d = (y - t) + fr, den = rel ? y * y + eps : 1.0f;
         loss_term = d * d / den;
-        return k * d / den * y;   // k = 2 scale / (3B)
+        return k * d / den * dydz;   // k = 2 scale / (3B)
     }
     loss_term = 0.0f;
-    return k * dr * y;            // k = scale
+    return k * dr * dydz;            // k = scale
 }
 
 }  // namespace
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
                     d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
-                                     args.fr ? args.fr[c] : 0.0f, lt);
+                                     args.fr ? args.fr[c] : 0.0f, args.sig != 0, lt);
                     loss_acc += lt;
                 }
             }
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32_wide(Points pts, 
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
                     d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
-                                     args.fr ? args.fr[c] : 0.0f, lt);
+                                     args.fr ? args.fr[c] : 0.0f, args.sig != 0, lt);
                     loss_acc += lt;
                 }
             }

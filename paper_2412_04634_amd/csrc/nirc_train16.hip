@@ -51,15 +51,16 @@ __device__ __forceinline__ void stage_chain(uint16_t *rows, const u32x4 (&v)[W /
 }
 
 __device__ inline float out_grad16(float z, float t, float dr, bool use_loss, float eps, float k, bool rel, float fr,
-                                   float &loss_term) {
-    const float y = expf(z);
+                                   bool sig, float &loss_term) {
+    const float y = sig ? logistic(z) : expf(z);
+    const float dydz = sig ? y * (1.0f - y) : y;
     if (use_loss) {
         const float d = (y - t) + fr, den = rel ? y * y + eps : 1.0f;
         loss_term = d * d / den;
-        return k * d / den * y;
+        return k * d / den * dydz;
     }
     loss_term = 0.0f;
-    return k * dr * y;
+    return k * dr * dydz;
 }
 
 }  // namespace
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries 
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
                     d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
-                                       args.fr ? args.fr[c] : 0.0f, lt);
+                                       args.fr ? args.fr[c] : 0.0f, args.sig != 0, lt);
                     loss_acc += lt;
                 }
             }
@@ -448,7 +449,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16_wide(Points pts, Que
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
                     d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
-                                       args.fr ? args.fr[c] : 0.0f, lt);
+                                       args.fr ? args.fr[c] : 0.0f, args.sig != 0, lt);
                     loss_acc += lt;
                 }
             }

@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "nirc.h")
 NIRC_FP32, NIRC_BF16, NIRC_FP16 = 0, 1, 2
 NIRC_FLAG_NONFINITE_GRAD = 1
 NIRC_LOSS_REL_L2, NIRC_LOSS_L2, NIRC_LOSS_VAR = 0, 1, 2
+NIRC_OUTPUT_RADIANCE, NIRC_OUTPUT_VISIBILITY, NIRC_OUTPUT_RADIANCE_OCCLUDED = 0, 1, 2
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -33,7 +34,7 @@ _sz = ctypes.c_size_t
 class Config(ctypes.Structure):
     _fields_ = [("width", _i32), ("precision", _i32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float), ("loss_eps", ctypes.c_float),
-                ("loss_scale", ctypes.c_float), ("loss", _i32)]
+                ("loss_scale", ctypes.c_float), ("loss", _i32), ("output", _i32)]
 
 
 class _Points(ctypes.Structure):
@@ -88,7 +89,8 @@ def lib():
                                      _vp]),
             "tlmc_estimate_biased": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp,
                                             _vp, _vp]),
-            "tlmc_train_batch": (_i32, [_Points, ctypes.POINTER(Lobes), _i64, _u64, _u64, _u32, _vp, _vp, _vp,
+            "tlmc_reference_occluded": (_i32, [_Points, ctypes.POINTER(Lobes), _i32, _vp, _vp]),
+            "tlmc_train_batch": (_i32, [_Points, ctypes.POINTER(Lobes), _i64, _u64, _u64, _u32, _i32, _vp, _vp, _vp,
                                         _vp, _vp, _vp]),
             "nirc_loss_grad": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp, _vp]),
             "nirc_backward": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
@@ -186,9 +188,10 @@ def lobes_struct(packed64) -> Lobes:
 
 
 def make_config(width=64, precision=NIRC_FP32, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8,
-                loss_eps=1e-2, loss_scale=1.0, loss=0) -> Config:
-    """loss: NIRC_LOSS_REL_L2 (eq. 12, default), NIRC_LOSS_L2 or NIRC_LOSS_VAR."""
-    return Config(width, precision, lr, beta1, beta2, adam_eps, loss_eps, loss_scale, loss)
+                loss_eps=1e-2, loss_scale=1.0, loss=0, output=0) -> Config:
+    """loss: NIRC_LOSS_REL_L2 (eq. 12, default), NIRC_LOSS_L2 or NIRC_LOSS_VAR.
+    output: NIRC_OUTPUT_RADIANCE (default), NIRC_OUTPUT_VISIBILITY or NIRC_OUTPUT_RADIANCE_OCCLUDED."""
+    return Config(width, precision, lr, beta1, beta2, adam_eps, loss_eps, loss_scale, loss, output)
 
 
 def nirc_n_params(width: int) -> int:
@@ -326,8 +329,9 @@ def tlmc_estimate_biased(model: Model, points: Points, lobes, n_cache: int, seed
     return b, c, cont
 
 
-def tlmc_train_batch(points: Points, lobes, batch: int, seed: int, frame: int, step: int):
-    """Training samples: (Queries with point indices, targets [B,3])."""
+def tlmc_train_batch(points: Points, lobes, batch: int, seed: int, frame: int, step: int, output: int = 0):
+    """Training samples: (Queries with point indices, targets [B,3]); output selects the targets
+    (radiance, visibility, or radiance of the occluded scene)."""
     dev = points.t[0].device
     L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
     idx = torch.empty(batch, dtype=torch.int32, device=dev)
@@ -335,7 +339,7 @@ def tlmc_train_batch(points: Points, lobes, batch: int, seed: int, frame: int, s
     wy = torch.empty_like(wx)
     wz = torch.empty_like(wx)
     tgt = torch.empty((batch, 3), dtype=torch.float32, device=dev)
-    _check(lib().tlmc_train_batch(points.c(), ctypes.byref(L), batch, seed, frame, step, _ptr(idx), _ptr(wx),
+    _check(lib().tlmc_train_batch(points.c(), ctypes.byref(L), batch, seed, frame, step, output, _ptr(idx), _ptr(wx),
                                   _ptr(wy), _ptr(wz), _ptr(tgt), _stream()), "tlmc_train_batch")
     return Queries(wx, wy, wz, idx), tgt
 
@@ -368,6 +372,15 @@ def nirc_train_step(model: Model, points: Points, queries: Queries, target: torc
 
 TLMC_CHEB_COEFFS = 128
 TLMC_STATS = 8
+
+
+def tlmc_reference_occluded(points: Points, lobes, n_nodes: int = 64) -> torch.Tensor:
+    """Quadrature reference of the occluded scene's integral, [P, 3] FP64."""
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    F = torch.empty((points.count, 3), dtype=torch.float64, device=points.t[0].device)
+    _check(lib().tlmc_reference_occluded(points.c(), ctypes.byref(L), n_nodes, _ptr(F), _stream()),
+           "tlmc_reference_occluded")
+    return F
 
 
 def tlmc_reference_table(lobes, device="cuda") -> torch.Tensor:

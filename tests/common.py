@@ -20,8 +20,8 @@ class Samples:
     """B training samples of one frame and step drawn by the oracle: point indices, directions
     and targets, the directions and targets rounded to FP32."""
 
-    def __init__(self, points, lobes, B, seed, frame, step):
-        idx, d, t = oracle.train_batch(points, lobes, B, seed, frame, step)
+    def __init__(self, points, lobes, B, seed, frame, step, output=0):
+        idx, d, t = oracle.train_batch(points, lobes, B, seed, frame, step, output=output)
         self.idx = np.ascontiguousarray(idx, np.int32)
         self.d32 = np.ascontiguousarray(d, np.float32)
         self.t32 = np.ascontiguousarray(t, np.float32)
