@@ -256,7 +256,7 @@ typedef struct {
 size_t tlmc_batch_bytes(void);
 
 /* Fill a work list (host memory of tlmc_batch_bytes) for n requests (1..TLMC_BATCH_MAX_REQUESTS)
- * whose models share width and precision.  The caller copies it to device memory and launches
+ * whose models share width, precision and output mode.  The caller copies it to device memory and launches
  * tlmc_estimate_batch on it; the list only holds device pointers, so it stays valid as long as
  * the models and buffers it names do. */
 nirc_status tlmc_batch_build(const tlmc_request *requests /* host */, int32_t n, void *list /* host */);
@@ -265,8 +265,9 @@ nirc_status tlmc_batch_build(const tlmc_request *requests /* host */, int32_t n,
  * chunks of 128 points, re-staging weights only when the request changes.  Results are identical
  * to tlmc_estimate of each request alone.  The launch shape does not depend on the list, so a
  * captured launch (hipGraph) can be replayed after writing a different list to the same buffer.
- * width and precision must match the list's models. */
-nirc_status tlmc_estimate_batch(const void *list /* device */, int32_t width, int32_t precision, void *stream);
+ * width, precision and output (NIRC_OUTPUT_*) must match the list's models. */
+nirc_status tlmc_estimate_batch(const void *list /* device */, int32_t width, int32_t precision, int32_t output,
+                                void *stream);
 
 /* Reference integral of the occluded scene, F(x) = (1/pi) int V(x, w) L(x, w) (n . w) dw, by
  * tensor Gauss-Legendre quadrature with n_nodes (8..128) nodes per axis over the two uniforms of

@@ -472,7 +472,9 @@ nirc_status tlmc_batch_build(const tlmc_request *requests, int32_t n, void *list
     int64_t chunk = 0;
     for (int i = 0; i < n; ++i) {
         const tlmc_request &r = requests[i];
-        if (!r.model || r.model->W != m0->W || r.model->cfg.precision != m0->cfg.precision) return NIRC_ERR_INVALID_ARG;
+        if (!r.model || r.model->W != m0->W || r.model->cfg.precision != m0->cfg.precision ||
+            r.model->cfg.output != m0->cfg.output)
+            return NIRC_ERR_INVALID_ARG;
         if (check_points(r.points) != NIRC_OK || r.points.count < 1) return NIRC_ERR_INVALID_ARG;
         if (r.n_cache < 1 || r.n_cache > 4096 || !r.out_tl) return NIRC_ERR_INVALID_ARG;
         BatchRequest &q = d->req[i];
@@ -501,14 +503,16 @@ nirc_status tlmc_batch_build(const tlmc_request *requests, int32_t n, void *list
     return NIRC_OK;
 }
 
-nirc_status tlmc_estimate_batch(const void *list, int32_t width, int32_t precision, void *stream) {
+nirc_status tlmc_estimate_batch(const void *list, int32_t width, int32_t precision, int32_t output, void *stream) {
     if (!list) return NIRC_ERR_INVALID_ARG;
     if (width != 64) return NIRC_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     const int grid = kMaxResidentBlocks;   // one persistent workgroup per CU
-    if (precision == NIRC_FP32) return hip_status(launch_tlmc_multi_f32(width, (const BatchDesc *)list, grid, s));
+    if (!output_ok(output)) return NIRC_ERR_INVALID_ARG;
+    if (precision == NIRC_FP32)
+        return hip_status(launch_tlmc_multi_f32(width, output, (const BatchDesc *)list, grid, s));
     if (precision == NIRC_BF16 || precision == NIRC_FP16)
-        return hip_status(launch_tlmc_multi_h16(width, precision, (const BatchDesc *)list, grid, s));
+        return hip_status(launch_tlmc_multi_h16(width, precision, output, (const BatchDesc *)list, grid, s));
     return NIRC_ERR_INVALID_ARG;
 }
 

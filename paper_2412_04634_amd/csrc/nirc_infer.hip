@@ -237,7 +237,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
 
 // T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
 // current point group through the FP32 chain, then per-point accumulation.
-template <int W, int T>
+// OCC: the occluded-scene variants (visibility cache, radiance cache of the occluded scene),
+// selected at run time by `mode`; the radiance cache of the plain scene compiles without them.
+template <int W, int T, bool OCC>
 __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN dn, const float *db, const float *hs,
                                                const float *sD, const float *sH, const float *sO,
                                                const nirc_lobes &lobes, const float *rrad, int64_t pc,
@@ -274,7 +276,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
     for (int tt = 0; tt < T; ++tt) {
         const int Tt = T0 + tt;
         float y0, y1, y2;
-        if (mode == NIRC_OUTPUT_VISIBILITY) {   // uniform: predicted visibility times the known radiance
+        if (OCC && mode == NIRC_OUTPUT_VISIBILITY) {   // uniform: predicted visibility times the known radiance
             const int64_t pj = min(p0 + jq[tt], pts.count - 1);
             float Lq[3];
             field_eval(lobes, pts.px[pj], pts.py[pj], pts.pz[pj], dx[tt], dy[tt], dz[tt], Lq);
@@ -296,7 +298,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
                 Lr[2] = rrad[3 * pc + 2];
             } else {
                 field_eval(lobes, xs[0], xs[1], xs[2], dx[tt], dy[tt], dz[tt], Lr);
-                if (mode != NIRC_OUTPUT_RADIANCE) {   // the occluded scene's residual sample V L
+                if (OCC && mode != NIRC_OUTPUT_RADIANCE) {   // the occluded scene's residual sample V L
                     const float V = visibility(lobes, xs[0], dx[tt], dy[tt], dz[tt]);
                     Lr[0] *= V;
                     Lr[1] *= V;
@@ -324,7 +326,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 // results are summed per point with a 16-lane prefix sum; the residual tile evaluates the
 // field and subtracts.  Only the final per-point values leave the chip.
 // One point group (16 points from p0) through the FP32 chain.
-template <int W>
+template <int W, bool OCC>
 __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
                                                uint32_t key1, uint32_t frame, int mode, const float *rrad,
                                                float *out_tl,
@@ -354,11 +356,11 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_f32<W, TP>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
+            tlmc_tiles_f32<W, TP, OCC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
                                   g, col, fc0, fc1, fc2, fr0, fr1, fr2);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_f32<W, 1>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
+            tlmc_tiles_f32<W, 1, OCC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
                                  g, col, fc0, fc1, fc2, fr0, fr1, fr2);
         tb = tend;
     }
@@ -366,7 +368,7 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         store_estimate(p0 + col, 1.0f / (float)n_cache, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
 }
 
-template <int W, int WAVES>
+template <int W, int WAVES, bool OCC>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes lobes,
                                                          const float *__restrict__ packed,
                                                          int n_cache, DivN dn, uint32_t key0, uint32_t key1,
@@ -395,12 +397,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
     float *db = hs + 16 * W;               // directions, SoA [3][kDirSlots]
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_f32<W>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode, rrad, out_tl, out_c, out_r, s_lobes, gS,
+        tlmc_group_f32<W, OCC>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode, rrad, out_tl, out_c, out_r, s_lobes, gS,
                           sD, sH, sO, hs, db, lane, g, col);
 }
 
 // Continuous batching with the FP32 chain (see k_tlmc_multi_h16).
-template <int W, int WAVES>
+template <int W, int WAVES, bool OCC>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_f32(const BatchDesc *__restrict__ desc) {
     constexpr F32Layout L{W};
     constexpr int NW = InferLds<W>::kWeights;
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_f32(const BatchDesc *
         }
         const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
         if (grp < (s_req.pts.count + 15) >> 4)
-            tlmc_group_f32<W>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
+            tlmc_group_f32<W, OCC>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
                               __builtin_amdgcn_readfirstlane(s_req.mode), uniform_ptr(s_req.rrad), s_req.out_tl,
                               s_req.out_c, s_req.out_r, s_req.lobes,
                               (const float *)s_req.packed + L.offset(SEC_S), sD, sH, sO, hs, db, lane, g, col);
@@ -518,11 +520,14 @@ hipError_t launch_infer(int W, int prec, const Points &pts, const Queries &q, co
     return hipGetLastError();
 }
 
-hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStream_t s) {
+hipError_t launch_tlmc_multi_f32(int W, int mode, const BatchDesc *desc, int grid, hipStream_t s) {
     constexpr int WAVES = 8;
     static_assert(WAVES == kBatchChunkGroups, "chunk size");
     if (W != 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_tlmc_multi_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
+    if (mode == NIRC_OUTPUT_RADIANCE)
+        hipLaunchKernelGGL((k_tlmc_multi_f32<64, WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
+    else
+        hipLaunchKernelGGL((k_tlmc_multi_f32<64, WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
     return hipGetLastError();
 }
 
@@ -535,15 +540,24 @@ hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lob
                                s);
     constexpr int WAVES = 8;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, kMaxResidentBlocks);
-    if (W == 64)
-        hipLaunchKernelGGL((k_tlmc_f32<64, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes,
-                           (const float *)packed, n_cache, make_divn(n_cache), (uint32_t)seed, (uint32_t)(seed >> 32),
-                           (uint32_t)frame, mode, rrad, out_tl, out_c, out_r);
-    else if (W == 128)   // one wave per SIMD: the width-128 FP32 pass needs more than 256 registers
-        hipLaunchKernelGGL((k_tlmc_f32<128, 4>), dim3(grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks)),
-                           dim3(4 * 64), 0, s, pts, lobes, (const float *)packed, n_cache, make_divn(n_cache),
-                           (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, mode, rrad, out_tl, out_c,
-                           out_r);
+    const unsigned grid128 = grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks);
+    const DivN dn = make_divn(n_cache);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), f = (uint32_t)frame;
+    const float *pk = (const float *)packed;
+    const bool occ = mode != NIRC_OUTPUT_RADIANCE;
+    if (W == 64 && !occ)
+        hipLaunchKernelGGL((k_tlmc_f32<64, WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk, n_cache,
+                           dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+    else if (W == 64)
+        hipLaunchKernelGGL((k_tlmc_f32<64, WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk, n_cache,
+                           dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+    // width 128: one wave per SIMD (the width-128 FP32 pass needs more than 256 registers)
+    else if (W == 128 && !occ)
+        hipLaunchKernelGGL((k_tlmc_f32<128, 4, false>), dim3(grid128), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
+                           dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+    else if (W == 128)
+        hipLaunchKernelGGL((k_tlmc_f32<128, 4, true>), dim3(grid128), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
+                           dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -100,7 +100,9 @@ struct Tlmc16Lds {
 // current point group through the 16-bit chain.  The output layer of all T tiles lands in one
 // accumulator (tile tt in columns 3tt..3tt+2), so the exponential and the per-point sums are
 // done once per pass: a lane holds 4 consecutive queries of one tile and channel.
-template <int W, int PREC, int T>
+// OCC: the occluded-scene variants (visibility cache, radiance cache of the occluded scene),
+// selected at run time by `mode`; the radiance cache of the plain scene compiles without them.
+template <int W, int PREC, int T, bool OCC>
 __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN dn, const GroupSlab &gs,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
                                                const u32x4 (&dfrag)[W / 8], int lane, int g, int col, float &rdx,
@@ -155,7 +157,7 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
     const int Tt = T0 + tt;
     const int q0 = 4 * g;   // first query (row) of this lane within its tile
     float e0, e1, e2, e3;
-    if (mode == NIRC_OUTPUT_VISIBILITY) {
+    if (OCC && mode == NIRC_OUTPUT_VISIBILITY) {
         // uniform: predicted visibility times channel c of the known radiance, for this lane's
         // four queries (their staged directions and their points' positions)
         const int ts = min(tt, T - 1);   // lanes past the pass's tiles compute an unused value
@@ -255,7 +257,7 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
 // into the slab, then the N + 1 query tiles in passes of 4 (and single-tile remainders), then the
 // per-point combine and store.  Weights for the direction/hidden/output layers are in LDS; the
 // surface columns are read from global memory (gS).
-template <int W, int PREC, int TP = 4>
+template <int W, int PREC, int TP, bool OCC>
 __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
                                                uint32_t key1, uint32_t frame, int mode, const float *rrad,
                                                float *out_tl,
@@ -288,11 +290,11 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         int t = tb;
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_h16<W, PREC, TP>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
+            tlmc_tiles_h16<W, PREC, TP, OCC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
                                         p0, mode, lobes);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_h16<W, PREC, 1>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
+            tlmc_tiles_h16<W, PREC, 1, OCC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
                                        p0, mode, lobes);
         tb = tend;
     }
@@ -312,7 +314,7 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
             Lr[c] += __shfl_xor(Lr[c], 16);
             Lr[c] += __shfl_xor(Lr[c], 32);
         }
-        if (mode != NIRC_OUTPUT_RADIANCE) {   // the occluded scene's residual sample V L
+        if (OCC && mode != NIRC_OUTPUT_RADIANCE) {   // the occluded scene's residual sample V L
             const float V = visibility(lobes, xs[0], rdx, rdy, rdz);
             Lr[0] *= V;
             Lr[1] *= V;
@@ -341,7 +343,7 @@ __device__ inline GroupSlab group_slab(float *base, int W) {
 
 // Fused two-level estimator for one request: 16 points per wave at a time, grid-stride over
 // point groups; weights staged once per workgroup.
-template <int W, int PREC, int WAVES>
+template <int W, int PREC, int WAVES, bool OCC>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes lobes, const uint16_t *__restrict__ packed,
                                                          int n_cache, DivN dn, uint32_t key0, uint32_t key1,
                                                          uint32_t frame, int mode, const float *__restrict__ rrad,
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
     const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, W);
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode,
+        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2, OCC>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode,
                                                                  rrad,
                                                                  out_tl, out_c, out_r, s_lobes, gS, sD, sH, sOS, gs,
                                                                  lane, g, col);
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
 // request; a workgroup takes chunks in grid-stride order and re-stages weights and field in LDS
 // only when the request changes.  The list lives in device memory, so a captured launch can be
 // replayed with a different mix.
-template <int W, int PREC, int WAVES>
+template <int W, int PREC, int WAVES, bool OCC>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *__restrict__ desc) {
     constexpr H16Layout L{W};
     constexpr int NW = Infer16Lds<W>::kWeights;
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *
         }
         const int64_t grp = (int64_t)(chunk - s_req.chunk_begin) * WAVES + wave;
         if (grp < (s_req.pts.count + 15) >> 4)
-            tlmc_group_h16<W, PREC>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
+            tlmc_group_h16<W, PREC, 4, OCC>(s_req.pts, grp << 4, s_req.n_cache, s_req.dn, s_req.key0, s_req.key1, s_req.frame,
                                     __builtin_amdgcn_readfirstlane(s_req.mode), uniform_ptr(s_req.rrad), s_req.out_tl,
                                     s_req.out_c, s_req.out_r, s_req.lobes,
                                     (const uint16_t *)s_req.packed + L.offset(SEC_S), sD, sH, sOS, gs, lane, g, col);
@@ -451,47 +453,69 @@ hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q
     return hipGetLastError();
 }
 
-hipError_t launch_tlmc_multi_h16(int W, int prec, const BatchDesc *desc, int grid, hipStream_t s) {
+hipError_t launch_tlmc_multi_h16(int W, int prec, int mode, const BatchDesc *desc, int grid, hipStream_t s) {
     constexpr int WAVES = 8;
     static_assert(WAVES == kBatchChunkGroups, "chunk size");
     if (W != 64) return hipErrorInvalidValue;
-    if (prec == NIRC_BF16)
-        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
+    const bool occ = mode != NIRC_OUTPUT_RADIANCE;
+    if (prec == NIRC_BF16 && !occ)
+        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_BF16, WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
+    else if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_BF16, WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
+    else if (!occ)
+        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_FP16, WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
     else
-        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
+        hipLaunchKernelGGL((k_tlmc_multi_h16<64, NIRC_FP16, WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, s, desc);
     return hipGetLastError();
 }
+
+namespace {
+
+struct TlmcArgs {
+    Points pts;
+    nirc_lobes lobes;
+    const uint16_t *pk;
+    int n_cache;
+    DivN dn;
+    uint32_t k0, k1, f;
+    int mode;
+    const float *rrad;
+    float *tl, *c, *r;
+};
+
+template <int W, int PREC, int WAVES>
+void launch_h16_variant(const TlmcArgs &a, unsigned grid, hipStream_t s) {
+    if (a.mode == NIRC_OUTPUT_RADIANCE)
+        hipLaunchKernelGGL((k_tlmc_h16<W, PREC, WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, a.pts, a.lobes, a.pk,
+                           a.n_cache, a.dn, a.k0, a.k1, a.f, a.mode, a.rrad, a.tl, a.c, a.r);
+    else
+        hipLaunchKernelGGL((k_tlmc_h16<W, PREC, WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, s, a.pts, a.lobes, a.pk,
+                           a.n_cache, a.dn, a.k0, a.k1, a.f, a.mode, a.rrad, a.tl, a.c, a.r);
+}
+
+}  // namespace
 
 hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,
                            int n_cache, uint64_t seed, uint64_t frame, int mode, const float *rrad, float *out_tl,
                            float *out_c, float *out_r, hipStream_t s) {
     constexpr int WAVES = 8;
     const unsigned grid = grid_for((pts.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
-    const uint16_t *pk = (const uint16_t *)packed;
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), f = (uint32_t)frame;
-    const DivN dn = make_divn(n_cache);
+    const TlmcArgs a{pts, lobes, (const uint16_t *)packed, n_cache, make_divn(n_cache), (uint32_t)seed,
+                     (uint32_t)(seed >> 32), (uint32_t)frame, mode, rrad, out_tl, out_c, out_r};
     if (W == 64 && prec == NIRC_BF16)
-        hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+        launch_h16_variant<64, NIRC_BF16, WAVES>(a, grid, s);
     else if (W == 64)
-        hipLaunchKernelGGL((k_tlmc_h16<64, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+        launch_h16_variant<64, NIRC_FP16, WAVES>(a, grid, s);
     // width 128: from 16 cache queries per point on, one wave per SIMD with 4-tile passes (half the weight
     // traffic from L2 per tile); below that, two waves per SIMD with 2-tile passes hide the per-point work better
-    else if (W == 128 && n_cache >= 16) {
-        const unsigned g4 = grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks);
-        if (prec == NIRC_BF16)
-            hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
-                               dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
-        else
-            hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, 4>), dim3(g4), dim3(4 * 64), 0, s, pts, lobes, pk, n_cache,
-                               dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
-    } else if (W == 128 && prec == NIRC_BF16)
-        hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_BF16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+    else if (W == 128 && n_cache >= 16 && prec == NIRC_BF16)
+        launch_h16_variant<128, NIRC_BF16, 4>(a, grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks), s);
+    else if (W == 128 && n_cache >= 16)
+        launch_h16_variant<128, NIRC_FP16, 4>(a, grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks), s);
+    else if (W == 128 && prec == NIRC_BF16)
+        launch_h16_variant<128, NIRC_BF16, WAVES>(a, grid, s);
     else if (W == 128)
-        hipLaunchKernelGGL((k_tlmc_h16<128, NIRC_FP16, WAVES>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
-                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+        launch_h16_variant<128, NIRC_FP16, WAVES>(a, grid, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

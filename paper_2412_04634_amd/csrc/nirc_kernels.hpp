@@ -395,8 +395,9 @@ struct QuadNodes {
 hipError_t launch_reference_occluded(const Points &pts, const nirc_lobes &lobes, const QuadNodes &nodes, double *F,
                                      hipStream_t s);
 unsigned grid_for(int64_t units, int waves, int max_blocks);
-hipError_t launch_tlmc_multi_h16(int W, int prec, const BatchDesc *desc, int grid, hipStream_t s);
-hipError_t launch_tlmc_multi_f32(int W, const BatchDesc *desc, int grid, hipStream_t s);
+// mode: the output mode shared by every request of the list (NIRC_OUTPUT_*)
+hipError_t launch_tlmc_multi_h16(int W, int prec, int mode, const BatchDesc *desc, int grid, hipStream_t s);
+hipError_t launch_tlmc_multi_f32(int W, int mode, const BatchDesc *desc, int grid, hipStream_t s);
 hipError_t launch_infer_h16(int W, int prec, const Points &pts, const Queries &q, const void *packed, float *rgb,
                             int sig, hipStream_t s);
 hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes &lobes, const void *packed,

@@ -104,7 +104,7 @@ def lib():
             "tlmc_accumulate": (_i32, [_vp, _i64, _vp, _vp, _vp]),
             "tlmc_batch_bytes": (_sz, []),
             "tlmc_batch_build": (_i32, [ctypes.POINTER(_Request), _i32, _vp]),
-            "tlmc_estimate_batch": (_i32, [_vp, _i32, _i32, _vp]),
+            "tlmc_estimate_batch": (_i32, [_vp, _i32, _i32, _i32, _vp]),
             "nirc_train_frame": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i64, _i32, _u64, _u64, _vp, _vp]),
             "nirc_status_string": (ctypes.c_char_p, [_i32]),
         }
@@ -441,6 +441,7 @@ class Batch:
         self.dev = torch.zeros(self.nbytes, dtype=torch.uint8, device=device)
         self.width = None
         self.precision = None
+        self.output = None
         self._keep = []
         self._copied = None
 
@@ -467,12 +468,14 @@ class Batch:
         _check(lib().tlmc_batch_build(arr, n, ctypes.c_void_p(self.host.data_ptr())), "tlmc_batch_build")
         self.width = requests[0]["model"].width
         self.precision = requests[0]["model"].cfg.precision
+        self.output = requests[0]["model"].cfg.output
         self.dev.copy_(self.host, non_blocking=True)
         self._copied = torch.cuda.Event()
         self._copied.record()
 
     def launch(self):
-        _check(lib().tlmc_estimate_batch(ctypes.c_void_p(self.dev.data_ptr()), self.width, self.precision, _stream()),
+        _check(lib().tlmc_estimate_batch(ctypes.c_void_p(self.dev.data_ptr()), self.width, self.precision, self.output,
+                                         _stream()),
                "tlmc_estimate_batch")
 
 
