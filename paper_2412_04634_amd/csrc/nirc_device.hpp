@@ -118,6 +118,31 @@ __host__ __device__ inline void sincos_turns(float u, float &s, float &c) {
     c = (((j + 2) >> 2) & 1) ? -b : b;
 }
 
+// sin(pi t) and cos(pi t) for |t| <= 2^22 (the encoding's arguments 2^k v, |v| <= 1, k <= 7):
+// t = n/2 + r with n = rint(2t) and |r| <= 1/4, both exact; the Taylor series of sin (to x^9)
+// and cos (to x^10) at x = pi r in [-pi/4, pi/4]; then the quarter turn n mod 4 swaps the pair and
+// sets the signs.  Multiples of 1/2 give exact values; elsewhere a few ulp.
+__host__ __device__ inline void sincospi_small(float t, float &s, float &c) {
+#pragma clang fp contract(off)
+    const float nf = rintf(2.0f * t);
+    const float r = fmaf(nf, -0.5f, t);
+    const float x = r * 3.14159265358979323846f;
+    const float x2 = x * x;
+    float sp = fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+    sp = fmaf(x2, sp, 1.0f / 120.0f);
+    sp = fmaf(x2, sp, -1.0f / 6.0f);
+    const float sn = fmaf(x * x2, sp, x);
+    float cp = fmaf(x2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    cp = fmaf(x2, cp, -1.0f / 720.0f);
+    cp = fmaf(x2, cp, 1.0f / 24.0f);
+    cp = fmaf(x2, cp, -0.5f);
+    const float cs = fmaf(x2, cp, 1.0f);
+    const int q = (int)nf & 3;
+    const float a = (q & 1) ? cs : sn, b = (q & 1) ? sn : cs;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
 // Cosine-weighted direction about unit normal n from uniforms (u1, u2): local
 // (sqrt(u1) cos 2pi u2, sqrt(u1) sin 2pi u2, sqrt(1 - u1)) in the branchless orthonormal basis
 // of Duff et al. (JCGT 2017).  sin/cos from sincos_turns, square roots and the reciprocal from
@@ -223,7 +248,7 @@ __device__ inline f32x4 mfma4(float a, float b, f32x4 c) {
 
 // Exact-argument sin/cos(pi * 2^k * v): 2^k v is exact in FP32, sincospif reduces exactly.
 __device__ inline void enc_pair(float v, int k, float &s, float &c) {
-    sincospif(ldexpf(v, k), &s, &c);
+    sincospi_small(ldexpf(v, k), s, c);
 }
 
 // ReLU on the FP32 bits: a signed integer max with 0 maps every negative value (sign bit set)
