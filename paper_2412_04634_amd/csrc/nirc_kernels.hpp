@@ -217,18 +217,17 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
         dir_from_rand(ra, ca.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], wa[0], wa[1], wa[2]);
         dir_from_rand(rb, cb.half, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], wb[0], wb[1], wb[2]);
     }
-    // residual directions of points 2 rl, 2 rl + 1 (one Philox block): every lane computes the
-    // pair of rl = lane % 8 and all lanes store, so lanes with the same rl write the same values
-    // (no divergent branch: the SIMD pays for the block either way)
-    float ra_[3] = {0.f, 0.f, 0.f}, rb_[3] = {0.f, 0.f, 0.f};
-    const int rl = lane & 7;
+    // residual direction of point rl = lane % 16 of the group: every lane computes that of its rl
+    // and all lanes store, so lanes with the same rl write the same value (no divergent branch:
+    // the SIMD pays for one direction per lane either way)
+    float ra_[3] = {0.f, 0.f, 0.f};
+    const int rl = lane & 15;
     if (fold) {
-        const int64_t pa = p0 + 2 * rl;
+        const int64_t pa = p0 + rl;
         const DirCounter c = dir_counter((uint32_t)pa, 0, true);
         const Rand4 r = philox(c.c0, c.c1, frame, c.stream, key0, key1);
-        const int64_t qa_ = min(pa, P - 1), qb_ = min(pa + 1, P - 1);
-        dir_from_rand(r, 0, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], ra_[0], ra_[1], ra_[2]);
-        dir_from_rand(r, 1, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], rb_[0], rb_[1], rb_[2]);
+        const int64_t qa_ = min(pa, P - 1);
+        dir_from_rand(r, c.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], ra_[0], ra_[1], ra_[2]);
     }
     wave_sync();   // the previous batch's readers are done
 #pragma unroll
@@ -238,10 +237,7 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
     }
     if (fold) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            db[kDirSlots * d + 128 + 2 * rl] = ra_[d];
-            db[kDirSlots * d + 128 + 2 * rl + 1] = rb_[d];
-        }
+        for (int d = 0; d < 3; ++d) db[kDirSlots * d + 128 + rl] = ra_[d];
     }
     wave_sync();
 }
