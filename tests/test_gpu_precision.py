@@ -135,3 +135,24 @@ def test_train_step_refreshes_16bit_copy(nirc, prec):
     assert rel_l2(y, host(nirc.nirc_infer(f32, dp, q))) <= 1e-2
     np.testing.assert_array_equal(host(nirc.tlmc_estimate(model, dp, lob, 8, 1, 0)),
                                   host(nirc.tlmc_estimate(fresh, dp, lob, 8, 1, 0)))
+
+
+def test_full_4k_bf16_sampled_points(nirc):
+    # the largest serving frame: 3840 x 2160 points, N = 32, BF16, checked on sampled points
+    # (the oracle samples their directions by frame index) including the ragged tail
+    print("4K N=32 BF16 sampled", flush=True)
+    P, N = 3840 * 2160, 32
+    pts = wl.make_points(37, P)
+    lob = wl.make_lobes(37).packed()
+    w0 = wl.make_weights(37, W)
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.Model(w0, cfg=nirc.make_config(precision=PRECS["bf16"]), max_batch=0)
+    tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lob, N, 3, 1, parts=True))
+    rng = np.random.default_rng(1)
+    sel = np.unique(np.concatenate([rng.choice(P, 2000, replace=False), np.arange(P - 23, P)]))
+    sub = pts.subset(sel)
+    dirs = oracle.sample_dirs(sub, N, 3, 1, ids=sel)
+    o_tl, o_c, o_r = oracle.estimate(sub, lob, w0, W, N, 3, 1, dirs=dirs)
+    assert rel_l2(c[sel], o_c) <= 1e-2
+    assert np.linalg.norm(tl[sel] - o_tl) <= 1e-2 * np.linalg.norm(o_c)
+    assert np.isfinite(tl).all()

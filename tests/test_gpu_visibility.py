@@ -158,3 +158,14 @@ def test_train_frames_visibility(nirc):
     print("  visibility losses", np.round(losses, 5), "oracle", np.round(o_losses, 5), flush=True)
     assert np.max(np.abs(np.array(losses) - o_losses) / np.array(o_losses)) <= 1e-3
     assert rel_l2(host(model.get_weights()) - w0, w - w0) <= 1e-2
+
+
+def test_batch_rejects_mixed_output_modes(nirc):
+    pts = nirc.Points.from_workload(wl.make_points(117, 100))
+    lob = wl.make_lobes(117).packed()
+    a = nirc.Model(wl.make_weights(117, 64), max_batch=0)
+    b = nirc.Model(wl.make_weights(118, 64), cfg=nirc.make_config(output=VIS), max_batch=0)
+    reqs = [dict(model=m, points=pts, lobes=lob, n_cache=4, seed=1, frame=0, out_tl=torch.empty((100, 3), device="cuda"))
+            for m in (a, b)]
+    with pytest.raises(nirc.NircError):
+        nirc.Batch().set(reqs)
