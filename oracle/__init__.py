@@ -78,6 +78,22 @@ def lib():
         L.oracle_threads.restype = _int
         L.oracle_set_threads.argtypes = [_int]
         L.oracle_set_threads.restype = None
+        L.oracle_hash_entries.argtypes = [_int, _int, _dbl]
+        L.oracle_hash_entries.restype = _i64
+        L.oracle_hash_n_params.argtypes = [_int, _int, _int, _dbl]
+        L.oracle_hash_n_params.restype = _i64
+        L.oracle_hash_levels.argtypes = [_int, _int, _dbl, _i64p, _i64p, _i32p]
+        L.oracle_sh.argtypes = [_i64, _f64p, _f64p]
+        L.oracle_hash_encode.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _int, _int, _dbl,
+                                         _f64p])
+        L.oracle_hash_infer.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _int, _int, _int, _dbl,
+                                        _f64p])
+        L.oracle_hash_estimate.argtypes = ([_i64] + [_f32p] * 7 + [_f32p, _f64p, _int, _int, _int, _dbl, _int, _u64,
+                                           _u64, _Opt(_f64p), _Opt(_f64p), _Opt(_f64p), _Opt(_f64p),
+                                           _Opt(_f64p)])
+        L.oracle_hash_loss_grad.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _f64p, _int, _int,
+                                            _int, _dbl, _dbl, _int, _int, _Opt(_f64p)])
+        L.oracle_hash_loss_grad.restype = _dbl
         _lib = L
     return _lib
 
@@ -274,3 +290,87 @@ def mrse(estimate_rgb, reference_rgb, eps: float = 1e-2) -> float:
     e = np.asarray(estimate_rgb, np.float64)
     r = np.asarray(reference_rgb, np.float64)
     return float(np.mean((e - r) ** 2 / (r * r + eps)))
+
+
+# ------------------------------------------------------------------------------------------
+# The paper's own cache input: hash grid on x, spherical harmonics of w, identity / one-blob
+# surface values (64 inputs).  `grid` is (log2_table, base_res, growth).
+
+HASH_GRID = (18, 16, 1.5)
+
+
+def hash_entries(grid=HASH_GRID) -> int:
+    return int(lib().oracle_hash_entries(int(grid[0]), int(grid[1]), float(grid[2])))
+
+
+def hash_n_params(width: int, grid=HASH_GRID) -> int:
+    return int(lib().oracle_hash_n_params(width, int(grid[0]), int(grid[1]), float(grid[2])))
+
+
+def hash_mlp_params(width: int) -> int:
+    return width * 64 + 3 * width * width + 3 * width
+
+
+def hash_levels(grid=HASH_GRID):
+    """(resolution [12], first entry [12], dense flag [12]) of the hash grid's levels."""
+    res = np.zeros(12, np.int64)
+    off = np.zeros(12, np.int64)
+    dense = np.zeros(12, np.int32)
+    lib().oracle_hash_levels(int(grid[0]), int(grid[1]), float(grid[2]), res, off, dense)
+    return res, off, dense
+
+
+def sh(dirs) -> np.ndarray:
+    """Real spherical harmonics of degree <= 4, [Q, 25] FP64 (index l^2 + l + m)."""
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    out = np.zeros((dirs.shape[0], 25), np.float64)
+    lib().oracle_sh(dirs.shape[0], dirs, out)
+    return out
+
+
+def hash_encode(points, point_idx, dirs, table, grid=HASH_GRID) -> np.ndarray:
+    """The 64 inputs of each query, [Q, 64] FP64 (table: [entries * 2])."""
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    Q = dirs.shape[0]
+    out = np.zeros((Q, 64), np.float64)
+    idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
+    lib().oracle_hash_encode(Q, *_pts(points), idx, dirs, _w64(table), int(grid[0]), int(grid[1]),
+                             float(grid[2]), out)
+    return out
+
+
+def hash_infer(points, point_idx, dirs, w, width: int = 64, grid=HASH_GRID) -> np.ndarray:
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    Q = dirs.shape[0]
+    out = np.zeros((Q, 3), np.float64)
+    idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
+    lib().oracle_hash_infer(Q, *_pts(points), idx, dirs, _w64(w), width, int(grid[0]), int(grid[1]),
+                            float(grid[2]), out)
+    return out
+
+
+def hash_estimate(points, lobes_packed, w, n_cache: int, seed: int, frame: int, width: int = 64,
+                  grid=HASH_GRID, dirs=None, rrad=None):
+    """Two-level estimator of the hash-input cache: (F_tl, F_c, F_r), each [P, 3] FP64."""
+    P = points.count
+    tl = np.zeros((P, 3), np.float64)
+    c = np.zeros((P, 3), np.float64)
+    r = np.zeros((P, 3), np.float64)
+    d = None if dirs is None else np.ascontiguousarray(dirs, np.float64).reshape(P * (n_cache + 1) * 3)
+    rr = None if rrad is None else np.ascontiguousarray(rrad, np.float64).reshape(P * 3)
+    lib().oracle_hash_estimate(P, *_pts(points), np.ascontiguousarray(lobes_packed, np.float32), _w64(w), width,
+                               int(grid[0]), int(grid[1]), float(grid[2]), n_cache, seed, frame, d, rr, tl, c, r)
+    return tl, c, r
+
+
+def hash_loss_grad(points, point_idx, dirs, target, w, width: int = 64, grid=HASH_GRID, eps: float = 1e-2,
+                   frozen: bool = True, want_grad: bool = True, kind: int = LOSS_REL_L2):
+    """Loss (relative L2 or L2) of the hash-input cache and its gradient over MLP and table (FP64)."""
+    dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+    B = dirs.shape[0]
+    g = np.zeros(hash_n_params(width, grid), np.float64) if want_grad else None
+    idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
+    loss = lib().oracle_hash_loss_grad(B, *_pts(points), idx, dirs,
+                                       np.ascontiguousarray(target, np.float64).reshape(-1), _w64(w), width,
+                                       int(grid[0]), int(grid[1]), float(grid[2]), eps, int(frozen), int(kind), g)
+    return float(loss), g

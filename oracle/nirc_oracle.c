@@ -230,7 +230,7 @@ typedef struct {
     double y[3];        /* output */
 } acts_t;
 
-static void net_forward(const net_t *net, const double e[NFEAT], acts_t *a)
+static void net_forward(const net_t *net, const double *e, acts_t *a)
 {
     const double *x = e;
     for (int l = 0; l < 4; ++l) {
@@ -777,4 +777,398 @@ void oracle_quadrature(int64_t P, const float *px, const float *py, const float 
     }
     free(xs);
     free(ws);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* The paper's own cache input (Sec. "Neural Incident Radiance Cache": the list of encodings,
+ * the amortised surface encoding, and the inference-pipeline figure, whose neural input vector
+ * is 24 hash-grid + 25 spherical-harmonics + 3+8+4 surface values = 64):
+ *   - x: multiresolution hash encoding (Mueller, Evans, Schied, Keller, "Instant neural graphics
+ *     primitives with a multiresolution hash encoding", SIGGRAPH 2022), 12 levels of 2
+ *     trainable features.  Level l has resolution N_l = floor(N_0 b^l); the position, clamped to
+ *     the unit cube, is scaled by N_l; the 8 corners of its cell are looked up (a dense
+ *     (N_l+1)^3 table when that fits in T entries, else the spatial hash
+ *     (v0 * 1 xor v1 * 2654435761 xor v2 * 805459861) mod T) and blended trilinearly.
+ *   - w: real spherical harmonics of degree <= 4 (25 values).
+ *   - phi: shading normal (identity, 3), roughness as a one-blob encoding with 8 bins (Mueller,
+ *     McWilliams, Rousselle, Gross, Novak, "Neural importance sampling", TOG 2019: a Gaussian of
+ *     width 1/8 centred on the value, read at the bin centres), albedo (identity, 3; the white
+ *     Lambertian surface has albedo 1) and one zero slot.
+ * Canonical input order: hash (2 l + f), SH (l^2 + l + m), n, one-blob, albedo, zero.
+ * Canonical parameter vector: W1 [W x 64], W2..W4 [W x W], W5 [3 x W] (row-major), then the
+ * feature table, [entries][2], levels in order.                                               */
+#define H_LEVELS 12
+#define H_FEAT 2
+#define H_IN 64
+#define H_SH 25
+#define H_MAX_LOG2T 24
+
+typedef struct {
+    int64_t T;
+    int64_t res[H_LEVELS], size[H_LEVELS], off[H_LEVELS];
+    int dense[H_LEVELS];
+    int64_t entries;
+} hgrid_t;
+
+static void hgrid_setup(hgrid_t *g, int log2_table, int base_res, double growth)
+{
+    g->T = (int64_t)1 << log2_table;
+    int64_t o = 0;
+    for (int l = 0; l < H_LEVELS; ++l) {
+        int64_t N = (int64_t)floor((double)base_res * pow(growth, (double)l));
+        int64_t v = (N + 1) * (N + 1) * (N + 1);
+        g->res[l] = N;
+        g->dense[l] = v <= g->T;
+        g->size[l] = g->dense[l] ? v : g->T;
+        g->off[l] = o;
+        o += g->size[l];
+    }
+    g->entries = o;
+}
+
+int64_t oracle_hash_entries(int log2_table, int base_res, double growth)
+{
+    hgrid_t g;
+    hgrid_setup(&g, log2_table, base_res, growth);
+    return g.entries;
+}
+
+/* Resolution, first entry and dense flag of every level (for tests). */
+void oracle_hash_levels(int log2_table, int base_res, double growth, int64_t *res, int64_t *off, int32_t *dense)
+{
+    hgrid_t g;
+    hgrid_setup(&g, log2_table, base_res, growth);
+    for (int l = 0; l < H_LEVELS; ++l) {
+        res[l] = g.res[l];
+        off[l] = g.off[l];
+        dense[l] = g.dense[l];
+    }
+}
+
+/* Entry index (within the whole table) and trilinear weight of the 8 cell corners of x at level l. */
+static void hash_corners(const hgrid_t *g, int l, const double x[3], int64_t idx[8], double wt[8])
+{
+    const int64_t N = g->res[l];
+    int64_t c[3];
+    double fr[3];
+    for (int d = 0; d < 3; ++d) {
+        double xc = x[d] < 0.0 ? 0.0 : (x[d] > 1.0 ? 1.0 : x[d]);
+        double p = xc * (double)N;
+        int64_t ci = (int64_t)floor(p);
+        if (ci > N - 1) ci = N - 1;
+        c[d] = ci;
+        fr[d] = p - (double)ci;
+    }
+    for (int k = 0; k < 8; ++k) {
+        int64_t v[3];
+        double w = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            int bit = (k >> d) & 1;
+            v[d] = c[d] + bit;
+            w *= bit ? fr[d] : 1.0 - fr[d];
+        }
+        int64_t i;
+        if (g->dense[l]) {
+            i = v[0] + (N + 1) * (v[1] + (N + 1) * v[2]);
+        } else {
+            uint32_t h = (uint32_t)v[0] * 1u ^ (uint32_t)v[1] * 2654435761u ^ (uint32_t)v[2] * 805459861u;
+            i = (int64_t)(h % (uint32_t)g->T);
+        }
+        idx[k] = g->off[l] + i;
+        wt[k] = w;
+    }
+}
+
+static double factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+/* Real spherical harmonics of degree <= 4 of the direction w (normalised here), without the
+ * Condon-Shortley phase: index l^2 + l + m,
+ *   m = 0: K_l^0 P_l(cos t);  m > 0: sqrt(2) K_l^m cos(m phi) P_l^m(cos t);
+ *   m < 0: sqrt(2) K_l^|m| sin(|m| phi) P_l^|m|(cos t);  K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!).
+ * P_l^m from the standard recurrences: P_m^m = (2m-1)!! sin^m t, P_{m+1}^m = (2m+1) cos t P_m^m,
+ * (l-m) P_l^m = (2l-1) cos t P_{l-1}^m - (l+m-1) P_{l-2}^m.                                     */
+static void sh25(const double w_in[3], double Y[H_SH])
+{
+    double r = sqrt(w_in[0] * w_in[0] + w_in[1] * w_in[1] + w_in[2] * w_in[2]);
+    double x = w_in[0] / r, y = w_in[1] / r, z = w_in[2] / r;
+    double s = sqrt(x * x + y * y);
+    double phi = atan2(y, x);
+    double P[5][5];
+    memset(P, 0, sizeof(P));
+    for (int m = 0; m <= 4; ++m) {
+        double pmm = 1.0;
+        for (int k = 1; k <= m; ++k) pmm *= (2.0 * k - 1.0) * s;
+        P[m][m] = pmm;
+        if (m < 4) P[m + 1][m] = (2.0 * m + 1.0) * z * pmm;
+        for (int l = m + 2; l <= 4; ++l)
+            P[l][m] = ((2.0 * l - 1.0) * z * P[l - 1][m] - (double)(l + m - 1) * P[l - 2][m]) / (double)(l - m);
+    }
+    for (int l = 0; l <= 4; ++l)
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * factorial(l - am) / factorial(l + am));
+            double v;
+            if (m == 0) v = K * P[l][0];
+            else if (m > 0) v = sqrt(2.0) * K * cos(m * phi) * P[l][m];
+            else v = sqrt(2.0) * K * sin(am * phi) * P[l][am];
+            Y[l * l + l + m] = v;
+        }
+}
+
+void oracle_sh(int64_t Q, const double *dirs, double *Y)
+{
+    for (int64_t q = 0; q < Q; ++q) sh25(dirs + 3 * q, Y + H_SH * q);
+}
+
+/* One-blob encoding of v in [0,1] with 8 bins: exp(-((v - (i + 1/2)/8) / (1/8))^2 / 2). */
+static void oneblob8(double v, double out[8])
+{
+    for (int i = 0; i < 8; ++i) {
+        double d = (v - (i + 0.5) / 8.0) * 8.0;
+        out[i] = exp(-0.5 * d * d);
+    }
+}
+
+/* The 64 inputs of point p and direction w; the table holds [entries][2] features. */
+static void hash_inputs(const hgrid_t *g, const double *table, const float *const pts[7], int64_t p,
+                        const double w[3], double e[H_IN])
+{
+    double x[3] = {pts[0][p], pts[1][p], pts[2][p]};
+    for (int l = 0; l < H_LEVELS; ++l) {
+        int64_t idx[8];
+        double wt[8];
+        hash_corners(g, l, x, idx, wt);
+        for (int f = 0; f < H_FEAT; ++f) {
+            double s = 0.0;
+            for (int k = 0; k < 8; ++k) s += wt[k] * table[2 * idx[k] + f];
+            e[2 * l + f] = s;
+        }
+    }
+    sh25(w, e + 24);
+    e[49] = pts[3][p];
+    e[50] = pts[4][p];
+    e[51] = pts[5][p];
+    oneblob8(pts[6][p], e + 52);
+    e[60] = e[61] = e[62] = 1.0;
+    e[63] = 0.0;
+}
+
+static int64_t hash_mlp_params(int width) { return (int64_t)width * H_IN + 3LL * width * width + 3LL * width; }
+
+int64_t oracle_hash_n_params(int width, int log2_table, int base_res, double growth)
+{
+    return hash_mlp_params(width) + 2 * oracle_hash_entries(log2_table, base_res, growth);
+}
+
+static void hash_net_setup(net_t *net, const double *w, int width)
+{
+    net->width = width;
+    net->vis = 0;
+    int rows[5] = {width, width, width, width, 3};
+    int cols[5] = {H_IN, width, width, width, width};
+    size_t off = 0;
+    for (int l = 0; l < 5; ++l) {
+        net->W[l] = w + off;
+        net->rows[l] = rows[l];
+        net->cols[l] = cols[l];
+        off += (size_t)rows[l] * cols[l];
+    }
+}
+
+void oracle_hash_encode(int64_t Q, const float *px, const float *py, const float *pz, const float *nx,
+                        const float *ny, const float *nz, const float *rough, const int32_t *point,
+                        const double *dirs, const double *table, int log2_table, int base_res, double growth,
+                        double *e /* [Q][64] */)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+    hgrid_t g;
+    hgrid_setup(&g, log2_table, base_res, growth);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) hash_inputs(&g, table, pts, point ? point[q] : q, dirs + 3 * q, e + H_IN * q);
+}
+
+void oracle_hash_infer(int64_t Q, const float *px, const float *py, const float *pz, const float *nx,
+                       const float *ny, const float *nz, const float *rough, const int32_t *point,
+                       const double *dirs, const double *w, int width, int log2_table, int base_res,
+                       double growth, double *rgb)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+    hgrid_t g;
+    hgrid_setup(&g, log2_table, base_res, growth);
+    net_t net;
+    hash_net_setup(&net, w, width);
+    const double *table = w + hash_mlp_params(width);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < Q; ++q) {
+        double e[H_IN];
+        acts_t a;
+        hash_inputs(&g, table, pts, point ? point[q] : q, dirs + 3 * q, e);
+        net_forward(&net, e, &a);
+        for (int c = 0; c < 3; ++c) rgb[3 * q + c] = a.y[c];
+    }
+}
+
+/* The two-level estimator of the radiance cache on this input (the same three sums as for the
+ * frequency input; directions sampled here, or given as [P][N+1][3]). */
+void oracle_hash_estimate(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
+                          const float *ny, const float *nz, const float *rough, const float *lobes,
+                          const double *w, int width, int log2_table, int base_res, double growth, int n_cache,
+                          uint64_t seed, uint64_t frame, const double *dirs, const double *residual_radiance,
+                          double *out_tl, double *out_c, double *out_r)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+    lobes_t L;
+    lobes_unpack(lobes, &L);
+    hgrid_t g;
+    hgrid_setup(&g, log2_table, base_res, growth);
+    net_t net;
+    hash_net_setup(&net, w, width);
+    const double *table = w + hash_mlp_params(width);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < P; ++p) {
+        double x[3] = {px[p], py[p], pz[p]};
+        double n[3] = {nx[p], ny[p], nz[p]};
+        double fc[3] = {0, 0, 0}, fr[3];
+        for (int k = 0; k <= n_cache; ++k) {
+            double wdir[3];
+            if (dirs) {
+                const double *d = dirs + ((size_t)p * (n_cache + 1) + k) * 3;
+                wdir[0] = d[0]; wdir[1] = d[1]; wdir[2] = d[2];
+            } else {
+                double u1, u2;
+                direction_uniforms(seed, (uint32_t)p, k, k == n_cache, (uint32_t)frame, &u1, &u2);
+                cosine_direction(n, u1, u2, wdir);
+            }
+            double e[H_IN];
+            acts_t a;
+            hash_inputs(&g, table, pts, p, wdir, e);
+            net_forward(&net, e, &a);
+            if (k < n_cache) {
+                for (int c = 0; c < 3; ++c) fc[c] += a.y[c];
+            } else {
+                double Lw[3];
+                if (residual_radiance) {
+                    for (int c = 0; c < 3; ++c) Lw[c] = residual_radiance[3 * p + c];
+                } else {
+                    field_eval(&L, x, wdir, Lw);
+                }
+                for (int c = 0; c < 3; ++c) fr[c] = Lw[c] - a.y[c];
+            }
+        }
+        for (int c = 0; c < 3; ++c) {
+            double Fc = fc[c] / n_cache;
+            if (out_c) out_c[3 * p + c] = Fc;
+            if (out_r) out_r[3 * p + c] = fr[c];
+            if (out_tl) out_tl[3 * p + c] = Fc + fr[c];
+        }
+    }
+}
+
+/* Loss and gradient of the hash-input cache (kind 0 relative L2 with the denominator held
+ * constant unless frozen == 0, kind 1 plain L2), as for the frequency input; in addition the
+ * gradient reaches the inputs of the hash features, dloss/de_k = sum_r W1[r][k] delta1[r], and
+ * each table entry receives the trilinear weight of its corner times that (the scatter of the
+ * interpolation's transpose).  grad: [n_params] in canonical order (MLP, then table).         */
+double oracle_hash_loss_grad(int64_t B, const float *px, const float *py, const float *pz, const float *nx,
+                             const float *ny, const float *nz, const float *rough, const int32_t *point,
+                             const double *dirs, const double *target, const double *w, int width,
+                             int log2_table, int base_res, double growth, double eps, int frozen, int kind,
+                             double *grad)
+{
+    const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
+    hgrid_t g;
+    hgrid_setup(&g, log2_table, base_res, growth);
+    net_t net;
+    hash_net_setup(&net, w, width);
+    const int W = width;
+    const int64_t nm = hash_mlp_params(W), nt = 2 * g.entries;
+    const double *table = w + nm;
+    if (grad) memset(grad, 0, sizeof(double) * (size_t)(nm + nt));
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    double *tg = grad ? (double *)calloc((size_t)nthreads * nm, sizeof(double)) : NULL;
+    double *tl = (double *)calloc((size_t)nthreads, sizeof(double));
+    double *de = grad ? (double *)calloc((size_t)B * 24, sizeof(double)) : NULL;   /* dloss/d(hash inputs) */
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *gm = tg ? tg + (size_t)tid * nm : NULL;
+#pragma omp for schedule(static)
+        for (int64_t b = 0; b < B; ++b) {
+            double e[H_IN];
+            acts_t a;
+            hash_inputs(&g, table, pts, point ? point[b] : b, dirs + 3 * b, e);
+            net_forward(&net, e, &a);
+            double dz[3];
+            for (int c = 0; c < 3; ++c) {
+                double y = a.y[c], t = target[3 * b + c];
+                double d = y - t;
+                double den = (kind == 0) ? y * y + eps : 1.0;
+                tl[tid] += d * d / den;
+                double dy = 2.0 * d / den;
+                if (!frozen && kind == 0) dy -= d * d * 2.0 * y / (den * den);
+                dz[c] = dy * y / (3.0 * (double)B);
+            }
+            if (!gm) continue;
+            double *gW5 = gm + (size_t)W * H_IN + 3LL * W * W;
+            for (int c = 0; c < 3; ++c)
+                for (int j = 0; j < W; ++j) gW5[(size_t)c * W + j] += dz[c] * a.h[3][j];
+            double delta[256], prev[256];
+            for (int j = 0; j < W; ++j) {
+                double s = 0.0;
+                for (int c = 0; c < 3; ++c) s += net.W[4][(size_t)c * W + j] * dz[c];
+                delta[j] = a.z[3][j] > 0.0 ? s : 0.0;
+            }
+            for (int l = 3; l >= 1; --l) {
+                double *gW = gm + (size_t)W * H_IN + (size_t)(l - 1) * W * W;
+                for (int r = 0; r < W; ++r)
+                    for (int c = 0; c < W; ++c) gW[(size_t)r * W + c] += delta[r] * a.h[l - 1][c];
+                for (int c = 0; c < W; ++c) {
+                    double s = 0.0;
+                    for (int r = 0; r < W; ++r) s += net.W[l][(size_t)r * W + c] * delta[r];
+                    prev[c] = a.z[l - 1][c] > 0.0 ? s : 0.0;
+                }
+                memcpy(delta, prev, sizeof(double) * W);
+            }
+            for (int r = 0; r < W; ++r)
+                for (int c = 0; c < H_IN; ++c) gm[(size_t)r * H_IN + c] += delta[r] * e[c];
+            for (int k = 0; k < 24; ++k) {
+                double s = 0.0;
+                for (int r = 0; r < W; ++r) s += net.W[0][(size_t)r * H_IN + k] * delta[r];
+                de[24 * b + k] = s;
+            }
+        }
+    }
+    double loss = 0.0;
+    for (int t = 0; t < nthreads; ++t) loss += tl[t];
+    if (grad) {
+        for (int t = 0; t < nthreads; ++t)
+            for (int64_t i = 0; i < nm; ++i) grad[i] += tg[(size_t)t * nm + i];
+        double *gt = grad + nm;
+        for (int64_t b = 0; b < B; ++b) {
+            int64_t p = point ? point[b] : b;
+            double x[3] = {px[p], py[p], pz[p]};
+            for (int l = 0; l < H_LEVELS; ++l) {
+                int64_t idx[8];
+                double wt[8];
+                hash_corners(&g, l, x, idx, wt);
+                for (int k = 0; k < 8; ++k)
+                    for (int f = 0; f < H_FEAT; ++f) gt[2 * idx[k] + f] += wt[k] * de[24 * b + 2 * l + f];
+            }
+        }
+    }
+    free(tg);
+    free(tl);
+    free(de);
+    return loss / (3.0 * (double)B);
 }

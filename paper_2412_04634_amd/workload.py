@@ -29,6 +29,7 @@ N_FEATURES = N_INPUTS * N_FREQ * 2   # 160
 _STREAM_LOBES = 0
 _STREAM_POINTS = 1
 _STREAM_WEIGHTS = 2
+_STREAM_HASH_TABLE = 3
 
 
 def _rng(seed: int, stream: int) -> np.random.Generator:
@@ -129,6 +130,28 @@ def make_weights(seed: int, width: int) -> np.ndarray:
     for rows, cols in layer_shapes(width):
         a = math.sqrt(6.0 / (rows + cols))
         out.append((a * (2.0 * rng.random((rows, cols)) - 1.0)).ravel())
+    return np.concatenate(out).astype(np.float32)
+
+
+HASH_INPUTS = 64      # hash grid 12 x 2, spherical harmonics 25, surface values 3 + 8 + 4
+
+
+def hash_layer_shapes(width: int):
+    """(rows, cols) of the five weight matrices of the hash-input cache: 64->W, 3 x (W->W), W->3."""
+    return [(width, HASH_INPUTS), (width, width), (width, width), (width, width), (3, width)]
+
+
+def make_hash_weights(seed: int, width: int, table_floats: int, table_scale: float = 1e-4) -> np.ndarray:
+    """Glorot-uniform MLP weights (canonical layout) followed by `table_floats` trainable grid
+    features drawn uniformly from [-table_scale, table_scale] (the small initial features of the
+    hash-encoding literature).  The table length is the caller's: it follows from the grid."""
+    rng = _rng(seed, _STREAM_WEIGHTS)
+    out = []
+    for rows, cols in hash_layer_shapes(width):
+        a = math.sqrt(6.0 / (rows + cols))
+        out.append((a * (2.0 * rng.random((rows, cols)) - 1.0)).ravel())
+    trng = _rng(seed, _STREAM_HASH_TABLE)
+    out.append(table_scale * (2.0 * trng.random(int(table_floats)) - 1.0))
     return np.concatenate(out).astype(np.float32)
 
 
