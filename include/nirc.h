@@ -361,6 +361,94 @@ nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_l
                              int64_t batch, int32_t steps, uint64_t seed, uint64_t frame, float *loss,
                              void *stream);
 
+/* ==========================================================================================
+ * The paper's own cache input (Sec. "Neural Incident Radiance Cache": the list of encodings,
+ * the amortised surface encoding and the inference-pipeline figure, whose neural input vector
+ * has 24 + 25 + (3 + 8 + 4) = 64 entries):
+ *   - inputs 0..23: a multiresolution hash grid on x (Mueller et al., "Instant neural graphics
+ *     primitives with a multiresolution hash encoding", SIGGRAPH 2022) with 12 levels of 2
+ *     trainable FP32 features, input 2 l + f.  Level l has resolution N_l = floor(base_res *
+ *     growth^l); x, clamped to the unit cube, is scaled by N_l and the 8 corners of its cell are
+ *     blended trilinearly.  A level whose (N_l + 1)^3 vertices fit in T = 2^log2_table entries
+ *     is a dense table (vertex v at v0 + (N_l+1) (v1 + (N_l+1) v2)); the others hold T entries
+ *     addressed by (v0 * 1 xor v1 * 2654435761 xor v2 * 805459861) mod T;
+ *   - inputs 24..48: the real spherical harmonics of degree <= 4 of w (index 24 + l^2 + l + m;
+ *     m > 0: sqrt(2) K cos(m phi) P_l^m, m < 0: sqrt(2) K sin(|m| phi) P_l^|m|, no
+ *     Condon-Shortley phase; w is taken as unit length);
+ *   - inputs 49..63: the surface values phi: normal (identity), roughness as an 8-bin one-blob
+ *     (Mueller et al., "Neural importance sampling", TOG 2019: exp(-(8 r - i - 1/2)^2 / 2) for
+ *     bin i), albedo (identity, 1 1 1 for the white Lambertian surface) and a zero slot.
+ * Network: 64 -> 4 hidden ReLU layers of width 64 -> 3 -> exp, no biases.  Canonical parameter
+ * vector (FP32): W1 [64 x 64], W2, W3, W4 [64 x 64], W5 [3 x 64] (16,576 values), then the grid
+ * features [entries][2] with the levels in order.  The grid and the MLP use one Adam state.
+ * Supported: width 64, precision NIRC_BF16 or NIRC_FP16 (the layer products; grid features and
+ * their interpolation stay FP32), loss NIRC_LOSS_REL_L2 or NIRC_LOSS_L2, output
+ * NIRC_OUTPUT_RADIANCE; anything else is NIRC_ERR_UNSUPPORTED.  Conventions as above.
+ * ========================================================================================== */
+typedef struct nirc_hash_model nirc_hash_model;
+
+/* Grid shape (host).  log2_table 10..22 (18: 2,334,718 entries, 18.7 MB of FP32 features with
+ * base_res 16 and growth 1.5), base_res >= 2, growth in [1, 4], N_11 <= 2^20. */
+typedef struct {
+    int32_t log2_table;
+    int32_t base_res;
+    float growth;
+} nirc_hash_grid;
+
+/* Entries of the grid (0 for an invalid grid). */
+int64_t nirc_hash_entries(const nirc_hash_grid *grid);
+
+/* Length of the canonical parameter vector: 16,576 + 2 * entries (0 for an invalid grid). */
+int64_t nirc_hash_n_params(const nirc_hash_grid *grid);
+
+/* Resolution, first entry and dense flag (1/0) of the 12 levels, host arrays of 12. */
+nirc_status nirc_hash_levels(const nirc_hash_grid *grid, int32_t *res, int64_t *offset, int32_t *dense);
+
+/* Bytes of model state (FP32 parameters, Adam moments, 16-bit packed layers, step, flags) and
+ * of training workspace for batches up to max_batch (0 for an invalid configuration). */
+size_t nirc_hash_state_bytes(const nirc_config *cfg, const nirc_hash_grid *grid);
+size_t nirc_hash_workspace_bytes(const nirc_config *cfg, const nirc_hash_grid *grid, int64_t max_batch);
+
+/* Creates a model on caller memory (state: 256-byte aligned, nirc_hash_state_bytes; workspace:
+ * NULL for inference only, else 256-byte aligned) from init_w [nirc_hash_n_params] (device). */
+nirc_status nirc_hash_create(const nirc_config *cfg, const nirc_hash_grid *grid, void *state, size_t state_bytes,
+                             void *workspace, size_t workspace_bytes, const float *init_w, void *stream,
+                             nirc_hash_model **out);
+nirc_status nirc_hash_destroy(nirc_hash_model *model);
+
+/* Replace (and reset Adam) / read the canonical parameter vector [nirc_hash_n_params]. */
+nirc_status nirc_hash_set_weights(nirc_hash_model *model, const float *w, void *stream);
+nirc_status nirc_hash_get_weights(const nirc_hash_model *model, float *w, void *stream);
+
+/* Cache predictions for explicit queries: rgb [queries.count][3]. */
+nirc_status nirc_hash_infer(const nirc_hash_model *model, nirc_points points, nirc_queries queries, float *rgb,
+                            void *stream);
+
+/* The fused two-level estimator with this cache, as tlmc_estimate (same directions, same
+ * residual handling, same outputs); the surface part (grid lookup, phi and its first-layer
+ * product) is computed once per point and shared by its N + 1 queries. */
+nirc_status nirc_hash_estimate(const nirc_hash_model *model, nirc_points points, const nirc_lobes *field /* host */,
+                               int32_t n_cache, uint64_t seed, uint64_t frame, const float *residual_radiance,
+                               float *out_tl, float *out_c, float *out_r, void *stream);
+
+/* Loss (device float, may be NULL) and gradient grad [nirc_hash_n_params] (device) of a batch,
+ * without an update: MLP weight gradients, and for every grid entry the sum over samples of
+ * its trilinear weight times the loss gradient of its level's input (entries no sample
+ * touches get 0).  Needs the workspace. */
+nirc_status nirc_hash_loss_grad(nirc_hash_model *model, nirc_points points, nirc_queries queries,
+                                const float *target, float *grad, float *loss, void *stream);
+
+/* One Adam step over the whole parameter vector with the given gradient (skipped, with
+ * NIRC_FLAG_NONFINITE_GRAD raised, when it holds a non-finite value). */
+nirc_status nirc_hash_adam_step(nirc_hash_model *model, const float *grad, void *stream);
+
+/* Loss and gradient into the workspace, then the Adam step. */
+nirc_status nirc_hash_train_step(nirc_hash_model *model, nirc_points points, nirc_queries queries,
+                                 const float *target, float *loss, void *stream);
+
+/* Flags raised by training (synchronises the stream); 0xFFFFFFFF on error. */
+uint32_t nirc_hash_read_flags(const nirc_hash_model *model, void *stream);
+
 const char *nirc_status_string(nirc_status s);
 
 #ifdef __cplusplus

@@ -210,16 +210,18 @@ __device__ __forceinline__ void direction_operands(float dx, float dy, float dz,
 // output layer's fragments (4 shifted copies x KB) for output16_packed.
 // The direction-layer fragments (`dfrag`, [kb][mt], from load_dir_fragments) stay in registers
 // across passes.
-template <int W>
+// DKB: K-blocks of the direction section (2 for the frequency input, 1 for spherical harmonics).
+template <int W, int DKB = 2>
 __device__ __forceinline__ void load_dir_fragments(u32x4 (&dfrag)[W / 8], const uint16_t *sD, int lane) {
     constexpr int MT = W / 16;
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
+    for (int kb = 0; kb < DKB; ++kb)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) dfrag[kb * MT + mt] = *(const u32x4 *)(sD + ((mt * 2 + kb) * 64 + lane) * 8);
+        for (int mt = 0; mt < MT; ++mt)
+            dfrag[kb * MT + mt] = *(const u32x4 *)(sD + ((mt * DKB + kb) * 64 + lane) * 8);
 }
 
-template <int W, int PREC, int T>
+template <int W, int PREC, int T, int DKB = 2>
 __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
                                       const u32x4 (&dfrag)[W / 8], const uint16_t *sH, const uint16_t *sOS, int lane,
                                       u32x4 (&aout)[4 * (W / 32)]) {
@@ -238,7 +240,7 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
                 for (int mt = 0; mt < MT; ++mt) h[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
+        for (int kb = 0; kb < (layer == 0 ? DKB : 2); ++kb)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll

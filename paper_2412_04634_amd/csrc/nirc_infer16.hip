@@ -1,7 +1,7 @@
 // BF16 / FP16 inference kernels: per-query inference and the fused two-level estimator with
 // 16-bit MFMA operands and FP32 accumulation (master weights stay FP32; a 16-bit packed copy is
 // refreshed after every Adam step).
-#include "nirc_h16.hpp"
+#include "nirc_hash.hpp"
 
 namespace nirc {
 
@@ -102,7 +102,8 @@ struct Tlmc16Lds {
 // done once per pass: a lane holds 4 consecutive queries of one tile and channel.
 // OCC: the occluded-scene variants (visibility cache, radiance cache of the occluded scene),
 // selected at run time by `mode`; the radiance cache of the plain scene compiles without them.
-template <int W, int PREC, int T, bool OCC>
+// ENC 1: the hash-grid model's direction input (25 spherical harmonics, one K-block).
+template <int W, int PREC, int T, bool OCC, int ENC = 0>
 __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN dn, const GroupSlab &gs,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
                                                const u32x4 (&dfrag)[W / 8], int lane, int g, int col, float &rdx,
@@ -117,7 +118,11 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
         const int q = 16 * s0 + lane;
         const int e0 = 64 * (lane >> 4) + (lane & 15);   // entry (tile lane / 16, group 0, query lane % 16)
         wave_lds_order();   // after the previous pass's reads of fa / fb
-        dir_features16<PREC>(gs.db[q], gs.db[kDirSlots + q], gs.db[2 * kDirSlots + q], gs.fa + e0, gs.fb + e0, 16);
+        if constexpr (ENC == 1)
+            sh_features16<PREC>(gs.db[q], gs.db[kDirSlots + q], gs.db[2 * kDirSlots + q], gs.fa + e0, 16);
+        else
+            dir_features16<PREC>(gs.db[q], gs.db[kDirSlots + q], gs.db[2 * kDirSlots + q], gs.fa + e0, gs.fb + e0,
+                                 16);
         wave_lds_order();
     }
 #pragma unroll
@@ -134,9 +139,16 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(gs.hs + j * W + 16 * mt + 4 * g);
         if constexpr (T == 4) {
             const int e = (tt * 4 + g) * 16 + col;
-            const uint2 b = gs.fb[e];
             bd[tt][0] = gs.fa[e];
-            bd[tt][1] = u32x4{b.x, b.y, 0u, 0u};
+            if constexpr (ENC == 1) {
+                bd[tt][1] = u32x4{0u, 0u, 0u, 0u};
+            } else {
+                const uint2 b = gs.fb[e];
+                bd[tt][1] = u32x4{b.x, b.y, 0u, 0u};
+            }
+        } else if constexpr (ENC == 1) {
+            bd[tt][0] = sh_operand<PREC>(gs.db[qi], gs.db[kDirSlots + qi], gs.db[2 * kDirSlots + qi], g);
+            bd[tt][1] = u32x4{0u, 0u, 0u, 0u};
         } else {
             direction_operands<PREC>(gs.db[qi], gs.db[kDirSlots + qi], gs.db[2 * kDirSlots + qi], g, bd[tt][0],
                                      bd[tt][1]);
@@ -145,7 +157,7 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
     u32x4 hb[T][KB];
     u32x4 aout[4 * KB];
     if constexpr (lds_weights(W)) {
-        mlp16<W, PREC, T>(h, hb, bd, dfrag, sH, sOS, lane, aout);
+        mlp16<W, PREC, T, ENC == 1 ? 1 : 2>(h, hb, bd, dfrag, sH, sOS, lane, aout);
     } else {   // weights in global memory: keep their loads inside the pass
         mlp16_wide<W, PREC, T>(h, hb, bd, opaque(sD), opaque(sH), opaque(sOS), lane, aout);
     }
@@ -257,13 +269,17 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
 // into the slab, then the N + 1 query tiles in passes of 4 (and single-tile remainders), then the
 // per-point combine and store.  Weights for the direction/hidden/output layers are in LDS; the
 // surface columns are read from global memory (gS).
-template <int W, int PREC, int TP, bool OCC>
+// ENC 1: the hash-grid model (surface part from the grid `slv`/`table` and phi, direction part
+// from spherical harmonics).
+template <int W, int PREC, int TP, bool OCC, int ENC = 0>
 __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
                                                uint32_t key1, uint32_t frame, int mode, const float *rrad,
                                                float *out_tl,
                                                float *out_c, float *out_r, const nirc_lobes &lobes, const uint16_t *gS,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
-                                               const GroupSlab &gs, int lane, int g, int col) {
+                                               const GroupSlab &gs, int lane, int g, int col,
+                                               const HashLevel *slv = nullptr, uint32_t tmask = 0u,
+                                               const float2 *table = nullptr) {
     constexpr int MT = W / 16;
     const int64_t P = pts.count;
     const int n_tiles = n_cache + 1;
@@ -273,7 +289,15 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         f32x4 hsum[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
+        if constexpr (ENC == 1) {
+            static_assert(W == 64, "the hash-grid model has width 64");
+            u32x4 b0, b1;
+            float v[6], ph[15];
+            hash_surface_operands<PREC>(slv, tmask, table, xs, g, b0, b1, v, ph);
+            hash_layer1_surface<PREC>(hsum, opaque(gS), b0, b1, lane);
+        } else {
+            layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
+        }
         wave_sync();   // the previous group's readers of the slab are done
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(gs.hs + col * W + 16 * mt + 4 * g) = hsum[mt];
@@ -282,7 +306,7 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
     }
     float rdx = 0.f, rdy = 0.f, rdz = 0.f;
     u32x4 dfrag[W / 8];   // direction-layer fragments, resident across the group's passes
-    if constexpr (lds_weights(W)) load_dir_fragments<W>(dfrag, sD, lane);
+    if constexpr (lds_weights(W)) load_dir_fragments<W, ENC == 1 ? 1 : 2>(dfrag, sD, lane);
     for (int tb = 0; tb < n_tiles;) {
         const bool fold = n_tiles - tb == 9;   // last 8 cache tiles + the residual tile
         gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db, fold);
@@ -290,12 +314,12 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         int t = tb;
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_h16<W, PREC, TP, OCC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
-                                        p0, mode, lobes);
+            tlmc_tiles_h16<W, PREC, TP, OCC, ENC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy,
+                                                 rdz, pts, p0, mode, lobes);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_h16<W, PREC, 1, OCC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy, rdz, pts,
-                                       p0, mode, lobes);
+            tlmc_tiles_h16<W, PREC, 1, OCC, ENC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy,
+                                                rdz, pts, p0, mode, lobes);
         tb = tend;
     }
     wave_sync();
@@ -516,6 +540,157 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
         launch_h16_variant<128, NIRC_BF16, WAVES>(a, grid, s);
     else if (W == 128)
         launch_h16_variant<128, NIRC_FP16, WAVES>(a, grid, s);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// The hash-grid model (width 64).
+
+// packed16[e] = 16-bit(master[hash_packed_source(e)]); after an Adam step thread 0 commits it.
+template <int PREC>
+__global__ void k_hash_pack16(uint16_t *packed, const float *master, int64_t *step, uint32_t *flags, uint32_t *bad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < kHashPacked) {
+        const int64_t s = hash_packed_source(e);
+        packed[e] = (uint16_t)(pack2<PREC>(s >= 0 ? master[s] : 0.0f, 0.0f) & 0xFFFFu);
+    }
+    if (step && e == 0) {
+        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        else *step += 1;
+        *bad = 0u;
+    }
+}
+
+// Direction, hidden and output sections staged in LDS: [D, T0) of the hash layout.
+constexpr int kHashLdsWeights = hash_sec(SEC_T0) - kHashSecD;
+
+// Per-query inference, 16 queries per wave per iteration.
+template <int PREC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_hash_infer_h16(Points pts, Queries q, const uint16_t *__restrict__ packed,
+                                                               const float2 *__restrict__ table, HashGridArgs grid,
+                                                               float *__restrict__ rgb) {
+    __shared__ u32x4 wsm[kHashLdsWeights / 8];
+    __shared__ HashLevel s_lv[kHashLevels];
+    {
+        const u32x4 *src = (const u32x4 *)(packed + kHashSecD);
+        for (int i = threadIdx.x; i < kHashLdsWeights / 8; i += WAVES * 64) wsm[i] = src[i];
+        stage_levels(s_lv, grid);
+    }
+    __syncthreads();
+    const uint16_t *sD = (const uint16_t *)wsm;
+    const uint16_t *sH = sD + (hash_sec(SEC_H0) - kHashSecD);
+    const uint16_t *sOS = sD + (hash_sec(SEC_OS) - kHashSecD);
+    const uint16_t *gS = packed + kHashSecS;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t Q = q.count;
+    const int64_t n_tiles = (Q + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < n_tiles; tile += (int64_t)gridDim.x * WAVES) {
+        const int64_t qi = min((tile << 4) + col, Q - 1);
+        const int64_t p = query_point(q, pts, qi);
+        const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+        f32x4 h[1][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        u32x4 b0, b1;
+        float v[6], ph[15];
+        hash_surface_operands<PREC>(s_lv, grid.tmask, table, xs, g, b0, b1, v, ph);
+        hash_layer1_surface<PREC>(h[0], opaque(gS), b0, b1, lane);
+        u32x4 bd[1][2];
+        bd[0][0] = sh_operand<PREC>(q.wx[qi], q.wy[qi], q.wz[qi], g);
+        bd[0][1] = u32x4{0u, 0u, 0u, 0u};
+        u32x4 hb[1][2], aout[8], dfrag[8];
+        load_dir_fragments<64, 1>(dfrag, sD, lane);
+        mlp16<64, PREC, 1, 1>(h, hb, bd, dfrag, sH, sOS, lane, aout);
+        const f32x4 z = output16_packed<64, PREC, 1>(hb, aout);
+        if (col < 3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t qo = (tile << 4) + 4 * g + i;
+                if (qo < Q) rgb[3 * qo + col] = __expf(z[i]);
+            }
+        }
+    }
+}
+
+// Fused two-level estimator with the hash-grid model: the estimator of k_tlmc_h16 with the
+// grid/phi surface part (once per point) and spherical-harmonics directions.
+template <int PREC, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_hash_tlmc_h16(Points pts, nirc_lobes lobes,
+                                                              const uint16_t *__restrict__ packed,
+                                                              const float2 *__restrict__ table, HashGridArgs grid,
+                                                              int n_cache, DivN dn, uint32_t key0, uint32_t key1,
+                                                              uint32_t frame, const float *__restrict__ rrad,
+                                                              float *__restrict__ out_tl, float *__restrict__ out_c,
+                                                              float *__restrict__ out_r) {
+    constexpr int SLAB = Tlmc16Lds<64>::kSlab;
+    __shared__ u32x4 wsm[kHashLdsWeights / 8];
+    __shared__ f32x4 slab4[WAVES * SLAB / 4];
+    __shared__ nirc_lobes s_lobes;
+    __shared__ HashLevel s_lv[kHashLevels];
+    {
+        const u32x4 *src = (const u32x4 *)(packed + kHashSecD);
+        for (int i = threadIdx.x; i < kHashLdsWeights / 8; i += WAVES * 64) wsm[i] = src[i];
+        if (threadIdx.x == 0) s_lobes = lobes;
+        stage_levels(s_lv, grid);
+    }
+    __syncthreads();
+    const uint16_t *sD = (const uint16_t *)wsm;
+    const uint16_t *sH = sD + (hash_sec(SEC_H0) - kHashSecD);
+    const uint16_t *sOS = sD + (hash_sec(SEC_OS) - kHashSecD);
+    const uint16_t *gS = packed + kHashSecS;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, 64);
+    const int64_t n_groups = (pts.count + 15) >> 4;
+    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
+        tlmc_group_h16<64, PREC, 4, false, 1>(pts, grp << 4, n_cache, dn, key0, key1, frame, NIRC_OUTPUT_RADIANCE, rrad,
+                                              out_tl, out_c, out_r, s_lobes, gS, sD, sH, sOS, gs, lane, g, col, s_lv,
+                                              grid.tmask, table);
+}
+
+hipError_t launch_hash_pack16(uint16_t *packed, const float *master, int prec, hipStream_t s, int64_t *step,
+                              uint32_t *flags, uint32_t *bad) {
+    const dim3 grid((kHashPacked + 255) / 256), block(256);
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL(k_hash_pack16<NIRC_BF16>, grid, block, 0, s, packed, master, step, flags, bad);
+    else if (prec == NIRC_FP16)
+        hipLaunchKernelGGL(k_hash_pack16<NIRC_FP16>, grid, block, 0, s, packed, master, step, flags, bad);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_infer(int prec, const Points &pts, const Queries &q, const uint16_t *packed, const float *table,
+                             const HashGridArgs &grid, float *rgb, hipStream_t s) {
+    constexpr int WAVES = 4;
+    const unsigned nb = grid_for((q.count + 15) / 16, WAVES, 4 * kMaxResidentBlocks);
+    const float2 *t2 = (const float2 *)table;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_hash_infer_h16<NIRC_BF16, WAVES>), dim3(nb), dim3(WAVES * 64), 0, s, pts, q, packed, t2,
+                           grid, rgb);
+    else if (prec == NIRC_FP16)
+        hipLaunchKernelGGL((k_hash_infer_h16<NIRC_FP16, WAVES>), dim3(nb), dim3(WAVES * 64), 0, s, pts, q, packed, t2,
+                           grid, rgb);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_tlmc(int prec, const Points &pts, const nirc_lobes &lobes, const uint16_t *packed,
+                            const float *table, const HashGridArgs &grid, int n_cache, uint64_t seed, uint64_t frame,
+                            const float *rrad, float *out_tl, float *out_c, float *out_r, hipStream_t s) {
+    constexpr int WAVES = 8;
+    const unsigned nb = grid_for((pts.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
+    const float2 *t2 = (const float2 *)table;
+    const DivN dn = make_divn(n_cache);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), f = (uint32_t)frame;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_hash_tlmc_h16<NIRC_BF16, WAVES>), dim3(nb), dim3(WAVES * 64), 0, s, pts, lobes, packed,
+                           t2, grid, n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
+    else if (prec == NIRC_FP16)
+        hipLaunchKernelGGL((k_hash_tlmc_h16<NIRC_FP16, WAVES>), dim3(nb), dim3(WAVES * 64), 0, s, pts, lobes, packed,
+                           t2, grid, n_cache, dn, k0, k1, f, rrad, out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

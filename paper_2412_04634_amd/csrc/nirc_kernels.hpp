@@ -448,6 +448,13 @@ hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_pa
                               float inv_scale, float loss_norm, float *grad, float *loss,
                               uint32_t *bad, hipStream_t s);
 hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStream_t s);
+hipError_t launch_reduce_grad_n(int64_t np, const float *partials, const float *loss_partials, int nblocks,
+                                float inv_scale, float loss_norm, float *grad, float *loss, uint32_t *bad,
+                                hipStream_t s);
+hipError_t launch_check_finite_n(int64_t np, const float *grad, uint32_t *bad, hipStream_t s);
+hipError_t launch_adam_n(int64_t np, float *master, float *m, float *v, const float *grad, const int64_t *step,
+                         const uint32_t *bad, float lr, float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s);
 // Adam on the master weights, then the refresh of the copy the kernels read (the FP32 copy for
 // FP32 models, only the 16-bit copy for 16-bit models) and the step commit.
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,

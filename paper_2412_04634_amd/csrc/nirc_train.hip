@@ -763,4 +763,40 @@ hipError_t launch_adam(int W, float *master, float *m, float *v, const float *gr
     return hipGetLastError();
 }
 
+// Explicit-length variants (the hash-grid model's parameter vector).
+hipError_t launch_reduce_grad_n(int64_t np, const float *partials, const float *loss_partials, int nblocks,
+                                float inv_scale, float loss_norm, float *grad, float *loss, uint32_t *bad,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 63) / 64)), dim3(kReduceWaves * 64), 0, s, partials,
+                       loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite_n(int64_t np, const float *grad, uint32_t *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_finite, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, grad, np, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_n(int64_t np, float *master, float *m, float *v, const float *grad, const int64_t *step,
+                         const uint32_t *bad, float lr, float b1, float b2, float eps, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad, step, bad, np,
+                       lr, b1, b2, eps);
+    return hipGetLastError();
+}
+
+// g[i] *= scale, raising `bad` on a non-finite result.
+__global__ void k_scale_check(float *__restrict__ g, int64_t n, float scale, uint32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const float v = g[i] * scale;
+        g[i] = v;
+        if (bad && !isfinite(v)) atomicOr(bad, 1u);
+    }
+}
+
+hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, n, scale, bad);
+    return hipGetLastError();
+}
+
 }  // namespace nirc

@@ -4,7 +4,7 @@
 // are shared.  The per-sample output gradient is not divided by the batch size inside the
 // kernel (the host folds 1/B into the loss scale), which keeps every 16-bit delta near unit
 // magnitude whatever the batch; the reduction divides the scale out again.
-#include "nirc_h16.hpp"
+#include "nirc_hash.hpp"
 
 namespace nirc {
 
@@ -613,6 +613,286 @@ hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Quer
     else
         hipLaunchKernelGGL((k_grad_h16<64, NIRC_FP16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, pk, a,
                            partials, loss_partials);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// The hash-grid model (width 64): the same two phases as k_grad_h16 with the 64 grid / SH / phi
+// inputs.  In addition, after the first layer's delta, each sample's gradient with respect to
+// its 24 grid values (W1_grid^T delta1, from the TS section) is scattered into the grid-entry
+// gradient: each of the 8 corners of the sample's cell at a level receives its trilinear weight
+// times the level's two values, by FP32 atomic adds.
+namespace {
+struct HashGrad16Lds {
+    static constexpr int kH = 4 * 64 * kRow16;
+    static constexpr int kD = 4 * 64 * kRow16;
+    static constexpr int kD5 = 4 * kRow16;
+    static constexpr int kE = kHashIn * kRow16;
+    static constexpr int kTotal = kH + kD + kD5 + kE;
+};
+}  // namespace
+
+template <int PREC>
+__global__ __launch_bounds__(kWaves16 * 64) void k_hash_grad_h16(Points pts, Queries q,
+                                                                 const uint16_t *__restrict__ packed,
+                                                                 const float2 *__restrict__ table, HashGridArgs grid,
+                                                                 TrainArgs args, float *__restrict__ partials,
+                                                                 float *__restrict__ loss_partials,
+                                                                 float *__restrict__ gtab) {
+    constexpr int MT = 4, KB = 2, W = 64;
+    using S = HashGrad16Lds;
+    __shared__ u32x4 smem4[(S::kTotal + 7) / 8];
+    __shared__ float sLoss[kWaves16];
+    __shared__ HashLevel s_lv[kHashLevels];
+    uint16_t *smem = (uint16_t *)smem4;
+    uint16_t *sH = smem;
+    uint16_t *sD = sH + S::kH;
+    uint16_t *sD5 = sD + S::kD;
+    uint16_t *sE = sD5 + S::kD5;
+    stage_levels(s_lv, grid);
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t B = q.count;
+    const bool rel = args.loss_kind == NIRC_LOSS_REL_L2;
+    // the host passes loss_scale * B: k = 2 loss_scale / 3 per sample
+    const float kscale = 2.0f * args.loss_scale / (3.0f * (float)B);
+
+    f32x4 g1[MT], gh[3][MT], g5;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        g1[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gh[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    g5 = f32x4{0.f, 0.f, 0.f, 0.f};
+    float loss_acc = 0.0f;
+
+    const int64_t n_chunks = (B + kChunk16 - 1) / kChunk16;
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        {
+            const uint16_t *pk = opaque(packed);
+            const int s = 16 * wave + col;
+            const int64_t b = chunk * kChunk16 + s;
+            const bool valid = b < B;
+            const int64_t bi = valid ? b : B - 1;
+            const int64_t p = query_point(q, pts, bi);
+            const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+
+            // inputs: operands for the MFMAs and 16-bit rows [canonical input][sample] for dW1
+            u32x4 b0, b1;
+            float v[6], ph[15];
+            hash_surface_operands<PREC>(s_lv, grid.tmask, table, xs, g, b0, b1, v, ph);
+            float Y[25];
+            sh25(q.wx[bi], q.wy[bi], q.wz[bi], Y);
+            const u32x4 bd0 = sh_operand_of<PREC>(Y, g);
+            // the rows hold exactly the 16-bit operand values
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sE[hash_surface_input(0, g, j) * kRow16 + s] = half_of(b0, j);
+                if (8 * g + j < 25) sE[(24 + 8 * g + j) * kRow16 + s] = half_of(bd0, j);
+            }
+            if (g == 0) {
+#pragma unroll
+                for (int j = 0; j < 7; ++j) sE[(57 + j) * kRow16 + s] = half_of(b1, j);
+            }
+
+            // forward
+            u32x4 hb[4][KB];
+            {
+                f32x4 h[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                hash_layer1_surface<PREC>(h, pk + kHashSecS, b0, b1, lane);
+                const uint16_t *gD = pk + kHashSecD;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[mt] = mfma16<PREC>(*(const u32x4 *)(gD + (mt * 64 + lane) * 8), bd0, h[mt]);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) hb[0][kb] = chain_operand<PREC>(h[2 * kb], h[2 * kb + 1]);
+            }
+#pragma unroll
+            for (int l = 1; l < 4; ++l) {
+                const uint16_t *sec = pk + hash_sec(SEC_H0 + (l - 1));
+                f32x4 h[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        h[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), hb[l - 1][kb],
+                                             h[mt]);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) hb[l][kb] = chain_operand<PREC>(h[2 * kb], h[2 * kb + 1]);
+            }
+            f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            {
+                const uint16_t *sec = pk + hash_sec(SEC_O);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) z5 = mfma16<PREC>(*(const u32x4 *)(sec + (kb * 64 + lane) * 8), hb[3][kb], z5);
+            }
+#pragma unroll
+            for (int l = 0; l < 4; ++l) stage_chain<W>(sH + l * W * kRow16, hb[l], g, s);
+
+            float d5[3] = {0.f, 0.f, 0.f};
+            if (g == 0 && valid) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float lt;
+                    d5[c] = out_grad16(z5[c], args.target[3 * b + c], 0.0f, true, args.loss_eps, kscale, rel, 0.0f,
+                                       false, lt);
+                    loss_acc += lt;
+                }
+            }
+            if (g == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sD5[c * kRow16 + s] = to16<PREC>(c < 3 ? d5[c] : 0.0f);
+            }
+
+            // backward
+            f32x4 dl[MT];
+            u32x4 db1[KB];   // delta1 as chained B operands
+            {
+                const u32x4 bop = g == 0 ? u32x4{pack2<PREC>(d5[0], d5[1]), pack2<PREC>(d5[2], 0.0f), 0u, 0u}
+                                         : u32x4{0u, 0u, 0u, 0u};
+                const uint16_t *sec = pk + hash_sec(SEC_OT);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    dl[mt] = mfma16<PREC>(*(const u32x4 *)(sec + (mt * 64 + lane) * 8), bop, f32x4{0.f, 0.f, 0.f, 0.f});
+            }
+#pragma unroll
+            for (int l = 3; l >= 0; --l) {
+                u32x4 db[KB];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint16_t hv = half_of(hb[l][mt >> 1], 4 * (mt & 1) + i);
+                        if (hv == 0) dl[mt][i] = 0.0f;
+                    }
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) db[kb] = chain_plain<PREC>(dl[2 * kb], dl[2 * kb + 1]);
+                stage_chain<W>(sD + l * W * kRow16, db, g, s);
+                if (l == 0) {
+                    db1[0] = db[0];
+                    db1[1] = db[1];
+                    break;
+                }
+                const uint16_t *sec = pk + hash_sec(SEC_T0 + (l - 1));
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) dl[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        dl[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), db[kb], dl[mt]);
+            }
+            // gradient of the grid values: rows 16 mt + 4 g + i of W1_grid^T delta1 for this
+            // sample (column col); rows 2 k and 2 k + 1 are the two values of level k
+            const uint16_t *sec = pk + kHashSecTS;
+            f32x4 de[2];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                de[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    de[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), db1[kb],
+                                          de[mt]);
+            }
+            // straight-line scatter (no lane-dependent branches): padding rows 24..31 (lane groups
+            // 2, 3 of the second tile) and the padded samples of the last round add zeros
+            const float keep = valid ? 1.0f : 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int hl = 0; hl < 2; ++hl) {
+                    const int lraw = 8 * mt + 2 * g + hl;
+                    const int level = min(lraw, kHashLevels - 1);
+                    const float k = lraw < kHashLevels ? keep : 0.0f;
+                    const float d0 = k * de[mt][2 * hl], d1 = k * de[mt][2 * hl + 1];
+                    const HashLevel lv = s_lv[level];
+                    const HashCell cell = hash_cell(xs[0], xs[1], xs[2], lv.res);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        float w;
+                        const uint32_t e = hash_entry(lv, grid.tmask, cell, c, w);
+                        unsafeAtomicAdd(gtab + 2 * (size_t)e, w * d0);
+                        unsafeAtomicAdd(gtab + 2 * (size_t)e + 1, w * d1);
+                    }
+                }
+        }
+        __syncthreads();
+        // phase 2: owned weight-gradient tiles (W1: inputs 16 wave .. 16 wave + 15)
+#pragma unroll
+        for (int kb = 0; kb < kChunk16 / 32; ++kb) {
+            const int s0 = 32 * kb + 8 * g;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const u32x4 bv = *(const u32x4 *)(sH + (a * W + 16 * wave + col) * kRow16 + s0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const u32x4 av = *(const u32x4 *)(sD + ((a + 1) * W + 16 * mt + col) * kRow16 + s0);
+                    gh[a][mt] = mfma16<PREC>(av, bv, gh[a][mt]);
+                }
+            }
+            {
+                const u32x4 bv = *(const u32x4 *)(sH + (3 * W + 16 * wave + col) * kRow16 + s0);
+                u32x4 av = u32x4{0u, 0u, 0u, 0u};
+                if (col < 3) av = *(const u32x4 *)(sD5 + col * kRow16 + s0);
+                g5 = mfma16<PREC>(av, bv, g5);
+            }
+            {
+                const u32x4 bv = *(const u32x4 *)(sE + (16 * wave + col) * kRow16 + s0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const u32x4 av = *(const u32x4 *)(sD + (16 * mt + col) * kRow16 + s0);
+                    g1[mt] = mfma16<PREC>(av, bv, g1[mt]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    float *out = partials + (int64_t)blockIdx.x * kHashMlp;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[(int64_t)(16 * mt + 4 * g + i) * kHashIn + 16 * wave + col] = g1[mt][i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[W * kHashIn + a * W * W + (int64_t)(16 * mt + 4 * g + i) * W + 16 * wave + col] = gh[a][mt][i];
+    if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[W * kHashIn + 3 * W * W + (int64_t)i * W + 16 * wave + col] = g5[i];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) loss_acc += __shfl_xor(loss_acc, d, 64);
+    if (lane == 0) sLoss[wave] = loss_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kWaves16; ++w) t += sLoss[w];
+        loss_partials[blockIdx.x] = t;
+    }
+}
+
+hipError_t launch_hash_grad(int prec, const Points &pts, const Queries &q, const uint16_t *packed, const float *table,
+                            const HashGridArgs &grid, TrainArgs a, float *partials, float *loss_partials,
+                            float *gtab, int nblocks, hipStream_t s) {
+    if (!a.target) return hipErrorInvalidValue;
+    const float2 *t2 = (const float2 *)table;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_hash_grad_h16<NIRC_BF16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, packed, t2,
+                           grid, a, partials, loss_partials, gtab);
+    else if (prec == NIRC_FP16)
+        hipLaunchKernelGGL((k_hash_grad_h16<NIRC_FP16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, packed, t2,
+                           grid, a, partials, loss_partials, gtab);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -55,6 +55,10 @@ class _Request(ctypes.Structure):
                 ("frame", _u64), ("residual_radiance", _vp), ("out_tl", _vp), ("out_c", _vp), ("out_r", _vp)]
 
 
+class HashGrid(ctypes.Structure):
+    _fields_ = [("log2_table", _i32), ("base_res", _i32), ("growth", ctypes.c_float)]
+
+
 class NircError(RuntimeError):
     pass
 
@@ -106,6 +110,23 @@ def lib():
             "tlmc_batch_build": (_i32, [ctypes.POINTER(_Request), _i32, _vp]),
             "tlmc_estimate_batch": (_i32, [_vp, _i32, _i32, _i32, _vp]),
             "nirc_train_frame": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i64, _i32, _u64, _u64, _vp, _vp]),
+            "nirc_hash_entries": (_i64, [ctypes.POINTER(HashGrid)]),
+            "nirc_hash_n_params": (_i64, [ctypes.POINTER(HashGrid)]),
+            "nirc_hash_levels": (_i32, [ctypes.POINTER(HashGrid), _vp, _vp, _vp]),
+            "nirc_hash_state_bytes": (_sz, [ctypes.POINTER(Config), ctypes.POINTER(HashGrid)]),
+            "nirc_hash_workspace_bytes": (_sz, [ctypes.POINTER(Config), ctypes.POINTER(HashGrid), _i64]),
+            "nirc_hash_create": (_i32, [ctypes.POINTER(Config), ctypes.POINTER(HashGrid), _vp, _sz, _vp, _sz, _vp,
+                                        _vp, ctypes.POINTER(_vp)]),
+            "nirc_hash_destroy": (_i32, [_vp]),
+            "nirc_hash_set_weights": (_i32, [_vp, _vp, _vp]),
+            "nirc_hash_get_weights": (_i32, [_vp, _vp, _vp]),
+            "nirc_hash_infer": (_i32, [_vp, _Points, _Queries, _vp, _vp]),
+            "nirc_hash_estimate": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp,
+                                          _vp, _vp]),
+            "nirc_hash_loss_grad": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp, _vp]),
+            "nirc_hash_adam_step": (_i32, [_vp, _vp, _vp]),
+            "nirc_hash_train_step": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
+            "nirc_hash_read_flags": (_u32, [_vp, _vp]),
             "nirc_status_string": (ctypes.c_char_p, [_i32]),
         }
         for name, (res, args) in sig.items():
@@ -497,3 +518,113 @@ class NircFunction(torch.autograd.Function):
     def backward(ctx, dy):
         g = nirc_backward(ctx.model, ctx.points, ctx.queries, dy.contiguous())
         return g, None, None, None
+
+
+# ------------------------------------------------------------------------------------------
+# The hash-grid cache input (hash grid on x, spherical harmonics of w, identity / one-blob phi)
+
+def make_hash_grid(log2_table: int = 18, base_res: int = 16, growth: float = 1.5) -> HashGrid:
+    return HashGrid(log2_table, base_res, growth)
+
+
+def nirc_hash_entries(grid: HashGrid) -> int:
+    return int(lib().nirc_hash_entries(ctypes.byref(grid)))
+
+
+def nirc_hash_n_params(grid: HashGrid) -> int:
+    return int(lib().nirc_hash_n_params(ctypes.byref(grid)))
+
+
+def nirc_hash_levels(grid: HashGrid):
+    """(resolution [12], first entry [12], dense flag [12]) as numpy arrays."""
+    res = np.zeros(12, np.int32)
+    off = np.zeros(12, np.int64)
+    dense = np.zeros(12, np.int32)
+    _check(lib().nirc_hash_levels(ctypes.byref(grid), res.ctypes.data, off.ctypes.data, dense.ctypes.data),
+           "nirc_hash_levels")
+    return res, off, dense
+
+
+class HashModel:
+    """A hash-grid cache model (width 64, 16-bit layer products) over torch-allocated memory."""
+
+    def __init__(self, init_w, cfg: Config | None = None, grid: HashGrid | None = None, max_batch: int = 65536,
+                 device="cuda"):
+        self.cfg = cfg or make_config(precision=NIRC_BF16)
+        self.grid = grid or make_hash_grid()
+        self.n_params = nirc_hash_n_params(self.grid)
+        sb = int(lib().nirc_hash_state_bytes(ctypes.byref(self.cfg), ctypes.byref(self.grid)))
+        if sb == 0 or self.n_params == 0:
+            raise NircError("unsupported hash-grid configuration")
+        self.state = torch.empty(sb, dtype=torch.uint8, device=device)
+        wb = int(lib().nirc_hash_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(self.grid), max_batch)) \
+            if max_batch > 0 else 0
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=device) if wb else None
+        w = init_w if isinstance(init_w, torch.Tensor) else _dev_f32(init_w, device)
+        assert w.numel() == self.n_params
+        self._w0 = w.contiguous()
+        h = _vp()
+        _check(lib().nirc_hash_create(ctypes.byref(self.cfg), ctypes.byref(self.grid), _ptr(self.state), sb,
+                                      _ptr(self.workspace), wb, _ptr(self._w0), _stream(), ctypes.byref(h)),
+               "nirc_hash_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.nirc_hash_destroy(h)
+            self.handle = None
+
+    def set_weights(self, w: torch.Tensor):
+        self._w0 = w.contiguous()
+        _check(lib().nirc_hash_set_weights(self.handle, _ptr(self._w0), _stream()), "nirc_hash_set_weights")
+
+    def get_weights(self) -> torch.Tensor:
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.state.device)
+        _check(lib().nirc_hash_get_weights(self.handle, _ptr(out), _stream()), "nirc_hash_get_weights")
+        return out
+
+    def read_flags(self) -> int:
+        return int(lib().nirc_hash_read_flags(self.handle, _stream()))
+
+
+def nirc_hash_infer(model: HashModel, points: Points, queries: Queries) -> torch.Tensor:
+    out = torch.empty((queries.count, 3), dtype=torch.float32, device=points.t[0].device)
+    _check(lib().nirc_hash_infer(model.handle, points.c(), queries.c(), _ptr(out), _stream()), "nirc_hash_infer")
+    return out
+
+
+def nirc_hash_estimate(model: HashModel, points: Points, lobes, n_cache: int, seed: int, frame: int,
+                       parts: bool = False, out=None, residual=None):
+    """Two-level estimate per point with the hash-grid cache; F_tl, or (F_tl, F_c, F_r)."""
+    dev = points.t[0].device
+    L = None if lobes is None else (lobes if isinstance(lobes, Lobes) else lobes_struct(lobes))
+    tl = out if out is not None else torch.empty((points.count, 3), dtype=torch.float32, device=dev)
+    c = torch.empty_like(tl) if parts else None
+    r = torch.empty_like(tl) if parts else None
+    if residual is not None:
+        assert residual.dtype == torch.float32 and residual.is_contiguous() and residual.numel() == 3 * points.count
+    _check(lib().nirc_hash_estimate(model.handle, points.c(), None if L is None else ctypes.byref(L), n_cache, seed,
+                                    frame, _ptr(residual), _ptr(tl), _ptr(c), _ptr(r), _stream()),
+           "nirc_hash_estimate")
+    return (tl, c, r) if parts else tl
+
+
+def nirc_hash_loss_grad(model: HashModel, points: Points, queries: Queries, target: torch.Tensor):
+    """(loss [1], gradient [n_params]) of a batch, without an update."""
+    grad = torch.empty(model.n_params, dtype=torch.float32, device=points.t[0].device)
+    loss = torch.empty(1, dtype=torch.float32, device=points.t[0].device)
+    t = target.contiguous()
+    _check(lib().nirc_hash_loss_grad(model.handle, points.c(), queries.c(), _ptr(t), _ptr(grad), _ptr(loss),
+                                     _stream()), "nirc_hash_loss_grad")
+    return loss, grad
+
+
+def nirc_hash_adam_step(model: HashModel, grad: torch.Tensor):
+    _check(lib().nirc_hash_adam_step(model.handle, _ptr(grad.contiguous()), _stream()), "nirc_hash_adam_step")
+
+
+def nirc_hash_train_step(model: HashModel, points: Points, queries: Queries, target: torch.Tensor, loss=None):
+    t = target.contiguous()
+    _check(lib().nirc_hash_train_step(model.handle, points.c(), queries.c(), _ptr(t), _ptr(loss), _stream()),
+           "nirc_hash_train_step")

@@ -55,3 +55,36 @@ def test_empty_inputs_are_no_ops():
     # zero points / zero queries enqueue nothing and succeed
     assert L.tlmc_sample_dirs(nirc._Points(), 4, 0, 0, None, None) == 0
     assert L.nirc_encode(nirc._Points(), nirc._Queries(), None, None) == 0
+
+
+def test_hash_grid_layout_matches_oracle():
+    # the library's level table (host computation) against the oracle's reading of the rule
+    import numpy as np
+    import oracle
+    for grid in ((18, 16, 1.5), (10, 4, 1.5), (22, 2, 2.0), (14, 8, 1.38)):
+        g = nirc.make_hash_grid(*grid)
+        res, off, dense = nirc.nirc_hash_levels(g)
+        o_res, o_off, o_dense = oracle.hash_levels(grid)
+        assert list(res) == list(o_res) and list(off) == list(o_off) and list(dense) == list(o_dense)
+        assert nirc.nirc_hash_entries(g) == oracle.hash_entries(grid)
+        assert nirc.nirc_hash_n_params(g) == oracle.hash_n_params(64, grid)
+    assert nirc.nirc_hash_n_params(nirc.make_hash_grid()) == 16576 + 2 * 2334718
+    # invalid grids
+    for grid in ((9, 16, 1.5), (23, 16, 1.5), (18, 1, 1.5), (18, 16, 0.5), (18, 16, 5.0), (18, 512, 4.0)):
+        assert nirc.nirc_hash_n_params(nirc.make_hash_grid(*grid)) == 0
+
+
+def test_hash_configuration_checks():
+    g = nirc.make_hash_grid()
+    L = nirc.lib()
+    ok = nirc.make_config(precision=nirc.NIRC_BF16)
+    assert L.nirc_hash_state_bytes(ctypes.byref(ok), ctypes.byref(g)) > 3 * 4 * nirc.nirc_hash_n_params(g)
+    assert L.nirc_hash_workspace_bytes(ctypes.byref(ok), ctypes.byref(g), 65536) > 0
+    for bad in (nirc.make_config(), nirc.make_config(width=128, precision=1), nirc.make_config(precision=1, loss=2),
+                nirc.make_config(precision=1, output=2)):
+        assert L.nirc_hash_state_bytes(ctypes.byref(bad), ctypes.byref(g)) == 0
+    h = ctypes.c_void_p()
+    assert L.nirc_hash_create(ctypes.byref(ok), ctypes.byref(g), None, 0, None, 0, None, None, ctypes.byref(h)) == -1
+    assert L.nirc_hash_infer(None, nirc._Points(), nirc._Queries(), None, None) == -1
+    assert L.nirc_hash_estimate(None, nirc._Points(), None, 8, 0, 0, None, None, None, None, None) == -1
+    assert L.nirc_hash_train_step(None, nirc._Points(), nirc._Queries(), None, None, None) == -1

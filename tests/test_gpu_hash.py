@@ -1,0 +1,213 @@
+"""The hash-grid cache input (12-level hash grid on x, degree-4 spherical harmonics of w,
+identity / one-blob surface values) on the GPU against the FP64 oracle (needs the GPU).
+
+Tolerances are those of the other 16-bit paths: outputs and estimator parts rel-L2 <= 1e-2,
+loss and gradients (MLP weights and grid entries) rel-L2 <= ten times the operand format's unit
+roundoff.  Grid features are drawn from [-0.5, 0.5] (not the 1e-4 training initialisation) so
+that the grid part of every input carries weight in the comparison.  Samples and weights come
+from the seeded generator or the oracle, never from the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2412_04634_amd import workload as wl
+from tests.common import Samples, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+PRECS = {"bf16": 1, "fp16": 2}
+GRAD_TOL = {"bf16": 10 * 2.0 ** -9, "fp16": 10 * 2.0 ** -12}
+GRIDS = {"default": (18, 16, 1.5), "small": (10, 4, 1.5)}
+
+
+@pytest.fixture(scope="module")
+def nirc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_04634_amd import nirc as m
+    m.lib()
+    return m
+
+
+def _model(nirc, prec, grid, seed, max_batch=0, scale=0.5, **cfg):
+    w = wl.make_hash_weights(seed, 64, 2 * oracle.hash_entries(grid), scale)
+    g = nirc.make_hash_grid(*grid)
+    m = nirc.HashModel(w, cfg=nirc.make_config(precision=PRECS[prec], **cfg), grid=g, max_batch=max_batch)
+    return m, w
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("grid", ["default", "small"])
+@pytest.mark.parametrize("Q", [1, 1000, 4099])
+def test_hash_infer(nirc, prec, grid, Q):
+    print(f"hash infer {prec} {grid} Q={Q}", flush=True)
+    P = 700
+    pts = wl.make_points(41, P)
+    dp = nirc.Points.from_workload(pts)
+    model, w = _model(nirc, prec, GRIDS[grid], 41)
+    g = torch.Generator().manual_seed(Q)
+    idx = torch.randint(0, P, (Q,), generator=g, dtype=torch.int32)
+    d = torch.randn(Q, 3, generator=g)
+    d = d / d.norm(dim=1, keepdim=True)
+    y = host(nirc.nirc_hash_infer(model, dp, nirc.Queries.from_dirs(d.cuda(), idx.cuda())))
+    ref = oracle.hash_infer(pts, idx.numpy(), d.double().numpy(), w, 64, GRIDS[grid])
+    e = rel_l2(y, ref)
+    print(f"  rel-L2 {e:.3e}", flush=True)
+    assert e <= 1e-2
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("P,N", [(17, 3), (4096, 8), (1000, 16), (100, 64), (4001, 5)])
+def test_hash_estimate(nirc, prec, P, N):
+    print(f"hash estimate {prec} P={P} N={N}", flush=True)
+    pts = wl.make_points(42, P)
+    lob = wl.make_lobes(42).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, w = _model(nirc, prec, GRIDS["default"], 42)
+    tl, c, r = (host(t) for t in nirc.nirc_hash_estimate(model, dp, lob, N, 9, 1, parts=True))
+    o_tl, o_c, o_r = oracle.hash_estimate(pts, lob, w, N, 9, 1)
+    print(f"  F_c rel-L2 {rel_l2(c, o_c):.3e}  F_tl {rel_l2(tl, o_tl):.3e}", flush=True)
+    assert rel_l2(c, o_c) <= 1e-2
+    assert rel_l2(tl, o_tl) <= 1e-2
+    assert np.linalg.norm(r - o_r) <= 1e-2 * np.linalg.norm(o_c)
+
+
+def test_hash_estimate_caller_residual(nirc):
+    P, N = 999, 16
+    pts = wl.make_points(43, P)
+    lob = wl.make_lobes(43).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, w = _model(nirc, "bf16", GRIDS["default"], 43)
+    rr = np.random.default_rng(43).random((P, 3)).astype(np.float32)
+    tl, c, r = (host(t) for t in nirc.nirc_hash_estimate(model, dp, None, N, 4, 2, parts=True,
+                                                         residual=torch.from_numpy(rr).cuda()))
+    o_tl, o_c, o_r = oracle.hash_estimate(pts, lob, w, N, 4, 2, rrad=rr.astype(np.float64))
+    assert rel_l2(c, o_c) <= 1e-2
+    assert np.linalg.norm(r - o_r) <= 1e-2 * np.linalg.norm(o_c)
+
+
+def test_hash_full_1080p_sampled_points(nirc):
+    # the full frame (1920 x 1080 points, N = 16, BF16) checked on sampled points, ragged tail
+    # included (the oracle samples their directions by frame index)
+    print("hash 1080p N=16 sampled", flush=True)
+    P, N = 1920 * 1080, 16
+    pts = wl.make_points(44, P)
+    lob = wl.make_lobes(44).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, w = _model(nirc, "bf16", GRIDS["default"], 44)
+    tl, c, r = (host(t) for t in nirc.nirc_hash_estimate(model, dp, lob, N, 3, 1, parts=True))
+    rng = np.random.default_rng(2)
+    sel = np.unique(np.concatenate([rng.choice(P, 2000, replace=False), np.arange(P - 23, P)]))
+    sub = pts.subset(sel)
+    dirs = oracle.sample_dirs(sub, N, 3, 1, ids=sel)
+    o_tl, o_c, o_r = oracle.hash_estimate(sub, lob, w, N, 3, 1, dirs=dirs)
+    assert rel_l2(c[sel], o_c) <= 1e-2
+    assert np.linalg.norm(tl[sel] - o_tl) <= 1e-2 * np.linalg.norm(o_c)
+    assert np.isfinite(tl).all()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("grid", ["default", "small"])
+@pytest.mark.parametrize("B,kind", [(1, 0), (1000, 0), (65536, 0), (4096, 1)])
+def test_hash_loss_grad(nirc, prec, grid, B, kind):
+    print(f"hash loss_grad {prec} {grid} B={B} kind={kind}", flush=True)
+    P = 3000
+    pts = wl.make_points(45, P)
+    lob = wl.make_lobes(45).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, w = _model(nirc, prec, GRIDS[grid], 45, max_batch=B, loss=kind)
+    sm = Samples(pts, lob, B, 46, 0, 0)
+    loss, grad = nirc.nirc_hash_loss_grad(model, dp, sm.queries(nirc), sm.target())
+    o_loss, o_grad = oracle.hash_loss_grad(pts, sm.idx, sm.d, sm.t, w.astype(np.float64), 64, GRIDS[grid], kind=kind)
+    g = host(grad)
+    nm = oracle.hash_mlp_params(64)
+    e_loss = abs(float(loss.item()) - o_loss) / abs(o_loss)
+    e_mlp = rel_l2(g[:nm], o_grad[:nm])
+    e_tab = rel_l2(g[nm:], o_grad[nm:])
+    print(f"  loss {e_loss:.3e}  mlp {e_mlp:.3e}  grid {e_tab:.3e}", flush=True)
+    assert e_loss <= GRAD_TOL[prec]
+    assert e_mlp <= GRAD_TOL[prec]
+    assert e_tab <= GRAD_TOL[prec]
+    # entries no sample touches stay exactly zero
+    assert np.all(g[nm:][o_grad[nm:] == 0.0] == 0.0)
+
+
+def test_hash_adam_step_matches_oracle(nirc):
+    # one Adam step from zero moments with the oracle's gradient given to both sides
+    P, B = 2000, 4096
+    pts = wl.make_points(47, P)
+    lob = wl.make_lobes(47).packed()
+    model, w = _model(nirc, "bf16", GRIDS["small"], 47, max_batch=B)
+    sm = Samples(pts, lob, B, 48, 0, 0)
+    _, g = oracle.hash_loss_grad(pts, sm.idx, sm.d, sm.t, w.astype(np.float64), 64, GRIDS["small"])
+    g32 = g.astype(np.float32)
+    nirc.nirc_hash_adam_step(model, torch.from_numpy(g32).cuda())
+    got = host(model.get_weights())
+    wo = w.astype(np.float64)
+    m = np.zeros_like(wo)
+    v = np.zeros_like(wo)
+    oracle.adam(wo, m, v, g32.astype(np.float64), 1)
+    np.testing.assert_allclose(got, wo, rtol=0, atol=2e-6)
+    assert model.read_flags() == 0
+
+
+def test_hash_nonfinite_gradient_skips_step(nirc):
+    model, w = _model(nirc, "bf16", GRIDS["small"], 49, max_batch=16)
+    g = np.zeros(model.n_params, np.float32)
+    g[-1] = np.nan
+    nirc.nirc_hash_adam_step(model, torch.from_numpy(g).cuda())
+    np.testing.assert_array_equal(host(model.get_weights()), w.astype(np.float64))
+    assert model.read_flags() & nirc.NIRC_FLAG_NONFINITE_GRAD
+
+
+def test_hash_training_reduces_cache_error(nirc):
+    # online training from the 1e-4 grid initialisation: the cache's relative L2 error on held-out
+    # samples falls well below its start within 30 frames of 4 steps
+    print("hash training", flush=True)
+    P, B = 65536, 16384
+    pts = wl.make_points(50, P)
+    lob = wl.make_lobes(50).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, _ = _model(nirc, "bf16", GRIDS["default"], 50, max_batch=B, scale=1e-4)
+    held = Samples(pts, lob, 8192, 51, 999, 0)
+    q = held.queries(nirc)
+
+    def err():
+        return rel_l2(host(nirc.nirc_hash_infer(model, dp, q)), held.t)
+
+    e0 = err()
+    for f in range(30):
+        for s in range(4):
+            qq, tgt = nirc.tlmc_train_batch(dp, lob, B, 52, f, s)
+            nirc.nirc_hash_train_step(model, dp, qq, tgt)
+    e1 = err()
+    print(f"  cache rel-L2 {e0:.3f} -> {e1:.3f}", flush=True)
+    assert model.read_flags() == 0
+    assert e1 < 0.35 * e0 and e1 < 0.3
+
+
+def test_hash_estimator_unbiased_over_seeds(nirc):
+    # E[F_tl] = F whatever the cache: mean over seeds against the closed-form integral
+    P, N, S = 64, 4, 400
+    pts = wl.make_points(53, P)
+    lob = wl.make_lobes(53).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, _ = _model(nirc, "bf16", GRIDS["default"], 53)
+    F = oracle.closed_form(pts, lob)
+    samples = np.stack([host(nirc.nirc_hash_estimate(model, dp, lob, N, 3000 + s, 0)) for s in range(S)])
+    z = (samples.mean(axis=0) - F) / (samples.std(axis=0, ddof=1) / math.sqrt(S))
+    assert np.abs(z).max() < 5.0
+
+
+def test_hash_rejects_unsupported_configurations(nirc):
+    w = wl.make_hash_weights(1, 64, 2 * oracle.hash_entries(GRIDS["small"]))
+    g = nirc.make_hash_grid(*GRIDS["small"])
+    for cfg in (nirc.make_config(precision=0), nirc.make_config(width=128, precision=1),
+                nirc.make_config(precision=1, loss=2), nirc.make_config(precision=1, output=1)):
+        with pytest.raises(nirc.NircError):
+            nirc.HashModel(w, cfg=cfg, grid=g, max_batch=0)
+    with pytest.raises(nirc.NircError):
+        nirc.HashModel(w, cfg=nirc.make_config(precision=1), grid=nirc.make_hash_grid(9, 16, 1.5), max_batch=0)

@@ -1,0 +1,67 @@
+"""Host builds of the hash-grid model's device code (no GPU): the spherical harmonics against the
+oracle, and the packed 16-bit weight layout's coverage of the canonical parameters."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def _build(tmp_path, name):
+    exe = str(tmp_path / name)
+    src = os.path.join(ROOT, "tests", "host", name + ".cpp")
+    cmd = [HIPCC, "-x", "hip", "--cuda-host-only", "-O2", "-std=c++17",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROOT, "paper_2412_04634_amd", "csrc"),
+           src, "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=300)
+    return exe
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+def test_device_sh_matches_oracle(tmp_path):
+    exe = _build(tmp_path, "sh25_check")
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=(5000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = np.concatenate([d, np.eye(3), -np.eye(3)]).astype(np.float32)
+    inp = "\n".join("%.9e %.9e %.9e" % tuple(r) for r in d) + "\n"
+    out = subprocess.run([exe], input=inp, check=True, capture_output=True, text=True, timeout=300).stdout
+    Y = np.array([[float(v) for v in l.split()] for l in out.strip().split("\n")])
+    ref = oracle.sh(d.astype(np.float64))
+    # FP32 polynomials on FP32 unit vectors: a few ulp of values below 1
+    assert np.abs(Y - ref).max() <= 2e-6
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+def test_hash_packed_layout_covers_parameters(tmp_path):
+    exe = _build(tmp_path, "hash_layout_check")
+    lines = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=300).stdout.split("\n")
+    total, secD, rest, secTS, secT0 = (int(v) for v in lines[0].split())
+    src = np.array([int(v) for v in lines[1:total + 1]])
+    W, nin = 64, 64
+    w1 = W * nin
+    # W1 surface + direction sections: every W1 entry exactly once (inputs 0..63)
+    s1 = src[:rest]
+    s1 = s1[s1 >= 0]
+    assert sorted(s1.tolist()) == list(range(w1))
+    # direction section holds the SH columns 24..48, surface section the others
+    d = src[secD:rest]
+    d = d[d >= 0]
+    assert set((d % nin).tolist()) == set(range(24, 49))
+    # hidden layers: W2..W4 twice (forward H and transposed T), W5 in O, OS (x4 copies) and OT
+    h = src[rest:secTS]
+    h = h[h >= 0]
+    counts = np.bincount(h, minlength=w1 + 3 * W * W + 3 * W)
+    assert (counts[:w1] == 0).all()
+    assert (counts[w1:w1 + 3 * W * W] == 2).all()
+    assert (counts[w1 + 3 * W * W:] >= 3).all()
+    # TS: the grid columns of W1 (inputs 0..23), each once
+    ts = src[secTS:]
+    ts = ts[ts >= 0]
+    assert sorted(ts.tolist()) == sorted(r * nin + c for r in range(W) for c in range(24))
+    assert secT0 > rest
