@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 PRECS = {"bf16": 1, "fp16": 2}
 GRAD_TOL = {"bf16": 10 * 2.0 ** -9, "fp16": 10 * 2.0 ** -12}
 GRIDS = {"default": (18, 16, 1.5), "small": (10, 4, 1.5)}
+GRID_TOL = 2e-2   # grid-entry gradients, see test_hash_loss_grad
 
 
 @pytest.fixture(scope="module")
@@ -138,7 +139,20 @@ def test_hash_loss_grad(nirc, prec, grid, B, kind):
           f"{rel_l2(g[nm:], o_grad[nm:]):.3e})", flush=True)
     assert e_loss <= GRAD_TOL[prec]
     assert e_mlp <= GRAD_TOL[prec]
-    assert e_tab <= GRAD_TOL[prec]
+    # entry by entry: even with the decisions taken in the kernel's precision, an activation that
+    # lands next to a 16-bit rounding midpoint rounds the other way from the FP64-summed oracle's
+    # in about one sample per thousand, and a unit of the next layer within that step of zero
+    # switches; such a sample's entries then differ by a large fraction (FP16 at B = 1000:
+    # 8e-3).  Hence 2e-2 entry by entry, and the per-level sums below at the rounding bound.
+    assert e_tab <= GRID_TOL
+    res, off, _ = oracle.hash_levels(GRIDS[grid])
+    ends = list(off[1:]) + [oracle.hash_entries(GRIDS[grid])]
+    for l in range(12):
+        a, b = 2 * off[l], 2 * ends[l]
+        tl_ = w64[nm + a:nm + b]
+        got_l = float(np.dot(tl_, g[nm + a:nm + b]))
+        ref_l = float(np.dot(tl_, p_grad[nm + a:nm + b]))
+        assert abs(got_l - ref_l) <= GRAD_TOL[prec] * float(np.abs(tl_ * p_grad[nm + a:nm + b]).sum()) + 1e-30, l
     # entries no sample touches stay exactly zero
     assert np.all(g[nm:][o_grad[nm:] == 0.0] == 0.0)
     # <table, grid gradient> = <W1 grid columns, their gradient> (both are sum_b sum_k e_bk de_bk)
