@@ -51,7 +51,6 @@ def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=12.0, ta
     proportional share of the training batch; reported as queries/s of the whole frame, on all
     the oracle's threads and on one."""
     import numpy as np
-    import oracle
 
     P = pts.count
     rng = np.random.default_rng(1234)
@@ -350,6 +349,78 @@ def loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S):
     return out
 
 
+def algorithmic_flops_hash(P: int, N: int, W: int = 64) -> float:
+    """Hash-grid model: 39 surface inputs (24 grid values + 15 surface values) projected once per
+    point, then per query the 25 SH inputs, three hidden layers and the output layer."""
+    return float(P) * (2 * 39 * W + (N + 1) * 2 * (25 * W + 3 * W * W + 3 * W))
+
+
+def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S, reps=20):
+    """The paper's own cache input (hash grid on x, spherical harmonics of w, one-blob surface
+    values) against the frequency input, both BF16, trained online from their initial weights
+    over the same rotating frames: time per estimate (N + 1 queries per point) and per training
+    frame, and on the last frame the MRSE of the two-level estimate and of the cache level alone
+    against the closed form, and the cache's relative L2 error on fresh samples."""
+    import torch
+    from paper_2412_04634_amd import workload as wl
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    grid = nirc.make_hash_grid()
+    wh = wl.make_hash_weights(seed, 64, 2 * nirc.nirc_hash_entries(grid))
+    models = {"frequency_bf16": nirc.Model(w0, cfg=nirc.make_config(precision=1), max_batch=B),
+              "hash_grid_bf16": nirc.HashModel(wh, cfg=nirc.make_config(precision=1), grid=grid, max_batch=B)}
+    out = {"grid": {"levels": 12, "features": 2, "log2_table": grid.log2_table, "base_res": grid.base_res,
+                    "growth": grid.growth, "entries": nirc.nirc_hash_entries(grid),
+                    "table_mb": 8 * nirc.nirc_hash_entries(grid) / 1e6}}
+    tl = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+    c = torch.empty_like(tl)
+    for name, m in models.items():
+        is_hash = isinstance(m, nirc.HashModel)
+        t_train = 0.0
+        for f in range(frames):
+            lob = nirc.lobes_struct(lobes_for(f))
+            ev[0].record(stream)
+            if is_hash:
+                for s_ in range(S):
+                    q, tgt = nirc.tlmc_train_batch(dp, lob, B, seed, f, s_)
+                    nirc.nirc_hash_train_step(m, dp, q, tgt)
+            else:
+                nirc.nirc_train_frame(m, dp, lob, B, S, seed, f)
+            ev[1].record(stream)
+            ev[1].synchronize()
+            t_train += ev[0].elapsed_time(ev[1])
+        lob = nirc.lobes_struct(lobes_for(frames))
+        est = (lambda: nirc.nirc_hash_estimate(m, dp, lob, N, seed, frames, out=tl)) if is_hash else \
+            (lambda: nirc.tlmc_estimate(m, dp, lob, N, seed, frames, out=tl))
+        for _ in range(3):
+            est()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            est()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        if is_hash:
+            nirc._check(nirc.lib().nirc_hash_estimate(m.handle, dp.c(), nirc.ctypes.byref(lob), N, seed, frames, None,
+                                                      nirc._ptr(tl), nirc._ptr(c), None, nirc._stream()), "estimate")
+        else:
+            nirc._check(nirc.lib().tlmc_estimate(m.handle, dp.c(), nirc.ctypes.byref(lob), N, seed, frames, None,
+                                                 nirc._ptr(tl), nirc._ptr(c), None, nirc._stream()), "estimate")
+        st = nirc.tlmc_frame_stats(dp, lob, table, tl, c, fs=fs)
+        q, tgt = nirc.tlmc_train_batch(dp, lob, 65536, seed + 7919, frames, 0)
+        y = nirc.nirc_hash_infer(m, dp, q) if is_hash else nirc.nirc_infer(m, dp, q)
+        flops = algorithmic_flops_hash(P, N) if is_hash else algorithmic_flops_estimate(P, N, 64)
+        out[name] = {"ms_estimate": ms, "queries_per_s": P * (N + 1) / (ms * 1e-3),
+                     "tflops": flops / (ms * 1e-3) / 1e12, "frac_bf16_peak": flops / (ms * 1e-3) / PEAK_BF16_MFMA,
+                     "flops_per_launch": flops, "ms_train_frame": t_train / frames,
+                     "mrse": float(st[4].item()), "mrse_cache_only": float(st[5].item()),
+                     "cache_rel_l2": float((y - tgt).norm() / tgt.norm()), "flags": m.read_flags()}
+    out["frames"] = frames
+    out["grid_gather_bytes_per_point"] = 12 * 8 * 8
+    return out
+
+
 def serving_run(seconds):
     """16 render streams (resolutions 360p..4K, N in {4, 8, 32}, width-64 BF16 caches with their
     own Adam state), Poisson arrivals at 240 frames/s, HBM-budget admission, continuous batching
@@ -410,7 +481,9 @@ def main():
     ap.add_argument("--workload", default="1080p_n16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true")
-    ap.add_argument("--estimate-only", choices=["fp32", "bf16", "fp16"], default=None,
+    ap.add_argument("--train-only", choices=["fp32", "bf16", "hash-bf16"], default=None,
+                    help="only time training frames (S steps of B samples) of this model")
+    ap.add_argument("--estimate-only", choices=["fp32", "bf16", "fp16", "hash-bf16"], default=None,
                     help="time only tlmc_estimate at this precision (for profiling runs)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="duration of the multi-stream serving run (0 to skip)")
@@ -420,6 +493,8 @@ def main():
                     help="visibility cache against a radiance cache on the occluded scene (100 frames each)")
     ap.add_argument("--loss-variants", action="store_true",
                     help="train a cache with each loss of the optimisation section (100 frames) and compare")
+    ap.add_argument("--hash-grid", action="store_true",
+                    help="also run the hash-grid / spherical-harmonics cache input against the frequency input")
     ap.add_argument("--train-convergence", action="store_true",
                     help="also run 300 frames of training only at batches 2^16, 2^18, 2^20")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -462,23 +537,61 @@ def main():
             lobes_frames[f] = base_lobes.rotated(f).packed()
         return lobes_frames[f]
 
+    if args.train_only:
+        if args.train_only == "hash-bf16":
+            grid = nirc.make_hash_grid()
+            m = nirc.HashModel(wl.make_hash_weights(seed, 64, 2 * nirc.nirc_hash_entries(grid)),
+                               cfg=nirc.make_config(precision=1), grid=grid, max_batch=B)
+
+            def train(f):
+                lob = nirc.lobes_struct(lobes_for(f))
+                for s_ in range(S):
+                    q, tgt = nirc.tlmc_train_batch(dp, lob, B, seed, f, s_)
+                    nirc.nirc_hash_train_step(m, dp, q, tgt)
+        else:
+            m = nirc.Model(w0, cfg=nirc.make_config(precision={"fp32": 0, "bf16": 1}[args.train_only]), max_batch=B)
+
+            def train(f):
+                nirc.nirc_train_frame(m, dp, nirc.lobes_struct(lobes_for(f)), B, S, seed, f)
+        for f in range(args.warmup):
+            train(f)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(torch.cuda.current_stream())
+        for f in range(args.steps):
+            train(args.warmup + f)
+        ev[1].record(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        print(json.dumps({"train_only": args.train_only, "ms_train_frame": ev[0].elapsed_time(ev[1]) / args.steps,
+                          "flags": m.read_flags()}), flush=True)
+        return
+
     if args.estimate_only:
-        prec = {"fp32": 0, "bf16": 1, "fp16": 2}[args.estimate_only]
-        m = nirc.Model(w0, cfg=nirc.make_config(precision=prec), max_batch=0)
         lob = nirc.lobes_struct(lobes_for(0))
         out = torch.empty((P, 3), dtype=torch.float32, device=dev)
+        if args.estimate_only == "hash-bf16":
+            grid = nirc.make_hash_grid()
+            m = nirc.HashModel(wl.make_hash_weights(seed, 64, 2 * nirc.nirc_hash_entries(grid)),
+                               cfg=nirc.make_config(precision=1), grid=grid, max_batch=0)
+            est = lambda: nirc.nirc_hash_estimate(m, dp, lob, N, seed, 0, out=out)
+            flops = algorithmic_flops_hash(P, N)
+        else:
+            prec = {"fp32": 0, "bf16": 1, "fp16": 2}[args.estimate_only]
+            m = nirc.Model(w0, cfg=nirc.make_config(precision=prec), max_batch=0)
+            est = lambda: nirc.tlmc_estimate(m, dp, lob, N, seed, 0, out=out)
+            flops = algorithmic_flops_estimate(P, N, W)
         for _ in range(args.warmup):
-            nirc.tlmc_estimate(m, dp, lob, N, seed, 0, out=out)
+            est()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         ev[0].record(torch.cuda.current_stream())
         for _ in range(args.steps):
-            nirc.tlmc_estimate(m, dp, lob, N, seed, 0, out=out)
+            est()
         ev[1].record(torch.cuda.current_stream())
         torch.cuda.synchronize()
         t = ev[0].elapsed_time(ev[1]) * 1e-3 / args.steps
         print(json.dumps({"estimate_only": args.estimate_only, "ms_estimate": t * 1e3,
-                          "tflops": algorithmic_flops_estimate(P, N, W) / t / 1e12}), flush=True)
+                          "tflops": flops / t / 1e12}), flush=True)
         return
 
     table = nirc.tlmc_reference_table(lobes_for(0))
@@ -584,6 +697,8 @@ def main():
                                                   table, fs, P, seed, args.warmup + args.steps)
     if args.visibility:
         result["visibility"] = visibility_compare(nirc, w0, dp, lobes_for, P, N, seed, 100, B, S)
+    if args.hash_grid:
+        result["hash_grid"] = hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
     if args.loss_variants:
         result["loss_variants"] = loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
     if args.train_convergence:
