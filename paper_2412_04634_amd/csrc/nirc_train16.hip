@@ -621,8 +621,9 @@ hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Quer
 // inputs.  In addition, after the first layer's delta, each sample's gradient with respect to
 // its 24 grid values (W1_grid^T delta1, from the TS section) is scattered into the grid-entry
 // gradient: each of the 8 corners of the sample's cell at a level receives its trilinear weight
-// times the level's two values, by FP32 atomic adds.
+// times the level's two values, by FP32 atomic adds (zero values are skipped).
 namespace {
+constexpr int kScatRow = 28;   // per sample: 24 grid-value gradients, position, pad
 struct HashGrad16Lds {
     static constexpr int kH = 4 * 64 * kRow16;
     static constexpr int kD = 4 * 64 * kRow16;
@@ -644,6 +645,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_hash_grad_h16(Points pts, Que
     __shared__ u32x4 smem4[(S::kTotal + 7) / 8];
     __shared__ float sLoss[kWaves16];
     __shared__ HashLevel s_lv[kHashLevels];
+    __shared__ float sScat[kWaves16 * 16 * kScatRow];
     uint16_t *smem = (uint16_t *)smem4;
     uint16_t *sH = smem;
     uint16_t *sD = sH + S::kH;
@@ -799,27 +801,40 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_hash_grad_h16(Points pts, Que
                     de[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), db1[kb],
                                           de[mt]);
             }
-            // straight-line scatter (no lane-dependent branches): padding rows 24..31 (lane groups
-            // 2, 3 of the second tile) and the padded samples of the last round add zeros
-            const float keep = valid ? 1.0f : 0.0f;
+            // scatter.  The L2 performs float atomics per cache line and instruction, so the 16
+            // values of one (sample, level) - 8 corners x 2 features - go to 16 consecutive lanes,
+            // corners along x (neighbouring entries: dense rows, and the hash's x multiplier is 1)
+            // in consecutive lane pairs; one instruction covers 4 (sample, level) pairs.  The
+            // wave's gradients and positions are staged in LDS first.
+            float *sg = sScat + wave * (16 * kScatRow);
 #pragma unroll
             for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-                for (int hl = 0; hl < 2; ++hl) {
-                    const int lraw = 8 * mt + 2 * g + hl;
-                    const int level = min(lraw, kHashLevels - 1);
-                    const float k = lraw < kHashLevels ? keep : 0.0f;
-                    const float d0 = k * de[mt][2 * hl], d1 = k * de[mt][2 * hl + 1];
-                    const HashLevel lv = s_lv[level];
-                    const HashCell cell = hash_cell(xs[0], xs[1], xs[2], lv.res);
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        float w;
-                        const uint32_t e = hash_entry(lv, grid.tmask, cell, c, w);
-                        unsafeAtomicAdd(gtab + 2 * (size_t)e, w * d0);
-                        unsafeAtomicAdd(gtab + 2 * (size_t)e + 1, w * d1);
-                    }
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * mt + 4 * g + i;
+                    if (k < 24) sg[col * kScatRow + k] = valid ? de[mt][i] : 0.0f;
                 }
+            if (g == 0) {
+                sg[col * kScatRow + 24] = xs[0];
+                sg[col * kScatRow + 25] = xs[1];
+                sg[col * kScatRow + 26] = xs[2];
+            }
+            wave_sync();
+            {
+                const int q = lane >> 4, corner = (lane & 15) >> 1, f = lane & 1;
+#pragma unroll 4
+                for (int it = 0; it < 16 * kHashLevels / 4; ++it) {
+                    const int pr = 4 * it + q;
+                    const int smp = pr / kHashLevels, level = pr - kHashLevels * smp;
+                    const float *row = sg + smp * kScatRow;
+                    const float d = row[2 * level + f];
+                    const HashLevel lv = s_lv[level];
+                    const HashCell cell = hash_cell(row[24], row[25], row[26], lv.res);
+                    float w;
+                    const uint32_t e = hash_entry(lv, grid.tmask, cell, corner, w);
+                    if (d != 0.0f) unsafeAtomicAdd(gtab + 2 * (size_t)e + f, w * d);
+                }
+            }
         }
         __syncthreads();
         // phase 2: owned weight-gradient tiles (W1: inputs 16 wave .. 16 wave + 15)
