@@ -200,30 +200,61 @@ __device__ __forceinline__ uint32_t hash_entry(const HashLevel &lv, uint32_t tma
     return lv.off + (lv.dense ? dense : hashed);
 }
 
-// Lane group g's six grid values (levels 3g, 3g + 1, 3g + 2) at x; all 24 loads are issued
-// before they are blended.
-__device__ __forceinline__ void hash_values6(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
-                                             float x1, float x2, int g, float (&v)[6]) {
-    float2 t[3][8];
-    float w[3][8];
+// The 24 corner features lane group g needs at x (levels 3g..3g+2, 8 corners each): loads only,
+// so that they can be issued one point group ahead of their use.
+__device__ __forceinline__ void hash_fetch24(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
+                                             float x1, float x2, int g, float2 (&t)[24]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const HashLevel lv = slv[3 * g + k];
         const HashCell h = hash_cell(x0, x1, x2, lv.res);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) t[k][c] = table[hash_entry(lv, tmask, h, c, w[k][c])];
+        for (int c = 0; c < 8; ++c) {
+            float w;
+            t[8 * k + c] = table[hash_entry(lv, tmask, h, c, w)];
+        }
     }
+}
+
+// Trilinear blend of fetched corner features into lane group g's six grid values.
+__device__ __forceinline__ void hash_blend6(const HashLevel *slv, float x0, float x1, float x2, int g,
+                                            const float2 (&t)[24], float (&v)[6]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
+        const HashLevel lv = slv[3 * g + k];
+        const HashCell h = hash_cell(x0, x1, x2, lv.res);
         float a = 0.0f, b = 0.0f;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            a += w[k][c] * t[k][c].x;
-            b += w[k][c] * t[k][c].y;
+            const float w = ((c & 1) ? h.f[0] : 1.0f - h.f[0]) * (((c >> 1) & 1) ? h.f[1] : 1.0f - h.f[1]) *
+                            (((c >> 2) & 1) ? h.f[2] : 1.0f - h.f[2]);
+            a += w * t[8 * k + c].x;
+            b += w * t[8 * k + c].y;
         }
         v[2 * k] = a;
         v[2 * k + 1] = b;
     }
+}
+
+// Lane group g's six grid values at x (all 24 loads issued before they are blended).
+__device__ __forceinline__ void hash_values6(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
+                                             float x1, float x2, int g, float (&v)[6]) {
+    float2 t[24];
+    hash_fetch24(slv, tmask, table, x0, x1, x2, g, t);
+    hash_blend6(slv, x0, x1, x2, g, t, v);
+}
+
+// Surface operands from grid values already blended (v) and the point's inputs.
+template <int PREC>
+__device__ __forceinline__ void hash_pack_surface(const float xs[7], int g, const float (&v)[6], u32x4 &b0,
+                                                  u32x4 &b1, float (&ph)[15]) {
+    phi_values(xs, ph);
+    const float p0 = g == 0 ? ph[0] : g == 1 ? ph[2] : g == 2 ? ph[4] : ph[6];
+    const float p1 = g == 0 ? ph[1] : g == 1 ? ph[3] : g == 2 ? ph[5] : ph[7];
+    b0 = u32x4{pack2<PREC>(v[0], v[1]), pack2<PREC>(v[2], v[3]), pack2<PREC>(v[4], v[5]), pack2<PREC>(p0, p1)};
+    b1 = g == 0 ? u32x4{pack2<PREC>(ph[8], ph[9]), pack2<PREC>(ph[10], ph[11]), pack2<PREC>(ph[12], ph[13]),
+                        pack2<PREC>(ph[14], 0.0f)}
+                : u32x4{0u, 0u, 0u, 0u};
 }
 
 // The two surface K-blocks of lane group g for a point (grid values and phi).
@@ -232,13 +263,7 @@ __device__ __forceinline__ void hash_surface_operands(const HashLevel *slv, uint
                                                       const float xs[7], int g, u32x4 &b0, u32x4 &b1,
                                                       float (&v)[6], float (&ph)[15]) {
     hash_values6(slv, tmask, table, xs[0], xs[1], xs[2], g, v);
-    phi_values(xs, ph);
-    const float p0 = g == 0 ? ph[0] : g == 1 ? ph[2] : g == 2 ? ph[4] : ph[6];
-    const float p1 = g == 0 ? ph[1] : g == 1 ? ph[3] : g == 2 ? ph[5] : ph[7];
-    b0 = u32x4{pack2<PREC>(v[0], v[1]), pack2<PREC>(v[2], v[3]), pack2<PREC>(v[4], v[5]), pack2<PREC>(p0, p1)};
-    b1 = g == 0 ? u32x4{pack2<PREC>(ph[8], ph[9]), pack2<PREC>(ph[10], ph[11]), pack2<PREC>(ph[12], ph[13]),
-                        pack2<PREC>(ph[14], 0.0f)}
-                : u32x4{0u, 0u, 0u, 0u};
+    hash_pack_surface<PREC>(xs, g, v, b0, b1, ph);
 }
 
 // h += W1_s e_s for one tile of 16 columns (the surface section read from global memory).

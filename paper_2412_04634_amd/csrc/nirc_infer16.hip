@@ -279,7 +279,8 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
                                                const GroupSlab &gs, int lane, int g, int col,
                                                const HashLevel *slv = nullptr, uint32_t tmask = 0u,
-                                               const float2 *table = nullptr) {
+                                               const float2 *table = nullptr, const float2 *fetched = nullptr,
+                                               float2 (*prefetch)[24] = nullptr, int64_t prefetch_pc = 0) {
     constexpr int MT = W / 16;
     const int64_t P = pts.count;
     const int n_tiles = n_cache + 1;
@@ -293,7 +294,9 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
             static_assert(W == 64, "the hash-grid model has width 64");
             u32x4 b0, b1;
             float v[6], ph[15];
-            hash_surface_operands<PREC>(slv, tmask, table, xs, g, b0, b1, v, ph);
+            // corner features fetched one group ahead by the caller
+            hash_blend6(slv, xs[0], xs[1], xs[2], g, *(const float2(*)[24])fetched, v);
+            hash_pack_surface<PREC>(xs, g, v, b0, b1, ph);
             hash_layer1_surface<PREC>(hsum, opaque(gS), b0, b1, lane);
         } else {
             layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
@@ -311,6 +314,13 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         const bool fold = n_tiles - tb == 9;   // last 8 cache tiles + the residual tile
         gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db, fold);
         const int tend = fold ? n_tiles : min(tb + 8, n_tiles);
+        if constexpr (ENC == 1) {
+            // the next group's grid corners, fetched behind this group's last tiles (after the
+            // last direction batch, whose point loads would otherwise wait for them)
+            if (tend == n_tiles && prefetch)
+                hash_fetch24(slv, tmask, table, pts.px[prefetch_pc], pts.py[prefetch_pc], pts.pz[prefetch_pc], g,
+                             *prefetch);
+        }
         int t = tb;
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
@@ -643,10 +653,25 @@ __global__ __launch_bounds__(WAVES * 64) void k_hash_tlmc_h16(Points pts, nirc_l
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, 64);
     const int64_t n_groups = (pts.count + 15) >> 4;
-    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
+    const int64_t stride = (int64_t)gridDim.x * WAVES;
+    // software pipeline over point groups: a group's grid corners are loaded while the previous
+    // group's last queries run through the MLP (the next index is clamped to the last point, so
+    // the final group's fetch stays in bounds and is simply unused)
+    float2 nxt[24];
+    int64_t grp = (int64_t)blockIdx.x * WAVES + __builtin_amdgcn_readfirstlane(wave);
+    {
+        const int64_t pc = min((grp << 4) + col, pts.count - 1);
+        hash_fetch24(s_lv, grid.tmask, table, pts.px[pc], pts.py[pc], pts.pz[pc], g, nxt);
+    }
+    for (; grp < n_groups; grp += stride) {
+        float2 cur[24];
+#pragma unroll
+        for (int i = 0; i < 24; ++i) cur[i] = nxt[i];
+        const int64_t npc = min(((grp + stride) << 4) + col, pts.count - 1);
         tlmc_group_h16<64, PREC, 4, false, 1>(pts, grp << 4, n_cache, dn, key0, key1, frame, NIRC_OUTPUT_RADIANCE, rrad,
                                               out_tl, out_c, out_r, s_lobes, gS, sD, sH, sOS, gs, lane, g, col, s_lv,
-                                              grid.tmask, table);
+                                              grid.tmask, table, cur, &nxt, npc);
+    }
 }
 
 hipError_t launch_hash_pack16(uint16_t *packed, const float *master, int prec, hipStream_t s, int64_t *step,
