@@ -420,6 +420,11 @@ nirc_status nirc_hash_destroy(nirc_hash_model *model);
 nirc_status nirc_hash_set_weights(nirc_hash_model *model, const float *w, void *stream);
 nirc_status nirc_hash_get_weights(const nirc_hash_model *model, float *w, void *stream);
 
+/* Checkpoint / resume: the whole training state (parameters, Adam moments and step, flags) as
+ * one blob of exactly nirc_hash_state_bytes bytes (device memory, 4-byte aligned). */
+nirc_status nirc_hash_get_state(const nirc_hash_model *model, void *blob, size_t blob_bytes, void *stream);
+nirc_status nirc_hash_set_state(nirc_hash_model *model, const void *blob, size_t blob_bytes, void *stream);
+
 /* Cache predictions for explicit queries: rgb [queries.count][3]. */
 nirc_status nirc_hash_infer(const nirc_hash_model *model, nirc_points points, nirc_queries queries, float *rgb,
                             void *stream);

@@ -184,6 +184,25 @@ nirc_status nirc_hash_get_weights(const nirc_hash_model *model, float *w, void *
     return hip_st(launch_copy_f32(w, model->master, model->np, (hipStream_t)stream));
 }
 
+// The state is one region from the FP32 parameters on (HashState); a blob is its image.
+nirc_status nirc_hash_get_state(const nirc_hash_model *model, void *blob, size_t blob_bytes, void *stream) {
+    if (!model || !blob || ((uintptr_t)blob % 4) != 0) return NIRC_ERR_INVALID_ARG;
+    const size_t bytes = HashState(model->np).total;
+    if (blob_bytes != bytes) return NIRC_ERR_INVALID_ARG;
+    return hip_st(launch_copy_f32((float *)blob, model->master, (int64_t)(bytes / 4), (hipStream_t)stream));
+}
+
+nirc_status nirc_hash_set_state(nirc_hash_model *model, const void *blob, size_t blob_bytes, void *stream) {
+    if (!model || !blob || ((uintptr_t)blob % 4) != 0) return NIRC_ERR_INVALID_ARG;
+    const size_t bytes = HashState(model->np).total;
+    if (blob_bytes != bytes) return NIRC_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_copy_f32(model->master, (const float *)blob, (int64_t)(bytes / 4), s);
+    // the packed layers follow the restored FP32 parameters whatever precision wrote the blob
+    if (e == hipSuccess) e = launch_hash_pack16(model->packed16, model->master, model->cfg.precision, s);
+    return hip_st(e);
+}
+
 nirc_status nirc_hash_infer(const nirc_hash_model *model, nirc_points points, nirc_queries queries, float *rgb,
                             void *stream) {
     if (!model) return NIRC_ERR_INVALID_ARG;

@@ -120,6 +120,8 @@ def lib():
             "nirc_hash_destroy": (_i32, [_vp]),
             "nirc_hash_set_weights": (_i32, [_vp, _vp, _vp]),
             "nirc_hash_get_weights": (_i32, [_vp, _vp, _vp]),
+            "nirc_hash_get_state": (_i32, [_vp, _vp, _sz, _vp]),
+            "nirc_hash_set_state": (_i32, [_vp, _vp, _sz, _vp]),
             "nirc_hash_infer": (_i32, [_vp, _Points, _Queries, _vp, _vp]),
             "nirc_hash_estimate": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _vp, _vp, _vp,
                                           _vp, _vp]),
@@ -583,6 +585,18 @@ class HashModel:
         out = torch.empty(self.n_params, dtype=torch.float32, device=self.state.device)
         _check(lib().nirc_hash_get_weights(self.handle, _ptr(out), _stream()), "nirc_hash_get_weights")
         return out
+
+    def get_state(self) -> torch.Tensor:
+        """The whole training state as a device byte tensor (checkpoint)."""
+        out = torch.empty(self.state.numel(), dtype=torch.uint8, device=self.state.device)
+        _check(lib().nirc_hash_get_state(self.handle, _ptr(out), out.numel(), _stream()), "nirc_hash_get_state")
+        return out
+
+    def set_state(self, blob: torch.Tensor):
+        """Restore a state written by get_state of a model with the same grid (resume)."""
+        b = blob.to(self.state.device).contiguous()
+        _check(lib().nirc_hash_set_state(self.handle, _ptr(b), b.numel(), _stream()), "nirc_hash_set_state")
+        torch.cuda.current_stream().synchronize()   # b may be a temporary
 
     def read_flags(self) -> int:
         return int(lib().nirc_hash_read_flags(self.handle, _stream()))

@@ -238,3 +238,59 @@ def test_hash_rejects_unsupported_configurations(nirc):
             nirc.HashModel(w, cfg=cfg, grid=g, max_batch=0)
     with pytest.raises(nirc.NircError):
         nirc.HashModel(w, cfg=nirc.make_config(precision=1), grid=nirc.make_hash_grid(9, 16, 1.5), max_batch=0)
+
+
+@pytest.mark.parametrize("P,N", [(3, 1), (5, 4096), (33, 2), (16, 9)])
+def test_hash_estimate_edge_counts(nirc, P, N):
+    # smallest and largest direction counts, a group smaller than a tile, N not dividing 16
+    print(f"hash edge P={P} N={N}", flush=True)
+    pts = wl.make_points(54, P)
+    lob = wl.make_lobes(54).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, w = _model(nirc, "bf16", GRIDS["small"], 54)
+    tl, c, r = (host(t) for t in nirc.nirc_hash_estimate(model, dp, lob, N, 2, 0, parts=True))
+    o_tl, o_c, o_r = oracle.hash_estimate(pts, lob, w, N, 2, 0, grid=GRIDS["small"])
+    assert rel_l2(c, o_c) <= 1e-2
+    assert np.linalg.norm(r - o_r) <= 1e-2 * np.linalg.norm(o_c)
+
+
+def test_hash_empty_inputs(nirc):
+    model, _ = _model(nirc, "bf16", GRIDS["small"], 55)
+    empty = nirc.Points.from_workload(wl.make_points(55, 0))
+    lob = wl.make_lobes(55).packed()
+    assert nirc.nirc_hash_estimate(model, empty, lob, 8, 0, 0).shape == (0, 3)
+    q = nirc.Queries.from_dirs(torch.zeros((0, 3), device="cuda"))
+    assert nirc.nirc_hash_infer(model, empty, q).shape == (0, 3)
+    torch.cuda.synchronize()
+
+
+def test_hash_checkpoint_resume(nirc):
+    # a restored checkpoint is the saved state bit for bit (and answers identically); training on
+    # from it follows the original's updates (the grid gradient's atomic sums make the two runs
+    # agree to rounding, not bit for bit)
+    P, B = 4096, 4096
+    pts = wl.make_points(56, P)
+    lob = wl.make_lobes(56).packed()
+    dp = nirc.Points.from_workload(pts)
+    a, _ = _model(nirc, "bf16", GRIDS["small"], 56, max_batch=B, scale=1e-4)
+    b, _ = _model(nirc, "bf16", GRIDS["small"], 57, max_batch=B, scale=1e-4)
+
+    def frames(m, f0):
+        for f in range(f0, f0 + 2):
+            for s_ in range(2):
+                q, tgt = nirc.tlmc_train_batch(dp, lob, B, 58, f, s_)
+                nirc.nirc_hash_train_step(m, dp, q, tgt)
+
+    frames(a, 0)
+    blob = a.get_state()
+    wc = host(a.get_weights())
+    q = nirc.Queries.from_dirs(torch.nn.functional.normalize(torch.randn(100, 3, device="cuda"), dim=1))
+    ya = host(nirc.nirc_hash_infer(a, dp, q))
+    b.set_state(blob)
+    np.testing.assert_array_equal(host(b.get_state()), host(blob))
+    np.testing.assert_array_equal(host(nirc.nirc_hash_infer(b, dp, q)), ya)
+    frames(a, 2)
+    frames(b, 2)
+    wa, wb = host(a.get_weights()), host(b.get_weights())
+    assert rel_l2(wb - wc, wa - wc) <= 2e-2
+    assert a.read_flags() == 0 and b.read_flags() == 0
