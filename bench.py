@@ -360,7 +360,8 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
     values) against the frequency input, both BF16, trained online from their initial weights
     over the same rotating frames: time per estimate (N + 1 queries per point) and per training
     frame, and on the last frame the MRSE of the two-level estimate and of the cache level alone
-    against the closed form, and the cache's relative L2 error on fresh samples."""
+    against the closed form, and the cache's relative L2 error on fresh samples (also before
+    frames 0, 5, 10, 25 and 50, as a convergence curve)."""
     import torch
     from paper_2412_04634_amd import workload as wl
     stream = torch.cuda.current_stream()
@@ -374,10 +375,21 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
                     "table_mb": 8 * nirc.nirc_hash_entries(grid) / 1e6}}
     tl = torch.empty((P, 3), dtype=torch.float32, device="cuda")
     c = torch.empty_like(tl)
+    checkpoints = [0, 5, 10, 25, 50, frames]
     for name, m in models.items():
         is_hash = isinstance(m, nirc.HashModel)
         t_train = 0.0
+        curve = []
+
+        def probe(f):
+            lob_p = nirc.lobes_struct(lobes_for(f))
+            qp, tp = nirc.tlmc_train_batch(dp, lob_p, 65536, seed + 7919, f, 0)
+            yp = nirc.nirc_hash_infer(m, dp, qp) if is_hash else nirc.nirc_infer(m, dp, qp)
+            curve.append([f, float((yp - tp).norm() / tp.norm())])
+
         for f in range(frames):
+            if f in checkpoints:
+                probe(f)
             lob = nirc.lobes_struct(lobes_for(f))
             ev[0].record(stream)
             if is_hash:
@@ -415,7 +427,8 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
                      "tflops": flops / (ms * 1e-3) / 1e12, "frac_bf16_peak": flops / (ms * 1e-3) / PEAK_BF16_MFMA,
                      "flops_per_launch": flops, "ms_train_frame": t_train / frames,
                      "mrse": float(st[4].item()), "mrse_cache_only": float(st[5].item()),
-                     "cache_rel_l2": float((y - tgt).norm() / tgt.norm()), "flags": m.read_flags()}
+                     "cache_rel_l2": float((y - tgt).norm() / tgt.norm()), "flags": m.read_flags(),
+                     "cache_rel_l2_by_frame": curve}
     out["frames"] = frames
     out["grid_gather_bytes_per_point"] = 12 * 8 * 8
     return out
