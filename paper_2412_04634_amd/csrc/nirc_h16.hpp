@@ -317,6 +317,64 @@ __device__ __forceinline__ void mlp16_wide(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T]
         for (int t4 = 0; t4 < T; ++t4) aout[kb * 4 + t4] = *(const u32x4 *)(sOS + ((t4 * KB + kb) * 64 + lane) * 8);
 }
 
+// The chain for widths above 64 with the hidden layers' fragments in LDS (sH), the direction
+// layer's fragments (dfrag, [kb][mt]) loaded from global memory by the caller before it builds
+// the pass's direction operands, and the output copies in global memory: every hidden K-block's
+// fragments are loaded one K-block ahead
+// (double buffer) so that LDS latency sits under the previous K-block's MFMAs, and the output
+// copies are requested when the last hidden layer starts.
+template <int W, int PREC, int T>
+__device__ __forceinline__ void mlp16_hl(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 32], const u32x4 (&bd)[T][2],
+                                         const u32x4 (&dfrag)[W / 8], const uint16_t *sH, const uint16_t *gOS,
+                                         int lane, u32x4 (&aout)[4 * (W / 32)]) {
+    constexpr int MT = W / 16, KB = W / 32, SEC = MT * KB * 512, NI = 3 * KB;
+    u32x4 a[2][MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) a[0][mt] = *(const u32x4 *)(sH + ((mt * KB) * 64 + lane) * 8);
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(dfrag[kb * MT + mt], bd[tt][kb], h[tt][mt]);
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) hb[tt][kb] = chain_operand<PREC>(h[tt][2 * kb], h[tt][2 * kb + 1]);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int kb = i % KB;
+        if (kb == 0) {
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (i == NI - KB) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+#pragma unroll
+                for (int t4 = 0; t4 < T; ++t4) aout[k * 4 + t4] = *(const u32x4 *)(gOS + ((t4 * KB + k) * 64 + lane) * 8);
+        }
+        if (i + 1 < NI) {
+            const int l1 = (i + 1) / KB, kb1 = (i + 1) % KB;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                a[(i + 1) & 1][mt] = *(const u32x4 *)(sH + l1 * SEC + ((mt * KB + kb1) * 64 + lane) * 8);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(a[i & 1][mt], hb[tt][kb], h[tt][mt]);
+        if (kb == KB - 1) {
+#pragma unroll
+            for (int tt = 0; tt < T; ++tt)
+#pragma unroll
+                for (int k = 0; k < KB; ++k) hb[tt][k] = chain_operand<PREC>(h[tt][2 * k], h[tt][2 * k + 1]);
+        }
+    }
+}
+
 // Output layer for T <= 4 tiles into ONE accumulator: the chained activations hb[tt] (B layout:
 // lane l holds neuron positions 8g + j of query l%16) are exactly an A operand of the transposed
 // product Y = H W5^T (A[query l%16][k 8g + j]), and shifted copy tt of W5^T sends tile tt to

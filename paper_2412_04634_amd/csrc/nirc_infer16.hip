@@ -91,9 +91,12 @@ struct GroupSlab {
     uint2 *fb;     // [4 tiles][4 lane groups][16 queries] direction features, second K-block
 };
 
+// Direction features of a 4-tile pass are staged in the slab at width 64 only; wider models
+// compute each tile's direction operands in the lanes that use them (and give the room to their
+// hidden-layer weights).
 template <int W>
 struct Tlmc16Lds {
-    static constexpr int kSlab = TlmcLds<W>::kSlab + 4 * 64 * 4 + 4 * 64 * 2;   // floats per wave
+    static constexpr int kSlab = TlmcLds<W>::kSlab + (lds_weights(W) ? 4 * 64 * 4 + 4 * 64 * 2 : 0);   // floats
 };
 
 // T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
@@ -103,7 +106,9 @@ struct Tlmc16Lds {
 // OCC: the occluded-scene variants (visibility cache, radiance cache of the occluded scene),
 // selected at run time by `mode`; the radiance cache of the plain scene compiles without them.
 // ENC 1: the hash-grid model's direction input (25 spherical harmonics, one K-block).
-template <int W, int PREC, int T, bool OCC, int ENC = 0>
+// HL: the hidden layers' fragments are in LDS (sH) while the direction and output sections stay
+// in global memory (widths above 64).
+template <int W, int PREC, int T, bool OCC, int ENC = 0, bool HL = false>
 __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN dn, const GroupSlab &gs,
                                                const uint16_t *sD, const uint16_t *sH, const uint16_t *sOS,
                                                const u32x4 (&dfrag)[W / 8], int lane, int g, int col, float &rdx,
@@ -112,7 +117,11 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
     constexpr int MT = W / 16, KB = W / 32;
     f32x4 h[T][MT];
     u32x4 bd[T][2];
-    if constexpr (T == 4) {
+    // hidden layers in LDS: the direction layer's fragments come from global memory, requested
+    // before the pass's direction operands are built so that their latency sits under that work
+    u32x4 dl2[HL ? W / 8 : 1];
+    if constexpr (HL) load_dir_fragments<W, 2>(dl2, opaque(sD), lane);
+    if constexpr (T == 4 && lds_weights(W)) {
         // a full pass: lane 16 tt + c encodes query c of tile tt once (all frequencies, by angle
         // doubling) into LDS, where every lane group picks up its part of the B operands
         const int q = 16 * s0 + lane;
@@ -137,7 +146,7 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
         const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(gs.hs + j * W + 16 * mt + 4 * g);
-        if constexpr (T == 4) {
+        if constexpr (T == 4 && lds_weights(W)) {
             const int e = (tt * 4 + g) * 16 + col;
             bd[tt][0] = gs.fa[e];
             if constexpr (ENC == 1) {
@@ -159,7 +168,10 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
     if constexpr (lds_weights(W)) {
         mlp16<W, PREC, T, ENC == 1 ? 1 : 2>(h, hb, bd, dfrag, sH, sOS, lane, aout);
     } else {   // weights in global memory: keep their loads inside the pass
-        mlp16_wide<W, PREC, T>(h, hb, bd, opaque(sD), opaque(sH), opaque(sOS), lane, aout);
+        if constexpr (HL)
+            mlp16_hl<W, PREC, T>(h, hb, bd, dl2, sH, opaque(sOS), lane, aout);
+        else
+            mlp16_wide<W, PREC, T>(h, hb, bd, opaque(sD), opaque(sH), opaque(sOS), lane, aout);
     }
     const f32x4 z = output16_packed<W, PREC, T>(hb, aout);
 
@@ -271,7 +283,7 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
 // surface columns are read from global memory (gS).
 // ENC 1: the hash-grid model (surface part from the grid `slv`/`table` and phi, direction part
 // from spherical harmonics).
-template <int W, int PREC, int TP, bool OCC, int ENC = 0>
+template <int W, int PREC, int TP, bool OCC, int ENC = 0, bool HL = false>
 __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
                                                uint32_t key1, uint32_t frame, int mode, const float *rrad,
                                                float *out_tl,
@@ -324,11 +336,11 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         int t = tb;
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_h16<W, PREC, TP, OCC, ENC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy,
+            tlmc_tiles_h16<W, PREC, TP, OCC, ENC, HL>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy,
                                                  rdz, pts, p0, mode, lobes);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_h16<W, PREC, 1, OCC, ENC>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy,
+            tlmc_tiles_h16<W, PREC, 1, OCC, ENC, HL>(t, t - tb, n_cache, dn, gs, sD, sH, sOS, dfrag, lane, g, col, rdx, rdy,
                                                 rdz, pts, p0, mode, lobes);
         tb = tend;
     }
@@ -385,30 +397,32 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_h16(Points pts, nirc_lobes 
                                                          float *__restrict__ out_r) {
     constexpr H16Layout L{W};
     constexpr bool kLds = lds_weights(W);
-    constexpr int NW = kLds ? Infer16Lds<W>::kWeights : 8;   // 16-bit elements
     constexpr int SLAB = Tlmc16Lds<W>::kSlab;                   // floats per wave
+    // wider models: the hidden layers alone go to LDS when they fit beside the slabs
+    constexpr int kHid = 3 * L.size(SEC_H0);                    // 16-bit elements
+    constexpr bool kHidLds = !kLds && kHid * 2 + WAVES * SLAB * 4 + 1024 <= 160 * 1024;
+    constexpr int NW = kLds ? Infer16Lds<W>::kWeights : kHidLds ? kHid : 8;   // 16-bit elements
     __shared__ u32x4 wsm[NW / 8];
     __shared__ f32x4 slab4[WAVES * SLAB / 4];
     __shared__ nirc_lobes s_lobes;
     {
-        const u32x4 *src = (const u32x4 *)(packed + L.offset(SEC_D));
-        if (kLds)
+        const u32x4 *src = (const u32x4 *)(packed + L.offset(kLds ? SEC_D : SEC_H0));
+        if (kLds || kHidLds)
             for (int i = threadIdx.x; i < NW / 8; i += WAVES * 64) wsm[i] = src[i];
         if (threadIdx.x == 0) s_lobes = lobes;
     }
     __syncthreads();
     const uint16_t *sD = kLds ? (const uint16_t *)wsm : packed + L.offset(SEC_D);
-    const uint16_t *sH = sD + L.size(SEC_D);
-    const uint16_t *sOS = sH + 3 * L.size(SEC_H0) + L.size(SEC_O);
+    const uint16_t *sH = kHidLds ? (const uint16_t *)wsm : sD + L.size(SEC_D);
+    const uint16_t *sOS = kLds ? sH + 3 * L.size(SEC_H0) + L.size(SEC_O) : packed + L.offset(SEC_OS);
     const uint16_t *gS = packed + L.offset(SEC_S);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const GroupSlab gs = group_slab((float *)slab4 + wave * SLAB, W);
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2, OCC>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode,
-                                                                 rrad,
-                                                                 out_tl, out_c, out_r, s_lobes, gS, sD, sH, sOS, gs,
-                                                                 lane, g, col);
+        tlmc_group_h16<W, PREC, (W <= 64 || WAVES <= 4) ? 4 : 2, OCC, 0, kHidLds>(
+            pts, grp << 4, n_cache, dn, key0, key1, frame, mode, rrad, out_tl, out_c, out_r, s_lobes, gS, sD, sH, sOS,
+            gs, lane, g, col);
 }
 
 // Continuous batching: a persistent grid walks a device work list of requests (each with its own
@@ -540,16 +554,12 @@ hipError_t launch_tlmc_h16(int W, int prec, const Points &pts, const nirc_lobes 
         launch_h16_variant<64, NIRC_BF16, WAVES>(a, grid, s);
     else if (W == 64)
         launch_h16_variant<64, NIRC_FP16, WAVES>(a, grid, s);
-    // width 128: from 16 cache queries per point on, one wave per SIMD with 4-tile passes (half the weight
-    // traffic from L2 per tile); below that, two waves per SIMD with 2-tile passes hide the per-point work better
-    else if (W == 128 && n_cache >= 16 && prec == NIRC_BF16)
-        launch_h16_variant<128, NIRC_BF16, 4>(a, grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks), s);
-    else if (W == 128 && n_cache >= 16)
-        launch_h16_variant<128, NIRC_FP16, 4>(a, grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks), s);
+    // width 128: one wave per SIMD with 4-tile passes and the hidden layers in LDS (the room of
+    // four slabs beside the 96 KB of hidden-layer fragments)
     else if (W == 128 && prec == NIRC_BF16)
-        launch_h16_variant<128, NIRC_BF16, WAVES>(a, grid, s);
+        launch_h16_variant<128, NIRC_BF16, 4>(a, grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks), s);
     else if (W == 128)
-        launch_h16_variant<128, NIRC_FP16, WAVES>(a, grid, s);
+        launch_h16_variant<128, NIRC_FP16, 4>(a, grid_for((pts.count + 15) / 16, 4, kMaxResidentBlocks), s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
