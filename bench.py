@@ -51,6 +51,7 @@ def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=12.0, ta
     proportional share of the training batch; reported as queries/s of the whole frame, on all
     the oracle's threads and on one."""
     import numpy as np
+    import oracle
 
     P = pts.count
     rng = np.random.default_rng(1234)

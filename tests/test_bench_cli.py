@@ -25,3 +25,14 @@ def test_algorithmic_flops():
     assert bench.algorithmic_flops_estimate(1, 0, 64) == 2 * 112 * 64 + 2 * (48 * 64 + 3 * 64 * 64 + 3 * 64)
     w = 128
     assert bench.algorithmic_flops_train(1, w) == 2 * (160 * w + 3 * w * w + 3 * w) * 2 + 2 * (3 * w * w + 3 * w)
+
+
+def test_cpu_baseline_leg_runs():
+    # the oracle leg of the bench line on a tiny frame (small time targets): keys and units
+    from paper_2412_04634_amd import workload as wl
+    pts = wl.make_points(3, 2048)
+    lob = wl.make_lobes(3).packed()
+    w0 = wl.make_weights(3, 64)
+    r = bench.cpu_baseline(pts, lambda f: lob, w0, 64, 4, 256, 1, target_s=0.05, target_1core_s=0.05)
+    assert r["kind"] == "oracle" and r["unit"] == "queries/s" and r["value"] > 0 and r["cores"] >= 1
+    assert r["one_core"]["cores"] == 1 and r["one_core"]["value"] > 0
