@@ -294,3 +294,18 @@ def test_hash_checkpoint_resume(nirc):
     wa, wb = host(a.get_weights()), host(b.get_weights())
     assert rel_l2(wb - wc, wa - wc) <= 2e-2
     assert a.read_flags() == 0 and b.read_flags() == 0
+
+
+def test_hash_positions_outside_the_unit_cube(nirc):
+    # positions are clamped to the grid's domain on both sides: points scattered over [-0.25, 1.25]^3
+    P, N = 1000, 8
+    pts = wl.make_points(59, P)
+    for a in (pts.px, pts.py, pts.pz):
+        a[:] = (a * 1.5 - 0.25).astype(np.float32)
+    lob = wl.make_lobes(59).packed()
+    dp = nirc.Points.from_workload(pts)
+    model, w = _model(nirc, "fp16", GRIDS["default"], 59)
+    tl, c, r = (host(t) for t in nirc.nirc_hash_estimate(model, dp, lob, N, 5, 0, parts=True))
+    o_tl, o_c, o_r = oracle.hash_estimate(pts, lob, w, N, 5, 0)
+    assert rel_l2(c, o_c) <= 1e-2
+    assert np.isfinite(tl).all()
