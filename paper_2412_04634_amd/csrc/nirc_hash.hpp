@@ -201,17 +201,25 @@ __device__ __forceinline__ uint32_t hash_entry(const HashLevel &lv, uint32_t tma
 }
 
 // The 24 corner features lane group g needs at x (levels 3g..3g+2, 8 corners each): loads only,
-// so that they can be issued one point group ahead of their use.
+// so that they can be issued one point group ahead of their use.  The y and z parts of the
+// dense index and of the hash are formed once per level and shared by the corners.
 __device__ __forceinline__ void hash_fetch24(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
                                              float x1, float x2, int g, float2 (&t)[24]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const HashLevel lv = slv[3 * g + k];
         const HashCell h = hash_cell(x0, x1, x2, lv.res);
+        const uint32_t n1 = (uint32_t)lv.res + 1u;
+        const uint32_t c0 = (uint32_t)h.c[0], c1 = (uint32_t)h.c[1], c2 = (uint32_t)h.c[2];
+        const uint32_t dy = n1 * (c1 + n1 * c2);                          // dense: corner (0, 0, 0)
+        const uint32_t hy0 = c1 * 2654435761u, hz0 = c2 * 805459861u;     // hash: y and z parts
+        const uint32_t hy1 = hy0 + 2654435761u, hz1 = hz0 + 805459861u;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            float w;
-            t[8 * k + c] = table[hash_entry(lv, tmask, h, c, w)];
+            const uint32_t bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+            const uint32_t dense = c0 + bx + dy + (by ? n1 : 0u) + (bz ? n1 * n1 : 0u);
+            const uint32_t hashed = ((c0 + bx) ^ (by ? hy1 : hy0) ^ (bz ? hz1 : hz0)) & tmask;
+            t[8 * k + c] = table[lv.off + (lv.dense ? dense : hashed)];
         }
     }
 }
@@ -244,16 +252,26 @@ __device__ __forceinline__ void hash_values6(const HashLevel *slv, uint32_t tmas
     hash_blend6(slv, x0, x1, x2, g, t, v);
 }
 
-// Surface operands from grid values already blended (v) and the point's inputs.
+// One bin of the roughness one-blob (index i may be any value; used only where in range).
+__device__ __forceinline__ float oneblob_bin(float r, float i) {
+    const float d = 8.0f * r - (i + 0.5f);
+    return expf(-0.5f * d * d);
+}
+
+// Surface operands from grid values already blended (v) and the point's inputs.  Lane group g
+// needs phi[2g], phi[2g+1] (and group 0 also phi[8..14]): normal (phi 0..2), one-blob bins
+// (phi 3..10), albedo 1 (phi 11..13), zero (phi 14); only the bins a group uses are evaluated.
 template <int PREC>
 __device__ __forceinline__ void hash_pack_surface(const float xs[7], int g, const float (&v)[6], u32x4 &b0,
-                                                  u32x4 &b1, float (&ph)[15]) {
-    phi_values(xs, ph);
-    const float p0 = g == 0 ? ph[0] : g == 1 ? ph[2] : g == 2 ? ph[4] : ph[6];
-    const float p1 = g == 0 ? ph[1] : g == 1 ? ph[3] : g == 2 ? ph[5] : ph[7];
+                                                  u32x4 &b1) {
+    // bins: group 0 -> 5, 6, 7 (phi 8..10); group 1 -> 0 (phi 3); group 2 -> 1, 2; group 3 -> 3, 4
+    const float i0 = g == 0 ? 5.0f : g == 1 ? 0.0f : g == 2 ? 1.0f : 3.0f;
+    const float e0 = oneblob_bin(xs[6], i0), e1 = oneblob_bin(xs[6], i0 + 1.0f);
+    const float e2 = oneblob_bin(xs[6], 7.0f);
+    const float p0 = g == 0 ? xs[3] : g == 1 ? xs[5] : e0;
+    const float p1 = g == 0 ? xs[4] : g == 1 ? e0 : e1;
     b0 = u32x4{pack2<PREC>(v[0], v[1]), pack2<PREC>(v[2], v[3]), pack2<PREC>(v[4], v[5]), pack2<PREC>(p0, p1)};
-    b1 = g == 0 ? u32x4{pack2<PREC>(ph[8], ph[9]), pack2<PREC>(ph[10], ph[11]), pack2<PREC>(ph[12], ph[13]),
-                        pack2<PREC>(ph[14], 0.0f)}
+    b1 = g == 0 ? u32x4{pack2<PREC>(e0, e1), pack2<PREC>(e2, 1.0f), pack2<PREC>(1.0f, 1.0f), pack2<PREC>(0.0f, 0.0f)}
                 : u32x4{0u, 0u, 0u, 0u};
 }
 
@@ -263,7 +281,8 @@ __device__ __forceinline__ void hash_surface_operands(const HashLevel *slv, uint
                                                       const float xs[7], int g, u32x4 &b0, u32x4 &b1,
                                                       float (&v)[6], float (&ph)[15]) {
     hash_values6(slv, tmask, table, xs[0], xs[1], xs[2], g, v);
-    hash_pack_surface<PREC>(xs, g, v, b0, b1, ph);
+    phi_values(xs, ph);
+    hash_pack_surface<PREC>(xs, g, v, b0, b1);
 }
 
 // h += W1_s e_s for one tile of 16 columns (the surface section read from global memory).

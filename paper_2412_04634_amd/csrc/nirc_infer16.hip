@@ -305,10 +305,10 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
         if constexpr (ENC == 1) {
             static_assert(W == 64, "the hash-grid model has width 64");
             u32x4 b0, b1;
-            float v[6], ph[15];
+            float v[6];
             // corner features fetched one group ahead by the caller
             hash_blend6(slv, xs[0], xs[1], xs[2], g, *(const float2(*)[24])fetched, v);
-            hash_pack_surface<PREC>(xs, g, v, b0, b1, ph);
+            hash_pack_surface<PREC>(xs, g, v, b0, b1);
             hash_layer1_surface<PREC>(hsum, opaque(gS), b0, b1, lane);
         } else {
             layer1_surface16<W, PREC>(hsum, opaque(gS), xs, lane, g);
