@@ -394,9 +394,7 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
             lob = nirc.lobes_struct(lobes_for(f))
             ev[0].record(stream)
             if is_hash:
-                for s_ in range(S):
-                    q, tgt = nirc.tlmc_train_batch(dp, lob, B, seed, f, s_)
-                    nirc.nirc_hash_train_step(m, dp, q, tgt)
+                nirc.nirc_hash_train_frame(m, dp, lob, B, S, seed, f)
             else:
                 nirc.nirc_train_frame(m, dp, lob, B, S, seed, f)
             ev[1].record(stream)
@@ -558,10 +556,7 @@ def main():
                                cfg=nirc.make_config(precision=1), grid=grid, max_batch=B)
 
             def train(f):
-                lob = nirc.lobes_struct(lobes_for(f))
-                for s_ in range(S):
-                    q, tgt = nirc.tlmc_train_batch(dp, lob, B, seed, f, s_)
-                    nirc.nirc_hash_train_step(m, dp, q, tgt)
+                nirc.nirc_hash_train_frame(m, dp, nirc.lobes_struct(lobes_for(f)), B, S, seed, f)
         else:
             m = nirc.Model(w0, cfg=nirc.make_config(precision={"fp32": 0, "bf16": 1}[args.train_only]), max_batch=B)
 

@@ -451,6 +451,13 @@ nirc_status nirc_hash_adam_step(nirc_hash_model *model, const float *grad, void 
 nirc_status nirc_hash_train_step(nirc_hash_model *model, nirc_points points, nirc_queries queries,
                                  const float *target, float *loss, void *stream);
 
+/* One frame's online training, as nirc_train_frame: steps x (tlmc_train_batch, then
+ * nirc_hash_train_step) with the samples in the workspace (nirc_hash_workspace_bytes of at least
+ * `batch`); loss (device float, may be NULL) receives the last step's loss. */
+nirc_status nirc_hash_train_frame(nirc_hash_model *model, nirc_points points, const nirc_lobes *field /* host */,
+                                  int64_t batch, int32_t steps, uint64_t seed, uint64_t frame, float *loss,
+                                  void *stream);
+
 /* Flags raised by training (synchronises the stream); 0xFFFFFFFF on error. */
 uint32_t nirc_hash_read_flags(const nirc_hash_model *model, void *stream);
 

@@ -29,15 +29,17 @@ struct HashState {
     }
 };
 
-// Workspace: MLP partials [nblocks][16,576] | loss partials [nblocks] | gradient [np] | loss.
+// Workspace: MLP partials [nblocks][16,576] | loss partials [nblocks] | gradient [np] | loss |
+// training samples of nirc_hash_train_frame (point [B], wx, wy, wz [B], target [B][3]).
 struct HashWork {
-    size_t partials, loss_partials, grad, loss, total;
-    HashWork(int64_t np, int nblocks) {
+    size_t partials, loss_partials, grad, loss, samples, total;
+    HashWork(int64_t np, int nblocks, int64_t sample_batch = 0) {
         size_t o = 0;
         partials = o; o += align_up((size_t)nblocks * kHashMlp * sizeof(float));
         loss_partials = o; o += align_up((size_t)nblocks * sizeof(float));
         grad = o; o += align_up((size_t)np * sizeof(float));
         loss = o; o += align_up(sizeof(float));
+        samples = o; o += align_up((size_t)sample_batch * 7 * sizeof(float));
         total = o;
     }
 };
@@ -119,7 +121,7 @@ size_t nirc_hash_state_bytes(const nirc_config *cfg, const nirc_hash_grid *grid)
 size_t nirc_hash_workspace_bytes(const nirc_config *cfg, const nirc_hash_grid *grid, int64_t max_batch) {
     HashGridArgs g;
     if (check_hash_config(cfg, grid, &g) != NIRC_OK || max_batch < 0) return 0;
-    return HashWork(hash_np(g), train_blocks16(max_batch)).total;
+    return HashWork(hash_np(g), train_blocks16(max_batch), max_batch).total;
 }
 
 nirc_status nirc_hash_create(const nirc_config *cfg, const nirc_hash_grid *grid, void *state, size_t state_bytes,
@@ -297,6 +299,29 @@ nirc_status nirc_hash_train_step(nirc_hash_model *model, nirc_points points, nir
     nirc_status st = hash_grad_into(model, points, queries, target, grad, loss, s);
     if (st != NIRC_OK) return st;
     return hip_st(hash_adam(model, grad, s));
+}
+
+nirc_status nirc_hash_train_frame(nirc_hash_model *model, nirc_points points, const nirc_lobes *field,
+                                  int64_t batch, int32_t steps, uint64_t seed, uint64_t frame, float *loss,
+                                  void *stream) {
+    if (!model || !field || batch < 1 || batch > INT32_MAX || steps < 0) return NIRC_ERR_INVALID_ARG;
+    nirc_status st = check_points_h(points);
+    if (st != NIRC_OK || points.count < 1) return NIRC_ERR_INVALID_ARG;
+    const HashWork wl(model->np, train_blocks16(batch), batch);
+    if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    float *smp = (float *)(model->ws + wl.samples);
+    int32_t *pidx = (int32_t *)smp;
+    float *wx = smp + batch, *wy = wx + batch, *wz = wy + batch, *tgt = wz + batch;
+    for (int32_t k = 0; k < steps; ++k) {
+        if (launch_train_batch(pts_of(points), *field, batch, seed, frame, (uint32_t)k, NIRC_OUTPUT_RADIANCE, pidx,
+                               wx, wy, wz, tgt, s) != hipSuccess)
+            return NIRC_ERR_HIP;
+        const nirc_queries q{wx, wy, wz, pidx, batch};
+        st = nirc_hash_train_step(model, points, q, tgt, k + 1 == steps ? loss : nullptr, s);
+        if (st != NIRC_OK) return st;
+    }
+    return NIRC_OK;
 }
 
 uint32_t nirc_hash_read_flags(const nirc_hash_model *model, void *stream) {

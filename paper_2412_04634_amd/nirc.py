@@ -129,6 +129,7 @@ def lib():
             "nirc_hash_adam_step": (_i32, [_vp, _vp, _vp]),
             "nirc_hash_train_step": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
             "nirc_hash_read_flags": (_u32, [_vp, _vp]),
+            "nirc_hash_train_frame": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i64, _i32, _u64, _u64, _vp, _vp]),
             "nirc_status_string": (ctypes.c_char_p, [_i32]),
         }
         for name, (res, args) in sig.items():
@@ -642,3 +643,11 @@ def nirc_hash_train_step(model: HashModel, points: Points, queries: Queries, tar
     t = target.contiguous()
     _check(lib().nirc_hash_train_step(model.handle, points.c(), queries.c(), _ptr(t), _ptr(loss), _stream()),
            "nirc_hash_train_step")
+
+
+def nirc_hash_train_frame(model: HashModel, points: Points, lobes, batch: int, steps: int, seed: int, frame: int,
+                          loss=None):
+    """One frame of online training of a hash-grid model (steps x generated batch + train step)."""
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    _check(lib().nirc_hash_train_frame(model.handle, points.c(), ctypes.byref(L), batch, steps, seed, frame,
+                                       _ptr(loss), _stream()), "nirc_hash_train_frame")

@@ -309,3 +309,24 @@ def test_hash_positions_outside_the_unit_cube(nirc):
     o_tl, o_c, o_r = oracle.hash_estimate(pts, lob, w, N, 5, 0)
     assert rel_l2(c, o_c) <= 1e-2
     assert np.isfinite(tl).all()
+
+
+def test_hash_train_frame_matches_step_loop(nirc):
+    # the native frame loop (samples generated into the workspace) against the same steps called
+    # one by one; the grid gradient's atomic sums make them agree to rounding
+    P, B = 4096, 2048
+    pts = wl.make_points(60, P)
+    lob = wl.make_lobes(60).packed()
+    dp = nirc.Points.from_workload(pts)
+    a, w = _model(nirc, "bf16", GRIDS["small"], 60, max_batch=B, scale=1e-4)
+    b, _ = _model(nirc, "bf16", GRIDS["small"], 60, max_batch=B, scale=1e-4)
+    loss = torch.zeros(1, device="cuda")
+    for f in range(2):
+        nirc.nirc_hash_train_frame(a, dp, lob, B, 3, 61, f, loss)
+        for s_ in range(3):
+            q, tgt = nirc.tlmc_train_batch(dp, lob, B, 61, f, s_)
+            nirc.nirc_hash_train_step(b, dp, q, tgt)
+    w0 = w.astype(np.float64)
+    wa, wb = host(a.get_weights()), host(b.get_weights())
+    assert rel_l2(wa - w0, wb - w0) <= 2e-2
+    assert np.isfinite(float(loss.item())) and float(loss.item()) > 0
