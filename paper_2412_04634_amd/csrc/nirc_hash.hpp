@@ -175,7 +175,7 @@ struct HashCell {
 };
 
 // Cell of x (clamped to the unit cube) at resolution N: lower corner and fractions.
-__device__ __forceinline__ HashCell hash_cell(float x0, float x1, float x2, int N) {
+__host__ __device__ __forceinline__ HashCell hash_cell(float x0, float x1, float x2, int N) {
     HashCell h;
     const float xs[3] = {x0, x1, x2};
 #pragma unroll
@@ -189,7 +189,7 @@ __device__ __forceinline__ HashCell hash_cell(float x0, float x1, float x2, int 
 }
 
 // Entry of corner k (bit d of k: +1 along axis d) and its trilinear weight.
-__device__ __forceinline__ uint32_t hash_entry(const HashLevel &lv, uint32_t tmask, const HashCell &h, int k,
+__host__ __device__ __forceinline__ uint32_t hash_entry(const HashLevel &lv, uint32_t tmask, const HashCell &h, int k,
                                                float &w) {
     const int v0 = h.c[0] + (k & 1), v1 = h.c[1] + ((k >> 1) & 1), v2 = h.c[2] + ((k >> 2) & 1);
     w = ((k & 1) ? h.f[0] : 1.0f - h.f[0]) * (((k >> 1) & 1) ? h.f[1] : 1.0f - h.f[1]) *
@@ -203,7 +203,7 @@ __device__ __forceinline__ uint32_t hash_entry(const HashLevel &lv, uint32_t tma
 // The 24 corner features lane group g needs at x (levels 3g..3g+2, 8 corners each): loads only,
 // so that they can be issued one point group ahead of their use.  The y and z parts of the
 // dense index and of the hash are formed once per level and shared by the corners.
-__device__ __forceinline__ void hash_fetch24(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
+__host__ __device__ __forceinline__ void hash_fetch24(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
                                              float x1, float x2, int g, float2 (&t)[24]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -225,7 +225,7 @@ __device__ __forceinline__ void hash_fetch24(const HashLevel *slv, uint32_t tmas
 }
 
 // Trilinear blend of fetched corner features into lane group g's six grid values.
-__device__ __forceinline__ void hash_blend6(const HashLevel *slv, float x0, float x1, float x2, int g,
+__host__ __device__ __forceinline__ void hash_blend6(const HashLevel *slv, float x0, float x1, float x2, int g,
                                             const float2 (&t)[24], float (&v)[6]) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -245,7 +245,7 @@ __device__ __forceinline__ void hash_blend6(const HashLevel *slv, float x0, floa
 }
 
 // Lane group g's six grid values at x (all 24 loads issued before they are blended).
-__device__ __forceinline__ void hash_values6(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
+__host__ __device__ __forceinline__ void hash_values6(const HashLevel *slv, uint32_t tmask, const float2 *table, float x0,
                                              float x1, float x2, int g, float (&v)[6]) {
     float2 t[24];
     hash_fetch24(slv, tmask, table, x0, x1, x2, g, t);

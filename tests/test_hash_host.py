@@ -65,3 +65,34 @@ def test_hash_packed_layout_covers_parameters(tmp_path):
     ts = ts[ts >= 0]
     assert sorted(ts.tolist()) == sorted(r * nin + c for r in range(W) for c in range(24))
     assert secT0 > rest
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+@pytest.mark.parametrize("grid", [(18, 16, 1.5), (10, 4, 1.5)])
+def test_device_grid_lookup_matches_oracle(tmp_path, grid):
+    # the kernels' grid fetch and trilinear blend (FP32) against the oracle's encoding (FP64), on
+    # random features in [-1, 1] and positions inside and outside the unit cube
+    from paper_2412_04634_amd import workload as wl
+    exe = _build(tmp_path, "hash_grid_check")
+    n = oracle.hash_entries(grid)
+    rng = np.random.default_rng(11)
+    table = rng.uniform(-1.0, 1.0, 2 * n).astype(np.float32)
+    pts = wl.make_points(12, 3000)
+    xyz = np.stack([pts.px, pts.py, pts.pz], axis=1).astype(np.float32)
+    xyz[:200] = (xyz[:200] * 1.4 - 0.2).astype(np.float32)
+    pts.px[:], pts.py[:], pts.pz[:] = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    ft, fp = str(tmp_path / "table.bin"), str(tmp_path / "pts.bin")
+    table.tofile(ft)
+    np.ascontiguousarray(xyz).tofile(fp)
+    out = subprocess.run([exe, ft, fp, str(grid[0]), str(grid[1]), str(grid[2])], check=True, capture_output=True,
+                         text=True, timeout=300).stdout
+    got = np.array([[float(v) for v in l.split()] for l in out.strip().split("\n")])
+    ref = oracle.hash_encode(pts, None, np.tile([[0.0, 0.0, 1.0]], (3000, 1)), table.astype(np.float64), grid)[:, :24]
+    # level l: the FP32 product x N_l is off by up to half an ulp (2^-24 N_l relative to the cell),
+    # which moves the blend of features in [-1, 1] by at most that times the largest corner
+    # difference (2) along each axis; the blend itself adds a few 1e-7
+    res, _, _ = oracle.hash_levels(grid)
+    err = np.abs(got - ref)
+    for l in range(12):
+        bound = 3 * 2 * 2.0 ** -24 * float(res[l]) * 2 + 1e-6
+        assert err[:, 2 * l:2 * l + 2].max() <= bound, (l, err[:, 2 * l:2 * l + 2].max(), bound)
