@@ -84,8 +84,12 @@ def test_device_grid_lookup_matches_oracle(tmp_path, grid):
     ft, fp = str(tmp_path / "table.bin"), str(tmp_path / "pts.bin")
     table.tofile(ft)
     np.ascontiguousarray(xyz).tofile(fp)
-    out = subprocess.run([exe, ft, fp, str(grid[0]), str(grid[1]), str(grid[2])], check=True, capture_output=True,
-                         text=True, timeout=300).stdout
+    run = subprocess.run([exe, ft, fp, str(grid[0]), str(grid[1]), str(grid[2])], check=True, capture_output=True,
+                         text=True, timeout=300)
+    out = run.stdout
+    # the training scatter's corner entries and weights agree with the fetch corner by corner
+    mismatch, max_w = run.stderr.split()
+    assert int(mismatch) == 0 and float(max_w) <= 1e-5
     got = np.array([[float(v) for v in l.split()] for l in out.strip().split("\n")])
     ref = oracle.hash_encode(pts, None, np.tile([[0.0, 0.0, 1.0]], (3000, 1)), table.astype(np.float64), grid)[:, :24]
     # level l: the FP32 product x N_l is off by up to half an ulp (2^-24 N_l relative to the cell),
