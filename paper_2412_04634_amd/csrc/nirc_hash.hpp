@@ -338,9 +338,118 @@ __device__ __forceinline__ void stage_levels(HashLevel *slv, const HashGridArgs 
         if ((int)threadIdx.x == l) slv[l] = grid.lv[l];
 }
 
+
+// ------------------------------------------------------------------------------------------
+// FP32 chain (16x16x4 MFMA: lane group g holds K index g of each K-step), inference only.
+// Packed FP32 weights: S (W1 surface columns: 4 row tiles x 12 K-steps), D (W1 direction
+// columns: 4 x 8), then H0..H2 and O exactly as in the frequency model's FP32 layout.  K-step k
+// of lane group g carries canonical input
+//   S: k < 6: grid value 6g + k (levels 3g..3g+2); 6 <= k < 10: surface value phi[4(k-6) + g]
+//      (none past phi 14); k = 10, 11: zero;
+//   D: k < 7: spherical harmonic 4k + g (none past 24); k = 7: zero.
+constexpr int kHash32S = 4 * 12 * 64;
+constexpr int kHash32D = 4 * 8 * 64;
+constexpr int kHash32Rest = F32Layout{64}.offset(SEC_T0) - F32Layout{64}.offset(SEC_H0);   // H0..H2, O
+constexpr int kHash32Packed = kHash32S + kHash32D + kHash32Rest;
+
+__host__ __device__ inline int64_t hash_packed_source32(int e) {
+    if (e < kHash32S + kHash32D) {
+        const bool dir = e >= kHash32S;
+        const int r = e - (dir ? kHash32S : 0);
+        const int NQ = dir ? 2 : 3;   // K-quads
+        const int kk = r & 3, lane = (r >> 2) & 63, rest = r >> 8;
+        const int kq = rest % NQ, m = rest / NQ;
+        const int k = 4 * kq + kk, row = 16 * m + (lane & 15), g = lane >> 4;
+        int in = -1;
+        if (dir) {
+            if (k < 7 && 4 * k + g < 25) in = 24 + 4 * k + g;
+        } else if (k < 6) {
+            in = 6 * g + k;
+        } else if (k < 10 && 4 * (k - 6) + g < 15) {
+            in = 49 + 4 * (k - 6) + g;
+        }
+        return in < 0 ? -1 : (int64_t)row * kHashIn + in;
+    }
+    if (e < kHash32Packed) {
+        const int64_t s = f32_packed_source(64, e - kHash32S - kHash32D + F32Layout{64}.offset(SEC_H0));
+        return s < 0 ? -1 : s - kHashCanonShift;
+    }
+    return -1;
+}
+
+// phi[4j + g], j = 0..3, for lane group g (normal, one-blob bins, albedo 1, zero slot, pad).
+__device__ __forceinline__ void hash_phi4(const float xs[7], int g, float (&ph)[4]) {
+    // bins needed: g < 3: g + 1 and g + 5; g = 3: 4 and 0
+    const float ia = g < 3 ? (float)(g + 1) : 4.0f, ib = g < 3 ? (float)(g + 5) : 0.0f;
+    const float ea = oneblob_bin(xs[6], ia), eb = oneblob_bin(xs[6], ib);
+    const float nrm = g == 0 ? xs[3] : g == 1 ? xs[4] : xs[5];
+    ph[0] = g < 3 ? nrm : eb;                  // phi[g]: normal, or bin 0
+    ph[1] = ea;                                // phi[4 + g]: bins 1..4
+    ph[2] = g < 3 ? eb : 1.0f;                 // phi[8 + g]: bins 5..7, albedo
+    ph[3] = g < 2 ? 1.0f : 0.0f;               // phi[12 + g]: albedo, albedo, zero slot, pad
+}
+
+// h += W1_s e_s for one tile of 16 points (FP32; surface section read from global memory).
+__device__ __forceinline__ void hash_layer1_surface_f32(f32x4 (&h)[4], const float *gS, const float (&v)[6],
+                                                        const float (&ph)[4], int lane) {
+    const float b[12] = {v[0], v[1], v[2], v[3], v[4], v[5], ph[0], ph[1], ph[2], ph[3], 0.0f, 0.0f};
+#pragma unroll
+    for (int kq = 0; kq < 3; ++kq) {
+        f32x4 a[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a[mt] = *(const f32x4 *)(gS + ((mt * 3 + kq) * 64 + lane) * 4);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) h[mt] = mfma4(a[mt][kk], b[4 * kq + kk], h[mt]);
+    }
+}
+
+// The 8 direction K values of lane group g: SH 4k + g (constant indices only, so the SH values
+// stay in registers).
+__device__ __forceinline__ void hash_dir_values_f32(float dx, float dy, float dz, int g, float (&s)[8]) {
+    float Y[25];
+    sh25(dx, dy, dz, Y);
+    s[0] = g == 0 ? Y[0] : g == 1 ? Y[1] : g == 2 ? Y[2] : Y[3];
+    s[1] = g == 0 ? Y[4] : g == 1 ? Y[5] : g == 2 ? Y[6] : Y[7];
+    s[2] = g == 0 ? Y[8] : g == 1 ? Y[9] : g == 2 ? Y[10] : Y[11];
+    s[3] = g == 0 ? Y[12] : g == 1 ? Y[13] : g == 2 ? Y[14] : Y[15];
+    s[4] = g == 0 ? Y[16] : g == 1 ? Y[17] : g == 2 ? Y[18] : Y[19];
+    s[5] = g == 0 ? Y[20] : g == 1 ? Y[21] : g == 2 ? Y[22] : Y[23];
+    s[6] = g == 0 ? Y[24] : 0.0f;
+    s[7] = 0.0f;
+}
+
+// h[tt] += W1_w e_w(direction of tile tt) for T tiles (FP32).
+template <int T>
+__device__ __forceinline__ void hash_layer1_direction_f32(f32x4 (&h)[T][4], const float *sD, const float *dx,
+                                                          const float *dy, const float *dz, int lane, int g) {
+    float b[T][8];
+#pragma unroll
+    for (int tt = 0; tt < T; ++tt) hash_dir_values_f32(dx[tt], dy[tt], dz[tt], g, b[tt]);
+#pragma unroll
+    for (int kq = 0; kq < 2; ++kq) {
+        f32x4 a[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a[mt] = *(const f32x4 *)(sD + ((mt * 2 + kq) * 64 + lane) * 4);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma4(a[mt][kk], b[tt][4 * kq + kk], h[tt][mt]);
+    }
+}
+
 // Launchers (host).
 hipError_t launch_hash_pack16(uint16_t *packed, const float *master, int prec, hipStream_t s, int64_t *step = nullptr,
                               uint32_t *flags = nullptr, uint32_t *bad = nullptr);
+hipError_t launch_hash_pack32(float *packed, const float *master, hipStream_t s);
+hipError_t launch_hash_infer32(const Points &pts, const Queries &q, const float *packed, const float *table,
+                               const HashGridArgs &grid, float *rgb, hipStream_t s);
+hipError_t launch_hash_tlmc32(const Points &pts, const nirc_lobes &lobes, const float *packed, const float *table,
+                              const HashGridArgs &grid, int n_cache, uint64_t seed, uint64_t frame, const float *rrad,
+                              float *out_tl, float *out_c, float *out_r, hipStream_t s);
 hipError_t launch_hash_infer(int prec, const Points &pts, const Queries &q, const uint16_t *packed, const float *table,
                              const HashGridArgs &grid, float *rgb, hipStream_t s);
 hipError_t launch_hash_tlmc(int prec, const Points &pts, const nirc_lobes &lobes, const uint16_t *packed,

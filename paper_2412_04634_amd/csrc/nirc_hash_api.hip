@@ -12,16 +12,18 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// State (each piece 256-byte aligned): parameters | m | v | packed 16-bit layers | step | flags | bad.
+// State (each piece 256-byte aligned): parameters | m | v | packed layers (16-bit, or FP32 for
+// FP32 models) | step | flags | bad.
 struct HashState {
     size_t master, m, v, packed16, step, flags, bad, total;
-    explicit HashState(int64_t np) {
+    HashState(int64_t np, int prec) {
         const size_t b = (size_t)np * sizeof(float);
         size_t o = 0;
         master = o; o += align_up(b);
         m = o; o += align_up(b);
         v = o; o += align_up(b);
-        packed16 = o; o += align_up((size_t)kHashPacked * sizeof(uint16_t));
+        packed16 = o;
+        o += align_up(prec == NIRC_FP32 ? (size_t)kHash32Packed * sizeof(float) : (size_t)kHashPacked * sizeof(uint16_t));
         step = o; o += align_up(sizeof(int64_t));
         flags = o; o += align_up(sizeof(uint32_t));
         bad = o; o += align_up(sizeof(uint32_t));
@@ -46,7 +48,7 @@ struct HashWork {
 
 nirc_status check_hash_config(const nirc_config *cfg, const nirc_hash_grid *grid, HashGridArgs *args) {
     if (!cfg || !grid) return NIRC_ERR_INVALID_ARG;
-    if (cfg->width != 64 || (cfg->precision != NIRC_BF16 && cfg->precision != NIRC_FP16) ||
+    if (cfg->width != 64 || (cfg->precision != NIRC_FP32 && cfg->precision != NIRC_BF16 && cfg->precision != NIRC_FP16) ||
         (cfg->loss != NIRC_LOSS_REL_L2 && cfg->loss != NIRC_LOSS_L2) || cfg->output != NIRC_OUTPUT_RADIANCE)
         return NIRC_ERR_UNSUPPORTED;
     if (!(cfg->lr > 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
@@ -84,13 +86,21 @@ struct nirc_hash_model {
     HashGridArgs grid;
     int64_t np;
     float *master, *m, *v;
-    uint16_t *packed16;
+    uint16_t *packed16;   // the packed layers (FP32 elements for FP32 models)
     int64_t *step;
     uint32_t *flags, *bad;
     char *ws;
     size_t ws_bytes;
     const float *table() const { return master + kHashMlp; }
+    float *packed32() const { return (float *)packed16; }
 };
+
+namespace {
+hipError_t repack(const nirc_hash_model *m, hipStream_t s) {
+    return m->cfg.precision == NIRC_FP32 ? launch_hash_pack32(m->packed32(), m->master, s)
+                                         : launch_hash_pack16(m->packed16, m->master, m->cfg.precision, s);
+}
+}  // namespace
 
 extern "C" {
 
@@ -115,7 +125,7 @@ nirc_status nirc_hash_levels(const nirc_hash_grid *grid, int32_t *res, int64_t *
 size_t nirc_hash_state_bytes(const nirc_config *cfg, const nirc_hash_grid *grid) {
     HashGridArgs g;
     if (check_hash_config(cfg, grid, &g) != NIRC_OK) return 0;
-    return HashState(hash_np(g)).total;
+    return HashState(hash_np(g), cfg->precision).total;
 }
 
 size_t nirc_hash_workspace_bytes(const nirc_config *cfg, const nirc_hash_grid *grid, int64_t max_batch) {
@@ -133,7 +143,7 @@ nirc_status nirc_hash_create(const nirc_config *cfg, const nirc_hash_grid *grid,
     if (!state || !init_w || !out || ((uintptr_t)state % kAlign) != 0) return NIRC_ERR_INVALID_ARG;
     if (workspace && ((uintptr_t)workspace % kAlign) != 0) return NIRC_ERR_INVALID_ARG;
     const int64_t np = hash_np(g);
-    const HashState sl(np);
+    const HashState sl(np, cfg->precision);
     if (state_bytes < sl.total) return NIRC_ERR_WORKSPACE;
     nirc_hash_model *m = new (std::nothrow) nirc_hash_model;
     if (!m) return NIRC_ERR_INVALID_ARG;
@@ -177,7 +187,7 @@ nirc_status nirc_hash_set_weights(nirc_hash_model *model, const float *w, void *
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->m, model->np, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->v, model->np, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->step, 2, 0u, s);
-    if (e == hipSuccess) e = launch_hash_pack16(model->packed16, model->master, model->cfg.precision, s);
+    if (e == hipSuccess) e = repack(model, s);
     return hip_st(e);
 }
 
@@ -189,19 +199,19 @@ nirc_status nirc_hash_get_weights(const nirc_hash_model *model, float *w, void *
 // The state is one region from the FP32 parameters on (HashState); a blob is its image.
 nirc_status nirc_hash_get_state(const nirc_hash_model *model, void *blob, size_t blob_bytes, void *stream) {
     if (!model || !blob || ((uintptr_t)blob % 4) != 0) return NIRC_ERR_INVALID_ARG;
-    const size_t bytes = HashState(model->np).total;
+    const size_t bytes = HashState(model->np, model->cfg.precision).total;
     if (blob_bytes != bytes) return NIRC_ERR_INVALID_ARG;
     return hip_st(launch_copy_f32((float *)blob, model->master, (int64_t)(bytes / 4), (hipStream_t)stream));
 }
 
 nirc_status nirc_hash_set_state(nirc_hash_model *model, const void *blob, size_t blob_bytes, void *stream) {
     if (!model || !blob || ((uintptr_t)blob % 4) != 0) return NIRC_ERR_INVALID_ARG;
-    const size_t bytes = HashState(model->np).total;
+    const size_t bytes = HashState(model->np, model->cfg.precision).total;
     if (blob_bytes != bytes) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_copy_f32(model->master, (const float *)blob, (int64_t)(bytes / 4), s);
-    // the packed layers follow the restored FP32 parameters whatever precision wrote the blob
-    if (e == hipSuccess) e = launch_hash_pack16(model->packed16, model->master, model->cfg.precision, s);
+    // the packed layers follow the restored FP32 parameters
+    if (e == hipSuccess) e = repack(model, s);
     return hip_st(e);
 }
 
@@ -213,6 +223,9 @@ nirc_status nirc_hash_infer(const nirc_hash_model *model, nirc_points points, ni
     if (st != NIRC_OK) return st;
     if (queries.count == 0) return NIRC_OK;
     if (!rgb) return NIRC_ERR_INVALID_ARG;
+    if (model->cfg.precision == NIRC_FP32)
+        return hip_st(launch_hash_infer32(pts_of(points), queries_of(queries), model->packed32(), model->table(),
+                                          model->grid, rgb, (hipStream_t)stream));
     return hip_st(launch_hash_infer(model->cfg.precision, pts_of(points), queries_of(queries), model->packed16,
                                     model->table(), model->grid, rgb, (hipStream_t)stream));
 }
@@ -227,6 +240,10 @@ nirc_status nirc_hash_estimate(const nirc_hash_model *model, nirc_points points,
     if (points.count == 0) return NIRC_OK;
     nirc_lobes none;
     memset(&none, 0, sizeof(none));
+    if (model->cfg.precision == NIRC_FP32)
+        return hip_st(launch_hash_tlmc32(pts_of(points), field ? *field : none, model->packed32(), model->table(),
+                                         model->grid, n_cache, seed, frame, residual_radiance, out_tl, out_c, out_r,
+                                         (hipStream_t)stream));
     return hip_st(launch_hash_tlmc(model->cfg.precision, pts_of(points), field ? *field : none, model->packed16,
                                    model->table(), model->grid, n_cache, seed, frame, residual_radiance, out_tl, out_c,
                                    out_r, (hipStream_t)stream));
@@ -235,6 +252,7 @@ nirc_status nirc_hash_estimate(const nirc_hash_model *model, nirc_points points,
 // Loss and gradient into grad/loss; the step's `bad` flag is raised on a non-finite value.
 static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &points, const nirc_queries &queries,
                                   const float *target, float *grad, float *loss, hipStream_t s) {
+    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;   // training runs in 16-bit
     nirc_status st = check_points_h(points);
     if (st == NIRC_OK) st = check_queries_h(queries, points);
     if (st != NIRC_OK) return st;
@@ -262,6 +280,7 @@ static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &poi
 }
 
 static hipError_t hash_adam(nirc_hash_model *model, const float *grad, hipStream_t s) {
+    if (model->cfg.precision == NIRC_FP32) return hipErrorNotSupported;
     hipError_t e = launch_adam_n(model->np, model->master, model->m, model->v, grad, model->step, model->bad,
                                  model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps, s);
     if (e == hipSuccess)
@@ -282,6 +301,7 @@ nirc_status nirc_hash_loss_grad(nirc_hash_model *model, nirc_points points, nirc
 
 nirc_status nirc_hash_adam_step(nirc_hash_model *model, const float *grad, void *stream) {
     if (!model || !grad) return NIRC_ERR_INVALID_ARG;
+    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_check_finite_n(model->np, grad, model->bad, s);
     if (e == hipSuccess) e = hash_adam(model, grad, s);
@@ -291,6 +311,7 @@ nirc_status nirc_hash_adam_step(nirc_hash_model *model, const float *grad, void 
 nirc_status nirc_hash_train_step(nirc_hash_model *model, nirc_points points, nirc_queries queries,
                                  const float *target, float *loss, void *stream) {
     if (!model) return NIRC_ERR_INVALID_ARG;
+    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (!model->ws) return NIRC_ERR_WORKSPACE;
     const HashWork wl(model->np, train_blocks16(queries.count > 0 ? queries.count : 1));
@@ -305,6 +326,7 @@ nirc_status nirc_hash_train_frame(nirc_hash_model *model, nirc_points points, co
                                   int64_t batch, int32_t steps, uint64_t seed, uint64_t frame, float *loss,
                                   void *stream) {
     if (!model || !field || batch < 1 || batch > INT32_MAX || steps < 0) return NIRC_ERR_INVALID_ARG;
+    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
     nirc_status st = check_points_h(points);
     if (st != NIRC_OK || points.count < 1) return NIRC_ERR_INVALID_ARG;
     const HashWork wl(model->np, train_blocks16(batch), batch);

@@ -1,6 +1,6 @@
 // Inference-side kernels: weight packing, input encoding, direction sampling, training-sample
 // generation, per-query cache inference and the fused two-level estimator.
-#include "nirc_kernels.hpp"
+#include "nirc_hash.hpp"
 
 namespace nirc {
 
@@ -239,7 +239,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
 // current point group through the FP32 chain, then per-point accumulation.
 // OCC: the occluded-scene variants (visibility cache, radiance cache of the occluded scene),
 // selected at run time by `mode`; the radiance cache of the plain scene compiles without them.
-template <int W, int T, bool OCC>
+// ENC 1: the hash-grid model's direction input (spherical harmonics; width 64).
+template <int W, int T, bool OCC, int ENC = 0>
 __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN dn, const float *db, const float *hs,
                                                const float *sD, const float *sH, const float *sO,
                                                const nirc_lobes &lobes, const float *rrad, int64_t pc,
@@ -267,7 +268,10 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(hs + j * W + 16 * mt + 4 * g);
     }
-    layer1_direction<W, T>(h, sD, dx, dy, dz, lane, g);
+    if constexpr (ENC == 1)
+        hash_layer1_direction_f32<T>(h, sD, dx, dy, dz, lane, g);
+    else
+        layer1_direction<W, T>(h, sD, dx, dy, dz, lane, g);
     relu_all<W, T>(h);
     hidden_layers<W, T>(h, sH, lane);
     f32x4 y[T];
@@ -326,13 +330,16 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 // results are summed per point with a 16-lane prefix sum; the residual tile evaluates the
 // field and subtracts.  Only the final per-point values leave the chip.
 // One point group (16 points from p0) through the FP32 chain.
-template <int W, bool OCC>
+// ENC 1: the hash-grid model (surface part from the grid `slv`/`table` and phi).
+template <int W, bool OCC, int ENC = 0>
 __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
                                                uint32_t key1, uint32_t frame, int mode, const float *rrad,
                                                float *out_tl,
                                                float *out_c, float *out_r, const nirc_lobes &lobes,
                                                const float *gS, const float *sD, const float *sH, const float *sO,
-                                               float *hs, float *db, int lane, int g, int col) {
+                                               float *hs, float *db, int lane, int g, int col,
+                                               const HashLevel *slv = nullptr, uint32_t tmask = 0u,
+                                               const float2 *table = nullptr) {
     constexpr int MT = W / 16;
     const int64_t P = pts.count;
     const int n_tiles = n_cache + 1;
@@ -342,7 +349,15 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         f32x4 hsum[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) hsum[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        layer1_surface<W>(hsum, opaque(gS), xs, lane, g);
+        if constexpr (ENC == 1) {
+            static_assert(W == 64, "the hash-grid model has width 64");
+            float v[6], ph[4];
+            hash_values6(slv, tmask, table, xs[0], xs[1], xs[2], g, v);
+            hash_phi4(xs, g, ph);
+            hash_layer1_surface_f32(hsum, opaque(gS), v, ph, lane);
+        } else {
+            layer1_surface<W>(hsum, opaque(gS), xs, lane, g);
+        }
         wave_sync();   // previous group's readers of the slab are done
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
@@ -356,12 +371,12 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_f32<W, TP, OCC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
-                                  g, col, fc0, fc1, fc2, fr0, fr1, fr2);
+            tlmc_tiles_f32<W, TP, OCC, ENC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs,
+                                            lane, g, col, fc0, fc1, fc2, fr0, fr1, fr2);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_f32<W, 1, OCC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs, lane,
-                                 g, col, fc0, fc1, fc2, fr0, fr1, fr2);
+            tlmc_tiles_f32<W, 1, OCC, ENC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs,
+                                           lane, g, col, fc0, fc1, fc2, fr0, fr1, fr2);
         tb = tend;
     }
     if (g == 0 && p0 + col < P)
@@ -560,6 +575,124 @@ hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lob
                            dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// The hash-grid model in FP32 (inference and estimation).
+
+__global__ void k_hash_pack32(float *packed, const float *master) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < kHash32Packed) {
+        const int64_t s = hash_packed_source32(e);
+        packed[e] = s >= 0 ? master[s] : 0.0f;
+    }
+}
+
+constexpr int kHash32LdsWeights = kHash32D + kHash32Rest;   // D, H0..H2, O
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_hash_tlmc_f32(Points pts, nirc_lobes lobes,
+                                                              const float *__restrict__ packed,
+                                                              const float2 *__restrict__ table, HashGridArgs grid,
+                                                              int n_cache, DivN dn, uint32_t key0, uint32_t key1,
+                                                              uint32_t frame, const float *__restrict__ rrad,
+                                                              float *__restrict__ out_tl, float *__restrict__ out_c,
+                                                              float *__restrict__ out_r) {
+    constexpr int NW = kHash32LdsWeights;
+    constexpr int SLAB = TlmcLds<64>::kSlab;
+    __shared__ f32x4 smem4[(NW + WAVES * SLAB) / 4];
+    __shared__ nirc_lobes s_lobes;
+    __shared__ HashLevel s_lv[kHashLevels];
+    float *smem = (float *)smem4;
+    {
+        const f32x4 *src = (const f32x4 *)(packed + kHash32S);
+        for (int i = threadIdx.x; i < NW / 4; i += WAVES * 64) smem4[i] = src[i];
+        if (threadIdx.x == 0) s_lobes = lobes;
+        stage_levels(s_lv, grid);
+    }
+    __syncthreads();
+    const float *sD = smem;
+    const float *sH = sD + kHash32D;
+    const float *sO = sH + 3 * F32Layout{64}.size(SEC_H0);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    float *hs = smem + NW + wave * SLAB;
+    float *db = hs + 16 * 64;
+    const int64_t n_groups = (pts.count + 15) >> 4;
+    for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
+        tlmc_group_f32<64, false, 1>(pts, grp << 4, n_cache, dn, key0, key1, frame, NIRC_OUTPUT_RADIANCE, rrad, out_tl,
+                                     out_c, out_r, s_lobes, packed, sD, sH, sO, hs, db, lane, g, col, s_lv, grid.tmask,
+                                     table);
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_hash_infer_f32(Points pts, Queries q, const float *__restrict__ packed,
+                                                               const float2 *__restrict__ table, HashGridArgs grid,
+                                                               float *__restrict__ rgb) {
+    constexpr int NW = kHash32LdsWeights;
+    __shared__ f32x4 smem4[NW / 4];
+    __shared__ HashLevel s_lv[kHashLevels];
+    {
+        const f32x4 *src = (const f32x4 *)(packed + kHash32S);
+        for (int i = threadIdx.x; i < NW / 4; i += WAVES * 64) smem4[i] = src[i];
+        stage_levels(s_lv, grid);
+    }
+    __syncthreads();
+    const float *sD = (const float *)smem4;
+    const float *sH = sD + kHash32D;
+    const float *sO = sH + 3 * F32Layout{64}.size(SEC_H0);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t Q = q.count;
+    const int64_t n_tiles = (Q + 15) >> 4;
+    for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < n_tiles; tile += (int64_t)gridDim.x * WAVES) {
+        const int64_t qi = min((tile << 4) + col, Q - 1);
+        const int64_t p = query_point(q, pts, qi);
+        const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+        f32x4 h[1][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) h[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float v[6], ph[4];
+        hash_values6(s_lv, grid.tmask, table, xs[0], xs[1], xs[2], g, v);
+        hash_phi4(xs, g, ph);
+        hash_layer1_surface_f32(h[0], opaque(packed), v, ph, lane);
+        const float dx[1] = {q.wx[qi]}, dy[1] = {q.wy[qi]}, dz[1] = {q.wz[qi]};
+        hash_layer1_direction_f32<1>(h, sD, dx, dy, dz, lane, g);
+        relu_all<64, 1>(h);
+        hidden_layers<64, 1>(h, sH, lane);
+        f32x4 y[1];
+        output_layer<64, 1>(y, h, sO, lane);
+        // lanes 0..15 hold rows 0..2 (the three channels) of their column
+        if (g == 0 && (tile << 4) + col < Q) {
+            const int64_t qo = (tile << 4) + col;
+            rgb[3 * qo] = expf(y[0][0]);
+            rgb[3 * qo + 1] = expf(y[0][1]);
+            rgb[3 * qo + 2] = expf(y[0][2]);
+        }
+    }
+}
+
+hipError_t launch_hash_pack32(float *packed, const float *master, hipStream_t s) {
+    hipLaunchKernelGGL(k_hash_pack32, dim3((kHash32Packed + 255) / 256), dim3(256), 0, s, packed, master);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_infer32(const Points &pts, const Queries &q, const float *packed, const float *table,
+                               const HashGridArgs &grid, float *rgb, hipStream_t s) {
+    constexpr int WAVES = 4;
+    const unsigned nb = grid_for((q.count + 15) / 16, WAVES, 4 * kMaxResidentBlocks);
+    hipLaunchKernelGGL((k_hash_infer_f32<WAVES>), dim3(nb), dim3(WAVES * 64), 0, s, pts, q, packed,
+                       (const float2 *)table, grid, rgb);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_tlmc32(const Points &pts, const nirc_lobes &lobes, const float *packed, const float *table,
+                              const HashGridArgs &grid, int n_cache, uint64_t seed, uint64_t frame, const float *rrad,
+                              float *out_tl, float *out_c, float *out_r, hipStream_t s) {
+    constexpr int WAVES = 8;
+    const unsigned nb = grid_for((pts.count + 15) / 16, WAVES, 2 * kMaxResidentBlocks);
+    hipLaunchKernelGGL((k_hash_tlmc_f32<WAVES>), dim3(nb), dim3(WAVES * 64), 0, s, pts, lobes, packed,
+                       (const float2 *)table, grid, n_cache, make_divn(n_cache), (uint32_t)seed,
+                       (uint32_t)(seed >> 32), (uint32_t)frame, rrad, out_tl, out_c, out_r);
     return hipGetLastError();
 }
 

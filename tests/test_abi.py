@@ -80,7 +80,7 @@ def test_hash_configuration_checks():
     ok = nirc.make_config(precision=nirc.NIRC_BF16)
     assert L.nirc_hash_state_bytes(ctypes.byref(ok), ctypes.byref(g)) > 3 * 4 * nirc.nirc_hash_n_params(g)
     assert L.nirc_hash_workspace_bytes(ctypes.byref(ok), ctypes.byref(g), 65536) > 0
-    for bad in (nirc.make_config(), nirc.make_config(width=128, precision=1), nirc.make_config(precision=1, loss=2),
+    for bad in (nirc.make_config(width=128, precision=1), nirc.make_config(precision=1, loss=2),
                 nirc.make_config(precision=1, output=2)):
         assert L.nirc_hash_state_bytes(ctypes.byref(bad), ctypes.byref(g)) == 0
     h = ctypes.c_void_p()

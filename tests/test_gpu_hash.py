@@ -232,7 +232,7 @@ def test_hash_estimator_unbiased_over_seeds(nirc):
 def test_hash_rejects_unsupported_configurations(nirc):
     w = wl.make_hash_weights(1, 64, 2 * oracle.hash_entries(GRIDS["small"]))
     g = nirc.make_hash_grid(*GRIDS["small"])
-    for cfg in (nirc.make_config(precision=0), nirc.make_config(width=128, precision=1),
+    for cfg in (nirc.make_config(width=128, precision=1),
                 nirc.make_config(precision=1, loss=2), nirc.make_config(precision=1, output=1)):
         with pytest.raises(nirc.NircError):
             nirc.HashModel(w, cfg=cfg, grid=g, max_batch=0)
@@ -330,3 +330,57 @@ def test_hash_train_frame_matches_step_loop(nirc):
     wa, wb = host(a.get_weights()), host(b.get_weights())
     assert rel_l2(wa - w0, wb - w0) <= 2e-2
     assert np.isfinite(float(loss.item())) and float(loss.item()) > 0
+
+
+# FP32 hash-grid model (inference and estimation only; training runs in 16-bit): the FP32 bound of
+# the frequency model, 1e-5 (measured: outputs ~4e-8, F_c <= 2e-7, F_tl <= 3e-7 of |F_c|; a
+# position whose FP32 product with N_l rounds across a cell edge moves its grid value by at most
+# 2^-24 N_l of a cell times a corner difference, rare and continuous).
+HASH_F32_TOL = 1e-5
+
+
+@pytest.mark.parametrize("grid", ["default", "small"])
+@pytest.mark.parametrize("Q", [1, 1000, 4099])
+def test_hash_infer_fp32(nirc, grid, Q):
+    P = 700
+    pts = wl.make_points(62, P)
+    dp = nirc.Points.from_workload(pts)
+    w = wl.make_hash_weights(62, 64, 2 * oracle.hash_entries(GRIDS[grid]), 0.5)
+    model = nirc.HashModel(w, cfg=nirc.make_config(precision=0), grid=nirc.make_hash_grid(*GRIDS[grid]), max_batch=0)
+    g = torch.Generator().manual_seed(Q)
+    idx = torch.randint(0, P, (Q,), generator=g, dtype=torch.int32)
+    d = torch.randn(Q, 3, generator=g)
+    d = d / d.norm(dim=1, keepdim=True)
+    y = host(nirc.nirc_hash_infer(model, dp, nirc.Queries.from_dirs(d.cuda(), idx.cuda())))
+    ref = oracle.hash_infer(pts, idx.numpy(), d.double().numpy(), w, 64, GRIDS[grid])
+    e = rel_l2(y, ref)
+    print(f"hash infer fp32 {grid} Q={Q}: rel-L2 {e:.3e}", flush=True)
+    assert e <= HASH_F32_TOL
+
+
+@pytest.mark.parametrize("P,N", [(17, 3), (4096, 8), (1000, 16), (100, 64), (4001, 5)])
+def test_hash_estimate_fp32(nirc, P, N):
+    pts = wl.make_points(63, P)
+    lob = wl.make_lobes(63).packed()
+    dp = nirc.Points.from_workload(pts)
+    w = wl.make_hash_weights(63, 64, 2 * oracle.hash_entries(GRIDS["default"]), 0.5)
+    model = nirc.HashModel(w, cfg=nirc.make_config(precision=0), grid=nirc.make_hash_grid(*GRIDS["default"]),
+                           max_batch=0)
+    tl, c, r = (host(t) for t in nirc.nirc_hash_estimate(model, dp, lob, N, 9, 1, parts=True))
+    o_tl, o_c, o_r = oracle.hash_estimate(pts, lob, w, N, 9, 1)
+    print(f"hash estimate fp32 P={P} N={N}: F_c {rel_l2(c, o_c):.3e} F_tl {np.linalg.norm(tl - o_tl) / np.linalg.norm(o_c):.3e}",
+          flush=True)
+    assert rel_l2(c, o_c) <= HASH_F32_TOL
+    assert np.linalg.norm(tl - o_tl) <= HASH_F32_TOL * np.linalg.norm(o_c)
+    assert np.linalg.norm(r - o_r) <= HASH_F32_TOL * np.linalg.norm(o_c)
+
+
+def test_hash_fp32_training_is_unsupported(nirc):
+    w = wl.make_hash_weights(64, 64, 2 * oracle.hash_entries(GRIDS["small"]))
+    model = nirc.HashModel(w, cfg=nirc.make_config(precision=0), grid=nirc.make_hash_grid(*GRIDS["small"]),
+                           max_batch=64)
+    pts = wl.make_points(64, 64)
+    dp = nirc.Points.from_workload(pts)
+    sm = Samples(pts, wl.make_lobes(64).packed(), 64, 65, 0, 0)
+    with pytest.raises(nirc.NircError):
+        nirc.nirc_hash_train_step(model, dp, sm.queries(nirc), sm.target())
