@@ -428,15 +428,15 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
                      "mrse": float(st[4].item()), "mrse_cache_only": float(st[5].item()),
                      "cache_rel_l2": float((y - tgt).norm() / tgt.norm()), "flags": m.read_flags(),
                      "cache_rel_l2_by_frame": curve}
-    # the trained hash-grid cache in both 16-bit formats over the direction counts of the
-    # precision study: time, MFMA fraction and MRSE; FP16 against BF16 on the same parameters
+    # the trained hash-grid cache in FP32, BF16 and FP16 over the direction counts of the
+    # precision study: time, MFMA fraction and MRSE; 16-bit against FP32 on the same parameters
     hm = models["hash_grid_bf16"]
     wt = hm.get_weights()
     lob = nirc.lobes_struct(lobes_for(frames))
     sweep = []
     for Nq in (4, 16, 64):
         ref = None
-        for pname, prec in (("bf16", 1), ("fp16", 2)):
+        for pname, prec in (("fp32", 0), ("bf16", 1), ("fp16", 2)):
             mm = nirc.HashModel(wt, cfg=nirc.make_config(precision=prec), grid=grid, max_batch=0)
             out_t = torch.empty((P, 3), dtype=torch.float32, device="cuda")
             nirc.nirc_hash_estimate(mm, dp, lob, Nq, seed, frames, out=out_t)
@@ -449,12 +449,13 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
             ms = ev[0].elapsed_time(ev[1]) / 5
             flops = algorithmic_flops_hash(P, Nq)
             mrse = float(nirc.tlmc_frame_stats(dp, lob, table, out_t, fs=fs)[4].item())
+            peak = PEAK_FP32_MFMA if prec == 0 else PEAK_BF16_MFMA
             row = {"n_cache": Nq, "precision": pname, "ms_estimate": ms, "queries_per_s": P * (Nq + 1) / (ms * 1e-3),
-                   "mfma_frac": flops / (ms * 1e-3) / PEAK_BF16_MFMA, "mrse": mrse}
+                   "mfma_frac": flops / (ms * 1e-3) / peak, "mrse": mrse}
             if ref is None:
                 ref = out_t.clone()
             else:
-                row["rel_l2_vs_bf16"] = float((out_t - ref).norm() / ref.norm())
+                row["rel_l2_vs_fp32"] = float((out_t - ref).norm() / ref.norm())
             sweep.append(row)
             del mm
     out["hash_precision_sweep"] = sweep

@@ -382,8 +382,10 @@ nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_l
  * vector (FP32): W1 [64 x 64], W2, W3, W4 [64 x 64], W5 [3 x 64] (16,576 values), then the grid
  * features [entries][2] with the levels in order.  The grid and the MLP use one Adam state.
  * Supported: width 64, precision NIRC_BF16 or NIRC_FP16 (the layer products; grid features and
- * their interpolation stay FP32), loss NIRC_LOSS_REL_L2 or NIRC_LOSS_L2, output
- * NIRC_OUTPUT_RADIANCE; anything else is NIRC_ERR_UNSUPPORTED.  Conventions as above.
+ * their interpolation stay FP32), or NIRC_FP32 for inference and estimation only (its training
+ * calls return NIRC_ERR_UNSUPPORTED; train in 16-bit and load the parameters), loss
+ * NIRC_LOSS_REL_L2 or NIRC_LOSS_L2, output NIRC_OUTPUT_RADIANCE; anything else is
+ * NIRC_ERR_UNSUPPORTED.  Conventions as above.
  * ========================================================================================== */
 typedef struct nirc_hash_model nirc_hash_model;
 
