@@ -384,3 +384,38 @@ def test_hash_fp32_training_is_unsupported(nirc):
     sm = Samples(pts, wl.make_lobes(64).packed(), 64, 65, 0, 0)
     with pytest.raises(nirc.NircError):
         nirc.nirc_hash_train_step(model, dp, sm.queries(nirc), sm.target())
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_hash_grid_gradient_without_relu_decisions(nirc, prec):
+    # a network whose every pre-activation is positive (non-negative grid features and first-layer
+    # grid columns, a positive albedo bias, positive hidden weights, no direction or other surface
+    # columns) takes no ReLU decision that rounding could flip, so the grid-entry gradient (the
+    # TS product and the scatter) is held to the rounding bound entry by entry
+    print(f"hash grid gradient, positive network, {prec}", flush=True)
+    grid = GRIDS["default"]
+    rng = np.random.default_rng(70)
+    n_tab = 2 * oracle.hash_entries(grid)
+    W1 = np.zeros((64, 64))
+    W1[:, :24] = rng.uniform(0.0, 2.0 / 24, (64, 24))
+    W1[:, 60:63] = rng.uniform(0.1, 0.3, (64, 3))
+    hid = [rng.uniform(0.0, 2.0 / 64, (64, 64)) for _ in range(3)]
+    W5 = rng.uniform(-0.05, 0.05, (3, 64))
+    table = rng.uniform(0.0, 0.5, n_tab)
+    w = np.concatenate([W1.ravel()] + [h.ravel() for h in hid] + [W5.ravel(), table]).astype(np.float32)
+    P, B = 3000, 16384
+    pts = wl.make_points(71, P)
+    lob = wl.make_lobes(71).packed()
+    dp = nirc.Points.from_workload(pts)
+    model = nirc.HashModel(w, cfg=nirc.make_config(precision=PRECS[prec]), grid=nirc.make_hash_grid(*grid),
+                           max_batch=B)
+    sm = Samples(pts, lob, B, 72, 0, 0)
+    loss, grad = nirc.nirc_hash_loss_grad(model, dp, sm.queries(nirc), sm.target())
+    o_loss, o_grad = oracle.hash_loss_grad(pts, sm.idx, sm.d, sm.t, w.astype(np.float64), 64, grid)
+    g = host(grad)
+    nm = oracle.hash_mlp_params(64)
+    e_mlp = rel_l2(g[:nm], o_grad[:nm])
+    e_tab = rel_l2(g[nm:], o_grad[nm:])
+    print(f"  mlp {e_mlp:.3e}  grid {e_tab:.3e}", flush=True)
+    assert e_mlp <= GRAD_TOL[prec]
+    assert e_tab <= GRAD_TOL[prec]
