@@ -358,8 +358,8 @@ def algorithmic_flops_hash(P: int, N: int, W: int = 64) -> float:
 
 def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S, reps=20):
     """The paper's own cache input (hash grid on x, spherical harmonics of w, one-blob surface
-    values) against the frequency input, both BF16, trained online from their initial weights
-    over the same rotating frames: time per estimate (N + 1 queries per point) and per training
+    values) against the frequency input, both BF16, and the hash-grid cache trained and evaluated
+    in FP32, each trained online from its initial weights over the same rotating frames: time per estimate (N + 1 queries per point) and per training
     frame, and on the last frame the MRSE of the two-level estimate and of the cache level alone
     against the closed form, and the cache's relative L2 error on fresh samples (also before
     frames 0, 5, 10, 25 and 50, as a convergence curve)."""
@@ -370,7 +370,8 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
     grid = nirc.make_hash_grid()
     wh = wl.make_hash_weights(seed, 64, 2 * nirc.nirc_hash_entries(grid))
     models = {"frequency_bf16": nirc.Model(w0, cfg=nirc.make_config(precision=1), max_batch=B),
-              "hash_grid_bf16": nirc.HashModel(wh, cfg=nirc.make_config(precision=1), grid=grid, max_batch=B)}
+              "hash_grid_bf16": nirc.HashModel(wh, cfg=nirc.make_config(precision=1), grid=grid, max_batch=B),
+              "hash_grid_fp32": nirc.HashModel(wh, cfg=nirc.make_config(precision=0), grid=grid, max_batch=B)}
     out = {"grid": {"levels": 12, "features": 2, "log2_table": grid.log2_table, "base_res": grid.base_res,
                     "growth": grid.growth, "entries": nirc.nirc_hash_entries(grid),
                     "table_mb": 8 * nirc.nirc_hash_entries(grid) / 1e6}}
@@ -422,9 +423,10 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
         q, tgt = nirc.tlmc_train_batch(dp, lob, 65536, seed + 7919, frames, 0)
         y = nirc.nirc_hash_infer(m, dp, q) if is_hash else nirc.nirc_infer(m, dp, q)
         flops = algorithmic_flops_hash(P, N) if is_hash else algorithmic_flops_estimate(P, N, 64)
+        peak = PEAK_FP32_MFMA if name.endswith("fp32") else PEAK_BF16_MFMA
         out[name] = {"ms_estimate": ms, "queries_per_s": P * (N + 1) / (ms * 1e-3),
-                     "tflops": flops / (ms * 1e-3) / 1e12, "frac_bf16_peak": flops / (ms * 1e-3) / PEAK_BF16_MFMA,
-                     "flops_per_launch": flops, "ms_train_frame": t_train / frames,
+                     "tflops": flops / (ms * 1e-3) / 1e12, "mfma_frac": flops / (ms * 1e-3) / peak,
+                     "mfma_peak_tflops": peak / 1e12, "flops_per_launch": flops, "ms_train_frame": t_train / frames,
                      "mrse": float(st[4].item()), "mrse_cache_only": float(st[5].item()),
                      "cache_rel_l2": float((y - tgt).norm() / tgt.norm()), "flags": m.read_flags(),
                      "cache_rel_l2_by_frame": curve}
@@ -524,7 +526,7 @@ def main():
     ap.add_argument("--workload", default="1080p_n16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-compare", action="store_true")
-    ap.add_argument("--train-only", choices=["fp32", "bf16", "hash-bf16"], default=None,
+    ap.add_argument("--train-only", choices=["fp32", "bf16", "hash-bf16", "hash-fp32"], default=None,
                     help="only time training frames (S steps of B samples) of this model")
     ap.add_argument("--estimate-only", choices=["fp32", "bf16", "fp16", "hash-bf16"], default=None,
                     help="time only tlmc_estimate at this precision (for profiling runs)")
@@ -581,10 +583,11 @@ def main():
         return lobes_frames[f]
 
     if args.train_only:
-        if args.train_only == "hash-bf16":
+        if args.train_only.startswith("hash-"):
             grid = nirc.make_hash_grid()
             m = nirc.HashModel(wl.make_hash_weights(seed, 64, 2 * nirc.nirc_hash_entries(grid)),
-                               cfg=nirc.make_config(precision=1), grid=grid, max_batch=B)
+                               cfg=nirc.make_config(precision=1 if args.train_only == "hash-bf16" else 0), grid=grid,
+                               max_batch=B)
 
             def train(f):
                 nirc.nirc_hash_train_frame(m, dp, nirc.lobes_struct(lobes_for(f)), B, S, seed, f)

@@ -381,11 +381,10 @@ nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_l
  * Network: 64 -> 4 hidden ReLU layers of width 64 -> 3 -> exp, no biases.  Canonical parameter
  * vector (FP32): W1 [64 x 64], W2, W3, W4 [64 x 64], W5 [3 x 64] (16,576 values), then the grid
  * features [entries][2] with the levels in order.  The grid and the MLP use one Adam state.
- * Supported: width 64, precision NIRC_BF16 or NIRC_FP16 (the layer products; grid features and
- * their interpolation stay FP32), or NIRC_FP32 for inference and estimation only (its training
- * calls return NIRC_ERR_UNSUPPORTED; train in 16-bit and load the parameters), loss
- * NIRC_LOSS_REL_L2 or NIRC_LOSS_L2, output NIRC_OUTPUT_RADIANCE; anything else is
- * NIRC_ERR_UNSUPPORTED.  Conventions as above.
+ * Supported: width 64, precision NIRC_FP32, NIRC_BF16 or NIRC_FP16 (the layer products; grid
+ * features and their interpolation stay FP32 in every precision), for inference, estimation and
+ * training alike, loss NIRC_LOSS_REL_L2 or NIRC_LOSS_L2, output NIRC_OUTPUT_RADIANCE; anything
+ * else is NIRC_ERR_UNSUPPORTED.  Conventions as above.
  * ========================================================================================== */
 typedef struct nirc_hash_model nirc_hash_model;
 
@@ -406,8 +405,9 @@ int64_t nirc_hash_n_params(const nirc_hash_grid *grid);
 /* Resolution, first entry and dense flag (1/0) of the 12 levels, host arrays of 12. */
 nirc_status nirc_hash_levels(const nirc_hash_grid *grid, int32_t *res, int64_t *offset, int32_t *dense);
 
-/* Bytes of model state (FP32 parameters, Adam moments, 16-bit packed layers, step, flags) and
- * of training workspace for batches up to max_batch (0 for an invalid configuration). */
+/* Bytes of model state (FP32 parameters, Adam moments, packed layers in the model's precision,
+ * step, flags) and of training workspace for batches up to max_batch (0 for an invalid
+ * configuration). */
 size_t nirc_hash_state_bytes(const nirc_config *cfg, const nirc_hash_grid *grid);
 size_t nirc_hash_workspace_bytes(const nirc_config *cfg, const nirc_hash_grid *grid, int64_t max_batch);
 

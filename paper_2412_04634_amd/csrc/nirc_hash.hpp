@@ -350,7 +350,16 @@ __device__ __forceinline__ void stage_levels(HashLevel *slv, const HashGridArgs 
 constexpr int kHash32S = 4 * 12 * 64;
 constexpr int kHash32D = 4 * 8 * 64;
 constexpr int kHash32Rest = F32Layout{64}.offset(SEC_T0) - F32Layout{64}.offset(SEC_H0);   // H0..H2, O
-constexpr int kHash32Packed = kHash32S + kHash32D + kHash32Rest;
+// training sections after the inference ones: T0..T2 and OT as in the frequency model's FP32
+// layout, then TS32 (W1's grid columns transposed: rows = grid inputs in 2 row tiles, K = neurons
+// in the FP32 chained order, 16 K-steps)
+constexpr int kHash32T = F32Layout{64}.offset(SEC_N) - F32Layout{64}.offset(SEC_T0);
+constexpr int kHash32TS = kHash32S + kHash32D + kHash32Rest + kHash32T;
+constexpr int kHash32Packed = kHash32TS + 2 * 16 * 64;
+// offset of a frequency-layout FP32 section (SEC_H0 and later) inside the hash FP32 layout
+__host__ __device__ constexpr int hash_sec32(int s) {
+    return kHash32S + kHash32D + F32Layout{64}.offset(s) - F32Layout{64}.offset(SEC_H0);
+}
 
 __host__ __device__ inline int64_t hash_packed_source32(int e) {
     if (e < kHash32S + kHash32D) {
@@ -370,19 +379,27 @@ __host__ __device__ inline int64_t hash_packed_source32(int e) {
         }
         return in < 0 ? -1 : (int64_t)row * kHashIn + in;
     }
-    if (e < kHash32Packed) {
+    if (e < kHash32TS) {
         const int64_t s = f32_packed_source(64, e - kHash32S - kHash32D + F32Layout{64}.offset(SEC_H0));
         return s < 0 ? -1 : s - kHashCanonShift;
+    }
+    if (e < kHash32Packed) {
+        const int r = e - kHash32TS;
+        const int kk = r & 3, lane = (r >> 2) & 63, rest = r >> 8;   // rest = mt * 4 + kq
+        const int kq = rest % 4, m = rest / 4;
+        const int kb = 4 * kq + kk, row = 16 * m + (lane & 15), g = lane >> 4;
+        return row < 24 ? (int64_t)chained_neuron(kb, g) * kHashIn + row : -1;
     }
     return -1;
 }
 
 // phi[4j + g], j = 0..3, for lane group g (normal, one-blob bins, albedo 1, zero slot, pad).
-__device__ __forceinline__ void hash_phi4(const float xs[7], int g, float (&ph)[4]) {
+// (The surface values come in as scalars so that the normal's selection stays a select of values.)
+__device__ __forceinline__ void hash_phi4(float nx, float ny, float nz, float rough, int g, float (&ph)[4]) {
     // bins needed: g < 3: g + 1 and g + 5; g = 3: 4 and 0
     const float ia = g < 3 ? (float)(g + 1) : 4.0f, ib = g < 3 ? (float)(g + 5) : 0.0f;
-    const float ea = oneblob_bin(xs[6], ia), eb = oneblob_bin(xs[6], ib);
-    const float nrm = g == 0 ? xs[3] : g == 1 ? xs[4] : xs[5];
+    const float ea = oneblob_bin(rough, ia), eb = oneblob_bin(rough, ib);
+    const float nrm = g == 0 ? nx : g == 1 ? ny : nz;
     ph[0] = g < 3 ? nrm : eb;                  // phi[g]: normal, or bin 0
     ph[1] = ea;                                // phi[4 + g]: bins 1..4
     ph[2] = g < 3 ? eb : 1.0f;                 // phi[8 + g]: bins 5..7, albedo
@@ -444,7 +461,11 @@ __device__ __forceinline__ void hash_layer1_direction_f32(f32x4 (&h)[T][4], cons
 // Launchers (host).
 hipError_t launch_hash_pack16(uint16_t *packed, const float *master, int prec, hipStream_t s, int64_t *step = nullptr,
                               uint32_t *flags = nullptr, uint32_t *bad = nullptr);
-hipError_t launch_hash_pack32(float *packed, const float *master, hipStream_t s);
+hipError_t launch_hash_pack32(float *packed, const float *master, hipStream_t s, int64_t *step = nullptr,
+                              uint32_t *flags = nullptr, uint32_t *bad = nullptr);
+hipError_t launch_hash_grad32(const Points &pts, const Queries &q, const float *packed, const float *table,
+                              const HashGridArgs &grid, TrainArgs a, float *partials, float *loss_partials,
+                              float *gtab, int nblocks, hipStream_t s);
 hipError_t launch_hash_infer32(const Points &pts, const Queries &q, const float *packed, const float *table,
                                const HashGridArgs &grid, float *rgb, hipStream_t s);
 hipError_t launch_hash_tlmc32(const Points &pts, const nirc_lobes &lobes, const float *packed, const float *table,

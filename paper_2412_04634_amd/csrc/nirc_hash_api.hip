@@ -252,7 +252,6 @@ nirc_status nirc_hash_estimate(const nirc_hash_model *model, nirc_points points,
 // Loss and gradient into grad/loss; the step's `bad` flag is raised on a non-finite value.
 static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &points, const nirc_queries &queries,
                                   const float *target, float *grad, float *loss, hipStream_t s) {
-    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;   // training runs in 16-bit
     nirc_status st = check_points_h(points);
     if (st == NIRC_OK) st = check_queries_h(queries, points);
     if (st != NIRC_OK) return st;
@@ -263,15 +262,18 @@ static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &poi
     float *partials = (float *)(model->ws + wl.partials);
     float *lpart = (float *)(model->ws + wl.loss_partials);
     // the batch size is folded into the loss scale (per-sample deltas near unit magnitude in the
-    // 16-bit operands); the reductions divide it out again
+    // 16-bit operands; the FP32 kernel takes the same convention); the reductions divide it out again
     const float scale = model->cfg.loss_scale * (float)queries.count;
     const TrainArgs a{target, nullptr, model->cfg.loss_eps, scale, model->cfg.loss, nullptr, 0};
     const int64_t nt = model->np - kHashMlp;
     float *gtab = grad + kHashMlp;
     hipError_t e = launch_fill_u32((uint32_t *)gtab, nt, 0u, s);
     if (e == hipSuccess)
-        e = launch_hash_grad(model->cfg.precision, pts_of(points), queries_of(queries), model->packed16,
-                             model->table(), model->grid, a, partials, lpart, gtab, nb, s);
+        e = model->cfg.precision == NIRC_FP32
+                ? launch_hash_grad32(pts_of(points), queries_of(queries), model->packed32(), model->table(),
+                                     model->grid, a, partials, lpart, gtab, nb, s)
+                : launch_hash_grad(model->cfg.precision, pts_of(points), queries_of(queries), model->packed16,
+                                   model->table(), model->grid, a, partials, lpart, gtab, nb, s);
     if (e == hipSuccess)
         e = launch_reduce_grad_n(kHashMlp, partials, lpart, nb, 1.0f / scale, 1.0f / (3.0f * (float)queries.count),
                                  grad, loss, model->bad, s);
@@ -280,12 +282,13 @@ static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &poi
 }
 
 static hipError_t hash_adam(nirc_hash_model *model, const float *grad, hipStream_t s) {
-    if (model->cfg.precision == NIRC_FP32) return hipErrorNotSupported;
     hipError_t e = launch_adam_n(model->np, model->master, model->m, model->v, grad, model->step, model->bad,
                                  model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps, s);
     if (e == hipSuccess)
-        e = launch_hash_pack16(model->packed16, model->master, model->cfg.precision, s, model->step, model->flags,
-                               model->bad);
+        e = model->cfg.precision == NIRC_FP32
+                ? launch_hash_pack32(model->packed32(), model->master, s, model->step, model->flags, model->bad)
+                : launch_hash_pack16(model->packed16, model->master, model->cfg.precision, s, model->step,
+                                     model->flags, model->bad);
     return e;
 }
 
@@ -301,7 +304,6 @@ nirc_status nirc_hash_loss_grad(nirc_hash_model *model, nirc_points points, nirc
 
 nirc_status nirc_hash_adam_step(nirc_hash_model *model, const float *grad, void *stream) {
     if (!model || !grad) return NIRC_ERR_INVALID_ARG;
-    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_check_finite_n(model->np, grad, model->bad, s);
     if (e == hipSuccess) e = hash_adam(model, grad, s);
@@ -311,7 +313,6 @@ nirc_status nirc_hash_adam_step(nirc_hash_model *model, const float *grad, void 
 nirc_status nirc_hash_train_step(nirc_hash_model *model, nirc_points points, nirc_queries queries,
                                  const float *target, float *loss, void *stream) {
     if (!model) return NIRC_ERR_INVALID_ARG;
-    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (!model->ws) return NIRC_ERR_WORKSPACE;
     const HashWork wl(model->np, train_blocks16(queries.count > 0 ? queries.count : 1));
@@ -326,7 +327,6 @@ nirc_status nirc_hash_train_frame(nirc_hash_model *model, nirc_points points, co
                                   int64_t batch, int32_t steps, uint64_t seed, uint64_t frame, float *loss,
                                   void *stream) {
     if (!model || !field || batch < 1 || batch > INT32_MAX || steps < 0) return NIRC_ERR_INVALID_ARG;
-    if (model->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
     nirc_status st = check_points_h(points);
     if (st != NIRC_OK || points.count < 1) return NIRC_ERR_INVALID_ARG;
     const HashWork wl(model->np, train_blocks16(batch), batch);

@@ -353,7 +353,7 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
             static_assert(W == 64, "the hash-grid model has width 64");
             float v[6], ph[4];
             hash_values6(slv, tmask, table, xs[0], xs[1], xs[2], g, v);
-            hash_phi4(xs, g, ph);
+            hash_phi4(xs[3], xs[4], xs[5], xs[6], g, ph);
             hash_layer1_surface_f32(hsum, opaque(gS), v, ph, lane);
         } else {
             layer1_surface<W>(hsum, opaque(gS), xs, lane, g);
@@ -581,11 +581,17 @@ hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lob
 // ------------------------------------------------------------------------------------------
 // The hash-grid model in FP32 (inference and estimation).
 
-__global__ void k_hash_pack32(float *packed, const float *master) {
+// After an Adam step (step != NULL) thread 0 also commits the step or records its skip.
+__global__ void k_hash_pack32(float *packed, const float *master, int64_t *step, uint32_t *flags, uint32_t *bad) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < kHash32Packed) {
         const int64_t s = hash_packed_source32(e);
         packed[e] = s >= 0 ? master[s] : 0.0f;
+    }
+    if (step && e == 0) {
+        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        else *step += 1;
+        *bad = 0u;
     }
 }
 
@@ -653,7 +659,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_hash_infer_f32(Points pts, Queri
         for (int mt = 0; mt < 4; ++mt) h[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
         float v[6], ph[4];
         hash_values6(s_lv, grid.tmask, table, xs[0], xs[1], xs[2], g, v);
-        hash_phi4(xs, g, ph);
+        hash_phi4(xs[3], xs[4], xs[5], xs[6], g, ph);
         hash_layer1_surface_f32(h[0], opaque(packed), v, ph, lane);
         const float dx[1] = {q.wx[qi]}, dy[1] = {q.wy[qi]}, dz[1] = {q.wz[qi]};
         hash_layer1_direction_f32<1>(h, sD, dx, dy, dz, lane, g);
@@ -671,8 +677,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_hash_infer_f32(Points pts, Queri
     }
 }
 
-hipError_t launch_hash_pack32(float *packed, const float *master, hipStream_t s) {
-    hipLaunchKernelGGL(k_hash_pack32, dim3((kHash32Packed + 255) / 256), dim3(256), 0, s, packed, master);
+hipError_t launch_hash_pack32(float *packed, const float *master, hipStream_t s, int64_t *step, uint32_t *flags,
+                              uint32_t *bad) {
+    hipLaunchKernelGGL(k_hash_pack32, dim3((kHash32Packed + 255) / 256), dim3(256), 0, s, packed, master, step, flags,
+                       bad);
     return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 // Training kernels: fused forward + relative-L2 loss + backward to per-workgroup weight-gradient
 // partials, a fixed-order reduction, and Adam with a refresh of the packed weights.
-#include "nirc_kernels.hpp"
+#include "nirc_hash.hpp"
 
 namespace nirc {
 
@@ -796,6 +796,322 @@ __global__ void k_scale_check(float *__restrict__ g, int64_t n, float scale, uin
 
 hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, n, scale, bad);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// The hash-grid model in FP32 (width 64): k_grad_f32's two phases with the 64 grid / SH / phi
+// inputs staged as rows [canonical input][sample] for the first layer's weight gradient.  Each
+// sample's gradient with respect to its 24 grid values (W1_grid^T delta1, from the transposed
+// TS32 section) is kept in registers through phase 2 and then scattered into the grid-entry
+// gradient by FP32 atomic adds (the 16 values of one (sample, level) in 16 consecutive lanes, x
+// neighbours in adjacent lane pairs, zero values skipped), staged through LDS that phase 2 has
+// released.
+namespace {
+constexpr int kScatRow32 = 28;   // per sample: 24 grid-value gradients, position, pad
+struct HashGrad32Lds {
+    static constexpr int kH = 4 * 64 * kStride;
+    static constexpr int kD = 4 * 64 * kStride;
+    static constexpr int kD5 = 4 * kStride;
+    static constexpr int kE = kHashIn * kStride;
+    static constexpr int kTotal = kH + kD + kD5 + kE;
+    static_assert(kTrainWaves * 16 * kScatRow32 <= kH, "scatter staging reuses the activation rows");
+};
+}  // namespace
+
+__global__ __launch_bounds__(kTrainWaves * 64) void k_hash_grad_f32(Points pts, Queries q,
+                                                                    const float *__restrict__ packed,
+                                                                    const float2 *__restrict__ table,
+                                                                    HashGridArgs grid, TrainArgs args,
+                                                                    float *__restrict__ partials,
+                                                                    float *__restrict__ loss_partials,
+                                                                    float *__restrict__ gtab) {
+    constexpr int W = 64, MT = 4, KQ = 4;
+    using S = HashGrad32Lds;
+    __shared__ f32x4 smem4[(S::kTotal + 3) / 4];
+    __shared__ float sLoss[kTrainWaves];
+    __shared__ HashLevel s_lv[kHashLevels];
+    float *smem = (float *)smem4;
+    float *sH = smem;
+    float *sD = sH + S::kH;
+    float *sD5 = sD + S::kD;
+    float *sE = sD5 + S::kD5;
+    stage_levels(s_lv, grid);
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
+    const int64_t B = q.count;
+    const bool rel = args.loss_kind == NIRC_LOSS_REL_L2;
+    // the host passes loss_scale * B: k = 2 loss_scale / 3 per sample
+    const float kscale = 2.0f * args.loss_scale / (3.0f * (float)B);
+
+    f32x4 g1[MT], gh[3][MT], g5;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        g1[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gh[a][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    g5 = f32x4{0.f, 0.f, 0.f, 0.f};
+    float loss_acc = 0.0f;
+
+    const int64_t n_chunks = (B + kChunk - 1) / kChunk;
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        // ---------------- phase 1: forward + backward of this wave's 16 samples
+        f32x4 de[2];   // rows 16 m + 4 g + i of W1_grid^T delta1 (grid values 2 k + f of level k)
+        float x0, x1, x2;
+        bool valid;
+        {
+            const float *pk = opaque(packed);
+            const int s = 16 * wave + col;
+            const int64_t b = chunk * kChunk + s;
+            valid = b < B;
+            const int64_t bi = valid ? b : B - 1;
+            const int64_t p = query_point(q, pts, bi);
+            const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
+            x0 = xs[0];
+            x1 = xs[1];
+            x2 = xs[2];
+            float v[6], ph[4], sd[8];
+            hash_values6(s_lv, grid.tmask, table, xs[0], xs[1], xs[2], g, v);
+            hash_phi4(xs[3], xs[4], xs[5], xs[6], g, ph);
+            hash_dir_values_f32(q.wx[bi], q.wy[bi], q.wz[bi], g, sd);
+            // canonical input rows: grid 6 g + k, SH 24 + 4 k + g, phi 49 + 4 j + g
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sE[(6 * g + k) * kStride + s] = v[k];
+#pragma unroll
+            for (int k = 0; k < 7; ++k)
+                if (4 * k + g < 25) sE[(24 + 4 * k + g) * kStride + s] = sd[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * j + g < 15) sE[(49 + 4 * j + g) * kStride + s] = ph[j];
+
+            f32x4 h[4][MT];
+            {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) h[0][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                hash_layer1_surface_f32(h[0], pk, v, ph, lane);
+                const float *gD = pk + kHash32S;
+#pragma unroll
+                for (int kq = 0; kq < 2; ++kq) {
+                    f32x4 a[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(gD + ((mt * 2 + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) h[0][mt] = mfma4(a[mt][kk], sd[4 * kq + kk], h[0][mt]);
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) h[0][mt][i] = relu_f32(h[0][mt][i]);
+            }
+#pragma unroll
+            for (int l = 1; l < 4; ++l) {
+                const float *sec = pk + hash_sec32(SEC_H0 + (l - 1));
+                f32x4 o[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    f32x4 a[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sec + ((mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) o[mt] = mfma4(a[mt][kk], h[l - 1][kq][kk], o[mt]);
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) h[l][mt][i] = relu_f32(o[mt][i]);
+            }
+            f32x4 z5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            {
+                const float *sec = pk + hash_sec32(SEC_O);
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    const f32x4 a = *(const f32x4 *)(sec + (kq * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) z5 = mfma4(a[kk], h[3][kq][kk], z5);
+                }
+            }
+            f32x4 d5 = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (g == 0 && valid) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float lt;
+                    d5[c] = out_grad(z5[c], args.target[3 * b + c], 0.0f, true, args.loss_eps, kscale, rel, 0.0f,
+                                     false, lt);
+                    loss_acc += lt;
+                }
+            }
+            if (g == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sD5[c * kStride + s] = d5[c];
+            }
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        sH[(l * W + 16 * mt + 4 * g + i) * kStride + s] = h[l][mt][i];
+            f32x4 d[MT];
+            {
+                const float *sec = pk + hash_sec32(SEC_OT);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const f32x4 a = *(const f32x4 *)(sec + (mt * 64 + lane) * 4);
+                    f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) o = mfma4(a[kk], d5[kk], o);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) d[mt][i] = h[3][mt][i] > 0.0f ? o[i] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sD[(3 * W + 16 * mt + 4 * g + i) * kStride + s] = d[mt][i];
+#pragma unroll
+            for (int l = 3; l >= 1; --l) {
+                const float *sec = pk + hash_sec32(SEC_T0 + (l - 1));
+                f32x4 o[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) o[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    f32x4 a[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) a[mt] = *(const f32x4 *)(sec + ((mt * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) o[mt] = mfma4(a[mt][kk], d[kq][kk], o[mt]);
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        d[mt][i] = h[l - 1][mt][i] > 0.0f ? o[mt][i] : 0.0f;
+                        sD[((l - 1) * W + 16 * mt + 4 * g + i) * kStride + s] = d[mt][i];
+                    }
+            }
+            // d = delta1; the grid-value gradient of this sample (column col)
+            const float *sec = pk + kHash32TS;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                de[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kq = 0; kq < KQ; ++kq) {
+                    const f32x4 a = *(const f32x4 *)(sec + ((m * KQ + kq) * 64 + lane) * 4);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) de[m] = mfma4(a[kk], d[kq][kk], de[m]);
+                }
+            }
+        }
+        __syncthreads();
+        // ---------------- phase 2: owned weight-gradient tiles (W1: inputs 16 wave .. 16 wave + 15)
+#pragma unroll 1
+        for (int sq = 0; sq < kChunk / 16; ++sq) {
+            const int s0 = 16 * sq + 4 * g;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const f32x4 bv = *(const f32x4 *)(sH + (a * W + 16 * wave + col) * kStride + s0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const f32x4 av = *(const f32x4 *)(sD + ((a + 1) * W + 16 * mt + col) * kStride + s0);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) gh[a][mt] = mfma4(av[kk], bv[kk], gh[a][mt]);
+                }
+            }
+            {
+                const f32x4 bv = *(const f32x4 *)(sH + (3 * W + 16 * wave + col) * kStride + s0);
+                f32x4 av = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (col < 3) av = *(const f32x4 *)(sD5 + col * kStride + s0);
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) g5 = mfma4(av[kk], bv[kk], g5);
+            }
+            {
+                const f32x4 bv = *(const f32x4 *)(sE + (16 * wave + col) * kStride + s0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const f32x4 av = *(const f32x4 *)(sD + (16 * mt + col) * kStride + s0);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) g1[mt] = mfma4(av[kk], bv[kk], g1[mt]);
+                }
+            }
+        }
+        __syncthreads();
+        // ---------------- scatter of the grid-value gradients (staging in the released rows)
+        {
+            float *sg = smem + wave * (16 * kScatRow32);
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 16 * m + 4 * g + i;
+                    if (k < 24) sg[col * kScatRow32 + k] = valid ? de[m][i] : 0.0f;
+                }
+            if (g == 0) {
+                sg[col * kScatRow32 + 24] = x0;
+                sg[col * kScatRow32 + 25] = x1;
+                sg[col * kScatRow32 + 26] = x2;
+            }
+            wave_sync();
+            const int qd = lane >> 4, corner = (lane & 15) >> 1, f = lane & 1;
+#pragma unroll 4
+            for (int it = 0; it < 16 * kHashLevels / 4; ++it) {
+                const int pr = 4 * it + qd;
+                const int smp = pr / kHashLevels, level = pr - kHashLevels * smp;
+                const float *row = sg + smp * kScatRow32;
+                const float dv = row[2 * level + f];
+                const HashLevel lv = s_lv[level];
+                const HashCell cell = hash_cell(row[24], row[25], row[26], lv.res);
+                float w;
+                const uint32_t e = hash_entry(lv, grid.tmask, cell, corner, w);
+                if (dv != 0.0f) unsafeAtomicAdd(gtab + 2 * (size_t)e + f, w * dv);
+            }
+        }
+        __syncthreads();   // the next chunk's rows overwrite the staging
+    }
+
+    float *out = partials + (int64_t)blockIdx.x * kHashMlp;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[(int64_t)(16 * mt + 4 * g + i) * kHashIn + 16 * wave + col] = g1[mt][i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[W * kHashIn + a * W * W + (int64_t)(16 * mt + 4 * g + i) * W + 16 * wave + col] = gh[a][mt][i];
+    if (g == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[W * kHashIn + 3 * W * W + (int64_t)i * W + 16 * wave + col] = g5[i];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) loss_acc += __shfl_xor(loss_acc, d, 64);
+    if (lane == 0) sLoss[wave] = loss_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kTrainWaves; ++w) t += sLoss[w];
+        loss_partials[blockIdx.x] = t;
+    }
+}
+
+hipError_t launch_hash_grad32(const Points &pts, const Queries &q, const float *packed, const float *table,
+                              const HashGridArgs &grid, TrainArgs a, float *partials, float *loss_partials,
+                              float *gtab, int nblocks, hipStream_t s) {
+    if (!a.target) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_hash_grad_f32, dim3(nblocks), dim3(kTrainWaves * 64), 0, s, pts, q, packed,
+                       (const float2 *)table, grid, a, partials, loss_partials, gtab);
     return hipGetLastError();
 }
 

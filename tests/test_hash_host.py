@@ -65,6 +65,19 @@ def test_hash_packed_layout_covers_parameters(tmp_path):
     ts = ts[ts >= 0]
     assert sorted(ts.tolist()) == sorted(r * nin + c for r in range(W) for c in range(24))
     assert secT0 > rest
+    # FP32 layout: surface + direction sections hold W1 once, the hidden sections W2..W4 twice
+    # (forward and transposed) and W5 in O and OT, the TS32 section W1's grid columns once
+    total32, rest32, ts32 = (int(v) for v in lines[total + 1].split())
+    src32 = np.array([int(v) for v in lines[total + 2:total + 2 + total32]])
+    s1 = src32[:rest32]
+    assert sorted(s1[s1 >= 0].tolist()) == list(range(w1))
+    h = src32[rest32:ts32]
+    counts = np.bincount(h[h >= 0], minlength=w1 + 3 * W * W + 3 * W)
+    assert (counts[:w1] == 0).all()
+    assert (counts[w1:w1 + 3 * W * W] == 2).all()
+    assert (counts[w1 + 3 * W * W:] >= 2).all()
+    ts = src32[ts32:]
+    assert sorted(ts[ts >= 0].tolist()) == sorted(r * nin + c for r in range(W) for c in range(24))
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
