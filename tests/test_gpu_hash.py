@@ -267,7 +267,8 @@ def test_hash_empty_inputs(nirc):
     torch.cuda.synchronize()
 
 
-def test_hash_checkpoint_resume(nirc):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_hash_checkpoint_resume(nirc, prec):
     # a restored checkpoint is the saved state bit for bit (and answers identically); training on
     # from it follows the original's updates (the grid gradient's atomic sums make the two runs
     # agree to rounding, not bit for bit)
@@ -275,8 +276,8 @@ def test_hash_checkpoint_resume(nirc):
     pts = wl.make_points(56, P)
     lob = wl.make_lobes(56).packed()
     dp = nirc.Points.from_workload(pts)
-    a, _ = _model(nirc, "bf16", GRIDS["small"], 56, max_batch=B, scale=1e-4)
-    b, _ = _model(nirc, "bf16", GRIDS["small"], 57, max_batch=B, scale=1e-4)
+    a, _ = _model(nirc, prec, GRIDS["small"], 56, max_batch=B, scale=1e-4)
+    b, _ = _model(nirc, prec, GRIDS["small"], 57, max_batch=B, scale=1e-4)
 
     def frames(m, f0):
         for f in range(f0, f0 + 2):
@@ -299,30 +300,45 @@ def test_hash_checkpoint_resume(nirc):
     assert a.read_flags() == 0 and b.read_flags() == 0
 
 
-def test_hash_positions_outside_the_unit_cube(nirc):
-    # positions are clamped to the grid's domain on both sides: points scattered over [-0.25, 1.25]^3
-    P, N = 1000, 8
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_hash_positions_outside_the_unit_cube(nirc, prec):
+    # positions are clamped to the grid's domain on both sides: points scattered over [-0.25, 1.25]^3,
+    # in the estimate and in the gradient (whose scatter then lands on the cube's faces)
+    P, N, B = 1000, 8, 4096
     pts = wl.make_points(59, P)
     for a in (pts.px, pts.py, pts.pz):
         a[:] = (a * 1.5 - 0.25).astype(np.float32)
     lob = wl.make_lobes(59).packed()
     dp = nirc.Points.from_workload(pts)
-    model, w = _model(nirc, "fp16", GRIDS["default"], 59)
+    model, w = _model(nirc, prec, GRIDS["default"], 59, max_batch=B)
     tl, c, r = (host(t) for t in nirc.nirc_hash_estimate(model, dp, lob, N, 5, 0, parts=True))
     o_tl, o_c, o_r = oracle.hash_estimate(pts, lob, w, N, 5, 0)
-    assert rel_l2(c, o_c) <= 1e-2
+    assert rel_l2(c, o_c) <= (HASH_F32_TOL if prec == "fp32" else 1e-2)
     assert np.isfinite(tl).all()
+    sm = Samples(pts, lob, B, 69, 0, 0)
+    _, grad = nirc.nirc_hash_loss_grad(model, dp, sm.queries(nirc), sm.target())
+    g = host(grad)
+    w64 = w.astype(np.float64)
+    _, o_grad = oracle.hash_loss_grad(pts, sm.idx, sm.d, sm.t, w64, 64, GRIDS["default"],
+                                      mask_prec=PRECS[prec])
+    nm = oracle.hash_mlp_params(64)
+    e_mlp, e_tab = rel_l2(g[:nm], o_grad[:nm]), rel_l2(g[nm:], o_grad[nm:])
+    print(f"hash outside the cube {prec}: F_c {rel_l2(c, o_c):.3e} mlp {e_mlp:.3e} grid {e_tab:.3e}", flush=True)
+    assert e_mlp <= GRAD_TOL[prec]
+    assert e_tab <= (HASH_F32_GRID_TOL if prec == "fp32" else GRID_TOL)
+    assert np.all(g[nm:][o_grad[nm:] == 0.0] == 0.0)
 
 
-def test_hash_train_frame_matches_step_loop(nirc):
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_hash_train_frame_matches_step_loop(nirc, prec):
     # the native frame loop (samples generated into the workspace) against the same steps called
     # one by one; the grid gradient's atomic sums make them agree to rounding
     P, B = 4096, 2048
     pts = wl.make_points(60, P)
     lob = wl.make_lobes(60).packed()
     dp = nirc.Points.from_workload(pts)
-    a, w = _model(nirc, "bf16", GRIDS["small"], 60, max_batch=B, scale=1e-4)
-    b, _ = _model(nirc, "bf16", GRIDS["small"], 60, max_batch=B, scale=1e-4)
+    a, w = _model(nirc, prec, GRIDS["small"], 60, max_batch=B, scale=1e-4)
+    b, _ = _model(nirc, prec, GRIDS["small"], 60, max_batch=B, scale=1e-4)
     loss = torch.zeros(1, device="cuda")
     for f in range(2):
         nirc.nirc_hash_train_frame(a, dp, lob, B, 3, 61, f, loss)
