@@ -777,10 +777,52 @@ hipError_t launch_check_finite_n(int64_t np, const float *grad, uint32_t *bad, h
     return hipGetLastError();
 }
 
+// k_adam over four consecutive elements per thread with 16-byte loads and stores (the long
+// parameter vectors of the hash-grid model: one streaming pass over w, m, v and the gradient);
+// the same arithmetic per element, and element by element in a ragged last group.
+__global__ void k_adam4(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                        const float *__restrict__ grad, const int64_t *step, const uint32_t *bad, int64_t np,
+                        float lr, float b1, float b2, float eps) {
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 >= np || *bad) return;
+    const float t = (float)(*step + 1);
+    const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
+    if (i0 + 4 <= np) {
+        const f32x4 g4 = *(const f32x4 *)(grad + i0);
+        f32x4 m4 = *(const f32x4 *)(m + i0), v4 = *(const f32x4 *)(v + i0), w4 = *(const f32x4 *)(w + i0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            m4[k] = b1 * m4[k] + (1.0f - b1) * g4[k];
+            v4[k] = b2 * v4[k] + (1.0f - b2) * g4[k] * g4[k];
+            w4[k] -= lr * (m4[k] / c1) / (sqrtf(v4[k] / c2) + eps);
+        }
+        *(f32x4 *)(m + i0) = m4;
+        *(f32x4 *)(v + i0) = v4;
+        *(f32x4 *)(w + i0) = w4;
+        return;
+    }
+    for (int64_t i = i0; i < np; ++i) {
+        const float gi = grad[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 hipError_t launch_adam_n(int64_t np, float *master, float *m, float *v, const float *grad, const int64_t *step,
                          const uint32_t *bad, float lr, float b1, float b2, float eps, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad, step, bad, np,
-                       lr, b1, b2, eps);
+    if (aligned16(master) && aligned16(m) && aligned16(v) && aligned16(grad)) {
+        const int64_t groups = (np + 3) / 4;
+        hipLaunchKernelGGL(k_adam4, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, master, m, v, grad, step,
+                           bad, np, lr, b1, b2, eps);
+    } else {
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad, step, bad,
+                           np, lr, b1, b2, eps);
+    }
     return hipGetLastError();
 }
 
@@ -794,7 +836,35 @@ __global__ void k_scale_check(float *__restrict__ g, int64_t n, float scale, uin
     }
 }
 
+// Four elements per thread with 16-byte accesses where the buffer allows it.
+__global__ void k_scale_check4(float *__restrict__ g, int64_t n, float scale, uint32_t *bad) {
+    const int64_t i0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i0 >= n) return;
+    bool fin = true;
+    if (i0 + 4 <= n) {
+        f32x4 x = *(const f32x4 *)(g + i0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x[k] *= scale;
+            fin = fin && isfinite(x[k]);
+        }
+        *(f32x4 *)(g + i0) = x;
+    } else {
+        for (int64_t i = i0; i < n; ++i) {
+            const float x = g[i] * scale;
+            g[i] = x;
+            fin = fin && isfinite(x);
+        }
+    }
+    if (bad && !fin) atomicOr(bad, 1u);
+}
+
 hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s) {
+    if (aligned16(g)) {
+        const int64_t groups = (n + 3) / 4;
+        hipLaunchKernelGGL(k_scale_check4, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, g, n, scale, bad);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scale_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, n, scale, bad);
     return hipGetLastError();
 }
