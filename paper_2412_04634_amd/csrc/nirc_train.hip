@@ -621,12 +621,18 @@ __global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *
         grad[i] = gi;
         if (bad && !isfinite(gi)) atomicOr(bad, 1u);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the loss: lane-strided sums of the partials, then a fixed shuffle tree (one wave, so the
+    // loads are in flight together rather than one dependent load per partial)
+    if (blockIdx.x == 0 && wave == 0) {
         float t = 0.0f;
-        for (int b = 0; b < nblocks; ++b) t += loss_partials[b];
-        t *= loss_norm;
-        if (loss) loss[0] = t;
-        if (bad && !isfinite(t)) atomicOr(bad, 1u);
+        for (int b = lane; b < nblocks; b += 64) t += loss_partials[b];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+        if (lane == 0) {
+            t *= loss_norm;
+            if (loss) loss[0] = t;
+            if (bad && !isfinite(t)) atomicOr(bad, 1u);
+        }
     }
 }
 
