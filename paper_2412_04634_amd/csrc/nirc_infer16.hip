@@ -7,8 +7,9 @@ namespace nirc {
 
 // packed16[e] = 16-bit(master[source(e)]) (round to nearest even), zero padding elsewhere.
 // After an Adam step (step != NULL) thread 0 also commits the step or records its skip.
-template <int PREC>
-__global__ void k_pack16(uint16_t *packed, const float *master, int W, int total, int64_t *step, uint32_t *flags,
+// (W is a template parameter so that the section search folds to constants.)
+template <int PREC, int W>
+__global__ void k_pack16(uint16_t *packed, const float *master, int total, int64_t *step, uint32_t *flags,
                          uint32_t *bad) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < total) {
@@ -473,13 +474,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *
 
 hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s, int64_t *step,
                          uint32_t *flags, uint32_t *bad) {
+    if (W != 64 && W != 128) return hipErrorInvalidValue;
     const int total = H16Layout{W}.total();
-    if (prec == NIRC_BF16)
-        hipLaunchKernelGGL(k_pack16<NIRC_BF16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
-                           step, flags, bad);
+    const dim3 grid((total + 255) / 256), block(256);
+    if (prec == NIRC_BF16 && W == 64)
+        hipLaunchKernelGGL((k_pack16<NIRC_BF16, 64>), grid, block, 0, s, packed, master, total, step, flags, bad);
+    else if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_pack16<NIRC_BF16, 128>), grid, block, 0, s, packed, master, total, step, flags, bad);
+    else if (W == 64)
+        hipLaunchKernelGGL((k_pack16<NIRC_FP16, 64>), grid, block, 0, s, packed, master, total, step, flags, bad);
     else
-        hipLaunchKernelGGL(k_pack16<NIRC_FP16>, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
-                           step, flags, bad);
+        hipLaunchKernelGGL((k_pack16<NIRC_FP16, 128>), grid, block, 0, s, packed, master, total, step, flags, bad);
     return hipGetLastError();
 }
 
