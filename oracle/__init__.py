@@ -92,10 +92,8 @@ def lib():
                                            _u64, _Opt(_f64p), _Opt(_f64p), _Opt(_f64p), _Opt(_f64p),
                                            _Opt(_f64p)])
         L.oracle_hash_loss_grad.argtypes = ([_i64] + [_f32p] * 7 + [_Opt(_i32p), _f64p, _f64p, _f64p, _int, _int,
-                                            _int, _dbl, _dbl, _int, _int, _int, _Opt(_f64p)])
+                                            _int, _dbl, _dbl, _int, _int, _Opt(_f64p)])
         L.oracle_hash_loss_grad.restype = _dbl
-        L.oracle_round_fmt.argtypes = [_dbl, _int]
-        L.oracle_round_fmt.restype = _dbl
         _lib = L
     return _lib
 
@@ -366,20 +364,14 @@ def hash_estimate(points, lobes_packed, w, n_cache: int, seed: int, frame: int, 
 
 
 def hash_loss_grad(points, point_idx, dirs, target, w, width: int = 64, grid=HASH_GRID, eps: float = 1e-2,
-                   frozen: bool = True, want_grad: bool = True, kind: int = LOSS_REL_L2, mask_prec: int = 0):
-    """Loss (relative L2 or L2) of the hash-input cache and its gradient over MLP and table (FP64).
-    mask_prec: ReLU decisions from the FP64 pass (0) or from a BF16 (1) / FP16 (2) operand pass."""
+                   frozen: bool = True, want_grad: bool = True, kind: int = LOSS_REL_L2):
+    """Loss (relative L2 or L2) of the hash-input cache and its gradient over MLP and table (FP64)."""
     dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
     B = dirs.shape[0]
     g = np.zeros(hash_n_params(width, grid), np.float64) if want_grad else None
     idx = None if point_idx is None else np.ascontiguousarray(point_idx, np.int32)
     loss = lib().oracle_hash_loss_grad(B, *_pts(points), idx, dirs,
                                        np.ascontiguousarray(target, np.float64).reshape(-1), _w64(w), width,
-                                       int(grid[0]), int(grid[1]), float(grid[2]), eps, int(frozen), int(kind),
-                                       int(mask_prec), g)
+                                       int(grid[0]), int(grid[1]), float(grid[2]), eps, int(frozen), int(kind), g)
     return float(loss), g
 
-
-def round_fmt(x: float, prec: int) -> float:
-    """x rounded to BF16 (prec 1) or FP16 (prec 2), to nearest even, as an FP64 value."""
-    return float(lib().oracle_round_fmt(float(x), int(prec)))

@@ -1069,79 +1069,17 @@ void oracle_hash_estimate(int64_t P, const float *px, const float *py, const flo
     }
 }
 
-/* Round x to a binary format with `bits` significand bits and minimum normal exponent emin,
- * to nearest, ties to even (BF16: 8 and -126; FP16: 11 and -14, subnormals included). */
-static double round_fmt(double x, int bits, int emin)
-{
-    if (x == 0.0 || !isfinite(x)) return x;
-    int E;
-    frexp(x, &E);   /* |x| in [2^(E-1), 2^E) */
-    int e = E - 1 < emin ? emin : E - 1;
-    double q = ldexp(1.0, e - (bits - 1));
-    return nearbyint(x / q) * q;
-}
-
-double oracle_round_fmt(double x, int prec) { return prec == 1 ? round_fmt(x, 8, -126) : round_fmt(x, 11, -14); }
-
-/* ReLU decisions of one input vector: mask_prec 0 takes them from the FP64 pass itself;
- * 1 (BF16) or 2 (FP16) from a pass whose operands (inputs, weights, hidden activations) are
- * rounded to that format, as the 16-bit kernels compute them (products and sums exact here). */
-static void hash_masks(const net_t *net, const double *e, int mask_prec, unsigned char mk[4][256])
-{
-    int bits = mask_prec == 1 ? 8 : 11, emin = mask_prec == 1 ? -126 : -14;
-    double h[256], hn[256];
-    int n = H_IN;
-    for (int c = 0; c < n; ++c) h[c] = mask_prec ? round_fmt(e[c], bits, emin) : e[c];
-    for (int l = 0; l < 4; ++l) {
-        for (int r = 0; r < net->rows[l]; ++r) {
-            double s = 0.0;
-            for (int c = 0; c < net->cols[l]; ++c) {
-                double wv = net->W[l][(size_t)r * net->cols[l] + c];
-                s += (mask_prec ? round_fmt(wv, bits, emin) : wv) * h[c];
-            }
-            mk[l][r] = s > 0.0;
-            double v = s > 0.0 ? s : 0.0;
-            hn[r] = mask_prec ? round_fmt(v, bits, emin) : v;
-        }
-        n = net->rows[l];
-        memcpy(h, hn, sizeof(double) * n);
-    }
-}
-
-/* FP64 forward with given ReLU decisions. */
-static void hash_forward_masked(const net_t *net, const double *e, unsigned char mk[4][256], acts_t *a)
-{
-    const double *x = e;
-    for (int l = 0; l < 4; ++l) {
-        for (int r = 0; r < net->rows[l]; ++r) {
-            double s = 0.0;
-            for (int c = 0; c < net->cols[l]; ++c) s += net->W[l][(size_t)r * net->cols[l] + c] * x[c];
-            a->z[l][r] = s;
-            a->h[l][r] = mk[l][r] ? s : 0.0;
-        }
-        x = a->h[l];
-    }
-    for (int r = 0; r < 3; ++r) {
-        double s = 0.0;
-        for (int c = 0; c < net->cols[4]; ++c) s += net->W[4][(size_t)r * net->cols[4] + c] * x[c];
-        a->zo[r] = s;
-        a->y[r] = exp(s);
-    }
-}
-
 /* Loss and gradient of the hash-input cache (kind 0 relative L2 with the denominator held
  * constant unless frozen == 0, kind 1 plain L2), as for the frequency input; in addition the
  * gradient reaches the inputs of the hash features, dloss/de_k = sum_r W1[r][k] delta1[r], and
  * each table entry receives the trilinear weight of its corner times that (the scatter of the
  * interpolation's transpose).  grad: [n_params] in canonical order (MLP, then table).
- * mask_prec: where the ReLU decisions come from (hash_masks): 0 the FP64 pass; 1 / 2 a pass in
- * BF16 / FP16 operands, the precision the 16-bit kernels decide them in (a unit's on/off state
- * is an integer decided by floating point, so both sides take it in one precision).        */
+ * ReLU'(0) = 0: a unit whose pre-activation is exactly zero passes no gradient.          */
 double oracle_hash_loss_grad(int64_t B, const float *px, const float *py, const float *pz, const float *nx,
                              const float *ny, const float *nz, const float *rough, const int32_t *point,
                              const double *dirs, const double *target, const double *w, int width,
                              int log2_table, int base_res, double growth, double eps, int frozen, int kind,
-                             int mask_prec, double *grad)
+                             double *grad)
 {
     const float *pts[7] = {px, py, pz, nx, ny, nz, rough};
     hgrid_t g;
@@ -1170,10 +1108,8 @@ double oracle_hash_loss_grad(int64_t B, const float *px, const float *py, const 
         for (int64_t b = 0; b < B; ++b) {
             double e[H_IN];
             acts_t a;
-            unsigned char mk[4][256];
             hash_inputs(&g, table, pts, point ? point[b] : b, dirs + 3 * b, e);
-            hash_masks(&net, e, mask_prec, mk);
-            hash_forward_masked(&net, e, mk, &a);
+            net_forward(&net, e, &a);
             double dz[3];
             for (int c = 0; c < 3; ++c) {
                 double y = a.y[c], t = target[3 * b + c];
@@ -1192,7 +1128,7 @@ double oracle_hash_loss_grad(int64_t B, const float *px, const float *py, const 
             for (int j = 0; j < W; ++j) {
                 double s = 0.0;
                 for (int c = 0; c < 3; ++c) s += net.W[4][(size_t)c * W + j] * dz[c];
-                delta[j] = mk[3][j] ? s : 0.0;
+                delta[j] = a.z[3][j] > 0.0 ? s : 0.0;
             }
             for (int l = 3; l >= 1; --l) {
                 double *gW = gm + (size_t)W * H_IN + (size_t)(l - 1) * W * W;
@@ -1201,7 +1137,7 @@ double oracle_hash_loss_grad(int64_t B, const float *px, const float *py, const 
                 for (int c = 0; c < W; ++c) {
                     double s = 0.0;
                     for (int r = 0; r < W; ++r) s += net.W[l][(size_t)r * W + c] * delta[r];
-                    prev[c] = mk[l - 1][c] ? s : 0.0;
+                    prev[c] = a.z[l - 1][c] > 0.0 ? s : 0.0;
                 }
                 memcpy(delta, prev, sizeof(double) * W);
             }

@@ -24,7 +24,8 @@ import torch
 
 import oracle
 from paper_2412_04634_amd import workload as wl
-from tests.common import Samples, host, oracle_dirs32, rel_l2
+from tests.common import (Samples, check_estimate_points, check_query_points, host, oracle_dirs32, rel_l2,
+                          residual_prediction)
 
 pytestmark = pytest.mark.gpu
 
@@ -103,9 +104,10 @@ def test_infer_matches_oracle(nirc, Q):
         return
     ref = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0, W)
     assert rel_l2(y, ref) <= 1e-5
+    check_query_points(f"infer Q={Q}", y, ref, "fp32")
 
 
-def check_estimate(tl, c, r, o_tl, o_c, o_r):
+def check_estimate(tl, c, r, o_tl, o_c, o_r, y_r=None):
     e_c = rel_l2(c, o_c)
     e_tl = np.linalg.norm(tl - o_tl) / np.linalg.norm(o_c)
     e_r = np.linalg.norm(r - o_r) / np.linalg.norm(o_c)
@@ -114,9 +116,12 @@ def check_estimate(tl, c, r, o_tl, o_c, o_r):
     assert e_tl <= EST_TOL
     # F_r = L - y can cancel: its error is bounded relative to the cache prediction's scale
     assert e_r <= EST_TOL
+    if y_r is not None:
+        check_estimate_points("per point", tl, c, r, o_tl, o_c, o_r, y_r, "fp32")
 
 
-@pytest.mark.parametrize("P,N", [(1, 1), (17, 3), (2048, 8), (4096, 8), (1000, 16), (333, 24), (100, 64)])
+@pytest.mark.parametrize("P,N", [(1, 1), (17, 3), (2048, 8), (4096, 8), (1000, 16), (333, 24), (100, 64),
+                                 (4001, 5), (1003, 1)])
 def test_estimate_matches_oracle(nirc, P, N):
     say(f"estimate P={P} N={N}")
     pts, lobes, w0 = scene(6, P)
@@ -125,7 +130,7 @@ def test_estimate_matches_oracle(nirc, P, N):
     seed, frame = 77, 2
     tl, c, r = (host(t) for t in nirc.tlmc_estimate(model, dp, lobes, N, seed, frame, parts=True))
     o_tl, o_c, o_r = oracle.estimate(pts, lobes, w0, W, N, seed, frame)
-    check_estimate(tl, c, r, o_tl, o_c, o_r)
+    check_estimate(tl, c, r, o_tl, o_c, o_r, residual_prediction(pts, w0, W, N, seed, frame))
     np.testing.assert_array_equal(tl, host(nirc.tlmc_estimate(model, dp, lobes, N, seed, frame)))
 
 
@@ -373,5 +378,5 @@ def test_full_1080p_sampled_points(nirc):
     # the oracle samples the directions of the selected points by their frame indices
     dirs = oracle.sample_dirs(sub, N, 2, 0, ids=sel)
     o_tl, o_c, o_r = oracle.estimate(sub, lobes, w0, W, N, 2, 0, dirs=dirs)
-    check_estimate(tl[sel], c[sel], r[sel], o_tl, o_c, o_r)
+    check_estimate(tl[sel], c[sel], r[sel], o_tl, o_c, o_r, residual_prediction(sub, w0, W, N, 2, 0, dirs=dirs))
     assert np.isfinite(tl).all()

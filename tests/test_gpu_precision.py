@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from paper_2412_04634_amd import workload as wl
-from tests.common import Samples, host, rel_l2
+from tests.common import Samples, check_estimate_points, check_query_points, host, rel_l2, residual_prediction
 
 pytestmark = pytest.mark.gpu
 W = 64
@@ -46,10 +46,11 @@ def test_infer_16bit(nirc, prec, Q):
     y = host(nirc.nirc_infer(model, dp, nirc.Queries.from_dirs(d.cuda(), idx.cuda())))
     ref = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0, W)
     assert rel_l2(y, ref) <= 1e-2
+    check_query_points(f"infer {prec} Q={Q}", y, ref, prec)
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-@pytest.mark.parametrize("P,N", [(17, 3), (4096, 8), (1000, 16), (100, 64)])
+@pytest.mark.parametrize("P,N", [(17, 3), (4096, 8), (1000, 16), (100, 64), (4001, 5), (1003, 1), (333, 24)])
 def test_estimate_16bit(nirc, prec, P, N):
     print(f"estimate {prec} P={P} N={N}", flush=True)
     pts = wl.make_points(32, P)
@@ -62,6 +63,8 @@ def test_estimate_16bit(nirc, prec, P, N):
     assert rel_l2(c, o_c) <= 1e-2
     assert rel_l2(tl, o_tl) <= 1e-2
     assert np.linalg.norm(r - o_r) <= 1e-2 * np.linalg.norm(o_c)
+    check_estimate_points(f"estimate {prec} P={P} N={N}", tl, c, r, o_tl, o_c, o_r,
+                          residual_prediction(pts, w0, W, N, 9, 1), prec)
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
@@ -155,4 +158,6 @@ def test_full_4k_bf16_sampled_points(nirc):
     o_tl, o_c, o_r = oracle.estimate(sub, lob, w0, W, N, 3, 1, dirs=dirs)
     assert rel_l2(c[sel], o_c) <= 1e-2
     assert np.linalg.norm(tl[sel] - o_tl) <= 1e-2 * np.linalg.norm(o_c)
+    check_estimate_points("4K sampled", tl[sel], c[sel], r[sel], o_tl, o_c, o_r,
+                          residual_prediction(sub, w0, W, N, 3, 1, dirs=dirs), "bf16")
     assert np.isfinite(tl).all()

@@ -15,6 +15,7 @@ import torch
 import oracle
 from paper_2412_04634_amd import workload as wl
 from tests.common import Samples, host
+from tests.common import check_estimate_points
 
 pytestmark = pytest.mark.gpu
 PRECS = {"fp32": 0, "bf16": 1, "fp16": 2}
@@ -54,6 +55,9 @@ def test_estimate_with_residual_radiance(nirc, prec, W, P, N):
     e_r = np.linalg.norm(r - (R - y_r)) / np.linalg.norm(o_c)
     print(f"  F_r error / |F_c| {e_r:.2e}", flush=True)
     assert e_r <= EST_TOL[prec]
+    # per point: F_c, and F_r = R - y_r relative to |F_c,p| + |y_r,p|
+    check_estimate_points(f"residual tile {prec} W={W}", tl, c, r, o_c + (R - y_r), o_c, R - y_r, y_r,
+                          prec)
     # R = the field at the oracle's residual directions reproduces the field path
     Lf = oracle.field(lob, pts, None, dirs[:, N, :]).astype(np.float32)
     tl2 = host(nirc.tlmc_estimate(model, dp, None, N, seed, frame, residual=torch.from_numpy(Lf).cuda()))

@@ -11,6 +11,7 @@ import torch
 import oracle
 from paper_2412_04634_amd import workload as wl
 from tests.common import Samples, host, rel_l2
+from tests.common import check_query_points
 
 pytestmark = pytest.mark.gpu
 VIS, OCC = 1, 2
@@ -56,6 +57,7 @@ def test_infer_visibility(nirc, prec):
     y = host(nirc.nirc_infer(model, dp, nirc.Queries.from_dirs(d.cuda(), idx.cuda())))
     ref = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0, 64, output=VIS)
     assert rel_l2(y, ref) <= TOL[prec]
+    check_query_points(f"visibility infer {prec}", y, ref, prec)
     assert (y > 0).all() and (y < 1).all()
 
 

@@ -12,6 +12,7 @@ import torch
 import oracle
 from paper_2412_04634_amd import workload as wl
 from tests.common import Samples, host, rel_l2
+from tests.common import check_estimate_points, check_query_points, residual_prediction
 
 pytestmark = pytest.mark.gpu
 W = 128
@@ -49,10 +50,11 @@ def test_infer_width128(nirc, prec, Q):
     y = host(nirc.nirc_infer(model, dp, nirc.Queries.from_dirs(d.cuda(), idx.cuda())))
     ref = oracle.infer(pts, idx.numpy(), d.double().numpy(), w0, W)
     assert rel_l2(y, ref) <= TOL[prec]
+    check_query_points(f"infer W=128 {prec} Q={Q}", y, ref, prec)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
-@pytest.mark.parametrize("P,N", [(17, 3), (4096, 4), (1000, 16), (100, 64)])
+@pytest.mark.parametrize("P,N", [(17, 3), (4096, 4), (1000, 16), (100, 64), (1001, 5), (300, 1)])
 def test_estimate_width128(nirc, prec, P, N):
     print(f"estimate W=128 {prec} P={P} N={N}", flush=True)
     pts = wl.make_points(42, P)
@@ -68,6 +70,8 @@ def test_estimate_width128(nirc, prec, P, N):
     assert rel_l2(c, o_c) <= TOL[prec]
     assert np.linalg.norm(tl - o_tl) <= EST_TOL[prec] * np.linalg.norm(o_c)
     assert np.linalg.norm(r - o_r) <= EST_TOL[prec] * np.linalg.norm(o_c)
+    check_estimate_points(f"estimate W=128 {prec}", tl, c, r, o_tl, o_c, o_r,
+                          residual_prediction(pts, w0, W, N, 11, 2), prec)
 
 
 # gradients at width 128 (three FP32 / two 16-bit sweeps over the batch): FP32 rel-L2 1e-5 as at
