@@ -225,8 +225,9 @@ nirc_status tlmc_estimate(const nirc_model *model, nirc_points points,
  * a uniform xi (Philox counter (p >> 2, 0, frame, 6), word p & 3) stops the path if xi > P_s,
  * and the point is then shaded by the N cache samples alone, out = F_c; otherwise the path goes
  * on and its radiance L(x, w_s) is the estimate (residual_radiance when given — the renderer
- * traces the continued paths — else the field).  The decision is taken in FP64 from the exact
- * 24-bit uniforms ((xi N)^2 > (1 - u1)(1 - xi)^2 with cos = sqrt(1 - u1)).
+ * traces the continued paths — else the field).  The decision is exact: with cos = sqrt(1 - u1)
+ * and the 24-bit uniforms xi = X 2^-24, u1 = U 2^-24 it is (X N)^2 2^24 > (2^24 - U)(2^24 - X)^2
+ * in 128-bit integers.
  * out_b [points.count][3]; out_c [points.count][3] (required: F_c); out_continue
  * [points.count] int32, 1 where the path continues (nullable). */
 nirc_status tlmc_estimate_biased(const nirc_model *model, nirc_points points,

@@ -418,8 +418,11 @@ void oracle_estimate(int64_t P, const float *px, const float *py, const float *p
  * cos / (cos + N), and a uniform xi from counter (p >> 2, 0, frame, STREAM_TERMINATE), word
  * p & 3, decides: xi > P_s stops the path and shades with the N cache samples (F_c); otherwise
  * the path continues and its radiance L(x, w_s) is the estimate (f_r cos / p = 1).
- * The decision is taken without a square root: with cos = sqrt(1 - u1) of the sampler,
- * xi > cos / (cos + N)  <=>  (xi N)^2 > (1 - u1) (1 - xi)^2, in FP64 products only.
+ * The decision is taken exactly: with cos = sqrt(1 - u1) of the sampler and both uniforms
+ * 24-bit fractions, xi = X 2^-24 and u1 = U 2^-24,
+ *   xi > cos / (cos + N)  <=>  (xi N)^2 > (1 - u1) (1 - xi)^2
+ *                         <=>  (X N)^2 2^24 > (2^24 - U) (2^24 - X)^2,
+ * compared in 128-bit integers (no rounding anywhere).
  * rrad (nullable): the radiance found along w_s (the field otherwise).  cont[p] = 1 where the
  * path continues. */
 void oracle_estimate_biased(int64_t P, const float *px, const float *py, const float *pz, const float *nx,
@@ -441,9 +444,9 @@ void oracle_estimate_biased(int64_t P, const float *px, const float *py, const f
         cosine_direction(n, u1, u2, ws);
         uint32_t ctr[4] = {(uint32_t)p >> 2, 0u, (uint32_t)frame, STREAM_TERMINATE}, r[4];
         oracle_philox(ctr, key, r);
-        const double xi = u24(r[p & 3]);
-        const double a = xi * (double)n_cache, b = 1.0 - xi;
-        const int stop = a * a > (1.0 - u1) * (b * b);
+        const unsigned __int128 X = r[p & 3] >> 8, U = (uint64_t)(u1 * 16777216.0), one = (uint64_t)1 << 24;
+        const int stop = X * X * (unsigned __int128)n_cache * (unsigned __int128)n_cache * one >
+                         (one - U) * (one - X) * (one - X);
         if (cont) cont[p] = !stop;
         if (stop) {
             for (int c = 0; c < 3; ++c) out[3 * p + c] = fc[3 * p + c];

@@ -85,13 +85,14 @@ __global__ void k_bth(Points pts, nirc_lobes lobes, int n_cache, uint32_t key0, 
     if (p >= pts.count) return;
     const DirCounter dc = dir_counter((uint32_t)p, n_cache, true);
     const Rand4 r = philox(dc.c0, dc.c1, frame, dc.stream, key0, key1);
-    const float u1 = u24(dc.half ? r.r[2] : r.r[0]);
     const Rand4 rt = philox((uint32_t)p >> 2, 0u, frame, (uint32_t)kStreamTerminate, key0, key1);
     const int q = (int)(p & 3);
     const uint32_t word = q == 0 ? rt.r[0] : q == 1 ? rt.r[1] : q == 2 ? rt.r[2] : rt.r[3];
-    const double xi = (double)u24(word);
-    const double a = xi * (double)n_cache, b = 1.0 - xi;
-    const bool stop = a * a > (1.0 - (double)u1) * (b * b);
+    // xi > cos / (cos + N) with cos = sqrt(1 - u1), xi = X 2^-24, u1 = U 2^-24 (24-bit integers):
+    // (X N)^2 2^24 > (2^24 - U) (2^24 - X)^2, both sides exact in 128-bit integers (X N < 2^36).
+    const uint64_t X = word >> 8, U = (dc.half ? r.r[2] : r.r[0]) >> 8;
+    const uint64_t xn = X * (uint64_t)n_cache, xc = (1ull << 24) - X;
+    const bool stop = ((unsigned __int128)xn * xn << 24) > (unsigned __int128)((1ull << 24) - U) * (xc * xc);
     if (cont) cont[p] = stop ? 0 : 1;
     float v[3];
     if (stop) {

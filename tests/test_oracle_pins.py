@@ -3,6 +3,7 @@
 Each test checks the oracle against something other than itself: published known-answer
 vectors, closed forms, exact special values, library routines, invariants and brute force.
 """
+import decimal
 import math
 
 import numpy as np
@@ -600,11 +601,21 @@ def test_bth_decision_and_outputs():
     n = np.stack([pts.nx, pts.ny, pts.nz], 1).astype(np.float64)
     cos = (n * dirs).sum(1)
     p_s = (cos / np.pi) / (cos / np.pi + N / np.pi)
-    xi = np.array([(int(oracle.philox([p >> 2, 0, frame, 6], [seed & 0xFFFFFFFF, seed >> 32])[p & 3]) >> 8)
-                   * 2.0 ** -24 for p in range(P)])
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    X = [int(oracle.philox([p >> 2, 0, frame, 6], key)[p & 3]) >> 8 for p in range(P)]
+    xi = np.array(X) * 2.0 ** -24
     clear = np.abs(xi - p_s) > 1e-9
     assert clear.sum() > P - 5
     np.testing.assert_array_equal(cont[clear] == 0, (xi > p_s)[clear])
+    # every decision, near-ties included, against xi > P_s evaluated in 60-digit decimal
+    # arithmetic from the exact 24-bit uniforms (u1 of the residual direction: counter
+    # (p >> 1, 0, frame, 4), word 0 or 2 by p & 1)
+    with decimal.localcontext() as ctx:
+        ctx.prec = 60
+        for p in range(P):
+            U = int(oracle.philox([p >> 1, 0, frame, 4], key)[2 * (p & 1)]) >> 8
+            c = (1 - decimal.Decimal(U) / 2 ** 24).sqrt()
+            assert (cont[p] == 0) == (decimal.Decimal(X[p]) / 2 ** 24 > c / (c + N)), p
     stop = cont == 0
     np.testing.assert_array_equal(out[stop], fc[stop])
     np.testing.assert_array_equal(out[~stop], oracle.field(lobes, pts, None, dirs)[~stop])
