@@ -80,8 +80,11 @@ typedef int32_t nirc_status;
 #define NIRC_OUTPUT_VISIBILITY 1
 #define NIRC_OUTPUT_RADIANCE_OCCLUDED 2
 
-/* Device flags raised by training (sticky until nirc_clear_flags). */
+/* Device flags of a model (sticky until nirc_clear_flags). */
 #define NIRC_FLAG_NONFINITE_GRAD 1u   /* a step saw a non-finite loss/gradient and was skipped */
+#define NIRC_FLAG_BAD_POINT_INDEX 2u  /* a query named a point index outside [0, points.count):
+                                         in training the step was skipped; in inference that
+                                         query's outputs are not defined */
 
 typedef struct nirc_model nirc_model;   /* opaque host handle */
 
@@ -110,8 +113,10 @@ typedef struct {
 } nirc_points;
 
 /* Cache queries: a direction per query and the index of its shading point (point == NULL
- * means query i uses point i).  FP32 / int32 device arrays of `count` entries.  Point indices
- * outside [0, points.count) are clamped into range by the kernels. */
+ * means query i uses point i).  FP32 / int32 device arrays of `count` entries.  A point index
+ * outside [0, points.count) is an error found on the device: the kernels never read out of
+ * bounds for it, raise NIRC_FLAG_BAD_POINT_INDEX in the model's flags (training skips the step,
+ * inference leaves that query's outputs undefined) and nirc_encode writes NaN features for it. */
 typedef struct {
     const float *wx, *wy, *wz;
     const int32_t *point;

@@ -36,7 +36,7 @@ struct StateLayout {
 };
 
 // Workspace layout: partials [nblocks][np] | loss partials [nblocks] | grad [np] | loss |
-// residual-variance loss pre-pass (predictions [B][3], kFrBlocks x 3 FP64 partials, F_r [3]; only
+// residual-variance loss pre-pass (predictions [B][3], kFrBlocks x 3 FP32 partials, F_r [3]; only
 // for NIRC_LOSS_VAR) | training samples of nirc_train_frame (point [B], wx, wy, wz [B],
 // target [B][3]).
 struct WorkLayout {
@@ -49,7 +49,7 @@ struct WorkLayout {
         grad = o; o += align_up(np * sizeof(float));
         loss = o; o += align_up(sizeof(float));
         pred = o; o += var_batch ? align_up((size_t)var_batch * 3 * sizeof(float)) : 0;
-        fr_part = o; o += var_batch ? align_up((size_t)kFrBlocks * 3 * sizeof(double)) : 0;
+        fr_part = o; o += var_batch ? align_up((size_t)kFrBlocks * 3 * sizeof(float)) : 0;
         fr = o; o += var_batch ? align_up(4 * sizeof(float)) : 0;
         samples = o; o += align_up((size_t)sample_batch * 7 * sizeof(float));
         total = o;
@@ -57,6 +57,13 @@ struct WorkLayout {
 };
 
 int64_t var_rows(const nirc_config &cfg, int64_t batch) { return cfg.loss == NIRC_LOSS_VAR ? batch : 0; }
+
+// Gradient-partial slabs of a batch: the grid of the precision's gradient kernel.  Every
+// workspace layout of a model (sizing, the partials, the reduced gradient after them) takes its
+// count from here, so that the layouts agree whatever the kernels' rounds are.
+int grad_blocks(int32_t precision, int64_t batch) {
+    return precision != NIRC_FP32 ? train_blocks16(batch) : train_blocks(batch);
+}
 
 nirc_status check_points(const nirc_points &p) {
     if (p.count < 0 || p.count > INT32_MAX) return NIRC_ERR_INVALID_ARG;
@@ -74,7 +81,9 @@ nirc_status check_queries(const nirc_queries &q, const nirc_points &p) {
 }
 
 Points to_points(const nirc_points &p) { return Points{p.px, p.py, p.pz, p.nx, p.ny, p.nz, p.rough, p.count}; }
-Queries to_queries(const nirc_queries &q) { return Queries{q.wx, q.wy, q.wz, q.point, q.count}; }
+// err: where a point index out of range is reported (the model's sticky flags, or the step's
+// flags of a training step, which then skips its update)
+Queries to_queries(const nirc_queries &q, uint32_t *err) { return Queries{q.wx, q.wy, q.wz, q.point, q.count, err}; }
 
 nirc_status hip_status(hipError_t e) { return e == hipSuccess ? NIRC_OK : NIRC_ERR_HIP; }
 
@@ -131,7 +140,7 @@ size_t nirc_state_bytes(const nirc_config *cfg) {
 
 size_t nirc_workspace_bytes(const nirc_config *cfg, int64_t max_batch) {
     if (check_config(cfg) != NIRC_OK || max_batch < 0) return 0;
-    return WorkLayout(cfg->width, train_blocks(max_batch), var_rows(*cfg, max_batch), max_batch).total;
+    return WorkLayout(cfg->width, grad_blocks(cfg->precision, max_batch), var_rows(*cfg, max_batch), max_batch).total;
 }
 
 nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes, void *workspace,
@@ -246,7 +255,7 @@ nirc_status nirc_encode(nirc_points points, nirc_queries queries, float *feature
     if (st == NIRC_OK) st = check_queries(queries, points);
     if (st != NIRC_OK) return st;
     if (queries.count > 0 && !features) return NIRC_ERR_INVALID_ARG;
-    return hip_status(launch_encode(to_points(points), to_queries(queries), features, (hipStream_t)stream));
+    return hip_status(launch_encode(to_points(points), to_queries(queries, nullptr), features, (hipStream_t)stream));
 }
 
 nirc_status nirc_infer(const nirc_model *model, nirc_points points, nirc_queries queries, float *rgb,
@@ -257,7 +266,7 @@ nirc_status nirc_infer(const nirc_model *model, nirc_points points, nirc_queries
     if (st != NIRC_OK) return st;
     if (queries.count > 0 && !rgb) return NIRC_ERR_INVALID_ARG;
     const void *pk = model->packed16 ? (const void *)model->packed16 : (const void *)model->packed;
-    return hip_status(launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries), pk, rgb,
+    return hip_status(launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries, model->flags), pk, rgb,
                                    model->cfg.output == NIRC_OUTPUT_VISIBILITY,
                                    (hipStream_t)stream));
 }
@@ -350,14 +359,14 @@ nirc_status tlmc_reference_occluded(nirc_points points, const nirc_lobes *field,
 // Gradient partials + reduction into `grad`/`loss`; the step's `bad` flag is raised on a
 // non-finite value.
 static nirc_status grad_into(nirc_model *model, const nirc_points &points, const nirc_queries &queries,
-                             const float *target, const float *d_rgb, float *grad, float *loss,
+                             const float *target, const float *d_rgb, float *grad, float *loss, uint32_t *err,
                              hipStream_t s) {
     nirc_status st = check_points(points);
     if (st == NIRC_OK) st = check_queries(queries, points);
     if (st != NIRC_OK) return st;
     if (queries.count < 1 || !grad) return NIRC_ERR_INVALID_ARG;
     const bool h16 = model->packed16 != nullptr;
-    const int nb = h16 ? train_blocks16(queries.count) : train_blocks(queries.count);
+    const int nb = grad_blocks(model->cfg.precision, queries.count);
     const bool var = target && model->cfg.loss == NIRC_LOSS_VAR;
     const WorkLayout wl(model->W, nb, var ? queries.count : 0);
     if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
@@ -372,16 +381,16 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
         float *pred = (float *)(model->ws + wl.pred);
         float *fr = (float *)(model->ws + wl.fr);
         const void *pk = h16 ? (const void *)model->packed16 : (const void *)model->packed;
-        hipError_t e = launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries), pk, pred,
+        hipError_t e = launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries, err), pk, pred,
                                     model->cfg.output == NIRC_OUTPUT_VISIBILITY, s);
         if (e == hipSuccess)
-            e = launch_residual_mean(pred, target, queries.count, (double *)(model->ws + wl.fr_part), fr, s);
+            e = launch_residual_mean(pred, target, queries.count, (float *)(model->ws + wl.fr_part), fr, s);
         if (e != hipSuccess) return NIRC_ERR_HIP;
         a.fr = fr;
     }
     hipError_t e = h16 ? launch_grad_partials16(model->W, model->cfg.precision, to_points(points),
-                                                to_queries(queries), model->packed16, a, partials, lpart, nb, s)
-                       : launch_grad_partials(model->W, to_points(points), to_queries(queries), model->packed, a,
+                                                to_queries(queries, err), model->packed16, a, partials, lpart, nb, s)
+                       : launch_grad_partials(model->W, to_points(points), to_queries(queries, err), model->packed, a,
                                               partials, lpart, nb, s);
     if (e != hipSuccess) return NIRC_ERR_HIP;
     const float loss_norm = 1.0f / (3.0f * (float)queries.count);
@@ -393,7 +402,7 @@ nirc_status nirc_loss_grad(nirc_model *model, nirc_points points, nirc_queries q
                            float *grad, float *loss, void *stream) {
     if (!model || !target) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss, s);
+    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss, model->flags, s);
     if (st != NIRC_OK) return st;
     // a standalone gradient does not start a step: clear the step's flag again
     return hip_status(launch_fill_u32(model->bad, 1, 0u, s));
@@ -403,7 +412,7 @@ nirc_status nirc_backward(nirc_model *model, nirc_points points, nirc_queries qu
                           float *grad, void *stream) {
     if (!model || !d_rgb) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    nirc_status st = grad_into(model, points, queries, nullptr, d_rgb, grad, nullptr, s);
+    nirc_status st = grad_into(model, points, queries, nullptr, d_rgb, grad, nullptr, model->flags, s);
     if (st != NIRC_OK) return st;
     return hip_status(launch_fill_u32(model->bad, 1, 0u, s));
 }
@@ -423,12 +432,11 @@ nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries 
                             float *loss, void *stream) {
     if (!model || !target) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    const int nb = train_blocks(queries.count);
-    const WorkLayout wl(model->W, nb);
+    const WorkLayout wl(model->W, grad_blocks(model->cfg.precision, queries.count));
     if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
     float *grad = (float *)(model->ws + wl.grad);
     float *wloss = (float *)(model->ws + wl.loss);
-    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss ? loss : wloss, s);
+    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss ? loss : wloss, model->bad, s);
     if (st != NIRC_OK) return st;
     hipError_t e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
                                model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps,
@@ -441,7 +449,7 @@ nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_l
     if (!model || !field || batch < 1 || batch > INT32_MAX || steps < 0) return NIRC_ERR_INVALID_ARG;
     nirc_status st = check_points(points);
     if (st != NIRC_OK || points.count < 1) return NIRC_ERR_INVALID_ARG;
-    const WorkLayout wl(model->W, train_blocks(batch), var_rows(model->cfg, batch), batch);
+    const WorkLayout wl(model->W, grad_blocks(model->cfg.precision, batch), var_rows(model->cfg, batch), batch);
     if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     float *smp = (float *)(model->ws + wl.samples);

@@ -31,14 +31,24 @@ struct Queries {
     const float *wx, *wy, *wz;
     const int32_t *point;
     int64_t count;
+    uint32_t *err;   // receives NIRC_FLAG_BAD_POINT_INDEX on an index out of range (nullable)
 };
 
-// Point index of query i: explicit (clamped into [0, count) so that a bad index can never read
-// out of bounds) or i itself.
+__device__ inline bool point_index_ok(const Queries &q, const Points &p, int64_t i) {
+    if (!q.point) return true;
+    const int64_t j = q.point[i];
+    return j >= 0 && j < p.count;
+}
+
+// Point index of query i: explicit or i itself.  An explicit index outside [0, count) raises
+// NIRC_FLAG_BAD_POINT_INDEX in q.err and is replaced by the nearest valid one, so that it never
+// reads out of bounds; the outputs of such a query are not defined.
 __device__ inline int64_t query_point(const Queries &q, const Points &p, int64_t i) {
     if (!q.point) return i;
     const int64_t j = q.point[i];
-    return j < 0 ? 0 : (j >= p.count ? p.count - 1 : j);
+    if (j >= 0 && j < p.count) return j;
+    if (q.err) atomicOr(q.err, NIRC_FLAG_BAD_POINT_INDEX);
+    return j < 0 ? 0 : p.count - 1;
 }
 
 // Division of a query index q by the cache sample count N without a hardware divide:

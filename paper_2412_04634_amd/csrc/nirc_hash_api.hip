@@ -76,7 +76,8 @@ nirc_status check_queries_h(const nirc_queries &q, const nirc_points &p) {
 }
 
 Points pts_of(const nirc_points &p) { return Points{p.px, p.py, p.pz, p.nx, p.ny, p.nz, p.rough, p.count}; }
-Queries queries_of(const nirc_queries &q) { return Queries{q.wx, q.wy, q.wz, q.point, q.count}; }
+// err: where a point index out of range is reported (sticky flags, or the step's flags)
+Queries queries_of(const nirc_queries &q, uint32_t *err) { return Queries{q.wx, q.wy, q.wz, q.point, q.count, err}; }
 nirc_status hip_st(hipError_t e) { return e == hipSuccess ? NIRC_OK : NIRC_ERR_HIP; }
 
 }  // namespace
@@ -224,10 +225,10 @@ nirc_status nirc_hash_infer(const nirc_hash_model *model, nirc_points points, ni
     if (queries.count == 0) return NIRC_OK;
     if (!rgb) return NIRC_ERR_INVALID_ARG;
     if (model->cfg.precision == NIRC_FP32)
-        return hip_st(launch_hash_infer32(pts_of(points), queries_of(queries), model->packed32(), model->table(),
+        return hip_st(launch_hash_infer32(pts_of(points), queries_of(queries, model->flags), model->packed32(), model->table(),
                                           model->grid, rgb, (hipStream_t)stream));
-    return hip_st(launch_hash_infer(model->cfg.precision, pts_of(points), queries_of(queries), model->packed16,
-                                    model->table(), model->grid, rgb, (hipStream_t)stream));
+    return hip_st(launch_hash_infer(model->cfg.precision, pts_of(points), queries_of(queries, model->flags),
+                                    model->packed16, model->table(), model->grid, rgb, (hipStream_t)stream));
 }
 
 nirc_status nirc_hash_estimate(const nirc_hash_model *model, nirc_points points, const nirc_lobes *field,
@@ -251,7 +252,7 @@ nirc_status nirc_hash_estimate(const nirc_hash_model *model, nirc_points points,
 
 // Loss and gradient into grad/loss; the step's `bad` flag is raised on a non-finite value.
 static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &points, const nirc_queries &queries,
-                                  const float *target, float *grad, float *loss, hipStream_t s) {
+                                  const float *target, float *grad, float *loss, uint32_t *err, hipStream_t s) {
     nirc_status st = check_points_h(points);
     if (st == NIRC_OK) st = check_queries_h(queries, points);
     if (st != NIRC_OK) return st;
@@ -270,9 +271,9 @@ static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &poi
     hipError_t e = launch_fill_u32((uint32_t *)gtab, nt, 0u, s);
     if (e == hipSuccess)
         e = model->cfg.precision == NIRC_FP32
-                ? launch_hash_grad32(pts_of(points), queries_of(queries), model->packed32(), model->table(),
+                ? launch_hash_grad32(pts_of(points), queries_of(queries, err), model->packed32(), model->table(),
                                      model->grid, a, partials, lpart, gtab, nb, s)
-                : launch_hash_grad(model->cfg.precision, pts_of(points), queries_of(queries), model->packed16,
+                : launch_hash_grad(model->cfg.precision, pts_of(points), queries_of(queries, err), model->packed16,
                                    model->table(), model->grid, a, partials, lpart, gtab, nb, s);
     if (e == hipSuccess)
         e = launch_reduce_grad_n(kHashMlp, partials, lpart, nb, 1.0f / scale, 1.0f / (3.0f * (float)queries.count),
@@ -296,7 +297,7 @@ nirc_status nirc_hash_loss_grad(nirc_hash_model *model, nirc_points points, nirc
                                 const float *target, float *grad, float *loss, void *stream) {
     if (!model) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    nirc_status st = hash_grad_into(model, points, queries, target, grad, loss, s);
+    nirc_status st = hash_grad_into(model, points, queries, target, grad, loss, model->flags, s);
     if (st != NIRC_OK) return st;
     // a standalone gradient does not start a step: clear the step's flag again
     return hip_st(launch_fill_u32(model->bad, 1, 0u, s));
@@ -318,7 +319,7 @@ nirc_status nirc_hash_train_step(nirc_hash_model *model, nirc_points points, nir
     const HashWork wl(model->np, train_blocks16(queries.count > 0 ? queries.count : 1));
     if (model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
     float *grad = (float *)(model->ws + wl.grad);
-    nirc_status st = hash_grad_into(model, points, queries, target, grad, loss, s);
+    nirc_status st = hash_grad_into(model, points, queries, target, grad, loss, model->bad, s);
     if (st != NIRC_OK) return st;
     return hip_st(hash_adam(model, grad, s));
 }

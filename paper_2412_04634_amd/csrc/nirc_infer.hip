@@ -47,6 +47,11 @@ __global__ void k_encode(Points pts, Queries q, float *feat) {
     default: v = pts.rough[p]; break;
     }
     float *o = feat + qi * kFeat + 16 * i;
+    if (!point_index_ok(q, pts, qi)) {   // no point to encode: the query's features are NaN
+#pragma unroll
+        for (int k = 0; k < 2 * kFreq; ++k) o[k] = __builtin_nanf("");
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < kFreq; ++k) enc_pair(v, k, o[2 * k], o[2 * k + 1]);
 }
@@ -590,7 +595,7 @@ __global__ void k_hash_pack32(float *packed, const float *master, int64_t *step,
         packed[e] = s >= 0 ? master[s] : 0.0f;
     }
     if (step && e == 0) {
-        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
         else *step += 1;
         *bad = 0u;
     }

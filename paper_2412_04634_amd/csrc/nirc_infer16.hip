@@ -18,7 +18,7 @@ __global__ void k_pack16(uint16_t *packed, const float *master, int total, int64
         packed[e] = (uint16_t)(pack2<PREC>(v, 0.0f) & 0xFFFFu);
     }
     if (step && e == 0) {
-        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
         else *step += 1;
         *bad = 0u;
     }
@@ -582,7 +582,7 @@ __global__ void k_hash_pack16(uint16_t *packed, const float *master, int64_t *st
         packed[e] = (uint16_t)(pack2<PREC>(s >= 0 ? master[s] : 0.0f, 0.0f) & 0xFFFFu);
     }
     if (step && e == 0) {
-        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
         else *step += 1;
         *bad = 0u;
     }

@@ -436,7 +436,7 @@ struct TrainArgs {
 // NIRC_LOSS_VAR: fr[c] = mean over the batch of t - y (y: the model's predictions [B][3]),
 // summed in a fixed order; part holds kFrBlocks x 3 doubles.
 constexpr int kFrBlocks = 256;
-hipError_t launch_residual_mean(const float *y, const float *t, int64_t B, double *part, float *fr, hipStream_t s);
+hipError_t launch_residual_mean(const float *y, const float *t, int64_t B, float *part, float *fr, hipStream_t s);
 int train_blocks(int64_t batch);     // workgroups used by the FP32 gradient kernel for a batch
 int train_blocks16(int64_t batch);   // workgroups used by the 16-bit gradient kernel
 hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Queries &q, const void *packed,

@@ -619,7 +619,7 @@ __global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *
         const float sum = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
         const float gi = sum * inv_scale;
         grad[i] = gi;
-        if (bad && !isfinite(gi)) atomicOr(bad, 1u);
+        if (bad && !isfinite(gi)) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
     }
     // the loss: lane-strided sums of the partials, then a fixed shuffle tree (one wave, so the
     // loads are in flight together rather than one dependent load per partial)
@@ -631,14 +631,14 @@ __global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *
         if (lane == 0) {
             t *= loss_norm;
             if (loss) loss[0] = t;
-            if (bad && !isfinite(t)) atomicOr(bad, 1u);
+            if (bad && !isfinite(t)) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
         }
     }
 }
 
 __global__ void k_check_finite(const float *__restrict__ grad, int64_t np, uint32_t *bad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < np && !isfinite(grad[i])) atomicOr(bad, 1u);
+    if (i < np && !isfinite(grad[i])) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
 }
 
 // Adam (Kingma & Ba) with bias correction, t = step + 1; skipped entirely when `bad` is set.
@@ -666,7 +666,7 @@ __global__ void k_pack_commit(float *packed, const float *master, int W, int tot
         packed[e] = s >= 0 ? master[s] : 0.0f;
     }
     if (e == 0) {
-        if (*bad) *flags |= NIRC_FLAG_NONFINITE_GRAD;
+        if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
         else *step += 1;
         *bad = 0u;
     }
@@ -675,19 +675,19 @@ __global__ void k_pack_commit(float *packed, const float *master, int W, int tot
 // ------------------------------------------------------------------------------------------
 
 // Batch estimate of the residual's expectation per channel for the residual-variance loss:
-// block b sums t - y over its contiguous share of the batch (lanes stride through it, then a
-// fixed tree), and one block adds the kFrBlocks partials in order.  FP64 sums: deterministic
-// and insensitive to the batch size.
+// block b sums t - y over its contiguous share of the batch (each lane a strided run, then a
+// fixed tree over the 256 lanes), and one wave adds the kFrBlocks block sums in a fixed tree.
+// FP32 throughout; the order never depends on timing, so the result is deterministic.
 __global__ __launch_bounds__(256) void k_residual_partials(const float *__restrict__ y, const float *__restrict__ t,
-                                                           int64_t B, double *__restrict__ part) {
-    __shared__ double sh[3][256];
+                                                           int64_t B, float *__restrict__ part) {
+    __shared__ float sh[3][256];
     const int64_t per = (B + gridDim.x - 1) / gridDim.x;
     const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(B, b0 + per);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
     for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
-        a0 += (double)t[3 * b] - (double)y[3 * b];
-        a1 += (double)t[3 * b + 1] - (double)y[3 * b + 1];
-        a2 += (double)t[3 * b + 2] - (double)y[3 * b + 2];
+        a0 += t[3 * b] - y[3 * b];
+        a1 += t[3 * b + 1] - y[3 * b + 1];
+        a2 += t[3 * b + 2] - y[3 * b + 2];
     }
     sh[0][threadIdx.x] = a0;
     sh[1][threadIdx.x] = a1;
@@ -701,19 +701,25 @@ __global__ __launch_bounds__(256) void k_residual_partials(const float *__restri
     if (threadIdx.x < 3) part[3 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void k_residual_final(const double *__restrict__ part, int nblk, int64_t B,
-                                                       float *__restrict__ fr) {
-    if (threadIdx.x < 3) {
-        double a = 0.0;
-        for (int i = 0; i < nblk; ++i) a += part[3 * i + threadIdx.x];
-        fr[threadIdx.x] = (float)(a / (double)B);
+__global__ __launch_bounds__(256) void k_residual_final(const float *__restrict__ part, int64_t B,
+                                                        float *__restrict__ fr) {
+    static_assert(kFrBlocks == 256, "one lane per block sum");
+    __shared__ float sh[3][256];
+    const int i = threadIdx.x;
+    for (int c = 0; c < 3; ++c) sh[c][i] = part[3 * i + c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (i < w)
+            for (int c = 0; c < 3; ++c) sh[c][i] += sh[c][i + w];
+        __syncthreads();
     }
+    if (i < 3) fr[i] = sh[i][0] / (float)B;
 }
 
-hipError_t launch_residual_mean(const float *y, const float *t, int64_t B, double *part, float *fr, hipStream_t s) {
+hipError_t launch_residual_mean(const float *y, const float *t, int64_t B, float *part, float *fr, hipStream_t s) {
     if (B < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_residual_partials, dim3(kFrBlocks), dim3(256), 0, s, y, t, B, part);
-    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(64), 0, s, part, kFrBlocks, B, fr);
+    hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, s, part, B, fr);
     return hipGetLastError();
 }
 
@@ -838,7 +844,7 @@ __global__ void k_scale_check(float *__restrict__ g, int64_t n, float scale, uin
     if (i < n) {
         const float v = g[i] * scale;
         g[i] = v;
-        if (bad && !isfinite(v)) atomicOr(bad, 1u);
+        if (bad && !isfinite(v)) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
     }
 }
 
@@ -862,7 +868,7 @@ __global__ void k_scale_check4(float *__restrict__ g, int64_t n, float scale, ui
             fin = fin && isfinite(x);
         }
     }
-    if (bad && !fin) atomicOr(bad, 1u);
+    if (bad && !fin) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
 }
 
 hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s) {

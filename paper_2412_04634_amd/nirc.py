@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(_PKG), "include", "nirc.h")
 
 NIRC_FP32, NIRC_BF16, NIRC_FP16 = 0, 1, 2
 NIRC_FLAG_NONFINITE_GRAD = 1
+NIRC_FLAG_BAD_POINT_INDEX = 2
 NIRC_LOSS_REL_L2, NIRC_LOSS_L2, NIRC_LOSS_VAR = 0, 1, 2
 NIRC_OUTPUT_RADIANCE, NIRC_OUTPUT_VISIBILITY, NIRC_OUTPUT_RADIANCE_OCCLUDED = 0, 1, 2
 

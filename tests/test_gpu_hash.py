@@ -22,6 +22,9 @@ pytestmark = pytest.mark.gpu
 PRECS = {"fp32": 0, "bf16": 1, "fp16": 2}
 GRAD_TOL = {"fp32": 1e-5, "bf16": 10 * 2.0 ** -9, "fp16": 10 * 2.0 ** -12}
 GRIDS = {"default": (18, 16, 1.5), "small": (10, 4, 1.5)}
+# 10,069 entries: an odd count, so the parameter vector's length is 2 mod 4 and the 4-wide Adam
+# and gradient-scaling passes run their ragged tails
+ODD_GRID = (10, 4, 1.4)
 
 
 @pytest.fixture(scope="module")
@@ -170,28 +173,34 @@ def test_hash_loss_grad(nirc, prec, grid, B, kind):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_hash_adam_step_matches_oracle(nirc, prec):
+@pytest.mark.parametrize("grid", [GRIDS["small"], ODD_GRID])
+def test_hash_adam_step_matches_oracle(nirc, prec, grid):
     # one Adam step from zero moments with the oracle's gradient given to both sides
     P, B = 2000, 4096
     pts = wl.make_points(47, P)
     lob = wl.make_lobes(47).packed()
-    model, w = _model(nirc, prec, GRIDS["small"], 47, max_batch=B)
+    model, w = _model(nirc, prec, grid, 47, max_batch=B)
+    assert model.n_params % 4 == (2 if grid == ODD_GRID else 0)
     sm = Samples(pts, lob, B, 48, 0, 0)
-    _, g = oracle.hash_loss_grad(pts, sm.idx, sm.d, sm.t, w.astype(np.float64), 64, GRIDS["small"])
+    _, g = oracle.hash_loss_grad(pts, sm.idx, sm.d, sm.t, w.astype(np.float64), 64, grid)
     g32 = g.astype(np.float32)
+    g32[-3:] = [3e-3, -2e-3, 1e-3]   # the last entries (a 4-wide pass's tail) take a step as well
     nirc.nirc_hash_adam_step(model, torch.from_numpy(g32).cuda())
     got = host(model.get_weights())
     wo = w.astype(np.float64)
     m = np.zeros_like(wo)
     v = np.zeros_like(wo)
+    w_start = w.astype(np.float64)
     oracle.adam(wo, m, v, g32.astype(np.float64), 1)
     np.testing.assert_allclose(got, wo, rtol=0, atol=2e-6)
+    assert np.all(np.abs(got[-3:] - w_start[-3:]) > 5e-4)
     assert model.read_flags() == 0
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_hash_nonfinite_gradient_skips_step(nirc, prec):
-    model, w = _model(nirc, prec, GRIDS["small"], 49, max_batch=16)
+@pytest.mark.parametrize("grid", [GRIDS["small"], ODD_GRID])
+def test_hash_nonfinite_gradient_skips_step(nirc, prec, grid):
+    model, w = _model(nirc, prec, grid, 49, max_batch=16)
     g = np.zeros(model.n_params, np.float32)
     g[-1] = np.nan
     nirc.nirc_hash_adam_step(model, torch.from_numpy(g).cuda())
