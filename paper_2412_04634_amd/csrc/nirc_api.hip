@@ -360,7 +360,7 @@ nirc_status tlmc_reference_occluded(nirc_points points, const nirc_lobes *field,
 // non-finite value.
 static nirc_status grad_into(nirc_model *model, const nirc_points &points, const nirc_queries &queries,
                              const float *target, const float *d_rgb, float *grad, float *loss, uint32_t *err,
-                             hipStream_t s) {
+                             char *ws, size_t ws_bytes, hipStream_t s) {
     nirc_status st = check_points(points);
     if (st == NIRC_OK) st = check_queries(queries, points);
     if (st != NIRC_OK) return st;
@@ -369,22 +369,22 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
     const int nb = grad_blocks(model->cfg.precision, queries.count);
     const bool var = target && model->cfg.loss == NIRC_LOSS_VAR;
     const WorkLayout wl(model->W, nb, var ? queries.count : 0);
-    if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
-    float *partials = (float *)(model->ws + wl.partials);
-    float *lpart = (float *)(model->ws + wl.loss_partials);
+    if (!ws || ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
+    float *partials = (float *)(ws + wl.partials);
+    float *lpart = (float *)(ws + wl.loss_partials);
     // 16-bit models: the batch size is folded into the loss scale, so that per-sample deltas stay
     // near unit magnitude in the 16-bit operands; the reduction divides it out again
     const float scale = h16 ? model->cfg.loss_scale * (float)queries.count : model->cfg.loss_scale;
     TrainArgs a{target, d_rgb, model->cfg.loss_eps, scale, model->cfg.loss, nullptr,
                 model->cfg.output == NIRC_OUTPUT_VISIBILITY};
     if (var) {   // the residual-variance loss needs F_r = mean(t - y) of this batch first
-        float *pred = (float *)(model->ws + wl.pred);
-        float *fr = (float *)(model->ws + wl.fr);
+        float *pred = (float *)(ws + wl.pred);
+        float *fr = (float *)(ws + wl.fr);
         const void *pk = h16 ? (const void *)model->packed16 : (const void *)model->packed;
         hipError_t e = launch_infer(model->W, model->cfg.precision, to_points(points), to_queries(queries, err), pk, pred,
                                     model->cfg.output == NIRC_OUTPUT_VISIBILITY, s);
         if (e == hipSuccess)
-            e = launch_residual_mean(pred, target, queries.count, (float *)(model->ws + wl.fr_part), fr, s);
+            e = launch_residual_mean(pred, target, queries.count, (float *)(ws + wl.fr_part), fr, s);
         if (e != hipSuccess) return NIRC_ERR_HIP;
         a.fr = fr;
     }
@@ -402,7 +402,7 @@ nirc_status nirc_loss_grad(nirc_model *model, nirc_points points, nirc_queries q
                            float *grad, float *loss, void *stream) {
     if (!model || !target) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss, model->flags, s);
+    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss, model->flags, model->ws, model->ws_bytes, s);
     if (st != NIRC_OK) return st;
     // a standalone gradient does not start a step: clear the step's flag again
     return hip_status(launch_fill_u32(model->bad, 1, 0u, s));
@@ -412,7 +412,7 @@ nirc_status nirc_backward(nirc_model *model, nirc_points points, nirc_queries qu
                           float *grad, void *stream) {
     if (!model || !d_rgb) return NIRC_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    nirc_status st = grad_into(model, points, queries, nullptr, d_rgb, grad, nullptr, model->flags, s);
+    nirc_status st = grad_into(model, points, queries, nullptr, d_rgb, grad, nullptr, model->flags, model->ws, model->ws_bytes, s);
     if (st != NIRC_OK) return st;
     return hip_status(launch_fill_u32(model->bad, 1, 0u, s));
 }
@@ -428,20 +428,27 @@ nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream) {
     return hip_status(e);
 }
 
-nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries queries, const float *target,
-                            float *loss, void *stream) {
+// Gradient into the workspace `ws`, then Adam on it.
+static nirc_status train_step_on(nirc_model *model, const nirc_points &points, const nirc_queries &queries,
+                                 const float *target, float *loss, char *ws, size_t ws_bytes, hipStream_t s) {
     if (!model || !target) return NIRC_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
     const WorkLayout wl(model->W, grad_blocks(model->cfg.precision, queries.count));
-    if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
-    float *grad = (float *)(model->ws + wl.grad);
-    float *wloss = (float *)(model->ws + wl.loss);
-    nirc_status st = grad_into(model, points, queries, target, nullptr, grad, loss ? loss : wloss, model->bad, s);
+    if (!ws || ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
+    float *grad = (float *)(ws + wl.grad);
+    float *wloss = (float *)(ws + wl.loss);
+    nirc_status st =
+        grad_into(model, points, queries, target, nullptr, grad, loss ? loss : wloss, model->bad, ws, ws_bytes, s);
     if (st != NIRC_OK) return st;
     hipError_t e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
                                model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps,
                                model->packed, model->packed16, model->cfg.precision, s);
     return hip_status(e);
+}
+
+nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries queries, const float *target,
+                            float *loss, void *stream) {
+    if (!model) return NIRC_ERR_INVALID_ARG;
+    return train_step_on(model, points, queries, target, loss, model->ws, model->ws_bytes, (hipStream_t)stream);
 }
 
 nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_lobes *field, int64_t batch,
