@@ -319,6 +319,19 @@ nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream);
 nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries queries,
                             const float *target, float *loss, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): nirc_train_step with its scratch (gradient partials,
+ * the reduced gradient, the loss, the residual-variance pre-pass) in a static device buffer of
+ * the library (9.3 MB per GPU, held until the process ends) instead of the model's workspace, so
+ * a model created without workspace can train.  Allocates nothing: no hipMalloc, no library
+ * allocation.  queries.count must be 1..NIRC_STATIC_MAX_BATCH (else NIRC_ERR_INVALID_ARG,
+ * before anything is enqueued).  Every call on one GPU shares that GPU's buffer: calls that
+ * overlap on one GPU (two streams, or two host threads) race and must be serialised by the
+ * caller.  Results are identical to nirc_train_step's on the same inputs. */
+#define NIRC_STATIC_MAX_BATCH 2048
+nirc_status nirc_train_step_static(nirc_model *model, nirc_points points, nirc_queries queries,
+                                   const float *target, float *loss, void *stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Frame statistics (FP64 on the device)                                                       */
 

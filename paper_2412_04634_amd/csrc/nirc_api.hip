@@ -1,5 +1,6 @@
 // C ABI of the NIRC library: argument validation, state/workspace layout and kernel launches.
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string.h>
 
@@ -449,6 +450,52 @@ nirc_status nirc_train_step(nirc_model *model, nirc_points points, nirc_queries 
                             float *loss, void *stream) {
     if (!model) return NIRC_ERR_INVALID_ARG;
     return train_step_on(model, points, queries, target, loss, model->ws, model->ws_bytes, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------------------------------
+// Training step without workspace: the gradient partials, reduced gradient and loss of one step
+// live in a static device array of the library.  Sized for NIRC_STATIC_MAX_BATCH samples at
+// width 128 (the larger layout): at most 32 partial slabs of 70,016 floats, the gradient, the
+// loss and the residual-variance pre-pass.  Each GPU holds its own copy at its own address;
+// host code reaches it only through the address hipGetSymbolAddress returns on that device.
+namespace {
+constexpr size_t cx_align(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int64_t kStaticSlabs = (NIRC_STATIC_MAX_BATCH + 63) / 64;
+constexpr size_t kStaticNp = 128 * 160 + 3 * 128 * 128 + 3 * 128;
+constexpr size_t kScratchBytes = cx_align(kStaticSlabs * kStaticNp * sizeof(float)) +
+                                 cx_align(kStaticSlabs * sizeof(float)) + cx_align(kStaticNp * sizeof(float)) +
+                                 cx_align(sizeof(float)) + cx_align((size_t)NIRC_STATIC_MAX_BATCH * 3 * sizeof(float)) +
+                                 cx_align((size_t)kFrBlocks * 3 * sizeof(float)) + cx_align(4 * sizeof(float));
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices];   // per device, set once with that device current
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+// The device address of this GPU's `scratch` (looked up once per device); NULL on failure.
+static char *scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+nirc_status nirc_train_step_static(nirc_model *model, nirc_points points, nirc_queries queries, const float *target,
+                                   float *loss, void *stream) {
+    if (!model || queries.count > NIRC_STATIC_MAX_BATCH) return NIRC_ERR_INVALID_ARG;
+    const WorkLayout wl(model->W, grad_blocks(model->cfg.precision, queries.count),
+                        var_rows(model->cfg, queries.count));
+    if (wl.total > kScratchBytes) return NIRC_ERR_INVALID_ARG;   // not reached for valid configurations
+    char *ws = scratch_on_current_device();
+    if (!ws) return NIRC_ERR_HIP;
+    // every part of the layout is written before it is read within the step: nothing to clear
+    return train_step_on(model, points, queries, target, loss, ws, kScratchBytes, (hipStream_t)stream);
 }
 
 nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_lobes *field, int64_t batch,

@@ -101,6 +101,7 @@ def lib():
             "nirc_backward": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
             "nirc_adam_step": (_i32, [_vp, _vp, _vp]),
             "nirc_train_step": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
+            "nirc_train_step_static": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
             "tlmc_reference_table": (_i32, [ctypes.POINTER(Lobes), _vp, _vp]),
             "tlmc_reference": (_i32, [_Points, ctypes.POINTER(Lobes), _vp, _vp, _vp]),
             "tlmc_frame_stats_scratch_bytes": (_sz, []),
@@ -392,6 +393,17 @@ def nirc_adam_step(model: Model, grad: torch.Tensor):
 def nirc_train_step(model: Model, points: Points, queries: Queries, target: torch.Tensor, loss=None):
     _check(lib().nirc_train_step(model.handle, points.c(), queries.c(), _ptr(target), _ptr(loss), _stream()),
            "nirc_train_step")
+    return loss
+
+
+NIRC_STATIC_MAX_BATCH = 2048
+
+
+def nirc_train_step_static(model: Model, points: Points, queries: Queries, target: torch.Tensor, loss=None):
+    """nirc_train_step on the library's static scratch (no workspace needed, nothing allocated;
+    batches up to NIRC_STATIC_MAX_BATCH; calls on one GPU must not overlap)."""
+    _check(lib().nirc_train_step_static(model.handle, points.c(), queries.c(), _ptr(target), _ptr(loss), _stream()),
+           "nirc_train_step_static")
     return loss
 
 
