@@ -209,7 +209,10 @@ nirc_status tlmc_sample_dirs(nirc_points points, int32_t n_cache, uint64_t seed,
  *   out_c  = (1/N) sum_k n(x, w_k)         (cache level, N = n_cache >= 1)
  *   out_r  = L(x, w_r) - n(x, w_r)          (residual)
  *   out_tl = out_c + out_r
- * Directions are generated in the kernel exactly as tlmc_sample_dirs returns them.  The
+ * Directions are generated in the kernel as tlmc_sample_dirs returns them: exactly for the FP32
+ * model and for every residual direction; the 16-bit models' cache directions take the
+ * hardware sine of the same uniforms (within ~1e-6 of the sampler's, far below their 16-bit
+ * operands; they never leave the kernel).  The
  * surface part of the first layer is computed once per point and shared by its N + 1 queries
  * (Sec. "Neural Network Architecture": amortised surface encoding).
  * L(x, w_r) is the residual sample's radiance (Sec. "Cache application": one path-traced

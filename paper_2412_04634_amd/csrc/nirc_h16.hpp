@@ -239,12 +239,18 @@ __device__ __forceinline__ void mlp16(f32x4 (&h)[T][W / 16], u32x4 (&hb)[T][W / 
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) h[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
+        // the wave's MFMA run at raised issue priority: the SIMD's other wave fills the gaps
+        // with its VALU work (measured: 1.5 % shorter estimates)
+        __builtin_amdgcn_s_setprio(1);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int kb = 0; kb < (layer == 0 ? DKB : 2); ++kb)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int tt = 0; tt < T; ++tt) h[tt][mt] = mfma16<PREC>(af[kb * MT + mt], bin[tt][kb], h[tt][mt]);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
         // prefetch the next layer's fragments (hidden layer `layer`, or the output copies)
         if (layer < 3) {
             const uint16_t *sec = sH + layer * (MT * KB * 512);
