@@ -10,6 +10,7 @@ All inputs are resident in HBM before timing starts.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import math
 import os
@@ -466,22 +467,61 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
     return out
 
 
-def serving_run(seconds):
+def serving_run(seconds, budget_frac=0.4):
     """16 render streams (resolutions 360p..4K, N in {4, 8, 32}, width-64 BF16 caches with their
-    own Adam state), Poisson arrivals at 240 frames/s, HBM-budget admission, continuous batching
-    into a graph-captured persistent launch, 4 training steps of 65,536 per frame."""
+    own Adam state and training workspace), Poisson arrivals at 240 frames/s, admission by an HBM
+    budget of `budget_frac` of what all streams would hold at once, continuous batching of each
+    mix's estimate and training into one replayed graph, 4 training steps of 65,536 per frame."""
+    import numpy as np
     from paper_2412_04634_amd import serve
-    st, sch, ex = serve.serve_run(seed=5, n_streams=16, rate_hz=240.0, duration_s=seconds, precision=1)
-    # the same streams one frame each: one batched launch vs one launch per stream (GPU time)
+    st, sch, ex = serve.serve_run(seed=5, n_streams=16, rate_hz=240.0, duration_s=seconds, precision=1,
+                                  budget_bytes=budget_frac)
+    st["budget_fraction"] = budget_frac
+    st["mean_train_batch"] = float(np.mean(sch.batch_sizes))
     import torch
     nirc = ex.nirc
     specs = serve.make_stream_specs(5, 16)
+    # the same frames run stream by stream: one frame of each stream alone (estimate + its
+    # training steps) timed on the GPU, summed over the frames each stream received
+    alone_ms = alone_frame_ms(nirc, ex, specs)
+    counts = collections.Counter(f.sid for f in sch.done)
+    serial_s = sum(alone_ms[sid] * n for sid, n in counts.items()) * 1e-3
+    st["stream_by_stream"] = {"gpu_s": serial_s, "queries_per_s": st["queries"] / serial_s,
+                              "frame_ms_by_stream": {str(k): v for k, v in sorted(alone_ms.items())}}
+    # the same streams one frame each: one batched launch vs one launch per stream (GPU time)
     st["one_frame_per_stream"] = batched_vs_separate(nirc, ex, specs)
     # small frames (16 streams of 640 x 360, N = 4), where one launch per stream leaves the GPU
     # partly idle
     small = [serve.StreamSpec(100 + i, 640, 360, 4, 5000 + i, 5500) for i in range(16)]
     st["small_frames_16x360p_n4"] = batched_vs_separate(nirc, ex, small)
     return st
+
+
+def alone_frame_ms(nirc, ex, specs, reps=3):
+    """GPU time of one frame of each stream on its own: tlmc_estimate, then nirc_train_frame."""
+    import torch
+    ex.prepare(specs)
+    out = {}
+    for s in specs:
+        if s.sid not in ex.streams:
+            ex.admit(s)
+        x = ex.streams[s.sid]
+        lob = x["lobes"].packed()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+        def one():
+            nirc.tlmc_estimate(x["model"], x["points"], lob, s.n_cache, s.seed, 0, out=x["out"])
+            nirc.nirc_train_frame(x["model"], x["points"], lob, ex.train_batch, ex.train_steps, s.seed, 0)
+        one()
+        torch.cuda.synchronize()
+        e[0].record()
+        for _ in range(reps):
+            one()
+        e[1].record()
+        torch.cuda.synchronize()
+        out[s.sid] = e[0].elapsed_time(e[1]) / reps
+        ex.release(s.sid)
+    return out
 
 
 def batched_vs_separate(nirc, ex, specs, reps=5):
@@ -530,7 +570,8 @@ def main():
                     help="only time training frames (S steps of B samples) of this model")
     ap.add_argument("--estimate-only", choices=["fp32", "bf16", "fp16", "hash-bf16"], default=None,
                     help="time only tlmc_estimate at this precision (for profiling runs)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
+    ap.add_argument("--serve-only", action="store_true", help="only the serving leg (16 streams)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the multi-stream serving run (0 to skip)")
     ap.add_argument("--precision-form", action="store_true",
                     help="also run the N x width x precision matrix of estimates")
@@ -560,6 +601,10 @@ def main():
     B, S = cfgw["train_batch"], cfgw["train_steps"]
     dev = "cuda"
     torch.cuda.set_device(0)
+
+    if args.serve_only:
+        print(json.dumps({"serving": serving_run(args.serve_seconds)}), flush=True)
+        return
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4

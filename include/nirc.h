@@ -278,6 +278,39 @@ nirc_status tlmc_batch_build(const tlmc_request *requests /* host */, int32_t n,
 nirc_status tlmc_estimate_batch(const void *list /* device */, int32_t width, int32_t precision, int32_t output,
                                 void *stream);
 
+/* Continuous batching of online training (several render streams, each with its own cache): one
+ * frame's training of each request of a work list, every step of all requests in one set of
+ * launches (samples, gradient, reduction, Adam, repack), so that a frame loop over many streams
+ * can replay one captured graph for the whole mix.  Host struct. */
+#define NIRC_TRAIN_BATCH_MAX_REQUESTS 64
+typedef struct {
+    nirc_model *model;     /* width 64, NIRC_BF16 or NIRC_FP16, loss other than NIRC_LOSS_VAR, created
+                              with a workspace of nirc_workspace_bytes(cfg, >= batch); at most once per list */
+    nirc_points points;
+    nirc_lobes field;      /* the frame's field (the training targets) */
+    int64_t batch;         /* samples per step, 1..max_batch */
+    uint64_t seed;
+    uint64_t frame;
+} nirc_train_request;
+
+/* Bytes of a training work list. */
+size_t nirc_train_list_bytes(void);
+
+/* Fill a training work list (host memory of nirc_train_list_bytes) for n requests
+ * (1..NIRC_TRAIN_BATCH_MAX_REQUESTS) whose models share width and precision; the caller copies it
+ * to device memory.  The list holds device pointers only (models, their workspaces, points). */
+nirc_status nirc_train_list_build(const nirc_train_request *requests, int32_t n, int64_t max_batch,
+                                  void *list /* host */);
+
+/* `steps` training steps of every request of a device work list: step s of request r is
+ * nirc_train_frame(model, points, field, batch, steps, seed, frame)'s step s, with bit-identical
+ * results (same samples, same gradient blocks, same reduction order; each model's own workspace),
+ * and the steps of all requests run together.  Losses are not returned.  precision must be the
+ * list's; max_batch bounds the list's batches and fixes the launch shapes, which do not depend on
+ * the list: a captured sequence can be replayed after writing another list to the same buffer. */
+nirc_status nirc_train_frame_batch(const void *list /* device */, int32_t steps, int32_t precision,
+                                   int64_t max_batch, void *stream);
+
 /* Reference integral of the occluded scene, F(x) = (1/pi) int V(x, w) L(x, w) (n . w) dw, by
  * tensor Gauss-Legendre quadrature with n_nodes (8..128) nodes per axis over the two uniforms of
  * the cosine-weighted map (whose pdf cancels the cosine); FP32 integrand, FP64 sums.  F is

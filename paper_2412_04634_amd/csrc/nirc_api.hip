@@ -578,6 +578,86 @@ nirc_status tlmc_estimate_batch(const void *list, int32_t width, int32_t precisi
     return NIRC_ERR_INVALID_ARG;
 }
 
+size_t nirc_train_list_bytes(void) { return sizeof(TrainDesc); }
+
+nirc_status nirc_train_list_build(const nirc_train_request *requests, int32_t n, int64_t max_batch, void *list) {
+    if (!requests || !list || n < 1 || n > NIRC_TRAIN_BATCH_MAX_REQUESTS || n > kBatchMaxRequests || max_batch < 1 ||
+        max_batch > INT32_MAX)
+        return NIRC_ERR_INVALID_ARG;
+    TrainDesc *d = (TrainDesc *)list;
+    memset(d, 0, sizeof(*d));
+    const nirc_model *m0 = requests[0].model;
+    if (!m0) return NIRC_ERR_INVALID_ARG;
+    if (m0->W != 64 || m0->cfg.precision == NIRC_FP32) return NIRC_ERR_UNSUPPORTED;
+    int64_t vb = 0;
+    for (int i = 0; i < n; ++i) {
+        const nirc_train_request &r = requests[i];
+        nirc_model *m = r.model;
+        if (!m || m->W != m0->W || m->cfg.precision != m0->cfg.precision) return NIRC_ERR_INVALID_ARG;
+        if (m->cfg.loss == NIRC_LOSS_VAR) return NIRC_ERR_UNSUPPORTED;
+        for (int j = 0; j < i; ++j)
+            if (requests[j].model == m) return NIRC_ERR_INVALID_ARG;   // one step of a model at a time
+        if (check_points(r.points) != NIRC_OK || r.points.count < 1) return NIRC_ERR_INVALID_ARG;
+        if (r.batch < 1 || r.batch > max_batch) return NIRC_ERR_INVALID_ARG;
+        const int nb = grad_blocks(m->cfg.precision, r.batch);
+        const WorkLayout wl(m->W, nb, 0, r.batch);
+        if (!m->ws || m->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
+        TrainReq &t = d->req[i];
+        t.pts = to_points(r.points);
+        t.lobes = r.field;
+        t.packed16 = m->packed16;
+        t.master = m->master;
+        t.m = m->m;
+        t.v = m->v;
+        t.step = m->step;
+        t.flags = m->flags;
+        t.bad = m->bad;
+        t.partials = (float *)(m->ws + wl.partials);
+        t.lpart = (float *)(m->ws + wl.loss_partials);
+        t.grad = (float *)(m->ws + wl.grad);
+        t.loss = (float *)(m->ws + wl.loss);
+        float *smp = (float *)(m->ws + wl.samples);
+        t.sp = (int32_t *)smp;
+        t.swx = smp + r.batch;
+        t.swy = t.swx + r.batch;
+        t.swz = t.swy + r.batch;
+        t.stgt = t.swz + r.batch;
+        t.batch = r.batch;
+        t.key0 = (uint32_t)r.seed;
+        t.key1 = (uint32_t)(r.seed >> 32);
+        t.frame = (uint32_t)r.frame;
+        t.nb = nb;
+        t.vb0 = (int32_t)vb;
+        vb += nb;
+        t.lr = m->cfg.lr;
+        t.b1 = m->cfg.beta1;
+        t.b2 = m->cfg.beta2;
+        t.eps = m->cfg.adam_eps;
+        t.loss_eps = m->cfg.loss_eps;
+        t.loss_scale = m->cfg.loss_scale;
+        t.loss_kind = m->cfg.loss;
+        t.output = m->cfg.output;
+    }
+    d->n = n;
+    d->total_vb = (int32_t)vb;
+    d->width = m0->W;
+    d->precision = m0->cfg.precision;
+    d->max_batch = max_batch;
+    return NIRC_OK;
+}
+
+nirc_status nirc_train_frame_batch(const void *list, int32_t steps, int32_t precision, int64_t max_batch,
+                                   void *stream) {
+    if (!list || steps < 0 || max_batch < 1 || max_batch > INT32_MAX) return NIRC_ERR_INVALID_ARG;
+    if (precision != NIRC_BF16 && precision != NIRC_FP16) return NIRC_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t k = 0; k < steps; ++k) {
+        const hipError_t e = launch_train_step_multi((const TrainDesc *)list, precision, (uint32_t)k, max_batch, s);
+        if (e != hipSuccess) return NIRC_ERR_HIP;
+    }
+    return NIRC_OK;
+}
+
 nirc_status tlmc_reference_table(const nirc_lobes *field, double *table, void *stream) {
     if (!field || !table) return NIRC_ERR_INVALID_ARG;
     for (int j = 0; j < 4; ++j)

@@ -166,11 +166,9 @@ hipError_t launch_reference_occluded(const Points &pts, const nirc_lobes &lobes,
 }
 
 // Training samples: one thread per sample.
-__global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint32_t key0,
-                              uint32_t key1, uint32_t frame, uint32_t step, int mode, int32_t *point,
-                              float *wx, float *wy, float *wz, float *target) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
+__device__ __forceinline__ void train_sample(const Points &pts, const nirc_lobes &lobes, uint32_t key0, uint32_t key1,
+                                             uint32_t frame, uint32_t step, int mode, int64_t b, int32_t *point,
+                                             float *wx, float *wy, float *wz, float *target) {
     const Rand4 r = philox((uint32_t)b, step, frame, (uint32_t)kStreamTrain, key0, key1);
     const int64_t p = (int64_t)(((uint64_t)r.r[0] * (uint64_t)pts.count) >> 32);
     float x, y, z;
@@ -190,6 +188,30 @@ __global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint3
     target[3 * b + 0] = L[0];
     target[3 * b + 1] = L[1];
     target[3 * b + 2] = L[2];
+}
+
+__global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint32_t key0,
+                              uint32_t key1, uint32_t frame, uint32_t step, int mode, int32_t *point,
+                              float *wx, float *wy, float *wz, float *target) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    train_sample(pts, lobes, key0, key1, frame, step, mode, b, point, wx, wy, wz, target);
+}
+
+// The training samples of step `step` of every request of a training work list (request
+// blockIdx.y), into each request's sample buffers.
+__global__ void k_train_batch_multi(const TrainDesc *__restrict__ desc, uint32_t step) {
+    if ((int)blockIdx.y >= desc->n) return;
+    const TrainReq &t = desc->req[blockIdx.y];
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= t.batch) return;
+    train_sample(t.pts, t.lobes, t.key0, t.key1, t.frame, step, t.output, b, t.sp, t.swx, t.swy, t.swz, t.stgt);
+}
+
+hipError_t launch_train_batch_multi(const TrainDesc *desc, uint32_t step, int64_t max_batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_train_batch_multi, dim3((unsigned)((max_batch + 255) / 256), kBatchMaxRequests), dim3(256), 0,
+                       s, desc, step);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------

@@ -9,9 +9,8 @@ namespace nirc {
 // After an Adam step (step != NULL) thread 0 also commits the step or records its skip.
 // (W is a template parameter so that the section search folds to constants.)
 template <int PREC, int W>
-__global__ void k_pack16(uint16_t *packed, const float *master, int total, int64_t *step, uint32_t *flags,
-                         uint32_t *bad) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pack16_elem(uint16_t *packed, const float *master, int total, int64_t *step,
+                                            uint32_t *flags, uint32_t *bad, int e) {
     if (e < total) {
         const int64_t s = h16_packed_source(W, e);
         const float v = s >= 0 ? master[s] * h16_packed_scale(W, e) : 0.0f;
@@ -22,6 +21,21 @@ __global__ void k_pack16(uint16_t *packed, const float *master, int total, int64
         else *step += 1;
         *bad = 0u;
     }
+}
+
+template <int PREC, int W>
+__global__ void k_pack16(uint16_t *packed, const float *master, int total, int64_t *step, uint32_t *flags,
+                         uint32_t *bad) {
+    pack16_elem<PREC, W>(packed, master, total, step, flags, bad, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The repack and step commit of every request of a training work list (request blockIdx.y).
+template <int PREC, int W>
+__global__ void k_pack16_multi(const TrainDesc *__restrict__ desc) {
+    if ((int)blockIdx.y >= desc->n) return;
+    const TrainReq &t = desc->req[blockIdx.y];
+    pack16_elem<PREC, W>(const_cast<uint16_t *>(t.packed16), t.master, H16Layout{W}.total(), t.step, t.flags, t.bad,
+                         blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int W>
@@ -557,6 +571,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *
 }
 
 // ------------------------------------------------------------------------------------------
+
+hipError_t launch_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s) {
+    if (W != 64) return hipErrorInvalidValue;
+    const int total = H16Layout{64}.total();
+    const dim3 grid((total + 255) / 256, kBatchMaxRequests), block(256);
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_pack16_multi<NIRC_BF16, 64>), grid, block, 0, s, desc);
+    else
+        hipLaunchKernelGGL((k_pack16_multi<NIRC_FP16, 64>), grid, block, 0, s, desc);
+    return hipGetLastError();
+}
 
 hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s, int64_t *step,
                          uint32_t *flags, uint32_t *bad) {

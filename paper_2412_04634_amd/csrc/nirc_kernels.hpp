@@ -367,6 +367,36 @@ struct BatchDesc {
     BatchRequest req[kBatchMaxRequests];
 };
 
+// Work list of a batched training step (several models, each with its own samples, workspace
+// and state): built on the host, read by the multi-request training kernels.
+struct TrainReq {
+    Points pts;
+    nirc_lobes lobes;
+    const uint16_t *packed16;            // the model's 16-bit copy (rewritten by the step)
+    float *master, *m, *v;
+    int64_t *step;
+    uint32_t *flags, *bad;
+    float *partials, *lpart, *grad, *loss;   // the model's workspace (WorkLayout of its batch)
+    int32_t *sp;                         // samples: point [B], wx, wy, wz [B], target [B][3]
+    float *swx, *swy, *swz, *stgt;
+    int64_t batch;
+    uint32_t key0, key1, frame;
+    int32_t nb;                          // gradient blocks of this request
+    int32_t vb0;                         // its first virtual block in the list
+    float lr, b1, b2, eps, loss_eps, loss_scale;
+    int32_t loss_kind, output;
+};
+
+struct TrainDesc {
+    int32_t n;
+    int32_t total_vb;
+    int32_t width;
+    int32_t precision;
+    int64_t max_batch;
+    int64_t pad;
+    TrainReq req[kBatchMaxRequests];
+};
+
 // ------------------------------------------------------------------------------------------
 // Launchers (return the launch status).
 hipError_t launch_pack(float *packed, const float *master, int W, hipStream_t s);
@@ -460,5 +490,13 @@ hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, h
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
                        float *packed, uint16_t *packed16, int prec, hipStream_t s);
+// One training step of every request of a device work list (width 64, 16-bit models): samples
+// of step `step`, gradient partials, reduction, Adam and the 16-bit repack with the step commit.
+// Launch shapes depend only on the list's capacity, so the sequence can be captured in a graph
+// and replayed over other lists.
+hipError_t launch_train_step_multi(const TrainDesc *desc, int prec, uint32_t step, int64_t max_batch, hipStream_t s);
+hipError_t launch_train_batch_multi(const TrainDesc *desc, uint32_t step, int64_t max_batch, hipStream_t s);
+hipError_t launch_reduce_adam_multi(const TrainDesc *desc, int W, hipStream_t s);
+hipError_t launch_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s);
 
 }  // namespace nirc

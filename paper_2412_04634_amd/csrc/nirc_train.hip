@@ -592,14 +592,13 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32_wide(Points pts, 
 // entry.  Block 0 also reduces the loss.
 constexpr int kReduceWaves = 16;
 
-__global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *__restrict__ partials,
-                                                                   const float *__restrict__ loss_partials,
-                                                                   int nblocks, int64_t np, float inv_scale,
-                                                                   float loss_norm, float *__restrict__ grad,
-                                                                   float *__restrict__ loss, uint32_t *bad) {
-    __shared__ float q[kReduceWaves][64];
+__device__ __forceinline__ void reduce_grad_block(const float *__restrict__ partials,
+                                                  const float *__restrict__ loss_partials, int nblocks, int64_t np,
+                                                  float inv_scale, float loss_norm, float *__restrict__ grad,
+                                                  float *__restrict__ loss, uint32_t *bad, int blk,
+                                                  float (*q)[64]) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t i = (int64_t)blk * 64 + lane;
     const int per = (nblocks + kReduceWaves - 1) / kReduceWaves;
     const int b0 = min(nblocks, wave * per), b1 = min(nblocks, b0 + per);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -623,7 +622,7 @@ __global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *
     }
     // the loss: lane-strided sums of the partials, then a fixed shuffle tree (one wave, so the
     // loads are in flight together rather than one dependent load per partial)
-    if (blockIdx.x == 0 && wave == 0) {
+    if (blk == 0 && wave == 0) {
         float t = 0.0f;
         for (int b = lane; b < nblocks; b += 64) t += loss_partials[b];
 #pragma unroll
@@ -636,16 +635,37 @@ __global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *
     }
 }
 
+__global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *__restrict__ partials,
+                                                                   const float *__restrict__ loss_partials,
+                                                                   int nblocks, int64_t np, float inv_scale,
+                                                                   float loss_norm, float *__restrict__ grad,
+                                                                   float *__restrict__ loss, uint32_t *bad) {
+    __shared__ float q[kReduceWaves][64];
+    reduce_grad_block(partials, loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad, blockIdx.x, q);
+}
+
+// The reduction of every request of a training work list (request blockIdx.y), with the scale
+// factors each request's own step uses (16-bit models: loss_scale * B).
+__global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad_multi(const TrainDesc *__restrict__ desc) {
+    __shared__ float q[kReduceWaves][64];
+    if ((int)blockIdx.y >= desc->n) return;
+    const TrainReq &t = desc->req[blockIdx.y];
+    const int64_t np = n_params(desc->width);
+    if ((int64_t)blockIdx.x * 64 >= np) return;
+    const float scale = t.loss_scale * (float)t.batch;
+    reduce_grad_block(t.partials, t.lpart, t.nb, np, 1.0f / scale, 1.0f / (3.0f * (float)t.batch), t.grad, t.loss,
+                      t.bad, blockIdx.x, q);
+}
+
 __global__ void k_check_finite(const float *__restrict__ grad, int64_t np, uint32_t *bad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < np && !isfinite(grad[i])) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
 }
 
 // Adam (Kingma & Ba) with bias correction, t = step + 1; skipped entirely when `bad` is set.
-__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                       const float *__restrict__ grad, const int64_t *step, const uint32_t *bad,
-                       int64_t np, float lr, float b1, float b2, float eps) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void adam_elem(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                          const float *__restrict__ grad, const int64_t *step, const uint32_t *bad,
+                                          int64_t np, float lr, float b1, float b2, float eps, int64_t i) {
     if (i >= np || *bad) return;
     const float t = (float)(*step + 1);
     const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
@@ -655,6 +675,20 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     m[i] = mi;
     v[i] = vi;
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ grad, const int64_t *step, const uint32_t *bad,
+                       int64_t np, float lr, float b1, float b2, float eps) {
+    adam_elem(w, m, v, grad, step, bad, np, lr, b1, b2, eps, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Adam of every request of a training work list (request blockIdx.y).
+__global__ void k_adam_multi(const TrainDesc *__restrict__ desc) {
+    if ((int)blockIdx.y >= desc->n) return;
+    const TrainReq &t = desc->req[blockIdx.y];
+    adam_elem(t.master, t.m, t.v, t.grad, t.step, t.bad, n_params(desc->width), t.lr, t.b1, t.b2, t.eps,
+              (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Repack the kernels' weight copy; thread 0 then commits the step (or records the skip).
@@ -772,6 +806,14 @@ hipError_t launch_adam(int W, float *master, float *m, float *v, const float *gr
     const int total = F32Layout{W}.total();
     hipLaunchKernelGGL(k_pack_commit, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
                        step, flags, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_adam_multi(const TrainDesc *desc, int W, hipStream_t s) {
+    const int64_t np = n_params(W);
+    hipLaunchKernelGGL(k_reduce_grad_multi, dim3((unsigned)((np + 63) / 64), kBatchMaxRequests),
+                       dim3(kReduceWaves * 64), 0, s, desc);
+    hipLaunchKernelGGL(k_adam_multi, dim3((unsigned)((np + 255) / 256), kBatchMaxRequests), dim3(256), 0, s, desc);
     return hipGetLastError();
 }
 

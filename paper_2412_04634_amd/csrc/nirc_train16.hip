@@ -71,17 +71,18 @@ __device__ inline float out_grad16(float z, float t, float dr, bool use_loss, fl
 // 16-bit rows [neuron][sample] in LDS (the ReLU masks come from the 16-bit activations).
 // Phase 2: each wave owns the same weight-gradient tiles as in the FP32 kernel and adds the
 // round with 16x16x32 MFMAs whose K dimension is the sample index.
+// Block `blk` of `nblk` over the batch (chunks blk, blk + nblk, ...): its partial gradient goes to
+// `out` [n_params], its loss partial to *loss_out.  smem: Grad16Lds<W>::kTotal 16-bit elements;
+// sLoss: kWaves16 floats.  Ends after a workgroup barrier, so a caller may run the next block on
+// the same LDS.
 template <int W, int PREC>
-__global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries q, const uint16_t *__restrict__ packed,
-                                                            TrainArgs args, float *__restrict__ partials,
-                                                            float *__restrict__ loss_partials) {
+__device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q, const uint16_t *packed,
+                                             const TrainArgs &args, float *out, float *loss_out, int64_t blk,
+                                             int64_t nblk, uint16_t *smem, float *sLoss) {
     static_assert(W == 64, "gradient kernel is laid out for width 64");
     constexpr H16Layout L{W};
     constexpr int MT = W / 16, KB = W / 32;
     using S = Grad16Lds<W>;
-    __shared__ u32x4 smem4[(S::kTotal + 7) / 8];
-    __shared__ float sLoss[kWaves16];
-    uint16_t *smem = (uint16_t *)smem4;
     uint16_t *sH = smem;
     uint16_t *sD = sH + S::kH;
     uint16_t *sD5 = sD + S::kD;
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries 
     float loss_acc = 0.0f;
 
     const int64_t n_chunks = (B + kChunk16 - 1) / kChunk16;
-    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+    for (int64_t chunk = blk; chunk < n_chunks; chunk += nblk) {
         // ---------------- phase 1: forward + backward of this wave's 16 samples
         {
             const uint16_t *pk = opaque(packed);
@@ -279,8 +280,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries 
         __syncthreads();
     }
 
-    // ---------------- write this workgroup's partial gradient (every entry exactly once)
-    float *out = partials + (int64_t)blockIdx.x * n_params(W);
+    // ---------------- write this block's partial gradient (every entry exactly once)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int input = wave + 4 * a;
@@ -309,7 +309,41 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries 
     if (threadIdx.x == 0) {
         float t = 0.0f;
         for (int w = 0; w < kWaves16; ++w) t += sLoss[w];
-        loss_partials[blockIdx.x] = t;
+        *loss_out = t;
+    }
+    __syncthreads();
+}
+
+template <int W, int PREC>
+__global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16(Points pts, Queries q, const uint16_t *__restrict__ packed,
+                                                            TrainArgs args, float *__restrict__ partials,
+                                                            float *__restrict__ loss_partials) {
+    __shared__ u32x4 smem4[(Grad16Lds<W>::kTotal + 7) / 8];
+    __shared__ float sLoss[kWaves16];
+    grad16_block<W, PREC>(pts, q, packed, args, partials + (int64_t)blockIdx.x * n_params(W),
+                          loss_partials + blockIdx.x, blockIdx.x, gridDim.x, (uint16_t *)smem4, sLoss);
+}
+
+// The gradient step of several models at once (continuous batching of the streams' training
+// passes): request r's workgroups are the virtual blocks vb0 .. vb0 + nb - 1 of the list, and a
+// fixed grid walks the virtual blocks in order.  Virtual block b of a request computes exactly
+// what block b of k_grad_h16 computes for that request alone (same chunks, same order), so the
+// partials, and everything after them, are bit-identical.
+template <int W, int PREC>
+__global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16_multi(const TrainDesc *__restrict__ desc) {
+    __shared__ u32x4 smem4[(Grad16Lds<W>::kTotal + 7) / 8];
+    __shared__ float sLoss[kWaves16];
+    const int n = desc->n, total = desc->total_vb;
+    for (int v = blockIdx.x; v < total; v += gridDim.x) {
+        int r = 0;
+        while (r + 1 < n && desc->req[r + 1].vb0 <= v) ++r;
+        const TrainReq &t = desc->req[r];
+        const int b = v - t.vb0;
+        const Queries q{t.swx, t.swy, t.swz, t.sp, t.batch, t.bad};
+        const TrainArgs a{t.stgt, nullptr, t.loss_eps, t.loss_scale * (float)t.batch, t.loss_kind, nullptr,
+                          t.output == NIRC_OUTPUT_VISIBILITY};
+        grad16_block<W, PREC>(t.pts, q, t.packed16, a, t.partials + (int64_t)b * n_params(W), t.lpart + b, b, t.nb,
+                              (uint16_t *)smem4, sLoss);
     }
 }
 
@@ -614,6 +648,19 @@ hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Quer
         hipLaunchKernelGGL((k_grad_h16<64, NIRC_FP16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, pk, a,
                            partials, loss_partials);
     return hipGetLastError();
+}
+
+hipError_t launch_train_step_multi(const TrainDesc *desc, int prec, uint32_t step, int64_t max_batch, hipStream_t s) {
+    hipError_t e = launch_train_batch_multi(desc, step, max_batch, s);
+    if (e != hipSuccess) return e;
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_grad_h16_multi<64, NIRC_BF16>), dim3(kMaxResidentBlocks), dim3(kWaves16 * 64), 0, s, desc);
+    else
+        hipLaunchKernelGGL((k_grad_h16_multi<64, NIRC_FP16>), dim3(kMaxResidentBlocks), dim3(kWaves16 * 64), 0, s, desc);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_reduce_adam_multi(desc, 64, s);
+    if (e == hipSuccess) e = launch_pack16_multi(desc, 64, prec, s);
+    return e;
 }
 
 // ------------------------------------------------------------------------------------------

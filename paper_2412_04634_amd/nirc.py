@@ -56,6 +56,11 @@ class _Request(ctypes.Structure):
                 ("frame", _u64), ("residual_radiance", _vp), ("out_tl", _vp), ("out_c", _vp), ("out_r", _vp)]
 
 
+class _TrainRequest(ctypes.Structure):
+    _fields_ = [("model", _vp), ("points", _Points), ("field", Lobes), ("batch", _i64), ("seed", _u64),
+                ("frame", _u64)]
+
+
 class HashGrid(ctypes.Structure):
     _fields_ = [("log2_table", _i32), ("base_res", _i32), ("growth", ctypes.c_float)]
 
@@ -111,6 +116,9 @@ def lib():
             "tlmc_batch_bytes": (_sz, []),
             "tlmc_batch_build": (_i32, [ctypes.POINTER(_Request), _i32, _vp]),
             "tlmc_estimate_batch": (_i32, [_vp, _i32, _i32, _i32, _vp]),
+            "nirc_train_list_bytes": (_sz, []),
+            "nirc_train_list_build": (_i32, [ctypes.POINTER(_TrainRequest), _i32, _i64, _vp]),
+            "nirc_train_frame_batch": (_i32, [_vp, _i32, _i32, _i64, _vp]),
             "nirc_train_frame": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i64, _i32, _u64, _u64, _vp, _vp]),
             "nirc_hash_entries": (_i64, [ctypes.POINTER(HashGrid)]),
             "nirc_hash_n_params": (_i64, [ctypes.POINTER(HashGrid)]),
@@ -287,11 +295,14 @@ class Model:
         _check(lib().nirc_get_state(self.handle, _ptr(out), out.numel(), _stream()), "nirc_get_state")
         return out
 
-    def set_state(self, blob: torch.Tensor):
-        """Restore a state written by get_state of a model of the same width (resume)."""
+    def set_state(self, blob: torch.Tensor, sync: bool = True):
+        """Restore a state written by get_state of a model of the same width (resume).  With
+        sync=False the copy stays enqueued: blob must then be a device tensor that lives on the
+        current stream until the copy has run."""
         b = blob.to(self.state.device).contiguous()
         _check(lib().nirc_set_state(self.handle, _ptr(b), b.numel(), _stream()), "nirc_set_state")
-        torch.cuda.current_stream().synchronize()   # b may be a temporary
+        if sync:
+            torch.cuda.current_stream().synchronize()   # b may be a temporary
 
     def read_flags(self) -> int:
         return int(lib().nirc_read_flags(self.handle, _stream()))
@@ -514,6 +525,48 @@ class Batch:
         _check(lib().tlmc_estimate_batch(ctypes.c_void_p(self.dev.data_ptr()), self.width, self.precision, self.output,
                                          _stream()),
                "tlmc_estimate_batch")
+
+
+NIRC_TRAIN_BATCH_MAX_REQUESTS = 64
+
+
+class TrainBatch:
+    """A reusable device work list for nirc_train_frame_batch (one frame's training of several
+    streams' caches in one set of launches)."""
+
+    def __init__(self, max_batch: int, device="cuda"):
+        self.nbytes = int(lib().nirc_train_list_bytes())
+        self.host = torch.zeros(self.nbytes, dtype=torch.uint8).pin_memory()
+        self.dev = torch.zeros(self.nbytes, dtype=torch.uint8, device=device)
+        self.max_batch = int(max_batch)
+        self.precision = None
+        self._keep = []
+        self._copied = None
+
+    def set(self, requests):
+        """requests: list of dicts with model, points, lobes, batch, seed, frame.  Writes the work
+        list to the device buffer on the current stream."""
+        n = len(requests)
+        if self._copied is not None:
+            self._copied.synchronize()   # the previous list's host-to-device copy has run
+        arr = (_TrainRequest * n)()
+        self._keep = list(requests)
+        for i, r in enumerate(requests):
+            lb = r["lobes"]
+            L = lb if isinstance(lb, Lobes) else lobes_struct(lb)
+            arr[i] = _TrainRequest(r["model"].handle.value, r["points"].c(), L, int(r["batch"]), int(r["seed"]),
+                                   int(r["frame"]))
+        _check(lib().nirc_train_list_build(arr, n, self.max_batch, ctypes.c_void_p(self.host.data_ptr())),
+               "nirc_train_list_build")
+        self.precision = requests[0]["model"].cfg.precision
+        self.dev.copy_(self.host, non_blocking=True)
+        self._copied = torch.cuda.Event()
+        self._copied.record()
+
+    def launch(self, steps: int, precision: int | None = None):
+        prec = self.precision if precision is None else precision
+        _check(lib().nirc_train_frame_batch(ctypes.c_void_p(self.dev.data_ptr()), steps, prec, self.max_batch,
+                                            _stream()), "nirc_train_frame_batch")
 
 
 class NircFunction(torch.autograd.Function):

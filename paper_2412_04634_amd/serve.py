@@ -1,14 +1,19 @@
 """Multi-stream serving of the two-level estimator: several render streams, each with its own
 cache (model + Adam state) resident on the GPU, frames arriving over time.
 
-* Admission by HBM budget: a stream is admitted (its points, outputs and model state are
-  allocated) only when its resident bytes fit in what the budget has left; a stream that has
-  no more frames releases its memory, and waiting streams are admitted in arrival order.
+* Admission by HBM budget: a stream is admitted (its points, outputs, model state and training
+  workspace are allocated) only when its resident bytes fit in what the budget has left.  When
+  the stream at the head of the waiting queue does not fit, idle resident streams (no frame
+  pending or in flight) are evicted, least recently used first: the training state goes to host
+  memory (the checkpoint blob) and comes back bit for bit when the stream is admitted again.  A
+  stream that has no more frames releases its memory for good.
 * Continuous batching: whenever the device can take more work, the oldest pending frame of
-  every admitted stream is put into one work list and estimated by one persistent launch
-  (tlmc_estimate_batch, replayed from a captured graph), then each of those streams takes its
-  training steps.  Frames that arrive meanwhile join the next batch.  A stream's frames stay in
-  order (frame f + 1 uses the weights trained after frame f).
+  every admitted stream is put into one estimate work list and one training work list; the
+  whole frame of the mix - one persistent estimate launch (tlmc_estimate_batch) and each
+  training step of all those streams at once (nirc_train_frame_batch) - is one captured graph,
+  replayed for every mix after the lists are rewritten.  Frames that arrive meanwhile join the
+  next batch.  A stream's frames stay in order (frame f + 1 uses the weights trained after
+  frame f).
 * Latency of a frame = GPU completion time of its training - its arrival time; reported as
   p50 / p99 with aggregate queries/s.
 
@@ -78,8 +83,9 @@ class Frame:
 
 class Scheduler:
     """Admission + continuous batching policy.  `executor` provides:
-         bytes_for(spec) -> int, admit(spec), release(sid),
-         submit(frames) -> handle, poll(handle) -> completion time (s) or None, now() -> s."""
+         bytes_for(spec) -> int, admit(spec), release(sid), evict(sid),
+         submit(frames) -> handle, poll(handle) -> completion time (s) or None, now() -> s.
+    admit() of an evicted stream restores the state evict() saved."""
 
     def __init__(self, specs, executor, budget_bytes: int, max_batch: int = 16, max_inflight: int = 2):
         self.specs = {s.sid: s for s in specs}
@@ -97,19 +103,40 @@ class Scheduler:
         self.remaining = collections.Counter()   # frames not yet arrived, per stream
         self.done = []
         self.admit_log = []
+        self.wait_since = {}     # sid -> time it started waiting for admission
+        self.admit_waits = []    # (sid, seconds waited for memory)
+        self.batch_sizes = []
+        self.last_used = {}      # sid -> time of its last launch (eviction order)
+        self.evictions = 0
+
+    def _evict_for(self, need):
+        """Evicts idle resident streams, least recently used first, until `need` bytes fit."""
+        idle = [sid for sid in self.admitted if not self.pending[sid] and sid not in self.busy]
+        idle.sort(key=lambda sid: self.last_used.get(sid, -1.0))
+        for sid in idle:
+            if self.used + need <= self.budget:
+                break
+            self.ex.evict(sid)
+            self.used -= self.ex.bytes_for(self.specs[sid])
+            self.admitted.discard(sid)
+            self.evictions += 1
 
     def _try_admit(self):
         keep = []
-        for sid in self.waiting:
+        for i, sid in enumerate(self.waiting):
             need = self.ex.bytes_for(self.specs[sid])
             if need > self.budget:
                 raise ValueError(f"stream {sid} needs {need} bytes, more than the whole budget")
+            if i == 0 and self.used + need > self.budget:
+                self._evict_for(need)   # room for the head of the queue
             if self.used + need <= self.budget:
                 self.ex.admit(self.specs[sid])
                 self.used += need
                 self.peak_used = max(self.peak_used, self.used)
                 self.admitted.add(sid)
-                self.admit_log.append((self.ex.now(), sid, self.used))
+                now = self.ex.now()
+                self.admit_log.append((now, sid, self.used))
+                self.admit_waits.append((sid, now - self.wait_since.pop(sid, now)))
             else:
                 keep.append(sid)
         self.waiting = keep
@@ -127,8 +154,11 @@ class Scheduler:
             return False
         ready.sort(key=lambda s: self.pending[s][0].arrival)
         frames = [self.pending[sid].popleft() for sid in ready[: self.max_batch]]
+        self.batch_sizes.append(len(frames))
+        now = self.ex.now()
         for f in frames:
             self.busy.add(f.sid)
+            self.last_used[f.sid] = now
         self.inflight.append((self.ex.submit(frames), frames))
         return True
 
@@ -148,6 +178,7 @@ class Scheduler:
                 self.remaining[sid] -= 1
                 if sid not in self.admitted and sid not in self.waiting:
                     self.waiting.append(sid)
+                    self.wait_since[sid] = t
                 i += 1
             self._release_idle()
             self._try_admit()
@@ -177,11 +208,20 @@ def latency_stats(frames):
             "mean_ms": float(lat.mean() * 1e3)}
 
 
+def latency_by_resolution(frames, specs):
+    """p50 / p99 frame latency per stream resolution."""
+    by = collections.defaultdict(list)
+    sp = {s.sid: s for s in specs}
+    for f in frames:
+        by[f"{sp[f.sid].width}x{sp[f.sid].height}"].append(f)
+    return {k: latency_stats(v) for k, v in sorted(by.items(), key=lambda kv: sp[kv[1][0].sid].points)}
+
+
 class GpuExecutor:
     """Runs admitted streams on the GPU with the NIRC library: per-stream resident points,
-    outputs and model (FP32 master + Adam + 16-bit copy), a training workspace shared by all
-    models (their training launches are serialized on one stream), and a captured graph of the
-    persistent batched estimator."""
+    outputs, model (FP32 master + Adam + 16-bit copy) and training workspace, and one captured
+    graph of a whole frame of the mix (the persistent batched estimate, then every training step
+    of all the mix's streams together)."""
 
     def __init__(self, precision: int = 1, train_batch: int = 65536, train_steps: int = 4, width: int = 64,
                  use_graph: bool = True):
@@ -194,18 +234,20 @@ class GpuExecutor:
         self.train_batch = train_batch
         self.train_steps = train_steps
         self.state_bytes = nirc.nirc_state_bytes(self.cfg)
-        wsb = nirc.nirc_workspace_bytes(self.cfg, train_batch)
-        self.workspace = torch.empty(wsb, dtype=torch.uint8, device="cuda")
-        self.fixed_bytes = wsb
+        self.workspace_bytes = nirc.nirc_workspace_bytes(self.cfg, train_batch)
+        self.fixed_bytes = 0
         self.streams = {}
-        # two work lists (and graphs) used alternately, so that writing the next list never
-        # races the copy or the launch of the previous one
+        # two pairs of work lists (and graphs) used alternately, so that writing the next lists
+        # never races the copy or the launch of the previous ones
         self.batches = [nirc.Batch(), nirc.Batch()]
+        self.train_lists = [nirc.TrainBatch(train_batch), nirc.TrainBatch(train_batch)]
         self.graphs = [None, None]
         self.turn = 0
         self.use_graph = use_graph
         self.keep_final = False
         self.final = {}
+        self.swapped = {}     # sid -> training state of an evicted stream (pinned host memory)
+        self.restores = 0
         self.queries = 0
         self.submits = 0
         self.host_points = {}
@@ -233,8 +275,8 @@ class GpuExecutor:
         self.t0 = time.perf_counter()
 
     def bytes_for(self, spec: StreamSpec) -> int:
-        # points (7 x FP32) + F_tl output (3 x FP32) + model state
-        return spec.points * (7 + 3) * 4 + self.state_bytes
+        # points (7 x FP32) + F_tl output (3 x FP32) + model state + its training workspace
+        return spec.points * (7 + 3) * 4 + self.state_bytes + self.workspace_bytes
 
     def admit(self, spec: StreamSpec):
         torch, nirc = self.torch, self.nirc
@@ -244,9 +286,26 @@ class GpuExecutor:
         dev.copy_(host, non_blocking=True)
         lobes, w0 = self.host_stream[spec.sid]
         st = dict(spec=spec, points=nirc.Points(list(dev.unbind(0))), lobes=lobes,
-                  model=nirc.Model(w0, cfg=self.cfg, max_batch=0, workspace=self.workspace),
+                  model=nirc.Model(w0, cfg=self.cfg, max_batch=self.train_batch),
                   out=torch.empty((spec.points, 3), dtype=torch.float32, device="cuda"))
+        saved = self.swapped.pop(spec.sid, None)
+        if saved is not None:   # an evicted stream comes back with its training state
+            blob = torch.empty(saved.shape, dtype=torch.uint8, device="cuda")
+            blob.copy_(saved, non_blocking=True)
+            st["model"].set_state(blob, sync=False)
+            st["restored_from"] = blob   # kept until the stream leaves (the copy is stream-ordered)
+            self.restores += 1
         self.streams[spec.sid] = st
+
+    def evict(self, sid: int):
+        """Moves an idle stream's training state to pinned host memory and frees its device
+        memory (stream-ordered: the copy runs after the stream's last frame)."""
+        torch = self.torch
+        st = self.streams.pop(sid)
+        blob = st["model"].get_state()
+        host = torch.empty(blob.shape, dtype=torch.uint8).pin_memory()
+        host.copy_(blob, non_blocking=True)
+        self.swapped[sid] = host
 
     def release(self, sid: int):
         st = self.streams.pop(sid, None)
@@ -267,27 +326,30 @@ class GpuExecutor:
             self.queries += st["spec"].points * (st["spec"].n_cache + 1)
             reqs.append(dict(model=st["model"], points=st["points"], lobes=st["lobes"].rotated(f.index).packed(),
                              n_cache=st["spec"].n_cache, seed=st["spec"].seed, frame=f.index, out_tl=st["out"]))
+        treqs = [dict(model=r["model"], points=r["points"], lobes=r["lobes"], batch=self.train_batch, seed=r["seed"],
+                      frame=r["frame"]) for r in reqs]
         k = self.turn
         self.turn ^= 1
         self.submits += 1
-        batch = self.batches[k]
+        batch, tlist = self.batches[k], self.train_lists[k]
         batch.set(reqs)
+        tlist.set(treqs)
         if self.use_graph:
             if self.graphs[k] is None:
-                batch.launch()   # the first use of a list runs eagerly, then its launch is captured
+                # the first use of a pair of lists runs eagerly, then the frame is captured
+                batch.launch()
+                tlist.launch(self.train_steps)
                 torch.cuda.synchronize()
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, stream=torch.cuda.Stream()):
                     batch.launch()
+                    tlist.launch(self.train_steps)
                 self.graphs[k] = g
             else:
                 self.graphs[k].replay()
         else:
             batch.launch()
-        for f, r in zip(frames, reqs):
-            st = self.streams[f.sid]
-            nirc.nirc_train_frame(st["model"], st["points"], r["lobes"], self.train_batch, self.train_steps,
-                                  st["spec"].seed, f.index)
+            tlist.launch(self.train_steps)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record()
         return ev
@@ -304,8 +366,7 @@ def run_alone(executor: GpuExecutor, spec: StreamSpec, n_frames: int):
     torch, nirc, wl = executor.torch, executor.nirc, executor.wl
     pts = nirc.Points.from_workload(wl.make_points(spec.scene_seed, spec.points))
     lobes = wl.make_lobes(spec.seed)
-    model = nirc.Model(wl.make_weights(spec.seed, executor.width), cfg=executor.cfg, max_batch=0,
-                       workspace=executor.workspace)
+    model = nirc.Model(wl.make_weights(spec.seed, executor.width), cfg=executor.cfg, max_batch=executor.train_batch)
     out = torch.empty((spec.points, 3), dtype=torch.float32, device="cuda")
     for f in range(n_frames):
         lob = lobes.rotated(f).packed()
@@ -325,6 +386,8 @@ def serve_run(seed: int = 5, n_streams: int = 16, rate_hz: float = 240.0, durati
     arrivals = poisson_arrivals(seed, rate_hz, duration_s, len(specs))
     if budget_bytes is None:
         budget_bytes = ex.fixed_bytes + sum(ex.bytes_for(s) for s in specs)
+    elif budget_bytes < 1.0:   # a fraction of what all streams would hold at once
+        budget_bytes = int(ex.fixed_bytes + budget_bytes * sum(ex.bytes_for(s) for s in specs))
     sch = Scheduler(specs, ex, budget_bytes - ex.fixed_bytes)
     ex.prepare(specs)
     ex.reset_clock()
@@ -338,5 +401,11 @@ def serve_run(seed: int = 5, n_streams: int = 16, rate_hz: float = 240.0, durati
                "frames_per_s": len(done) / makespan, "batches": ex.submits,
                "mean_batch": len(done) / max(ex.submits, 1),
                "peak_resident_bytes": sch.peak_used + ex.fixed_bytes, "budget_bytes": budget_bytes,
+               "all_streams_bytes": ex.fixed_bytes + sum(ex.bytes_for(s) for s in specs),
+               "admissions": len(sch.admit_log), "evictions": sch.evictions,
+               "admission_wait_ms": {"mean": float(np.mean([w for _, w in sch.admit_waits]) * 1e3),
+                                     "p99": float(np.percentile([w for _, w in sch.admit_waits], 99) * 1e3),
+                                     "max": float(max(w for _, w in sch.admit_waits) * 1e3)},
+               "latency_by_resolution": latency_by_resolution(done, specs),
                "host_wall_s": ex.now() - t0})
     return st, sch, ex

@@ -27,6 +27,10 @@ class SimExecutor:
     def release(self, sid):
         del self.resident[sid]
 
+    def evict(self, sid):
+        del self.resident[sid]
+        self.evicted = getattr(self, "evicted", 0) + 1
+
     def now(self):
         return self.t
 
@@ -89,3 +93,19 @@ def test_poisson_rate_and_uniform_streams():
     for _, s in arr:
         counts[s] += 1
     assert min(counts) > 0.6 * len(arr) / 16
+
+
+def test_tight_budget_evicts_idle_streams_and_bounds_latency():
+    # a budget of a third of all streams: idle streams are evicted for waiting ones, so no stream
+    # waits for another's last frame; every frame completes, in order, within the budget
+    specs = serve.make_stream_specs(5, 16)
+    arr = serve.poisson_arrivals(6, 240.0, 3.0, 16)
+    ex = SimExecutor(per_frame=0.002)
+    total = sum(ex.bytes_for(s) for s in specs)
+    sch = serve.Scheduler(specs, ex, budget_bytes=total // 3)
+    done = sch.run(arr)
+    assert len(done) == len(arr)
+    assert sch.peak_used <= total // 3
+    assert sch.evictions > 0 and ex.evicted == sch.evictions
+    lat = serve.latency_stats(done)
+    assert lat["p99_ms"] < 200.0, lat
