@@ -90,7 +90,12 @@ typedef struct nirc_model nirc_model;   /* opaque host handle */
 
 /* Host struct.  Adam hyper-parameters follow Kingma & Ba; the paper trains with Adam, several
  * steps per frame (Sec. "Results").  loss_eps is the epsilon of the relative L2 loss (eq. 12).
- * loss_scale multiplies the loss before the backward pass and divides the gradient after it. */
+ * loss_scale multiplies the loss before the backward pass and divides the gradient after it; for
+ * BF16 and FP16 models it is taken per sample (times the batch size, so that 16-bit deltas stay
+ * near unit size).  FP16 models scale dynamically: loss_scale is the starting value, a training
+ * step skipped for a non-finite gradient halves the scale, 1000 finite steps in a row double it
+ * (within [2^-14, 2^24]); nirc_read_loss_scale returns the current value, and the training state
+ * (nirc_get_state) carries it. */
 typedef struct {
     int32_t width;       /* hidden width: 64 or 128 (the batched estimator: 64 only) */
     int32_t precision;   /* NIRC_FP32 | NIRC_BF16 | NIRC_FP16 */
@@ -181,6 +186,10 @@ nirc_status nirc_set_state(nirc_model *model, const void *blob, size_t blob_byte
 uint32_t nirc_read_flags(const nirc_model *model, void *stream);
 nirc_status nirc_clear_flags(nirc_model *model, void *stream);
 
+/* The model's current loss scale (the dynamic one of FP16 models, else loss_scale); reads it
+ * synchronously on `stream`; -1 on error. */
+float nirc_read_loss_scale(const nirc_model *model, void *stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Inference                                                                                   */
 
@@ -242,6 +251,25 @@ nirc_status tlmc_estimate_biased(const nirc_model *model, nirc_points points,
                                  const nirc_lobes *field /* host */, int32_t n_cache, uint64_t seed,
                                  uint64_t frame, const float *residual_radiance /* nullable */,
                                  float *out_b, float *out_c, int32_t *out_continue, void *stream);
+
+/* The estimator with the fusions of the paper's inference pipeline undone, for measuring what
+ * each buys (Sec. "Neural Network Architecture": the pipeline comparison of shared surface
+ * encodings, the direction encoding fused into the network, and direct output from on-chip
+ * memory).  Every stage computes the estimate of tlmc_estimate (same directions and features;
+ * sums in another order):
+ *   stage 0: one kernel writes every query's 160 encoded inputs (16-bit MFMA operands) to the
+ *            workspace, the network kernel reads them and writes one prediction per query, a
+ *            third kernel forms F_c, F_r and F_tl per point;
+ *   stage 1: as 0, the surface inputs encoded once per point and shared by its N + 1 queries;
+ *   stage 2: as 1, the directions drawn and encoded inside the network kernel;
+ *   stage 3: tlmc_estimate itself.
+ * BF16 / FP16 models of width 64 with NIRC_OUTPUT_RADIANCE; the field is required.  workspace:
+ * 256-byte aligned, tlmc_unfused_workspace_bytes (0 for stage 3, and for invalid arguments or
+ * more than 2^32 queries). */
+size_t tlmc_unfused_workspace_bytes(int64_t points, int32_t n_cache, int32_t stage);
+nirc_status tlmc_estimate_unfused(const nirc_model *model, nirc_points points, const nirc_lobes *field /* host */,
+                                  int32_t n_cache, uint64_t seed, uint64_t frame, int32_t stage, void *workspace,
+                                  size_t workspace_bytes, float *out_tl, float *out_c, float *out_r, void *stream);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Continuous batching of estimates (several render streams, each with its own cache)         */

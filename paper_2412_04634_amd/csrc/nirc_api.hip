@@ -17,9 +17,9 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 bool width_ok(int32_t w) { return w == 64 || w == 128; }
 
 // State layout (each piece 256-byte aligned): master | m | v | packed FP32 | packed 16-bit (BF16
-// and FP16 models only) | step | flags | bad.
+// and FP16 models only) | step | flags | bad | loss scale (FP32) and good-step count (uint32).
 struct StateLayout {
-    size_t master, m, v, packed, packed16, step, flags, bad, total;
+    size_t master, m, v, packed, packed16, step, flags, bad, scale, total;
     StateLayout(int W, int prec) {
         const size_t np = (size_t)n_params(W) * sizeof(float);
         size_t o = 0;
@@ -32,6 +32,7 @@ struct StateLayout {
         step = o; o += align_up(sizeof(int64_t));
         flags = o; o += align_up(sizeof(uint32_t));
         bad = o; o += align_up(sizeof(uint32_t));
+        scale = o; o += align_up(2 * sizeof(uint32_t));
         total = o;
     }
 };
@@ -98,8 +99,13 @@ struct nirc_model {
     uint16_t *packed16;   // NULL for FP32 models
     int64_t *step;
     uint32_t *flags, *bad;
+    float *scale;          // the current loss scale (dynamic for FP16 models)
+    uint32_t *good;        // finite steps since the scale last changed
     char *ws;
     size_t ws_bytes;
+    // FP16 models scale their loss dynamically; BF16 and FP32 keep cfg.loss_scale
+    float *dyn() const { return cfg.precision == NIRC_FP16 ? scale : nullptr; }
+    uint32_t *dyn_good() const { return cfg.precision == NIRC_FP16 ? good : nullptr; }
 };
 
 extern "C" {
@@ -166,6 +172,8 @@ nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes,
     m->step = (int64_t *)(base + sl.step);
     m->flags = (uint32_t *)(base + sl.flags);
     m->bad = (uint32_t *)(base + sl.bad);
+    m->scale = (float *)(base + sl.scale);
+    m->good = (uint32_t *)(base + sl.scale + sizeof(float));
     m->ws = (char *)workspace;
     m->ws_bytes = workspace ? workspace_bytes : 0;
     st = nirc_set_weights(m, init_w, stream);
@@ -195,6 +203,9 @@ nirc_status nirc_set_weights(nirc_model *model, const float *w, void *stream) {
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->m, model->np, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->v, model->np, 0u, s);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->step, 2, 0u, s);
+    // the loss scale starts again from the configured one
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->scale, 1, __builtin_bit_cast(uint32_t, model->cfg.loss_scale), s);
+    if (e == hipSuccess) e = launch_fill_u32(model->good, 1, 0u, s);
     if (e == hipSuccess) e = launch_pack(model->packed, model->master, model->W, s);
     if (e == hipSuccess && model->packed16)
         e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
@@ -243,6 +254,15 @@ uint32_t nirc_read_flags(const nirc_model *model, void *stream) {
     if (hipMemcpyAsync(&f, model->flags, sizeof(f), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
         return 0xFFFFFFFFu;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return 0xFFFFFFFFu;
+    return f;
+}
+
+float nirc_read_loss_scale(const nirc_model *model, void *stream) {
+    if (!model) return -1.0f;
+    float f = 0.0f;
+    if (hipMemcpyAsync(&f, model->scale, sizeof(f), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
+        return -1.0f;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return -1.0f;
     return f;
 }
 
@@ -377,7 +397,7 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
     // near unit magnitude in the 16-bit operands; the reduction divides it out again
     const float scale = h16 ? model->cfg.loss_scale * (float)queries.count : model->cfg.loss_scale;
     TrainArgs a{target, d_rgb, model->cfg.loss_eps, scale, model->cfg.loss, nullptr,
-                model->cfg.output == NIRC_OUTPUT_VISIBILITY};
+                model->cfg.output == NIRC_OUTPUT_VISIBILITY, model->dyn()};
     if (var) {   // the residual-variance loss needs F_r = mean(t - y) of this batch first
         float *pred = (float *)(ws + wl.pred);
         float *fr = (float *)(ws + wl.fr);
@@ -395,7 +415,8 @@ static nirc_status grad_into(nirc_model *model, const nirc_points &points, const
                                               partials, lpart, nb, s);
     if (e != hipSuccess) return NIRC_ERR_HIP;
     const float loss_norm = 1.0f / (3.0f * (float)queries.count);
-    e = launch_reduce_grad(model->W, partials, lpart, nb, 1.0f / scale, loss_norm, grad, loss, model->bad, s);
+    e = launch_reduce_grad(model->W, partials, lpart, nb, 1.0f / scale, loss_norm, grad, loss, model->bad, s,
+                           model->dyn(), (float)queries.count);
     return hip_status(e);
 }
 
@@ -442,7 +463,7 @@ static nirc_status train_step_on(nirc_model *model, const nirc_points &points, c
     if (st != NIRC_OK) return st;
     hipError_t e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
                                model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps,
-                               model->packed, model->packed16, model->cfg.precision, s);
+                               model->packed, model->packed16, model->cfg.precision, s, model->dyn(), model->dyn_good());
     return hip_status(e);
 }
 
@@ -578,6 +599,30 @@ nirc_status tlmc_estimate_batch(const void *list, int32_t width, int32_t precisi
     return NIRC_ERR_INVALID_ARG;
 }
 
+size_t tlmc_unfused_workspace_bytes(int64_t points, int32_t n_cache, int32_t stage) {
+    if (points < 0 || points > INT32_MAX || n_cache < 1 || n_cache > 4096 || stage < 0 || stage > 3) return 0;
+    if (points * (int64_t)(n_cache + 1) > (int64_t)UINT32_MAX) return 0;
+    return stage == 3 ? 0 : ablation_workspace_bytes(points, n_cache, stage);
+}
+
+nirc_status tlmc_estimate_unfused(const nirc_model *model, nirc_points points, const nirc_lobes *field,
+                                  int32_t n_cache, uint64_t seed, uint64_t frame, int32_t stage, void *workspace,
+                                  size_t workspace_bytes, float *out_tl, float *out_c, float *out_r, void *stream) {
+    if (!model || !field || stage < 0 || stage > 3) return NIRC_ERR_INVALID_ARG;
+    if (model->W != 64 || !model->packed16 || model->cfg.output != NIRC_OUTPUT_RADIANCE) return NIRC_ERR_UNSUPPORTED;
+    if (stage == 3)
+        return tlmc_estimate(model, points, field, n_cache, seed, frame, nullptr, out_tl, out_c, out_r, stream);
+    nirc_status st = check_points(points);
+    if (st != NIRC_OK) return st;
+    if (n_cache < 1 || n_cache > 4096 || (points.count > 0 && !out_tl)) return NIRC_ERR_INVALID_ARG;
+    const size_t need = tlmc_unfused_workspace_bytes(points.count, n_cache, stage);
+    if (need == 0 && points.count > 0) return NIRC_ERR_INVALID_ARG;
+    if (points.count > 0 && (!workspace || workspace_bytes < need || ((uintptr_t)workspace % kAlign) != 0))
+        return NIRC_ERR_WORKSPACE;
+    return hip_status(launch_ablation(model->cfg.precision, stage, to_points(points), *field, model->packed16, n_cache,
+                                      seed, frame, (char *)workspace, out_tl, out_c, out_r, (hipStream_t)stream));
+}
+
 size_t nirc_train_list_bytes(void) { return sizeof(TrainDesc); }
 
 nirc_status nirc_train_list_build(const nirc_train_request *requests, int32_t n, int64_t max_batch, void *list) {
@@ -637,6 +682,8 @@ nirc_status nirc_train_list_build(const nirc_train_request *requests, int32_t n,
         t.loss_scale = m->cfg.loss_scale;
         t.loss_kind = m->cfg.loss;
         t.output = m->cfg.output;
+        t.dyn_scale = m->dyn();
+        t.good_steps = m->dyn_good();
     }
     d->n = n;
     d->total_vb = (int32_t)vb;

@@ -10,23 +10,36 @@ namespace nirc {
 // (W is a template parameter so that the section search folds to constants.)
 template <int PREC, int W>
 __device__ __forceinline__ void pack16_elem(uint16_t *packed, const float *master, int total, int64_t *step,
-                                            uint32_t *flags, uint32_t *bad, int e) {
+                                            uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good,
+                                            int e) {
     if (e < total) {
         const int64_t s = h16_packed_source(W, e);
         const float v = s >= 0 ? master[s] * h16_packed_scale(W, e) : 0.0f;
         packed[e] = (uint16_t)(pack2<PREC>(v, 0.0f) & 0xFFFFu);
     }
     if (step && e == 0) {
-        if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
-        else *step += 1;
+        const uint32_t b = *bad;
+        if (b) {
+            *flags |= b;   // the step's NIRC_FLAG_* bits
+            if (dyn_scale && (b & NIRC_FLAG_NONFINITE_GRAD)) {   // back off
+                *dyn_scale = fmaxf(*dyn_scale * 0.5f, kLossScaleMin);
+                *good = 0u;
+            }
+        } else {
+            *step += 1;
+            if (dyn_scale && ++*good >= kLossScaleGrowth) {
+                *dyn_scale = fminf(*dyn_scale * 2.0f, kLossScaleMax);
+                *good = 0u;
+            }
+        }
         *bad = 0u;
     }
 }
 
 template <int PREC, int W>
 __global__ void k_pack16(uint16_t *packed, const float *master, int total, int64_t *step, uint32_t *flags,
-                         uint32_t *bad) {
-    pack16_elem<PREC, W>(packed, master, total, step, flags, bad, blockIdx.x * blockDim.x + threadIdx.x);
+                         uint32_t *bad, float *dyn_scale, uint32_t *good) {
+    pack16_elem<PREC, W>(packed, master, total, step, flags, bad, dyn_scale, good, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // The repack and step commit of every request of a training work list (request blockIdx.y).
@@ -35,7 +48,7 @@ __global__ void k_pack16_multi(const TrainDesc *__restrict__ desc) {
     if ((int)blockIdx.y >= desc->n) return;
     const TrainReq &t = desc->req[blockIdx.y];
     pack16_elem<PREC, W>(const_cast<uint16_t *>(t.packed16), t.master, H16Layout{W}.total(), t.step, t.flags, t.bad,
-                         blockIdx.x * blockDim.x + threadIdx.x);
+                         t.dyn_scale, t.good_steps, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int W>
@@ -114,25 +127,6 @@ template <int W>
 struct Tlmc16Lds {
     static constexpr int kSlab = TlmcLds<W>::kSlab + 48 + (lds_weights(W) ? 4 * 64 * 4 + 4 * 64 * 2 : 0);   // floats
 };
-
-// Cosine-weighted direction from uniforms (u1, u2) about a unit normal, with the hardware sine
-// and cosine of 2 pi u2 (argument in revolutions; absolute error ~1e-6, far below the 16-bit
-// operands the direction feeds).  Used for the cache directions of the 16-bit estimators, whose
-// directions never leave the kernel; residual directions keep the exact map of cosine_dir.
-__device__ __forceinline__ void cosine_dir_fast(float nx, float ny, float nz, float u1, float u2, float &wx,
-                                                float &wy, float &wz) {
-    const float r = __builtin_amdgcn_sqrtf(u1);
-    const float lx = r * __builtin_amdgcn_cosf(u2), ly = r * __builtin_amdgcn_sinf(u2);
-    const float lz = __builtin_amdgcn_sqrtf(1.0f - u1);
-    const float s = nz >= 0.0f ? 1.0f : -1.0f;
-    const float a = -__builtin_amdgcn_rcpf(s + nz);
-    const float b = nx * ny * a;
-    const float tx = 1.0f + s * nx * nx * a, ty = s * b, tz = -s * nx;
-    const float by = s + ny * ny * a;
-    wx = lx * tx + ly * b + lz * nx;
-    wy = lx * ty + ly * by + lz * ny;
-    wz = lx * tz - ly * ny + lz * nz;
-}
 
 // The 16-bit estimators' direction batch: as gen_dirs_batch (same counters, same slots), with the
 // group's normals read from the slab (nrm, staged once per group) instead of global memory,
@@ -584,18 +578,18 @@ hipError_t launch_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream
 }
 
 hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s, int64_t *step,
-                         uint32_t *flags, uint32_t *bad) {
+                         uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good) {
     if (W != 64 && W != 128) return hipErrorInvalidValue;
     const int total = H16Layout{W}.total();
     const dim3 grid((total + 255) / 256), block(256);
     if (prec == NIRC_BF16 && W == 64)
-        hipLaunchKernelGGL((k_pack16<NIRC_BF16, 64>), grid, block, 0, s, packed, master, total, step, flags, bad);
+        hipLaunchKernelGGL((k_pack16<NIRC_BF16, 64>), grid, block, 0, s, packed, master, total, step, flags, bad, dyn_scale, good);
     else if (prec == NIRC_BF16)
-        hipLaunchKernelGGL((k_pack16<NIRC_BF16, 128>), grid, block, 0, s, packed, master, total, step, flags, bad);
+        hipLaunchKernelGGL((k_pack16<NIRC_BF16, 128>), grid, block, 0, s, packed, master, total, step, flags, bad, dyn_scale, good);
     else if (W == 64)
-        hipLaunchKernelGGL((k_pack16<NIRC_FP16, 64>), grid, block, 0, s, packed, master, total, step, flags, bad);
+        hipLaunchKernelGGL((k_pack16<NIRC_FP16, 64>), grid, block, 0, s, packed, master, total, step, flags, bad, dyn_scale, good);
     else
-        hipLaunchKernelGGL((k_pack16<NIRC_FP16, 128>), grid, block, 0, s, packed, master, total, step, flags, bad);
+        hipLaunchKernelGGL((k_pack16<NIRC_FP16, 128>), grid, block, 0, s, packed, master, total, step, flags, bad, dyn_scale, good);
     return hipGetLastError();
 }
 

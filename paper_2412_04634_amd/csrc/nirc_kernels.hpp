@@ -385,6 +385,8 @@ struct TrainReq {
     int32_t vb0;                         // its first virtual block in the list
     float lr, b1, b2, eps, loss_eps, loss_scale;
     int32_t loss_kind, output;
+    float *dyn_scale;                    // FP16: the model's dynamic loss scale, else NULL
+    uint32_t *good_steps;                // FP16: finite steps since the last change of the scale
 };
 
 struct TrainDesc {
@@ -402,7 +404,8 @@ struct TrainDesc {
 hipError_t launch_pack(float *packed, const float *master, int W, hipStream_t s);
 // Packs the 16-bit copy; with step/flags/bad (after Adam) it also commits the step.
 hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s,
-                         int64_t *step = nullptr, uint32_t *flags = nullptr, uint32_t *bad = nullptr);
+                         int64_t *step = nullptr, uint32_t *flags = nullptr, uint32_t *bad = nullptr,
+                         float *dyn_scale = nullptr, uint32_t *good_steps = nullptr);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_encode(const Points &pts, const Queries &q, float *feat, hipStream_t s);
@@ -462,7 +465,14 @@ struct TrainArgs {
     int32_t loss_kind;     // NIRC_LOSS_*
     const float *fr;       // NIRC_LOSS_VAR: batch estimate of F_r per channel [3], else NULL
     int32_t sig;           // sigmoid outputs (the visibility cache) instead of exp
+    const float *dyn_scale;   // FP16 models: the current dynamic loss scale (device), which
+                              // replaces loss_scale as dyn_scale * B; NULL: loss_scale as given
 };
+
+// Dynamic loss scaling of FP16 models: a step skipped for a non-finite gradient halves the scale,
+// kLossScaleGrowth finite steps in a row double it, within [kLossScaleMin, kLossScaleMax].
+constexpr uint32_t kLossScaleGrowth = 1000;
+constexpr float kLossScaleMin = 0x1p-14f, kLossScaleMax = 0x1p24f;
 // NIRC_LOSS_VAR: fr[c] = mean over the batch of t - y (y: the model's predictions [B][3]),
 // summed in a fixed order; part holds kFrBlocks x 3 doubles.
 constexpr int kFrBlocks = 256;
@@ -474,9 +484,11 @@ hipError_t launch_grad_partials16(int W, int prec, const Points &pts, const Quer
 hipError_t launch_grad_partials(int W, const Points &pts, const Queries &q, const float *packed,
                                 TrainArgs a, float *partials, float *loss_partials, int nblocks,
                                 hipStream_t s);
+// dyn_scale (nullable): the gradient is divided by dyn_scale * dyn_batch instead of multiplied by
+// inv_scale.
 hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_partials, int nblocks,
                               float inv_scale, float loss_norm, float *grad, float *loss,
-                              uint32_t *bad, hipStream_t s);
+                              uint32_t *bad, hipStream_t s, const float *dyn_scale = nullptr, float dyn_batch = 1.0f);
 hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStream_t s);
 hipError_t launch_reduce_grad_n(int64_t np, const float *partials, const float *loss_partials, int nblocks,
                                 float inv_scale, float loss_norm, float *grad, float *loss, uint32_t *bad,
@@ -489,13 +501,19 @@ hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, h
 // FP32 models, only the 16-bit copy for 16-bit models) and the step commit.
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
-                       float *packed, uint16_t *packed16, int prec, hipStream_t s);
+                       float *packed, uint16_t *packed16, int prec, hipStream_t s, float *dyn_scale = nullptr,
+                       uint32_t *good_steps = nullptr);
 // One training step of every request of a device work list (width 64, 16-bit models): samples
 // of step `step`, gradient partials, reduction, Adam and the 16-bit repack with the step commit.
 // Launch shapes depend only on the list's capacity, so the sequence can be captured in a graph
 // and replayed over other lists.
 hipError_t launch_train_step_multi(const TrainDesc *desc, int prec, uint32_t step, int64_t max_batch, hipStream_t s);
 hipError_t launch_train_batch_multi(const TrainDesc *desc, uint32_t step, int64_t max_batch, hipStream_t s);
+// The estimator with its fusions undone (stages 0..2; 16-bit, width 64), for measuring them.
+size_t ablation_workspace_bytes(int64_t P, int n_cache, int stage);
+hipError_t launch_ablation(int prec, int stage, const Points &pts, const nirc_lobes &lobes, const uint16_t *packed,
+                           int n_cache, uint64_t seed, uint64_t frame, char *ws, float *out_tl, float *out_c,
+                           float *out_r, hipStream_t s);
 hipError_t launch_reduce_adam_multi(const TrainDesc *desc, int W, hipStream_t s);
 hipError_t launch_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s);
 

@@ -596,7 +596,8 @@ __device__ __forceinline__ void reduce_grad_block(const float *__restrict__ part
                                                   const float *__restrict__ loss_partials, int nblocks, int64_t np,
                                                   float inv_scale, float loss_norm, float *__restrict__ grad,
                                                   float *__restrict__ loss, uint32_t *bad, int blk,
-                                                  float (*q)[64]) {
+                                                  float (*q)[64], const float *dyn_scale, float dyn_batch) {
+    if (dyn_scale) inv_scale = 1.0f / (*dyn_scale * dyn_batch);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blk * 64 + lane;
     const int per = (nblocks + kReduceWaves - 1) / kReduceWaves;
@@ -639,9 +640,11 @@ __global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad(const float *
                                                                    const float *__restrict__ loss_partials,
                                                                    int nblocks, int64_t np, float inv_scale,
                                                                    float loss_norm, float *__restrict__ grad,
-                                                                   float *__restrict__ loss, uint32_t *bad) {
+                                                                   float *__restrict__ loss, uint32_t *bad,
+                                                                   const float *dyn_scale, float dyn_batch) {
     __shared__ float q[kReduceWaves][64];
-    reduce_grad_block(partials, loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad, blockIdx.x, q);
+    reduce_grad_block(partials, loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad, blockIdx.x, q,
+                      dyn_scale, dyn_batch);
 }
 
 // The reduction of every request of a training work list (request blockIdx.y), with the scale
@@ -654,7 +657,7 @@ __global__ __launch_bounds__(kReduceWaves * 64) void k_reduce_grad_multi(const T
     if ((int64_t)blockIdx.x * 64 >= np) return;
     const float scale = t.loss_scale * (float)t.batch;
     reduce_grad_block(t.partials, t.lpart, t.nb, np, 1.0f / scale, 1.0f / (3.0f * (float)t.batch), t.grad, t.loss,
-                      t.bad, blockIdx.x, q);
+                      t.bad, blockIdx.x, q, t.dyn_scale, (float)t.batch);
 }
 
 __global__ void k_check_finite(const float *__restrict__ grad, int64_t np, uint32_t *bad) {
@@ -781,10 +784,10 @@ hipError_t launch_grad_partials(int W, const Points &pts, const Queries &q, cons
 
 hipError_t launch_reduce_grad(int W, const float *partials, const float *loss_partials, int nblocks,
                               float inv_scale, float loss_norm, float *grad, float *loss,
-                              uint32_t *bad, hipStream_t s) {
+                              uint32_t *bad, hipStream_t s, const float *dyn_scale, float dyn_batch) {
     const int64_t np = n_params(W);
     hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 63) / 64)), dim3(kReduceWaves * 64), 0, s, partials,
-                       loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad);
+                       loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad, dyn_scale, dyn_batch);
     return hipGetLastError();
 }
 
@@ -796,13 +799,14 @@ hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStrea
 
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
-                       float *packed, uint16_t *packed16, int prec, hipStream_t s) {
+                       float *packed, uint16_t *packed16, int prec, hipStream_t s, float *dyn_scale,
+                       uint32_t *good_steps) {
     const int64_t np = n_params(W);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad,
                        step, bad, np, lr, b1, b2, eps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (packed16) return launch_pack16(packed16, master, W, prec, s, step, flags, bad);
+    if (packed16) return launch_pack16(packed16, master, W, prec, s, step, flags, bad, dyn_scale, good_steps);
     const int total = F32Layout{W}.total();
     hipLaunchKernelGGL(k_pack_commit, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
                        step, flags, bad);
@@ -822,7 +826,7 @@ hipError_t launch_reduce_grad_n(int64_t np, const float *partials, const float *
                                 float inv_scale, float loss_norm, float *grad, float *loss, uint32_t *bad,
                                 hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((np + 63) / 64)), dim3(kReduceWaves * 64), 0, s, partials,
-                       loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad);
+                       loss_partials, nblocks, np, inv_scale, loss_norm, grad, loss, bad, (const float *)nullptr, 1.0f);
     return hipGetLastError();
 }
 

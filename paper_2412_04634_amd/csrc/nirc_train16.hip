@@ -91,8 +91,10 @@ __device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const int64_t B = q.count;
     const bool use_loss = args.target != nullptr;
-    // the host passes loss_scale * B for 16-bit models: k = 2 loss_scale / 3 per sample
-    const float kscale = use_loss ? 2.0f * args.loss_scale / (3.0f * (float)B) : args.loss_scale;
+    // the host passes loss_scale * B for 16-bit models (or the dynamic scale is taken times B):
+    // k = 2 loss_scale / 3 per sample
+    const float ls = args.dyn_scale ? *args.dyn_scale * (float)B : args.loss_scale;
+    const float kscale = use_loss ? 2.0f * ls / (3.0f * (float)B) : ls;
 
     f32x4 g1[3][MT], gh[3][MT], g5;
 #pragma unroll
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16_multi(const TrainDes
         const int b = v - t.vb0;
         const Queries q{t.swx, t.swy, t.swz, t.sp, t.batch, t.bad};
         const TrainArgs a{t.stgt, nullptr, t.loss_eps, t.loss_scale * (float)t.batch, t.loss_kind, nullptr,
-                          t.output == NIRC_OUTPUT_VISIBILITY};
+                          t.output == NIRC_OUTPUT_VISIBILITY, t.dyn_scale};
         grad16_block<W, PREC>(t.pts, q, t.packed16, a, t.partials + (int64_t)b * n_params(W), t.lpart + b, b, t.nb,
                               (uint16_t *)smem4, sLoss);
     }
@@ -383,7 +385,8 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_grad_h16_wide(Points pts, Que
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const int64_t B = q.count;
     const bool use_loss = args.target != nullptr;
-    const float kscale = use_loss ? 2.0f * args.loss_scale / (3.0f * (float)B) : args.loss_scale;
+    const float ls = args.dyn_scale ? *args.dyn_scale * (float)B : args.loss_scale;
+    const float kscale = use_loss ? 2.0f * ls / (3.0f * (float)B) : ls;
 
     constexpr int NACC = SWEEP == 0 ? 3 * 2 * MT : 3 * MT + 2;
     f32x4 acc[NACC];

@@ -92,6 +92,7 @@ def lib():
             "nirc_set_state": (_i32, [_vp, _vp, _sz, _vp]),
             "nirc_read_flags": (_u32, [_vp, _vp]),
             "nirc_clear_flags": (_i32, [_vp, _vp]),
+            "nirc_read_loss_scale": (ctypes.c_float, [_vp, _vp]),
             "nirc_encode": (_i32, [_Points, _Queries, _vp, _vp]),
             "nirc_infer": (_i32, [_vp, _Points, _Queries, _vp, _vp]),
             "tlmc_sample_dirs": (_i32, [_Points, _i32, _u64, _u64, _vp, _vp]),
@@ -116,6 +117,9 @@ def lib():
             "tlmc_batch_bytes": (_sz, []),
             "tlmc_batch_build": (_i32, [ctypes.POINTER(_Request), _i32, _vp]),
             "tlmc_estimate_batch": (_i32, [_vp, _i32, _i32, _i32, _vp]),
+            "tlmc_unfused_workspace_bytes": (_sz, [_i64, _i32, _i32]),
+            "tlmc_estimate_unfused": (_i32, [_vp, _Points, ctypes.POINTER(Lobes), _i32, _u64, _u64, _i32, _vp, _sz,
+                                             _vp, _vp, _vp, _vp]),
             "nirc_train_list_bytes": (_sz, []),
             "nirc_train_list_build": (_i32, [ctypes.POINTER(_TrainRequest), _i32, _i64, _vp]),
             "nirc_train_frame_batch": (_i32, [_vp, _i32, _i32, _i64, _vp]),
@@ -307,6 +311,10 @@ class Model:
     def read_flags(self) -> int:
         return int(lib().nirc_read_flags(self.handle, _stream()))
 
+    def read_loss_scale(self) -> float:
+        """The current loss scale (dynamic for FP16 models); synchronises the stream."""
+        return float(lib().nirc_read_loss_scale(self.handle, _stream()))
+
     def clear_flags(self):
         _check(lib().nirc_clear_flags(self.handle, _stream()), "nirc_clear_flags")
 
@@ -346,6 +354,30 @@ def tlmc_estimate(model: Model, points: Points, lobes, n_cache: int, seed: int, 
         assert residual.dtype == torch.float32 and residual.is_contiguous() and residual.numel() == 3 * points.count
     _check(lib().tlmc_estimate(model.handle, points.c(), None if L is None else ctypes.byref(L), n_cache, seed,
                                frame, _ptr(residual), _ptr(tl), _ptr(c), _ptr(r), _stream()), "tlmc_estimate")
+    return (tl, c, r) if parts else tl
+
+
+def tlmc_unfused_workspace_bytes(points: int, n_cache: int, stage: int) -> int:
+    return int(lib().tlmc_unfused_workspace_bytes(points, n_cache, stage))
+
+
+def tlmc_estimate_unfused(model: Model, points: Points, lobes, n_cache: int, seed: int, frame: int, stage: int,
+                          workspace=None, parts: bool = False, out=None):
+    """The estimate with the pipeline fusions undone up to `stage` (0: every query's encoded
+    inputs through memory, 1: + surface encoding shared per point, 2: + direction encoding in the
+    network kernel, 3: the fused estimator).  workspace: a device byte tensor of at least
+    tlmc_unfused_workspace_bytes (allocated here if None)."""
+    dev = points.t[0].device
+    L = lobes if isinstance(lobes, Lobes) else lobes_struct(lobes)
+    need = tlmc_unfused_workspace_bytes(points.count, n_cache, stage)
+    if workspace is None and need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    tl = out if out is not None else torch.empty((points.count, 3), dtype=torch.float32, device=dev)
+    c = torch.empty_like(tl) if parts else None
+    r = torch.empty_like(tl) if parts else None
+    _check(lib().tlmc_estimate_unfused(model.handle, points.c(), ctypes.byref(L), n_cache, seed, frame, stage,
+                                       _ptr(workspace), 0 if workspace is None else workspace.numel(), _ptr(tl),
+                                       _ptr(c), _ptr(r), _stream()), "tlmc_estimate_unfused")
     return (tl, c, r) if parts else tl
 
 
