@@ -463,9 +463,34 @@ hipError_t launch_hash_pack16(uint16_t *packed, const float *master, int prec, h
                               uint32_t *flags = nullptr, uint32_t *bad = nullptr);
 hipError_t launch_hash_pack32(float *packed, const float *master, hipStream_t s, int64_t *step = nullptr,
                               uint32_t *flags = nullptr, uint32_t *bad = nullptr);
+// Grid-entry gradients are summed in fixed point (integer adds are associative, so the sum does
+// not depend on the order the atomics land in): each contribution v (already multiplied by the
+// loss scale, so of order one) is added as round(v 2^kGridFix) to a 64-bit accumulator; a
+// non-finite or out-of-range contribution raises *nonfinite instead.
+constexpr int kGridFix = 36;
+struct GridAcc {
+    unsigned long long *acc;   // [2 entries] 64-bit two's-complement sums
+    uint32_t *nonfinite;       // raised (1) when a contribution cannot be represented
+};
+
+__device__ __forceinline__ void grid_acc_add(const GridAcc &g, size_t i, float v) {
+    if (v == 0.0f) return;
+    const float x = v * 0x1p36f;
+    if (!(fabsf(x) < 0x1p62f)) {   // also catches NaN
+        atomicOr(g.nonfinite, 1u);
+        return;
+    }
+    atomicAdd(g.acc + i, (unsigned long long)llrintf(x));
+}
+
+// grad[i] = (acc[i] 2^-kGridFix) * scale for i < n, or NaN everywhere when *nonfinite; raises
+// `bad` on a non-finite result.
+hipError_t launch_grid_acc_finish(const GridAcc &g, float *grad, int64_t n, float scale, uint32_t *bad,
+                                  hipStream_t s);
+
 hipError_t launch_hash_grad32(const Points &pts, const Queries &q, const float *packed, const float *table,
                               const HashGridArgs &grid, TrainArgs a, float *partials, float *loss_partials,
-                              float *gtab, int nblocks, hipStream_t s);
+                              GridAcc gacc, int nblocks, hipStream_t s);
 hipError_t launch_hash_infer32(const Points &pts, const Queries &q, const float *packed, const float *table,
                                const HashGridArgs &grid, float *rgb, hipStream_t s);
 hipError_t launch_hash_tlmc32(const Points &pts, const nirc_lobes &lobes, const float *packed, const float *table,
@@ -480,6 +505,6 @@ hipError_t launch_hash_tlmc(int prec, const Points &pts, const nirc_lobes &lobes
 // atomics into gtab ([entries][2], zeroed by the caller); both carry the loss scale of `a`.
 hipError_t launch_hash_grad(int prec, const Points &pts, const Queries &q, const uint16_t *packed, const float *table,
                             const HashGridArgs &grid, TrainArgs a, float *partials, float *loss_partials,
-                            float *gtab, int nblocks, hipStream_t s);
+                            GridAcc gacc, int nblocks, hipStream_t s);
 
 }  // namespace nirc

@@ -33,14 +33,18 @@ struct HashState {
 
 // Workspace: MLP partials [nblocks][16,576] | loss partials [nblocks] | gradient [np] | loss |
 // training samples of nirc_hash_train_frame (point [B], wx, wy, wz [B], target [B][3]).
+// Workspace: MLP partials | loss partials | gradient [np] | loss | grid-gradient fixed-point
+// accumulators [np - kHashMlp] int64 and their non-finite flag | samples of the frame loop.
 struct HashWork {
-    size_t partials, loss_partials, grad, loss, samples, total;
+    size_t partials, loss_partials, grad, loss, gacc, gflag, samples, total;
     HashWork(int64_t np, int nblocks, int64_t sample_batch = 0) {
         size_t o = 0;
         partials = o; o += align_up((size_t)nblocks * kHashMlp * sizeof(float));
         loss_partials = o; o += align_up((size_t)nblocks * sizeof(float));
         grad = o; o += align_up((size_t)np * sizeof(float));
         loss = o; o += align_up(sizeof(float));
+        gacc = o; o += align_up((size_t)(np - kHashMlp) * sizeof(unsigned long long));
+        gflag = o; o += align_up(sizeof(uint32_t));
         samples = o; o += align_up((size_t)sample_batch * 7 * sizeof(float));
         total = o;
     }
@@ -268,17 +272,19 @@ static nirc_status hash_grad_into(nirc_hash_model *model, const nirc_points &poi
     const TrainArgs a{target, nullptr, model->cfg.loss_eps, scale, model->cfg.loss, nullptr, 0};
     const int64_t nt = model->np - kHashMlp;
     float *gtab = grad + kHashMlp;
-    hipError_t e = launch_fill_u32((uint32_t *)gtab, nt, 0u, s);
+    const GridAcc ga{(unsigned long long *)(model->ws + wl.gacc), (uint32_t *)(model->ws + wl.gflag)};
+    hipError_t e = launch_fill_u32((uint32_t *)ga.acc, 2 * nt, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(ga.nonfinite, 1, 0u, s);
     if (e == hipSuccess)
         e = model->cfg.precision == NIRC_FP32
                 ? launch_hash_grad32(pts_of(points), queries_of(queries, err), model->packed32(), model->table(),
-                                     model->grid, a, partials, lpart, gtab, nb, s)
+                                     model->grid, a, partials, lpart, ga, nb, s)
                 : launch_hash_grad(model->cfg.precision, pts_of(points), queries_of(queries, err), model->packed16,
-                                   model->table(), model->grid, a, partials, lpart, gtab, nb, s);
+                                   model->table(), model->grid, a, partials, lpart, ga, nb, s);
     if (e == hipSuccess)
         e = launch_reduce_grad_n(kHashMlp, partials, lpart, nb, 1.0f / scale, 1.0f / (3.0f * (float)queries.count),
                                  grad, loss, model->bad, s);
-    if (e == hipSuccess) e = launch_scale_check(gtab, nt, 1.0f / scale, model->bad, s);
+    if (e == hipSuccess) e = launch_grid_acc_finish(ga, gtab, nt, 1.0f / scale, model->bad, s);
     return hip_st(e);
 }
 

@@ -917,6 +917,23 @@ __global__ void k_scale_check4(float *__restrict__ g, int64_t n, float scale, ui
     if (bad && !fin) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
 }
 
+__global__ void k_grid_acc_finish(const unsigned long long *__restrict__ acc, const uint32_t *__restrict__ nonfinite,
+                                  float *__restrict__ g, int64_t n, float scale, uint32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = *nonfinite ? __builtin_nanf("") : __ll2float_rn((long long)acc[i]) * 0x1p-36f * scale;
+    g[i] = v;
+    if (bad && !isfinite(v)) atomicOr(bad, NIRC_FLAG_NONFINITE_GRAD);
+}
+
+hipError_t launch_grid_acc_finish(const GridAcc &ga, float *grad, int64_t n, float scale, uint32_t *bad,
+                                  hipStream_t s) {
+    static_assert(kGridFix == 36, "the finish kernel scales by 2^-36");
+    hipLaunchKernelGGL(k_grid_acc_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ga.acc, ga.nonfinite,
+                       grad, n, scale, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s) {
     if (aligned16(g)) {
         const int64_t groups = (n + 3) / 4;
@@ -953,7 +970,7 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_hash_grad_f32(Points pts, 
                                                                     HashGridArgs grid, TrainArgs args,
                                                                     float *__restrict__ partials,
                                                                     float *__restrict__ loss_partials,
-                                                                    float *__restrict__ gtab) {
+                                                                    GridAcc gacc) {
     constexpr int W = 64, MT = 4, KQ = 4;
     using S = HashGrad32Lds;
     __shared__ f32x4 smem4[(S::kTotal + 3) / 4];
@@ -1201,7 +1218,7 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_hash_grad_f32(Points pts, 
                 const HashCell cell = hash_cell(row[24], row[25], row[26], lv.res);
                 float w;
                 const uint32_t e = hash_entry(lv, grid.tmask, cell, corner, w);
-                if (dv != 0.0f) unsafeAtomicAdd(gtab + 2 * (size_t)e + f, w * dv);
+                grid_acc_add(gacc, 2 * (size_t)e + f, w * dv);
             }
         }
         __syncthreads();   // the next chunk's rows overwrite the staging
@@ -1236,10 +1253,10 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_hash_grad_f32(Points pts, 
 
 hipError_t launch_hash_grad32(const Points &pts, const Queries &q, const float *packed, const float *table,
                               const HashGridArgs &grid, TrainArgs a, float *partials, float *loss_partials,
-                              float *gtab, int nblocks, hipStream_t s) {
+                              GridAcc gacc, int nblocks, hipStream_t s) {
     if (!a.target) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_hash_grad_f32, dim3(nblocks), dim3(kTrainWaves * 64), 0, s, pts, q, packed,
-                       (const float2 *)table, grid, a, partials, loss_partials, gtab);
+                       (const float2 *)table, grid, a, partials, loss_partials, gacc);
     return hipGetLastError();
 }
 

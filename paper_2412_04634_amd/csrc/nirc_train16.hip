@@ -689,7 +689,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_hash_grad_h16(Points pts, Que
                                                                  const float2 *__restrict__ table, HashGridArgs grid,
                                                                  TrainArgs args, float *__restrict__ partials,
                                                                  float *__restrict__ loss_partials,
-                                                                 float *__restrict__ gtab) {
+                                                                 GridAcc gacc) {
     constexpr int MT = 4, KB = 2, W = 64;
     using S = HashGrad16Lds;
     __shared__ u32x4 smem4[(S::kTotal + 7) / 8];
@@ -882,7 +882,7 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_hash_grad_h16(Points pts, Que
                     const HashCell cell = hash_cell(row[24], row[25], row[26], lv.res);
                     float w;
                     const uint32_t e = hash_entry(lv, grid.tmask, cell, corner, w);
-                    if (d != 0.0f) unsafeAtomicAdd(gtab + 2 * (size_t)e + f, w * d);
+                    grid_acc_add(gacc, 2 * (size_t)e + f, w * d);
                 }
             }
         }
@@ -947,15 +947,15 @@ __global__ __launch_bounds__(kWaves16 * 64) void k_hash_grad_h16(Points pts, Que
 
 hipError_t launch_hash_grad(int prec, const Points &pts, const Queries &q, const uint16_t *packed, const float *table,
                             const HashGridArgs &grid, TrainArgs a, float *partials, float *loss_partials,
-                            float *gtab, int nblocks, hipStream_t s) {
+                            GridAcc gacc, int nblocks, hipStream_t s) {
     if (!a.target) return hipErrorInvalidValue;
     const float2 *t2 = (const float2 *)table;
     if (prec == NIRC_BF16)
         hipLaunchKernelGGL((k_hash_grad_h16<NIRC_BF16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, packed, t2,
-                           grid, a, partials, loss_partials, gtab);
+                           grid, a, partials, loss_partials, gacc);
     else if (prec == NIRC_FP16)
         hipLaunchKernelGGL((k_hash_grad_h16<NIRC_FP16>), dim3(nblocks), dim3(kWaves16 * 64), 0, s, pts, q, packed, t2,
-                           grid, a, partials, loss_partials, gtab);
+                           grid, a, partials, loss_partials, gacc);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -288,8 +288,8 @@ def test_hash_empty_inputs(nirc):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_hash_checkpoint_resume(nirc, prec):
     # a restored checkpoint is the saved state bit for bit (and answers identically); training on
-    # from it follows the original's updates (the grid gradient's atomic sums make the two runs
-    # agree to rounding, not bit for bit)
+    # from it follows the original bit for bit (the grid gradient is summed in fixed point, so
+    # the order of its atomic adds does not matter)
     P, B = 4096, 4096
     pts = wl.make_points(56, P)
     lob = wl.make_lobes(56).packed()
@@ -313,8 +313,8 @@ def test_hash_checkpoint_resume(nirc, prec):
     np.testing.assert_array_equal(host(nirc.nirc_hash_infer(b, dp, q)), ya)
     frames(a, 2)
     frames(b, 2)
-    wa, wb = host(a.get_weights()), host(b.get_weights())
-    assert rel_l2(wb - wc, wa - wc) <= 2e-2
+    # (the blobs' alignment padding is not state: compare what the updates produce)
+    np.testing.assert_array_equal(host(a.get_weights()), host(b.get_weights()))
     assert a.read_flags() == 0 and b.read_flags() == 0
 
 
@@ -350,7 +350,7 @@ def test_hash_positions_outside_the_unit_cube(nirc, prec):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_hash_train_frame_matches_step_loop(nirc, prec):
     # the native frame loop (samples generated into the workspace) against the same steps called
-    # one by one; the grid gradient's atomic sums make them agree to rounding
+    # one by one: bit for bit
     P, B = 4096, 2048
     pts = wl.make_points(60, P)
     lob = wl.make_lobes(60).packed()
@@ -363,9 +363,7 @@ def test_hash_train_frame_matches_step_loop(nirc, prec):
         for s_ in range(3):
             q, tgt = nirc.tlmc_train_batch(dp, lob, B, 61, f, s_)
             nirc.nirc_hash_train_step(b, dp, q, tgt)
-    w0 = w.astype(np.float64)
-    wa, wb = host(a.get_weights()), host(b.get_weights())
-    assert rel_l2(wa - w0, wb - w0) <= 2e-2
+    np.testing.assert_array_equal(host(a.get_weights()), host(b.get_weights()))
     assert np.isfinite(float(loss.item())) and float(loss.item()) > 0
 
 
@@ -524,3 +522,20 @@ def test_hash_grid_gradient_without_relu_decisions(nirc, prec):
     print(f"  mlp {e_mlp:.3e}  grid {e_tab:.3e}", flush=True)
     assert e_mlp <= GRAD_TOL[prec]
     assert e_tab <= GRAD_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_hash_gradient_is_deterministic(nirc, prec):
+    # the same batch twice (and on a second model): identical gradients, bit for bit, although
+    # the grid part is gathered by atomic adds from every workgroup
+    P, B = 3000, 65536
+    pts = wl.make_points(62, P)
+    lob = wl.make_lobes(62).packed()
+    dp = nirc.Points.from_workload(pts)
+    m1, _ = _model(nirc, prec, GRIDS["default"], 62, max_batch=B)
+    m2, _ = _model(nirc, prec, GRIDS["default"], 62, max_batch=B)
+    q, tgt = nirc.tlmc_train_batch(dp, lob, B, 63, 0, 0)
+    g = [host(nirc.nirc_hash_loss_grad(m, dp, q, tgt)[1]) for m in (m1, m1, m2)]
+    np.testing.assert_array_equal(g[0], g[1])
+    np.testing.assert_array_equal(g[0], g[2])
+    assert np.count_nonzero(g[0][oracle.hash_mlp_params(64):]) > 1000
