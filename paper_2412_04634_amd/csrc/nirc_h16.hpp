@@ -164,26 +164,6 @@ __device__ __forceinline__ void dir_features16(float dx, float dy, float dz, u32
     }
 }
 
-// Cosine-weighted direction from uniforms (u1, u2) about a unit normal, with the hardware sine
-// and cosine of 2 pi u2 (argument in revolutions; absolute error ~1e-6, far below the 16-bit
-// operands the direction feeds).  Used for the cache directions of the 16-bit estimators, whose
-// directions never leave the kernel; residual directions keep the exact map of cosine_dir.
-__device__ __forceinline__ void cosine_dir_fast(float nx, float ny, float nz, float u1, float u2, float &wx,
-                                                float &wy, float &wz) {
-#pragma clang fp contract(off)
-    const float r = __builtin_amdgcn_sqrtf(u1);
-    const float lx = r * __builtin_amdgcn_cosf(u2), ly = r * __builtin_amdgcn_sinf(u2);
-    const float lz = __builtin_amdgcn_sqrtf(1.0f - u1);
-    const float s = nz >= 0.0f ? 1.0f : -1.0f;
-    const float a = -__builtin_amdgcn_rcpf(s + nz);
-    const float b = nx * ny * a;
-    const float tx = 1.0f + s * nx * nx * a, ty = s * b, tz = -s * nx;
-    const float by = s + ny * ny * a;
-    wx = lx * tx + ly * b + lz * nx;
-    wy = lx * ty + ly * by + lz * ny;
-    wz = lx * tz - ly * ny + lz * nz;
-}
-
 // B operand (two K-blocks of the chain) from two result tiles, with ReLU.
 template <int PREC>
 __device__ __forceinline__ u32x4 chain_operand(const f32x4 &lo, const f32x4 &hi) {

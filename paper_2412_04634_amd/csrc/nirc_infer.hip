@@ -389,11 +389,14 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         wave_sync();   // previous group's readers of the slab are done
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) *(f32x4 *)(hs + col * W + 16 * mt + 4 * g) = hsum[mt];
+        // the group's normals, behind the staged directions (nrm [3][16])
+        if (g < 3) db[3 * kDirSlots + 16 * g + col] = g == 0 ? xs[3] : g == 1 ? xs[4] : xs[5];
+        wave_sync();
     }
     float fc0 = 0.f, fc1 = 0.f, fc2 = 0.f, fr0 = 0.f, fr1 = 0.f, fr2 = 0.f;
     for (int tb = 0; tb < n_tiles;) {
         const bool fold = n_tiles - tb == 9;   // last 8 cache tiles + the residual tile
-        gen_dirs_batch(pts, p0, tb, n_cache, dn, key0, key1, frame, lane, db, fold);
+        gen_dirs_batch_nrm<false>((uint32_t)p0, tb, n_cache, dn, key0, key1, frame, lane, db, db + 3 * kDirSlots, fold);
         const int tend = fold ? n_tiles : min(tb + 8, n_tiles);
         int t = tb;
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)

@@ -128,70 +128,6 @@ struct Tlmc16Lds {
     static constexpr int kSlab = TlmcLds<W>::kSlab + 48 + (lds_weights(W) ? 4 * 64 * 4 + 4 * 64 * 2 : 0);   // floats
 };
 
-// The 16-bit estimators' direction batch: as gen_dirs_batch (same counters, same slots), with the
-// group's normals read from the slab (nrm, staged once per group) instead of global memory,
-// 32-bit point indices (point counts stay below 2^31), and the fast map for cache directions.
-// Residual directions (tile n_cache, and the folded residual tile) use the exact map, so that
-// they equal the directions tlmc_sample_dirs returns.
-__device__ __forceinline__ void gen_dirs_batch16(uint32_t p0, int tb, int n_cache, DivN dn, uint32_t key0,
-                                                 uint32_t key1, uint32_t frame, int lane, float *db, const float *nrm,
-                                                 bool fold) {
-    const int T = tb + (lane >> 3);
-    const int c0 = (2 * lane) & 15;
-    float wa[3] = {0.f, 0.f, 0.f}, wb[3] = {0.f, 0.f, 0.f};
-    if (T <= n_cache) {
-        const bool res = (T == n_cache);
-        int ja, jb, ka = 0, kb = 0;
-        if (res) {
-            ja = c0;
-            jb = c0 + 1;
-        } else {
-            const int qa = 16 * T + c0;
-            ja = (int)div_n((uint32_t)qa, dn);
-            ka = qa - ja * n_cache;
-            jb = (int)div_n((uint32_t)(qa + 1), dn);
-            kb = qa + 1 - jb * n_cache;
-        }
-        const DirCounter ca = dir_counter(p0 + (uint32_t)ja, ka, res);
-        const DirCounter cb = dir_counter(p0 + (uint32_t)jb, kb, res);
-        const Rand4 ra = philox(ca.c0, ca.c1, frame, ca.stream, key0, key1);
-        Rand4 rb = ra;
-        if (ca.c0 != cb.c0 || ca.c1 != cb.c1)   // only for odd N
-            rb = philox(cb.c0, cb.c1, frame, cb.stream, key0, key1);
-        const float nax = nrm[ja], nay = nrm[16 + ja], naz = nrm[32 + ja];
-        const float nbx = nrm[jb], nby = nrm[16 + jb], nbz = nrm[32 + jb];
-        const float ua1 = u24(ca.half ? ra.r[2] : ra.r[0]), ua2 = u24(ca.half ? ra.r[3] : ra.r[1]);
-        const float ub1 = u24(cb.half ? rb.r[2] : rb.r[0]), ub2 = u24(cb.half ? rb.r[3] : rb.r[1]);
-        if (res) {
-            cosine_dir(nax, nay, naz, ua1, ua2, wa[0], wa[1], wa[2]);
-            cosine_dir(nbx, nby, nbz, ub1, ub2, wb[0], wb[1], wb[2]);
-        } else {
-            cosine_dir_fast(nax, nay, naz, ua1, ua2, wa[0], wa[1], wa[2]);
-            cosine_dir_fast(nbx, nby, nbz, ub1, ub2, wb[0], wb[1], wb[2]);
-        }
-    }
-    // residual direction of point rl = lane % 16 of the group (exact map): every lane computes
-    // that of its rl and all lanes store the same value
-    float ra_[3] = {0.f, 0.f, 0.f};
-    const int rl = lane & 15;
-    if (fold) {
-        const DirCounter c = dir_counter(p0 + (uint32_t)rl, 0, true);
-        const Rand4 r = philox(c.c0, c.c1, frame, c.stream, key0, key1);
-        dir_from_rand(r, c.half, nrm[rl], nrm[16 + rl], nrm[32 + rl], ra_[0], ra_[1], ra_[2]);
-    }
-    wave_sync();   // the previous batch's readers are done
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        db[kDirSlots * d + 2 * lane] = wa[d];
-        db[kDirSlots * d + 2 * lane + 1] = wb[d];
-    }
-    if (fold) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) db[kDirSlots * d + 128 + rl] = ra_[d];
-    }
-    wave_sync();
-}
-
 // T consecutive query tiles (first tile T0, staged directions from batch slot s0) of the
 // current point group through the 16-bit chain.  The output layer of all T tiles lands in one
 // accumulator (tile tt in columns 3tt..3tt+2), so the exponential and the per-point sums are
@@ -418,7 +354,7 @@ __device__ __forceinline__ void tlmc_group_h16(const Points &pts, int64_t p0, in
     if constexpr (lds_weights(W)) load_dir_fragments<W, ENC == 1 ? 1 : 2>(dfrag, sD, lane);
     for (int tb = 0; tb < n_tiles;) {
         const bool fold = n_tiles - tb == 9;   // last 8 cache tiles + the residual tile
-        gen_dirs_batch16((uint32_t)p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db, gs.nrm, fold);
+        gen_dirs_batch_nrm<true>((uint32_t)p0, tb, n_cache, dn, key0, key1, frame, lane, gs.db, gs.nrm, fold);
         const int tend = fold ? n_tiles : min(tb + 8, n_tiles);
         if constexpr (ENC == 1) {
             // the next group's grid corners, fetched behind this group's last tiles (after the

@@ -27,7 +27,8 @@ constexpr int kDirSlots = 144;
 template <int W>
 struct TlmcLds {
     // h_s of 16 points, 128 staged directions, per-point cache sums [16][4], residual
-    // predictions [16][4] and a per-tile query buffer [16][4]
+    // predictions [16][4] and a per-tile query buffer [16][4] (the FP32 estimator keeps its sums
+    // in registers and puts the group's normals [3][16] there instead)
     static constexpr int kSlab = 16 * W + 3 * kDirSlots + 3 * 64;
 };
 
@@ -139,6 +140,8 @@ __device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float
         for (int tt = 0; tt < T; ++tt)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) o[tt][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // the layer's MFMA run at raised issue priority (the SIMD's other wave fills the gaps)
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int kq = 0; kq < KQ; ++kq) {
             f32x4 a[MT];
@@ -151,6 +154,8 @@ __device__ __forceinline__ void hidden_layers(f32x4 (&h)[T][W / 16], const float
 #pragma unroll
                     for (int tt = 0; tt < T; ++tt) o[tt][mt] = mfma4(a[mt][kk], h[tt][kq][kk], o[tt][mt]);
         }
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int tt = 0; tt < T; ++tt)
 #pragma unroll
@@ -181,15 +186,35 @@ __device__ __forceinline__ void output_layer(f32x4 (&y)[T], const f32x4 (&h)[T][
 // ------------------------------------------------------------------------------------------
 // Pieces of the fused estimator shared by all precisions.
 
-// Directions of queries 2 lane and 2 lane + 1 of the 128-query batch starting at tile tb of the
-// point group at p0 (N cache tiles, then one residual tile); one Philox block serves both
-// (two blocks only for odd N).  With `fold` (the batch holds the group's last 8 cache tiles and
-// the residual tile follows), lanes 0..7 also generate the residual tile into slots 128..143,
-// which saves a batch that would hold one tile.  Written to db as SoA [3][kDirSlots].
-__device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, int tb, int n_cache, DivN dn,
-                                               uint32_t key0, uint32_t key1, uint32_t frame, int lane, float *db,
-                                               bool fold) {
-    const int64_t P = pts.count;
+// Cosine-weighted direction from uniforms (u1, u2) about a unit normal, with the hardware sine
+// and cosine of 2 pi u2 (argument in revolutions; absolute error ~1e-6, far below the 16-bit
+// operands the direction feeds).  Used for the cache directions of the 16-bit estimators, whose
+// directions never leave the kernel; residual directions keep the exact map of cosine_dir.
+__device__ __forceinline__ void cosine_dir_fast(float nx, float ny, float nz, float u1, float u2, float &wx,
+                                                float &wy, float &wz) {
+#pragma clang fp contract(off)
+    const float r = __builtin_amdgcn_sqrtf(u1);
+    const float lx = r * __builtin_amdgcn_cosf(u2), ly = r * __builtin_amdgcn_sinf(u2);
+    const float lz = __builtin_amdgcn_sqrtf(1.0f - u1);
+    const float s = nz >= 0.0f ? 1.0f : -1.0f;
+    const float a = -__builtin_amdgcn_rcpf(s + nz);
+    const float b = nx * ny * a;
+    const float tx = 1.0f + s * nx * nx * a, ty = s * b, tz = -s * nx;
+    const float by = s + ny * ny * a;
+    wx = lx * tx + ly * b + lz * nx;
+    wy = lx * ty + ly * by + lz * ny;
+    wz = lx * tz - ly * ny + lz * nz;
+}
+
+// The estimators' direction batch: as gen_dirs_batch (same counters, same slots), with the
+// group's normals read from the slab (nrm [3][16], staged once per group) instead of global
+// memory and 32-bit point indices (point counts stay below 2^31).  FAST (the 16-bit estimators):
+// cache directions by the fast map; residual directions (tile n_cache, and the folded residual
+// tile) always use the exact map, so that they equal the directions tlmc_sample_dirs returns.
+template <bool FAST>
+__device__ __forceinline__ void gen_dirs_batch_nrm(uint32_t p0, int tb, int n_cache, DivN dn, uint32_t key0,
+                                                 uint32_t key1, uint32_t frame, int lane, float *db, const float *nrm,
+                                                 bool fold) {
     const int T = tb + (lane >> 3);
     const int c0 = (2 * lane) & 15;
     float wa[3] = {0.f, 0.f, 0.f}, wb[3] = {0.f, 0.f, 0.f};
@@ -206,28 +231,32 @@ __device__ __forceinline__ void gen_dirs_batch(const Points &pts, int64_t p0, in
             jb = (int)div_n((uint32_t)(qa + 1), dn);
             kb = qa + 1 - jb * n_cache;
         }
-        const int64_t pa = p0 + ja, pb = p0 + jb;
-        const DirCounter ca = dir_counter((uint32_t)pa, ka, res);
-        const DirCounter cb = dir_counter((uint32_t)pb, kb, res);
+        const DirCounter ca = dir_counter(p0 + (uint32_t)ja, ka, res);
+        const DirCounter cb = dir_counter(p0 + (uint32_t)jb, kb, res);
         const Rand4 ra = philox(ca.c0, ca.c1, frame, ca.stream, key0, key1);
         Rand4 rb = ra;
         if (ca.c0 != cb.c0 || ca.c1 != cb.c1)   // only for odd N
             rb = philox(cb.c0, cb.c1, frame, cb.stream, key0, key1);
-        const int64_t qa_ = min(pa, P - 1), qb_ = min(pb, P - 1);
-        dir_from_rand(ra, ca.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], wa[0], wa[1], wa[2]);
-        dir_from_rand(rb, cb.half, pts.nx[qb_], pts.ny[qb_], pts.nz[qb_], wb[0], wb[1], wb[2]);
+        const float nax = nrm[ja], nay = nrm[16 + ja], naz = nrm[32 + ja];
+        const float nbx = nrm[jb], nby = nrm[16 + jb], nbz = nrm[32 + jb];
+        const float ua1 = u24(ca.half ? ra.r[2] : ra.r[0]), ua2 = u24(ca.half ? ra.r[3] : ra.r[1]);
+        const float ub1 = u24(cb.half ? rb.r[2] : rb.r[0]), ub2 = u24(cb.half ? rb.r[3] : rb.r[1]);
+        if (!FAST || res) {
+            cosine_dir(nax, nay, naz, ua1, ua2, wa[0], wa[1], wa[2]);
+            cosine_dir(nbx, nby, nbz, ub1, ub2, wb[0], wb[1], wb[2]);
+        } else {
+            cosine_dir_fast(nax, nay, naz, ua1, ua2, wa[0], wa[1], wa[2]);
+            cosine_dir_fast(nbx, nby, nbz, ub1, ub2, wb[0], wb[1], wb[2]);
+        }
     }
-    // residual direction of point rl = lane % 16 of the group: every lane computes that of its rl
-    // and all lanes store, so lanes with the same rl write the same value (no divergent branch:
-    // the SIMD pays for one direction per lane either way)
+    // residual direction of point rl = lane % 16 of the group (exact map): every lane computes
+    // that of its rl and all lanes store the same value
     float ra_[3] = {0.f, 0.f, 0.f};
     const int rl = lane & 15;
     if (fold) {
-        const int64_t pa = p0 + rl;
-        const DirCounter c = dir_counter((uint32_t)pa, 0, true);
+        const DirCounter c = dir_counter(p0 + (uint32_t)rl, 0, true);
         const Rand4 r = philox(c.c0, c.c1, frame, c.stream, key0, key1);
-        const int64_t qa_ = min(pa, P - 1);
-        dir_from_rand(r, c.half, pts.nx[qa_], pts.ny[qa_], pts.nz[qa_], ra_[0], ra_[1], ra_[2]);
+        dir_from_rand(r, c.half, nrm[rl], nrm[16 + rl], nrm[32 + rl], ra_[0], ra_[1], ra_[2]);
     }
     wave_sync();   // the previous batch's readers are done
 #pragma unroll
