@@ -17,7 +17,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 bool width_ok(int32_t w) { return w == 64 || w == 128; }
 
 // State layout (each piece 256-byte aligned): master | m | v | packed FP32 | packed 16-bit (BF16
-// and FP16 models only) | step | flags | bad | loss scale (FP32) and good-step count (uint32).
+// and FP16 models only) | step | flags | bad | loss scale (FP32), good-step count and the Adam
+// kernel's finished-workgroup count (uint32, zero between steps).
 struct StateLayout {
     size_t master, m, v, packed, packed16, step, flags, bad, scale, total;
     StateLayout(int W, int prec) {
@@ -32,7 +33,7 @@ struct StateLayout {
         step = o; o += align_up(sizeof(int64_t));
         flags = o; o += align_up(sizeof(uint32_t));
         bad = o; o += align_up(sizeof(uint32_t));
-        scale = o; o += align_up(2 * sizeof(uint32_t));
+        scale = o; o += align_up(3 * sizeof(uint32_t));
         total = o;
     }
 };
@@ -101,6 +102,7 @@ struct nirc_model {
     uint32_t *flags, *bad;
     float *scale;          // the current loss scale (dynamic for FP16 models)
     uint32_t *good;        // finite steps since the scale last changed
+    uint32_t *done;        // finished workgroups of the running 16-bit Adam launch (zero between steps)
     char *ws;
     size_t ws_bytes;
     // FP16 models scale their loss dynamically; BF16 and FP32 keep cfg.loss_scale
@@ -174,6 +176,7 @@ nirc_status nirc_create(const nirc_config *cfg, void *state, size_t state_bytes,
     m->bad = (uint32_t *)(base + sl.bad);
     m->scale = (float *)(base + sl.scale);
     m->good = (uint32_t *)(base + sl.scale + sizeof(float));
+    m->done = (uint32_t *)(base + sl.scale + sizeof(float) + sizeof(uint32_t));
     m->ws = (char *)workspace;
     m->ws_bytes = workspace ? workspace_bytes : 0;
     st = nirc_set_weights(m, init_w, stream);
@@ -205,7 +208,7 @@ nirc_status nirc_set_weights(nirc_model *model, const float *w, void *stream) {
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->step, 2, 0u, s);
     // the loss scale starts again from the configured one
     if (e == hipSuccess) e = launch_fill_u32((uint32_t *)model->scale, 1, __builtin_bit_cast(uint32_t, model->cfg.loss_scale), s);
-    if (e == hipSuccess) e = launch_fill_u32(model->good, 1, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(model->good, 2, 0u, s);   // good-step and workgroup counts
     if (e == hipSuccess) e = launch_pack(model->packed, model->master, model->W, s);
     if (e == hipSuccess && model->packed16)
         e = launch_pack16(model->packed16, model->master, model->W, model->cfg.precision, s);
@@ -446,7 +449,7 @@ nirc_status nirc_adam_step(nirc_model *model, const float *grad, void *stream) {
     if (e == hipSuccess)
         e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags, model->bad,
                         model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps, model->packed,
-                        model->packed16, model->cfg.precision, s);
+                        model->packed16, model->cfg.precision, s, model->done);
     return hip_status(e);
 }
 
@@ -463,7 +466,8 @@ static nirc_status train_step_on(nirc_model *model, const nirc_points &points, c
     if (st != NIRC_OK) return st;
     hipError_t e = launch_adam(model->W, model->master, model->m, model->v, grad, model->step, model->flags,
                                model->bad, model->cfg.lr, model->cfg.beta1, model->cfg.beta2, model->cfg.adam_eps,
-                               model->packed, model->packed16, model->cfg.precision, s, model->dyn(), model->dyn_good());
+                               model->packed, model->packed16, model->cfg.precision, s, model->done, model->dyn(),
+                               model->dyn_good());
     return hip_status(e);
 }
 
@@ -684,6 +688,7 @@ nirc_status nirc_train_list_build(const nirc_train_request *requests, int32_t n,
         t.output = m->cfg.output;
         t.dyn_scale = m->dyn();
         t.good_steps = m->dyn_good();
+        t.done = m->done;
     }
     d->n = n;
     d->total_vb = (int32_t)vb;

@@ -80,6 +80,54 @@ __host__ __device__ inline int64_t h16_packed_source(int W, int e) {
     }
 }
 
+// The packed 16-bit elements that hold canonical parameter i (the inverse of h16_packed_source):
+// writes their indices to e[] and the scale each stores (h16_packed_scale) to sc[]; returns how
+// many (W1: 1, W2..W4: 2 (forward and transposed sections), W5: 6 (O, four OS copies, OT)).
+__host__ __device__ inline int h16_packed_targets(int W, int64_t i, int (&e)[6], float (&sc)[6]) {
+    const H16Layout L{W};
+    const int KB = W / 32;
+    // chained position of hidden neuron n: K-block, lane group and slot
+    auto chain_pos = [](int n, int &kb, int &g, int &j) {
+        kb = n >> 5;
+        const int r = n & 31;
+        g = (r & 15) >> 2;
+        j = 4 * (r >> 4) + (r & 3);
+    };
+    if (i < w_offset(W, 1)) {   // W1 [W][160]
+        const int row = (int)(i / kFeat), f = (int)(i % kFeat);
+        const int input = f >> 4, k = (f & 15) >> 1, s_c = f & 1;
+        const int g = k >> 1, fq = k & 1;
+        const bool surface = input < 3 || input > 5;
+        const int pos = surface ? (input < 3 ? input : input - 3) : input - 3;   // index in its list
+        const int t = 4 * pos + 2 * fq + s_c;
+        const int sec = surface ? SEC_S : SEC_D, kbs = surface ? 4 : 2;
+        const int lane = 16 * g + (row & 15), m = row >> 4;
+        e[0] = L.offset(sec) + ((m * kbs + (t >> 3)) * 64 + lane) * 8 + (t & 7);
+        sc[0] = s_c ? 0.5f : 1.0f;
+        return 1;
+    }
+    if (i < w_offset(W, 4)) {   // W2..W4 [W][W]: forward section and transposed section
+        const int l = (int)((i - w_offset(W, 1)) / ((int64_t)W * W));
+        const int r = (int)((i - w_offset(W, 1 + l)) / W), c = (int)((i - w_offset(W, 1 + l)) % W);
+        int kb, g, j;
+        chain_pos(c, kb, g, j);   // forward: row r, K position of neuron c
+        e[0] = L.offset(SEC_H0 + l) + (((r >> 4) * KB + kb) * 64 + 16 * g + (r & 15)) * 8 + j;
+        chain_pos(r, kb, g, j);   // transposed: row c, K position of neuron r
+        e[1] = L.offset(SEC_T0 + l) + (((c >> 4) * KB + kb) * 64 + 16 * g + (c & 15)) * 8 + j;
+        sc[0] = sc[1] = 1.0f;
+        return 2;
+    }
+    // W5 [3][W]
+    const int r = (int)((i - w_offset(W, 4)) / W), c = (int)((i - w_offset(W, 4)) % W);
+    int kb, g, j;
+    chain_pos(c, kb, g, j);
+    e[0] = L.offset(SEC_O) + (kb * 64 + 16 * g + r) * 8 + j;
+    for (int m = 0; m < 4; ++m) e[1 + m] = L.offset(SEC_OS) + ((m * KB + kb) * 64 + 16 * g + 3 * m + r) * 8 + j;
+    e[5] = L.offset(SEC_OT) + ((c >> 4) * 64 + (c & 15)) * 8 + r;
+    for (int k = 0; k < 6; ++k) sc[k] = 1.0f;
+    return 6;
+}
+
 // Scale applied to packed element e: the 16-bit input features carry 2 cos instead of cos
 // (angle doubling is then one multiply and one FMA per step), so the weights of the cosine
 // features (odd positions of the S and D sections) are stored halved.  Halving is exact in

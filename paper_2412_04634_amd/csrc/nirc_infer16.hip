@@ -42,13 +42,91 @@ __global__ void k_pack16(uint16_t *packed, const float *master, int total, int64
     pack16_elem<PREC, W>(packed, master, total, step, flags, bad, dyn_scale, good, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// The repack and step commit of every request of a training work list (request blockIdx.y).
+// Adam on the FP32 master weights with the 16-bit copy refreshed in the same pass: thread i
+// updates parameter i (the arithmetic of adam_elem) and stores it, scaled, into every packed
+// element that holds it (h16_packed_targets); a skipped step (`bad` set) changes nothing.  The
+// last workgroup to finish (counted in `done`) commits the step as pack16_elem does: every other
+// workgroup has read `step` and `bad` before it counted itself.
 template <int PREC, int W>
-__global__ void k_pack16_multi(const TrainDesc *__restrict__ desc) {
+__device__ __forceinline__ void adam_pack16_block(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                                  const float *__restrict__ grad, int64_t *step, uint32_t *flags,
+                                                  uint32_t *bad, float *dyn_scale, uint32_t *good, uint32_t *done,
+                                                  uint16_t *__restrict__ packed, float lr, float b1, float b2,
+                                                  float eps, int blk, int nblk) {
+    constexpr int64_t np = n_params(W);
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
+    if (i < np && *bad == 0u) {
+        const float t = (float)(*step + 1);
+        const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
+        const float gi = grad[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        int e[6];
+        float sc[6];
+        const int n = h16_packed_targets(W, i, e, sc);
+        for (int k = 0; k < n; ++k) packed[e[k]] = (uint16_t)(pack2<PREC>(wi * sc[k], 0.0f) & 0xFFFFu);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(done, 1u) == (uint32_t)nblk - 1u) {
+            __threadfence();
+            pack16_elem<PREC, W>(packed, w, 0, step, flags, bad, dyn_scale, good, 0);   // commit only
+            *done = 0u;
+        }
+    }
+}
+
+template <int PREC, int W>
+__global__ __launch_bounds__(256) void k_adam_pack16(float *w, float *m, float *v, const float *grad, int64_t *step,
+                                                     uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good,
+                                                     uint32_t *done, uint16_t *packed, float lr, float b1, float b2,
+                                                     float eps) {
+    adam_pack16_block<PREC, W>(w, m, v, grad, step, flags, bad, dyn_scale, good, done, packed, lr, b1, b2, eps,
+                               blockIdx.x, gridDim.x);
+}
+
+// Adam + repack + commit of every request of a training work list (request blockIdx.y).
+template <int PREC, int W>
+__global__ __launch_bounds__(256) void k_adam_pack16_multi(const TrainDesc *__restrict__ desc) {
     if ((int)blockIdx.y >= desc->n) return;
     const TrainReq &t = desc->req[blockIdx.y];
-    pack16_elem<PREC, W>(const_cast<uint16_t *>(t.packed16), t.master, H16Layout{W}.total(), t.step, t.flags, t.bad,
-                         t.dyn_scale, t.good_steps, blockIdx.x * blockDim.x + threadIdx.x);
+    adam_pack16_block<PREC, W>(t.master, t.m, t.v, t.grad, t.step, t.flags, t.bad, t.dyn_scale, t.good_steps,
+                               t.done, const_cast<uint16_t *>(t.packed16), t.lr, t.b1, t.b2, t.eps, blockIdx.x,
+                               gridDim.x);
+}
+
+hipError_t launch_adam_pack16(int W, int prec, float *w, float *m, float *v, const float *grad, int64_t *step,
+                              uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good, uint32_t *done,
+                              uint16_t *packed, float lr, float b1, float b2, float eps, hipStream_t s) {
+    const dim3 grid((unsigned)((n_params(W) + 255) / 256)), block(256);
+    if (W == 64 && prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_adam_pack16<NIRC_BF16, 64>), grid, block, 0, s, w, m, v, grad, step, flags, bad, dyn_scale,
+                           good, done, packed, lr, b1, b2, eps);
+    else if (W == 64)
+        hipLaunchKernelGGL((k_adam_pack16<NIRC_FP16, 64>), grid, block, 0, s, w, m, v, grad, step, flags, bad, dyn_scale,
+                           good, done, packed, lr, b1, b2, eps);
+    else if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_adam_pack16<NIRC_BF16, 128>), grid, block, 0, s, w, m, v, grad, step, flags, bad,
+                           dyn_scale, good, done, packed, lr, b1, b2, eps);
+    else
+        hipLaunchKernelGGL((k_adam_pack16<NIRC_FP16, 128>), grid, block, 0, s, w, m, v, grad, step, flags, bad,
+                           dyn_scale, good, done, packed, lr, b1, b2, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s) {
+    if (W != 64) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n_params(64) + 255) / 256), kBatchMaxRequests), block(256);
+    if (prec == NIRC_BF16)
+        hipLaunchKernelGGL((k_adam_pack16_multi<NIRC_BF16, 64>), grid, block, 0, s, desc);
+    else
+        hipLaunchKernelGGL((k_adam_pack16_multi<NIRC_FP16, 64>), grid, block, 0, s, desc);
+    return hipGetLastError();
 }
 
 template <int W>
@@ -502,16 +580,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_multi_h16(const BatchDesc *
 
 // ------------------------------------------------------------------------------------------
 
-hipError_t launch_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s) {
-    if (W != 64) return hipErrorInvalidValue;
-    const int total = H16Layout{64}.total();
-    const dim3 grid((total + 255) / 256, kBatchMaxRequests), block(256);
-    if (prec == NIRC_BF16)
-        hipLaunchKernelGGL((k_pack16_multi<NIRC_BF16, 64>), grid, block, 0, s, desc);
-    else
-        hipLaunchKernelGGL((k_pack16_multi<NIRC_FP16, 64>), grid, block, 0, s, desc);
-    return hipGetLastError();
-}
+
 
 hipError_t launch_pack16(uint16_t *packed, const float *master, int W, int prec, hipStream_t s, int64_t *step,
                          uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good) {

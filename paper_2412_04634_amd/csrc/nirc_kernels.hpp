@@ -416,6 +416,7 @@ struct TrainReq {
     int32_t loss_kind, output;
     float *dyn_scale;                    // FP16: the model's dynamic loss scale, else NULL
     uint32_t *good_steps;                // FP16: finite steps since the last change of the scale
+    uint32_t *done;                      // the model's count of finished Adam workgroups (zero between steps)
 };
 
 struct TrainDesc {
@@ -527,11 +528,12 @@ hipError_t launch_adam_n(int64_t np, float *master, float *m, float *v, const fl
                          const uint32_t *bad, float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s);
 // Adam on the master weights, then the refresh of the copy the kernels read (the FP32 copy for
-// FP32 models, only the 16-bit copy for 16-bit models) and the step commit.
+// FP32 models, only the 16-bit copy for 16-bit models) and the step commit.  16-bit models do
+// all three in one launch (launch_adam_pack16, `done` its workgroup counter).
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
-                       float *packed, uint16_t *packed16, int prec, hipStream_t s, float *dyn_scale = nullptr,
-                       uint32_t *good_steps = nullptr);
+                       float *packed, uint16_t *packed16, int prec, hipStream_t s, uint32_t *done,
+                       float *dyn_scale = nullptr, uint32_t *good_steps = nullptr);
 // One training step of every request of a device work list (width 64, 16-bit models): samples
 // of step `step`, gradient partials, reduction, Adam and the 16-bit repack with the step commit.
 // Launch shapes depend only on the list's capacity, so the sequence can be captured in a graph
@@ -543,7 +545,12 @@ size_t ablation_workspace_bytes(int64_t P, int n_cache, int stage);
 hipError_t launch_ablation(int prec, int stage, const Points &pts, const nirc_lobes &lobes, const uint16_t *packed,
                            int n_cache, uint64_t seed, uint64_t frame, char *ws, float *out_tl, float *out_c,
                            float *out_r, hipStream_t s);
-hipError_t launch_reduce_adam_multi(const TrainDesc *desc, int W, hipStream_t s);
-hipError_t launch_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s);
+hipError_t launch_reduce_grad_multi(const TrainDesc *desc, int W, hipStream_t s);
+// Adam with the 16-bit copy refreshed in the same pass and the step committed by the last
+// workgroup (done: a counter that is zero between steps).
+hipError_t launch_adam_pack16(int W, int prec, float *w, float *m, float *v, const float *grad, int64_t *step,
+                              uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good, uint32_t *done,
+                              uint16_t *packed, float lr, float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_adam_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s);
 
 }  // namespace nirc

@@ -686,14 +686,6 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     adam_elem(w, m, v, grad, step, bad, np, lr, b1, b2, eps, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Adam of every request of a training work list (request blockIdx.y).
-__global__ void k_adam_multi(const TrainDesc *__restrict__ desc) {
-    if ((int)blockIdx.y >= desc->n) return;
-    const TrainReq &t = desc->req[blockIdx.y];
-    adam_elem(t.master, t.m, t.v, t.grad, t.step, t.bad, n_params(desc->width), t.lr, t.b1, t.b2, t.eps,
-              (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-}
-
 // Repack the kernels' weight copy; thread 0 then commits the step (or records the skip).
 __global__ void k_pack_commit(float *packed, const float *master, int W, int total, int64_t *step,
                               uint32_t *flags, uint32_t *bad) {
@@ -799,25 +791,26 @@ hipError_t launch_check_finite(int W, const float *grad, uint32_t *bad, hipStrea
 
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
-                       float *packed, uint16_t *packed16, int prec, hipStream_t s, float *dyn_scale,
-                       uint32_t *good_steps) {
+                       float *packed, uint16_t *packed16, int prec, hipStream_t s, uint32_t *done,
+                       float *dyn_scale, uint32_t *good_steps) {
     const int64_t np = n_params(W);
+    if (packed16)
+        return launch_adam_pack16(W, prec, master, m, v, grad, step, flags, bad, dyn_scale, good_steps, done,
+                                  packed16, lr, b1, b2, eps, s);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad,
                        step, bad, np, lr, b1, b2, eps);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (packed16) return launch_pack16(packed16, master, W, prec, s, step, flags, bad, dyn_scale, good_steps);
     const int total = F32Layout{W}.total();
     hipLaunchKernelGGL(k_pack_commit, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
                        step, flags, bad);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_adam_multi(const TrainDesc *desc, int W, hipStream_t s) {
+hipError_t launch_reduce_grad_multi(const TrainDesc *desc, int W, hipStream_t s) {
     const int64_t np = n_params(W);
     hipLaunchKernelGGL(k_reduce_grad_multi, dim3((unsigned)((np + 63) / 64), kBatchMaxRequests),
                        dim3(kReduceWaves * 64), 0, s, desc);
-    hipLaunchKernelGGL(k_adam_multi, dim3((unsigned)((np + 255) / 256), kBatchMaxRequests), dim3(256), 0, s, desc);
     return hipGetLastError();
 }
 

@@ -661,8 +661,8 @@ hipError_t launch_train_step_multi(const TrainDesc *desc, int prec, uint32_t ste
     else
         hipLaunchKernelGGL((k_grad_h16_multi<64, NIRC_FP16>), dim3(kMaxResidentBlocks), dim3(kWaves16 * 64), 0, s, desc);
     e = hipGetLastError();
-    if (e == hipSuccess) e = launch_reduce_adam_multi(desc, 64, s);
-    if (e == hipSuccess) e = launch_pack16_multi(desc, 64, prec, s);
+    if (e == hipSuccess) e = launch_reduce_grad_multi(desc, 64, s);
+    if (e == hipSuccess) e = launch_adam_pack16_multi(desc, 64, prec, s);
     return e;
 }
 

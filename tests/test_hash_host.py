@@ -113,3 +113,17 @@ def test_device_grid_lookup_matches_oracle(tmp_path, grid):
     for l in range(12):
         bound = 3 * 2 * 2.0 ** -24 * float(res[l]) * 2 + 1e-6
         assert err[:, 2 * l:2 * l + 2].max() <= bound, (l, err[:, 2 * l:2 * l + 2].max(), bound)
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
+def test_h16_packed_targets_invert_the_packing(tmp_path):
+    # the per-parameter list of packed 16-bit elements (used to refresh the copy right after each
+    # Adam update) is exactly the inverse of the packing, scales included, at both widths
+    exe = _build(tmp_path, "h16_targets_check")
+    out = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=300).stdout.split("\n")
+    rows = [list(map(int, l.split())) for l in out if l.strip()]
+    assert [r[0] for r in rows] == [64, 128]
+    for W, bad, np_, used, listed in rows:
+        assert bad == 0, (W, bad)
+        assert used == listed   # every stored element is some parameter's target
+        assert np_ == W * 160 + 3 * W * W + 3 * W
