@@ -63,6 +63,39 @@ __device__ inline float out_grad16(float z, float t, float dr, bool use_loss, fl
     return k * dr * dydz;
 }
 
+// One sample's inputs to a training round: its point's attributes, its direction and its
+// target (or output gradient).  Loaded ahead of use in two steps, so that neither the point
+// index nor the attributes that depend on it are waited for: the query's own values one round
+// ahead (load_query16), the point's attributes half a round ahead (load_point16).
+struct Sample16 {
+    float x[7], w[3], t[3];
+    int64_t bi;   // the query (the batch's last one for the slots past its end)
+    int64_t j;    // its point index as given (bi itself when the queries carry none)
+    bool valid;
+};
+
+__device__ __forceinline__ void load_query16(const Queries &q, const TrainArgs &args, int64_t b, int64_t B,
+                                             Sample16 &o) {
+    o.valid = b < B;
+    o.bi = o.valid ? b : B - 1;
+    o.j = q.point ? (int64_t)q.point[o.bi] : o.bi;
+    o.w[0] = q.wx[o.bi], o.w[1] = q.wy[o.bi], o.w[2] = q.wz[o.bi];
+    const float *t = args.target ? args.target : args.d_rgb;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o.t[c] = t[3 * o.bi + c];
+}
+
+__device__ __forceinline__ void load_point16(const Points &pts, const Queries &q, Sample16 &o) {
+    // the checks of query_point on the index loaded before
+    int64_t p = o.j;
+    if (p < 0 || p >= pts.count) {
+        if (q.err) atomicOr(q.err, NIRC_FLAG_BAD_POINT_INDEX);
+        p = p < 0 ? 0 : pts.count - 1;
+    }
+    o.x[0] = pts.px[p], o.x[1] = pts.py[p], o.x[2] = pts.pz[p];
+    o.x[3] = pts.nx[p], o.x[4] = pts.ny[p], o.x[5] = pts.nz[p], o.x[6] = pts.rough[p];
+}
+
 }  // namespace
 
 // One workgroup of 4 waves processes rounds of 64 samples.  Phase 1: each wave takes 16 samples
@@ -108,17 +141,24 @@ __device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q
     float loss_acc = 0.0f;
 
     const int64_t n_chunks = (B + kChunk16 - 1) / kChunk16;
+    const int s = 16 * wave + col;   // sample slot in the round
+    Sample16 next;
+    if (blk < n_chunks) {
+        load_query16(q, args, blk * kChunk16 + s, B, next);
+        load_point16(pts, q, next);
+    }
     for (int64_t chunk = blk; chunk < n_chunks; chunk += nblk) {
         // ---------------- phase 1: forward + backward of this wave's 16 samples
         {
             const uint16_t *pk = opaque(packed);
-            const int s = 16 * wave + col;   // sample slot in the round
-            const int64_t b = chunk * kChunk16 + s;
-            const bool valid = b < B;
-            const int64_t bi = valid ? b : B - 1;
-            const int64_t p = query_point(q, pts, bi);
-            const float xs[7] = {pts.px[p], pts.py[p], pts.pz[p], pts.nx[p], pts.ny[p], pts.nz[p], pts.rough[p]};
-            const float ws[3] = {q.wx[bi], q.wy[bi], q.wz[bi]};
+            const Sample16 cur = next;
+            const bool more = chunk + nblk < n_chunks;
+            if (more) load_query16(q, args, (chunk + nblk) * kChunk16 + s, B, next);
+            const bool valid = cur.valid;
+            const float *xs = cur.x, *ws = cur.w;
+            // scheduling fences between the steps of a round: left free, the compiler interleaves
+            // the steps' loads and LDS stores in an order that measured a third slower
+            __builtin_amdgcn_sched_barrier(0);
 
             // input features of frequencies 2g, 2g + 1: (sin, 2 cos) pairs for the MFMAs, and
             // (sin, cos) rows for the first layer's gradient
@@ -134,6 +174,7 @@ __device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q
 #pragma unroll
             for (int t = 0; t < 12; ++t)
                 sE[feature_of(false, g, t) * kRow16 + s] = to16<PREC>((t & 1) ? 0.5f * f[28 + t] : f[28 + t]);
+            __builtin_amdgcn_sched_barrier(0);
 
             // forward
             u32x4 hb[4][KB];   // h1..h4 after ReLU, as chained B operands
@@ -187,6 +228,8 @@ __device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q
                 for (int kb = 0; kb < KB; ++kb)
                     z5 = mfma16<PREC>(*(const u32x4 *)(sec + (kb * 64 + lane) * 8), hb[3][kb], z5);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) load_point16(pts, q, next);
 #pragma unroll
             for (int l = 0; l < 4; ++l) stage_chain<W>(sH + l * W * kRow16, hb[l], g, s);
 
@@ -195,8 +238,8 @@ __device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q
             if (g == 0 && valid) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const float t = use_loss ? args.target[3 * b + c] : 0.0f;
-                    const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
+                    const float t = use_loss ? cur.t[c] : 0.0f;
+                    const float dr = use_loss ? 0.0f : cur.t[c];
                     float lt;
                     d5[c] = out_grad16(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
                                        args.fr ? args.fr[c] : 0.0f, args.sig != 0, lt);
@@ -246,7 +289,9 @@ __device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q
                         dl[mt] = mfma16<PREC>(*(const u32x4 *)(sec + ((mt * KB + kb) * 64 + lane) * 8), db[kb], dl[mt]);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
         // ---------------- phase 2: owned gradient tiles += staged deltas x activations
         // K position 8g + j of K-block kb <-> sample 32 kb + 8 g + j
 #pragma unroll
@@ -279,7 +324,9 @@ __device__ __forceinline__ void grad16_block(const Points &pts, const Queries &q
                 }
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---------------- write this block's partial gradient (every entry exactly once)
