@@ -504,7 +504,7 @@ struct TrainArgs {
 constexpr uint32_t kLossScaleGrowth = 1000;
 constexpr float kLossScaleMin = 0x1p-14f, kLossScaleMax = 0x1p24f;
 // NIRC_LOSS_VAR: fr[c] = mean over the batch of t - y (y: the model's predictions [B][3]),
-// summed in a fixed order; part holds kFrBlocks x 3 doubles.
+// summed in a fixed order; part holds kFrBlocks x 3 floats.
 constexpr int kFrBlocks = 256;
 hipError_t launch_residual_mean(const float *y, const float *t, int64_t B, float *part, float *fr, hipStream_t s);
 int train_blocks(int64_t batch);     // workgroups used by the FP32 gradient kernel for a batch

@@ -942,9 +942,9 @@ hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, h
 // inputs staged as rows [canonical input][sample] for the first layer's weight gradient.  Each
 // sample's gradient with respect to its 24 grid values (W1_grid^T delta1, from the transposed
 // TS32 section) is kept in registers through phase 2 and then scattered into the grid-entry
-// gradient by FP32 atomic adds (the 16 values of one (sample, level) in 16 consecutive lanes, x
-// neighbours in adjacent lane pairs, zero values skipped), staged through LDS that phase 2 has
-// released.
+// gradient by 64-bit fixed-point integer atomic adds (grid_acc_add; the 16 values of one
+// (sample, level) in 16 consecutive lanes, x neighbours in adjacent lane pairs, zero values
+// skipped), staged through LDS that phase 2 has released.
 namespace {
 constexpr int kScatRow32 = 28;   // per sample: 24 grid-value gradients, position, pad
 struct HashGrad32Lds {

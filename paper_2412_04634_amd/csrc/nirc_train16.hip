@@ -718,7 +718,8 @@ hipError_t launch_train_step_multi(const TrainDesc *desc, int prec, uint32_t ste
 // inputs.  In addition, after the first layer's delta, each sample's gradient with respect to
 // its 24 grid values (W1_grid^T delta1, from the TS section) is scattered into the grid-entry
 // gradient: each of the 8 corners of the sample's cell at a level receives its trilinear weight
-// times the level's two values, by FP32 atomic adds (zero values are skipped).
+// times the level's two values, by 64-bit fixed-point integer atomic adds (grid_acc_add; zero
+// values are skipped), so that the sums do not depend on the order of the adds.
 namespace {
 constexpr int kScatRow = 28;   // per sample: 24 grid-value gradients, position, pad
 struct HashGrad16Lds {

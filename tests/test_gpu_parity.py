@@ -272,20 +272,23 @@ def test_train_steps_follow_oracle(nirc):
     assert np.quantile(np.abs(w - ow), 0.999) <= 0.05 * 12 * 1e-3
 
 
+@pytest.mark.parametrize("prec,output", [(0, 0), (1, 0), (2, 0), (1, 1), (2, 2)])
 @pytest.mark.parametrize("P,B,steps", [(4096, 4096, 4), (777, 1000, 3), (5000, 65, 1)])
-def test_train_frame_equals_separate_steps(nirc, P, B, steps):
+def test_train_frame_equals_separate_steps(nirc, P, B, steps, prec, output):
     # the one-call frame of training draws the same samples and takes the same Adam steps as
-    # tlmc_train_batch + nirc_train_step called step by step
-    say("train_frame", P, B, steps)
+    # tlmc_train_batch + nirc_train_step called step by step (16-bit models make the samples
+    # inside the gradient kernel, FP32 models through the sample buffers)
+    say("train_frame", P, B, steps, prec, output)
     pts, lobes, w0 = scene(23, P)
     dp = nirc.Points.from_workload(pts)
-    a = nirc.Model(w0, max_batch=B)
-    b = nirc.Model(w0, max_batch=B)
+    cfg = nirc.make_config(precision=prec, output=output)
+    a = nirc.Model(w0, cfg=cfg, max_batch=B)
+    b = nirc.Model(w0, cfg=cfg, max_batch=B)
     la = torch.zeros(1, device="cuda")
     lb = torch.zeros(1, device="cuda")
     for f in range(2):
         for s in range(steps):
-            q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 24, f, s)
+            q, tgt = nirc.tlmc_train_batch(dp, lobes, B, 24, f, s, output)
             nirc.nirc_train_step(a, dp, q, tgt, la)
         nirc.nirc_train_frame(b, dp, lobes, B, steps, 24, f, lb)
     np.testing.assert_array_equal(host(a.get_weights()), host(b.get_weights()))
