@@ -151,7 +151,8 @@ size_t nirc_state_bytes(const nirc_config *cfg /* host */);
 
 /* Bytes of workspace needed by training calls on batches of up to max_batch queries
  * (per-workgroup gradient partials, reduced gradient, loss, and the sample buffers of
- * nirc_train_frame).  Inference needs none. */
+ * nirc_train_frame, which makes the samples of up to 4 steps in one launch).  Inference needs
+ * none. */
 size_t nirc_workspace_bytes(const nirc_config *cfg /* host */, int64_t max_batch);
 
 /* Create a model over caller-owned device buffers.  `state` must hold nirc_state_bytes and be

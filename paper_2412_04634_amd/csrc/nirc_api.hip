@@ -1,4 +1,5 @@
 // C ABI of the NIRC library: argument validation, state/workspace layout and kernel launches.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <new>
@@ -54,7 +55,7 @@ struct WorkLayout {
         pred = o; o += var_batch ? align_up((size_t)var_batch * 3 * sizeof(float)) : 0;
         fr_part = o; o += var_batch ? align_up((size_t)kFrBlocks * 3 * sizeof(float)) : 0;
         fr = o; o += var_batch ? align_up(4 * sizeof(float)) : 0;
-        samples = o; o += align_up((size_t)sample_batch * 7 * sizeof(float));
+        samples = o; o += align_up((size_t)kFrameSampleSteps * sample_batch * 7 * sizeof(float));
         total = o;
     }
 };
@@ -531,14 +532,19 @@ nirc_status nirc_train_frame(nirc_model *model, nirc_points points, const nirc_l
     const WorkLayout wl(model->W, grad_blocks(model->cfg.precision, batch), var_rows(model->cfg, batch), batch);
     if (!model->ws || model->ws_bytes < wl.total) return NIRC_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    float *smp = (float *)(model->ws + wl.samples);
-    int32_t *pidx = (int32_t *)smp;
-    float *wx = smp + batch, *wy = wx + batch, *wz = wy + batch, *tgt = wz + batch;
+    // the samples of up to kFrameSampleSteps steps in one launch (they do not depend on the
+    // weights), 7 values per sample and step: point, wx, wy, wz, target x 3
+    const int64_t stride = 7 * batch;
     for (int32_t k = 0; k < steps; ++k) {
-        hipError_t e = launch_train_batch(to_points(points), *field, batch, seed, frame, (uint32_t)k, model->cfg.output,
-                                          pidx, wx, wy, wz,
-                                          tgt, s);
-        if (e != hipSuccess) return NIRC_ERR_HIP;
+        float *smp = (float *)(model->ws + wl.samples) + (k % kFrameSampleSteps) * stride;
+        int32_t *pidx = (int32_t *)smp;
+        float *wx = smp + batch, *wy = wx + batch, *wz = wy + batch, *tgt = wz + batch;
+        if (k % kFrameSampleSteps == 0) {
+            const hipError_t e = launch_train_batch(to_points(points), *field, batch, seed, frame, (uint32_t)k,
+                                                    model->cfg.output, pidx, wx, wy, wz, tgt, s,
+                                                    std::min(kFrameSampleSteps, steps - k), stride);
+            if (e != hipSuccess) return NIRC_ERR_HIP;
+        }
         nirc_queries q{wx, wy, wz, pidx, batch};
         st = nirc_train_step(model, points, q, tgt, k + 1 == steps ? loss : nullptr, s);
         if (st != NIRC_OK) return st;

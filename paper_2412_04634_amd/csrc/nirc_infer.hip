@@ -190,12 +190,15 @@ __device__ __forceinline__ void train_sample(const Points &pts, const nirc_lobes
     target[3 * b + 2] = L[2];
 }
 
+// Step step + blockIdx.y into the buffers offset by blockIdx.y * stride.
 __global__ void k_train_batch(Points pts, nirc_lobes lobes, int64_t batch, uint32_t key0,
                               uint32_t key1, uint32_t frame, uint32_t step, int mode, int32_t *point,
-                              float *wx, float *wy, float *wz, float *target) {
+                              float *wx, float *wy, float *wz, float *target, int64_t stride) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
-    train_sample(pts, lobes, key0, key1, frame, step, mode, b, point, wx, wy, wz, target);
+    const int64_t o = (int64_t)blockIdx.y * stride;
+    train_sample(pts, lobes, key0, key1, frame, step + blockIdx.y, mode, b, point + o, wx + o, wy + o, wz + o,
+                 target + o);
 }
 
 // The training samples of step `step` of every request of a training work list (request
@@ -534,11 +537,12 @@ hipError_t launch_bth(const Points &pts, const nirc_lobes &lobes, int n_cache, u
 
 hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_t batch,
                               uint64_t seed, uint64_t frame, uint32_t step, int mode, int32_t *point,
-                              float *wx, float *wy, float *wz, float *target, hipStream_t s) {
-    if (batch == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_train_batch, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, pts,
+                              float *wx, float *wy, float *wz, float *target, hipStream_t s, int nsteps,
+                              int64_t stride) {
+    if (batch == 0 || nsteps < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_train_batch, dim3((unsigned)((batch + 255) / 256), (unsigned)nsteps), dim3(256), 0, s, pts,
                        lobes, batch, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)frame, step, mode,
-                       point, wx, wy, wz, target);
+                       point, wx, wy, wz, target, stride);
     return hipGetLastError();
 }
 

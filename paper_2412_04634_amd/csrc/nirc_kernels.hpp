@@ -441,9 +441,14 @@ hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t 
 hipError_t launch_encode(const Points &pts, const Queries &q, float *feat, hipStream_t s);
 hipError_t launch_sample_dirs(const Points &pts, int n_cache, uint64_t seed, uint64_t frame,
                               float *dirs, hipStream_t s);
+// Training samples of steps step .. step + nsteps - 1 in one launch; step k's buffers start
+// (k - step) * stride elements after the given ones.
 hipError_t launch_train_batch(const Points &pts, const nirc_lobes &lobes, int64_t batch,
                               uint64_t seed, uint64_t frame, uint32_t step, int mode, int32_t *point,
-                              float *wx, float *wy, float *wz, float *target, hipStream_t s);
+                              float *wx, float *wy, float *wz, float *target, hipStream_t s, int nsteps = 1,
+                              int64_t stride = 0);
+// Steps of a training frame whose samples one launch makes (the workspace holds them).
+constexpr int kFrameSampleSteps = 4;
 // Reference integral of V L over the hemisphere (tensor Gauss-Legendre on the cosine map's
 // uniforms; nodes and weights on [0, 1] from the host), FP64 [P][3].
 constexpr int kMaxQuadNodes = 128;
