@@ -120,6 +120,37 @@ def cpu_baseline(pts, lobes_for, w0, W, N, B, steps_per_frame, target_s=12.0, ta
                          "sample": f"{n1} points, training batch {b1}; {t1:.1f} s"}}
 
 
+def mfma_probe(nirc):
+    """The matrix rate a kernel of independent MFMA chains reaches here (1024 workgroups, 4 waves
+    per SIMD; second launch of each), per precision, and the same BF16 kernel with 32 or 64 FP32
+    FMAs per 8 MFMAs in each wave: the measured peak the roofline fractions are also quoted
+    against, and whether VALU work hides under the MFMAs."""
+    import torch
+    sink = torch.empty(1024 * 256, dtype=torch.float32, device="cuda")
+    out = {}
+
+    def timed(prec, iters, fmas):
+        t = None
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            flops = nirc.nirc_probe_mfma(prec, iters, fmas, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3
+        return flops, t
+
+    for name, prec, iters in (("fp32", 0, 2048), ("bf16", 1, 4096), ("fp16", 2, 4096)):
+        flops, t = timed(prec, iters, 0)
+        out[name] = {"tflops": flops / t / 1e12, "ms": t * 1e3,
+                     "frac_of_vendor_peak": flops / t / (PEAK_FP32_MFMA if prec == 0 else PEAK_BF16_MFMA)}
+    _, t0 = timed(1, 4096, 0)
+    for fm in (32, 64):
+        _, t = timed(1, 4096, fm)
+        out[f"bf16_plus_{fm}_fma_per_8_mfma"] = {"ms": t * 1e3, "ratio_to_mfma_only": t / t0}
+    return out
+
+
 def precision_compare(nirc, model32, dp, lobes_for, table, fs, P, N, W, seed, frame, reps, B, S):
     """BF16 and FP16 estimates with the FP32 model's current weights, same seed and frame:
     time per launch (HIP events on the launch stream) and MRSE against the exact integral; and
@@ -856,9 +887,16 @@ def main():
         "v_rel_residual_ema": v_rel_ema,
         "final_loss": float(loss.item()),
     }
+    probe = mfma_probe(nirc)
+    result["mfma_probe"] = probe
+    result["roofline"]["peak_measured"] = probe["fp32"]["tflops"]
+    result["roofline"]["frac_measured"] = achieved / 1e12 / probe["fp32"]["tflops"]
     if not args.no_precision_compare:
         result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
                                                         args.warmup + args.steps, args.steps, B, S)
+        for name, v in result["precision_compare"].items():
+            v["roofline"]["peak_measured"] = probe[name]["tflops"]
+            v["roofline"]["frac_measured"] = v["roofline"]["achieved"] / probe[name]["tflops"]
         result["biased_bth"] = biased_compare(nirc, model, dp, lobes_for, table, fs, P, N, seed,
                                               args.warmup + args.steps, min(args.steps, 20))
         result["precision_trained"] = precision_trained(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)

@@ -547,6 +547,17 @@ nirc_status nirc_hash_train_frame(nirc_hash_model *model, nirc_points points, co
 /* Flags raised by training (synchronises the stream); 0xFFFFFFFF on error. */
 uint32_t nirc_hash_read_flags(const nirc_hash_model *model, void *stream);
 
+/* Matrix-core microbenchmark (measurement, not part of the method): `blocks` workgroups of 256
+ * threads, each wave running `iters` (a multiple of 32) iterations of 8 independent MFMA accumulations
+ * (16x16x32 for NIRC_BF16 / NIRC_FP16: 16,384 FLOPs each; 16x16x4 FP32 for NIRC_FP32: 2,048
+ * FLOPs each) followed by `fmas` (0, 32 or 64) independent FP32 FMAs per lane.  Writes one float
+ * per thread to sink [blocks x 256] (device) so that nothing is optimised away.  Timed by the
+ * caller: 8 x iters x 4 x blocks MFMAs per launch give the matrix rate the roofline fractions
+ * are also quoted against (beside the vendor peak); fmas > 0 shows whether FP32 VALU work hides
+ * under the MFMAs.  NIRC_ERR_INVALID_ARG for other precisions, counts or a NULL sink. */
+nirc_status nirc_probe_mfma(int32_t precision, int32_t iters, int32_t fmas, int32_t blocks, float *sink,
+                            void *stream);
+
 const char *nirc_status_string(nirc_status s);
 
 #ifdef __cplusplus

@@ -108,6 +108,7 @@ def lib():
             "nirc_adam_step": (_i32, [_vp, _vp, _vp]),
             "nirc_train_step": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
             "nirc_train_step_static": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
+            "nirc_probe_mfma": (_i32, [_i32, _i32, _i32, _i32, _vp, _vp]),
             "tlmc_reference_table": (_i32, [ctypes.POINTER(Lobes), _vp, _vp]),
             "tlmc_reference": (_i32, [_Points, ctypes.POINTER(Lobes), _vp, _vp, _vp]),
             "tlmc_frame_stats_scratch_bytes": (_sz, []),
@@ -437,6 +438,16 @@ def nirc_train_step(model: Model, points: Points, queries: Queries, target: torc
     _check(lib().nirc_train_step(model.handle, points.c(), queries.c(), _ptr(target), _ptr(loss), _stream()),
            "nirc_train_step")
     return loss
+
+
+def nirc_probe_mfma(precision: int, iters: int, fmas: int, sink: torch.Tensor):
+    """Matrix-core microbenchmark on the current stream: sink.numel() // 256 workgroups, each wave
+    `iters` (a multiple of 32) iterations of 8 independent MFMAs plus `fmas` (0, 32, 64) FP32 FMAs;
+    returns the FLOPs of its MFMAs (the caller times the launch)."""
+    blocks = sink.numel() // 256
+    _check(lib().nirc_probe_mfma(precision, iters, fmas, blocks, _ptr(sink), _stream()), "nirc_probe_mfma")
+    per_mfma = 2048 if precision == NIRC_FP32 else 16384
+    return 8 * iters * 4 * blocks * per_mfma
 
 
 NIRC_STATIC_MAX_BATCH = 2048
