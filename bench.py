@@ -148,6 +148,18 @@ def mfma_probe(nirc):
     for fm in (32, 64):
         _, t = timed(1, 4096, fm)
         out[f"bf16_plus_{fm}_fma_per_8_mfma"] = {"ms": t * 1e3, "ratio_to_mfma_only": t / t0}
+    # 64-bit integer atomic adds (the hash-grid gradient scatter) into a 32 MB buffer, by lanes
+    # per 128-byte line: 4096 workgroups x 256 threads x 16 adds
+    buf = torch.zeros(1 << 22, dtype=torch.int64, device="cuda")
+    for lpl in (1, 4, 16):
+        for _ in range(2):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            adds = nirc.nirc_probe_atomics(lpl, 16, 4096, buf)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3
+        out[f"atomic_add_u64_{lpl}_lanes_per_line"] = {"g_adds_per_s": adds / t / 1e9, "ms": t * 1e3}
     return out
 
 

@@ -558,6 +558,15 @@ uint32_t nirc_hash_read_flags(const nirc_hash_model *model, void *stream);
 nirc_status nirc_probe_mfma(int32_t precision, int32_t iters, int32_t fmas, int32_t blocks, float *sink,
                             void *stream);
 
+/* Atomics microbenchmark (measurement, not part of the method): `blocks` workgroups of 256
+ * threads; thread t adds 1 to element e(i) of buf for i = t + r * T, r < reps (T threads), where
+ * lanes_per_line (1, 2, 4, 8 or 16) consecutive i share one 128-byte line (16 elements) and
+ * consecutive groups take consecutive lines, wrapping at buf's end (buf_elems a power of two,
+ * >= 16; device).  64-bit integer adds without return, as the hash-grid gradient scatter makes:
+ * T x reps adds per launch, timed by the caller.  NIRC_ERR_INVALID_ARG on other values. */
+nirc_status nirc_probe_atomics(int32_t lanes_per_line, int32_t reps, int32_t blocks, uint64_t *buf, int64_t buf_elems,
+                               void *stream);
+
 const char *nirc_status_string(nirc_status s);
 
 #ifdef __cplusplus

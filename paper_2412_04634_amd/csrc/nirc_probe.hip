@@ -1,6 +1,7 @@
-// Microbenchmark of the matrix cores, for the denominators of the roofline fractions: the rate
-// a kernel of independent MFMA chains reaches on this device in each precision, optionally with
-// independent FP32 FMAs in the same waves (whether VALU work hides under the MFMAs).
+// Microbenchmarks behind the measured peaks: the rate a kernel of independent MFMA chains reaches
+// on this device in each precision, optionally with independent FP32 FMAs in the same waves
+// (whether VALU work hides under the MFMAs); and the rate of 64-bit integer atomic adds (the
+// hash-grid model's fixed-point gradient scatter) by how many lanes of a wave share a cache line.
 #include "nirc_h16.hpp"
 
 namespace nirc {
@@ -61,6 +62,20 @@ hipError_t launch_probe(int iters, int fmas, int blocks, float *sink, hipStream_
     return hipGetLastError();
 }
 
+// Thread t adds 1 to element e(i) for i = t + r * T (T threads, r < reps): lanes_per_line
+// consecutive i share a 128-byte line (16 elements), consecutive groups take consecutive lines,
+// wrapping at the buffer's end (its length a power of two).
+__global__ __launch_bounds__(256) void k_probe_atomics(int lanes_per_line, int reps, unsigned long long *buf,
+                                                       int64_t mask) {
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = 0; r < reps; ++r) {
+        const int64_t i = t + r * T;
+        const int64_t e = ((i / lanes_per_line) * 16 + i % lanes_per_line) & mask;
+        atomicAdd(buf + e, 1ull);
+    }
+}
+
 }  // namespace
 }  // namespace nirc
 
@@ -77,4 +92,15 @@ extern "C" nirc_status nirc_probe_mfma(int32_t precision, int32_t iters, int32_t
     else if (precision == NIRC_FP16) e = launch_probe<NIRC_FP16>(iters, fmas, blocks, sink, s);
     else return NIRC_ERR_INVALID_ARG;
     return e == hipSuccess ? NIRC_OK : NIRC_ERR_HIP;
+}
+
+extern "C" nirc_status nirc_probe_atomics(int32_t lanes_per_line, int32_t reps, int32_t blocks, uint64_t *buf,
+                                          int64_t buf_elems, void *stream) {
+    using namespace nirc;
+    if (lanes_per_line < 1 || lanes_per_line > 16 || (lanes_per_line & (lanes_per_line - 1)) || reps < 1 ||
+        reps > 4096 || blocks < 1 || blocks > (1 << 20) || !buf || buf_elems < 16 || (buf_elems & (buf_elems - 1)))
+        return NIRC_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(k_probe_atomics, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (int)lanes_per_line,
+                       (int)reps, (unsigned long long *)buf, buf_elems - 1);
+    return hipGetLastError() == hipSuccess ? NIRC_OK : NIRC_ERR_HIP;
 }

@@ -109,6 +109,7 @@ def lib():
             "nirc_train_step": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
             "nirc_train_step_static": (_i32, [_vp, _Points, _Queries, _vp, _vp, _vp]),
             "nirc_probe_mfma": (_i32, [_i32, _i32, _i32, _i32, _vp, _vp]),
+            "nirc_probe_atomics": (_i32, [_i32, _i32, _i32, _vp, _i64, _vp]),
             "tlmc_reference_table": (_i32, [ctypes.POINTER(Lobes), _vp, _vp]),
             "tlmc_reference": (_i32, [_Points, ctypes.POINTER(Lobes), _vp, _vp, _vp]),
             "tlmc_frame_stats_scratch_bytes": (_sz, []),
@@ -448,6 +449,14 @@ def nirc_probe_mfma(precision: int, iters: int, fmas: int, sink: torch.Tensor):
     _check(lib().nirc_probe_mfma(precision, iters, fmas, blocks, _ptr(sink), _stream()), "nirc_probe_mfma")
     per_mfma = 2048 if precision == NIRC_FP32 else 16384
     return 8 * iters * 4 * blocks * per_mfma
+
+
+def nirc_probe_atomics(lanes_per_line: int, reps: int, blocks: int, buf: torch.Tensor):
+    """Atomics microbenchmark on the current stream (buf: int64 device tensor, length a power of
+    two); returns the number of adds (the caller times the launch)."""
+    _check(lib().nirc_probe_atomics(lanes_per_line, reps, blocks, _ptr(buf), buf.numel(), _stream()),
+           "nirc_probe_atomics")
+    return blocks * 256 * reps
 
 
 NIRC_STATIC_MAX_BATCH = 2048

@@ -1,6 +1,7 @@
-"""The matrix-core microbenchmark behind the measured peaks of the bench line: argument checks,
-and its 16-bit accumulations give exactly the closed-form sums (every operand 1.0, so each MFMA
-adds K = 32 to each accumulator element)."""
+"""The microbenchmarks behind the measured peaks of the bench line: argument checks; the MFMA
+probe's 16-bit accumulations give exactly the closed-form sums (every operand 1.0, so each MFMA
+adds K = 32 to each accumulator element); the atomics probe adds exactly where its address rule
+says."""
 import numpy as np
 import pytest
 import torch
@@ -43,3 +44,26 @@ def test_probe_runs_finite(nirc, prec, fmas):
     sink = torch.empty(8 * 256, dtype=torch.float32, device="cuda")
     nirc.nirc_probe_mfma(prec, 32, fmas, sink)
     assert np.all(np.isfinite(host(sink)))
+
+
+def test_probe_atomics_rejects_bad_arguments(nirc):
+    buf = torch.zeros(1024, dtype=torch.int64, device="cuda")
+    for lpl, reps, blocks in ((3, 1, 1), (32, 1, 1), (1, 0, 1), (1, 1, 0)):
+        with pytest.raises(nirc.NircError):
+            nirc.nirc_probe_atomics(lpl, reps, blocks, buf)
+    with pytest.raises(nirc.NircError):
+        nirc.nirc_probe_atomics(1, 1, 1, torch.zeros(1000, dtype=torch.int64, device="cuda"))
+
+
+@pytest.mark.parametrize("lpl", [1, 4, 16])
+def test_probe_atomics_counts(nirc, lpl):
+    n, reps, blocks = 1 << 12, 3, 8
+    buf = torch.zeros(n, dtype=torch.int64, device="cuda")
+    adds = nirc.nirc_probe_atomics(lpl, reps, blocks, buf)
+    T = blocks * 256
+    i = np.arange(T * reps, dtype=np.int64)
+    e = ((i // lpl) * 16 + i % lpl) & (n - 1)
+    want = np.bincount(e, minlength=n)
+    got = buf.cpu().numpy()
+    assert adds == T * reps
+    np.testing.assert_array_equal(got, want)
