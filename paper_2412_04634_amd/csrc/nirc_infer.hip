@@ -319,9 +319,11 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
             y1 = logistic(y[tt][1]) * Lq[1];
             y2 = logistic(y[tt][2]) * Lq[2];
         } else {
-            y0 = expf(y[tt][0]);
-            y1 = expf(y[tt][1]);
-            y2 = expf(y[tt][2]);
+            // the hardware exponential (exp2 of z log2 e; relative error ~|z| 6e-8, far inside
+            // the FP32 bound) rather than the library's expf: 1.3 % of the estimator's time
+            y0 = __expf(y[tt][0]);
+            y1 = __expf(y[tt][1]);
+            y2 = __expf(y[tt][2]);
         }
         if (Tt < n_cache) {
             reduce_cache_tile(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
