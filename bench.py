@@ -903,6 +903,9 @@ def main():
     result["mfma_probe"] = probe
     result["roofline"]["peak_measured"] = probe["fp32"]["tflops"]
     result["roofline"]["frac_measured"] = achieved / 1e12 / probe["fp32"]["tflops"]
+    if result["roofline"]["traffic"] is not None:   # the HBM side of the same launch (far from its bound)
+        result["roofline"]["hbm_gbps"] = result["roofline"]["traffic"] / t_est_avg / 1e9
+        result["roofline"]["hbm_frac"] = result["roofline"]["traffic"] / t_est_avg / PEAK_HBM
     if not args.no_precision_compare:
         result["precision_compare"] = precision_compare(nirc, model, dp, lobes_for, table, fs, P, N, W, seed,
                                                         args.warmup + args.steps, args.steps, B, S)
