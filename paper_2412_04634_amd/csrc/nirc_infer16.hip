@@ -252,7 +252,9 @@ __device__ __forceinline__ void tlmc_tiles_h16(int T0, int s0, int n_cache, DivN
             rdy = gs.db[kDirSlots + qi];
             rdz = gs.db[2 * kDirSlots + qi];
         }
-        const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(16 * Tt + col), dn) : col;
+        // the point of this column's query; with N a multiple of 16 a cache tile holds one point
+        // (a wave-uniform row of the slab)
+        const int j = (Tt < n_cache) ? (int)div_n((uint32_t)(N16 ? 16 * Tt : 16 * Tt + col), dn) : col;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) h[tt][mt] = *(const f32x4 *)(gs.hs + j * W + 16 * mt + 4 * g);
         if constexpr (T == 4 && lds_weights(W)) {
