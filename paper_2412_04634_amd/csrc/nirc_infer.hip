@@ -271,7 +271,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_infer_f32(Points pts, Queries q,
 // OCC: the occluded-scene variants (visibility cache, radiance cache of the occluded scene),
 // selected at run time by `mode`; the radiance cache of the plain scene compiles without them.
 // ENC 1: the hash-grid model's direction input (spherical harmonics; width 64).
-template <int W, int T, bool OCC, int ENC = 0>
+template <int W, int T, bool OCC, int ENC = 0, bool N16 = false>
 __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN dn, const float *db, const float *hs,
                                                const float *sD, const float *sH, const float *sO,
                                                const nirc_lobes &lobes, const float *rrad, int64_t pc,
@@ -326,7 +326,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
             y2 = __expf(y[tt][2]);
         }
         if (Tt < n_cache) {
-            reduce_cache_tile(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
+            reduce_cache_tile<N16>(Tt, n_cache, col, y0, y1, y2, fc0, fc1, fc2);
         } else {
             float Lr[3];
             if (rrad) {   // uniform: the caller's residual radiance
@@ -364,7 +364,7 @@ __device__ __forceinline__ void tlmc_tiles_f32(int T0, int s0, int n_cache, DivN
 // field and subtracts.  Only the final per-point values leave the chip.
 // One point group (16 points from p0) through the FP32 chain.
 // ENC 1: the hash-grid model (surface part from the grid `slv`/`table` and phi).
-template <int W, bool OCC, int ENC = 0>
+template <int W, bool OCC, int ENC = 0, bool N16 = false>
 __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, int n_cache, DivN dn, uint32_t key0,
                                                uint32_t key1, uint32_t frame, int mode, const float *rrad,
                                                float *out_tl,
@@ -407,11 +407,11 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         constexpr int TP = W <= 64 ? 4 : 2;   // tiles per pass (register budget)
 #pragma unroll 1
         for (; t + TP <= tend; t += TP)
-            tlmc_tiles_f32<W, TP, OCC, ENC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs,
+            tlmc_tiles_f32<W, TP, OCC, ENC, N16>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs,
                                             lane, g, col, fc0, fc1, fc2, fr0, fr1, fr2);
 #pragma unroll 1
         for (; t < tend; ++t)
-            tlmc_tiles_f32<W, 1, OCC, ENC>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs,
+            tlmc_tiles_f32<W, 1, OCC, ENC, N16>(t, t - tb, n_cache, dn, db, hs, sD, sH, sO, lobes, rrad, pc, pts, p0, mode, xs,
                                            lane, g, col, fc0, fc1, fc2, fr0, fr1, fr2);
         tb = tend;
     }
@@ -419,7 +419,8 @@ __device__ __forceinline__ void tlmc_group_f32(const Points &pts, int64_t p0, in
         store_estimate(p0 + col, 1.0f / (float)n_cache, fc0, fc1, fc2, fr0, fr1, fr2, out_tl, out_c, out_r);
 }
 
-template <int W, int WAVES, bool OCC>
+// N16: n_cache is a multiple of 16 (the per-point sums' other paths compiled out).
+template <int W, int WAVES, bool OCC, bool N16 = false>
 __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes lobes,
                                                          const float *__restrict__ packed,
                                                          int n_cache, DivN dn, uint32_t key0, uint32_t key1,
@@ -448,8 +449,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_tlmc_f32(Points pts, nirc_lobes 
     float *db = hs + 16 * W;               // directions, SoA [3][kDirSlots]
     const int64_t n_groups = (pts.count + 15) >> 4;
     for (int64_t grp = (int64_t)blockIdx.x * WAVES + wave; grp < n_groups; grp += (int64_t)gridDim.x * WAVES)
-        tlmc_group_f32<W, OCC>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode, rrad, out_tl, out_c, out_r, s_lobes, gS,
-                          sD, sH, sO, hs, db, lane, g, col);
+        tlmc_group_f32<W, OCC, 0, N16>(pts, grp << 4, n_cache, dn, key0, key1, frame, mode, rrad, out_tl, out_c, out_r,
+                                       s_lobes, gS, sD, sH, sO, hs, db, lane, g, col);
 }
 
 // Continuous batching with the FP32 chain (see k_tlmc_multi_h16).
@@ -597,7 +598,10 @@ hipError_t launch_tlmc(int W, int prec, const Points &pts, const nirc_lobes &lob
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32), f = (uint32_t)frame;
     const float *pk = (const float *)packed;
     const bool occ = mode != NIRC_OUTPUT_RADIANCE;
-    if (W == 64 && !occ)
+    if (W == 64 && !occ && n_cache % 16 == 0)
+        hipLaunchKernelGGL((k_tlmc_f32<64, WAVES, false, true>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk,
+                           n_cache, dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
+    else if (W == 64 && !occ)
         hipLaunchKernelGGL((k_tlmc_f32<64, WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, pts, lobes, pk, n_cache,
                            dn, k0, k1, f, mode, rrad, out_tl, out_c, out_r);
     else if (W == 64)

@@ -289,9 +289,11 @@ __device__ __forceinline__ float dpp_add(float x, int ctrl_step) {
 // sum of its queries in this tile.  N a multiple of 16: the tile belongs to one point and a DPP
 // row sum suffices; N dividing 16: DPP segment sums and one cross-lane read; any other N:
 // 16-lane inclusive prefix sums.
+// N16: n_cache is known to be a multiple of 16 (only the first path is compiled).
+template <bool N16 = false>
 __device__ __forceinline__ void reduce_cache_tile(int T, int n_cache, int col, float y0, float y1, float y2,
                                                   float &fc0, float &fc1, float &fc2) {
-    if ((n_cache & 15) == 0) {
+    if (N16 || (n_cache & 15) == 0) {
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             y0 = dpp_add(y0, st);
@@ -305,48 +307,50 @@ __device__ __forceinline__ void reduce_cache_tile(int T, int n_cache, int col, f
         }
         return;
     }
-    if (n_cache < 16 && (16 % n_cache) == 0) {
-        const int steps = n_cache == 8 ? 3 : n_cache == 4 ? 2 : n_cache == 2 ? 1 : 0;
-        for (int st = 0; st < steps; ++st) {
-            y0 = dpp_add(y0, st);
-            y1 = dpp_add(y1, st);
-            y2 = dpp_add(y2, st);
+    if constexpr (!N16) {
+        if (n_cache < 16 && (16 % n_cache) == 0) {
+            const int steps = n_cache == 8 ? 3 : n_cache == 4 ? 2 : n_cache == 2 ? 1 : 0;
+            for (int st = 0; st < steps; ++st) {
+                y0 = dpp_add(y0, st);
+                y1 = dpp_add(y1, st);
+                y2 = dpp_add(y2, st);
+            }
+            // point `col` is segment (col - 16T/N) of this tile if that lies in [0, 16/N)
+            const int seg = col - (16 * T) / n_cache;
+            const bool mine = seg >= 0 && seg < 16 / n_cache;
+            const int src = mine ? seg * n_cache : 0;
+            const float s0 = __shfl(y0, src, 16), s1 = __shfl(y1, src, 16), s2 = __shfl(y2, src, 16);
+            if (mine) {
+                fc0 += s0;
+                fc1 += s1;
+                fc2 += s2;
+            }
+            return;
         }
-        // point `col` is segment (col - 16T/N) of this tile if that lies in [0, 16/N)
-        const int seg = col - (16 * T) / n_cache;
-        const bool mine = seg >= 0 && seg < 16 / n_cache;
-        const int src = mine ? seg * n_cache : 0;
-        const float s0 = __shfl(y0, src, 16), s1 = __shfl(y1, src, 16), s2 = __shfl(y2, src, 16);
-        if (mine) {
-            fc0 += s0;
-            fc1 += s1;
-            fc2 += s2;
-        }
-        return;
-    }
-    float s0 = y0, s1 = y1, s2 = y2;
+        float s0 = y0, s1 = y1, s2 = y2;
 #pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-        const float u0 = __shfl_up(s0, d, 16);
-        const float u1 = __shfl_up(s1, d, 16);
-        const float u2 = __shfl_up(s2, d, 16);
-        if (col >= d) {
-            s0 += u0;
-            s1 += u1;
-            s2 += u2;
+        for (int d = 1; d < 16; d <<= 1) {
+            const float u0 = __shfl_up(s0, d, 16);
+            const float u1 = __shfl_up(s1, d, 16);
+            const float u2 = __shfl_up(s2, d, 16);
+            if (col >= d) {
+                s0 += u0;
+                s1 += u1;
+                s2 += u2;
+            }
         }
-    }
-    // point `col` owns queries [col N, col N + N) -> columns [lo, hi)
-    const int a = col * n_cache - 16 * T;
-    const int lo = max(a, 0), hi = min(a + n_cache, 16);
-    const int shi = min(max(hi - 1, 0), 15), slo = min(max(lo - 1, 0), 15);
-    const float h0 = __shfl(s0, shi, 16), l0 = __shfl(s0, slo, 16);
-    const float h1 = __shfl(s1, shi, 16), l1 = __shfl(s1, slo, 16);
-    const float h2 = __shfl(s2, shi, 16), l2 = __shfl(s2, slo, 16);
-    if (lo < hi) {
-        fc0 += lo > 0 ? h0 - l0 : h0;
-        fc1 += lo > 0 ? h1 - l1 : h1;
-        fc2 += lo > 0 ? h2 - l2 : h2;
+        // point `col` owns queries [col N, col N + N) -> columns [lo, hi)
+        const int a = col * n_cache - 16 * T;
+        const int lo = max(a, 0), hi = min(a + n_cache, 16);
+        const int shi = min(max(hi - 1, 0), 15), slo = min(max(lo - 1, 0), 15);
+        const float h0 = __shfl(s0, shi, 16), l0 = __shfl(s0, slo, 16);
+        const float h1 = __shfl(s1, shi, 16), l1 = __shfl(s1, slo, 16);
+        const float h2 = __shfl(s2, shi, 16), l2 = __shfl(s2, slo, 16);
+        if (lo < hi) {
+            fc0 += lo > 0 ? h0 - l0 : h0;
+            fc1 += lo > 0 ? h1 - l1 : h1;
+            fc2 += lo > 0 ? h2 - l2 : h2;
+        }
     }
 }
 
