@@ -46,7 +46,9 @@ __device__ inline float out_grad(float z, float t, float dr, bool use_loss, floa
 // (a quarter of every layer's column tiles) held in registers across rounds, and adds the
 // round's 64 samples with MFMAs whose K dimension is the sample index.  At the end every tile is
 // written once into this workgroup's partial gradient (canonical layout).
-template <int W>
+// PLAIN: targets given, relative L2 of eq. 12, no residual-variance mean, exp outputs (the general
+// loss arithmetic compiled out).
+template <int W, bool PLAIN = false>
 __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queries q,
                                                                const float *__restrict__ packed,
                                                                TrainArgs args, float *__restrict__ partials,
@@ -65,7 +67,7 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, g = lane >> 4;
     const int64_t B = q.count;
-    const bool use_loss = args.target != nullptr;
+    const bool use_loss = PLAIN || args.target != nullptr;
     const float kscale = use_loss ? 2.0f * args.loss_scale / (3.0f * (float)B) : args.loss_scale;
 
     // owned gradient tiles: first layer input columns {wave, wave+4, wave+8} (< 10), column tile
@@ -150,8 +152,10 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_grad_f32(Points pts, Queri
                     const float t = use_loss ? args.target[3 * b + c] : 0.0f;
                     const float dr = use_loss ? 0.0f : args.d_rgb[3 * b + c];
                     float lt;
-                    d5[c] = out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale, args.loss_kind == NIRC_LOSS_REL_L2,
-                                     args.fr ? args.fr[c] : 0.0f, args.sig != 0, lt);
+                    d5[c] = PLAIN ? out_grad(z5[c], t, 0.0f, true, args.loss_eps, kscale, true, 0.0f, false, lt)
+                                  : out_grad(z5[c], t, dr, use_loss, args.loss_eps, kscale,
+                                             args.loss_kind == NIRC_LOSS_REL_L2, args.fr ? args.fr[c] : 0.0f,
+                                             args.sig != 0, lt);
                     loss_acc += lt;
                 }
             }
@@ -769,8 +773,12 @@ hipError_t launch_grad_partials(int W, const Points &pts, const Queries &q, cons
         return hipGetLastError();
     }
     if (W != 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_grad_f32<64>), dim3(nblocks), dim3(kTrainWaves * 64), 0, s, pts, q, packed, a,
-                       partials, loss_partials);
+    if (a.target && a.loss_kind == NIRC_LOSS_REL_L2 && !a.fr && !a.sig)
+        hipLaunchKernelGGL((k_grad_f32<64, true>), dim3(nblocks), dim3(kTrainWaves * 64), 0, s, pts, q, packed, a,
+                           partials, loss_partials);
+    else
+        hipLaunchKernelGGL((k_grad_f32<64>), dim3(nblocks), dim3(kTrainWaves * 64), 0, s, pts, q, packed, a,
+                           partials, loss_partials);
     return hipGetLastError();
 }
 
