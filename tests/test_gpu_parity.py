@@ -273,11 +273,11 @@ def test_train_steps_follow_oracle(nirc):
 
 
 @pytest.mark.parametrize("prec,output", [(0, 0), (1, 0), (2, 0), (1, 1), (2, 2)])
-@pytest.mark.parametrize("P,B,steps", [(4096, 4096, 4), (777, 1000, 3), (5000, 65, 1)])
+@pytest.mark.parametrize("P,B,steps", [(4096, 4096, 4), (777, 1000, 3), (5000, 65, 1), (3000, 512, 6)])
 def test_train_frame_equals_separate_steps(nirc, P, B, steps, prec, output):
     # the one-call frame of training draws the same samples and takes the same Adam steps as
-    # tlmc_train_batch + nirc_train_step called step by step (16-bit models make the samples
-    # inside the gradient kernel, FP32 models through the sample buffers)
+    # tlmc_train_batch + nirc_train_step called step by step (the frame makes the samples of up
+    # to 4 steps in one launch; 6 steps take two such launches)
     say("train_frame", P, B, steps, prec, output)
     pts, lobes, w0 = scene(23, P)
     dp = nirc.Points.from_workload(pts)
