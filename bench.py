@@ -429,7 +429,7 @@ def algorithmic_flops_hash(P: int, N: int, W: int = 64) -> float:
     return float(P) * (2 * 39 * W + (N + 1) * 2 * (25 * W + 3 * W * W + 3 * W))
 
 
-def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S, reps=20):
+def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B, S, reps=20, pts_host=None):
     """The paper's own cache input (hash grid on x, spherical harmonics of w, one-blob surface
     values) against the frequency input, both BF16, and the hash-grid cache trained and evaluated
     in FP32, each trained online from its initial weights over the same rotating frames: time per estimate (N + 1 queries per point) and per training
@@ -534,6 +534,24 @@ def hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, frames, B,
             sweep.append(row)
             del mm
     out["hash_precision_sweep"] = sweep
+    # the same BF16 estimate with the points in a locality (Morton) order, as a renderer's
+    # screen-space order would give them: the grid gather's cache lines are shared by neighbours
+    if pts_host is not None:
+        dpm = nirc.Points.from_workload(pts_host.subset(wl.morton_order(pts_host)))
+        out_m = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+        nirc.nirc_hash_estimate(hm, dpm, lob, N, seed, frames, out=out_m)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            nirc.nirc_hash_estimate(hm, dpm, lob, N, seed, frames, out=out_m)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        flops = algorithmic_flops_hash(P, N)
+        out["hash_grid_bf16_locality_order"] = {
+            "ms_estimate": ms, "queries_per_s": P * (N + 1) / (ms * 1e-3), "mfma_frac": flops / (ms * 1e-3) / PEAK_BF16_MFMA,
+            "mrse": float(nirc.tlmc_frame_stats(dpm, lob, table, out_m, fs=fs)[4].item())}
+        del dpm
     out["frames"] = frames
     out["grid_gather_bytes_per_point"] = 12 * 8 * 8
     return out
@@ -921,7 +939,8 @@ def main():
     if args.visibility:
         result["visibility"] = visibility_compare(nirc, w0, dp, lobes_for, P, N, seed, 100, B, S)
     if args.hash_grid:
-        result["hash_grid"] = hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
+        result["hash_grid"] = hash_grid_compare(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S,
+                                                pts_host=scene.points)
     if args.loss_variants:
         result["loss_variants"] = loss_variants(nirc, w0, dp, lobes_for, table, fs, P, N, seed, 100, B, S)
     if args.train_convergence:

@@ -114,6 +114,20 @@ def make_points(seed: int, count: int) -> Points:
                   f(nrm[:, 2]), f(rough))
 
 
+def morton_order(points: Points, bits: int = 10) -> np.ndarray:
+    """A locality order of the points: indices sorted by the Morton (Z-order) code of their
+    positions quantised to 2^bits cells per axis.  Stands in for the screen-space coherence of a
+    renderer's shading points when a kernel gathers by position (the set and each point's
+    values are unchanged; only the order)."""
+    q = [np.clip((np.asarray(a, np.float64) * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+         for a in (points.px, points.py, points.pz)]
+    code = np.zeros(points.count, np.int64)
+    for b in range(bits):
+        for axis in range(3):
+            code |= ((q[axis] >> b) & 1) << (3 * b + axis)
+    return np.argsort(code, kind="stable")
+
+
 def layer_shapes(width: int):
     """(rows, cols) of the five weight matrices: 160->W, 3 x (W->W), W->3 (no biases)."""
     return [(width, N_FEATURES), (width, width), (width, width), (width, width), (3, width)]

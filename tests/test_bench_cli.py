@@ -1,9 +1,12 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a message (the hot path
-runs on one GPU), and the flop counts it reports follow the per-point formulas."""
+runs on one GPU), the flop counts it reports follow the per-point formulas, and the locality
+order it times the hash-grid estimate with is a permutation of neighbours."""
 import json
 import os
 import subprocess
 import sys
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -36,3 +39,16 @@ def test_cpu_baseline_leg_runs():
     r = bench.cpu_baseline(pts, lambda f: lob, w0, 64, 4, 256, 1, target_s=0.05, target_1core_s=0.05)
     assert r["kind"] == "oracle" and r["unit"] == "queries/s" and r["value"] > 0 and r["cores"] >= 1
     assert r["one_core"]["cores"] == 1 and r["one_core"]["value"] > 0
+
+
+def test_morton_order_is_a_locality_permutation():
+    from paper_2412_04634_amd import workload as wl
+    p = wl.make_points(5, 20000)
+    o = wl.morton_order(p)
+    assert np.array_equal(np.sort(o), np.arange(p.count))
+    q = p.subset(o)
+    step = lambda a: np.abs(np.diff(a.px)) + np.abs(np.diff(a.py)) + np.abs(np.diff(a.pz))
+    # consecutive points are neighbours in the new order (a random order steps ~1.0 on average)
+    assert step(q).mean() < 0.1 * step(p).mean()
+    # each point keeps its values
+    assert np.array_equal(q.px, p.px[o]) and np.array_equal(q.rough, p.rough[o])
