@@ -206,9 +206,11 @@ __device__ __forceinline__ void cosine_dir_fast(float nx, float ny, float nz, fl
     wz = lx * tz - ly * ny + lz * nz;
 }
 
-// The estimators' direction batch: as gen_dirs_batch (same counters, same slots), with the
-// group's normals read from the slab (nrm [3][16], staged once per group) instead of global
-// memory and 32-bit point indices (point counts stay below 2^31).  FAST (the 16-bit estimators):
+// The estimators' direction batch: the directions of tiles tb .. tb + 7 of a point group (with
+// `fold`, also the residual tile after them) into the slab's slots db [3][kDirSlots], one Philox
+// block per lane giving two directions (the counters of dir_counter), with the group's normals
+// read from the slab (nrm [3][16], staged once per group) and 32-bit point indices (point counts
+// stay below 2^31).  FAST (the 16-bit estimators):
 // cache directions by the fast map; residual directions (tile n_cache, and the folded residual
 // tile) always use the exact map, so that they equal the directions tlmc_sample_dirs returns.
 template <bool FAST>
