@@ -176,25 +176,28 @@ __global__ __launch_bounds__(kStatThreads) void k_frame_stats(Points pts, nirc_l
                                                               double eps, double *partials) {
     __shared__ double tab[4 * TLMC_CHEB_COEFFS];
     __shared__ double red[kStatThreads / 64][4];
+    __shared__ int s_nk;
     for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x) tab[i] = table[i];
     __syncthreads();
-    const int nk = cheb_terms(tab);
+    if (threadIdx.x == 0) s_nk = cheb_terms(tab);   // once per workgroup
+    __syncthreads();
+    const int nk = s_nk;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pts.count;
          p += (int64_t)gridDim.x * blockDim.x) {
         double F[3];
         reference_at(lobes, tab, nk, pts, p, F);
         for (int c = 0; c < 3; ++c) {
-            const double den = F[c] * F[c] + eps;
+            const double inv = 1.0 / (F[c] * F[c] + eps);   // one division per channel
             const double e = (double)tl[3 * p + c] - F[c];
-            acc[0] += e * e / den;
+            acc[0] += e * e * inv;
             if (fc) {
                 const double ec = (double)fc[3 * p + c] - F[c];
-                acc[1] += ec * ec / den;
+                acc[1] += ec * ec * inv;
             }
             if (fr) {
                 const double r = fr[3 * p + c];
-                acc[2] += r * r / den;
+                acc[2] += r * r * inv;
             }
             acc[3] += 1.0;
         }
