@@ -28,7 +28,7 @@ PEAK_HBM = 8.0e12              # bytes/s
 # HBM bytes per launch of k_tlmc_f32 in the frame configuration (1080p, N = 16, F_tl + F_c + F_r
 # written), from FETCH_SIZE x 2.0 + WRITE_SIZE (factors from a plain 512 MiB copy); recorded in
 # profiles/k_tlmc_hbm_counters_1080p_n16.md and to be measured again whenever the kernel changes.
-TRAFFIC_K_TLMC_F32 = 134375424
+TRAFFIC_K_TLMC_F32 = 134192896
 
 
 def algorithmic_flops_estimate(P: int, N: int, W: int) -> float:
