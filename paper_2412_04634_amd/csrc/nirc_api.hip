@@ -103,7 +103,7 @@ struct nirc_model {
     uint32_t *flags, *bad;
     float *scale;          // the current loss scale (dynamic for FP16 models)
     uint32_t *good;        // finite steps since the scale last changed
-    uint32_t *done;        // finished workgroups of the running 16-bit Adam launch (zero between steps)
+    uint32_t *done;        // finished workgroups of the running Adam launch (zero between steps)
     char *ws;
     size_t ws_bytes;
     // FP16 models scale their loss dynamically; BF16 and FP32 keep cfg.loss_scale

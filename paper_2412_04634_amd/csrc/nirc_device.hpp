@@ -370,4 +370,39 @@ __host__ __device__ inline int64_t f32_packed_source(int W, int e) {
     }
 }
 
+// The packed FP32 elements that hold canonical parameter i (the inverse of f32_packed_source):
+// writes their indices to e[] and returns how many (W1: 1, W2..W5: 2, the forward and the
+// transposed section).
+__host__ __device__ inline int f32_packed_targets(int W, int64_t i, int (&e)[2]) {
+    const F32Layout L{W};
+    // element of section s holding A[row][K position (kb, g)]
+    auto at = [&](int s, int row, int kb, int g) {
+        const int lane = 16 * g + (row & 15);
+        return L.offset(s) + (((row >> 4) * (L.kb(s) / 4) + (kb >> 2)) * 64 + lane) * 4 + (kb & 3);
+    };
+    // chained K position of hidden neuron n
+    auto chain_kb = [](int n) { return 4 * (n >> 4) + (n & 3); };
+    auto chain_g = [](int n) { return (n & 15) >> 2; };
+    if (i < w_offset(W, 1)) {   // W1 [W][160]: input feature f = 16 input + 2 (2 g + fq) + sc
+        const int row = (int)(i / kFeat), f = (int)(i % kFeat);
+        const int input = f >> 4, k = (f & 15) >> 1, sc = f & 1;
+        const bool surface = input < 3 || input > 5;
+        const int pos = input < 3 ? input : input - 3;   // index in the surface or direction list
+        e[0] = at(surface ? SEC_S : SEC_D, row, 4 * pos + 2 * (k & 1) + sc, k >> 1);
+        return 1;
+    }
+    if (i < w_offset(W, 4)) {   // W2..W4 [W][W]: row r (output neuron), column c (input neuron)
+        const int l = (int)((i - w_offset(W, 1)) / ((int64_t)W * W));
+        const int r = (int)((i - w_offset(W, 1 + l)) / W), c = (int)((i - w_offset(W, 1 + l)) % W);
+        e[0] = at(SEC_H0 + l, r, chain_kb(c), chain_g(c));
+        e[1] = at(SEC_T0 + l, c, chain_kb(r), chain_g(r));
+        return 2;
+    }
+    // W5 [3][W]: output row r sits at K position (r, 0) of the transposed section
+    const int r = (int)((i - w_offset(W, 4)) / W), c = (int)((i - w_offset(W, 4)) % W);
+    e[0] = at(SEC_O, r, chain_kb(c), chain_g(c));
+    e[1] = at(SEC_OT, c, r, 0);
+    return 2;
+}
+
 }  // namespace nirc

@@ -538,9 +538,9 @@ hipError_t launch_check_finite_n(int64_t np, const float *grad, uint32_t *bad, h
 hipError_t launch_adam_n(int64_t np, float *master, float *m, float *v, const float *grad, const int64_t *step,
                          const uint32_t *bad, float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_scale_check(float *g, int64_t n, float scale, uint32_t *bad, hipStream_t s);
-// Adam on the master weights, then the refresh of the copy the kernels read (the FP32 copy for
-// FP32 models, only the 16-bit copy for 16-bit models) and the step commit.  16-bit models do
-// all three in one launch (launch_adam_pack16, `done` its workgroup counter).
+// Adam on the master weights, the refresh of the copy the kernels read (the FP32 copy for FP32
+// models, only the 16-bit copy for 16-bit models) and the step commit, in one launch (`done` its
+// workgroup counter, zero between steps).
 hipError_t launch_adam(int W, float *master, float *m, float *v, const float *grad, int64_t *step,
                        uint32_t *flags, uint32_t *bad, float lr, float b1, float b2, float eps,
                        float *packed, uint16_t *packed16, int prec, hipStream_t s, uint32_t *done,

@@ -690,18 +690,44 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
     adam_elem(w, m, v, grad, step, bad, np, lr, b1, b2, eps, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Repack the kernels' weight copy; thread 0 then commits the step (or records the skip).
-__global__ void k_pack_commit(float *packed, const float *master, int W, int total, int64_t *step,
-                              uint32_t *flags, uint32_t *bad) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < total) {
-        const int64_t s = f32_packed_source(W, e);
-        packed[e] = s >= 0 ? master[s] : 0.0f;
+// Adam on the master weights with the FP32 packed copy refreshed in the same pass: thread i
+// updates parameter i (the arithmetic of adam_elem) and stores it into the packed elements that
+// hold it (f32_packed_targets; the zero padding is written once, when the weights are set).  A
+// skipped step (`bad` set) changes nothing.  The last workgroup to finish (counted in `done`, zero
+// between steps) commits the step or records its skip: every other workgroup has read `step` and
+// `bad` before it counted itself.
+template <int W>
+__global__ __launch_bounds__(256) void k_adam_pack32(float *__restrict__ w, float *__restrict__ m,
+                                                     float *__restrict__ v, const float *__restrict__ grad,
+                                                     int64_t *step, uint32_t *flags, uint32_t *bad, uint32_t *done,
+                                                     float *__restrict__ packed, float lr, float b1, float b2,
+                                                     float eps) {
+    constexpr int64_t np = n_params(W);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np && *bad == 0u) {
+        const float t = (float)(*step + 1);
+        const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
+        const float gi = grad[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        int e[2];
+        const int n = f32_packed_targets(W, i, e);
+        for (int k = 0; k < n; ++k) packed[e[k]] = wi;
     }
-    if (e == 0) {
-        if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
-        else *step += 1;
-        *bad = 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(done, 1u) == gridDim.x - 1u) {
+            __threadfence();
+            if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
+            else *step += 1;
+            *bad = 0u;
+            *done = 0u;
+        }
     }
 }
 
@@ -805,13 +831,15 @@ hipError_t launch_adam(int W, float *master, float *m, float *v, const float *gr
     if (packed16)
         return launch_adam_pack16(W, prec, master, m, v, grad, step, flags, bad, dyn_scale, good_steps, done,
                                   packed16, lr, b1, b2, eps, s);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, master, m, v, grad,
-                       step, bad, np, lr, b1, b2, eps);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int total = F32Layout{W}.total();
-    hipLaunchKernelGGL(k_pack_commit, dim3((total + 255) / 256), dim3(256), 0, s, packed, master, W, total,
-                       step, flags, bad);
+    const dim3 grid((unsigned)((np + 255) / 256)), block(256);
+    if (W == 64)
+        hipLaunchKernelGGL(k_adam_pack32<64>, grid, block, 0, s, master, m, v, grad, step, flags, bad, done, packed,
+                           lr, b1, b2, eps);
+    else if (W == 128)
+        hipLaunchKernelGGL(k_adam_pack32<128>, grid, block, 0, s, master, m, v, grad, step, flags, bad, done,
+                           packed, lr, b1, b2, eps);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

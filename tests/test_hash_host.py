@@ -117,13 +117,18 @@ def test_device_grid_lookup_matches_oracle(tmp_path, grid):
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
 def test_h16_packed_targets_invert_the_packing(tmp_path):
-    # the per-parameter list of packed 16-bit elements (used to refresh the copy right after each
-    # Adam update) is exactly the inverse of the packing, scales included, at both widths
+    # the per-parameter lists of packed elements (used to refresh the kernels' copies right after
+    # each Adam update) are exactly the inverses of the packings, 16-bit scales included, at both
+    # widths and in both layouts
     exe = _build(tmp_path, "h16_targets_check")
     out = subprocess.run([exe], check=True, capture_output=True, text=True, timeout=300).stdout.split("\n")
     rows = [list(map(int, l.split())) for l in out if l.strip()]
-    assert [r[0] for r in rows] == [64, 128]
-    for W, bad, np_, used, listed in rows:
+    h16 = [r for r in rows if len(r) == 5]
+    f32 = [r[1:] for r in rows if len(r) == 6 and r[0] == 32]
+    assert [r[0] for r in h16] == [64, 128] and [r[0] for r in f32] == [64, 128]
+    for W, bad, np_, used, listed in h16 + f32:
         assert bad == 0, (W, bad)
         assert used == listed   # every stored element is some parameter's target
         assert np_ == W * 160 + 3 * W * W + 3 * W
+    for W, bad, np_, used, listed in f32:
+        assert listed == np_ + 3 * W * W + 3 * W   # W2..W5 twice (forward and transposed)
