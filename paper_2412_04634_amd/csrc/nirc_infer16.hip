@@ -17,23 +17,7 @@ __device__ __forceinline__ void pack16_elem(uint16_t *packed, const float *maste
         const float v = s >= 0 ? master[s] * h16_packed_scale(W, e) : 0.0f;
         packed[e] = (uint16_t)(pack2<PREC>(v, 0.0f) & 0xFFFFu);
     }
-    if (step && e == 0) {
-        const uint32_t b = *bad;
-        if (b) {
-            *flags |= b;   // the step's NIRC_FLAG_* bits
-            if (dyn_scale && (b & NIRC_FLAG_NONFINITE_GRAD)) {   // back off
-                *dyn_scale = fmaxf(*dyn_scale * 0.5f, kLossScaleMin);
-                *good = 0u;
-            }
-        } else {
-            *step += 1;
-            if (dyn_scale && ++*good >= kLossScaleGrowth) {
-                *dyn_scale = fminf(*dyn_scale * 2.0f, kLossScaleMax);
-                *good = 0u;
-            }
-        }
-        *bad = 0u;
-    }
+    if (step && e == 0) commit_step(step, flags, bad, dyn_scale, good);
 }
 
 template <int PREC, int W>
@@ -58,12 +42,10 @@ __device__ __forceinline__ void adam_pack16_block(float *__restrict__ w, float *
     if (i < np && *bad == 0u) {
         const float t = (float)(*step + 1);
         const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
-        const float gi = grad[i];
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        float mi = m[i], vi = v[i];
+        const float wi = adam_update(w[i], mi, vi, grad[i], c1, c2, lr, b1, b2, eps);
         m[i] = mi;
         v[i] = vi;
-        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
         w[i] = wi;
         int e[6];
         float sc[6];
@@ -75,7 +57,7 @@ __device__ __forceinline__ void adam_pack16_block(float *__restrict__ w, float *
         __threadfence();
         if (atomicAdd(done, 1u) == (uint32_t)nblk - 1u) {
             __threadfence();
-            pack16_elem<PREC, W>(packed, w, 0, step, flags, bad, dyn_scale, good, 0);   // commit only
+            commit_step(step, flags, bad, dyn_scale, good);
             *done = 0u;
         }
     }

@@ -514,6 +514,41 @@ struct TrainArgs {
 // kLossScaleGrowth finite steps in a row double it, within [kLossScaleMin, kLossScaleMax].
 constexpr uint32_t kLossScaleGrowth = 1000;
 constexpr float kLossScaleMin = 0x1p-14f, kLossScaleMax = 0x1p24f;
+
+// Adam (Kingma & Ba) for one parameter with bias correction at t = step + 1 (c1 = 1 - b1^t,
+// c2 = 1 - b2^t): updates the moments m and v from gradient g and returns the new weight.  Every
+// Adam kernel uses this one expression with every product and sum rounded on its own (no fused
+// multiply-adds, which the compiler could otherwise form differently in different kernels), so
+// that all of them produce the same bits.
+__device__ __forceinline__ float adam_update(float w, float &m, float &v, float g, float c1, float c2, float lr,
+                                             float b1, float b2, float eps) {
+#pragma clang fp contract(off)
+    m = b1 * m + (1.0f - b1) * g;
+    v = b2 * v + (1.0f - b2) * g * g;
+    return w - lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// The commit of a training step, by the one thread that finishes it: a step flagged in `bad`
+// records its NIRC_FLAG_* bits in `flags` and, for a non-finite gradient with a dynamic loss
+// scale, halves the scale; a finite step advances the step count and, after kLossScaleGrowth
+// of them in a row, doubles the scale.  Clears `bad` for the next step.
+__device__ inline void commit_step(int64_t *step, uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good) {
+    const uint32_t b = *bad;
+    if (b) {
+        *flags |= b;
+        if (dyn_scale && (b & NIRC_FLAG_NONFINITE_GRAD)) {   // back off
+            *dyn_scale = fmaxf(*dyn_scale * 0.5f, kLossScaleMin);
+            *good = 0u;
+        }
+    } else {
+        *step += 1;
+        if (dyn_scale && ++*good >= kLossScaleGrowth) {
+            *dyn_scale = fminf(*dyn_scale * 2.0f, kLossScaleMax);
+            *good = 0u;
+        }
+    }
+    *bad = 0u;
+}
 // NIRC_LOSS_VAR: fr[c] = mean over the batch of t - y (y: the model's predictions [B][3]),
 // summed in a fixed order; part holds kFrBlocks x 3 floats.
 constexpr int kFrBlocks = 256;

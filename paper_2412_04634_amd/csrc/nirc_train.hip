@@ -676,12 +676,10 @@ __device__ __forceinline__ void adam_elem(float *__restrict__ w, float *__restri
     if (i >= np || *bad) return;
     const float t = (float)(*step + 1);
     const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
-    const float gi = grad[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    float mi = m[i], vi = v[i];
+    w[i] = adam_update(w[i], mi, vi, grad[i], c1, c2, lr, b1, b2, eps);
     m[i] = mi;
     v[i] = vi;
-    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
@@ -707,12 +705,10 @@ __global__ __launch_bounds__(256) void k_adam_pack32(float *__restrict__ w, floa
     if (i < np && *bad == 0u) {
         const float t = (float)(*step + 1);
         const float c1 = 1.0f - powf(b1, t), c2 = 1.0f - powf(b2, t);
-        const float gi = grad[i];
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        float mi = m[i], vi = v[i];
+        const float wi = adam_update(w[i], mi, vi, grad[i], c1, c2, lr, b1, b2, eps);
         m[i] = mi;
         v[i] = vi;
-        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
         w[i] = wi;
         int e[2];
         const int n = f32_packed_targets(W, i, e);
@@ -723,9 +719,7 @@ __global__ __launch_bounds__(256) void k_adam_pack32(float *__restrict__ w, floa
         __threadfence();
         if (atomicAdd(done, 1u) == gridDim.x - 1u) {
             __threadfence();
-            if (*bad) *flags |= *bad;   // the step's NIRC_FLAG_* bits
-            else *step += 1;
-            *bad = 0u;
+            commit_step(step, flags, bad, nullptr, nullptr);
             *done = 0u;
         }
     }
@@ -879,9 +873,10 @@ __global__ void k_adam4(float *__restrict__ w, float *__restrict__ m, float *__r
         f32x4 m4 = *(const f32x4 *)(m + i0), v4 = *(const f32x4 *)(v + i0), w4 = *(const f32x4 *)(w + i0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            m4[k] = b1 * m4[k] + (1.0f - b1) * g4[k];
-            v4[k] = b2 * v4[k] + (1.0f - b2) * g4[k] * g4[k];
-            w4[k] -= lr * (m4[k] / c1) / (sqrtf(v4[k] / c2) + eps);
+            float mk = m4[k], vk = v4[k];
+            w4[k] = adam_update(w4[k], mk, vk, g4[k], c1, c2, lr, b1, b2, eps);
+            m4[k] = mk;
+            v4[k] = vk;
         }
         *(f32x4 *)(m + i0) = m4;
         *(f32x4 *)(v + i0) = v4;
@@ -889,12 +884,10 @@ __global__ void k_adam4(float *__restrict__ w, float *__restrict__ m, float *__r
         return;
     }
     for (int64_t i = i0; i < np; ++i) {
-        const float gi = grad[i];
-        const float mi = b1 * m[i] + (1.0f - b1) * gi;
-        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        float mi = m[i], vi = v[i];
+        w[i] = adam_update(w[i], mi, vi, grad[i], c1, c2, lr, b1, b2, eps);
         m[i] = mi;
         v[i] = vi;
-        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     }
 }
 
