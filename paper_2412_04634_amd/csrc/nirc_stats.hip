@@ -101,31 +101,40 @@ __global__ __launch_bounds__(256) void k_reference_table(nirc_lobes lobes, doubl
     for (int k = threadIdx.x; k < M; k += blockDim.x) table[j * M + k] = sc[k];
 }
 
-// Number of leading coefficients that can be nonzero (the maximum over the four lobes).
-__device__ inline int cheb_terms(const double *tab) {
-    int n = 1;
-    for (int j = 0; j < 4; ++j)
-        for (int k = TLMC_CHEB_COEFFS - 1; k >= n; --k)
-            if (tab[j * TLMC_CHEB_COEFFS + k] != 0.0) {
-                n = k + 1;
-                break;
-            }
-    return n;
+// The table staged in LDS with the four lobes' coefficients of one degree side by side
+// (tab[4 k + j] = c_jk), so that a degree's four coefficients are two 16-byte reads, and the
+// number of leading coefficients that can be nonzero (the maximum over the four lobes; thread 0
+// finds it).  Ends with a barrier.
+__device__ inline int stage_cheb_table(const double *table, double *tab, int *s_nk) {
+    for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x)
+        tab[4 * (i % TLMC_CHEB_COEFFS) + i / TLMC_CHEB_COEFFS] = table[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int n = 1;
+        for (int k = TLMC_CHEB_COEFFS - 1; k >= 1 && n == 1; --k)
+            for (int j = 0; j < 4; ++j)
+                if (tab[4 * k + j] != 0.0) n = k + 1;
+        *s_nk = n;
+    }
+    __syncthreads();
+    return *s_nk;
 }
 
 // J_j(t_j) for the four lobes: Clenshaw recurrences for sum_k c_jk T_k(t_j), run side by side.
 __device__ inline void cheb_eval4(const double *tab, int nk, const double t[4], double J[4]) {
     double b1[4] = {0.0, 0.0, 0.0, 0.0}, b2[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = nk - 1; k >= 1; --k) {
+        const double2 c01 = *(const double2 *)(tab + 4 * k), c23 = *(const double2 *)(tab + 4 * k + 2);
+        const double c[4] = {c01.x, c01.y, c23.x, c23.y};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const double b0 = 2.0 * t[j] * b1[j] - b2[j] + tab[j * TLMC_CHEB_COEFFS + k];
+            const double b0 = 2.0 * t[j] * b1[j] - b2[j] + c[j];
             b2[j] = b1[j];
             b1[j] = b0;
         }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) J[j] = t[j] * b1[j] - b2[j] + tab[j * TLMC_CHEB_COEFFS];
+    for (int j = 0; j < 4; ++j) J[j] = t[j] * b1[j] - b2[j] + tab[j];
 }
 
 __device__ inline void reference_at(const nirc_lobes &L, const double *tab, int nk, const Points &pts, int64_t p,
@@ -151,10 +160,9 @@ __device__ inline void reference_at(const nirc_lobes &L, const double *tab, int 
 }
 
 __global__ void k_reference(Points pts, nirc_lobes lobes, const double *table, double *F) {
-    __shared__ double tab[4 * TLMC_CHEB_COEFFS];
-    for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x) tab[i] = table[i];
-    __syncthreads();
-    const int nk = cheb_terms(tab);
+    __shared__ __align__(16) double tab[4 * TLMC_CHEB_COEFFS];
+    __shared__ int s_nk;
+    const int nk = stage_cheb_table(table, tab, &s_nk);
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= pts.count) return;
     double f[3];
@@ -174,14 +182,10 @@ constexpr int kStatThreads = 256;
 __global__ __launch_bounds__(kStatThreads) void k_frame_stats(Points pts, nirc_lobes lobes, const double *table,
                                                               const float *tl, const float *fc, const float *fr,
                                                               double eps, double *partials) {
-    __shared__ double tab[4 * TLMC_CHEB_COEFFS];
+    __shared__ __align__(16) double tab[4 * TLMC_CHEB_COEFFS];
     __shared__ double red[kStatThreads / 64][4];
     __shared__ int s_nk;
-    for (int i = threadIdx.x; i < 4 * TLMC_CHEB_COEFFS; i += blockDim.x) tab[i] = table[i];
-    __syncthreads();
-    if (threadIdx.x == 0) s_nk = cheb_terms(tab);   // once per workgroup
-    __syncthreads();
-    const int nk = s_nk;
+    const int nk = stage_cheb_table(table, tab, &s_nk);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pts.count;
          p += (int64_t)gridDim.x * blockDim.x) {
