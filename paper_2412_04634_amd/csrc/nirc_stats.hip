@@ -120,56 +120,74 @@ __device__ inline int stage_cheb_table(const double *table, double *tab, int *s_
     return *s_nk;
 }
 
-// J_j(t_j) for the four lobes: Clenshaw recurrences for sum_k c_jk T_k(t_j), run side by side.
-__device__ inline void cheb_eval4(const double *tab, int nk, const double t[4], double J[4]) {
-    double b1[4] = {0.0, 0.0, 0.0, 0.0}, b2[4] = {0.0, 0.0, 0.0, 0.0};
+// J_j(t_ij) for the four lobes at NP points: Clenshaw recurrences for sum_k c_jk T_k(t_ij), run
+// side by side (each degree's coefficients read once for all NP points).
+template <int NP>
+__device__ inline void cheb_eval(const double *tab, int nk, const double (&t)[NP][4], double (&J)[NP][4]) {
+    double b1[NP][4], b2[NP][4];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b1[i][j] = b2[i][j] = 0.0;
     for (int k = nk - 1; k >= 1; --k) {
         const double2 c01 = *(const double2 *)(tab + 4 * k), c23 = *(const double2 *)(tab + 4 * k + 2);
         const double c[4] = {c01.x, c01.y, c23.x, c23.y};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double b0 = 2.0 * t[j] * b1[j] - b2[j] + c[j];
-            b2[j] = b1[j];
-            b1[j] = b0;
-        }
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double b0 = 2.0 * t[i][j] * b1[i][j] - b2[i][j] + c[j];
+                b2[i][j] = b1[i][j];
+                b1[i][j] = b0;
+            }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) J[j] = t[j] * b1[j] - b2[j] + tab[j];
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) J[i][j] = t[i][j] * b1[i][j] - b2[i][j] + tab[j];
 }
 
-__device__ inline void reference_at(const nirc_lobes &L, const double *tab, int nk, const Points &pts, int64_t p,
-                                    double F[3]) {
-    const double x0 = pts.px[p], x1 = pts.py[p], x2 = pts.pz[p];
-    const double n0 = pts.nx[p], n1 = pts.ny[p], n2 = pts.nz[p];
-    double t[4], J[4];
+// The closed form F at NP points (indices p[i]).
+template <int NP>
+__device__ inline void reference_at(const nirc_lobes &L, const double *tab, int nk, const Points &pts,
+                                    const int64_t (&p)[NP], double (&F)[NP][3]) {
+    double t[NP][4], J[NP][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const double d = (double)L.axis[j][0] * n0 + (double)L.axis[j][1] * n1 + (double)L.axis[j][2] * n2;
-        t[j] = fmin(1.0, fmax(-1.0, d));
-    }
-    cheb_eval4(tab, nk, t, J);
-    F[0] = F[1] = F[2] = 0.0;
+    for (int i = 0; i < NP; ++i) {
+        const double n0 = pts.nx[p[i]], n1 = pts.ny[p[i]], n2 = pts.nz[p[i]];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double a = (double)L.alpha[j][c] + (double)L.beta[j][c][0] * x0 + (double)L.beta[j][c][1] * x1 +
-                             (double)L.beta[j][c][2] * x2;
-            F[c] += a * J[j];
+        for (int j = 0; j < 4; ++j) {
+            const double d = (double)L.axis[j][0] * n0 + (double)L.axis[j][1] * n1 + (double)L.axis[j][2] * n2;
+            t[i][j] = fmin(1.0, fmax(-1.0, d));
         }
+    }
+    cheb_eval<NP>(tab, nk, t, J);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const double x0 = pts.px[p[i]], x1 = pts.py[p[i]], x2 = pts.pz[p[i]];
+        F[i][0] = F[i][1] = F[i][2] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double a = (double)L.alpha[j][c] + (double)L.beta[j][c][0] * x0 +
+                                 (double)L.beta[j][c][1] * x1 + (double)L.beta[j][c][2] * x2;
+                F[i][c] += a * J[i][j];
+            }
+    }
 }
 
 __global__ void k_reference(Points pts, nirc_lobes lobes, const double *table, double *F) {
     __shared__ __align__(16) double tab[4 * TLMC_CHEB_COEFFS];
     __shared__ int s_nk;
     const int nk = stage_cheb_table(table, tab, &s_nk);
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= pts.count) return;
-    double f[3];
-    reference_at(lobes, tab, nk, pts, p, f);
-    F[3 * p + 0] = f[0];
-    F[3 * p + 1] = f[1];
-    F[3 * p + 2] = f[2];
+    const int64_t p[1] = {(int64_t)blockIdx.x * blockDim.x + threadIdx.x};
+    if (p[0] >= pts.count) return;
+    double f[1][3];
+    reference_at<1>(lobes, tab, nk, pts, p, f);
+    F[3 * p[0] + 0] = f[0][0];
+    F[3 * p[0] + 1] = f[0][1];
+    F[3 * p[0] + 2] = f[0][2];
 }
 
 constexpr int kStatBlocks = 2048;   // multiple of 64
@@ -187,24 +205,29 @@ __global__ __launch_bounds__(kStatThreads) void k_frame_stats(Points pts, nirc_l
     __shared__ int s_nk;
     const int nk = stage_cheb_table(table, tab, &s_nk);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pts.count;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        double F[3];
-        reference_at(lobes, tab, nk, pts, p, F);
-        for (int c = 0; c < 3; ++c) {
-            const double inv = 1.0 / (F[c] * F[c] + eps);   // one division per channel
-            const double e = (double)tl[3 * p + c] - F[c];
-            acc[0] += e * e * inv;
-            if (fc) {
-                const double ec = (double)fc[3 * p + c] - F[c];
-                acc[1] += ec * ec * inv;
+    // this thread's points p0, p0 + S, p0 + 2 S, ... (S the grid's thread count), two at a time so
+    // that each coefficient read serves both; they are added in that order
+    const int64_t S = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < pts.count; p0 += 2 * S) {
+        const bool two = p0 + S < pts.count;
+        const int64_t p[2] = {p0, two ? p0 + S : p0};
+        double F[2][3];
+        reference_at<2>(lobes, tab, nk, pts, p, F);
+        for (int i = 0; i < (two ? 2 : 1); ++i)
+            for (int c = 0; c < 3; ++c) {
+                const double inv = 1.0 / (F[i][c] * F[i][c] + eps);   // one division per channel
+                const double e = (double)tl[3 * p[i] + c] - F[i][c];
+                acc[0] += e * e * inv;
+                if (fc) {
+                    const double ec = (double)fc[3 * p[i] + c] - F[i][c];
+                    acc[1] += ec * ec * inv;
+                }
+                if (fr) {
+                    const double r = fr[3 * p[i] + c];
+                    acc[2] += r * r * inv;
+                }
+                acc[3] += 1.0;
             }
-            if (fr) {
-                const double r = fr[3 * p + c];
-                acc[2] += r * r * inv;
-            }
-            acc[3] += 1.0;
-        }
     }
     // fixed-order reduction: wave butterflies, then waves in order
     for (int k = 0; k < 4; ++k) {
