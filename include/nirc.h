@@ -309,8 +309,8 @@ nirc_status tlmc_estimate_batch(const void *list /* device */, int32_t width, in
 
 /* Continuous batching of online training (several render streams, each with its own cache): one
  * frame's training of each request of a work list, every step of all requests in one set of
- * launches (samples, gradient, reduction, Adam, repack), so that a frame loop over many streams
- * can replay one captured graph for the whole mix.  Host struct. */
+ * launches (samples, gradient, reduction, Adam with the 16-bit refresh), so that a frame loop
+ * over many streams can replay one captured graph for the whole mix.  Host struct. */
 #define NIRC_TRAIN_BATCH_MAX_REQUESTS 64
 typedef struct {
     nirc_model *model;     /* width 64, NIRC_BF16 or NIRC_FP16, loss other than NIRC_LOSS_VAR, created
