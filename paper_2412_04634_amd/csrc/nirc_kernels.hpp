@@ -549,6 +549,7 @@ __device__ inline void commit_step(int64_t *step, uint32_t *flags, uint32_t *bad
     }
     *bad = 0u;
 }
+
 // NIRC_LOSS_VAR: fr[c] = mean over the batch of t - y (y: the model's predictions [B][3]),
 // summed in a fixed order; part holds kFrBlocks x 3 floats.
 constexpr int kFrBlocks = 256;
