@@ -193,6 +193,7 @@ __global__ void k_reference(Points pts, nirc_lobes lobes, const double *table, d
 constexpr int kStatBlocks = 2048;   // multiple of 64
 static_assert(kStatBlocks % 64 == 0, "final reduction splits the blocks into 64 chunks");
 constexpr int kStatThreads = 256;
+constexpr int kStatPts = 2;   // points per thread evaluated together (3 and 4 measured slower)
 
 // Per-block FP64 partial sums over points and channels:
 //   0: (F_tl - F)^2 / (F^2 + eps)      1: (F_c - F)^2 / (F^2 + eps)   (when F_c is given)
@@ -205,15 +206,21 @@ __global__ __launch_bounds__(kStatThreads) void k_frame_stats(Points pts, nirc_l
     __shared__ int s_nk;
     const int nk = stage_cheb_table(table, tab, &s_nk);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    // this thread's points p0, p0 + S, p0 + 2 S, ... (S the grid's thread count), two at a time so
-    // that each coefficient read serves both; they are added in that order
+    // this thread's points p0, p0 + S, p0 + 2 S, ... (S the grid's thread count), kStatPts at a
+    // time so that each coefficient read serves all of them; they are added in that order
     const int64_t S = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < pts.count; p0 += 2 * S) {
-        const bool two = p0 + S < pts.count;
-        const int64_t p[2] = {p0, two ? p0 + S : p0};
-        double F[2][3];
-        reference_at<2>(lobes, tab, nk, pts, p, F);
-        for (int i = 0; i < (two ? 2 : 1); ++i)
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < pts.count; p0 += kStatPts * S) {
+        int64_t p[kStatPts];
+        int n = 0;
+#pragma unroll
+        for (int i = 0; i < kStatPts; ++i) {
+            const bool in = p0 + i * S < pts.count;
+            p[i] = in ? p0 + i * S : p0;
+            n += in;
+        }
+        double F[kStatPts][3];
+        reference_at<kStatPts>(lobes, tab, nk, pts, p, F);
+        for (int i = 0; i < n; ++i)
             for (int c = 0; c < 3; ++c) {
                 const double inv = 1.0 / (F[i][c] * F[i][c] + eps);   // one division per channel
                 const double e = (double)tl[3 * p[i] + c] - F[i][c];
