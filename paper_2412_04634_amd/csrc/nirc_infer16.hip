@@ -64,7 +64,7 @@ __device__ __forceinline__ void adam_pack16_block(float *__restrict__ w, float *
 }
 
 template <int PREC, int W>
-__global__ __launch_bounds__(256) void k_adam_pack16(float *w, float *m, float *v, const float *grad, int64_t *step,
+__global__ __launch_bounds__(kAdamThreads) void k_adam_pack16(float *w, float *m, float *v, const float *grad, int64_t *step,
                                                      uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good,
                                                      uint32_t *done, uint16_t *packed, float lr, float b1, float b2,
                                                      float eps) {
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_adam_pack16(float *w, float *m, float *
 
 // Adam + repack + commit of every request of a training work list (request blockIdx.y).
 template <int PREC, int W>
-__global__ __launch_bounds__(256) void k_adam_pack16_multi(const TrainDesc *__restrict__ desc) {
+__global__ __launch_bounds__(kAdamThreads) void k_adam_pack16_multi(const TrainDesc *__restrict__ desc) {
     if ((int)blockIdx.y >= desc->n) return;
     const TrainReq &t = desc->req[blockIdx.y];
     adam_pack16_block<PREC, W>(t.master, t.m, t.v, t.grad, t.step, t.flags, t.bad, t.dyn_scale, t.good_steps,
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_adam_pack16_multi(const TrainDesc *__re
 hipError_t launch_adam_pack16(int W, int prec, float *w, float *m, float *v, const float *grad, int64_t *step,
                               uint32_t *flags, uint32_t *bad, float *dyn_scale, uint32_t *good, uint32_t *done,
                               uint16_t *packed, float lr, float b1, float b2, float eps, hipStream_t s) {
-    const dim3 grid((unsigned)((n_params(W) + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((n_params(W) + kAdamThreads - 1) / kAdamThreads)), block(kAdamThreads);
     if (W == 64 && prec == NIRC_BF16)
         hipLaunchKernelGGL((k_adam_pack16<NIRC_BF16, 64>), grid, block, 0, s, w, m, v, grad, step, flags, bad, dyn_scale,
                            good, done, packed, lr, b1, b2, eps);
@@ -103,7 +103,7 @@ hipError_t launch_adam_pack16(int W, int prec, float *w, float *m, float *v, con
 
 hipError_t launch_adam_pack16_multi(const TrainDesc *desc, int W, int prec, hipStream_t s) {
     if (W != 64) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((n_params(64) + 255) / 256), kBatchMaxRequests), block(256);
+    const dim3 grid((unsigned)((n_params(64) + kAdamThreads - 1) / kAdamThreads), kBatchMaxRequests), block(kAdamThreads);
     if (prec == NIRC_BF16)
         hipLaunchKernelGGL((k_adam_pack16_multi<NIRC_BF16, 64>), grid, block, 0, s, desc);
     else

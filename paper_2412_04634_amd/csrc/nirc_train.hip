@@ -695,7 +695,7 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
 // between steps) commits the step or records its skip: every other workgroup has read `step` and
 // `bad` before it counted itself.
 template <int W>
-__global__ __launch_bounds__(256) void k_adam_pack32(float *__restrict__ w, float *__restrict__ m,
+__global__ __launch_bounds__(kAdamThreads) void k_adam_pack32(float *__restrict__ w, float *__restrict__ m,
                                                      float *__restrict__ v, const float *__restrict__ grad,
                                                      int64_t *step, uint32_t *flags, uint32_t *bad, uint32_t *done,
                                                      float *__restrict__ packed, float lr, float b1, float b2,
@@ -825,7 +825,7 @@ hipError_t launch_adam(int W, float *master, float *m, float *v, const float *gr
     if (packed16)
         return launch_adam_pack16(W, prec, master, m, v, grad, step, flags, bad, dyn_scale, good_steps, done,
                                   packed16, lr, b1, b2, eps, s);
-    const dim3 grid((unsigned)((np + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((np + kAdamThreads - 1) / kAdamThreads)), block(kAdamThreads);
     if (W == 64)
         hipLaunchKernelGGL(k_adam_pack32<64>, grid, block, 0, s, master, m, v, grad, step, flags, bad, done, packed,
                            lr, b1, b2, eps);
